@@ -1,0 +1,227 @@
+/*
+ * idx.h -- C ABI of the static GPU index library (libidx.so, gfx950 / MI355X).
+ *
+ * The library indexes a column of unsigned integer keys (32 or 64 bit) with
+ * unique 32-bit row IDs and answers the two lookups of the paper's problem
+ * statement (Section 1):
+ *   - point lookup: the row ID of the row whose key equals X;
+ *   - range lookup: the row IDs of all rows whose key e satisfies L <= e <= U.
+ * Three physical layouts are offered (Sections 3 and 6):
+ *   IDX_BS  -- the (key, rowid) pairs sorted by key, searched by binary search;
+ *   IDX_EBS -- binary Eytzinger (level) order, 1-based with an empty slot 0
+ *              (Section 3, Figure 5), searched from slot 1 going to 2i or 2i+1;
+ *   IDX_EKS -- k-ary Eytzinger order: k-1 sorted pivots per node, no empty
+ *              slot, the children of the node starting at slot i start at
+ *              i*k + (j+1)*(k-1), j = 0..k-1 (Section 6, Figures 10 and 11).
+ * The Eytzinger layouts are produced from the sorted array by a parallel
+ * permutation with one read and one write per element (Sections 4 and 6.1).
+ *
+ * Conventions shared by every call:
+ *   - Every data pointer (keys, rowids, queries, bounds, outputs) is a DEVICE
+ *     pointer on the current HIP device.  The caller owns inputs and outputs.
+ *   - `stream` is a hipStream_t passed as void*; NULL is the legacy null stream.
+ *     Calls enqueue their work on it and return without waiting, except where
+ *     a call states that it synchronises the stream.
+ *   - Keys compare as unsigned integers of the declared width (flags).
+ *   - Status codes: IDX_OK (0) or a negative IDX_ERR_* value; no C++
+ *     exception crosses this boundary.  After IDX_ERR_HIP the HIP error code
+ *     of the failing runtime call is available from idx_last_hip_error().
+ */
+#ifndef IDX_H
+#define IDX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct idx_index *idx_handle; /* opaque; owns the layout's device buffers */
+typedef void *idx_stream;             /* hipStream_t */
+
+/* layouts */
+#define IDX_BS 0
+#define IDX_EBS 1
+#define IDX_EKS 2
+
+/* build flags (bitwise OR) */
+#define IDX_KEY_U32 0u /* keys are uint32 */
+#define IDX_KEY_U64 1u /* keys are uint64 */
+#define IDX_SOA 0u     /* rowids in an array parallel to the keys (Section 7.1) */
+#define IDX_AOS 2u     /* rowids interleaved with the keys (Section 7.1); see idx_build */
+
+/* point-lookup miss sentinel; also a reserved row ID value */
+#define IDX_MISS 0xFFFFFFFFu
+
+/* status codes */
+#define IDX_OK 0
+#define IDX_ERR_ARG (-1)            /* invalid argument (null pointer, bad layout/k/flags, size limit) */
+#define IDX_ERR_RESERVED_ROWID (-2) /* a row ID equals IDX_MISS */
+#define IDX_ERR_NOMEM (-3)          /* device allocation failed */
+#define IDX_ERR_HIP (-4)            /* a HIP runtime call or kernel launch failed */
+#define IDX_ERR_CAPACITY (-5)       /* range output does not fit the given capacity */
+
+/* Largest supported number of build keys. */
+#define IDX_MAX_KEYS 0xFFFFFFFEull
+/* Largest supported EKS fan-out (k - 1 pivots must fit one 64-lane wave). */
+#define IDX_MAX_FANOUT 65u
+
+/*
+ * Optional device allocator used for the handle's buffers and for the
+ * temporary buffers of a call.  alloc(ctx, bytes, stream) returns a device
+ * pointer (256-byte aligned) or NULL; release(ctx, ptr, stream) frees it.
+ * Both must be stream-ordered with respect to `stream`: a buffer released on
+ * a stream may be reused only by work enqueued after the release.  Passing
+ * NULL selects hipMallocAsync / hipFreeAsync on the call's stream.
+ */
+typedef struct idx_allocator {
+    void *(*alloc)(void *ctx, size_t bytes, idx_stream stream);
+    void (*release)(void *ctx, void *ptr, idx_stream stream);
+    void *ctx;
+} idx_allocator;
+
+/*
+ * idx_build -- build a static index over n (key, rowid) pairs.
+ *
+ * Sorts the pairs by key with a stable LSD radix sort (Section 3: the BS
+ * index is a key-value sort; equal keys keep their input order), then for
+ * IDX_EBS / IDX_EKS rearranges the sorted array into Eytzinger order by the
+ * inverse permutation: the thread of target slot t loads the sorted entry of
+ * rank p'(t) (Section 4 for k = 2, Section 6.1 for general k).
+ *
+ *   keys     device array of n keys (uint32 or uint64 per flags)
+ *   rowids   device array of n uint32 row IDs; none may equal IDX_MISS
+ *   n        0 <= n <= IDX_MAX_KEYS (n = 0 builds an empty index)
+ *   layout   IDX_BS, IDX_EBS or IDX_EKS
+ *   k        fan-out: ignored for IDX_BS, must be 2 for IDX_EBS,
+ *            2 <= k <= IDX_MAX_FANOUT for IDX_EKS (k - 1 keys per node; the
+ *            paper's choice is k - 1 a power of two, any k is accepted)
+ *   flags    IDX_KEY_U32 or IDX_KEY_U64, OR-ed with IDX_SOA or IDX_AOS.
+ *            AoS stores each node's k-1 keys followed by its k-1 row IDs
+ *            (node = one key for BS and EBS), same footprint as SoA.
+ *   alloc    allocator for the handle and the build's temporaries, or NULL
+ *   stream   stream to build on
+ *   out      receives the handle (set to NULL on failure)
+ *
+ * The caller's keys/rowids are only read; they may be freed once the stream
+ * reaches the end of the build.  The call synchronises `stream` once, at its
+ * end, to read back the reserved-rowid and duplicate-key checks.
+ * Errors: IDX_ERR_ARG, IDX_ERR_RESERVED_ROWID (nothing is kept),
+ * IDX_ERR_NOMEM, IDX_ERR_HIP.
+ */
+int idx_build(const void *keys, const uint32_t *rowids, uint64_t n, int layout, uint32_t k, uint32_t flags,
+              const idx_allocator *alloc, idx_stream stream, idx_handle *out);
+
+/*
+ * idx_point -- batched point lookups (Section 1; search procedures of
+ * Sections 3 and 6.2).
+ *
+ *   queries    device array of m keys of the index's key width
+ *   m          number of lookups (0 is allowed)
+ *   out_rowid  device array of m uint32: out_rowid[q] is the row ID of the
+ *              first build pair (in stable sorted order) whose key equals
+ *              queries[q], or IDX_MISS when there is none
+ * Enqueued on `stream`, no synchronisation.  Errors: IDX_ERR_ARG, IDX_ERR_HIP.
+ */
+int idx_point(idx_handle h, const void *queries, uint64_t m, uint32_t *out_rowid, idx_stream stream);
+
+/*
+ * idx_range -- batched range lookups [lo[q], hi[q]] (Section 1; level
+ * scans of Section 5 for the Eytzinger layouts).
+ *
+ *   lo, hi       device arrays of m inclusive bounds (lo > hi gives an empty range)
+ *   out_offsets  device array of m + 1 uint64: the rowids of query q are
+ *                out_rowids[out_offsets[q] .. out_offsets[q+1]), out_offsets[0] = 0
+ *   out_rowids   device array of `capacity` uint32, or NULL to count only.
+ *                Each query's rowids are in ascending key order (equal keys in
+ *                input order), whatever the layout.
+ *   capacity     number of uint32 slots in out_rowids
+ *   total        host pointer receiving the total number of matches, or NULL
+ * Synchronises `stream` once to read the total.  out_offsets is always
+ * written; when total > capacity the call returns IDX_ERR_CAPACITY and
+ * writes no rowids.  Errors: IDX_ERR_ARG, IDX_ERR_NOMEM, IDX_ERR_HIP,
+ * IDX_ERR_CAPACITY.
+ */
+int idx_range(idx_handle h, const void *lo, const void *hi, uint64_t m, uint64_t *out_offsets,
+              uint32_t *out_rowids, uint64_t capacity, uint64_t *total, idx_stream stream);
+
+/* idx_destroy -- free the handle and its device buffers (stream-ordered on
+ * the stream of the last call that used the handle).  NULL is accepted. */
+int idx_destroy(idx_handle h);
+
+/* Text for a status code (static storage). */
+const char *idx_strerror(int status);
+
+/* HIP error code (hipError_t) of the most recent IDX_ERR_HIP in this thread. */
+int idx_last_hip_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Introspection
+ * ------------------------------------------------------------------------- */
+
+typedef struct idx_info {
+    uint64_t n;               /* build keys */
+    uint64_t slots;           /* layout slots (n, or n + 1 for EBS) */
+    uint64_t footprint_bytes; /* device bytes permanently held for keys + rowids */
+    int32_t layout;
+    uint32_t k;               /* fan-out (1 for BS, 2 for EBS) */
+    uint32_t flags;
+    uint32_t unique;          /* 1 when all build keys are distinct */
+    uint32_t levels;          /* tree levels (BS: binary-search steps) */
+    uint32_t full_levels;     /* fully occupied levels m (Sections 4, 6.1) */
+    uint64_t bottom_keys;     /* keys on the partial lowest level b */
+    float build_ms_sort;      /* device time of the sort phase of the last build */
+    float build_ms_permute;   /* device time of the permutation phase (0 for BS) */
+} idx_info;
+
+int idx_get_info(idx_handle h, idx_info *out);
+
+/*
+ * idx_export -- copy the layout, slot by slot, into caller buffers as
+ * structure-of-arrays: keys_out[slots] (key width of the index) and
+ * rowids_out[slots] (uint32).  For EBS slot 0 is the empty slot (key 0,
+ * rowid IDX_MISS).  Either pointer may be NULL.  Enqueued on `stream`.
+ */
+int idx_export(idx_handle h, void *keys_out, uint32_t *rowids_out, idx_stream stream);
+
+/*
+ * idx_slot_rank -- host-side evaluation of the build permutation: the sorted
+ * rank of the entry stored at 0-based level-order slot `slot` of the k-ary
+ * Eytzinger layout over n keys (k = 2 is the binary layout, whose 1-based
+ * slot s is level-order slot s - 1).  This is the inverse permutation p'(t)
+ * of Sections 4 and 6.1 that the build kernel evaluates for every slot.
+ * Returns UINT64_MAX when k < 2 or slot >= n.  Pure function, no device use.
+ */
+uint64_t idx_slot_rank(uint64_t n, uint32_t k, uint64_t slot);
+
+/* ---------------------------------------------------------------------------
+ * Lookup tuning (Section 7: limiting concurrency, cache pinning, local
+ * lookup reordering; Section 6.2: EKS group vs single).  Any field left 0
+ * takes the library's default for the index's size class.
+ * ------------------------------------------------------------------------- */
+
+typedef struct idx_lookup_params {
+    uint32_t group;      /* EKS lanes per lookup: 1 = EKS (single), else a power of
+                            two >= k - 1 (EKS (group)); ignored for BS/EBS */
+    uint32_t block;      /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    uint32_t per_lane;   /* lookups held per lane (group) at once: 1, 2, 4 or 8 */
+    uint32_t lds_levels; /* top tree levels served from LDS (cache pinning); 0 = none */
+    uint32_t persistent; /* 0 = one workgroup per tile of lookups; c > 0 = persistent
+                            grid of c workgroups per compute unit (limited concurrency) */
+    uint32_t reorder;    /* 1 = sort each workgroup's lookups locally before searching */
+    uint32_t early_exit; /* 1 = stop at an equal key (only used when keys are unique) */
+    uint32_t reserved;
+} idx_lookup_params;
+
+/* Set (p != NULL) or reset to defaults (p == NULL).  Errors: IDX_ERR_ARG for an
+ * unsupported combination (the handle keeps its previous parameters). */
+int idx_set_params(idx_handle h, const idx_lookup_params *p);
+/* The parameters point lookups will use (defaults resolved). */
+int idx_get_params(idx_handle h, idx_lookup_params *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IDX_H */

@@ -1,0 +1,243 @@
+"""ctypes binding of libidx.so -- argument marshalling only.
+
+Tensors are device buffers; their ``data_ptr()`` values and the current HIP
+stream handle are passed straight through the C ABI of ``include/idx.h``.
+Every computation happens inside the library's HIP kernels.  If the library
+has not been built, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libidx.so")
+
+IDX_BS, IDX_EBS, IDX_EKS = 0, 1, 2
+IDX_KEY_U32, IDX_KEY_U64, IDX_SOA, IDX_AOS = 0, 1, 0, 2
+IDX_MISS = 0xFFFFFFFF
+IDX_OK = 0
+IDX_ERR_ARG = -1
+IDX_ERR_RESERVED_ROWID = -2
+IDX_ERR_NOMEM = -3
+IDX_ERR_HIP = -4
+IDX_ERR_CAPACITY = -5
+
+LAYOUTS = {"bs": IDX_BS, "ebs": IDX_EBS, "eks": IDX_EKS}
+
+
+class IdxError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        msg = lib().idx_strerror(status).decode()
+        if status == IDX_ERR_HIP:
+            msg += f" (hip error {lib().idx_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{status}]")
+
+
+class idx_allocator(ctypes.Structure):
+    _fields_ = [
+        ("alloc", ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)),
+        ("release", ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)),
+        ("ctx", ctypes.c_void_p),
+    ]
+
+
+class idx_info(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint64),
+        ("slots", ctypes.c_uint64),
+        ("footprint_bytes", ctypes.c_uint64),
+        ("layout", ctypes.c_int32),
+        ("k", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("unique", ctypes.c_uint32),
+        ("levels", ctypes.c_uint32),
+        ("full_levels", ctypes.c_uint32),
+        ("bottom_keys", ctypes.c_uint64),
+        ("build_ms_sort", ctypes.c_float),
+        ("build_ms_permute", ctypes.c_float),
+    ]
+
+
+class idx_lookup_params(ctypes.Structure):
+    _fields_ = [
+        ("group", ctypes.c_uint32),
+        ("block", ctypes.c_uint32),
+        ("per_lane", ctypes.c_uint32),
+        ("lds_levels", ctypes.c_uint32),
+        ("persistent", ctypes.c_uint32),
+        ("reorder", ctypes.c_uint32),
+        ("early_exit", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+_lib = None
+
+# Every symbol include/idx.h declares, with its ctypes signature.
+_P = ctypes.c_void_p
+_U64 = ctypes.c_uint64
+_U32 = ctypes.c_uint32
+_I = ctypes.c_int
+SIGNATURES = {
+    "idx_build": (_I, [_P, _P, _U64, _I, _U32, _U32, ctypes.POINTER(idx_allocator), _P, ctypes.POINTER(_P)]),
+    "idx_point": (_I, [_P, _P, _U64, _P, _P]),
+    "idx_range": (_I, [_P, _P, _P, _U64, _P, _P, _U64, ctypes.POINTER(_U64), _P]),
+    "idx_destroy": (_I, [_P]),
+    "idx_strerror": (ctypes.c_char_p, [_I]),
+    "idx_last_hip_error": (_I, []),
+    "idx_get_info": (_I, [_P, ctypes.POINTER(idx_info)]),
+    "idx_export": (_I, [_P, _P, _P, _P]),
+    "idx_slot_rank": (_U64, [_U64, _U32, _U64]),
+    "idx_set_params": (_I, [_P, ctypes.POINTER(idx_lookup_params)]),
+    "idx_get_params": (_I, [_P, ctypes.POINTER(idx_lookup_params)]),
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _check(status: int, what: str):
+    if status != IDX_OK:
+        raise IdxError(status, what)
+
+
+def _key_flag(t: torch.Tensor) -> int:
+    if t.element_size() == 8:
+        return IDX_KEY_U64
+    if t.element_size() == 4:
+        return IDX_KEY_U32
+    raise TypeError("keys must be 32- or 64-bit integers (their bits are read as unsigned)")
+
+
+def _dev(t: torch.Tensor, name: str):
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous device tensor")
+
+
+class Index:
+    """A static index over (keys, rowids) device tensors.
+
+    keys: 32- or 64-bit integer tensor (bit pattern read as unsigned);
+    rowids: int32/uint32 tensor of row IDs (0xFFFFFFFF is reserved).
+    layout: "bs", "ebs" or "eks"; k: fan-out for "eks"; aos: interleave rowids.
+    """
+
+    def __init__(self, keys: torch.Tensor, rowids: torch.Tensor, layout: str = "eks", k: int = 9,
+                 aos: bool = False, stream=None):
+        _dev(keys, "keys")
+        _dev(rowids, "rowids")
+        if rowids.element_size() != 4 or len(rowids) != len(keys):
+            raise ValueError("rowids must be 32-bit and as long as keys")
+        self.layout = layout
+        self.key_bits = keys.element_size() * 8
+        self.key_dtype = keys.dtype
+        lay = LAYOUTS[layout]
+        kk = {IDX_BS: 1, IDX_EBS: 2, IDX_EKS: k}[lay]
+        flags = _key_flag(keys) | (IDX_AOS if aos else IDX_SOA)
+        h = ctypes.c_void_p()
+        st = lib().idx_build(keys.data_ptr(), rowids.data_ptr(), len(keys), lay, kk, flags, None, _stream(stream),
+                             ctypes.byref(h))
+        _check(st, "idx_build")
+        self._h = h
+        self.n = len(keys)
+        self.k = kk
+
+    # -- lifecycle
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().idx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- lookups
+    def point(self, queries: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        _dev(queries, "queries")
+        if queries.element_size() * 8 != self.key_bits:
+            raise ValueError("query width differs from the key width")
+        if out is None:
+            out = torch.empty(len(queries), dtype=torch.int32, device=queries.device)
+        _dev(out, "out")
+        _check(lib().idx_point(self._h, queries.data_ptr(), len(queries), out.data_ptr(), _stream(stream)),
+               "idx_point")
+        return out
+
+    def range(self, lo: torch.Tensor, hi: torch.Tensor, capacity: int | None = None, count_only: bool = False,
+              stream=None):
+        """Returns (offsets[m+1] int64, rowids[total] int32)."""
+        _dev(lo, "lo")
+        _dev(hi, "hi")
+        m = len(lo)
+        offsets = torch.empty(m + 1, dtype=torch.int64, device=lo.device)
+        total = ctypes.c_uint64(0)
+        s = _stream(stream)
+        if count_only or capacity is None:
+            _check(lib().idx_range(self._h, lo.data_ptr(), hi.data_ptr(), m, offsets.data_ptr(), None, 0,
+                                   ctypes.byref(total), s), "idx_range(count)")
+            if count_only:
+                return offsets, None
+            capacity = total.value
+        out = torch.empty(max(1, capacity), dtype=torch.int32, device=lo.device)
+        _check(lib().idx_range(self._h, lo.data_ptr(), hi.data_ptr(), m, offsets.data_ptr(), out.data_ptr(),
+                               capacity, ctypes.byref(total), s), "idx_range")
+        return offsets, out[: total.value]
+
+    # -- introspection and tuning
+    def info(self) -> dict:
+        i = idx_info()
+        _check(lib().idx_get_info(self._h, ctypes.byref(i)), "idx_get_info")
+        return {f: getattr(i, f) for f, _ in i._fields_}
+
+    def export(self, stream=None):
+        info = self.info()
+        keys = torch.empty(info["slots"], dtype=self.key_dtype, device="cuda")
+        rows = torch.empty(info["slots"], dtype=torch.int32, device="cuda")
+        _check(lib().idx_export(self._h, keys.data_ptr(), rows.data_ptr(), _stream(stream)), "idx_export")
+        return keys, rows
+
+    def set_params(self, **kw):
+        p = idx_lookup_params(**kw)
+        _check(lib().idx_set_params(self._h, ctypes.byref(p)), "idx_set_params")
+        return self.params()
+
+    def reset_params(self):
+        _check(lib().idx_set_params(self._h, None), "idx_set_params")
+
+    def params(self) -> dict:
+        p = idx_lookup_params()
+        _check(lib().idx_get_params(self._h, ctypes.byref(p)), "idx_get_params")
+        return p.as_dict()

@@ -1,0 +1,161 @@
+// Internal declarations of libidx: the handle, the tree geometry and the
+// host-side launchers each kernel file provides.  gfx950 (MI355X) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/idx.h"
+
+namespace idx {
+
+constexpr uint32_t kMiss = IDX_MISS;
+constexpr int kWave = 64;
+constexpr int kMaxLevels = 40;
+
+// Shape of the complete k-ary search tree over n keys stored in level order
+// (Sections 4 and 6.1).  Level l holds (k-1)*k^l slots starting at slot
+// k^l - 1; the first m levels are full (k^m - 1 <= n), the b = n - (k^m - 1)
+// remaining keys sit left-aligned on level m.
+struct Geo {
+    uint64_t n;
+    uint32_t k;      // fan-out
+    uint32_t g;      // k - 1 keys per node
+    uint32_t m;      // full levels
+    uint32_t levels; // m + (b > 0)
+    int32_t gshift;  // log2(g) when g is a power of two, else -1
+    uint32_t pad;
+    uint64_t b;                  // keys on the partial level
+    uint64_t start[kMaxLevels];  // start[l] = k^l - 1 (saturated), l <= levels
+};
+
+Geo make_geo(uint64_t n, uint32_t k);
+
+// Default-stream-ordered device memory through the handle's allocator.
+struct Alloc {
+    idx_allocator a{};
+    bool custom = false;
+    void *get(size_t bytes, hipStream_t s) const;
+    void put(void *p, hipStream_t s) const;
+};
+
+struct LearnedModel;  // learned rank model (learned.hip)
+
+}  // namespace idx
+
+struct idx_index {
+    uint64_t n = 0;
+    uint64_t slots = 0;
+    int layout = IDX_BS;
+    uint32_t k = 1;
+    uint32_t flags = 0;
+    bool u64 = false;
+    bool aos = false;
+    bool unique = true;
+    uint32_t node = 1;  // keys per AoS block (k - 1 for EKS, 1 otherwise)
+    void *keys = nullptr;       // SoA keys or AoS blocks
+    uint32_t *rowids = nullptr; // SoA rowids (nullptr for AoS)
+    size_t key_bytes = 0, row_bytes = 0;
+    void *pin = nullptr;        // top of the search tree, ready to copy to LDS
+    uint32_t pin_keys = 0;      // keys in `pin`
+    uint32_t pin_levels_built = 0;
+    idx::Geo geo{};
+    idx::Alloc alloc;
+    idx_lookup_params params{};
+    float ms_sort = 0.f, ms_permute = 0.f;
+    hipStream_t last_stream = nullptr;
+    int cu_count = 256;
+};
+
+namespace idx {
+
+// ---- sort.hip ---------------------------------------------------------------
+// Bytes of temporary device memory sort_pairs needs for n keys.
+size_t sort_temp_bytes(uint64_t n, bool u64);
+// Stable LSD radix sort of (key, rowid) by key.  in_* are read only; the
+// result is written to out_*; temp holds sort_temp_bytes(n, u64) bytes.
+// Synchronises `s` once (to decide which digit passes can be skipped).
+int sort_pairs(const void *keys_in, const uint32_t *rows_in, uint64_t n, bool u64, void *keys_out,
+               uint32_t *rows_out, void *temp, hipStream_t s);
+
+// ---- layout.hip -------------------------------------------------------------
+// Fills the layout buffers of h from the sorted arrays (permutation for
+// EBS/EKS, copy or interleave for BS).
+int build_layout(idx_index *h, const void *sorted_keys, const uint32_t *sorted_rows, hipStream_t s);
+// flags[0] |= 1 when two adjacent sorted keys are equal, flags[1] |= 1 when a
+// rowid equals IDX_MISS.
+int check_sorted(const void *sorted_keys, const uint32_t *sorted_rows, uint64_t n, bool u64, uint32_t *flags,
+                 hipStream_t s);
+// Copies the layout into SoA caller buffers.
+int export_layout(const idx_index *h, void *keys_out, uint32_t *rows_out, hipStream_t s);
+// (Re)builds the LDS pin table of the top `levels` tree levels.
+int build_pin(idx_index *h, uint32_t levels, hipStream_t s);
+// Sorted rank of level-order slot t (0-based) -- Sections 4 and 6.1.
+__host__ __device__ inline uint64_t slot_rank(const Geo &G, uint64_t t);
+
+// ---- point.hip --------------------------------------------------------------
+int point_lookup(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s);
+// Resolve defaults and validate a parameter set for h.
+int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_params *out);
+// Largest number of top levels whose keys fit in `bytes` of LDS.
+uint32_t pin_levels_for(const idx_index *h, size_t bytes);
+
+// ---- range.hip --------------------------------------------------------------
+int range_lookup(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
+                 uint64_t capacity, uint64_t *total, hipStream_t s);
+
+// ---- error plumbing ----------------------------------------------------------
+int hip_fail(hipError_t e);
+
+}  // namespace idx
+
+#define IDX_HIP(call)                                 \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return idx::hip_fail(e_); \
+    } while (0)
+
+#define IDX_LAUNCH_CHECK() IDX_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// Inline device helpers shared by the kernel files.
+// ---------------------------------------------------------------------------
+namespace idx {
+
+// Sorted rank of level-order slot t (0-based), t < n.  Bottom (partial) level
+// entries: rank i + floor(i/(k-1)) with i the position within the level;
+// upper-level entries: the rank p in the perfect tree of m levels,
+// p = k^(m-l-1) * (1 + i + floor(i/(k-1))) - 1, shifted right by the number
+// of bottom-level keys that precede it, min(b, (k-1)(p+1)).  This is the
+// reading of Sections 4 and 6.1 with the two cases assigned to the bottom and
+// upper levels respectively and m = floor(log_k(n+1)), l(t) = floor(log_k(t+1)).
+__host__ __device__ inline uint64_t div_g(const Geo &G, uint64_t v) {
+    return G.gshift >= 0 ? (v >> G.gshift) : v / G.g;
+}
+
+__host__ __device__ inline uint64_t slot_rank(const Geo &G, uint64_t t) {
+    const uint64_t bottom_start = G.start[G.m];
+    if (t >= bottom_start) {
+        const uint64_t i = t - bottom_start;
+        return i + div_g(G, i);
+    }
+    uint32_t l = 0;
+    if (G.k == 2) {
+#ifdef __HIP_DEVICE_COMPILE__
+        l = 63u - (uint32_t)__clzll((long long)(t + 1));
+#else
+        l = 63u - (uint32_t)__builtin_clzll(t + 1);
+#endif
+    } else {
+        while (G.start[l + 1] <= t) ++l;
+    }
+    const uint64_t i = t - G.start[l];
+    // k^(m-l-1) = start[m-l-1] + 1
+    const uint64_t p = (G.start[G.m - l - 1] + 1) * (1 + i + div_g(G, i)) - 1;
+    const uint64_t skip = G.g * (p + 1);
+    return p + (skip < G.b ? skip : G.b);
+}
+
+}  // namespace idx

@@ -1,0 +1,491 @@
+// Batched point lookups on the three layouts (gfx950, wave64).
+//
+//  BS   lower-bound binary search on the sorted array (Section 3), branchless
+//       with a fixed step count, then an equality test.
+//  EBS  Eytzinger binary search (Section 3): from slot 1 go to 2i when the
+//       key is >= the target, else 2i+1, until i exceeds n.  The lower-bound
+//       slot is recovered from the final i by dropping its trailing right
+//       turns and the last left turn (i >> (ctz(~i) + 1); Khuong and Morin,
+//       "Array layouts for comparison-based searching", 2017).
+//  EKS  Eytzinger k-ary search (Section 6.2).  (group): a group of lanes loads
+//       one node's k-1 pivots with one coalesced access, a 64-bit wave ballot
+//       masked to the group and a popcount give j = #pivots < target, the
+//       search continues at node c*k + 1 + j (slot i*k + (j+1)(k-1)).
+//       (single): one lane per lookup reads the whole node (vector loads when
+//       the node is 16-byte aligned) and counts in registers.
+//
+// Every lane (or lane group) holds R independent lookups and advances them
+// level by level together, so R dependent-load chains are in flight per lane.
+// Optional cache pinning (Section 7.3) copies the top levels into LDS once per
+// workgroup; with a persistent grid (Section 7.2, limited concurrency) the
+// copy is amortised over many tiles.  The lower bound is tracked during the
+// descent (deepest candidate), so only the row ID needs one more load.
+#include <type_traits>
+
+#include "internal.hpp"
+#include "access.hpp"
+
+namespace idx {
+namespace {
+
+template <typename K, bool AOS>
+struct PointArgs {
+    Load<K, AOS> L;
+    Geo G;
+    const K *__restrict__ q;
+    uint64_t m;
+    uint32_t *__restrict__ out;
+    const K *__restrict__ pin;
+    uint32_t pin_entries;
+    uint32_t pin_levels;
+    uint32_t early;     // stop at an equal key (unique keys only)
+    uint32_t bs_iters;  // binary-search steps over n keys
+};
+
+// Cooperative copy of the pin table into LDS.
+template <typename K>
+__device__ __forceinline__ void load_pin(K *s_pin, const K *__restrict__ pin, uint32_t count) {
+    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) s_pin[i] = pin[i];
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------------- BS
+
+template <typename K, bool AOS, int R>
+__global__ __launch_bounds__(1024) void k_point_bs(PointArgs<K, AOS> a) {
+    extern __shared__ __align__(16) char smem[];
+    K *s_pin = (K *)smem;
+    if (a.pin_levels) load_pin(s_pin, a.pin, a.pin_entries);
+    const uint64_t n = a.G.n;
+    const uint64_t tile = (uint64_t)blockDim.x * R;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < a.m; t0 += (uint64_t)gridDim.x * tile) {
+        K x[R];
+        uint64_t base[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
+            x[r] = qi < a.m ? a.q[qi] : K(0);
+            base[r] = 0;
+        }
+        uint64_t len = n;
+        if (a.pin_levels) {
+            uint32_t v[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[r] = 1;
+            for (uint32_t d = 0; d < a.pin_levels; ++d) {
+                const uint64_t half = len >> 1;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const bool go = s_pin[v[r]] < x[r];
+                    base[r] += go ? half : 0;
+                    v[r] = 2 * v[r] + (go ? 1u : 0u);
+                }
+                len -= half;
+            }
+        }
+        while (len > 1) {
+            const uint64_t half = len >> 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) base[r] = (a.L.key(base[r] + half) < x[r]) ? base[r] + half : base[r];
+            len -= half;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
+            if (qi >= a.m) continue;
+            uint32_t res = kMiss;
+            if (n > 0) {
+                const K kb = a.L.key(base[r]);
+                const uint64_t pos = base[r] + (kb < x[r] ? 1 : 0);
+                if (pos < n) {
+                    const K kp = kb < x[r] ? a.L.key(pos) : kb;
+                    if (kp == x[r]) res = a.L.row(pos);
+                }
+            }
+            a.out[qi] = res;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------- EBS
+
+template <typename K, bool AOS, int R>
+__global__ __launch_bounds__(1024) void k_point_ebs(PointArgs<K, AOS> a) {
+    extern __shared__ __align__(16) char smem[];
+    K *s_pin = (K *)smem;
+    if (a.pin_levels) load_pin(s_pin, a.pin, a.pin_entries);
+    const uint64_t n = a.G.n;
+    const uint32_t m_full = a.G.m;
+    const uint64_t tile = (uint64_t)blockDim.x * R;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < a.m; t0 += (uint64_t)gridDim.x * tile) {
+        K x[R], ck[R];
+        uint64_t i[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
+            x[r] = qi < a.m ? a.q[qi] : K(0);
+            i[r] = 1;
+            ck[r] = key_max<K>();
+        }
+        uint32_t lvl = 0;
+        for (; lvl < a.pin_levels; ++lvl) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const K kk = s_pin[i[r]];
+                const bool right = kk < x[r];
+                ck[r] = right ? ck[r] : kk;
+                i[r] = 2 * i[r] + (right ? 1 : 0);
+            }
+        }
+        for (; lvl < m_full; ++lvl) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const K kk = a.L.key(i[r]);
+                const bool right = kk < x[r];
+                ck[r] = right ? ck[r] : kk;
+                i[r] = 2 * i[r] + (right ? 1 : 0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (i[r] <= n) {
+                const K kk = a.L.key(i[r]);
+                const bool right = kk < x[r];
+                ck[r] = right ? ck[r] : kk;
+                i[r] = 2 * i[r] + (right ? 1 : 0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
+            if (qi >= a.m) continue;
+            const uint64_t j = i[r] >> (__builtin_ctzll(~i[r]) + 1);
+            a.out[qi] = (j != 0 && ck[r] == x[r]) ? a.L.row(j) : kMiss;
+        }
+    }
+}
+
+// --------------------------------------------------------------- EKS group
+
+// GL lanes per lookup (a power of two >= k-1); 64/GL lookups per wave per
+// register slot; R register slots.
+template <typename K, bool AOS, int GL, int R>
+__global__ __launch_bounds__(1024) void k_point_eks_group(PointArgs<K, AOS> a) {
+    extern __shared__ __align__(16) char smem[];
+    K *s_pin = (K *)smem;
+    if (a.pin_levels) load_pin(s_pin, a.pin, a.pin_entries);
+    constexpr int GPW = kWave / GL;  // groups per wave
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t sub = lane & (GL - 1);
+    const uint32_t grp = lane / GL;
+    const uint64_t gmask = (GL == kWave) ? ~0ull : (((1ull << GL) - 1ull) << (grp * GL));
+    const uint64_t n = a.G.n;
+    const uint32_t g = a.G.g;
+    const uint32_t kf = a.G.k;
+    const bool lane_ok = sub < g;
+    const uint32_t waves = blockDim.x / kWave;
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint64_t tile = (uint64_t)waves * GPW * R;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < a.m; t0 += (uint64_t)gridDim.x * tile) {
+        const uint64_t wbase = t0 + (uint64_t)wave * GPW * R;
+        K x[R];
+        uint64_t c[R], cand[R];
+        bool ceq[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = wbase + (uint64_t)r * GPW + grp;
+            x[r] = qi < a.m ? a.q[qi] : K(0);
+            c[r] = qi < a.m ? 0 : ~0ull;  // node index; ~0 = finished
+            cand[r] = 0;
+            ceq[r] = false;
+        }
+        for (uint32_t lvl = 0; lvl < a.G.levels; ++lvl) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const bool live = c[r] != ~0ull;
+                const uint64_t i = live ? c[r] * g : n;  // node's first slot
+                const uint64_t s = i + sub;
+                const bool valid = live && lane_ok && s < n;
+                K kk = key_max<K>();
+                if (valid) kk = (lvl < a.pin_levels) ? s_pin[s] : a.L.nkey(c[r], sub);
+                const uint64_t lt = __ballot(valid && kk < x[r]) & gmask;
+                const uint64_t eq = __ballot(valid && kk == x[r]) & gmask;
+                const uint32_t j = (uint32_t)__popcll(lt);
+                if (live) {
+                    const uint64_t nv = (n - i) < g ? (n - i) : g;  // pivots present in the node
+                    if (j < nv) {
+                        cand[r] = i + j;
+                        ceq[r] = eq != 0;
+                    }
+                    const uint64_t child = c[r] * kf + 1 + j;
+                    const bool stop = (a.early && eq != 0) || child * g >= n;
+                    c[r] = stop ? ~0ull : child;
+                }
+            }
+        }
+        if (sub == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t qi = wbase + (uint64_t)r * GPW + grp;
+                if (qi < a.m) a.out[qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
+            }
+        }
+    }
+}
+
+// -------------------------------------------------------------- EKS single
+
+// One lane per lookup.  GMAX = pivots read per node (>= k-1); VEC = nodes are
+// exactly GMAX keys, 16-byte aligned, read with 16-byte loads (SoA only).
+template <typename K, bool AOS, int GMAX, bool VEC, int R>
+__global__ __launch_bounds__(1024) void k_point_eks_single(PointArgs<K, AOS> a) {
+    extern __shared__ __align__(16) char smem[];
+    K *s_pin = (K *)smem;
+    if (a.pin_levels) load_pin(s_pin, a.pin, a.pin_entries);
+    const uint64_t n = a.G.n;
+    const uint32_t g = a.G.g;
+    const uint32_t kf = a.G.k;
+    const uint64_t tile = (uint64_t)blockDim.x * R;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < a.m; t0 += (uint64_t)gridDim.x * tile) {
+        K x[R];
+        uint64_t c[R], cand[R];
+        bool ceq[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
+            x[r] = qi < a.m ? a.q[qi] : K(0);
+            c[r] = qi < a.m ? 0 : ~0ull;
+            cand[r] = 0;
+            ceq[r] = false;
+        }
+        for (uint32_t lvl = 0; lvl < a.G.levels; ++lvl) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (c[r] == ~0ull) continue;
+                const uint64_t i = c[r] * g;
+                const uint64_t nv = (n - i) < g ? (n - i) : g;
+                K kk[GMAX];
+                if (lvl < a.pin_levels) {
+#pragma unroll
+                    for (int e = 0; e < GMAX; ++e) kk[e] = (e < (int)nv) ? s_pin[i + e] : key_max<K>();
+                } else if constexpr (VEC) {
+                    // full node of GMAX keys, 16-byte aligned; partial last node
+                    // reads stay inside the padded allocation and are masked
+                    constexpr int W = 16 / sizeof(K);
+                    const uint4 *p = (const uint4 *)a.L.node_ptr(c[r]);
+#pragma unroll
+                    for (int v = 0; v < GMAX / W; ++v) {
+                        const uint4 w = p[v];
+                        if constexpr (sizeof(K) == 8) {
+                            kk[2 * v] = ((uint64_t)w.y << 32) | w.x;
+                            kk[2 * v + 1] = ((uint64_t)w.w << 32) | w.z;
+                        } else {
+                            kk[4 * v] = w.x;
+                            kk[4 * v + 1] = w.y;
+                            kk[4 * v + 2] = w.z;
+                            kk[4 * v + 3] = w.w;
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < GMAX; ++e)
+                        if (e >= (int)nv) kk[e] = key_max<K>();
+                } else {
+#pragma unroll
+                    for (int e = 0; e < GMAX; ++e) kk[e] = (e < (int)nv) ? a.L.nkey(c[r], e) : key_max<K>();
+                }
+                uint32_t j = 0;
+                bool eq = false;
+#pragma unroll
+                for (int e = 0; e < GMAX; ++e) {
+                    j += (e < (int)nv && kk[e] < x[r]) ? 1u : 0u;
+                    eq |= (e < (int)nv && kk[e] == x[r]);
+                }
+                if (j < nv) {
+                    cand[r] = i + j;
+                    ceq[r] = eq;
+                }
+                const uint64_t child = c[r] * kf + 1 + j;
+                c[r] = ((a.early && eq) || child * g >= n) ? ~0ull : child;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
+            if (qi < a.m) a.out[qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+template <typename K, bool AOS>
+PointArgs<K, AOS> make_args(const idx_index *h, const void *q, uint64_t m, uint32_t *out, uint32_t pin_levels,
+                            bool early) {
+    PointArgs<K, AOS> a{};
+    a.L = make_load<K, AOS>(h);
+    a.G = h->geo;
+    a.q = (const K *)q;
+    a.m = m;
+    a.out = out;
+    a.pin = (const K *)h->pin;
+    a.pin_entries = pin_levels ? h->pin_keys : 0;
+    a.pin_levels = pin_levels;
+    a.early = early ? 1u : 0u;
+    a.bs_iters = 0;
+    return a;
+}
+
+struct Launch {
+    uint32_t grid, block;
+    size_t smem;
+};
+
+Launch plan(const idx_index *h, const idx_lookup_params &p, uint64_t m, uint64_t lookups_per_block) {
+    Launch L{};
+    L.block = p.block;
+    L.smem = p.lds_levels ? (size_t)h->pin_keys * (h->u64 ? 8 : 4) : 0;
+    const uint64_t tiles = (m + lookups_per_block - 1) / lookups_per_block;
+    uint64_t grid = tiles;
+    if (p.persistent) {
+        const uint64_t cap = (uint64_t)h->cu_count * p.persistent;
+        if (grid > cap) grid = cap;
+    }
+    if (grid > 0x7FFFFFFFull) grid = 0x7FFFFFFFull;
+    L.grid = (uint32_t)(grid ? grid : 1);
+    return L;
+}
+
+template <typename K, bool AOS, int R>
+int run_bs(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
+    auto a = make_args<K, AOS>(h, q, m, out, p.lds_levels, false);
+    const Launch L = plan(h, p, m, (uint64_t)p.block * R);
+    hipLaunchKernelGGL((k_point_bs<K, AOS, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+    IDX_LAUNCH_CHECK();
+    return IDX_OK;
+}
+
+template <typename K, bool AOS, int R>
+int run_ebs(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
+    auto a = make_args<K, AOS>(h, q, m, out, p.lds_levels, false);
+    const Launch L = plan(h, p, m, (uint64_t)p.block * R);
+    hipLaunchKernelGGL((k_point_ebs<K, AOS, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+    IDX_LAUNCH_CHECK();
+    return IDX_OK;
+}
+
+template <typename K, bool AOS, int GL, int R>
+int run_group(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out,
+              hipStream_t s) {
+    auto a = make_args<K, AOS>(h, q, m, out, p.lds_levels, p.early_exit == 1 && h->unique);
+    const Launch L = plan(h, p, m, (uint64_t)(p.block / kWave) * (kWave / GL) * R);
+    hipLaunchKernelGGL((k_point_eks_group<K, AOS, GL, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+    IDX_LAUNCH_CHECK();
+    return IDX_OK;
+}
+
+template <typename K, bool AOS, int GMAX, int R>
+int run_single(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out,
+               hipStream_t s) {
+    auto a = make_args<K, AOS>(h, q, m, out, p.lds_levels, p.early_exit == 1 && h->unique);
+    const Launch L = plan(h, p, m, (uint64_t)p.block * R);
+    constexpr bool vec_ok = !AOS && (GMAX * sizeof(K)) % 16 == 0;
+    if (vec_ok && h->geo.g == GMAX)
+        hipLaunchKernelGGL((k_point_eks_single<K, AOS, GMAX, vec_ok, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+    else
+        hipLaunchKernelGGL((k_point_eks_single<K, AOS, GMAX, false, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+    IDX_LAUNCH_CHECK();
+    return IDX_OK;
+}
+
+template <int R, typename F>
+int with_r(uint32_t r, F &&f) {
+    switch (r) {
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        default: return IDX_ERR_ARG;
+    }
+}
+
+template <typename K, bool AOS>
+int point_t(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
+    if (h->layout == IDX_BS)
+        return with_r<0>(p.per_lane, [&](auto R) { return run_bs<K, AOS, decltype(R)::value>(h, p, q, m, out, s); });
+    if (h->layout == IDX_EBS)
+        return with_r<0>(p.per_lane, [&](auto R) { return run_ebs<K, AOS, decltype(R)::value>(h, p, q, m, out, s); });
+    if (p.group <= 1) {
+        const uint32_t g = h->geo.g;
+        return with_r<0>(p.per_lane, [&](auto R) {
+            constexpr int RR = decltype(R)::value;
+            if (g <= 4) return run_single<K, AOS, 4, RR>(h, p, q, m, out, s);
+            if (g <= 8) return run_single<K, AOS, 8, RR>(h, p, q, m, out, s);
+            if (g <= 16) return run_single<K, AOS, 16, RR>(h, p, q, m, out, s);
+            return run_single<K, AOS, 32, RR>(h, p, q, m, out, s);
+        });
+    }
+    return with_r<0>(p.per_lane, [&](auto R) {
+        constexpr int RR = decltype(R)::value;
+        switch (p.group) {
+            case 2: return run_group<K, AOS, 2, RR>(h, p, q, m, out, s);
+            case 4: return run_group<K, AOS, 4, RR>(h, p, q, m, out, s);
+            case 8: return run_group<K, AOS, 8, RR>(h, p, q, m, out, s);
+            case 16: return run_group<K, AOS, 16, RR>(h, p, q, m, out, s);
+            case 32: return run_group<K, AOS, 32, RR>(h, p, q, m, out, s);
+            case 64: return run_group<K, AOS, 64, RR>(h, p, q, m, out, s);
+            default: return IDX_ERR_ARG;
+        }
+    });
+}
+
+uint32_t pow2_at_least(uint32_t v) {
+    uint32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_params *out) {
+    idx_lookup_params p{};
+    if (in) p = *in;
+    const uint32_t g = h->layout == IDX_EKS ? h->geo.g : 1;
+    if (h->layout == IDX_EKS) {
+        if (p.group == 0) p.group = pow2_at_least(g);
+        if (p.group != 1 && (p.group < g || p.group > 64 || (p.group & (p.group - 1)))) return IDX_ERR_ARG;
+        // EKS (single) keeps a whole node in registers: at most 32 pivots
+        if (p.group == 1 && g > 32) return IDX_ERR_ARG;
+    } else {
+        p.group = 1;
+    }
+    if (p.block == 0) p.block = 256;
+    if (p.block < 64 || p.block > 1024 || (p.block & (p.block - 1))) return IDX_ERR_ARG;
+    if (p.per_lane == 0) p.per_lane = (h->layout == IDX_EKS && p.group > 1) ? 2 : 4;
+    if (p.per_lane != 1 && p.per_lane != 2 && p.per_lane != 4 && p.per_lane != 8) return IDX_ERR_ARG;
+    // cache pinning: at most 64 KiB of LDS and only complete levels
+    const size_t kb = h->u64 ? 8 : 4;
+    const uint32_t max_levels = pin_levels_for(h, 64 * 1024);
+    if (p.lds_levels > max_levels) return IDX_ERR_ARG;
+    (void)kb;
+    if (p.persistent > 64) return IDX_ERR_ARG;
+    if (p.reorder > 1) return IDX_ERR_ARG;
+    if (p.reorder) return IDX_ERR_ARG;  // local reordering: not offered by this build
+    // early exit: 0 = default (on), 1 = on, 2 = off; only effective for unique keys
+    if (p.early_exit == 0) p.early_exit = 1;
+    if (p.early_exit > 2) return IDX_ERR_ARG;
+    *out = p;
+    return IDX_OK;
+}
+
+int point_lookup(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
+    if (m == 0) return IDX_OK;
+    const idx_lookup_params &p = h->params;
+    if (p.lds_levels) {
+        const int rc = build_pin(h, p.lds_levels, s);
+        if (rc != IDX_OK) return rc;
+    }
+    if (h->u64) return h->aos ? point_t<uint64_t, true>(h, p, q, m, out, s) : point_t<uint64_t, false>(h, p, q, m, out, s);
+    return h->aos ? point_t<uint32_t, true>(h, p, q, m, out, s) : point_t<uint32_t, false>(h, p, q, m, out, s);
+}
+
+}  // namespace idx

@@ -1,0 +1,293 @@
+// Batched range lookups [lo, hi] returning row IDs in key order.
+//
+// Three phases:
+//  1. count: per query, the sorted rank of the first key >= lo and of the
+//     first key > hi (a lower-bound descent for each; on the Eytzinger
+//     layouts the rank of the descent's slot t is slot_rank(t)), giving the
+//     match count; the first rank is kept in a scratch array;
+//  2. exclusive scan of the counts into the caller's offsets (u64);
+//  3. fill: BS copies the contiguous rowid run; EBS/EKS run the level scan of
+//     Section 5: follow the lower-bound path of lo and, on every level, scan
+//     right from the path position while keys are <= hi and the level has not
+//     ended (qualifying entries of a level are contiguous, and at most two
+//     extra entries per level are read).  The scan meets the matches in level
+//     order; each is written at offset + slot_rank(t) - first rank, which puts
+//     the query's rowids in key order.
+// EBS is handled as the k = 2 level-order tree shifted by its empty slot.
+#include "internal.hpp"
+#include "access.hpp"
+
+namespace idx {
+namespace {
+
+template <typename K, bool AOS>
+struct RangeArgs {
+    Load<K, AOS> L;
+    Geo G;
+    uint32_t off;  // layout slot of level-order slot 0 (1 for EBS)
+    int layout;
+    const K *__restrict__ lo;
+    const K *__restrict__ hi;
+    uint64_t m;
+    uint64_t *__restrict__ offsets;
+    uint32_t *__restrict__ first_rank;
+    uint32_t *__restrict__ out;
+};
+
+// Rank of the first key >= x.
+template <typename K, bool AOS>
+__device__ __forceinline__ uint64_t lower_rank(const RangeArgs<K, AOS> &a, K x) {
+    const uint64_t n = a.G.n;
+    if (n == 0) return 0;
+    if (a.layout == IDX_BS) {
+        uint64_t base = 0, len = n;
+        while (len > 1) {
+            const uint64_t half = len >> 1;
+            base = (a.L.key(base + half) < x) ? base + half : base;
+            len -= half;
+        }
+        return base + (a.L.key(base) < x ? 1 : 0);
+    }
+    const uint32_t g = a.G.g, kf = a.G.k;
+    uint64_t c = 0, cand = ~0ull;
+    while (c * g < n) {
+        const uint64_t i = c * g;
+        const uint64_t nv = (n - i) < g ? (n - i) : g;
+        uint32_t j = 0;
+        for (uint32_t e = 0; e < nv; ++e) j += a.L.key(a.off + i + e) < x ? 1u : 0u;
+        if (j < nv) cand = i + j;
+        c = c * kf + 1 + j;
+    }
+    return cand == ~0ull ? n : slot_rank(a.G, cand);
+}
+
+template <typename K, bool AOS>
+__global__ __launch_bounds__(256) void k_range_count(RangeArgs<K, AOS> a) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.m) return;
+    const K L = a.lo[q], U = a.hi[q];
+    uint64_t r0 = 0, r1 = 0;
+    if (L <= U) {
+        r0 = lower_rank(a, L);
+        r1 = (U == key_max<K>()) ? a.G.n : lower_rank(a, (K)(U + 1));
+    }
+    a.first_rank[q] = (uint32_t)r0;
+    a.offsets[q] = r1 > r0 ? r1 - r0 : 0;
+}
+
+// BS: one 16-lane group per query copies the contiguous rowid run.
+template <typename K, bool AOS>
+__global__ __launch_bounds__(256) void k_range_fill_bs(RangeArgs<K, AOS> a) {
+    constexpr int GL = 16;
+    const uint64_t q = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL;
+    const uint32_t sub = threadIdx.x & (GL - 1);
+    if (q >= a.m) return;
+    const uint64_t o = a.offsets[q];
+    const uint64_t cnt = a.offsets[q + 1] - o;
+    const uint64_t r0 = a.first_rank[q];
+    for (uint64_t e = sub; e < cnt; e += GL) a.out[o + e] = a.L.row(r0 + e);
+}
+
+// EBS/EKS: single-lane level scan along the lower-bound path of lo.
+template <typename K, bool AOS>
+__global__ __launch_bounds__(256) void k_range_fill_eyt(RangeArgs<K, AOS> a) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.m) return;
+    const uint64_t o = a.offsets[q];
+    const uint64_t cnt = a.offsets[q + 1] - o;
+    if (cnt == 0) return;
+    const K L = a.lo[q], U = a.hi[q];
+    const uint64_t r0 = a.first_rank[q];
+    const uint64_t n = a.G.n;
+    const uint32_t g = a.G.g, kf = a.G.k;
+    uint64_t c = 0;
+    uint32_t lvl = 0;
+    while (c * g < n) {
+        const uint64_t i = c * g;
+        const uint64_t nv = (n - i) < g ? (n - i) : g;
+        uint32_t j = 0;
+        for (uint32_t e = 0; e < nv; ++e) j += a.L.key(a.off + i + e) < L ? 1u : 0u;
+        const uint64_t level_end = a.G.start[lvl + 1] < n ? a.G.start[lvl + 1] : n;
+        for (uint64_t t = i + j; t < level_end; ++t) {
+            const uint64_t s = a.off + t;
+            const K kk = a.L.key(s);
+            if (kk > U) break;
+            const uint64_t d = slot_rank(a.G, t) - r0;  // position in key order
+            if (d < cnt) a.out[o + d] = a.L.row(s);
+        }
+        c = c * kf + 1 + j;
+        ++lvl;
+    }
+}
+
+// ------------------------------------------------------------- u64 scan
+
+constexpr int SC_THREADS = 256;
+constexpr int SC_ITEMS = 16;
+constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+
+__device__ __forceinline__ uint64_t block_scan_u64(uint64_t v, uint64_t *s_wave, uint64_t *total) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wave = threadIdx.x / kWave;
+    uint64_t incl = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t t = __shfl_up(incl, off, kWave);
+        if (lane >= (uint32_t)off) incl += t;
+    }
+    if (lane == kWave - 1) s_wave[wave] = incl;
+    __syncthreads();
+    uint64_t before = 0, sum = 0;
+#pragma unroll
+    for (int w = 0; w < SC_THREADS / kWave; ++w) {
+        const uint64_t c = s_wave[w];
+        before += (w < (int)wave) ? c : 0;
+        sum += c;
+    }
+    __syncthreads();
+    *total = sum;
+    return before + incl - v;
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint64_t *__restrict__ v, uint64_t m,
+                                                            uint64_t *__restrict__ partial) {
+    __shared__ uint64_t s_wave[SC_THREADS / kWave];
+    const uint64_t base = (uint64_t)blockIdx.x * SC_TILE;
+    uint64_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < SC_ITEMS; ++j) {
+        const uint64_t i = base + (uint64_t)j * SC_THREADS + threadIdx.x;
+        sum += i < m ? v[i] : 0;
+    }
+    uint64_t total;
+    block_scan_u64(sum, s_wave, &total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Single workgroup: exclusive scan of the per-tile partial sums in place.
+__global__ __launch_bounds__(SC_THREADS) void k_scan_partials(uint64_t *__restrict__ partial, uint64_t tiles) {
+    __shared__ uint64_t s_wave[SC_THREADS / kWave];
+    uint64_t running = 0;
+    for (uint64_t chunk = 0; chunk < tiles; chunk += SC_TILE) {
+        uint64_t v[SC_ITEMS], sum = 0;
+        const uint64_t first = chunk + (uint64_t)threadIdx.x * SC_ITEMS;
+#pragma unroll
+        for (int j = 0; j < SC_ITEMS; ++j) {
+            v[j] = first + j < tiles ? partial[first + j] : 0;
+            sum += v[j];
+        }
+        uint64_t total;
+        uint64_t acc = running + block_scan_u64(sum, s_wave, &total);
+#pragma unroll
+        for (int j = 0; j < SC_ITEMS; ++j) {
+            if (first + j < tiles) partial[first + j] = acc;
+            acc += v[j];
+        }
+        running += total;
+    }
+}
+
+// Tile-local exclusive scan plus the tile's prefix; writes offsets[m] = total.
+__global__ __launch_bounds__(SC_THREADS) void k_scan_apply(uint64_t *__restrict__ v, uint64_t m,
+                                                           const uint64_t *__restrict__ partial) {
+    __shared__ uint64_t s_wave[SC_THREADS / kWave];
+    const uint64_t base = (uint64_t)blockIdx.x * SC_TILE + (uint64_t)threadIdx.x * SC_ITEMS;
+    uint64_t x[SC_ITEMS], sum = 0;
+#pragma unroll
+    for (int j = 0; j < SC_ITEMS; ++j) {
+        x[j] = base + j < m ? v[base + j] : 0;
+        sum += x[j];
+    }
+    uint64_t total;
+    uint64_t acc = partial[blockIdx.x] + block_scan_u64(sum, s_wave, &total);
+#pragma unroll
+    for (int j = 0; j < SC_ITEMS; ++j) {
+        if (base + j < m) v[base + j] = acc;
+        acc += x[j];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SC_THREADS - 1) v[m] = acc;
+}
+
+int exclusive_scan(uint64_t *v, uint64_t m, uint64_t *partial, hipStream_t s) {
+    const uint64_t tiles = (m + SC_TILE - 1) / SC_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)tiles), dim3(SC_THREADS), 0, s, v, m, partial);
+    IDX_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SC_THREADS), 0, s, partial, tiles);
+    IDX_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_apply, dim3((uint32_t)tiles), dim3(SC_THREADS), 0, s, v, m, partial);
+    IDX_LAUNCH_CHECK();
+    return IDX_OK;
+}
+
+template <typename K, bool AOS>
+int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
+            uint64_t capacity, uint64_t *total, hipStream_t s) {
+    RangeArgs<K, AOS> a{};
+    a.L = make_load<K, AOS>(h);
+    a.G = h->geo;
+    a.off = h->layout == IDX_EBS ? 1u : 0u;
+    a.layout = h->layout;
+    a.lo = (const K *)lo;
+    a.hi = (const K *)hi;
+    a.m = m;
+    a.offsets = offsets;
+    a.out = out;
+    const uint64_t tiles = (m + SC_TILE - 1) / SC_TILE;
+    const size_t rank_bytes = ((m * 4 + 255) / 256) * 256;
+    char *scratch = (char *)h->alloc.get(rank_bytes + tiles * 8 + 256, s);
+    if (!scratch) return IDX_ERR_NOMEM;
+    a.first_rank = (uint32_t *)scratch;
+    uint64_t *partial = (uint64_t *)(scratch + rank_bytes);
+    int rc = IDX_OK;
+    uint64_t tot = 0;
+    const uint32_t blocks = (uint32_t)((m + 255) / 256);
+    do {
+        hipLaunchKernelGGL((k_range_count<K, AOS>), dim3(blocks), dim3(256), 0, s, a);
+        if (hipGetLastError() != hipSuccess) {
+            rc = IDX_ERR_HIP;
+            break;
+        }
+        rc = exclusive_scan(offsets, m, partial, s);
+        if (rc != IDX_OK) break;
+        hipError_t e = hipMemcpyAsync(&tot, offsets + m, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            rc = hip_fail(e);
+            break;
+        }
+        if (total) *total = tot;
+        if (!out || tot == 0) break;
+        if (tot > capacity) {
+            rc = IDX_ERR_CAPACITY;
+            break;
+        }
+        if (h->layout == IDX_BS) {
+            const uint64_t threads = m * 16;
+            hipLaunchKernelGGL((k_range_fill_bs<K, AOS>), dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((k_range_fill_eyt<K, AOS>), dim3(blocks), dim3(256), 0, s, a);
+        }
+        if (hipGetLastError() != hipSuccess) rc = IDX_ERR_HIP;
+    } while (0);
+    h->alloc.put(scratch, s);
+    return rc;
+}
+
+}  // namespace
+
+int range_lookup(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
+                 uint64_t capacity, uint64_t *total, hipStream_t s) {
+    if (m == 0) {
+        // offsets[0] = 0
+        IDX_HIP(hipMemsetAsync(offsets, 0, sizeof(uint64_t), s));
+        if (total) *total = 0;
+        return IDX_OK;
+    }
+    if (h->u64)
+        return h->aos ? range_t<uint64_t, true>(h, lo, hi, m, offsets, out, capacity, total, s)
+                      : range_t<uint64_t, false>(h, lo, hi, m, offsets, out, capacity, total, s);
+    return h->aos ? range_t<uint32_t, true>(h, lo, hi, m, offsets, out, capacity, total, s)
+                  : range_t<uint32_t, false>(h, lo, hi, m, offsets, out, capacity, total, s);
+}
+
+}  // namespace idx
