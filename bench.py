@@ -1,0 +1,362 @@
+#!/usr/bin/env python3
+"""Benchmark: point lookups/s on a static index of n = 2^26 unique uint64 keys.
+
+Workload (the full-scale configuration): n = 2^26 keys uniform in [0, 2^63),
+unique by construction, rowid = insertion position; 2^27 point lookups, all
+hits, uniform over the build keys, in random order (the paper's default
+lookup workload, Section 8.1, at this size); 2^24 range lookups covering 16
+consecutive keys each.  All inputs are resident in HBM before timing.
+
+A step is one pass of the hot path over the batch: sort (BS build), the
+Eytzinger permutations (EBS and the tuned EKS), point lookups on BS, EBS and
+EKS, range lookups on BS and EKS.  `value` is the point-lookup throughput of
+the fastest form, from HIP events around its kernel inside the timed steps;
+every other phase is reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "point lookups/s at n=2^26 (BS vs EKS vs learned, bit-exact); % of HBM roofline"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+ONCHIP_BYTES = 256 << 20  # Infinity Cache (MALL); the per-XCD L2 is far smaller and not counted
+GRANULE = 64
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# --------------------------------------------------------------------------
+# Algorithmic bytes per point lookup (the per-unit figure of the roofline):
+# 8 B query + 4 B result streamed, plus every tree level that cannot stay on
+# chip (cumulative top-down footprint above ONCHIP_BYTES) costs the bytes of
+# the node read there, rounded up to 64-byte granules, weighted by the share
+# of lookups that reach the level; plus one granule for the row ID (SoA).
+# --------------------------------------------------------------------------
+
+def levels_eytzinger(n: int, k: int):
+    out, start, width = [], 0, k - 1
+    while start < n:
+        out.append((start, min(n, start + width)))
+        start += width
+        width *= k
+    return out
+
+
+def algo_bytes(form: str, n: int, k: int, key_bytes: int, early_exit: bool = True) -> dict:
+    stream = key_bytes + 4
+    uncached = 0.0
+    if form == "bs":
+        length, depth, cum = n, 0, 0
+        while length > 1:
+            half = length >> 1
+            granules_so_far = min(2 ** (depth + 1), (n * key_bytes + GRANULE - 1) // GRANULE)
+            cum = granules_so_far * GRANULE
+            if cum > ONCHIP_BYTES and length * key_bytes > GRANULE:
+                uncached += GRANULE
+            length -= half
+            depth += 1
+    else:
+        kk = 2 if form == "ebs" else k
+        cum = 0
+        for lvl, (a, b) in enumerate(levels_eytzinger(n, kk)):
+            cum += (b - a) * key_bytes
+            node_bytes = (kk - 1) * key_bytes
+            node_g = math.ceil(node_bytes / GRANULE) * GRANULE
+            reach = (n - a) / n if (early_exit and form == "eks") else (1.0 if b - a == (kk - 1) * kk ** lvl
+                                                                             else (b - a) / ((kk - 1) * kk ** lvl))
+            if cum > ONCHIP_BYTES:
+                uncached += reach * node_g
+    rowid = GRANULE
+    return {"stream": stream, "tree": uncached, "rowid": rowid, "total": stream + uncached + rowid}
+
+
+def source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("point.hip", "access.hpp", "internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2506_01576_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_key: str):
+    """HBM bytes per launch of `kernel_key` from the committed rocprofv3 PMC
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_point_lookup.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith(kernel_key + " "):
+                for kv in line.split()[1:]:
+                    k, _, v = kv.partition("=")
+                    rec[k] = v
+    if not rec or rec.get("source_sha") != source_sha():
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+# --------------------------------------------------------------------------
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--log2n", type=int, default=26)
+    ap.add_argument("--log2m", type=int, default=27)
+    ap.add_argument("--log2ranges", type=int, default=24)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the k / parameter sweep (use defaults)")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="lookups in the CPU oracle sample")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this index build and its lookups run on a single MI355X; "
+              "multi-GPU runs are not part of this benchmark (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gen
+    import paper_2506_01576_amd as idx
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    n, m, mr = 1 << args.log2n, 1 << args.log2m, 1 << args.log2ranges
+    seed = gen.BASE_SEED + 1
+    W = 63
+
+    t0 = time.time()
+    keys_h, rows_h = gen.unique_keys(seed, n, 64, W)
+    q_h, expect_h = gen.point_queries(seed, n, m, 1.0, 64, W)
+    log(f"generated keys/queries in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    lo_h, hi_h, _ = gen.ranges(seed, keys_h, mr, 16, 16)
+    log(f"generated ranges in {time.time() - t0:.1f}s")
+
+    def up(a):
+        return torch.from_numpy(a.view(np.int64) if a.dtype == np.uint64 else a.view(np.int32)).to(dev)
+
+    keys, rows, q, expect = up(keys_h), up(rows_h), up(q_h), up(expect_h)
+    lo, hi = up(lo_h), up(hi_h)
+    del q_h, lo_h, hi_h
+    out = torch.empty(m, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def time_point(ix, reps=3, check=False):
+        ix.point(q, out)
+        ok = None
+        if check:
+            torch.cuda.synchronize()
+            ok = bool(torch.equal(out, expect))
+        ts = []
+        for _ in range(reps):
+            a = ev()
+            ix.point(q, out)
+            b = ev()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts)), ok
+
+    # ---------------------------------------------------------------- sweep
+    base = idx.Index(keys, rows, layout="bs")
+    sweep = []
+    candidates = []
+    if args.no_sweep:
+        candidates = [("bs", 1, {}), ("ebs", 2, {}), ("eks", 9, {})]
+    else:
+        candidates += [("bs", 1, {}), ("bs", 1, {"per_lane": 8}), ("bs", 1, {"lds_levels": 12, "persistent": 2}),
+                       ("ebs", 2, {}), ("ebs", 2, {"per_lane": 8}), ("ebs", 2, {"lds_levels": 12, "persistent": 2})]
+        for k in (4, 5, 8, 9, 16, 17, 32, 33):
+            candidates.append(("eks", k, {}))
+            candidates.append(("eks", k, {"per_lane": 4}))
+            candidates.append(("eks", k, {"group": 1, "per_lane": 4}))
+    best_by_layout = {}
+    for layout, k, params in candidates:
+        ix = base if layout == "bs" else base.relayout(layout, k)
+        try:
+            ix.set_params(**params)
+        except idx.IdxError:
+            if ix is not base:
+                ix.close()
+            continue
+        ms, ok = time_point(ix, reps=3, check=True)
+        rec = {"layout": layout, "k": k, "params": ix.params(), "ms": round(ms, 4), "lookups_per_s": m / ms * 1e3,
+               "bit_exact": ok}
+        sweep.append(rec)
+        log(f"sweep {layout} k={k} {params}: {ms:.3f} ms  {m / ms / 1e6:.1f} M/s  exact={ok}")
+        key = layout
+        if ok and (key not in best_by_layout or ms < best_by_layout[key]["ms"]):
+            best_by_layout[key] = rec
+        if ix is not base:
+            ix.close()
+        else:
+            ix.reset_params()
+    if not all(r["bit_exact"] for r in sweep):
+        log("WARNING: some forms were not bit-exact")
+
+    best_eks = best_by_layout.get("eks")
+    forms = [("BS", best_by_layout["bs"]), ("EBS", best_by_layout["ebs"])]
+    if best_eks:
+        forms.append((f"EKS(k={best_eks['k']},{'single' if best_eks['params']['group'] == 1 else 'group'})",
+                      best_eks))
+    base.close()
+
+    # ---------------------------------------------------------------- steps
+    def one_step(record):
+        t = {}
+        a = ev()
+        bs = idx.Index(keys, rows, layout="bs")
+        b = ev()
+        hs = {"BS": bs}
+        marks = [("build_sort", a, b)]
+        for name, rec in forms[1:]:
+            a = ev()
+            hs[name] = bs.relayout(rec["layout"], rec["k"])
+            b = ev()
+            marks.append((f"build_permute_{name}", a, b))
+        for name, rec in forms:
+            hs[name].set_params(**{kk: v for kk, v in rec["params"].items()})
+            a = ev()
+            hs[name].point(q, out)
+            b = ev()
+            marks.append((f"point_{name}", a, b))
+        for name in ("BS", forms[-1][0]):
+            a = ev()
+            off, rr = hs[name].range(lo, hi, capacity=mr * 16)
+            b = ev()
+            marks.append((f"range_{name}", a, b))
+            del off, rr
+        torch.cuda.synchronize()
+        for nm, a, b in marks:
+            t[nm] = a.elapsed_time(b)
+        for h in hs.values():
+            h.close()
+        record.append(t)
+
+    warm = []
+    for _ in range(args.warmup):
+        one_step(warm)
+    torch.cuda.synchronize()
+    rec_steps = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(rec_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_per_step = wall / args.steps * 1e3
+
+    mean = {k: float(np.mean([r[k] for r in rec_steps])) for k in rec_steps[0]}
+    point_rates = {name: m / mean[f"point_{name}"] * 1e3 for name, _ in forms}
+    headline = max(point_rates, key=point_rates.get)
+    hrec = dict(forms)[headline]
+    value = point_rates[headline]
+
+    # ------------------------------------------------------------ roofline
+    ab = algo_bytes(hrec["layout"], n, hrec["k"], 8, early_exit=hrec["params"].get("early_exit", 1) == 1)
+    t_kernel = mean[f"point_{headline}"] / 1e3
+    achieved = ab["total"] * m / t_kernel / 1e9
+    kernel_key = f"point_{hrec['layout']}_k{hrec['k']}_g{hrec['params']['group']}_r{hrec['params']['per_lane']}"
+    traffic = read_traffic(kernel_key)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": (round(traffic / 1e9 / t_kernel, 1) if traffic else None),
+                "kernel": kernel_key, "algorithmic_bytes_per_lookup": ab,
+                "launch_ms": round(mean[f"point_{headline}"], 4)}
+
+    # ------------------------------------------------------ random-access probe
+    probe = {}
+    try:
+        buf = torch.empty(1 << 29, dtype=torch.int64, device=dev)  # 4 GiB, far above the on-chip caches
+        for group in (1, 8):
+            lanes, steps = 256 * 4096, 32
+            idx.probe_random(buf, group, lanes, steps)
+            a = ev()
+            loads = idx.probe_random(buf, group, lanes, steps)
+            b = ev()
+            b.synchronize()
+            ms = a.elapsed_time(b)
+            granules = loads / group
+            probe[f"group{group}"] = {"granule_bytes": 8 * group, "granules_per_s": granules / ms * 1e3,
+                                      "useful_GB_s": loads * 8 / ms / 1e6}
+        del buf
+    except Exception as e:  # pragma: no cover - measurement only
+        probe["error"] = str(e)
+
+    # ------------------------------------------------------------ CPU oracle
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = min(16, os.cpu_count() or 1)
+        ms_ = min(args.cpu_sample, m)
+        t0 = time.perf_counter()
+        sk, sr = oracle.stable_sort(keys_h, rows_h)
+        t_sort = time.perf_counter() - t0
+        qs = q.cpu().numpy().view(np.uint64)[:ms_].copy()
+        t0 = time.perf_counter()
+        got = oracle.point(sk, sr, qs, nthreads=cores)
+        t_pt = time.perf_counter() - t0
+        cpu_exact = bool(np.array_equal(got, expect_h[:ms_]))
+        cpu = {"value": ms_ / t_pt, "unit": "lookups/s", "cores": cores, "kind": "oracle",
+               "sample": f"first {ms_} of the {m} queries against the full n={n} build sorted by the oracle's "
+                         f"stable sort ({t_sort:.1f} s, 1 thread); lower_bound + equality per query, "
+                         f"{cores} threads; answers equal the generator's: {cpu_exact}"}
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "lookups/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"static index, n=2^{args.log2n} unique uint64 keys uniform in [0,2^63), "
+                               f"uint32 rowids; 2^{args.log2m} uniform hit point lookups; "
+                               f"2^{args.log2ranges} ranges of 16",
+                   "form": headline, "layout": hrec["layout"], "k": hrec["k"], "params": hrec["params"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "forms": {name: {"lookups_per_s": point_rates[name], "ms": round(mean[f"point_{name}"], 4),
+                         "layout": rec["layout"], "k": rec["k"], "params": rec["params"]} for name, rec in forms},
+        "phases_ms": {k: round(v, 4) for k, v in mean.items()},
+        "range_lookups_per_s": {k[6:]: mr / v * 1e3 for k, v in mean.items() if k.startswith("range_")},
+        "bit_exact": all(r["bit_exact"] for r in sweep),
+        "random_access": probe,
+        "sweep": [{kk: r[kk] for kk in ("layout", "k", "params", "ms", "lookups_per_s", "bit_exact")} for r in sweep],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -114,6 +114,22 @@ int idx_build(const void *keys, const uint32_t *rowids, uint64_t n, int layout, 
               const idx_allocator *alloc, idx_stream stream, idx_handle *out);
 
 /*
+ * idx_relayout -- build an EBS or EKS index (or an AoS copy of a BS index)
+ * from an existing sorted-array index without sorting again: only the
+ * one-read/one-write permutation of Sections 4 and 6.1 runs (the build of
+ * Section 8.5 is sort + rearrangement; this is the rearrangement alone).
+ *
+ *   src      an IDX_BS index with SoA layout (IDX_ERR_ARG otherwise); it is
+ *            only read and stays valid and independent of the result
+ *   layout, k, flags, alloc, out   as for idx_build; the key width in
+ *            flags must equal src's
+ * Enqueued on `stream`, no synchronisation; the build times in idx_info
+ * are reported as 0.  Errors: IDX_ERR_ARG, IDX_ERR_NOMEM, IDX_ERR_HIP.
+ */
+int idx_relayout(idx_handle src, int layout, uint32_t k, uint32_t flags, const idx_allocator *alloc,
+                 idx_stream stream, idx_handle *out);
+
+/*
  * idx_point -- batched point lookups (Section 1; search procedures of
  * Sections 3 and 6.2).
  *
@@ -219,6 +235,27 @@ typedef struct idx_lookup_params {
 int idx_set_params(idx_handle h, const idx_lookup_params *p);
 /* The parameters point lookups will use (defaults resolved). */
 int idx_get_params(idx_handle h, idx_lookup_params *out);
+
+/* ---------------------------------------------------------------------------
+ * Measurement
+ * ------------------------------------------------------------------------- */
+
+/*
+ * idx_probe_random -- random-access probe after the coalescing
+ * micro-benchmark of Section 5.1 (Figure 9): `lanes` threads in groups of
+ * `group` neighbouring lanes; in each of `steps` steps every group reads
+ * `group` consecutive 64-bit words of `buf` at a random group-aligned
+ * position, with 8 independent streams per lane, so one launch performs
+ * lanes * steps * 8 word loads.  It measures the random granule throughput
+ * of the memory system (the ceiling a dependent-load search approaches).
+ *
+ *   buf    device array of `words` uint64 (contents irrelevant)
+ *   group  power of two in [1, 64]; lanes a multiple of 256
+ *   sink   device uint64 written only to keep the loads alive
+ * Enqueued on `stream`.  Errors: IDX_ERR_ARG, IDX_ERR_HIP.
+ */
+int idx_probe_random(const void *buf, uint64_t words, uint32_t group, uint64_t lanes, uint32_t steps,
+                     uint64_t seed, uint64_t *sink, idx_stream stream);
 
 #ifdef __cplusplus
 }

@@ -87,6 +87,7 @@ _U32 = ctypes.c_uint32
 _I = ctypes.c_int
 SIGNATURES = {
     "idx_build": (_I, [_P, _P, _U64, _I, _U32, _U32, ctypes.POINTER(idx_allocator), _P, ctypes.POINTER(_P)]),
+    "idx_relayout": (_I, [_P, _I, _U32, _U32, ctypes.POINTER(idx_allocator), _P, ctypes.POINTER(_P)]),
     "idx_point": (_I, [_P, _P, _U64, _P, _P]),
     "idx_range": (_I, [_P, _P, _P, _U64, _P, _P, _U64, ctypes.POINTER(_U64), _P]),
     "idx_destroy": (_I, [_P]),
@@ -97,7 +98,19 @@ SIGNATURES = {
     "idx_slot_rank": (_U64, [_U64, _U32, _U64]),
     "idx_set_params": (_I, [_P, ctypes.POINTER(idx_lookup_params)]),
     "idx_get_params": (_I, [_P, ctypes.POINTER(idx_lookup_params)]),
+    "idx_probe_random": (_I, [_P, _U64, _U32, _U64, _U32, _U64, _P, _P]),
 }
+
+
+def probe_random(buf: torch.Tensor, group: int, lanes: int, steps: int, seed: int = 1, stream=None):
+    """Launch the random-access probe over `buf` (a device tensor of 8-byte
+    words); returns the number of word loads it issues."""
+    _dev(buf, "buf")
+    sink = torch.zeros(1, dtype=torch.int64, device=buf.device)
+    words = buf.numel() * buf.element_size() // 8
+    _check(lib().idx_probe_random(buf.data_ptr(), words, group, lanes, steps, seed, sink.data_ptr(),
+                                  _stream(stream)), "idx_probe_random")
+    return lanes * steps * 8
 
 
 def lib():
@@ -165,6 +178,24 @@ class Index:
         self._h = h
         self.n = len(keys)
         self.k = kk
+
+    @classmethod
+    def _wrap(cls, h, n, k, layout, key_bits, key_dtype):
+        self = cls.__new__(cls)
+        self._h = h
+        self.n, self.k, self.layout = n, k, layout
+        self.key_bits, self.key_dtype = key_bits, key_dtype
+        return self
+
+    def relayout(self, layout: str, k: int = 9, aos: bool = False, stream=None) -> "Index":
+        """Another layout of this (BS, SoA) index's key set, built by the
+        permutation alone (no second sort)."""
+        lay = LAYOUTS[layout]
+        kk = {IDX_BS: 1, IDX_EBS: 2, IDX_EKS: k}[lay]
+        flags = (IDX_KEY_U64 if self.key_bits == 64 else IDX_KEY_U32) | (IDX_AOS if aos else IDX_SOA)
+        h = ctypes.c_void_p()
+        _check(lib().idx_relayout(self._h, lay, kk, flags, None, _stream(stream), ctypes.byref(h)), "idx_relayout")
+        return Index._wrap(h, self.n, kk, layout, self.key_bits, self.key_dtype)
 
     # -- lifecycle
     def close(self):

@@ -96,12 +96,17 @@ const char *idx_strerror(int status) {
 
 int idx_last_hip_error(void) { return g_last_hip; }
 
-int idx_build(const void *keys, const uint32_t *rowids, uint64_t n, int layout, uint32_t k, uint32_t flags,
-              const idx_allocator *alloc, idx_stream stream, idx_handle *out) {
-    if (!out) return IDX_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// Validates (layout, k, flags, alloc) and creates a handle with its layout
+// buffers allocated.  The first allocation precedes every other HIP call, so
+// an allocator failure is reported without touching the device.
+int new_handle(uint64_t n, int layout, uint32_t k, uint32_t flags, const idx_allocator *alloc, hipStream_t s,
+               idx_index **out) {
     *out = nullptr;
     if (n > IDX_MAX_KEYS) return IDX_ERR_ARG;
-    if (n > 0 && (!keys || !rowids)) return IDX_ERR_ARG;
     if (flags & ~(IDX_KEY_U64 | IDX_AOS)) return IDX_ERR_ARG;
     if (layout == IDX_BS) k = 1;
     else if (layout == IDX_EBS) {
@@ -115,7 +120,6 @@ int idx_build(const void *keys, const uint32_t *rowids, uint64_t n, int layout, 
 
     idx_index *h = new (std::nothrow) idx_index();
     if (!h) return IDX_ERR_NOMEM;
-    hipStream_t s = (hipStream_t)stream;
     h->n = n;
     h->layout = layout;
     h->k = k;
@@ -140,9 +144,6 @@ int idx_build(const void *keys, const uint32_t *rowids, uint64_t n, int layout, 
         h->key_bytes = ps * kb;
         h->row_bytes = ps * 4;
     }
-
-    // The first allocation precedes every other HIP call, so an allocator
-    // failure is reported without touching the device.
     h->keys = h->alloc.get(h->key_bytes, s);
     if (!h->keys) {
         delete h;
@@ -158,6 +159,34 @@ int idx_build(const void *keys, const uint32_t *rowids, uint64_t n, int layout, 
         }
     }
     h->cu_count = cu_count_of_current_device();
+    *out = h;
+    return IDX_OK;
+}
+
+int finish_handle(idx_index *h, hipStream_t s, idx_handle *out) {
+    if (resolve_params(h, nullptr, &h->params) != IDX_OK) {
+        free_handle_buffers(h, s);
+        delete h;
+        return IDX_ERR_ARG;
+    }
+    *out = h;
+    return IDX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int idx_build(const void *keys, const uint32_t *rowids, uint64_t n, int layout, uint32_t k, uint32_t flags,
+              const idx_allocator *alloc, idx_stream stream, idx_handle *out) {
+    if (!out) return IDX_ERR_ARG;
+    *out = nullptr;
+    if (n > 0 && (!keys || !rowids)) return IDX_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    idx_index *h = nullptr;
+    int rc = new_handle(n, layout, k, flags, alloc, s, &h);
+    if (rc != IDX_OK) return rc;
+    const size_t kb = h->u64 ? 8 : 4;
 
     // Temporaries: sorted SoA copy (unless the layout is BS/SoA, which the
     // sort writes directly), sort scratch, check flags.
@@ -176,7 +205,6 @@ int idx_build(const void *keys, const uint32_t *rowids, uint64_t n, int layout, 
     void *sort_tmp = tmp + sorted_kb + sorted_rb;
     uint32_t *dflags = (uint32_t *)(tmp + sorted_kb + sorted_rb + sort_b);
 
-    int rc = IDX_OK;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     uint32_t hflags[2] = {0, 0};
     do {
@@ -218,13 +246,35 @@ int idx_build(const void *keys, const uint32_t *rowids, uint64_t n, int layout, 
         return rc;
     }
     h->unique = hflags[0] == 0;
-    if (resolve_params(h, nullptr, &h->params) != IDX_OK) {
+    return finish_handle(h, s, out);
+}
+
+int idx_relayout(idx_handle src, int layout, uint32_t k, uint32_t flags, const idx_allocator *alloc,
+                 idx_stream stream, idx_handle *out) {
+    if (!out) return IDX_ERR_ARG;
+    *out = nullptr;
+    if (!src || src->layout != IDX_BS || src->aos) return IDX_ERR_ARG;
+    if (((flags & IDX_KEY_U64) != 0) != src->u64) return IDX_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    idx_index *h = nullptr;
+    int rc = new_handle(src->n, layout, k, flags, alloc, s, &h);
+    if (rc != IDX_OK) return rc;
+    h->unique = src->unique;
+    src->last_stream = s;
+    if (layout == IDX_BS && !h->aos) {
+        hipError_t e = hipMemcpyAsync(h->keys, src->keys, src->n * (h->u64 ? 8 : 4), hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(h->rowids, src->rowids, src->n * 4, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) rc = hip_fail(e);
+    } else {
+        rc = build_layout(h, src->keys, src->rowids, s);
+    }
+    if (rc != IDX_OK) {
+        (void)hipStreamSynchronize(s);
         free_handle_buffers(h, s);
         delete h;
-        return IDX_ERR_ARG;
+        return rc;
     }
-    *out = h;
-    return IDX_OK;
+    return finish_handle(h, s, out);
 }
 
 int idx_point(idx_handle h, const void *queries, uint64_t m, uint32_t *out_rowid, idx_stream stream) {

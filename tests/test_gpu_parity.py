@@ -114,6 +114,34 @@ def test_layout_parity(layout, k, aos, bits):
             assert np.array_equal(rows_host(gr), er)
 
 
+@pytest.mark.parametrize("bits", [32, 64])
+def test_relayout_parity(bits):
+    """Layouts permuted from an existing sorted-array index (no second sort)
+    equal the oracle's layouts; the source index is left intact."""
+    for n, kind in ((20011, "unique"), (4097, "dup"), (0, "unique"), (1, "unique")):
+        keys, rows = key_set(n + 5, n, bits, kind)
+        sk, sr = oracle.stable_sort(keys, rows)
+        with build(keys, rows, "bs") as base:
+            for layout, k, aos in (("ebs", 2, False), ("eks", 9, False), ("eks", 17, True), ("eks", 4, False),
+                                   ("bs", 1, True), ("bs", 1, False)):
+                say(f"relayout bits={bits} n={n} {kind} -> {layout} k={k} aos={aos}")
+                with base.relayout(layout, k, aos) as ix:
+                    gk, gr = ix.export()
+                    if layout == "bs":
+                        ek, er = sk, sr
+                    else:
+                        ek, er = oracle.eytzinger_layout(sk, sr, k, one_based=(layout == "ebs"))
+                    assert np.array_equal(to_host(gk, bits), ek)
+                    assert np.array_equal(rows_host(gr), er)
+                    assert ix.info()["unique"] == base.info()["unique"]
+                    check_point(ix, keys, rows, bits, seed=n + k, m=4099)
+            bk, br = base.export()
+            assert np.array_equal(to_host(bk, bits), sk) and np.array_equal(rows_host(br), sr)
+        with build(keys, rows, "ebs") as not_sorted:
+            with pytest.raises(idx.IdxError):
+                not_sorted.relayout("eks", 9)
+
+
 # ----------------------------------------------------------------- points ---
 
 def check_point(ix, keys, rows, bits, seed, m=30011):
