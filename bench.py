@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the k / parameter sweep (use defaults)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="lookups in the CPU oracle sample")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a plain 1 GiB device copy (known bytes) to scale hardware byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -184,22 +186,52 @@ def main():
             ts.append(a.elapsed_time(b))
         return float(np.median(ts)), ok
 
+    if args.calibrate:
+        src = torch.empty(1 << 27, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        log("calibration copy: 1073741824 bytes read, 1073741824 bytes written")
+        del src, dst
+
     # ---------------------------------------------------------------- sweep
     base = idx.Index(keys, rows, layout="bs")
     sweep = []
     candidates = []
     if args.no_sweep:
-        candidates = [("bs", 1, {}), ("ebs", 2, {}), ("eks", 9, {})]
+        candidates = [("bs", 1, False, {}), ("ebs", 2, False, {}), ("eks", 9, False, {})]
     else:
-        candidates += [("bs", 1, {}), ("bs", 1, {"per_lane": 8}), ("bs", 1, {"lds_levels": 12, "persistent": 2}),
-                       ("ebs", 2, {}), ("ebs", 2, {"per_lane": 8}), ("ebs", 2, {"lds_levels": 12, "persistent": 2})]
+        candidates += [("bs", 1, False, {}), ("bs", 1, False, {"per_lane": 8}),
+                       ("bs", 1, False, {"lds_levels": 12, "persistent": 2}),
+                       ("ebs", 2, False, {}), ("ebs", 2, False, {"per_lane": 8}),
+                       ("ebs", 2, False, {"lds_levels": 12, "persistent": 2})]
         for k in (4, 5, 8, 9, 16, 17, 32, 33):
-            candidates.append(("eks", k, {}))
-            candidates.append(("eks", k, {"per_lane": 4}))
-            candidates.append(("eks", k, {"group": 1, "per_lane": 4}))
+            g = k - 1
+            wide = 1 << (g - 1).bit_length()  # one pivot per lane
+            candidates.append(("eks", k, False, {"group": wide, "per_lane": 4}))
+            candidates.append(("eks", k, False, {"group": 1, "per_lane": 4}))
+            if g % 2 == 0:  # 16-byte pivot chunks per lane
+                vg = 1 << ((g // 2) - 1).bit_length()
+                for r in (2, 4, 8):
+                    candidates.append(("eks", k, False, {"group": vg, "per_lane": r}))
+        for k in (9, 17):
+            vg = 1 << (((k - 1) // 2) - 1).bit_length()
+            candidates.append(("eks", k, True, {"group": vg, "per_lane": 4}))
+            candidates.append(("eks", k, "padded", {"group": 1, "per_lane": 4}))
+            candidates.append(("eks", k, "padded", {"group": vg, "per_lane": 4}))
+            candidates.append(("eks", k, "padded", {"group": 1, "per_lane": 4, "lds_levels": 3, "persistent": 2,
+                                                    "block": 1024}))
+            candidates.append(("eks", k, True, {"group": 1, "per_lane": 4}))
+            lds = 4 if k == 9 else 3  # top levels that fit 64 KiB of LDS
+            candidates.append(("eks", k, False, {"group": vg, "per_lane": 4, "lds_levels": lds, "persistent": 2,
+                                                 "block": 1024}))
+            candidates.append(("eks", k, False, {"group": 1, "per_lane": 4, "lds_levels": lds, "persistent": 2,
+                                                 "block": 1024}))
     best_by_layout = {}
-    for layout, k, params in candidates:
-        ix = base if layout == "bs" else base.relayout(layout, k)
+    for layout, k, aos, params in candidates:
+        ix = base if (layout == "bs" and not aos) else base.relayout(layout, k, aos)
         try:
             ix.set_params(**params)
         except idx.IdxError:
@@ -207,10 +239,10 @@ def main():
                 ix.close()
             continue
         ms, ok = time_point(ix, reps=3, check=True)
-        rec = {"layout": layout, "k": k, "params": ix.params(), "ms": round(ms, 4), "lookups_per_s": m / ms * 1e3,
-               "bit_exact": ok}
+        rec = {"layout": layout, "k": k, "aos": aos, "params": ix.params(), "ms": round(ms, 4),
+               "lookups_per_s": m / ms * 1e3, "bit_exact": ok}
         sweep.append(rec)
-        log(f"sweep {layout} k={k} {params}: {ms:.3f} ms  {m / ms / 1e6:.1f} M/s  exact={ok}")
+        log(f"sweep {layout} k={k} aos={aos} {params}: {ms:.3f} ms  {m / ms / 1e6:.2f} G lookups/s  exact={ok}")
         key = layout
         if ok and (key not in best_by_layout or ms < best_by_layout[key]["ms"]):
             best_by_layout[key] = rec
@@ -234,11 +266,11 @@ def main():
         a = ev()
         bs = idx.Index(keys, rows, layout="bs")
         b = ev()
-        hs = {"BS": bs}
+        hs = {"BS": bs if not forms[0][1]["aos"] else bs.relayout("bs", 1, True)}
         marks = [("build_sort", a, b)]
         for name, rec in forms[1:]:
             a = ev()
-            hs[name] = bs.relayout(rec["layout"], rec["k"])
+            hs[name] = bs.relayout(rec["layout"], rec["k"], rec["aos"])
             b = ev()
             marks.append((f"build_permute_{name}", a, b))
         for name, rec in forms:
@@ -353,7 +385,8 @@ def main():
         "range_lookups_per_s": {k[6:]: mr / v * 1e3 for k, v in mean.items() if k.startswith("range_")},
         "bit_exact": all(r["bit_exact"] for r in sweep),
         "random_access": probe,
-        "sweep": [{kk: r[kk] for kk in ("layout", "k", "params", "ms", "lookups_per_s", "bit_exact")} for r in sweep],
+        "sweep": [{kk: r[kk] for kk in ("layout", "k", "aos", "params", "ms", "lookups_per_s", "bit_exact")}
+                  for r in sweep],
     }
     print(json.dumps(line), flush=True)
 

@@ -50,6 +50,8 @@ typedef void *idx_stream;             /* hipStream_t */
 #define IDX_KEY_U64 1u /* keys are uint64 */
 #define IDX_SOA 0u     /* rowids in an array parallel to the keys (Section 7.1) */
 #define IDX_AOS 2u     /* rowids interleaved with the keys (Section 7.1); see idx_build */
+#define IDX_AOS_PADDED 4u /* with IDX_AOS: each node block padded to a power of two bytes (whole cache
+                             lines), so a node's row IDs share its keys' line; larger footprint */
 
 /* point-lookup miss sentinel; also a reserved row ID value */
 #define IDX_MISS 0xFFFFFFFFu
@@ -100,6 +102,8 @@ typedef struct idx_allocator {
  *   flags    IDX_KEY_U32 or IDX_KEY_U64, OR-ed with IDX_SOA or IDX_AOS.
  *            AoS stores each node's k-1 keys followed by its k-1 row IDs
  *            (node = one key for BS and EBS), same footprint as SoA.
+ *            IDX_AOS | IDX_AOS_PADDED rounds every such block up to a power
+ *            of two bytes (e.g. 96 -> 128 for k = 9 with 64-bit keys).
  *   alloc    allocator for the handle and the build's temporaries, or NULL
  *   stream   stream to build on
  *   out      receives the handle (set to NULL on failure)

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libidx.so")
 
 IDX_BS, IDX_EBS, IDX_EKS = 0, 1, 2
-IDX_KEY_U32, IDX_KEY_U64, IDX_SOA, IDX_AOS = 0, 1, 0, 2
+IDX_KEY_U32, IDX_KEY_U64, IDX_SOA, IDX_AOS, IDX_AOS_PADDED = 0, 1, 0, 2, 4
 IDX_MISS = 0xFFFFFFFF
 IDX_OK = 0
 IDX_ERR_ARG = -1
@@ -146,6 +146,12 @@ def _key_flag(t: torch.Tensor) -> int:
     raise TypeError("keys must be 32- or 64-bit integers (their bits are read as unsigned)")
 
 
+def _aos_flags(aos) -> int:
+    if aos == "padded":
+        return IDX_AOS | IDX_AOS_PADDED
+    return IDX_AOS if aos else IDX_SOA
+
+
 def _dev(t: torch.Tensor, name: str):
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous device tensor")
@@ -170,7 +176,7 @@ class Index:
         self.key_dtype = keys.dtype
         lay = LAYOUTS[layout]
         kk = {IDX_BS: 1, IDX_EBS: 2, IDX_EKS: k}[lay]
-        flags = _key_flag(keys) | (IDX_AOS if aos else IDX_SOA)
+        flags = _key_flag(keys) | _aos_flags(aos)
         h = ctypes.c_void_p()
         st = lib().idx_build(keys.data_ptr(), rowids.data_ptr(), len(keys), lay, kk, flags, None, _stream(stream),
                              ctypes.byref(h))
@@ -187,12 +193,12 @@ class Index:
         self.key_bits, self.key_dtype = key_bits, key_dtype
         return self
 
-    def relayout(self, layout: str, k: int = 9, aos: bool = False, stream=None) -> "Index":
+    def relayout(self, layout: str, k: int = 9, aos: bool | str = False, stream=None) -> "Index":
         """Another layout of this (BS, SoA) index's key set, built by the
-        permutation alone (no second sort)."""
+        permutation alone (no second sort).  aos: False, True or "padded"."""
         lay = LAYOUTS[layout]
         kk = {IDX_BS: 1, IDX_EBS: 2, IDX_EKS: k}[lay]
-        flags = (IDX_KEY_U64 if self.key_bits == 64 else IDX_KEY_U32) | (IDX_AOS if aos else IDX_SOA)
+        flags = (IDX_KEY_U64 if self.key_bits == 64 else IDX_KEY_U32) | _aos_flags(aos)
         h = ctypes.c_void_p()
         _check(lib().idx_relayout(self._h, lay, kk, flags, None, _stream(stream), ctypes.byref(h)), "idx_relayout")
         return Index._wrap(h, self.n, kk, layout, self.key_bits, self.key_dtype)

@@ -107,7 +107,8 @@ int new_handle(uint64_t n, int layout, uint32_t k, uint32_t flags, const idx_all
                idx_index **out) {
     *out = nullptr;
     if (n > IDX_MAX_KEYS) return IDX_ERR_ARG;
-    if (flags & ~(IDX_KEY_U64 | IDX_AOS)) return IDX_ERR_ARG;
+    if (flags & ~(IDX_KEY_U64 | IDX_AOS | IDX_AOS_PADDED)) return IDX_ERR_ARG;
+    if ((flags & IDX_AOS_PADDED) && !(flags & IDX_AOS)) return IDX_ERR_ARG;
     if (layout == IDX_BS) k = 1;
     else if (layout == IDX_EBS) {
         if (k != 2) return IDX_ERR_ARG;
@@ -138,7 +139,14 @@ int new_handle(uint64_t n, int layout, uint32_t k, uint32_t flags, const idx_all
     const uint64_t ps = padded_slots(h->slots);
     if (h->aos) {
         const uint64_t blocks = (ps + h->node - 1) / h->node;
-        h->key_bytes = blocks * h->node * (kb + 4);
+        uint32_t stride = h->node * (uint32_t)(kb + 4);
+        if (flags & IDX_AOS_PADDED) {
+            uint32_t p2 = 16;
+            while (p2 < stride) p2 <<= 1;
+            stride = p2;
+        }
+        h->stride = stride;
+        h->key_bytes = blocks * stride;
         h->row_bytes = 0;
     } else {
         h->key_bytes = ps * kb;
@@ -310,7 +318,8 @@ int idx_get_info(idx_handle h, idx_info *o) {
     idx_info i{};
     i.n = h->n;
     i.slots = h->slots;
-    i.footprint_bytes = h->slots * ((h->u64 ? 8 : 4) + 4);
+    i.footprint_bytes = h->aos ? ((h->slots + h->node - 1) / h->node) * h->stride
+                               : h->slots * ((h->u64 ? 8 : 4) + 4);
     i.layout = h->layout;
     i.k = h->k;
     i.flags = h->flags;

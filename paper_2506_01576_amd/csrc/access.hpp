@@ -2,7 +2,9 @@
 //   SoA: keys[s] and rowids[s] in two arrays;
 //   AoS: blocks of `node` slots, each block holding its node keys followed by
 //        its node rowids (node = k - 1 for EKS, 1 for BS/EBS), so a node's
-//        keys stay contiguous and aligned and the footprint equals SoA.
+//        keys stay contiguous and the footprint equals SoA; optionally each
+//        block is padded to a power of two bytes (`stride`) so it occupies
+//        whole cache lines.
 // 64-bit keys in AoS blocks may be only 4-byte aligned; they are moved as two
 // 32-bit words.
 #pragma once
@@ -53,7 +55,8 @@ struct Load<K, true> {
     const char *__restrict__ base;
     const uint32_t *r_unused;
     uint32_t node;
-    __device__ __forceinline__ uint64_t block_bytes() const { return (uint64_t)node * (sizeof(K) + 4); }
+    uint32_t stride;  // bytes per block: node * (sizeof(K) + 4), or padded to a power of two
+    __device__ __forceinline__ uint64_t block_bytes() const { return stride; }
     __device__ __forceinline__ K nkey(uint64_t c, uint32_t j) const {
         return load_key_words<K>(base + c * block_bytes() + (uint64_t)j * sizeof(K));
     }
@@ -92,10 +95,11 @@ struct Store<K, true> {
     char *__restrict__ base;
     uint32_t *r_unused;
     uint32_t node;
+    uint32_t stride;
     __device__ __forceinline__ void put(uint64_t s, K key, uint32_t row) const {
         const uint64_t c = node == 1 ? s : s / node;
         const uint32_t j = (uint32_t)(s - c * node);
-        char *blk = base + c * (uint64_t)node * (sizeof(K) + 4);
+        char *blk = base + c * (uint64_t)stride;
         store_key_words<K>(blk + (uint64_t)j * sizeof(K), key);
         *(uint32_t *)(blk + (uint64_t)node * sizeof(K) + (uint64_t)j * 4) = row;
     }
@@ -107,6 +111,7 @@ inline Load<K, AOS> make_load(const idx_index *h) {
     if constexpr (AOS) {
         L.base = (const char *)h->keys;
         L.r_unused = nullptr;
+        L.stride = h->stride;
     } else {
         L.k = (const K *)h->keys;
         L.r = h->rowids;
@@ -121,6 +126,7 @@ inline Store<K, AOS> make_store(idx_index *h) {
     if constexpr (AOS) {
         S.base = (char *)h->keys;
         S.r_unused = nullptr;
+        S.stride = h->stride;
     } else {
         S.k = (K *)h->keys;
         S.r = h->rowids;

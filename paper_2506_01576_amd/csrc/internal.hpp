@@ -55,6 +55,7 @@ struct idx_index {
     bool aos = false;
     bool unique = true;
     uint32_t node = 1;  // keys per AoS block (k - 1 for EKS, 1 otherwise)
+    uint32_t stride = 0;  // bytes per AoS block
     void *keys = nullptr;       // SoA keys or AoS blocks
     uint32_t *rowids = nullptr; // SoA rowids (nullptr for AoS)
     size_t key_bytes = 0, row_bytes = 0;

@@ -233,6 +233,98 @@ __global__ __launch_bounds__(1024) void k_point_eks_group(PointArgs<K, AOS> a) {
     }
 }
 
+// --------------------------------------------------------- EKS vector group
+
+// VG lanes per lookup, each lane reading V = 16 / sizeof(K) consecutive
+// pivots with one 16-byte load, so a node of up to VG*V pivots arrives with
+// one load instruction per lane group (a 64-byte node of 8 u64 keys: 4 lanes).
+// j = sum over the V key positions of popcount(ballot(key_e < x) & group).
+// Requires 16-byte aligned nodes (k-1 a multiple of V; AoS blocks too).
+template <typename K, bool AOS, int VG, int R>
+__global__ __launch_bounds__(1024) void k_point_eks_vgroup(PointArgs<K, AOS> a) {
+    extern __shared__ __align__(16) char smem[];
+    K *s_pin = (K *)smem;
+    if (a.pin_levels) load_pin(s_pin, a.pin, a.pin_entries);
+    constexpr int V = 16 / sizeof(K);
+    constexpr int GPW = kWave / VG;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t sub = lane & (VG - 1);
+    const uint32_t grp = lane / VG;
+    const uint64_t gmask = (VG == kWave) ? ~0ull : (((1ull << VG) - 1ull) << (grp * VG));
+    const uint64_t n = a.G.n;
+    const uint32_t g = a.G.g;
+    const uint32_t kf = a.G.k;
+    const uint32_t first = sub * V;  // first pivot of this lane within the node
+    const uint32_t waves = blockDim.x / kWave;
+    const uint32_t wave = threadIdx.x / kWave;
+    const uint64_t tile = (uint64_t)waves * GPW * R;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < a.m; t0 += (uint64_t)gridDim.x * tile) {
+        const uint64_t wbase = t0 + (uint64_t)wave * GPW * R;
+        K x[R];
+        uint64_t c[R], cand[R];
+        bool ceq[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = wbase + (uint64_t)r * GPW + grp;
+            x[r] = qi < a.m ? a.q[qi] : K(0);
+            c[r] = qi < a.m ? 0 : ~0ull;
+            cand[r] = 0;
+            ceq[r] = false;
+        }
+        for (uint32_t lvl = 0; lvl < a.G.levels; ++lvl) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const bool live = c[r] != ~0ull;
+                const uint64_t i = live ? c[r] * g : n;
+                const bool lane_live = live && first < g && i + first < n;
+                K kk[V];
+#pragma unroll
+                for (int e = 0; e < V; ++e) kk[e] = key_max<K>();
+                if (lane_live) {
+                    uint4 w;
+                    if (lvl < a.pin_levels) w = *(const uint4 *)(s_pin + i + first);
+                    else w = *(const uint4 *)(a.L.node_ptr(c[r]) + first);
+                    if constexpr (sizeof(K) == 8) {
+                        kk[0] = ((uint64_t)w.y << 32) | w.x;
+                        kk[1] = ((uint64_t)w.w << 32) | w.z;
+                    } else {
+                        kk[0] = w.x;
+                        kk[1] = w.y;
+                        kk[2] = w.z;
+                        kk[3] = w.w;
+                    }
+                }
+                uint32_t j = 0;
+                bool eql = false;
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const bool valid = lane_live && first + e < g && i + first + e < n;
+                    j += (uint32_t)__popcll(__ballot(valid && kk[e] < x[r]) & gmask);
+                    eql |= valid && kk[e] == x[r];
+                }
+                const uint64_t eq = __ballot(eql) & gmask;
+                if (live) {
+                    const uint64_t nv = (n - i) < g ? (n - i) : g;
+                    if (j < nv) {
+                        cand[r] = i + j;
+                        ceq[r] = eq != 0;
+                    }
+                    const uint64_t child = c[r] * kf + 1 + j;
+                    const bool stop = (a.early && eq != 0) || child * g >= n;
+                    c[r] = stop ? ~0ull : child;
+                }
+            }
+        }
+        if (sub == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t qi = wbase + (uint64_t)r * GPW + grp;
+                if (qi < a.m) a.out[qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
+            }
+        }
+    }
+}
+
 // -------------------------------------------------------------- EKS single
 
 // One lane per lookup.  GMAX = pivots read per node (>= k-1); VEC = nodes are
@@ -383,13 +475,25 @@ int run_group(const idx_index *h, const idx_lookup_params &p, const void *q, uin
     return IDX_OK;
 }
 
+template <typename K, bool AOS, int VG, int R>
+int run_vgroup(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out,
+               hipStream_t s) {
+    auto a = make_args<K, AOS>(h, q, m, out, p.lds_levels, p.early_exit == 1 && h->unique);
+    const Launch L = plan(h, p, m, (uint64_t)(p.block / kWave) * (kWave / VG) * R);
+    hipLaunchKernelGGL((k_point_eks_vgroup<K, AOS, VG, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+    IDX_LAUNCH_CHECK();
+    return IDX_OK;
+}
+
 template <typename K, bool AOS, int GMAX, int R>
 int run_single(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out,
                hipStream_t s) {
     auto a = make_args<K, AOS>(h, q, m, out, p.lds_levels, p.early_exit == 1 && h->unique);
     const Launch L = plan(h, p, m, (uint64_t)p.block * R);
-    constexpr bool vec_ok = !AOS && (GMAX * sizeof(K)) % 16 == 0;
-    if (vec_ok && h->geo.g == GMAX)
+    // 16-byte node loads need 16-byte aligned nodes: SoA nodes of GMAX keys,
+    // or AoS blocks whose stride is a multiple of 16
+    constexpr bool vec_ok = (GMAX * sizeof(K)) % 16 == 0;
+    if (vec_ok && h->geo.g == GMAX && (!AOS || h->stride % 16 == 0))
         hipLaunchKernelGGL((k_point_eks_single<K, AOS, GMAX, vec_ok, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
     else
         hipLaunchKernelGGL((k_point_eks_single<K, AOS, GMAX, false, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
@@ -424,6 +528,19 @@ int point_t(const idx_index *h, const idx_lookup_params &p, const void *q, uint6
             return run_single<K, AOS, 32, RR>(h, p, q, m, out, s);
         });
     }
+    if (p.group < h->geo.g) {
+        return with_r<0>(p.per_lane, [&](auto R) {
+            constexpr int RR = decltype(R)::value;
+            switch (p.group) {
+                case 2: return run_vgroup<K, AOS, 2, RR>(h, p, q, m, out, s);
+                case 4: return run_vgroup<K, AOS, 4, RR>(h, p, q, m, out, s);
+                case 8: return run_vgroup<K, AOS, 8, RR>(h, p, q, m, out, s);
+                case 16: return run_vgroup<K, AOS, 16, RR>(h, p, q, m, out, s);
+                case 32: return run_vgroup<K, AOS, 32, RR>(h, p, q, m, out, s);
+                default: return IDX_ERR_ARG;
+            }
+        });
+    }
     return with_r<0>(p.per_lane, [&](auto R) {
         constexpr int RR = decltype(R)::value;
         switch (p.group) {
@@ -451,8 +568,19 @@ int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_p
     if (in) p = *in;
     const uint32_t g = h->layout == IDX_EKS ? h->geo.g : 1;
     if (h->layout == IDX_EKS) {
-        if (p.group == 0) p.group = pow2_at_least(g);
-        if (p.group != 1 && (p.group < g || p.group > 64 || (p.group & (p.group - 1)))) return IDX_ERR_ARG;
+        // lanes per lookup: 1 = single; >= k-1 = one pivot per lane; fewer =
+        // 16-byte pivot chunks per lane (vector group)
+        const uint32_t V = 16 / (h->u64 ? 8 : 4);
+        const bool vec_ok = g % V == 0 && (!h->aos || h->stride % 16 == 0);
+        const uint32_t vg = pow2_at_least((g + V - 1) / V);
+        // Default (measured on MI355X): one lane per lookup reading the node
+        // with 16-byte loads when the node is at most 64 bytes and aligned;
+        // otherwise 16-byte chunks over a lane group; otherwise one pivot per lane.
+        const uint32_t node_bytes = g * (h->u64 ? 8 : 4);
+        const bool single_vec = (!h->aos || h->stride % 16 == 0) && node_bytes % 16 == 0 && node_bytes <= 64;
+        if (p.group == 0) p.group = single_vec ? 1 : (vec_ok && vg < g) ? vg : pow2_at_least(g);
+        if (p.group > 64 || (p.group & (p.group - 1))) return IDX_ERR_ARG;
+        if (p.group != 1 && p.group < g && !(vec_ok && p.group >= vg && p.group <= 32)) return IDX_ERR_ARG;
         // EKS (single) keeps a whole node in registers: at most 32 pivots
         if (p.group == 1 && g > 32) return IDX_ERR_ARG;
     } else {

@@ -56,6 +56,7 @@ def test_build_argument_errors():
     assert _build(keys=None)[0] == E
     assert _build(rows=None)[0] == E
     assert _build(flags=8)[0] == E
+    assert _build(flags=idx.IDX_AOS_PADDED)[0] == E  # padding only applies to AoS
     st, h = _build()
     assert h.value is None
 

@@ -97,7 +97,7 @@ LAYOUT_CASES = [("ebs", 2)] + [("eks", k) for k in (2, 3, 4, 5, 8, 9, 16, 17, 32
 
 
 @pytest.mark.parametrize("bits", [32, 64])
-@pytest.mark.parametrize("aos", [False, True])
+@pytest.mark.parametrize("aos", [False, True, "padded"])
 @pytest.mark.parametrize("layout,k", LAYOUT_CASES)
 def test_layout_parity(layout, k, aos, bits):
     """Eytzinger layouts built by the closed-form permutation equal the
@@ -160,31 +160,29 @@ POINT_PARAMS = {
             {"lds_levels": 2}],
     "eks": [{}, {"group": 1}, {"group": 1, "per_lane": 8}, {"per_lane": 1, "block": 1024},
             {"per_lane": 8, "early_exit": 2}, {"lds_levels": 2, "persistent": 1}, {"group": 64},
-            {"group": 1, "lds_levels": 2}],
+            {"group": 1, "lds_levels": 2}, {"group": 2}, {"group": 4, "per_lane": 8}, {"group": 8, "per_lane": 1},
+            {"group": 16, "lds_levels": 2, "persistent": 2}, {"group": 4, "early_exit": 2, "lds_levels": 1}],
 }
 
 
-def resolve(ix, p, layout, k):
+def resolve(ix, p):
+    """Apply a parameter set, lowering lds_levels to what the tree and LDS
+    allow; returns False for a set the index does not support (e.g. a lane
+    group narrower than its node without 16-byte aligned nodes)."""
     p = dict(p)
-    info = ix.info()
-    if "lds_levels" in p:
-        # clamp to what the tree has (and what fits 64 KiB of LDS)
-        lim = info["full_levels"] if layout != "bs" else max(0, int(np.ceil(np.log2(max(info["n"], 1)))) - 1)
-        while p["lds_levels"] > 0:
-            try:
-                ix.set_params(**p)
-                return p
-            except idx.IdxError:
+    while True:
+        try:
+            ix.set_params(**p)
+            return True
+        except idx.IdxError:
+            if p.get("lds_levels", 0) > 0:
                 p["lds_levels"] -= 1
-        p.pop("lds_levels")
-    if layout == "eks" and p.get("group", 0) > 1 and p["group"] < k - 1:
-        p["group"] = 1
-    ix.set_params(**p)
-    return p
+            else:
+                return False
 
 
 @pytest.mark.parametrize("bits", [32, 64])
-@pytest.mark.parametrize("aos", [False, True])
+@pytest.mark.parametrize("aos", [False, True, "padded"])
 @pytest.mark.parametrize("layout,k", [("bs", 1), ("ebs", 2)] + [("eks", k) for k in (3, 4, 5, 8, 9, 16, 17, 32, 33)])
 def test_point_parity(layout, k, aos, bits):
     for n, kind in ((20011, "unique"), (20011, "dup"), (4096, "extreme"), (k * k, "unique"), (1, "unique"),
@@ -192,7 +190,8 @@ def test_point_parity(layout, k, aos, bits):
         keys, rows = key_set(n * 13 + k, n, bits, kind)
         with build(keys, rows, layout, k, aos) as ix:
             for p in POINT_PARAMS["eks" if layout == "eks" else layout]:
-                pp = resolve(ix, p, layout, k)
+                if not resolve(ix, p):
+                    continue
                 say(f"point {layout} k={k} aos={aos} bits={bits} n={n} {kind} params={ix.params()}")
                 check_point(ix, keys, rows, bits, seed=n + k)
                 ix.reset_params()
@@ -231,7 +230,7 @@ def check_range(ix, keys, rows, bits, seed, m=5003):
 
 
 @pytest.mark.parametrize("bits", [32, 64])
-@pytest.mark.parametrize("aos", [False, True])
+@pytest.mark.parametrize("aos", [False, True, "padded"])
 @pytest.mark.parametrize("layout,k", [("bs", 1), ("ebs", 2)] + [("eks", k) for k in (3, 5, 8, 9, 17, 33)])
 def test_range_parity(layout, k, aos, bits):
     for n, kind in ((20011, "unique"), (20011, "dup"), (3000, "extreme"), (k * k + 1, "unique"), (1, "unique"),
@@ -257,7 +256,14 @@ def test_bad_params_rejected():
     keys, rows = key_set(1, 5000, 32)
     with build(keys, rows, "eks", 9) as ix:
         before = ix.params()
-        for bad in ({"group": 4}, {"group": 3}, {"block": 96}, {"per_lane": 3}, {"lds_levels": 30}):
+        for bad in ({"group": 128}, {"group": 3}, {"block": 96}, {"per_lane": 3}, {"lds_levels": 30},
+                    {"early_exit": 3}, {"reorder": 2}):
             with pytest.raises(idx.IdxError):
                 ix.set_params(**bad)
             assert ix.params() == before
+        ix.set_params(group=2)  # 4 u32 pivots per lane
+        ix.set_params(group=8)  # one pivot per lane
+    with build(keys, rows, "eks", 8) as ix:  # 7 pivots: nodes are not 16-byte aligned
+        with pytest.raises(idx.IdxError):
+            ix.set_params(group=4)
+        ix.set_params(group=8)
