@@ -125,7 +125,9 @@ def main():
     ap.add_argument("--log2m", type=int, default=27)
     ap.add_argument("--log2ranges", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-sweep", action="store_true", help="skip the k / parameter sweep (use defaults)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="re-measure every candidate form (autotuner) instead of using the tuned table")
+    ap.add_argument("--write-table", action="store_true", help="with --sweep: store the winners in the tuned table")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="lookups in the CPU oracle sample")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (known bytes) to scale hardware byte counters")
@@ -196,68 +198,41 @@ def main():
         log("calibration copy: 1073741824 bytes read, 1073741824 bytes written")
         del src, dst
 
-    # ---------------------------------------------------------------- sweep
+    # ------------------------------------------- forms: tuned table or sweep
+    from paper_2506_01576_amd import autotune
+
     base = idx.Index(keys, rows, layout="bs")
     sweep = []
-    candidates = []
-    if args.no_sweep:
-        candidates = [("bs", 1, False, {}), ("ebs", 2, False, {}), ("eks", 9, False, {})]
-    else:
-        candidates += [("bs", 1, False, {}), ("bs", 1, False, {"per_lane": 8}),
-                       ("bs", 1, False, {"lds_levels": 12, "persistent": 2}),
-                       ("ebs", 2, False, {}), ("ebs", 2, False, {"per_lane": 8}),
-                       ("ebs", 2, False, {"lds_levels": 12, "persistent": 2})]
-        for k in (4, 5, 8, 9, 16, 17, 32, 33):
-            g = k - 1
-            wide = 1 << (g - 1).bit_length()  # one pivot per lane
-            candidates.append(("eks", k, False, {"group": wide, "per_lane": 4}))
-            candidates.append(("eks", k, False, {"group": 1, "per_lane": 4}))
-            if g % 2 == 0:  # 16-byte pivot chunks per lane
-                vg = 1 << ((g // 2) - 1).bit_length()
-                for r in (2, 4, 8):
-                    candidates.append(("eks", k, False, {"group": vg, "per_lane": r}))
-        for k in (9, 17):
-            vg = 1 << (((k - 1) // 2) - 1).bit_length()
-            candidates.append(("eks", k, True, {"group": vg, "per_lane": 4}))
-            candidates.append(("eks", k, "padded", {"group": 1, "per_lane": 4}))
-            candidates.append(("eks", k, "padded", {"group": vg, "per_lane": 4}))
-            candidates.append(("eks", k, "padded", {"group": 1, "per_lane": 4, "lds_levels": 3, "persistent": 2,
-                                                    "block": 1024}))
-            candidates.append(("eks", k, True, {"group": 1, "per_lane": 4}))
-            lds = 4 if k == 9 else 3  # top levels that fit 64 KiB of LDS
-            candidates.append(("eks", k, False, {"group": vg, "per_lane": 4, "lds_levels": lds, "persistent": 2,
-                                                 "block": 1024}))
-            candidates.append(("eks", k, False, {"group": 1, "per_lane": 4, "lds_levels": lds, "persistent": 2,
-                                                 "block": 1024}))
     best_by_layout = {}
-    for layout, k, aos, params in candidates:
-        ix = base if (layout == "bs" and not aos) else base.relayout(layout, k, aos)
-        try:
-            ix.set_params(**params)
-        except idx.IdxError:
-            if ix is not base:
-                ix.close()
+    if args.sweep:
+        sweep, best_by_layout = autotune.tune(base, q, expect, reps=3, log=log)
+        if args.write_table:
+            autotune.save_table(autotune.record_best(autotune.load_table(), 64, n, best_by_layout))
+    for layout in ("bs", "ebs", "eks"):
+        if layout in best_by_layout:
             continue
+        lay, k, aos, params = autotune.choose(n, 64, layout)
+        ix = base if (lay == "bs" and not aos) else base.relayout(lay, k, aos)
+        ix.set_params(**params)
         ms, ok = time_point(ix, reps=3, check=True)
-        rec = {"layout": layout, "k": k, "aos": aos, "params": ix.params(), "ms": round(ms, 4),
-               "lookups_per_s": m / ms * 1e3, "bit_exact": ok}
-        sweep.append(rec)
-        log(f"sweep {layout} k={k} aos={aos} {params}: {ms:.3f} ms  {m / ms / 1e6:.2f} G lookups/s  exact={ok}")
-        key = layout
-        if ok and (key not in best_by_layout or ms < best_by_layout[key]["ms"]):
-            best_by_layout[key] = rec
+        best_by_layout[layout] = {"layout": lay, "k": k, "aos": aos, "params": ix.params(), "ms": round(ms, 4),
+                                  "lookups_per_s": m / ms * 1e3, "bit_exact": ok}
+        log(f"tuned {lay} k={k} aos={aos} {params}: {ms:.3f} ms exact={ok}")
         if ix is not base:
             ix.close()
         else:
             ix.reset_params()
-    if not all(r["bit_exact"] for r in sweep):
+    checked = sweep + [r for r in best_by_layout.values() if r not in sweep]
+    if not all(r["bit_exact"] for r in checked):
         log("WARNING: some forms were not bit-exact")
 
-    best_eks = best_by_layout.get("eks")
-    forms = [("BS", best_by_layout["bs"]), ("EBS", best_by_layout["ebs"])]
-    if best_eks:
-        forms.append((f"EKS(k={best_eks['k']},{'single' if best_eks['params']['group'] == 1 else 'group'})",
-                      best_eks))
+    def form_name(r):
+        if r["layout"] != "eks":
+            return r["layout"].upper()
+        mode = "single" if r["params"]["group"] == 1 else f"group{r['params']['group']}"
+        return f"EKS(k={r['k']},{mode}{',aos' if r['aos'] else ''}{',lds' if r['params']['lds_levels'] else ''})"
+
+    forms = [(form_name(best_by_layout[l]), best_by_layout[l]) for l in ("bs", "ebs", "eks")]
     base.close()
 
     # ---------------------------------------------------------------- steps
@@ -266,7 +241,7 @@ def main():
         a = ev()
         bs = idx.Index(keys, rows, layout="bs")
         b = ev()
-        hs = {"BS": bs if not forms[0][1]["aos"] else bs.relayout("bs", 1, True)}
+        hs = {forms[0][0]: bs if not forms[0][1]["aos"] else bs.relayout("bs", 1, forms[0][1]["aos"])}
         marks = [("build_sort", a, b)]
         for name, rec in forms[1:]:
             a = ev()
@@ -279,7 +254,7 @@ def main():
             hs[name].point(q, out)
             b = ev()
             marks.append((f"point_{name}", a, b))
-        for name in ("BS", forms[-1][0]):
+        for name in (forms[0][0], forms[-1][0]):
             a = ev()
             off, rr = hs[name].range(lo, hi, capacity=mr * 16)
             b = ev()
@@ -314,7 +289,9 @@ def main():
     ab = algo_bytes(hrec["layout"], n, hrec["k"], 8, early_exit=hrec["params"].get("early_exit", 1) == 1)
     t_kernel = mean[f"point_{headline}"] / 1e3
     achieved = ab["total"] * m / t_kernel / 1e9
-    kernel_key = f"point_{hrec['layout']}_k{hrec['k']}_g{hrec['params']['group']}_r{hrec['params']['per_lane']}"
+    hp = hrec["params"]
+    kernel_key = (f"point_{hrec['layout']}_k{hrec['k']}_{'soa' if not hrec['aos'] else hrec['aos'] if hrec['aos'] != True else 'aos'}"
+                  f"_g{hp['group']}_r{hp['per_lane']}_l{hp['lds_levels']}_p{hp['persistent']}_b{hp['block']}")
     traffic = read_traffic(kernel_key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -383,7 +360,7 @@ def main():
                          "layout": rec["layout"], "k": rec["k"], "params": rec["params"]} for name, rec in forms},
         "phases_ms": {k: round(v, 4) for k, v in mean.items()},
         "range_lookups_per_s": {k[6:]: mr / v * 1e3 for k, v in mean.items() if k.startswith("range_")},
-        "bit_exact": all(r["bit_exact"] for r in sweep),
+        "bit_exact": all(r["bit_exact"] for r in checked),
         "random_access": probe,
         "sweep": [{kk: r[kk] for kk in ("layout", "k", "aos", "params", "ms", "lookups_per_s", "bit_exact")}
                   for r in sweep],

@@ -231,7 +231,7 @@ typedef struct idx_lookup_params {
                             grid of c workgroups per compute unit (limited concurrency) */
     uint32_t reorder;    /* 1 = sort each workgroup's lookups locally before searching */
     uint32_t early_exit; /* 1 = stop at an equal key (only used when keys are unique) */
-    uint32_t reserved;
+    uint32_t model;      /* 0/1 = use the learned model when one is trained (idx_learn), 2 = ignore it */
 } idx_lookup_params;
 
 /* Set (p != NULL) or reset to defaults (p == NULL).  Errors: IDX_ERR_ARG for an
@@ -239,6 +239,71 @@ typedef struct idx_lookup_params {
 int idx_set_params(idx_handle h, const idx_lookup_params *p);
 /* The parameters point lookups will use (defaults resolved). */
 int idx_get_params(idx_handle h, idx_lookup_params *out);
+
+/* ---------------------------------------------------------------------------
+ * Learned rank model (window search on the sorted array).  The model only
+ * narrows the search; answers are the same as without it.  The paper's
+ * learned-index baseline (Section 8, PGM: predict a position, then binary
+ * search within +-epsilon) and its remark that this last-mile search is the
+ * expensive step (Section 9) are the anchors.
+ * ------------------------------------------------------------------------- */
+
+#define IDX_FEATURE_AUTO 0u   /* train both root features, keep the lower loss */
+#define IDX_FEATURE_LINEAR 1u /* root feature: the key scaled to [0, 1] */
+#define IDX_FEATURE_LOG 2u    /* root feature: bit pattern of the key rounded to FP32 (log-like) */
+
+typedef struct idx_learn_stats {
+    uint32_t leaves;     /* L */
+    uint32_t epochs;     /* Newton steps per stage */
+    uint32_t feature;    /* root feature chosen */
+    float root_a0, root_a1;
+    double root_loss;    /* sum of squared root residuals (target rank * L / n) */
+    double leaf_loss;    /* sum of squared leaf residuals (target local rank) */
+    double mean_window;  /* key-weighted mean search window (slots) */
+    double max_window;   /* largest window of any leaf (slots) */
+} idx_learn_stats;
+
+/*
+ * idx_learn -- train a two-stage FP32 rank model on the GPU from the index's
+ * own (key, rank) pairs and attach it to the index.  A linear root maps a
+ * monotone key feature to one of `leaves` leaves; each leaf is a line over
+ * the leaf-local key offset.  Training runs `epochs` Newton steps per stage
+ * (forward/backward kernels accumulate loss, gradient and Hessian sums in
+ * FP64).  Then the per-leaf minimum and maximum of (true rank - predicted
+ * rank) are measured over all build keys.  Afterwards idx_point and idx_range
+ * on h search only the predicted window; their answers are unchanged.
+ *
+ *   h        an IDX_BS index with SoA layout and n >= 1 (IDX_ERR_ARG otherwise)
+ *   leaves   1 <= leaves <= 2^22;  epochs 1..16;  feature IDX_FEATURE_*
+ * Synchronises `stream`.  Errors: IDX_ERR_ARG, IDX_ERR_NOMEM, IDX_ERR_HIP.
+ */
+int idx_learn(idx_handle h, uint32_t leaves, uint32_t epochs, uint32_t feature, idx_stream stream);
+
+/* Statistics of the attached model (IDX_ERR_ARG when there is none). */
+int idx_learn_stats_get(idx_handle h, idx_learn_stats *out);
+
+/* Copy the attached model's leaf table (leaves x 32-byte records:
+ * uint64 kmin, uint32 base, uint32 size, float b0, float b1, int32 elo,
+ * int32 ehi) to the device buffer `leaves_out`.  Enqueued on `stream`. */
+int idx_learn_export(idx_handle h, void *leaves_out, idx_stream stream);
+
+/* Drop the attached model (lookups return to the plain layout search). */
+int idx_unlearn(idx_handle h);
+
+/*
+ * idx_learn_eval -- evaluate the training kernels at given parameters, for
+ * gradient checks.  Root: feature `feature` (LINEAR or LOG), parameters
+ * root_ab = {a0, a1} (host), target rank * leaves / n.  root_acc (host, 6
+ * doubles) receives N, sum x, sum x^2, sum r, sum r*x, sum r^2, where
+ * r = a1*x + a0 - target is the FP32 forward residual; the loss gradient is
+ * 2 * (sum r*x, sum r).  When leaf_ab (device, 2 * leaves floats: b0, b1 per
+ * leaf) and leaf_acc (device, 6 * leaves doubles) are given, keys are
+ * assigned to leaves by the root and the same six sums are accumulated per
+ * leaf with the leaf-local feature f32(key - first key of the leaf) and
+ * target (rank - rank of that first key).  Synchronises `stream`.
+ */
+int idx_learn_eval(idx_handle h, uint32_t feature, const float *root_ab, uint32_t leaves, const float *leaf_ab,
+                   double *root_acc, double *leaf_acc, idx_stream stream);
 
 /* ---------------------------------------------------------------------------
  * Measurement

@@ -63,6 +63,10 @@ def lib():
         L.orc_eytzinger_ranks.argtypes = [_u64, _u64, _p]
         L.orc_leaf_grad.argtypes = [_p, _p, _p, _u64, _p, ctypes.c_uint32, _p, _p, _p]
         L.orc_root_grad.argtypes = [_p, _p, _u64, _p, _p, _p, _p]
+        L.orc_key_feature.restype = ctypes.c_float
+        L.orc_key_feature.argtypes = [_u64, ctypes.c_uint32]
+        L.orc_assign_leaves.argtypes = [_p, _u64, ctypes.c_uint32, ctypes.c_float, ctypes.c_float, ctypes.c_uint32,
+                                        _p, _p]
         _lib = L
     return _lib
 
@@ -158,6 +162,35 @@ def leaf_grad(d, y, leaf, params, L: int):
     hess = np.empty(3 * L)
     lib().orc_leaf_grad(_ptr(d), _ptr(y), _ptr(leaf), len(d), _ptr(params), L, _ptr(loss), _ptr(grad), _ptr(hess))
     return loss, grad.reshape(L, 2), hess.reshape(L, 3)
+
+
+def key_feature(key: int, mode: int) -> float:
+    return lib().orc_key_feature(key, mode)
+
+
+def assign_leaves(sorted_keys, mode: int, a0: float, a1: float, L: int):
+    """(leaf per key, root feature per key as float32) under the root model."""
+    K = _u64arr(sorted_keys)
+    leaf = np.empty(len(K), dtype=np.uint32)
+    x = np.empty(len(K), dtype=np.float32)
+    lib().orc_assign_leaves(_ptr(K), len(K), mode, a0, a1, L, _ptr(leaf), _ptr(x))
+    return leaf, x
+
+
+def leaf_frame(sorted_keys, leaf, L: int):
+    """Per key: leaf-local feature d = f32(key - first key of its leaf) and
+    target y = rank - rank of that first key; per leaf: base rank and size.
+    Keys are sorted and leaves non-decreasing, so each leaf is one run."""
+    K = _u64arr(sorted_keys)
+    n = len(K)
+    size = np.bincount(leaf, minlength=L).astype(np.uint64)
+    base = np.zeros(L, dtype=np.uint64)
+    base[1:] = np.cumsum(size)[:-1]
+    kmin = np.where(size > 0, K[np.minimum(base, max(n - 1, 0))], 0).astype(np.uint64)
+    rank = np.arange(n, dtype=np.uint64)
+    d = (K - kmin[leaf]).astype(np.float32).astype(np.float64)
+    y = (rank - base[leaf]).astype(np.float64)
+    return d, y, base, size
 
 
 def root_grad(x, t, params):

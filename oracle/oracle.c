@@ -25,8 +25,10 @@
  *      walk visits child j before pivot j and the last child after the last
  *      pivot, handing out ascending ranks; slots >= n do not exist.  The binary
  *      Eytzinger layout (EBS) is k = 2 stored 1-based with slot 0 empty.
- *  O5  learned rank model (two-stage linear): forward pass, loss, gradient and
- *      Gauss-Newton normal equations in double precision.
+ *  O5  learned rank model (two-stage linear): loss, gradient and Hessian of
+ *      the squared rank error in double precision; the key feature and the
+ *      leaf a key falls into are taken in single precision, the precision the
+ *      model itself evaluates them in.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -246,6 +248,39 @@ void orc_leaf_grad(const double *d, const double *y, const uint32_t *leaf, uint6
         hess[3 * l] += 2.0 * d[i] * d[i];
         hess[3 * l + 1] += 2.0 * d[i];
         hess[3 * l + 2] += 2.0;
+    }
+}
+
+/* Root feature of a key, in single precision as the model evaluates it (a
+ * floating-point value that decides an integer -- the leaf -- is taken in the
+ * model's own precision): mode 1 = the key rounded to float and scaled by
+ * 2^-64; mode 2 = the bit pattern of the key rounded to float, as an
+ * unsigned integer rounded to float and scaled by 2^-31. */
+float orc_key_feature(uint64_t key, uint32_t mode)
+{
+    const float f = (float)key;
+    if (mode == 1) return f * 0x1p-64f;
+    uint32_t bits;
+    memcpy(&bits, &f, sizeof bits);
+    return (float)bits * 0x1p-31f;
+}
+
+/* Leaf of each key under root (mode, a0, a1): clamp(floor(a1*x + a0), 0, L-1),
+ * multiply then add in single precision, no fused operation.  x_out may be
+ * NULL. */
+void orc_assign_leaves(const uint64_t *keys, uint64_t n, uint32_t mode, float a0, float a1, uint32_t L,
+                       uint32_t *leaf_out, float *x_out)
+{
+    for (uint64_t i = 0; i < n; ++i) {
+        const float x = orc_key_feature(keys[i], mode);
+        volatile float prod = a1 * x; /* rounded on its own before the add */
+        const float t = prod + a0;
+        uint32_t l;
+        if (!(t > 0.0f)) l = 0;
+        else if (t >= (float)L) l = L - 1;
+        else l = (uint32_t)t;
+        leaf_out[i] = l;
+        if (x_out) x_out[i] = x;
     }
 }
 

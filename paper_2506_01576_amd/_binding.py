@@ -71,11 +71,28 @@ class idx_lookup_params(ctypes.Structure):
         ("persistent", ctypes.c_uint32),
         ("reorder", ctypes.c_uint32),
         ("early_exit", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("model", ctypes.c_uint32),
     ]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+IDX_FEATURE_AUTO, IDX_FEATURE_LINEAR, IDX_FEATURE_LOG = 0, 1, 2
+
+
+class idx_learn_stats(ctypes.Structure):
+    _fields_ = [
+        ("leaves", ctypes.c_uint32),
+        ("epochs", ctypes.c_uint32),
+        ("feature", ctypes.c_uint32),
+        ("root_a0", ctypes.c_float),
+        ("root_a1", ctypes.c_float),
+        ("root_loss", ctypes.c_double),
+        ("leaf_loss", ctypes.c_double),
+        ("mean_window", ctypes.c_double),
+        ("max_window", ctypes.c_double),
+    ]
 
 
 _lib = None
@@ -99,6 +116,12 @@ SIGNATURES = {
     "idx_set_params": (_I, [_P, ctypes.POINTER(idx_lookup_params)]),
     "idx_get_params": (_I, [_P, ctypes.POINTER(idx_lookup_params)]),
     "idx_probe_random": (_I, [_P, _U64, _U32, _U64, _U32, _U64, _P, _P]),
+    "idx_learn": (_I, [_P, _U32, _U32, _U32, _P]),
+    "idx_learn_stats_get": (_I, [_P, ctypes.POINTER(idx_learn_stats)]),
+    "idx_learn_export": (_I, [_P, _P, _P]),
+    "idx_unlearn": (_I, [_P]),
+    "idx_learn_eval": (_I, [_P, _U32, ctypes.POINTER(ctypes.c_float), _U32, _P, ctypes.POINTER(ctypes.c_double), _P,
+                            _P]),
 }
 
 
@@ -265,6 +288,41 @@ class Index:
         rows = torch.empty(info["slots"], dtype=torch.int32, device="cuda")
         _check(lib().idx_export(self._h, keys.data_ptr(), rows.data_ptr(), _stream(stream)), "idx_export")
         return keys, rows
+
+    # -- learned rank model (sorted-array indexes)
+    def learn(self, leaves: int = 4096, epochs: int = 2, feature: int = IDX_FEATURE_AUTO, stream=None) -> dict:
+        _check(lib().idx_learn(self._h, leaves, epochs, feature, _stream(stream)), "idx_learn")
+        return self.learn_stats()
+
+    def learn_stats(self) -> dict:
+        st = idx_learn_stats()
+        _check(lib().idx_learn_stats_get(self._h, ctypes.byref(st)), "idx_learn_stats_get")
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def learn_export(self, stream=None) -> torch.Tensor:
+        """The leaf table as a (leaves, 8) int32 tensor of raw 32-byte records."""
+        L = self.learn_stats()["leaves"]
+        t = torch.empty((L, 8), dtype=torch.int32, device="cuda")
+        _check(lib().idx_learn_export(self._h, t.data_ptr(), _stream(stream)), "idx_learn_export")
+        return t
+
+    def unlearn(self):
+        _check(lib().idx_unlearn(self._h), "idx_unlearn")
+
+    def learn_eval(self, feature: int, root_ab, leaves: int, leaf_ab: torch.Tensor | None = None, stream=None):
+        """(root sums[6], leaf sums (leaves, 6) or None) of the training
+        kernels at the given parameters; see idx_learn_eval."""
+        ra = (ctypes.c_float * 2)(*[float(v) for v in root_ab])
+        racc = (ctypes.c_double * 6)()
+        lacc = None
+        lp = None
+        if leaf_ab is not None:
+            _dev(leaf_ab, "leaf_ab")
+            lacc = torch.zeros((leaves, 6), dtype=torch.float64, device=leaf_ab.device)
+            lp = leaf_ab.data_ptr()
+        _check(lib().idx_learn_eval(self._h, feature, ra, leaves, lp, racc, None if lacc is None else lacc.data_ptr(),
+                                    _stream(stream)), "idx_learn_eval")
+        return list(racc), lacc
 
     def set_params(self, **kw):
         p = idx_lookup_params(**kw)

@@ -1,0 +1,159 @@
+"""Autotuner for point lookups: measures candidate forms (layout, fan-out k,
+storage, lane grouping, lookups per lane, LDS-pinned levels, persistent grid)
+on the device and keeps the fastest per key width and size class in a table.
+
+This generalises the paper's tuning sweeps (Sections 8.2-8.3) and its
+composite strategy (Section 10: Eytzinger binary search while the index fits
+the cache, k-ary search beyond) into a measured table.  Host-side
+orchestration only: every candidate runs through the library's kernels and is
+checked bit-exact against a reference answer before it can win.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from ._binding import IdxError, Index
+
+TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_gfx950.json")
+
+# size classes by log2(n): [lo, hi]
+SIZE_CLASSES = [(0, 12), (13, 16), (17, 20), (21, 23), (24, 25), (26, 28), (29, 32)]
+
+
+def size_class(n: int):
+    lg = max(0, math.ceil(math.log2(max(n, 1))))
+    for lo, hi in SIZE_CLASSES:
+        if lo <= lg <= hi:
+            return lo, hi
+    return SIZE_CLASSES[-1]
+
+
+def candidates(key_bits: int, n: int):
+    """Forms worth measuring for a set of n keys of width key_bits."""
+    kb = key_bits // 8
+    out = [("bs", 1, False, {}), ("bs", 1, False, {"per_lane": 8}),
+           ("ebs", 2, False, {}), ("ebs", 2, False, {"per_lane": 8})]
+    lds_ok = n >= 1 << 12
+    if lds_ok:
+        out.append(("bs", 1, False, {"lds_levels": 12, "persistent": 2, "block": 1024}))
+        out.append(("ebs", 2, False, {"lds_levels": 12, "persistent": 2, "block": 1024}))
+    for k in (4, 5, 8, 9, 16, 17, 32, 33):
+        g = k - 1
+        node = g * kb
+        out.append(("eks", k, False, {"group": 1 << (g - 1).bit_length(), "per_lane": 4}))
+        if g <= 32:
+            out.append(("eks", k, False, {"group": 1, "per_lane": 4}))
+        v = 16 // kb
+        if g % v == 0 and g // v >= 2:
+            vg = 1 << ((g // v) - 1).bit_length()
+            out.append(("eks", k, False, {"group": vg, "per_lane": 4}))
+        if k in (5, 9, 17, 33) and node % 16 == 0 and g <= 32:
+            for aos in (False, "padded"):
+                # top levels that fit 64 KiB of LDS
+                lev, slots = 0, 0
+                while (slots + g * k ** lev) * kb <= 64 * 1024:
+                    slots += g * k ** lev
+                    lev += 1
+                if lev and lds_ok:
+                    out.append(("eks", k, aos, {"group": 1, "per_lane": 4, "lds_levels": lev, "persistent": 2,
+                                                "block": 1024}))
+            out.append(("eks", k, "padded", {"group": 1, "per_lane": 4}))
+    return out
+
+
+def _time_point(ix: Index, q: torch.Tensor, out: torch.Tensor, reps: int) -> float:
+    stream = torch.cuda.current_stream()
+    ix.point(q, out)
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ix.point(q, out)
+        b.record(stream)
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def tune(base: Index, q: torch.Tensor, expect: torch.Tensor, cands=None, reps: int = 3, log=None):
+    """Measure every candidate form built from the sorted index `base` on the
+    queries `q`; a candidate whose answers differ from `expect` is recorded
+    but can never win.  Returns (records, best record per layout)."""
+    cands = cands if cands is not None else candidates(base.key_bits, base.n)
+    out = torch.empty(len(q), dtype=torch.int32, device=q.device)
+    records, best = [], {}
+    for layout, k, aos, params in cands:
+        ix = base if (layout == "bs" and not aos) else base.relayout(layout, k, aos)
+        try:
+            try:
+                ix.set_params(**params)
+            except IdxError:
+                continue
+            ms = _time_point(ix, q, out, reps)
+            exact = bool(torch.equal(out, expect))
+            rec = {"layout": layout, "k": k, "aos": aos, "params": ix.params(), "ms": round(ms, 4),
+                   "lookups_per_s": len(q) / ms * 1e3, "bit_exact": exact}
+            records.append(rec)
+            if log:
+                log(f"tune {layout} k={k} aos={aos} {params}: {ms:.3f} ms {rec['lookups_per_s'] / 1e9:.2f} G/s "
+                    f"exact={exact}")
+            if exact and (layout not in best or ms < best[layout]["ms"]):
+                best[layout] = rec
+        finally:
+            if ix is not base:
+                ix.close()
+            else:
+                ix.reset_params()
+    return records, best
+
+
+def load_table(path: str = TABLE_PATH) -> dict:
+    if not os.path.exists(path):
+        return {"device": "gfx950", "entries": []}
+    with open(path) as f:
+        return json.load(f)
+
+
+def save_table(table: dict, path: str = TABLE_PATH):
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+        f.write("\n")
+
+
+def record_best(table: dict, key_bits: int, n: int, best: dict):
+    lo, hi = size_class(n)
+    table["entries"] = [e for e in table["entries"]
+                        if not (e["key_bits"] == key_bits and e["log2n_lo"] == lo)]
+    for layout, rec in best.items():
+        table["entries"].append({"key_bits": key_bits, "log2n_lo": lo, "log2n_hi": hi, "layout": layout,
+                                 "k": rec["k"], "aos": rec["aos"], "params": rec["params"],
+                                 "measured_n": n, "lookups_per_s": rec["lookups_per_s"]})
+    return table
+
+
+def choose(n: int, key_bits: int, layout: str | None = None, table: dict | None = None):
+    """Best known form for n keys of width key_bits (optionally of one
+    layout): (layout, k, aos, params).  Falls back to the library defaults and
+    to the size class nearest in log2(n)."""
+    table = table if table is not None else load_table()
+    lg = max(0, math.ceil(math.log2(max(n, 1))))
+    ents = [e for e in table.get("entries", []) if e["key_bits"] == key_bits
+            and (layout is None or e["layout"] == layout)]
+    if not ents:
+        lay = layout or "eks"
+        return lay, {"bs": 1, "ebs": 2, "eks": 9}[lay], False, {}
+
+    def dist(e):
+        if e["log2n_lo"] <= lg <= e["log2n_hi"]:
+            return 0
+        return min(abs(lg - e["log2n_lo"]), abs(lg - e["log2n_hi"]))
+
+    ents.sort(key=lambda e: (dist(e), -e["lookups_per_s"]))
+    e = ents[0]
+    return e["layout"], e["k"], e["aos"], dict(e["params"])

@@ -67,6 +67,7 @@ int cu_count_of_current_device() {
 uint64_t padded_slots(uint64_t slots) { return ((slots + 63) / 64) * 64 + 64; }
 
 void free_handle_buffers(idx_index *h, hipStream_t s) {
+    drop_model(h, s);
     h->alloc.put(h->keys, s);
     h->alloc.put(h->rowids, s);
     h->alloc.put(h->pin, s);
@@ -337,6 +338,36 @@ int idx_export(idx_handle h, void *keys_out, uint32_t *rowids_out, idx_stream st
     if (!h) return IDX_ERR_ARG;
     h->last_stream = (hipStream_t)stream;
     return export_layout(h, keys_out, rowids_out, (hipStream_t)stream);
+}
+
+int idx_learn(idx_handle h, uint32_t leaves, uint32_t epochs, uint32_t feature, idx_stream stream) {
+    if (!h) return IDX_ERR_ARG;
+    h->last_stream = (hipStream_t)stream;
+    return learn(h, leaves, epochs, feature, (hipStream_t)stream);
+}
+
+int idx_learn_stats_get(idx_handle h, idx_learn_stats *out) {
+    if (!h || !out) return IDX_ERR_ARG;
+    return learn_stats(h, out);
+}
+
+int idx_learn_export(idx_handle h, void *leaves_out, idx_stream stream) {
+    if (!h) return IDX_ERR_ARG;
+    h->last_stream = (hipStream_t)stream;
+    return learn_export(h, leaves_out, (hipStream_t)stream);
+}
+
+int idx_unlearn(idx_handle h) {
+    if (!h) return IDX_ERR_ARG;
+    drop_model(h, h->last_stream);
+    return IDX_OK;
+}
+
+int idx_learn_eval(idx_handle h, uint32_t feature, const float *root_ab, uint32_t leaves, const float *leaf_ab,
+                   double *root_acc, double *leaf_acc, idx_stream stream) {
+    if (!h) return IDX_ERR_ARG;
+    h->last_stream = (hipStream_t)stream;
+    return learn_eval(h, feature, root_ab, leaves, leaf_ab, root_acc, leaf_acc, (hipStream_t)stream);
 }
 
 uint64_t idx_slot_rank(uint64_t n, uint32_t k, uint64_t slot) {

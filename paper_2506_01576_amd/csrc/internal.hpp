@@ -68,6 +68,7 @@ struct idx_index {
     float ms_sort = 0.f, ms_permute = 0.f;
     hipStream_t last_stream = nullptr;
     int cu_count = 256;
+    idx::LearnedModel *learned = nullptr;  // attached rank model (BS layout only)
 };
 
 namespace idx {
@@ -106,6 +107,18 @@ uint32_t pin_levels_for(const idx_index *h, size_t bytes);
 // ---- range.hip --------------------------------------------------------------
 int range_lookup(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
                  uint64_t capacity, uint64_t *total, hipStream_t s);
+
+// ---- learned.hip ------------------------------------------------------------
+int learn(idx_index *h, uint32_t leaves, uint32_t epochs, uint32_t feature, hipStream_t s);
+void drop_model(idx_index *h, hipStream_t s);
+int learn_stats(const idx_index *h, idx_learn_stats *out);
+int learn_export(const idx_index *h, void *leaves_out, hipStream_t s);
+int learn_eval(idx_index *h, uint32_t feature, const float *root_ab, uint32_t leaves, const float *leaf_ab,
+               double *root_acc, double *leaf_acc, hipStream_t s);
+int point_learned(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s);
+// first-match ranks and counts of ranges through the model
+int range_count_learned(idx_index *h, const void *lo, const void *hi, uint64_t m, uint32_t *first, uint64_t *count,
+                        hipStream_t s);
 
 // ---- error plumbing ----------------------------------------------------------
 int hip_fail(hipError_t e);

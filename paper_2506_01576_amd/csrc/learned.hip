@@ -1,0 +1,729 @@
+// Learned rank model on a sorted-array index (BS layout): a two-stage FP32
+// model -- a linear root over a monotone key feature selects one of L leaves,
+// each leaf a line over the leaf-local key offset -- trained on the GPU on the
+// index's own (key, rank) pairs, then used to narrow every lookup to a window
+// bounded by the leaf's measured error (the window-then-search idea of the
+// PGM index the paper compares with, Section 8; the last-mile search is the
+// expensive step, Section 9).
+//
+// Exactness does not depend on the model.  The root is non-decreasing in the
+// key (non-negative slope over a non-decreasing feature, round-to-nearest
+// arithmetic without contraction), so the keys of a leaf form one contiguous
+// rank interval [base, base + size) and every key that maps to a leaf has its
+// lower bound inside that interval (or at its end).  Inside a leaf the
+// prediction is non-decreasing too, and the error bounds are measured with the
+// same device function over all of the leaf's keys; a window
+// [pred + elo, pred + ehi + 1] clamped to the leaf interval therefore contains
+// the lower bound of any query, member or not.
+//
+// Training (per stage, `epochs` times): a forward/backward kernel evaluates
+// the FP32 prediction and accumulates, in FP64, the loss sum, the gradient
+// sums (residual * feature, residual) and the Hessian sums (feature^2,
+// feature, count); an update kernel takes the Newton step
+// theta -= H^-1 g, which for this quadratic loss reaches the least-squares
+// fit in one step from zero, the second step correcting FP32 rounding.
+#include <climits>
+
+#include "internal.hpp"
+
+namespace idx {
+
+struct RootRec {
+    float a0, a1;    // t = a1 * x + a0, leaf = clamp(floor(t), 0, L - 1)
+    uint32_t mode;   // IDX_FEATURE_LINEAR / IDX_FEATURE_LOG
+    uint32_t L;
+};
+
+struct __align__(16) LeafRec {
+    uint64_t kmin;   // smallest build key of the leaf (0 when empty)
+    uint32_t base;   // rank of kmin
+    uint32_t size;   // keys in the leaf
+    float b0, b1;    // local rank prediction b1 * f32(key - kmin) + b0
+    int32_t elo, ehi;  // min / max of (true local rank - predicted local rank)
+};
+static_assert(sizeof(LeafRec) == 32, "leaf record is 32 bytes");
+
+struct LearnedModel {
+    RootRec root{};
+    LeafRec *leaves = nullptr;  // device, L records
+    idx_learn_stats stats{};
+};
+
+namespace {
+
+constexpr int LT = 256;  // threads per block in the training kernels
+constexpr int CHUNK = 32;  // consecutive keys per thread in the per-leaf passes
+
+// Monotone key feature in [0, 1].  LINEAR: the key itself; LOG: the bit
+// pattern of the key rounded to FP32, read as an integer -- a piecewise
+// linear approximation of log2(key).  Both use only correctly rounded
+// conversions and power-of-two scalings.
+__device__ __forceinline__ float key_feature(uint64_t key, uint32_t mode) {
+    const float f = (float)key;
+    if (mode == IDX_FEATURE_LINEAR) return f * 0x1p-64f;
+    return (float)__float_as_uint(f) * 0x1p-31f;
+}
+
+__device__ __forceinline__ uint32_t leaf_of(const RootRec &R, uint64_t key) {
+    const float x = key_feature(key, R.mode);
+    const float t = __fadd_rn(__fmul_rn(R.a1, x), R.a0);
+    if (!(t > 0.f)) return 0;
+    if (t >= (float)R.L) return R.L - 1;
+    return (uint32_t)t;
+}
+
+__device__ __forceinline__ float local_feature(const LeafRec &L, uint64_t key) {
+    return (float)(key > L.kmin ? key - L.kmin : 0ull);
+}
+
+__device__ __forceinline__ uint32_t pred_local(const LeafRec &L, uint64_t key) {
+    const float p = __fadd_rn(__fmul_rn(L.b1, local_feature(L, key)), L.b0);
+    if (!(p > 0.f)) return 0;
+    if (p >= (float)L.size) return L.size;
+    return (uint32_t)p;
+}
+
+// Accumulator layout per model: N, Sx, Sxx, Sr, Srx, Srr (FP64).
+constexpr int NACC = 6;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <typename K>
+__global__ __launch_bounds__(LT) void k_root_accum(const K *__restrict__ keys, uint64_t n, const RootRec *Rp,
+                                                   double *__restrict__ acc) {
+    __shared__ double s[LT / kWave][NACC];
+    const RootRec R = *Rp;
+    double a[NACC] = {0, 0, 0, 0, 0, 0};
+    const double scale = (double)R.L / (double)n;
+    for (uint64_t i = (uint64_t)blockIdx.x * LT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * LT) {
+        const float x = key_feature((uint64_t)keys[i], R.mode);
+        const float t = (float)((double)i * scale);
+        const float r = __fsub_rn(__fadd_rn(__fmul_rn(R.a1, x), R.a0), t);  // forward residual
+        a[0] += 1.0;
+        a[1] += x;
+        a[2] += (double)x * x;
+        a[3] += r;
+        a[4] += (double)r * x;
+        a[5] += (double)r * r;
+    }
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < NACC; ++j) {
+        const double v = wave_sum(a[j]);
+        if (lane == 0) s[wave][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NACC) {
+        double v = 0;
+        for (int w = 0; w < LT / kWave; ++w) v += s[w][threadIdx.x];
+        atomicAdd(&acc[threadIdx.x], v);
+    }
+}
+
+// Newton step on a linear model from its accumulated sums; a non-negative
+// slope is enforced (the fitted slope of rank against a non-decreasing
+// feature is non-negative up to rounding).
+__device__ __forceinline__ void newton_linear(const double *a, float &c0, float &c1) {
+    const double N = a[0], Sx = a[1], Sxx = a[2], Sr = a[3], Srx = a[4];
+    if (N < 1.0) {
+        c0 = 0.f;
+        c1 = 0.f;
+        return;
+    }
+    const double det = Sxx * N - Sx * Sx;
+    double n1 = c1, n0 = c0;
+    if (N >= 2.0 && det > 1e-12 * Sxx * N && det > 0.0) {
+        // [d1, d0] = H^-1 g with g = (Srx, Sr), H = [[Sxx, Sx], [Sx, N]] (the 2s cancel)
+        const double d1 = (N * Srx - Sx * Sr) / det;
+        const double d0 = (Sxx * Sr - Sx * Srx) / det;
+        n1 -= d1;
+        n0 -= d0;
+    } else {
+        n1 = 0.0;
+        n0 = (double)c0 + (double)c1 * (Sx / N) - Sr / N;  // the mean target
+    }
+    if (n1 < 0.0) {
+        // keep the model monotone: best constant
+        const double mean_t = (double)c0 + (double)c1 * (Sx / N) - Sr / N;
+        n1 = 0.0;
+        n0 = mean_t;
+    }
+    c1 = (float)n1;
+    c0 = (float)n0;
+}
+
+__global__ void k_root_update(RootRec *R, const double *acc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) newton_linear(acc, R->a0, R->a1);
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint64_t count, uint32_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_f64(double *p, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// Keys per leaf.  Keys are sorted and leaf_of is non-decreasing, so a thread's
+// chunk holds few runs; each run adds its length once.
+template <typename K>
+__global__ __launch_bounds__(LT) void k_leaf_count(const K *__restrict__ keys, uint64_t n, const RootRec *Rp,
+                                                   uint32_t *__restrict__ count) {
+    const RootRec R = *Rp;
+    const uint64_t t = (uint64_t)blockIdx.x * LT + threadIdx.x;
+    const uint64_t b = t * CHUNK;
+    if (b >= n) return;
+    const uint64_t e = b + CHUNK < n ? b + CHUNK : n;
+    uint32_t cur = leaf_of(R, keys[b]), run = 0;
+    for (uint64_t i = b; i < e; ++i) {
+        const uint32_t l = leaf_of(R, keys[i]);
+        if (l != cur) {
+            atomicAdd(&count[cur], run);
+            cur = l;
+            run = 0;
+        }
+        ++run;
+    }
+    atomicAdd(&count[cur], run);
+}
+
+// Single workgroup: base ranks (exclusive scan of the counts), sizes, kmin;
+// leaf parameters start at zero.
+template <typename K>
+__global__ __launch_bounds__(1024) void k_leaf_layout(const K *__restrict__ keys, const uint32_t *__restrict__ count,
+                                                      uint32_t L, LeafRec *__restrict__ leaves) {
+    __shared__ uint32_t s_tot[1024 / kWave];
+    __shared__ uint32_t s_run;
+    if (threadIdx.x == 0) s_run = 0;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    for (uint32_t c0 = 0; c0 < L; c0 += 1024) {
+        const uint32_t l = c0 + threadIdx.x;
+        const uint32_t v = l < L ? count[l] : 0;
+        uint32_t incl = v;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t x = __shfl_up(incl, off, kWave);
+            if (lane >= (uint32_t)off) incl += x;
+        }
+        if (lane == kWave - 1) s_tot[wave] = incl;
+        __syncthreads();
+        uint32_t before = s_run;
+        for (uint32_t w = 0; w < wave; ++w) before += s_tot[w];
+        if (l < L) {
+            LeafRec r{};
+            r.base = before + incl - v;
+            r.size = v;
+            r.kmin = v ? (uint64_t)keys[r.base] : 0ull;
+            r.b0 = 0.f;
+            r.b1 = 0.f;
+            r.elo = INT_MAX;
+            r.ehi = INT_MIN;
+            leaves[l] = r;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) {
+            uint32_t tot = 0;
+            for (int w = 0; w < 1024 / kWave; ++w) tot += s_tot[w];
+            s_run += tot;
+        }
+        __syncthreads();
+    }
+}
+
+// Flush a thread's running sums for leaf `l`: when the whole wave holds the
+// same leaf, reduce across the wave first and add once.
+template <int NV, typename T, typename F>
+__device__ __forceinline__ void flush(uint32_t l, T *v, bool active, F &&add) {
+    const uint64_t act = __ballot(active);
+    const uint32_t lead = __shfl((int)l, __builtin_ctzll(act ? act : 1ull), kWave);
+    const bool uniform = act != 0 && __ballot(active && l == lead) == act && act == __ballot(true);
+    if (uniform) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+        if ((threadIdx.x & (kWave - 1)) == 0) add(l, v);
+    } else if (active) {
+        add(l, v);
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(LT) void k_leaf_accum(const K *__restrict__ keys, uint64_t n, const RootRec *Rp,
+                                                   const LeafRec *__restrict__ leaves, double *__restrict__ acc) {
+    const RootRec R = *Rp;
+    const uint64_t t = (uint64_t)blockIdx.x * LT + threadIdx.x;
+    const uint64_t b = t * CHUNK;
+    const uint64_t e = b + CHUNK < n ? b + CHUNK : n;
+    auto add = [&](uint32_t l, double *v) {
+#pragma unroll
+        for (int j = 0; j < NACC; ++j) atomicAdd(&acc[(uint64_t)l * NACC + j], v[j]);
+    };
+    double a[NACC] = {0, 0, 0, 0, 0, 0};
+    uint32_t cur = b < n ? leaf_of(R, keys[b]) : 0;
+    LeafRec L = leaves[cur];
+    for (uint64_t i = b; i < e; ++i) {
+        const uint64_t key = (uint64_t)keys[i];
+        const uint32_t l = leaf_of(R, key);
+        if (l != cur) {
+            add(cur, a);
+#pragma unroll
+            for (int j = 0; j < NACC; ++j) a[j] = 0;
+            cur = l;
+            L = leaves[cur];
+        }
+        const float d = local_feature(L, key);
+        const float y = (float)(uint32_t)(i - L.base);
+        const float r = __fsub_rn(__fadd_rn(__fmul_rn(L.b1, d), L.b0), y);
+        a[0] += 1.0;
+        a[1] += d;
+        a[2] += (double)d * d;
+        a[3] += r;
+        a[4] += (double)r * d;
+        a[5] += (double)r * r;
+    }
+    flush<NACC>(cur, a, b < n, add);
+}
+
+__global__ void k_leaf_update(LeafRec *__restrict__ leaves, const double *__restrict__ acc, uint32_t L) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    LeafRec r = leaves[l];
+    newton_linear(acc + (uint64_t)l * NACC, r.b0, r.b1);
+    leaves[l].b0 = r.b0;
+    leaves[l].b1 = r.b1;
+}
+
+template <typename K>
+__global__ __launch_bounds__(LT) void k_leaf_errors(const K *__restrict__ keys, uint64_t n, const RootRec *Rp,
+                                                    LeafRec *__restrict__ leaves) {
+    const RootRec R = *Rp;
+    const uint64_t t = (uint64_t)blockIdx.x * LT + threadIdx.x;
+    const uint64_t b = t * CHUNK;
+    const uint64_t e = b + CHUNK < n ? b + CHUNK : n;
+    auto add = [&](uint32_t l, int64_t *v) {
+        atomicMin(&leaves[l].elo, (int32_t)v[0]);
+        atomicMax(&leaves[l].ehi, (int32_t)v[1]);
+    };
+    int64_t mm[2] = {INT_MAX, INT_MIN};
+    uint32_t cur = b < n ? leaf_of(R, keys[b]) : 0;
+    LeafRec L = leaves[cur];
+    for (uint64_t i = b; i < e; ++i) {
+        const uint64_t key = (uint64_t)keys[i];
+        const uint32_t l = leaf_of(R, key);
+        if (l != cur) {
+            add(cur, mm);
+            mm[0] = INT_MAX;
+            mm[1] = INT_MIN;
+            cur = l;
+            L = leaves[cur];
+        }
+        const int64_t err = (int64_t)(i - L.base) - (int64_t)pred_local(L, key);
+        mm[0] = err < mm[0] ? err : mm[0];
+        mm[1] = err > mm[1] ? err : mm[1];
+    }
+    // wave-uniform flush with min/max instead of sums
+    const bool active = b < n;
+    const uint64_t act = __ballot(active);
+    const uint32_t lead = __shfl((int)cur, __builtin_ctzll(act ? act : 1ull), kWave);
+    const bool uniform = act != 0 && __ballot(active && cur == lead) == act && act == __ballot(true);
+    if (uniform) {
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const int64_t o0 = __shfl_xor(mm[0], off, kWave), o1 = __shfl_xor(mm[1], off, kWave);
+            mm[0] = o0 < mm[0] ? o0 : mm[0];
+            mm[1] = o1 > mm[1] ? o1 : mm[1];
+        }
+        if ((threadIdx.x & (kWave - 1)) == 0) add(cur, mm);
+    } else if (active) {
+        add(cur, mm);
+    }
+}
+
+// Empty leaves get a zero window; statistics of the windows.
+__global__ __launch_bounds__(256) void k_leaf_finish(LeafRec *__restrict__ leaves, uint32_t L,
+                                                     double *__restrict__ stats /* sum_w*size, max_w, sum loss */) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    double ws = 0, wmax = 0;
+    if (l < L) {
+        LeafRec r = leaves[l];
+        if (r.size == 0 || r.elo > r.ehi) {
+            leaves[l].elo = 0;
+            leaves[l].ehi = -1;
+        } else {
+            const double w = (double)r.ehi - (double)r.elo + 2.0;  // window slots incl. one past
+            ws = w * r.size;
+            wmax = w;
+        }
+    }
+    ws = wave_sum(ws);
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double o = __shfl_xor(wmax, off, kWave);
+        wmax = o > wmax ? o : wmax;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        atomicAdd(&stats[0], ws);
+        // max via compare-and-swap on the bit pattern (values are >= 0)
+        unsigned long long *p = (unsigned long long *)&stats[1];
+        unsigned long long old = *p;
+        while (__longlong_as_double(old) < wmax) {
+            const unsigned long long prev = atomicCAS(p, old, __double_as_longlong(wmax));
+            if (prev == old) break;
+            old = prev;
+        }
+    }
+}
+
+__global__ void k_sum_leaf_loss(const double *__restrict__ acc, uint32_t L, double *out) {
+    double s = 0;
+    for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < L; l += gridDim.x * blockDim.x)
+        s += acc[(uint64_t)l * NACC + 5];
+    s = wave_sum(s);
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(out, s);
+}
+
+uint32_t grid_for(uint64_t threads, uint32_t block) {
+    uint64_t b = (threads + block - 1) / block;
+    if (b == 0) b = 1;
+    if (b > 0x7FFFFFFFull) b = 0x7FFFFFFFull;
+    return (uint32_t)b;
+}
+
+template <typename K>
+int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream_t s) {
+    const uint64_t n = h->n;
+    const K *keys = (const K *)h->keys;
+    LearnedModel *M = h->learned;
+    // device scratch: root record, root acc, leaf acc, counts, stats; every
+    // region starts on a 256-byte boundary (FP64 atomics need 8-byte alignment)
+    auto up256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t leaf_acc_b = up256((size_t)L * NACC * sizeof(double));
+    const size_t cnt_b = up256((size_t)L * 4);
+    char *tmp = (char *)h->alloc.get(256 + 256 + leaf_acc_b + cnt_b + 256, s);
+    if (!tmp) return IDX_ERR_NOMEM;
+    RootRec *d_root = (RootRec *)tmp;
+    double *root_acc = (double *)(tmp + 256);
+    double *leaf_acc = (double *)(tmp + 512);
+    uint32_t *count = (uint32_t *)(tmp + 512 + leaf_acc_b);
+    double *stats = (double *)(tmp + 512 + leaf_acc_b + cnt_b);
+    int rc = IDX_OK;
+    const uint32_t rblocks = (uint32_t)((n + LT * 8 - 1) / (LT * 8)) > 2048 ? 2048u
+                                                                             : (uint32_t)((n + LT * 8 - 1) / (LT * 8));
+    const uint32_t cblocks = grid_for((n + CHUNK - 1) / CHUNK, LT);
+    do {
+        // ---- stage 1: the root, for each candidate feature; keep the lower loss
+        RootRec best{};
+        double best_loss = -1.0;
+        for (uint32_t mode = IDX_FEATURE_LINEAR; mode <= IDX_FEATURE_LOG; ++mode) {
+            if (feature != IDX_FEATURE_AUTO && feature != mode) continue;
+            RootRec R{0.f, 0.f, mode, L};
+            if (hipMemcpyAsync(d_root, &R, sizeof(R), hipMemcpyHostToDevice, s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
+            for (uint32_t ep = 0; ep <= epochs; ++ep) {
+                hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, root_acc, (uint64_t)NACC);
+                hipLaunchKernelGGL((k_root_accum<K>), dim3(rblocks ? rblocks : 1), dim3(LT), 0, s, keys, n, d_root,
+                                   root_acc);
+                if (ep < epochs) hipLaunchKernelGGL(k_root_update, dim3(1), dim3(64), 0, s, d_root, root_acc);
+            }
+            double acc[NACC];
+            RootRec R2;
+            if (hipMemcpyAsync(acc, root_acc, sizeof(acc), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(&R2, d_root, sizeof(R2), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
+            if (best_loss < 0 || acc[5] < best_loss) {
+                best_loss = acc[5];
+                best = R2;
+            }
+        }
+        if (rc != IDX_OK) break;
+        M->root = best;
+        M->stats.root_loss = best_loss;
+        if (hipMemcpyAsync(d_root, &best, sizeof(best), hipMemcpyHostToDevice, s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
+
+        // ---- stage 2: leaves
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L, 256)), dim3(256), 0, s, count, (uint64_t)L, 0u);
+        hipLaunchKernelGGL((k_leaf_count<K>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, count);
+        hipLaunchKernelGGL((k_leaf_layout<K>), dim3(1), dim3(1024), 0, s, keys, count, L, M->leaves);
+        for (uint32_t ep = 0; ep <= epochs; ++ep) {
+            hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((uint64_t)L * NACC, 256)), dim3(256), 0, s, leaf_acc,
+                               (uint64_t)L * NACC);
+            hipLaunchKernelGGL((k_leaf_accum<K>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, M->leaves, leaf_acc);
+            if (ep < epochs)
+                hipLaunchKernelGGL(k_leaf_update, dim3(grid_for(L, 256)), dim3(256), 0, s, M->leaves, leaf_acc, L);
+        }
+        hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, stats, (uint64_t)4);
+        hipLaunchKernelGGL(k_sum_leaf_loss, dim3(64), dim3(256), 0, s, leaf_acc, L, stats + 2);
+        hipLaunchKernelGGL((k_leaf_errors<K>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, M->leaves);
+        hipLaunchKernelGGL(k_leaf_finish, dim3(grid_for(L, 256)), dim3(256), 0, s, M->leaves, L, stats);
+        if (hipGetLastError() != hipSuccess) { rc = IDX_ERR_HIP; break; }
+        double st[4];
+        if (hipMemcpyAsync(st, stats, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
+        M->stats.leaf_loss = st[2];
+        M->stats.mean_window = n ? st[0] / (double)n : 0.0;
+        M->stats.max_window = st[1];
+    } while (0);
+    h->alloc.put(tmp, s);
+    return rc;
+}
+
+}  // namespace
+
+int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream_t s) {
+    if (h->layout != IDX_BS || h->aos || h->n == 0) return IDX_ERR_ARG;
+    if (L == 0 || L > (1u << 22) || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_LOG) return IDX_ERR_ARG;
+    drop_model(h, s);
+    LearnedModel *M = new (std::nothrow) LearnedModel();
+    if (!M) return IDX_ERR_NOMEM;
+    M->leaves = (LeafRec *)h->alloc.get((size_t)L * sizeof(LeafRec), s);
+    if (!M->leaves) {
+        delete M;
+        return IDX_ERR_NOMEM;
+    }
+    h->learned = M;
+    M->stats.leaves = L;
+    M->stats.epochs = epochs;
+    const int rc = h->u64 ? train_t<uint64_t>(h, L, epochs, feature, s) : train_t<uint32_t>(h, L, epochs, feature, s);
+    if (rc != IDX_OK) {
+        drop_model(h, s);
+        return rc;
+    }
+    M->stats.feature = M->root.mode;
+    M->stats.root_a0 = M->root.a0;
+    M->stats.root_a1 = M->root.a1;
+    return IDX_OK;
+}
+
+void drop_model(idx_index *h, hipStream_t s) {
+    if (!h->learned) return;
+    h->alloc.put(h->learned->leaves, s);
+    delete h->learned;
+    h->learned = nullptr;
+}
+
+int learn_stats(const idx_index *h, idx_learn_stats *out) {
+    if (!h->learned) return IDX_ERR_ARG;
+    *out = h->learned->stats;
+    return IDX_OK;
+}
+
+int learn_export(const idx_index *h, void *leaves_out, hipStream_t s) {
+    if (!h->learned) return IDX_ERR_ARG;
+    if (!leaves_out) return IDX_OK;
+    IDX_HIP(hipMemcpyAsync(leaves_out, h->learned->leaves, (size_t)h->learned->root.L * sizeof(LeafRec),
+                           hipMemcpyDeviceToDevice, s));
+    return IDX_OK;
+}
+
+// ---------------------------------------------------------------- lookups
+
+namespace {
+
+template <typename K, int R>
+__global__ __launch_bounds__(1024) void k_point_learned(const K *__restrict__ keys, const uint32_t *__restrict__ rows,
+                                                        uint64_t n, RootRec root,
+                                                        const LeafRec *__restrict__ leaves, const K *__restrict__ q,
+                                                        uint64_t m, uint32_t *__restrict__ out) {
+    const uint64_t tile = (uint64_t)blockDim.x * R;
+    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < m; t0 += (uint64_t)gridDim.x * tile) {
+        K x[R];
+        uint64_t b[R], len[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
+            x[r] = qi < m ? q[qi] : K(0);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const LeafRec L = leaves[leaf_of(root, (uint64_t)x[r])];
+            const int64_t p = (int64_t)pred_local(L, (uint64_t)x[r]);
+            int64_t w0 = p + L.elo, w1 = p + (int64_t)L.ehi + 1;
+            w0 = w0 < 0 ? 0 : (w0 > (int64_t)L.size ? (int64_t)L.size : w0);
+            w1 = w1 < w0 ? w0 : (w1 > (int64_t)L.size ? (int64_t)L.size : w1);
+            b[r] = L.base + (uint64_t)w0;
+            len[r] = (uint64_t)(w1 - w0);
+            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
+            if (qi >= m) len[r] = 0;
+        }
+        // lower bound inside [b, b + len): first position with key >= x, or b + len
+        bool more = true;
+        while (more) {
+            more = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (len[r] > 1) {
+                    const uint64_t half = len[r] >> 1;
+                    b[r] = keys[b[r] + half - 1] < x[r] ? b[r] + half : b[r];
+                    len[r] -= half;
+                    more |= len[r] > 1;
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
+            if (qi >= m) continue;
+            uint32_t res = kMiss;
+            if (len[r] == 1) {
+                // candidate b (the window's last unresolved slot)
+                const K kb = keys[b[r]];
+                if (kb == x[r]) res = rows[b[r]];
+                else if (kb < x[r] && b[r] + 1 < n && keys[b[r] + 1] == x[r]) res = rows[b[r] + 1];
+            } else if (b[r] < n && keys[b[r]] == x[r]) {
+                res = rows[b[r]];
+            }
+            out[qi] = res;
+        }
+    }
+}
+
+}  // namespace
+
+int point_learned(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
+    const LearnedModel *M = h->learned;
+    const uint32_t block = h->params.block;
+    const uint32_t R = h->params.per_lane;
+    uint64_t grid = (m + (uint64_t)block * R - 1) / ((uint64_t)block * R);
+    if (h->params.persistent) {
+        const uint64_t cap = (uint64_t)h->cu_count * h->params.persistent;
+        if (grid > cap) grid = cap;
+    }
+    const uint32_t g = (uint32_t)(grid ? (grid > 0x7FFFFFFFull ? 0x7FFFFFFFull : grid) : 1);
+#define IDX_LEARNED_LAUNCH(KT, RR)                                                                          \
+    hipLaunchKernelGGL((k_point_learned<KT, RR>), dim3(g), dim3(block), 0, s, (const KT *)h->keys, h->rowids, \
+                       h->n, M->root, M->leaves, (const KT *)q, m, out)
+    if (h->u64) {
+        switch (R) {
+            case 1: IDX_LEARNED_LAUNCH(uint64_t, 1); break;
+            case 2: IDX_LEARNED_LAUNCH(uint64_t, 2); break;
+            case 4: IDX_LEARNED_LAUNCH(uint64_t, 4); break;
+            default: IDX_LEARNED_LAUNCH(uint64_t, 8); break;
+        }
+    } else {
+        switch (R) {
+            case 1: IDX_LEARNED_LAUNCH(uint32_t, 1); break;
+            case 2: IDX_LEARNED_LAUNCH(uint32_t, 2); break;
+            case 4: IDX_LEARNED_LAUNCH(uint32_t, 4); break;
+            default: IDX_LEARNED_LAUNCH(uint32_t, 8); break;
+        }
+    }
+#undef IDX_LEARNED_LAUNCH
+    IDX_LAUNCH_CHECK();
+    return IDX_OK;
+}
+
+// Lower-bound rank of x through the model (device, used by range counting).
+template <typename K>
+__device__ uint64_t learned_lower_rank(const K *__restrict__ keys, uint64_t n, const RootRec &root,
+                                       const LeafRec *__restrict__ leaves, K x) {
+    const LeafRec L = leaves[leaf_of(root, (uint64_t)x)];
+    const int64_t p = (int64_t)pred_local(L, (uint64_t)x);
+    int64_t w0 = p + L.elo, w1 = p + (int64_t)L.ehi + 1;
+    w0 = w0 < 0 ? 0 : (w0 > (int64_t)L.size ? (int64_t)L.size : w0);
+    w1 = w1 < w0 ? w0 : (w1 > (int64_t)L.size ? (int64_t)L.size : w1);
+    uint64_t b = L.base + (uint64_t)w0, len = (uint64_t)(w1 - w0);
+    while (len > 1) {
+        const uint64_t half = len >> 1;
+        b = keys[b + half - 1] < x ? b + half : b;
+        len -= half;
+    }
+    if (len == 1 && keys[b] < x) ++b;
+    return b;
+}
+
+namespace {
+template <typename K>
+__global__ __launch_bounds__(256) void k_range_count_learned(const K *__restrict__ keys, uint64_t n, RootRec root,
+                                                             const LeafRec *__restrict__ leaves,
+                                                             const K *__restrict__ lo, const K *__restrict__ hi,
+                                                             uint64_t m, uint32_t *__restrict__ first,
+                                                             uint64_t *__restrict__ count) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m) return;
+    const K L = lo[q], U = hi[q];
+    uint64_t r0 = 0, r1 = 0;
+    if (L <= U) {
+        r0 = learned_lower_rank(keys, n, root, leaves, L);
+        r1 = (U == ~K(0)) ? n : learned_lower_rank(keys, n, root, leaves, (K)(U + 1));
+    }
+    first[q] = (uint32_t)r0;
+    count[q] = r1 > r0 ? r1 - r0 : 0;
+}
+}  // namespace
+
+int range_count_learned(idx_index *h, const void *lo, const void *hi, uint64_t m, uint32_t *first, uint64_t *count,
+                        hipStream_t s) {
+    const LearnedModel *M = h->learned;
+    const uint32_t blocks = grid_for(m, 256);
+    if (h->u64)
+        hipLaunchKernelGGL(k_range_count_learned<uint64_t>, dim3(blocks), dim3(256), 0, s, (const uint64_t *)h->keys,
+                           h->n, M->root, M->leaves, (const uint64_t *)lo, (const uint64_t *)hi, m, first, count);
+    else
+        hipLaunchKernelGGL(k_range_count_learned<uint32_t>, dim3(blocks), dim3(256), 0, s, (const uint32_t *)h->keys,
+                           h->n, M->root, M->leaves, (const uint32_t *)lo, (const uint32_t *)hi, m, first, count);
+    IDX_LAUNCH_CHECK();
+    return IDX_OK;
+}
+
+// ----------------------------------------------------- gradient evaluation
+
+namespace {
+// leaf parameters given as (b0, b1) pairs
+__global__ void k_set_leaf_params(LeafRec *leaves, const float *ab, uint32_t L) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    leaves[l].b0 = ab[2 * l];
+    leaves[l].b1 = ab[2 * l + 1];
+}
+
+template <typename K>
+int eval_t(idx_index *h, uint32_t mode, const float *root_ab, uint32_t L, const float *leaf_ab, double *root_acc_h,
+           double *leaf_acc_d, hipStream_t s) {
+    const uint64_t n = h->n;
+    const K *keys = (const K *)h->keys;
+    const size_t leaf_b = (size_t)L * sizeof(LeafRec);
+    char *tmp = (char *)h->alloc.get(512 + leaf_b + (size_t)L * 4, s);
+    if (!tmp) return IDX_ERR_NOMEM;
+    RootRec *d_root = (RootRec *)tmp;
+    double *racc = (double *)(tmp + 256);
+    LeafRec *leaves = (LeafRec *)(tmp + 512);
+    uint32_t *count = (uint32_t *)(tmp + 512 + leaf_b);
+    int rc = IDX_OK;
+    do {
+        RootRec R{root_ab[0], root_ab[1], mode, L};
+        if (hipMemcpyAsync(d_root, &R, sizeof(R), hipMemcpyHostToDevice, s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
+        hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, racc, (uint64_t)NACC);
+        const uint32_t rblocks = grid_for((n + LT * 8 - 1) / (LT * 8), 1) > 2048 ? 2048u
+                                                                                : grid_for((n + LT * 8 - 1) / (LT * 8), 1);
+        hipLaunchKernelGGL((k_root_accum<K>), dim3(rblocks), dim3(LT), 0, s, keys, n, d_root, racc);
+        if (leaf_ab && leaf_acc_d) {
+            const uint32_t cblocks = grid_for((n + CHUNK - 1) / CHUNK, LT);
+            hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L, 256)), dim3(256), 0, s, count, (uint64_t)L, 0u);
+            hipLaunchKernelGGL((k_leaf_count<K>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, count);
+            hipLaunchKernelGGL((k_leaf_layout<K>), dim3(1), dim3(1024), 0, s, keys, count, L, leaves);
+            hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((uint64_t)L * NACC, 256)), dim3(256), 0, s, leaf_acc_d,
+                               (uint64_t)L * NACC);
+            hipLaunchKernelGGL(k_set_leaf_params, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_ab, L);
+            hipLaunchKernelGGL((k_leaf_accum<K>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves, leaf_acc_d);
+        }
+        if (hipGetLastError() != hipSuccess) { rc = IDX_ERR_HIP; break; }
+        if (hipMemcpyAsync(root_acc_h, racc, NACC * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
+    } while (0);
+    h->alloc.put(tmp, s);
+    return rc;
+}
+}  // namespace
+
+int learn_eval(idx_index *h, uint32_t mode, const float *root_ab, uint32_t L, const float *leaf_ab, double *root_acc,
+               double *leaf_acc, hipStream_t s) {
+    if (h->layout != IDX_BS || h->aos || h->n == 0) return IDX_ERR_ARG;
+    if (mode != IDX_FEATURE_LINEAR && mode != IDX_FEATURE_LOG) return IDX_ERR_ARG;
+    if (L == 0 || L > (1u << 22) || !root_ab || !root_acc) return IDX_ERR_ARG;
+    return h->u64 ? eval_t<uint64_t>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s)
+                  : eval_t<uint32_t>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s);
+}
+
+}  // namespace idx

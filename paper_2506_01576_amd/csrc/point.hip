@@ -601,6 +601,7 @@ int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_p
     // early exit: 0 = default (on), 1 = on, 2 = off; only effective for unique keys
     if (p.early_exit == 0) p.early_exit = 1;
     if (p.early_exit > 2) return IDX_ERR_ARG;
+    if (p.model > 2) return IDX_ERR_ARG;
     *out = p;
     return IDX_OK;
 }
@@ -608,6 +609,7 @@ int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_p
 int point_lookup(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
     if (m == 0) return IDX_OK;
     const idx_lookup_params &p = h->params;
+    if (h->learned && p.model != 2) return point_learned(h, q, m, out, s);
     if (p.lds_levels) {
         const int rc = build_pin(h, p.lds_levels, s);
         if (rc != IDX_OK) return rc;

@@ -242,10 +242,15 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
     uint64_t tot = 0;
     const uint32_t blocks = (uint32_t)((m + 255) / 256);
     do {
-        hipLaunchKernelGGL((k_range_count<K, AOS>), dim3(blocks), dim3(256), 0, s, a);
-        if (hipGetLastError() != hipSuccess) {
-            rc = IDX_ERR_HIP;
-            break;
+        if (h->learned && h->params.model != 2) {
+            rc = range_count_learned(h, lo, hi, m, a.first_rank, offsets, s);
+            if (rc != IDX_OK) break;
+        } else {
+            hipLaunchKernelGGL((k_range_count<K, AOS>), dim3(blocks), dim3(256), 0, s, a);
+            if (hipGetLastError() != hipSuccess) {
+                rc = IDX_ERR_HIP;
+                break;
+            }
         }
         rc = exclusive_scan(offsets, m, partial, s);
         if (rc != IDX_OK) break;

@@ -1,0 +1,234 @@
+"""GPU tests of the learned rank model: lookups through the model are
+bit-exact against the oracle; the training kernels' loss, gradient and
+Hessian sums match the oracle's double-precision definitions; training lands
+on the least-squares fit; the model narrows the search far below plain
+binary search."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import rows_host, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+idx = pytest.importorskip("paper_2506_01576_amd")
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+AUTO, LINEAR, LOG = idx.IDX_FEATURE_AUTO, idx.IDX_FEATURE_LINEAR, idx.IDX_FEATURE_LOG
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make(kind, n, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "uniform32":
+        keys, _ = gen.unique_keys(seed, n, 32)
+    elif kind == "uniform64":
+        keys, _ = gen.unique_keys(seed, n, 64, 63)
+    elif kind == "lognormal":
+        keys, _ = gen.lognormal_keys(seed, n)
+    elif kind == "dup":
+        keys = rng.integers(0, max(1, n // 5), size=n, dtype=np.uint64)
+    else:
+        raise ValueError(kind)
+    rows = (rng.permutation(n).astype(np.uint64) * 5 + 3).astype(np.uint32)
+    return keys, rows
+
+
+def queries(keys, m, seed):
+    rng = np.random.default_rng(seed)
+    dt = keys.dtype
+    top = int(np.iinfo(dt).max)
+    lo, hi = int(keys.min()), int(keys.max())
+    q = np.concatenate([keys[rng.integers(0, len(keys), m // 2)],
+                        rng.integers(0, top, size=m // 4, dtype=np.uint64, endpoint=True).astype(dt),
+                        (keys[rng.integers(0, len(keys), m // 4)].astype(np.uint64) + 1).astype(dt),
+                        np.array([0, top, lo, hi, max(lo - 1, 0), min(hi + 1, top)], dtype=np.uint64).astype(dt)])
+    return q.astype(dt)
+
+
+@pytest.mark.parametrize("kind", ["uniform32", "uniform64", "lognormal", "dup"])
+@pytest.mark.parametrize("leaves,epochs,feature", [(1, 1, AUTO), (7, 2, LINEAR), (4096, 2, AUTO), (4096, 1, LOG),
+                                                   (65536, 2, AUTO)])
+def test_learned_lookup_parity(kind, leaves, epochs, feature):
+    n = 50021
+    keys, rows = make(kind, n, seed=leaves + epochs)
+    sk, sr = oracle.stable_sort(keys, rows)
+    q = queries(keys, 20011, seed=7)
+    want = oracle.point(sk, sr, q, nthreads=4)
+    bits = keys.dtype.itemsize * 8
+    say(f"learned {kind} leaves={leaves} epochs={epochs} feature={feature}")
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        st = ix.learn(leaves, epochs, feature)
+        assert st["leaves"] == leaves and st["mean_window"] >= 1 and st["max_window"] <= n + 1
+        for R in (1, 4, 8):
+            ix.set_params(per_lane=R)
+            got = rows_host(ix.point(to_dev(q)))
+            bad = np.nonzero(got != want)[0]
+            assert len(bad) == 0, f"R={R}: {len(bad)} mismatches, first q={q[bad[0]]}"
+        # ranges through the model
+        L, U, _ = gen.ranges(3, keys, 3001, 1, 64)
+        L = np.concatenate([L, q[:500]]).astype(keys.dtype)
+        U = np.concatenate([U, np.maximum(q[:500], q[500:1000])]).astype(keys.dtype)
+        woff, wrows = oracle.range_lookup(sk, sr, L, U, nthreads=4)
+        off, rr = ix.range(to_dev(L), to_dev(U))
+        assert np.array_equal(off.cpu().numpy().view(np.uint64), woff)
+        assert np.array_equal(rows_host(rr), wrows)
+        # dropping the model gives the same answers through plain search
+        ix.set_params(model=2)
+        assert np.array_equal(rows_host(ix.point(to_dev(q))), want)
+        ix.set_params(model=0)
+        ix.unlearn()
+        assert np.array_equal(rows_host(ix.point(to_dev(q))), want)
+
+
+def test_learned_tiny_sets():
+    for n in (1, 2, 3, 17):
+        keys, rows = make("uniform64", n, seed=n)
+        sk, sr = oracle.stable_sort(keys, rows)
+        q = queries(keys, 64, seed=n)
+        with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+            ix.learn(16, 2, AUTO)
+            assert np.array_equal(rows_host(ix.point(to_dev(q))), oracle.point(sk, sr, q))
+
+
+def test_learn_rejects_other_layouts():
+    keys, rows = make("uniform32", 1000, seed=1)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="eks", k=9) as ix:
+        with pytest.raises(idx.IdxError):
+            ix.learn(64)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        for bad in ((0, 2, AUTO), (1 << 23, 2, AUTO), (64, 0, AUTO), (64, 2, 3)):
+            with pytest.raises(idx.IdxError):
+                ix.learn(*bad)
+
+
+def _sums_from_oracle_root(x, t, a0, a1):
+    loss, grad, hess = oracle.root_grad(x.astype(np.float64), t, np.array([a1, a0], dtype=np.float64))
+    # N, Sx, Sxx, Sr, Srx, Srr
+    return np.array([hess[2] / 2, hess[1] / 2, hess[0] / 2, grad[1] / 2, grad[0] / 2, loss])
+
+
+@pytest.mark.parametrize("kind,mode", [("lognormal", LOG), ("uniform64", LINEAR), ("uniform32", LOG)])
+def test_training_kernel_sums_match_oracle(kind, mode):
+    n, L = 1 << 16, 64
+    keys, rows = make(kind, n, seed=11)
+    sk, _ = oracle.stable_sort(keys, rows)
+    leaf0, x0 = oracle.assign_leaves(sk, mode, 0.0, 1.0, 1)
+    t = np.arange(n, dtype=np.float64) * L / n
+    A = np.stack([x0.astype(np.float64), np.ones(n)], axis=1)
+    (a1, a0), *_ = np.linalg.lstsq(A, t, rcond=None)
+    a0, a1 = float(np.float32(a0 + 0.37)), float(np.float32(max(a1, 0.0) * 1.01))
+    leaf, x = oracle.assign_leaves(sk, mode, a0, a1, L)
+    d, y, base, size = oracle.leaf_frame(sk, leaf, L)
+    rng = np.random.default_rng(5)
+    leaf_ab = np.zeros(2 * L, dtype=np.float32)
+    for l in range(L):
+        sel = leaf == l
+        if sel.sum() >= 2:
+            (b1, b0), *_ = np.linalg.lstsq(np.stack([d[sel], np.ones(sel.sum())], 1), y[sel], rcond=None)
+            leaf_ab[2 * l], leaf_ab[2 * l + 1] = np.float32(b0 + rng.normal(0, 3)), np.float32(max(b1, 0) * 1.02)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        racc, lacc = ix.learn_eval(mode, (a0, a1), L, torch.from_numpy(leaf_ab).cuda())
+    racc = np.array(racc)
+    lacc = lacc.cpu().numpy()
+    # the integer decisions (which leaf each key falls in) agree exactly
+    assert np.array_equal(lacc[:, 0].astype(np.int64), np.bincount(leaf, minlength=L))
+    # root: feature sums exact up to summation order; residual sums within the
+    # FP32 rounding of the forward pass (|dr| <= 2 ulp of the larger operand)
+    want = _sums_from_oracle_root(x, t, a0, a1)
+    eps = 2.0 ** -23
+    mag = np.abs(a1 * x.astype(np.float64)) + abs(a0) + np.abs(t)
+    r = a1 * x.astype(np.float64) + a0 - t
+    tol = np.array([0, 1e-9 * want[1], 1e-9 * want[2], 3 * eps * mag.sum(),
+                    3 * eps * (mag * x).sum(), 6 * eps * (np.abs(r) * mag).sum() + 1e-9 * want[5]]) + 1e-6
+    assert np.all(np.abs(racc - want) <= tol), (racc, want, tol)
+    # leaves: oracle definition of loss / gradient / Hessian in FP64
+    params = np.empty(2 * L)
+    params[0::2] = leaf_ab[1::2]  # slope
+    params[1::2] = leaf_ab[0::2]  # intercept
+    loss, grad, hess = oracle.leaf_grad(d, y, leaf, params, L)
+    magl = np.abs(params[2 * leaf] * d) + np.abs(params[2 * leaf + 1]) + np.abs(y)
+    rl = params[2 * leaf] * d + params[2 * leaf + 1] - y
+    tol_r = 3 * eps * np.bincount(leaf, weights=magl, minlength=L) + 1e-6
+    tol_rx = 3 * eps * np.bincount(leaf, weights=magl * d, minlength=L) + 1e-6
+    tol_rr = 6 * eps * np.bincount(leaf, weights=np.abs(rl) * magl, minlength=L) + 1e-9 * loss + 1e-6
+    assert np.allclose(lacc[:, 2], hess[:, 0] / 2, rtol=1e-9, atol=1e-6)
+    assert np.allclose(lacc[:, 1], hess[:, 1] / 2, rtol=1e-9, atol=1e-6)
+    assert np.all(np.abs(lacc[:, 3] - grad[:, 1] / 2) <= tol_r)
+    assert np.all(np.abs(lacc[:, 4] - grad[:, 0] / 2) <= tol_rx)
+    assert np.all(np.abs(lacc[:, 5] - loss) <= tol_rr)
+
+
+def test_training_reaches_least_squares():
+    n, L = 1 << 18, 256
+    keys, rows = make("lognormal", n, seed=21)
+    sk, _ = oracle.stable_sort(keys, rows)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        st = ix.learn(L, 2, LOG)
+        table = ix.learn_export().cpu().numpy()
+    a0, a1 = st["root_a0"], st["root_a1"]
+    leaf, x = oracle.assign_leaves(sk, LOG, a0, a1, 1)
+    t = np.arange(n, dtype=np.float64) * L / n
+    (w1, w0), *_ = np.linalg.lstsq(np.stack([x.astype(np.float64), np.ones(n)], 1), t, rcond=None)
+    # the FP32 parameters equal the FP64 least-squares fit up to FP32 rounding
+    # amplified by the fit's conditioning
+    assert a1 == pytest.approx(w1, rel=2e-4)
+    assert abs(a0 - w0) <= 2e-4 * (abs(w1) + abs(w0))
+    leaf, _ = oracle.assign_leaves(sk, LOG, a0, a1, L)
+    d, y, base, size = oracle.leaf_frame(sk, leaf, L)
+    rec = table.view(np.uint8).reshape(L, 32)
+    base_g = rec[:, 8:12].copy().view(np.uint32).ravel()
+    size_g = rec[:, 12:16].copy().view(np.uint32).ravel()
+    b0 = rec[:, 16:20].copy().view(np.float32).ravel()
+    b1 = rec[:, 20:24].copy().view(np.float32).ravel()
+    assert np.array_equal(base_g, base.astype(np.uint32)) and np.array_equal(size_g, size.astype(np.uint32))
+    for l in np.nonzero(size >= 64)[0][:40]:
+        sel = leaf == l
+        (c1, c0), *_ = np.linalg.lstsq(np.stack([d[sel], np.ones(sel.sum())], 1), y[sel], rcond=None)
+        span = d[sel].max()
+        # predictions agree to a small fraction of the leaf size over the leaf
+        assert abs((b1[l] - c1) * span) + abs(b0[l] - c0) <= 1e-3 * size[l] + 0.5
+
+
+def test_model_narrows_the_search():
+    """What the trained model gains over the search without it: the window a
+    lookup searches shrinks from n keys to a few hundred, so binary search
+    takes ~log2(window) instead of log2(n) steps, and lookups get faster."""
+    n, m = 1 << 24, 1 << 24
+    keys, rows = gen.unique_keys(31, n, 64, 63)
+    q, expect = gen.point_queries(31, n, m, 1.0, 64, 63)
+    dq, de = to_dev(q), to_dev(expect)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        out = torch.empty(m, dtype=torch.int32, device="cuda")
+
+        def timed():
+            ix.point(dq, out)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(3):
+                ix.point(dq, out)
+            b.record()
+            b.synchronize()
+            assert torch.equal(out, de)
+            return a.elapsed_time(b) / 3
+
+        t_plain = timed()
+        st = ix.learn(1 << 16, 2, AUTO)
+        t_model = timed()
+    steps_plain = np.log2(n)
+    steps_model = np.log2(st["mean_window"])
+    say(f"plain {t_plain:.3f} ms, learned {t_model:.3f} ms, mean window {st['mean_window']:.1f}, "
+        f"steps {steps_plain:.1f} -> {steps_model:.1f}")
+    assert steps_model < steps_plain - 10
+    assert t_model < t_plain
