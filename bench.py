@@ -56,10 +56,21 @@ def levels_eytzinger(n: int, k: int):
     return out
 
 
-def algo_bytes(form: str, n: int, k: int, key_bytes: int, early_exit: bool = True) -> dict:
+def algo_bytes(form: str, n: int, k: int, key_bytes: int, early_exit: bool = True, window: float = 0.0,
+               leaves: int = 0) -> dict:
     stream = key_bytes + 4
     uncached = 0.0
-    if form == "bs":
+    if form == "learned":
+        # leaf record (32 B each; counted only if the table exceeds on-chip
+        # capacity) + binary search over the mean window: one granule per
+        # step until the remaining interval fits one granule
+        if leaves * 32 > ONCHIP_BYTES:
+            uncached += GRANULE
+        span = max(window, 1.0) * key_bytes
+        uncached += GRANULE * max(0.0, math.ceil(math.log2(max(span / GRANULE, 1.0))))
+        if span > 0:
+            uncached += GRANULE  # the final granule holding the answer
+    elif form == "bs":
         length, depth, cum = n, 0, 0
         while length > 1:
             half = length >> 1
@@ -125,6 +136,7 @@ def main():
     ap.add_argument("--log2m", type=int, default=27)
     ap.add_argument("--log2ranges", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="leave the learned form out")
     ap.add_argument("--sweep", action="store_true",
                     help="re-measure every candidate form (autotuner) instead of using the tuned table")
     ap.add_argument("--write-table", action="store_true", help="with --sweep: store the winners in the tuned table")
@@ -222,18 +234,56 @@ def main():
             ix.close()
         else:
             ix.reset_params()
-    checked = sweep + [r for r in best_by_layout.values() if r not in sweep]
+    # learned form: the sorted array plus a trained rank model (leaves tuned)
+    lrec = None
+    if not args.no_learned:
+        if args.sweep:
+            cands = [(L, r) for L in (1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20) for r in (4, 8)]
+        else:
+            _, _, _, lp = autotune.choose(n, 64, "learned")
+            cands = [(lp.get("leaves", 1 << 16), lp.get("per_lane", 4))]
+        trained = None
+        for L, r in cands:
+            if trained != L:
+                st = base.learn(L, 2)
+                trained = L
+            base.set_params(per_lane=r, model=0)
+            ms, ok = time_point(base, reps=3, check=True)
+            rec = {"layout": "learned", "k": 1, "aos": False, "params": dict(base.params(), leaves=L), "ms": round(ms, 4),
+                   "lookups_per_s": m / ms * 1e3, "bit_exact": ok, "mean_window": st["mean_window"],
+                   "max_window": st["max_window"]}
+            if args.sweep:
+                sweep.append(rec)
+            log(f"learned leaves={L} R={r}: {ms:.3f} ms exact={ok} mean window {st['mean_window']:.1f}")
+            if ok and (lrec is None or ms < lrec["ms"]):
+                lrec = rec
+        base.unlearn()
+        base.reset_params()
+        if args.sweep and args.write_table and lrec:
+            autotune.save_table(autotune.record_best(autotune.load_table(), 64, n, {**best_by_layout,
+                                                                                    "learned": lrec}))
+
+    checked = sweep + [r for r in best_by_layout.values() if r not in sweep] + ([lrec] if lrec else [])
     if not all(r["bit_exact"] for r in checked):
         log("WARNING: some forms were not bit-exact")
 
     def form_name(r):
+        if r["layout"] == "learned":
+            return f"LEARNED(leaves={r['params']['leaves']})"
         if r["layout"] != "eks":
             return r["layout"].upper()
         mode = "single" if r["params"]["group"] == 1 else f"group{r['params']['group']}"
         return f"EKS(k={r['k']},{mode}{',aos' if r['aos'] else ''}{',lds' if r['params']['lds_levels'] else ''})"
 
     forms = [(form_name(best_by_layout[l]), best_by_layout[l]) for l in ("bs", "ebs", "eks")]
+    if lrec:
+        forms.append((form_name(lrec), lrec))
     base.close()
+
+    def lookup_params(rec):
+        p = {kk: v for kk, v in rec["params"].items() if kk != "leaves"}
+        p["model"] = 0 if rec["layout"] == "learned" else 2
+        return p
 
     # ---------------------------------------------------------------- steps
     def one_step(record):
@@ -244,17 +294,27 @@ def main():
         hs = {forms[0][0]: bs if not forms[0][1]["aos"] else bs.relayout("bs", 1, forms[0][1]["aos"])}
         marks = [("build_sort", a, b)]
         for name, rec in forms[1:]:
+            if rec["layout"] == "learned":
+                # the model attaches to the sorted array itself
+                a = ev()
+                bs.learn(rec["params"]["leaves"], 2)
+                b = ev()
+                hs[name] = bs
+                marks.append((f"train_{name}", a, b))
+                continue
             a = ev()
             hs[name] = bs.relayout(rec["layout"], rec["k"], rec["aos"])
             b = ev()
             marks.append((f"build_permute_{name}", a, b))
         for name, rec in forms:
-            hs[name].set_params(**{kk: v for kk, v in rec["params"].items()})
+            hs[name].set_params(**lookup_params(rec))
             a = ev()
             hs[name].point(q, out)
             b = ev()
             marks.append((f"point_{name}", a, b))
-        for name in (forms[0][0], forms[-1][0]):
+        range_forms = [forms[0], forms[2]] + ([forms[3]] if len(forms) > 3 else [])
+        for name, rec in range_forms:
+            hs[name].set_params(**lookup_params(rec))
             a = ev()
             off, rr = hs[name].range(lo, hi, capacity=mr * 16)
             b = ev()
@@ -286,7 +346,8 @@ def main():
     value = point_rates[headline]
 
     # ------------------------------------------------------------ roofline
-    ab = algo_bytes(hrec["layout"], n, hrec["k"], 8, early_exit=hrec["params"].get("early_exit", 1) == 1)
+    ab = algo_bytes(hrec["layout"], n, hrec["k"], 8, early_exit=hrec["params"].get("early_exit", 1) == 1,
+                    window=hrec.get("mean_window", 0.0), leaves=hrec["params"].get("leaves", 0))
     t_kernel = mean[f"point_{headline}"] / 1e3
     achieved = ab["total"] * m / t_kernel / 1e9
     hp = hrec["params"]
@@ -357,7 +418,9 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": {name: {"lookups_per_s": point_rates[name], "ms": round(mean[f"point_{name}"], 4),
-                         "layout": rec["layout"], "k": rec["k"], "params": rec["params"]} for name, rec in forms},
+                         "layout": rec["layout"], "k": rec["k"], "aos": rec["aos"], "params": rec["params"],
+                         **({"mean_window": rec["mean_window"], "max_window": rec["max_window"]}
+                            if "mean_window" in rec else {})} for name, rec in forms},
         "phases_ms": {k: round(v, 4) for k, v in mean.items()},
         "range_lookups_per_s": {k[6:]: mr / v * 1e3 for k, v in mean.items() if k.startswith("range_")},
         "bit_exact": all(r["bit_exact"] for r in checked),

@@ -306,6 +306,43 @@ int idx_learn_eval(idx_handle h, uint32_t feature, const float *root_ab, uint32_
                    double *root_acc, double *leaf_acc, idx_stream stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched lookups over many indexes in one launch
+ * ------------------------------------------------------------------------- */
+
+typedef struct idx_batch *idx_batch_t;
+
+#define IDX_BATCH_GRAPH 1u /* replay the launch from a captured HIP graph */
+
+/*
+ * idx_batch_create -- gather `count` indexes (same key width, SoA layouts;
+ * any of BS, EBS, EKS, or BS with a learned model) into one batch.  The
+ * indexes must outlive the batch and keep the lookup parameters they had
+ * at creation (EKS early exit, use of the model).  Synchronises `stream`.
+ * Errors: IDX_ERR_ARG (null, mixed key widths, AoS layout), IDX_ERR_NOMEM.
+ */
+int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream stream, idx_batch_t *out);
+
+/*
+ * idx_batch_point -- point lookups for every index of the batch in one
+ * persistent launch (the static scheduling of Section 7.2 applied across
+ * indexes).  Index i's queries are queries[offsets[i] .. offsets[i+1]) and
+ * its answers land at the same positions of out_rowid (rowid or IDX_MISS).
+ *
+ *   queries    device array of offsets[count] keys
+ *   offsets    device array of count + 1 non-decreasing uint64, offsets[0] = 0
+ *   out_rowid  device array of offsets[count] uint32
+ *   flags      0, or IDX_BATCH_GRAPH to launch from a HIP graph captured on
+ *              the first call with these three pointers (re-captured when
+ *              they change); the graph holds one kernel node, no memset
+ * Enqueued on `stream`.  Errors: IDX_ERR_ARG, IDX_ERR_HIP.
+ */
+int idx_batch_point(idx_batch_t b, const void *queries, const uint64_t *offsets, uint32_t *out_rowid, uint32_t flags,
+                    idx_stream stream);
+
+/* Free the batch (synchronises the device first).  NULL is accepted. */
+int idx_batch_destroy(idx_batch_t b);
+
+/* ---------------------------------------------------------------------------
  * Measurement
  * ------------------------------------------------------------------------- */
 

@@ -116,6 +116,9 @@ SIGNATURES = {
     "idx_set_params": (_I, [_P, ctypes.POINTER(idx_lookup_params)]),
     "idx_get_params": (_I, [_P, ctypes.POINTER(idx_lookup_params)]),
     "idx_probe_random": (_I, [_P, _U64, _U32, _U64, _U32, _U64, _P, _P]),
+    "idx_batch_create": (_I, [ctypes.POINTER(_P), _U32, _P, ctypes.POINTER(_P)]),
+    "idx_batch_point": (_I, [_P, _P, _P, _P, _U32, _P]),
+    "idx_batch_destroy": (_I, [_P]),
     "idx_learn": (_I, [_P, _U32, _U32, _U32, _P]),
     "idx_learn_stats_get": (_I, [_P, ctypes.POINTER(idx_learn_stats)]),
     "idx_learn_export": (_I, [_P, _P, _P]),
@@ -336,3 +339,45 @@ class Index:
         p = idx_lookup_params()
         _check(lib().idx_get_params(self._h, ctypes.byref(p)), "idx_get_params")
         return p.as_dict()
+
+
+IDX_BATCH_GRAPH = 1
+
+
+class Batch:
+    """Many indexes served by one persistent launch (idx_batch_*).  The
+    indexes must stay open while the batch is used."""
+
+    def __init__(self, indexes, stream=None):
+        self._indexes = list(indexes)
+        arr = (ctypes.c_void_p * len(self._indexes))(*[ix._h.value for ix in self._indexes])
+        h = ctypes.c_void_p()
+        _check(lib().idx_batch_create(arr, len(self._indexes), _stream(stream), ctypes.byref(h)), "idx_batch_create")
+        self._h = h
+
+    def point(self, queries: torch.Tensor, offsets: torch.Tensor, out: torch.Tensor | None = None,
+              graph: bool = False, stream=None) -> torch.Tensor:
+        _dev(queries, "queries")
+        _dev(offsets, "offsets")
+        if out is None:
+            out = torch.empty(len(queries), dtype=torch.int32, device=queries.device)
+        _check(lib().idx_batch_point(self._h, queries.data_ptr(), offsets.data_ptr(), out.data_ptr(),
+                                     IDX_BATCH_GRAPH if graph else 0, _stream(stream)), "idx_batch_point")
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().idx_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

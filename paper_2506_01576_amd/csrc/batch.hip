@@ -1,0 +1,306 @@
+// Batched point lookups over many independent indexes in one persistent
+// launch.  The queries of all indexes are concatenated (index i owns
+// queries[offsets[i] .. offsets[i+1])); a persistent grid walks that flat
+// array in wave-sized chunks, so load balance is perfect however uneven the
+// indexes and their batches are (the static scheduling of Section 7.2, with
+// the work split over lookups rather than over indexes).  Each wave finds the
+// index of its chunk with one binary search over the offsets (a per-lane
+// search only where a chunk straddles an index boundary), reads that index's
+// descriptor and runs its descent per lane: BS, EBS, EKS (single lane, whole
+// node in registers) or the learned window search -- the form the autotuner
+// chose for the index's size class.  Everything the kernel needs is in device
+// memory, so the launch can be captured once in a HIP graph and replayed.
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+#include "learned_model.hpp"
+
+namespace idx {
+namespace {
+
+enum : uint32_t { F_BS = 0, F_EBS = 1, F_EKS = 2, F_LEARNED = 3 };
+
+struct __align__(16) Desc {
+    const void *keys;
+    const uint32_t *rows;
+    uint64_t n;
+    const LeafRec *leaves;  // learned form only
+    uint32_t form, k, g, levels;
+    uint32_t m_full, early, gshift, pad0;
+    RootRec root;           // learned form only
+};
+static_assert(sizeof(Desc) == 80, "descriptor layout");
+
+constexpr int BT = 256;     // threads per workgroup
+constexpr int BR = 4;       // lookups per lane
+
+template <typename K>
+__device__ __forceinline__ uint32_t bs_find(const K *__restrict__ keys, const uint32_t *__restrict__ rows,
+                                            uint64_t n, K x) {
+    if (n == 0) return kMiss;
+    uint64_t base = 0, len = n;
+    while (len > 1) {
+        const uint64_t half = len >> 1;
+        base = keys[base + half] < x ? base + half : base;
+        len -= half;
+    }
+    const K kb = keys[base];
+    const uint64_t pos = base + (kb < x ? 1 : 0);
+    if (pos >= n) return kMiss;
+    const K kp = kb < x ? keys[pos] : kb;
+    return kp == x ? rows[pos] : kMiss;
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t ebs_find(const K *__restrict__ keys, const uint32_t *__restrict__ rows,
+                                             uint64_t n, uint32_t m_full, K x) {
+    uint64_t i = 1;
+    K ck = ~K(0);
+    for (uint32_t l = 0; l < m_full; ++l) {
+        const K kk = keys[i];
+        const bool right = kk < x;
+        ck = right ? ck : kk;
+        i = 2 * i + (right ? 1 : 0);
+    }
+    if (i <= n) {
+        const K kk = keys[i];
+        const bool right = kk < x;
+        ck = right ? ck : kk;
+        i = 2 * i + (right ? 1 : 0);
+    }
+    const uint64_t j = i >> (__builtin_ctzll(~i) + 1);
+    return (j != 0 && ck == x) ? rows[j] : kMiss;
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t eks_find(const K *__restrict__ keys, const uint32_t *__restrict__ rows,
+                                             const Desc &d, K x) {
+    const uint64_t n = d.n;
+    const uint32_t g = d.g, kf = d.k;
+    uint64_t c = 0, cand = 0;
+    bool ceq = false;
+    for (uint32_t lvl = 0; lvl < d.levels; ++lvl) {
+        const uint64_t i = c * g;
+        if (i >= n) break;
+        const uint64_t nv = (n - i) < g ? (n - i) : g;
+        uint32_t j = 0;
+        bool eq = false;
+        for (uint32_t e = 0; e < nv; ++e) {
+            const K kk = keys[i + e];
+            j += kk < x ? 1u : 0u;
+            eq |= kk == x;
+        }
+        if (j < nv) {
+            cand = i + j;
+            ceq = eq;
+        }
+        if (d.early && eq) break;
+        c = c * kf + 1 + j;
+    }
+    return ceq ? rows[cand] : kMiss;
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t learned_find(const K *__restrict__ keys, const uint32_t *__restrict__ rows,
+                                                 const Desc &d, K x) {
+    const uint64_t r = learned_lower_rank(keys, d.n, d.root, d.leaves, x);
+    return (r < d.n && keys[r] == x) ? rows[r] : kMiss;
+}
+
+// Index owning flat query position p: the last i with offsets[i] <= p, for
+// i in [lo, hi).
+__device__ __forceinline__ uint32_t owner(const uint64_t *__restrict__ off, uint32_t lo, uint32_t hi, uint64_t p) {
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (off[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename K>
+__global__ __launch_bounds__(BT) void k_batch_point(const Desc *__restrict__ descs, uint32_t count,
+                                                    const uint64_t *__restrict__ off, const K *__restrict__ q,
+                                                    uint32_t *__restrict__ out) {
+    const uint64_t total = off[count];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t wave_global = ((uint64_t)blockIdx.x * BT + threadIdx.x) / kWave;
+    const uint64_t waves = (uint64_t)gridDim.x * (BT / kWave);
+    constexpr uint64_t CH = (uint64_t)kWave * BR;  // queries per wave chunk
+    for (uint64_t c0 = wave_global * CH; c0 < total; c0 += waves * CH) {
+        const uint64_t c1 = c0 + CH < total ? c0 + CH : total;
+        // wave-uniform owners of the chunk's first and last query
+        const uint32_t i0 = owner(off, 0, count, c0);
+        const uint32_t i1 = owner(off, i0, count, c1 - 1);
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+            if (p >= c1) continue;
+            const uint32_t ii = (i0 == i1) ? i0 : owner(off, i0, i1 + 1, p);
+            const Desc d = descs[ii];
+            const K x = q[p];
+            const K *keys = (const K *)d.keys;
+            uint32_t res;
+            switch (d.form) {
+                case F_BS: res = bs_find<K>(keys, d.rows, d.n, x); break;
+                case F_EBS: res = ebs_find<K>(keys, d.rows, d.n, d.m_full, x); break;
+                case F_EKS: res = eks_find<K>(keys, d.rows, d, x); break;
+                default: res = learned_find<K>(keys, d.rows, d, x); break;
+            }
+            out[p] = res;
+        }
+    }
+}
+
+}  // namespace
+}  // namespace idx
+
+struct idx_batch {
+    idx::Desc *descs = nullptr;  // device
+    uint32_t count = 0;
+    bool u64 = false;
+    int cu_count = 256;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *g_q = nullptr;
+    const uint64_t *g_off = nullptr;
+    uint32_t *g_out = nullptr;
+    hipStream_t g_stream = nullptr;
+};
+
+using namespace idx;
+
+namespace {
+
+int launch_batch(idx_batch *b, const void *q, const uint64_t *off, uint32_t *out, hipStream_t s) {
+    // persistent grid: 8 workgroups of 4 waves per CU
+    const uint32_t grid = (uint32_t)b->cu_count * 8;
+    if (b->u64)
+        hipLaunchKernelGGL(k_batch_point<uint64_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->count, off,
+                           (const uint64_t *)q, out);
+    else
+        hipLaunchKernelGGL(k_batch_point<uint32_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->count, off,
+                           (const uint32_t *)q, out);
+    IDX_LAUNCH_CHECK();
+    return IDX_OK;
+}
+
+void drop_graph(idx_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->g_q = nullptr;
+    b->g_off = nullptr;
+    b->g_out = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream stream, idx_batch_t *out) {
+    if (!out) return IDX_ERR_ARG;
+    *out = nullptr;
+    if (!indexes || count == 0) return IDX_ERR_ARG;
+    const bool u64 = indexes[0] && indexes[0]->u64;
+    std::vector<Desc> host;
+    try {
+        host.resize(count);
+    } catch (...) {
+        return IDX_ERR_NOMEM;
+    }
+    for (uint32_t i = 0; i < count; ++i) {
+        const idx_index *h = indexes[i];
+        if (!h || h->u64 != u64 || h->aos) return IDX_ERR_ARG;
+        Desc d{};
+        d.keys = h->keys;
+        d.rows = h->rowids;
+        d.n = h->n;
+        d.k = h->geo.k;
+        d.g = h->geo.g;
+        d.levels = h->geo.levels;
+        d.m_full = h->geo.m;
+        d.gshift = (uint32_t)h->geo.gshift;
+        d.early = (h->unique && h->params.early_exit == 1) ? 1u : 0u;
+        if (h->layout == IDX_BS) {
+            d.form = F_BS;
+            if (h->learned && h->params.model != 2) {
+                d.form = F_LEARNED;
+                d.leaves = model_leaves(h);
+                d.root = model_root(h);
+            }
+        } else if (h->layout == IDX_EBS) {
+            d.form = F_EBS;
+        } else {
+            d.form = F_EKS;
+        }
+        host[i] = d;
+    }
+    idx_batch *b = new (std::nothrow) idx_batch();
+    if (!b) return IDX_ERR_NOMEM;
+    b->count = count;
+    b->u64 = u64;
+    hipStream_t s = (hipStream_t)stream;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        b->cu_count = cus;
+    (void)hipGetLastError();
+    if (hipMalloc((void **)&b->descs, sizeof(Desc) * count) != hipSuccess) {
+        (void)hipGetLastError();
+        delete b;
+        return IDX_ERR_NOMEM;
+    }
+    const hipError_t e = hipMemcpyAsync(b->descs, host.data(), sizeof(Desc) * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && hipStreamSynchronize(s) == hipSuccess) {
+        *out = b;
+        return IDX_OK;
+    }
+    (void)hipFree(b->descs);
+    delete b;
+    return hip_fail(e != hipSuccess ? e : hipErrorUnknown);
+}
+
+int idx_batch_point(idx_batch_t b, const void *queries, const uint64_t *offsets, uint32_t *out_rowid, uint32_t flags,
+                    idx_stream stream) {
+    if (!b || !offsets || (flags & ~IDX_BATCH_GRAPH)) return IDX_ERR_ARG;
+    if (!queries || !out_rowid) return IDX_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (!(flags & IDX_BATCH_GRAPH)) return launch_batch(b, queries, offsets, out_rowid, s);
+    if (!b->exec || b->g_q != queries || b->g_off != offsets || b->g_out != out_rowid || b->g_stream != s) {
+        drop_graph(b);
+        hipStream_t cs = nullptr;
+        IDX_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        int rc = IDX_OK;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            rc = launch_batch(b, queries, offsets, out_rowid, cs);
+            e = hipStreamEndCapture(cs, &b->graph);
+        }
+        if (e == hipSuccess && rc == IDX_OK) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess || rc != IDX_OK) {
+            drop_graph(b);
+            return rc != IDX_OK ? rc : hip_fail(e);
+        }
+        b->g_q = queries;
+        b->g_off = offsets;
+        b->g_out = out_rowid;
+        b->g_stream = s;
+    }
+    IDX_HIP(hipGraphLaunch(b->exec, s));
+    return IDX_OK;
+}
+
+int idx_batch_destroy(idx_batch_t b) {
+    if (!b) return IDX_OK;
+    (void)hipDeviceSynchronize();
+    drop_graph(b);
+    if (b->descs) (void)hipFree(b->descs);
+    (void)hipGetLastError();
+    delete b;
+    return IDX_OK;
+}
+
+}  // extern "C"

@@ -24,64 +24,17 @@
 // fit in one step from zero, the second step correcting FP32 rounding.
 #include <climits>
 
+#include <new>
+
 #include "internal.hpp"
+#include "learned_model.hpp"
 
 namespace idx {
-
-struct RootRec {
-    float a0, a1;    // t = a1 * x + a0, leaf = clamp(floor(t), 0, L - 1)
-    uint32_t mode;   // IDX_FEATURE_LINEAR / IDX_FEATURE_LOG
-    uint32_t L;
-};
-
-struct __align__(16) LeafRec {
-    uint64_t kmin;   // smallest build key of the leaf (0 when empty)
-    uint32_t base;   // rank of kmin
-    uint32_t size;   // keys in the leaf
-    float b0, b1;    // local rank prediction b1 * f32(key - kmin) + b0
-    int32_t elo, ehi;  // min / max of (true local rank - predicted local rank)
-};
-static_assert(sizeof(LeafRec) == 32, "leaf record is 32 bytes");
-
-struct LearnedModel {
-    RootRec root{};
-    LeafRec *leaves = nullptr;  // device, L records
-    idx_learn_stats stats{};
-};
 
 namespace {
 
 constexpr int LT = 256;  // threads per block in the training kernels
 constexpr int CHUNK = 32;  // consecutive keys per thread in the per-leaf passes
-
-// Monotone key feature in [0, 1].  LINEAR: the key itself; LOG: the bit
-// pattern of the key rounded to FP32, read as an integer -- a piecewise
-// linear approximation of log2(key).  Both use only correctly rounded
-// conversions and power-of-two scalings.
-__device__ __forceinline__ float key_feature(uint64_t key, uint32_t mode) {
-    const float f = (float)key;
-    if (mode == IDX_FEATURE_LINEAR) return f * 0x1p-64f;
-    return (float)__float_as_uint(f) * 0x1p-31f;
-}
-
-__device__ __forceinline__ uint32_t leaf_of(const RootRec &R, uint64_t key) {
-    const float x = key_feature(key, R.mode);
-    const float t = __fadd_rn(__fmul_rn(R.a1, x), R.a0);
-    if (!(t > 0.f)) return 0;
-    if (t >= (float)R.L) return R.L - 1;
-    return (uint32_t)t;
-}
-
-__device__ __forceinline__ float local_feature(const LeafRec &L, uint64_t key) {
-    return (float)(key > L.kmin ? key - L.kmin : 0ull);
-}
-
-__device__ __forceinline__ uint32_t pred_local(const LeafRec &L, uint64_t key) {
-    const float p = __fadd_rn(__fmul_rn(L.b1, local_feature(L, key)), L.b0);
-    if (!(p > 0.f)) return 0;
-    if (p >= (float)L.size) return L.size;
-    return (uint32_t)p;
-}
 
 // Accumulator layout per model: N, Sx, Sxx, Sr, Srx, Srr (FP64).
 constexpr int NACC = 6;
@@ -537,13 +490,7 @@ __global__ __launch_bounds__(1024) void k_point_learned(const K *__restrict__ ke
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const LeafRec L = leaves[leaf_of(root, (uint64_t)x[r])];
-            const int64_t p = (int64_t)pred_local(L, (uint64_t)x[r]);
-            int64_t w0 = p + L.elo, w1 = p + (int64_t)L.ehi + 1;
-            w0 = w0 < 0 ? 0 : (w0 > (int64_t)L.size ? (int64_t)L.size : w0);
-            w1 = w1 < w0 ? w0 : (w1 > (int64_t)L.size ? (int64_t)L.size : w1);
-            b[r] = L.base + (uint64_t)w0;
-            len[r] = (uint64_t)(w1 - w0);
+            learned_window(root, leaves, (uint64_t)x[r], b[r], len[r]);
             const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
             if (qi >= m) len[r] = 0;
         }
@@ -612,25 +559,6 @@ int point_learned(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStr
 #undef IDX_LEARNED_LAUNCH
     IDX_LAUNCH_CHECK();
     return IDX_OK;
-}
-
-// Lower-bound rank of x through the model (device, used by range counting).
-template <typename K>
-__device__ uint64_t learned_lower_rank(const K *__restrict__ keys, uint64_t n, const RootRec &root,
-                                       const LeafRec *__restrict__ leaves, K x) {
-    const LeafRec L = leaves[leaf_of(root, (uint64_t)x)];
-    const int64_t p = (int64_t)pred_local(L, (uint64_t)x);
-    int64_t w0 = p + L.elo, w1 = p + (int64_t)L.ehi + 1;
-    w0 = w0 < 0 ? 0 : (w0 > (int64_t)L.size ? (int64_t)L.size : w0);
-    w1 = w1 < w0 ? w0 : (w1 > (int64_t)L.size ? (int64_t)L.size : w1);
-    uint64_t b = L.base + (uint64_t)w0, len = (uint64_t)(w1 - w0);
-    while (len > 1) {
-        const uint64_t half = len >> 1;
-        b = keys[b + half - 1] < x ? b + half : b;
-        len -= half;
-    }
-    if (len == 1 && keys[b] < x) ++b;
-    return b;
 }
 
 namespace {

@@ -1,0 +1,92 @@
+// The learned rank model's records and its evaluation, shared by the
+// training/lookup kernels (learned.hip) and the batched launch (batch.hip).
+#pragma once
+
+#include "internal.hpp"
+
+namespace idx {
+
+struct RootRec {
+    float a0, a1;    // t = a1 * x + a0, leaf = clamp(floor(t), 0, L - 1)
+    uint32_t mode;   // IDX_FEATURE_LINEAR / IDX_FEATURE_LOG
+    uint32_t L;
+};
+
+struct __align__(16) LeafRec {
+    uint64_t kmin;     // smallest build key of the leaf (0 when empty)
+    uint32_t base;     // rank of kmin
+    uint32_t size;     // keys in the leaf
+    float b0, b1;      // local rank prediction b1 * f32(key - kmin) + b0
+    int32_t elo, ehi;  // min / max of (true local rank - predicted local rank)
+};
+static_assert(sizeof(LeafRec) == 32, "leaf record is 32 bytes");
+
+struct LearnedModel {
+    RootRec root{};
+    LeafRec *leaves = nullptr;  // device, L records
+    idx_learn_stats stats{};
+};
+
+inline const LeafRec *model_leaves(const idx_index *h) { return h->learned->leaves; }
+inline RootRec model_root(const idx_index *h) { return h->learned->root; }
+
+// Monotone key feature in [0, 1].  LINEAR: the key itself; LOG: the bit
+// pattern of the key rounded to FP32, read as an integer -- a piecewise
+// linear approximation of log2(key).  Both use only correctly rounded
+// conversions and power-of-two scalings.
+__device__ __forceinline__ float key_feature(uint64_t key, uint32_t mode) {
+    const float f = (float)key;
+    if (mode == IDX_FEATURE_LINEAR) return f * 0x1p-64f;
+    return (float)__float_as_uint(f) * 0x1p-31f;
+}
+
+// Multiply, then add, each rounded on its own (no contraction), so the same
+// key always lands in the same leaf wherever this is evaluated.
+__device__ __forceinline__ uint32_t leaf_of(const RootRec &R, uint64_t key) {
+    const float x = key_feature(key, R.mode);
+    const float t = __fadd_rn(__fmul_rn(R.a1, x), R.a0);
+    if (!(t > 0.f)) return 0;
+    if (t >= (float)R.L) return R.L - 1;
+    return (uint32_t)t;
+}
+
+__device__ __forceinline__ float local_feature(const LeafRec &L, uint64_t key) {
+    return (float)(key > L.kmin ? key - L.kmin : 0ull);
+}
+
+__device__ __forceinline__ uint32_t pred_local(const LeafRec &L, uint64_t key) {
+    const float p = __fadd_rn(__fmul_rn(L.b1, local_feature(L, key)), L.b0);
+    if (!(p > 0.f)) return 0;
+    if (p >= (float)L.size) return L.size;
+    return (uint32_t)p;
+}
+
+// Search window [first, first + len] of x: the leaf's predicted local rank
+// widened by the leaf's measured errors, clamped to the leaf's rank interval.
+__device__ __forceinline__ void learned_window(const RootRec &root, const LeafRec *__restrict__ leaves, uint64_t x,
+                                               uint64_t &first, uint64_t &len) {
+    const LeafRec L = leaves[leaf_of(root, x)];
+    const int64_t p = (int64_t)pred_local(L, x);
+    int64_t w0 = p + L.elo, w1 = p + (int64_t)L.ehi + 1;
+    w0 = w0 < 0 ? 0 : (w0 > (int64_t)L.size ? (int64_t)L.size : w0);
+    w1 = w1 < w0 ? w0 : (w1 > (int64_t)L.size ? (int64_t)L.size : w1);
+    first = L.base + (uint64_t)w0;
+    len = (uint64_t)(w1 - w0);
+}
+
+// Lower-bound rank of x through the model (exact: the window holds it).
+template <typename K>
+__device__ __forceinline__ uint64_t learned_lower_rank(const K *__restrict__ keys, uint64_t n, const RootRec &root,
+                                                       const LeafRec *__restrict__ leaves, K x) {
+    uint64_t b, len;
+    learned_window(root, leaves, (uint64_t)x, b, len);
+    while (len > 1) {
+        const uint64_t half = len >> 1;
+        b = keys[b + half - 1] < x ? b + half : b;
+        len -= half;
+    }
+    if (len == 1 && keys[b] < x) ++b;
+    return b;
+}
+
+}  // namespace idx

@@ -1,0 +1,126 @@
+"""GPU tests of the batched launch: one persistent launch over many indexes
+of mixed forms returns exactly what a per-index launch loop returns and what
+the oracle says; the HIP-graph replay path matches the eager launch on every
+replay."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import rows_host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+idx = pytest.importorskip("paper_2506_01576_amd")
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+FORMS = [("bs", 1, None), ("ebs", 2, None), ("eks", 5, None), ("eks", 9, None), ("eks", 17, None),
+         ("eks", 4, None), ("bs", 1, 64)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_batch(count, bits, seed, max_log2n=14, max_log2q=10):
+    rng = np.random.default_rng(seed)
+    sizes = gen.log_uniform(seed, 1, 1, 1 << max_log2n, count).astype(np.int64)
+    sizes[::17] = 0  # some empty indexes
+    sizes[5::23] = 1
+    qcounts = gen.log_uniform(seed, 2, 1, 1 << max_log2q, count).astype(np.int64)
+    qcounts[3::11] = 0  # some indexes get no queries
+    sets, qs = [], []
+    for i in range(count):
+        n = int(sizes[i])
+        if i % 5 == 0:  # duplicates
+            keys = rng.integers(0, max(1, n // 2), size=n, dtype=np.uint64).astype(np.uint64 if bits == 64 else np.uint32)
+        else:
+            keys, _ = gen.unique_keys(seed * 7919 + i, n, bits, 63 if bits == 64 else 32)
+        rows = (rng.permutation(n).astype(np.uint64) * 3 + 1).astype(np.uint32)
+        m = int(qcounts[i])
+        if n:
+            q = np.concatenate([keys[rng.integers(0, n, size=m - m // 5)],
+                                rng.integers(0, np.iinfo(keys.dtype).max, size=m // 5, dtype=np.uint64,
+                                             endpoint=True).astype(keys.dtype)])
+        else:
+            q = rng.integers(0, 1000, size=m, dtype=np.uint64).astype(np.uint64 if bits == 64 else np.uint32)
+        sets.append((keys, rows))
+        qs.append(q.astype(keys.dtype if n else q.dtype))
+    return sets, qs
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_batch_matches_loop_and_oracle(bits):
+    count = 300
+    sets, qs = make_batch(count, bits, seed=bits)
+    idxs = []
+    for i, (keys, rows) in enumerate(sets):
+        layout, k, learned = FORMS[i % len(FORMS)]
+        if learned and len(keys) == 0:
+            layout, learned = "bs", None
+        ix = idx.Index(to_dev(keys), to_dev(rows), layout=layout, k=k)
+        if learned:
+            ix.learn(learned, 2)
+        idxs.append(ix)
+    counts = np.array([len(q) for q in qs], dtype=np.uint64)
+    offsets = np.zeros(count + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(counts)
+    allq = np.concatenate(qs)
+    dq, doff = to_dev(allq), to_dev(offsets)
+    want = np.concatenate([oracle.point(*oracle.stable_sort(*sets[i]), qs[i]) if len(qs[i]) else
+                           np.zeros(0, np.uint32) for i in range(count)])
+    # per-index launch loop
+    loop = torch.empty(len(allq), dtype=torch.int32, device="cuda")
+    for i, ix in enumerate(idxs):
+        a, b = int(offsets[i]), int(offsets[i + 1])
+        if b > a:
+            ix.point(dq[a:b], loop[a:b])
+    loop_h = rows_host(loop)
+    assert np.array_equal(loop_h, want)
+    with idx.Batch(idxs) as bt:
+        got = rows_host(bt.point(dq, doff))
+        assert np.array_equal(got, want)
+        # graph replays, with eager work and synchronisations between them
+        out = torch.empty(len(allq), dtype=torch.int32, device="cuda")
+        for rep in range(4):
+            out.fill_(-7)
+            bt.point(dq, doff, out, graph=True)
+            torch.cuda.synchronize()
+            assert np.array_equal(rows_host(out), want), f"replay {rep}"
+            idxs[rep].point(dq[:16], loop[:16])  # unrelated eager work between replays
+            torch.cuda.synchronize()
+        # a different output buffer re-captures
+        out2 = torch.empty_like(out)
+        bt.point(dq, doff, out2, graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(rows_host(out2), want)
+    for ix in idxs:
+        ix.close()
+
+
+def test_batch_rejects_bad_sets():
+    k32, r32 = gen.unique_keys(1, 100, 32)
+    k64, r64 = gen.unique_keys(1, 100, 64)
+    with idx.Index(to_dev(k32), to_dev(r32), "bs") as a, idx.Index(to_dev(k64), to_dev(r64), "bs") as b:
+        with pytest.raises(idx.IdxError):
+            idx.Batch([a, b])
+    with idx.Index(to_dev(k32), to_dev(r32), "eks", k=9, aos=True) as c:
+        with pytest.raises(idx.IdxError):
+            idx.Batch([c])
+
+
+def test_batch_empty_query_set():
+    k32, r32 = gen.unique_keys(2, 1000, 32)
+    with idx.Index(to_dev(k32), to_dev(r32), "eks", k=9) as a:
+        with idx.Batch([a, a]) as bt:
+            off = torch.zeros(3, dtype=torch.int64, device="cuda")
+            q = torch.zeros(1, dtype=torch.int32, device="cuda")
+            out = torch.empty(1, dtype=torch.int32, device="cuda")
+            bt.point(q, off, out)
+            bt.point(q, off, out, graph=True)
+            torch.cuda.synchronize()
