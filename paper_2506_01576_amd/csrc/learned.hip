@@ -494,17 +494,19 @@ __global__ __launch_bounds__(1024) void k_point_learned(const K *__restrict__ ke
             const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
             if (qi >= m) len[r] = 0;
         }
-        // lower bound inside [b, b + len): first position with key >= x, or b + len
+        // The lower bound lies in [b, b + len].  Narrow wide windows with
+        // binary-search steps, then read the last <= 15 keys and the key after
+        // them in one round of independent loads.
         bool more = true;
         while (more) {
             more = false;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (len[r] > 1) {
+                if (len[r] > 15) {
                     const uint64_t half = len[r] >> 1;
                     b[r] = keys[b[r] + half - 1] < x[r] ? b[r] + half : b[r];
                     len[r] -= half;
-                    more |= len[r] > 1;
+                    more |= len[r] > 15;
                 }
             }
         }
@@ -513,14 +515,10 @@ __global__ __launch_bounds__(1024) void k_point_learned(const K *__restrict__ ke
             const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
             if (qi >= m) continue;
             uint32_t res = kMiss;
-            if (len[r] == 1) {
-                // candidate b (the window's last unresolved slot)
-                const K kb = keys[b[r]];
-                if (kb == x[r]) res = rows[b[r]];
-                else if (kb < x[r] && b[r] + 1 < n && keys[b[r] + 1] == x[r]) res = rows[b[r] + 1];
-            } else if (b[r] < n && keys[b[r]] == x[r]) {
-                res = rows[b[r]];
-            }
+            const uint64_t sl = (len[r] + 1) < (n - b[r]) ? (len[r] + 1) : (n - b[r]);
+            bool eq;
+            const uint32_t c = count_below<K, 16>(keys, b[r], (uint32_t)sl, x[r], eq);
+            if (eq) res = rows[b[r] + c];
             out[qi] = res;
         }
     }

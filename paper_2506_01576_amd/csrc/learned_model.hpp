@@ -3,6 +3,7 @@
 #pragma once
 
 #include "internal.hpp"
+#include "search.hpp"
 
 namespace idx {
 
@@ -80,13 +81,13 @@ __device__ __forceinline__ uint64_t learned_lower_rank(const K *__restrict__ key
                                                        const LeafRec *__restrict__ leaves, K x) {
     uint64_t b, len;
     learned_window(root, leaves, (uint64_t)x, b, len);
-    while (len > 1) {
+    while (len > 15) {
         const uint64_t half = len >> 1;
         b = keys[b + half - 1] < x ? b + half : b;
         len -= half;
     }
-    if (len == 1 && keys[b] < x) ++b;
-    return b;
+    bool eq;
+    return b + count_below<K, 16>(keys, b, (uint32_t)len, x, eq);
 }
 
 }  // namespace idx

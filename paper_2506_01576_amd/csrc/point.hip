@@ -24,6 +24,7 @@
 
 #include "internal.hpp"
 #include "access.hpp"
+#include "search.hpp"
 
 namespace idx {
 namespace {
@@ -83,11 +84,30 @@ __global__ __launch_bounds__(1024) void k_point_bs(PointArgs<K, AOS> a) {
                 len -= half;
             }
         }
-        while (len > 1) {
+        // SoA: stop the dependent probes at a window of at most 15 keys and
+        // read it (plus the key after it) with independent 16-byte loads
+        const uint64_t stop = AOS ? 1 : 15;
+        while (len > stop) {
             const uint64_t half = len >> 1;
 #pragma unroll
             for (int r = 0; r < R; ++r) base[r] = (a.L.key(base[r] + half) < x[r]) ? base[r] + half : base[r];
             len -= half;
+        }
+        if constexpr (!AOS) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
+                if (qi >= a.m) continue;
+                uint32_t res = kMiss;
+                if (n > 0) {
+                    const uint64_t sl = (len + 1) < (n - base[r]) ? (len + 1) : (n - base[r]);
+                    bool eq;
+                    const uint32_t c = count_below<K, 16>(a.L.k, base[r], (uint32_t)sl, x[r], eq);
+                    if (eq) res = a.L.row(base[r] + c);
+                }
+                a.out[qi] = res;
+            }
+            continue;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
