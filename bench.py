@@ -124,6 +124,82 @@ def read_traffic(kernel_key: str):
         return None
 
 
+def run_batched(args, idx, gen, np, torch, dev, log, table):
+    """Many uneven indexes in one persistent launch: `batch_indexes` uint32
+    indexes with n log-uniform in [2^6, 2^22], each with a point batch of
+    log-uniform size in [1, 2^16], 80% hits; the form of each index comes from
+    the tuned per-size-class table.  The one-launch rate (eager and replayed
+    from a HIP graph) is compared with a loop of one launch per index."""
+    from paper_2506_01576_amd import autotune
+
+    count = args.batch_indexes
+    seed = gen.BASE_SEED + 2
+    t0 = time.time()
+    sizes = gen.log_uniform(seed, 1, 1 << 6, 1 << 22, count)
+    qcounts = gen.log_uniform(seed, 2, 1, 1 << 16, count)
+    idxs, qs, ex, forms_used = [], [], [], {}
+    for j in range(count):
+        n = int(sizes[j])
+        kh, rh = gen.unique_keys(seed * 100003 + j, n, 32)
+        qh, eh = gen.point_queries(seed * 100003 + j, n, int(qcounts[j]), 0.8, 32)
+        form = autotune.batch_form(n, 32, table)
+        forms_used[str(form)] = forms_used.get(str(form), 0) + 1
+        ix = autotune.build_form(torch.from_numpy(kh.view(np.int32)).to(dev),
+                                 torch.from_numpy(rh.view(np.int32)).to(dev), form)
+        idxs.append(ix)
+        qs.append(qh)
+        ex.append(eh)
+    dq = torch.from_numpy(np.concatenate(qs).view(np.int32)).to(dev)
+    de = torch.from_numpy(np.concatenate(ex).view(np.int32)).to(dev)
+    off = np.zeros(count + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(q) for q in qs])
+    doff = torch.from_numpy(off).to(dev)
+    out = torch.empty(len(dq), dtype=torch.int32, device=dev)
+    total = int(off[-1])
+    log(f"batched: built {count} indexes ({int(sizes.sum())} keys), {total} queries in {time.time() - t0:.1f}s")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    res = {"indexes": count, "keys": int(sizes.sum()), "queries": total, "forms_by_count": forms_used}
+    with idx.Batch(idxs) as bt:
+        ms_eager = timed(lambda: bt.point(dq, doff, out), 10)
+        exact_eager = bool(torch.equal(out, de))
+        out.fill_(-1)
+        ms_graph = timed(lambda: bt.point(dq, doff, out, graph=True), 10)
+        exact_graph = bool(torch.equal(out, de))
+
+    def loop():
+        for j, ix in enumerate(idxs):
+            a, b = int(off[j]), int(off[j + 1])
+            if b > a:
+                ix.point(dq[a:b], out[a:b])
+
+    out.fill_(-1)
+    ms_loop = timed(loop, 2)
+    exact_loop = bool(torch.equal(out, de))
+    res.update({"ms_one_launch": round(ms_eager, 4), "ms_graph_replay": round(ms_graph, 4),
+                "ms_per_index_loop": round(ms_loop, 4),
+                "lookups_per_s_one_launch": total / ms_eager * 1e3,
+                "lookups_per_s_graph_replay": total / ms_graph * 1e3,
+                "lookups_per_s_per_index_loop": total / ms_loop * 1e3,
+                "speedup_vs_loop": ms_loop / min(ms_eager, ms_graph),
+                "bit_exact": exact_eager and exact_graph and exact_loop})
+    log(f"batched: one launch {ms_eager:.3f} ms, graph {ms_graph:.3f} ms, loop {ms_loop:.3f} ms")
+    for ix in idxs:
+        ix.close()
+    return res
+
+
 # --------------------------------------------------------------------------
 
 
@@ -137,6 +213,8 @@ def main():
     ap.add_argument("--log2ranges", type=int, default=24)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="leave the learned form out")
+    ap.add_argument("--no-batched", action="store_true", help="leave the many-index batched workload out")
+    ap.add_argument("--batch-indexes", type=int, default=8192)
     ap.add_argument("--sweep", action="store_true",
                     help="re-measure every candidate form (autotuner) instead of using the tuned table")
     ap.add_argument("--write-table", action="store_true", help="with --sweep: store the winners in the tuned table")
@@ -398,6 +476,20 @@ def main():
                          f"stable sort ({t_sort:.1f} s, 1 thread); lower_bound + equality per query, "
                          f"{cores} threads; answers equal the generator's: {cpu_exact}"}
 
+    # -------------------------------------------------- batched many-index launch
+    batched = None
+    if not args.no_batched:
+        del out, q, expect
+        torch.cuda.empty_cache()
+        from paper_2506_01576_amd import autotune as _at
+        table = _at.load_table()
+        if args.sweep:
+            batch_sweep = _at.tune_batch(gen, 32, log=log)
+            table = _at.record_batch(table, 32, batch_sweep)
+        batched = run_batched(args, idx, gen, np, torch, dev, log, table)
+        if args.sweep:
+            batched["class_sweep"] = table.get("batch")
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -425,6 +517,7 @@ def main():
         "range_lookups_per_s": {k[6:]: mr / v * 1e3 for k, v in mean.items() if k.startswith("range_")},
         "bit_exact": all(r["bit_exact"] for r in checked),
         "random_access": probe,
+        "batched": batched,
         "sweep": [{kk: r[kk] for kk in ("layout", "k", "aos", "params", "ms", "lookups_per_s", "bit_exact")}
                   for r in sweep],
     }

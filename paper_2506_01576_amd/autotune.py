@@ -157,3 +157,95 @@ def choose(n: int, key_bits: int, layout: str | None = None, table: dict | None 
     ents.sort(key=lambda e: (dist(e), -e["lookups_per_s"]))
     e = ents[0]
     return e["layout"], e["k"], e["aos"], dict(e["params"])
+
+
+# --------------------------------------------------------------- batched
+# Forms the batched launch supports (per-lane descents): (layout, k, learned
+# leaves per key or 0).
+BATCH_FORMS = [("bs", 1, 0), ("ebs", 2, 0), ("eks", 5, 0), ("eks", 9, 0), ("eks", 17, 0), ("bs", 1, 64)]
+BATCH_CLASSES = [(6, 8), (9, 11), (12, 14), (15, 17), (18, 20), (21, 22)]
+
+
+def build_form(keys: torch.Tensor, rows: torch.Tensor, form) -> Index:
+    """Build one index in a batch form (layout, k, keys-per-leaf or 0)."""
+    layout, k, per_leaf = form
+    ix = Index(keys, rows, layout=layout, k=k)
+    if per_leaf:
+        ix.learn(max(1, len(keys) // per_leaf), 2)
+    return ix
+
+
+def tune_batch(gen_module, key_bits: int = 32, per_class: int = 48, queries_per_index: int = 1 << 13,
+               seed: int = 7, log=None):
+    """For every size class, time the batched launch over `per_class`
+    indexes built in each candidate form; returns {class_lo: best record}."""
+    from ._binding import Batch
+    import numpy as np
+
+    best = {}
+    dev = torch.device("cuda")
+    for lo, hi in BATCH_CLASSES:
+        sizes = gen_module.log_uniform(seed + lo, 3, 1 << lo, 1 << hi, per_class)
+        sets, qs, ex = [], [], []
+        for j, n in enumerate(sizes.tolist()):
+            kh, rh = gen_module.unique_keys(seed * 1000 + lo * 100 + j, int(n), key_bits)
+            qh, eh = gen_module.point_queries(seed * 1000 + lo * 100 + j, int(n), queries_per_index, 0.8, key_bits)
+            sets.append((kh, rh))
+            qs.append(qh)
+            ex.append(eh)
+        view = np.int32 if key_bits == 32 else np.int64
+        dq = torch.from_numpy(np.concatenate(qs).view(view)).to(dev)
+        de = torch.from_numpy(np.concatenate(ex).view(np.int32)).to(dev)
+        off = np.zeros(per_class + 1, dtype=np.int64)
+        off[1:] = np.cumsum([len(q) for q in qs])
+        doff = torch.from_numpy(off).to(dev)
+        out = torch.empty(len(dq), dtype=torch.int32, device=dev)
+        for form in BATCH_FORMS:
+            idxs = [build_form(torch.from_numpy(kh.view(view)).to(dev), torch.from_numpy(rh.view(np.int32)).to(dev),
+                               form) for kh, rh in sets]
+            with Batch(idxs) as bt:
+                bt.point(dq, doff, out)
+                torch.cuda.synchronize()
+                exact = bool(torch.equal(out, de))
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(5):
+                    bt.point(dq, doff, out)
+                b.record()
+                b.synchronize()
+                ms = a.elapsed_time(b) / 5
+            for ix in idxs:
+                ix.close()
+            rec = {"log2n_lo": lo, "log2n_hi": hi, "layout": form[0], "k": form[1], "keys_per_leaf": form[2],
+                   "ms": round(ms, 4), "lookups_per_s": len(dq) / ms * 1e3, "bit_exact": exact}
+            if log:
+                log(f"batch class 2^{lo}-2^{hi} form {form}: {ms:.3f} ms {rec['lookups_per_s'] / 1e9:.2f} G/s "
+                    f"exact={exact}")
+            if exact and (lo not in best or ms < best[lo]["ms"]):
+                best[lo] = rec
+    return best
+
+
+def record_batch(table: dict, key_bits: int, best: dict):
+    table["batch"] = [e for e in table.get("batch", []) if e["key_bits"] != key_bits]
+    for lo, rec in sorted(best.items()):
+        table["batch"].append({"key_bits": key_bits, **rec})
+    return table
+
+
+def batch_form(n: int, key_bits: int, table: dict | None = None):
+    """(layout, k, keys per leaf) for an index of n keys in a batch."""
+    table = table if table is not None else load_table()
+    lg = max(0, math.ceil(math.log2(max(n, 1))))
+    ents = [e for e in table.get("batch", []) if e["key_bits"] == key_bits]
+    if not ents:
+        return ("ebs", 2, 0) if lg <= 16 else ("eks", 9, 0)
+
+    def dist(e):
+        if e["log2n_lo"] <= lg <= e["log2n_hi"]:
+            return 0
+        return min(abs(lg - e["log2n_lo"]), abs(lg - e["log2n_hi"]))
+
+    e = min(ents, key=dist)
+    return e["layout"], e["k"], e["keys_per_leaf"]
