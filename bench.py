@@ -96,10 +96,14 @@ def algo_bytes(form: str, n: int, k: int, key_bytes: int, early_exit: bool = Tru
 
 
 def source_sha() -> str:
+    """Hash of every kernel source: traffic counters are only reported while
+    they were taken on exactly these sources."""
     h = hashlib.sha256()
-    for f in ("point.hip", "access.hpp", "internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2506_01576_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2506_01576_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
