@@ -279,6 +279,23 @@ typedef struct idx_learn_stats {
  */
 int idx_learn(idx_handle h, uint32_t leaves, uint32_t epochs, uint32_t feature, idx_stream stream);
 
+/*
+ * idx_learn_batch -- train the models of `count` indexes at once: every
+ * kernel of one launch sequence spans all of them (the batched form of
+ * idx_learn: same model, stages and Newton steps; the FP64 sums may add in
+ * another order, so weights can differ from idx_learn's in the last FP32
+ * bit, while every lookup answer stays exact).
+ *
+ *   indexes  count distinct IDX_BS SoA indexes, n >= 1, one key width
+ *   leaves   count leaf counts (host array), each 1 .. 2^22
+ *   epochs   1..16;  feature IDX_FEATURE_* (AUTO picks per index)
+ * Each index's previous model is replaced.  Scratch comes from the first
+ * index's allocator.  Synchronises `stream` once.  Errors: IDX_ERR_ARG
+ * (nothing changed), IDX_ERR_NOMEM, IDX_ERR_HIP (no index keeps a model).
+ */
+int idx_learn_batch(const idx_handle *indexes, uint32_t count, const uint32_t *leaves, uint32_t epochs,
+                    uint32_t feature, idx_stream stream);
+
 /* Statistics of the attached model (IDX_ERR_ARG when there is none). */
 int idx_learn_stats_get(idx_handle h, idx_learn_stats *out);
 
@@ -338,6 +355,33 @@ int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream strea
  */
 int idx_batch_point(idx_batch_t b, const void *queries, const uint64_t *offsets, uint32_t *out_rowid, uint32_t flags,
                     idx_stream stream);
+
+/*
+ * idx_batch_mixed -- a stream of point and range lookups over every index of
+ * the batch (Section 1's two lookup kinds; range output as idx_range).
+ * Queries are grouped by index as in idx_batch_point (offsets: count + 1
+ * device u64, offsets[count] = m).  Query p is a point lookup of lo[p] when
+ * kind[p] == 0 (hi[p] ignored) and the range [lo[p], hi[p]] when kind[p] == 1
+ * (inclusive; lo > hi is empty).
+ *
+ *   lo, hi         m keys each (device, the batch's key width)
+ *   kind           m bytes (device), 0 or 1
+ *   out_rowid      m (device): the row ID or IDX_MISS for points, IDX_MISS
+ *                  for ranges
+ *   range_offsets  m + 1 (device u64): exclusive prefix of the match counts
+ *                  (0 for points); range_offsets[m] = total
+ *   range_rowids   capacity entries (device): each range's row IDs in key
+ *                  order from range_offsets[p]; NULL = counts only
+ *   total          host, receives the number of matches (may be NULL)
+ * Two persistent launches around one scan: the first answers the points and
+ * sizes the ranges, the second writes the ranges.  Synchronises `stream`
+ * once (to read the total).  m <= 2^32 - 1.  Errors: IDX_ERR_ARG,
+ * IDX_ERR_CAPACITY (total > capacity: offsets and point answers written,
+ * no range row IDs), IDX_ERR_HIP.
+ */
+int idx_batch_mixed(idx_batch_t b, uint64_t m, const void *lo, const void *hi, const uint8_t *kind,
+                    const uint64_t *offsets, uint32_t *out_rowid, uint64_t *range_offsets, uint32_t *range_rowids,
+                    uint64_t capacity, uint64_t *total, idx_stream stream);
 
 /* Free the batch (synchronises the device first).  NULL is accepted. */
 int idx_batch_destroy(idx_batch_t b);

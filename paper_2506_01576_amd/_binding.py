@@ -119,6 +119,8 @@ SIGNATURES = {
     "idx_batch_create": (_I, [ctypes.POINTER(_P), _U32, _P, ctypes.POINTER(_P)]),
     "idx_batch_point": (_I, [_P, _P, _P, _P, _U32, _P]),
     "idx_batch_destroy": (_I, [_P]),
+    "idx_batch_mixed": (_I, [_P, _U64, _P, _P, _P, _P, _P, _P, _P, _U64, ctypes.POINTER(_U64), _P]),
+    "idx_learn_batch": (_I, [ctypes.POINTER(_P), _U32, ctypes.POINTER(_U32), _U32, _U32, _P]),
     "idx_learn": (_I, [_P, _U32, _U32, _U32, _P]),
     "idx_learn_stats_get": (_I, [_P, ctypes.POINTER(idx_learn_stats)]),
     "idx_learn_export": (_I, [_P, _P, _P]),
@@ -344,6 +346,20 @@ class Index:
 IDX_BATCH_GRAPH = 1
 
 
+def learn_batch(indexes, leaves, epochs: int = 2, feature: int = IDX_FEATURE_AUTO, stream=None):
+    """Train the models of many sorted-array indexes with one launch sequence
+    (idx_learn_batch); `leaves` is one count per index.  Returns each
+    index's model statistics."""
+    indexes = list(indexes)
+    leaves = list(leaves)
+    if len(leaves) != len(indexes):
+        raise ValueError("one leaf count per index")
+    arr = (ctypes.c_void_p * len(indexes))(*[ix._h.value for ix in indexes])
+    lv = (ctypes.c_uint32 * len(leaves))(*leaves)
+    _check(lib().idx_learn_batch(arr, len(indexes), lv, epochs, feature, _stream(stream)), "idx_learn_batch")
+    return [ix.learn_stats() for ix in indexes]
+
+
 class Batch:
     """Many indexes served by one persistent launch (idx_batch_*).  The
     indexes must stay open while the batch is used."""
@@ -364,6 +380,30 @@ class Batch:
         _check(lib().idx_batch_point(self._h, queries.data_ptr(), offsets.data_ptr(), out.data_ptr(),
                                      IDX_BATCH_GRAPH if graph else 0, _stream(stream)), "idx_batch_point")
         return out
+
+    def mixed(self, lo: torch.Tensor, hi: torch.Tensor, kind: torch.Tensor, offsets: torch.Tensor,
+              capacity: int | None = None, stream=None):
+        """Mixed point/range stream (idx_batch_mixed).  Returns (rowid[m]
+        int32, range_offsets[m+1] int64, range_rowids[total] int32)."""
+        for t, nm in ((lo, "lo"), (hi, "hi"), (kind, "kind"), (offsets, "offsets")):
+            _dev(t, nm)
+        if kind.dtype != torch.uint8:
+            raise TypeError("kind must be uint8")
+        m = len(lo)
+        out = torch.empty(m, dtype=torch.int32, device=lo.device)
+        offs = torch.empty(m + 1, dtype=torch.int64, device=lo.device)
+        total = ctypes.c_uint64(0)
+        s = _stream(stream)
+        if capacity is None:
+            _check(lib().idx_batch_mixed(self._h, m, lo.data_ptr(), hi.data_ptr(), kind.data_ptr(), offsets.data_ptr(),
+                                         out.data_ptr(), offs.data_ptr(), None, 0, ctypes.byref(total), s),
+                   "idx_batch_mixed(count)")
+            capacity = total.value
+        rows = torch.empty(max(1, capacity), dtype=torch.int32, device=lo.device)
+        _check(lib().idx_batch_mixed(self._h, m, lo.data_ptr(), hi.data_ptr(), kind.data_ptr(), offsets.data_ptr(),
+                                     out.data_ptr(), offs.data_ptr(), rows.data_ptr(), capacity, ctypes.byref(total),
+                                     s), "idx_batch_mixed")
+        return out, offs, rows[: total.value]
 
     def close(self):
         if getattr(self, "_h", None):

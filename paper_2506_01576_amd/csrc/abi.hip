@@ -62,12 +62,23 @@ int cu_count_of_current_device() {
     return cus > 0 ? cus : 256;
 }
 
+size_t lds_max_of_current_device() {
+    int dev = 0, bytes = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&bytes, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 64 * 1024;
+    }
+    return bytes > 0 ? (size_t)bytes : 64 * 1024;
+}
+
 // Layout allocations are padded so that a full-node vector read at the last
 // (partial) node stays inside the buffer.
 uint64_t padded_slots(uint64_t slots) { return ((slots + 63) / 64) * 64 + 64; }
 
 void free_handle_buffers(idx_index *h, hipStream_t s) {
     drop_model(h, s);
+    drop_splitters(h, s);
     h->alloc.put(h->keys, s);
     h->alloc.put(h->rowids, s);
     h->alloc.put(h->pin, s);
@@ -168,6 +179,7 @@ int new_handle(uint64_t n, int layout, uint32_t k, uint32_t flags, const idx_all
         }
     }
     h->cu_count = cu_count_of_current_device();
+    h->lds_max = lds_max_of_current_device();
     *out = h;
     return IDX_OK;
 }
@@ -344,6 +356,16 @@ int idx_learn(idx_handle h, uint32_t leaves, uint32_t epochs, uint32_t feature, 
     if (!h) return IDX_ERR_ARG;
     h->last_stream = (hipStream_t)stream;
     return learn(h, leaves, epochs, feature, (hipStream_t)stream);
+}
+
+int idx_learn_batch(const idx_handle *indexes, uint32_t count, const uint32_t *leaves, uint32_t epochs,
+                    uint32_t feature, idx_stream stream) {
+    if (!indexes || count == 0) return IDX_ERR_ARG;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (!indexes[i]) return IDX_ERR_ARG;
+        indexes[i]->last_stream = (hipStream_t)stream;
+    }
+    return learn_batch(indexes, count, leaves, epochs, feature, (hipStream_t)stream);
 }
 
 int idx_learn_stats_get(idx_handle h, idx_learn_stats *out) {

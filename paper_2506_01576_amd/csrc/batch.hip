@@ -10,6 +10,15 @@
 // node in registers) or the learned window search -- the form the autotuner
 // chose for the index's size class.  Everything the kernel needs is in device
 // memory, so the launch can be captured once in a HIP graph and replayed.
+//
+// The mixed stream (idx_batch_mixed) adds range lookups to the same walk: a
+// first persistent launch answers every point lookup and sizes every range
+// (first and past-the-end rank of its bounds), an exclusive scan turns the
+// sizes into output offsets, and a second persistent launch writes each
+// range's row IDs in key order -- a wave-cooperative copy of the contiguous
+// run on the sorted-array forms, the level scan with rank scatter of
+// Section 5 on the Eytzinger forms (each index's tree geometry is kept in a
+// device table beside its descriptor).
 #include <new>
 #include <vector>
 
@@ -153,11 +162,176 @@ __global__ __launch_bounds__(BT) void k_batch_point(const Desc *__restrict__ des
     }
 }
 
+// ------------------------------------------------------------ mixed stream
+
+enum : uint8_t { Q_POINT = 0, Q_RANGE = 1 };
+
+// Sorted rank of the first key >= x in the index of descriptor d.
+template <typename K>
+__device__ __forceinline__ uint64_t form_lower_rank(const Desc &d, const Geo &G, K x) {
+    const K *keys = (const K *)d.keys;
+    const uint64_t n = d.n;
+    if (n == 0) return 0;
+    if (d.form == F_BS) {
+        uint64_t base = 0, len = n;
+        while (len > 1) {
+            const uint64_t half = len >> 1;
+            base = keys[base + half] < x ? base + half : base;
+            len -= half;
+        }
+        return base + (keys[base] < x ? 1 : 0);
+    }
+    if (d.form == F_LEARNED) return learned_lower_rank(keys, n, d.root, d.leaves, x);
+    // Eytzinger layouts: deepest path position of the lower bound, then its rank
+    const uint64_t off = d.form == F_EBS ? 1 : 0;
+    const uint32_t g = G.g, kf = G.k;
+    uint64_t c = 0, cand = ~0ull;
+    while (c * g < n) {
+        const uint64_t i = c * g;
+        const uint64_t nv = (n - i) < g ? (n - i) : g;
+        uint32_t j = 0;
+        for (uint32_t e = 0; e < nv; ++e) j += keys[off + i + e] < x ? 1u : 0u;
+        if (j < nv) cand = i + j;
+        c = c * kf + 1 + j;
+    }
+    return cand == ~0ull ? n : slot_rank(G, cand);
+}
+
+template <typename K>
+__device__ __forceinline__ uint32_t form_find(const Desc &d, K x) {
+    const K *keys = (const K *)d.keys;
+    switch (d.form) {
+        case F_BS: return bs_find<K>(keys, d.rows, d.n, x);
+        case F_EBS: return ebs_find<K>(keys, d.rows, d.n, d.m_full, x);
+        case F_EKS: return eks_find<K>(keys, d.rows, d, x);
+        default: return learned_find<K>(keys, d.rows, d, x);
+    }
+}
+
+// Pass 1: point answers; range sizes into offs (scanned afterwards) and the
+// first rank of every range.
+template <typename K>
+__global__ __launch_bounds__(BT) void k_batch_mixed_count(const Desc *__restrict__ descs, const Geo *__restrict__ geos,
+                                                          uint32_t count, const uint64_t *__restrict__ off, uint64_t m,
+                                                          const K *__restrict__ lo, const K *__restrict__ hi,
+                                                          const uint8_t *__restrict__ kind,
+                                                          uint32_t *__restrict__ out, uint32_t *__restrict__ first,
+                                                          uint64_t *__restrict__ offs) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t wave_global = ((uint64_t)blockIdx.x * BT + threadIdx.x) / kWave;
+    const uint64_t waves = (uint64_t)gridDim.x * (BT / kWave);
+    constexpr uint64_t CH = (uint64_t)kWave * BR;
+    for (uint64_t c0 = wave_global * CH; c0 < m; c0 += waves * CH) {
+        const uint64_t c1 = c0 + CH < m ? c0 + CH : m;
+        const uint32_t i0 = owner(off, 0, count, c0);
+        const uint32_t i1 = owner(off, i0, count, c1 - 1);
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+            if (p >= c1) continue;
+            const uint32_t ii = (i0 == i1) ? i0 : owner(off, i0, i1 + 1, p);
+            const Desc d = descs[ii];
+            if (kind[p] == Q_POINT) {
+                out[p] = form_find<K>(d, lo[p]);
+                first[p] = 0;
+                offs[p] = 0;
+                continue;
+            }
+            out[p] = kMiss;
+            const K L = lo[p], U = hi[p];
+            uint64_t r0 = 0, r1 = 0;
+            if (L <= U) {
+                const Geo &G = geos[ii];
+                r0 = form_lower_rank<K>(d, G, L);
+                r1 = (U == ~K(0)) ? d.n : form_lower_rank<K>(d, G, (K)(U + 1));
+            }
+            first[p] = (uint32_t)r0;
+            offs[p] = r1 > r0 ? r1 - r0 : 0;
+        }
+    }
+}
+
+// Pass 2: row IDs of every range in key order at its offset.
+template <typename K>
+__global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict__ descs, const Geo *__restrict__ geos,
+                                                         uint32_t count, const uint64_t *__restrict__ off, uint64_t m,
+                                                         const K *__restrict__ lo, const K *__restrict__ hi,
+                                                         const uint8_t *__restrict__ kind,
+                                                         const uint32_t *__restrict__ first,
+                                                         const uint64_t *__restrict__ offs,
+                                                         uint32_t *__restrict__ rows_out) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t wave_global = ((uint64_t)blockIdx.x * BT + threadIdx.x) / kWave;
+    const uint64_t waves = (uint64_t)gridDim.x * (BT / kWave);
+    constexpr uint64_t CH = (uint64_t)kWave * BR;
+    for (uint64_t c0 = wave_global * CH; c0 < m; c0 += waves * CH) {
+        const uint64_t c1 = c0 + CH < m ? c0 + CH : m;
+        const uint32_t i0 = owner(off, 0, count, c0);
+        const uint32_t i1 = owner(off, i0, count, c1 - 1);
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+            const bool live = p < c1;
+            const uint32_t ii = !live ? 0u : (i0 == i1) ? i0 : owner(off, i0, i1 + 1, p);
+            // this lane's run: a sorted-array range is copied by the whole
+            // wave below; an Eytzinger range is scanned by its own lane
+            const uint32_t *run_rows = nullptr;
+            uint64_t run_first = 0, run_out = 0, run_len = 0;
+            if (live && kind[p] == Q_RANGE) {
+                const uint64_t o = offs[p], cnt = offs[p + 1] - o;
+                const Desc d = descs[ii];
+                if (cnt > 0 && (d.form == F_BS || d.form == F_LEARNED)) {
+                    run_rows = d.rows;
+                    run_first = first[p];
+                    run_out = o;
+                    run_len = cnt;
+                } else if (cnt > 0) {
+                    const Geo &G = geos[ii];
+                    const K *keys = (const K *)d.keys;
+                    const uint64_t base = d.form == F_EBS ? 1 : 0;
+                    const K L = lo[p], U = hi[p];
+                    const uint64_t r0 = first[p], n = d.n;
+                    const uint32_t g = G.g, kf = G.k;
+                    uint64_t c = 0;
+                    uint32_t lvl = 0;
+                    while (c * g < n) {
+                        const uint64_t i = c * g;
+                        const uint64_t nv = (n - i) < g ? (n - i) : g;
+                        uint32_t j = 0;
+                        for (uint32_t e = 0; e < nv; ++e) j += keys[base + i + e] < L ? 1u : 0u;
+                        const uint64_t level_end = G.start[lvl + 1] < n ? G.start[lvl + 1] : n;
+                        for (uint64_t t = i + j; t < level_end; ++t) {
+                            if (keys[base + t] > U) break;
+                            const uint64_t dd = slot_rank(G, t) - r0;  // position in key order
+                            if (dd < cnt) rows_out[o + dd] = d.rows[base + t];
+                        }
+                        c = c * kf + 1 + j;
+                        ++lvl;
+                    }
+                }
+            }
+            // wave-cooperative copies of the sorted-array runs, one lane's run at a time
+            uint64_t pending = __ballot(run_len > 0);
+            while (pending) {
+                const int src = __builtin_ctzll(pending);
+                pending &= pending - 1;
+                const uint64_t rr = (uint64_t)__shfl((long long)(uintptr_t)run_rows, src, kWave);
+                const uint64_t f0 = (uint64_t)__shfl((long long)run_first, src, kWave);
+                const uint64_t o0 = (uint64_t)__shfl((long long)run_out, src, kWave);
+                const uint64_t len = (uint64_t)__shfl((long long)run_len, src, kWave);
+                const uint32_t *rows = (const uint32_t *)(uintptr_t)rr;
+                for (uint64_t e = lane; e < len; e += kWave) rows_out[o0 + e] = rows[f0 + e];
+            }
+        }
+    }
+}
+
 }  // namespace
 }  // namespace idx
 
 struct idx_batch {
     idx::Desc *descs = nullptr;  // device
+    idx::Geo *geos = nullptr;    // device, one per index (tree geometry for range lookups)
     uint32_t count = 0;
     bool u64 = false;
     int cu_count = 256;
@@ -247,19 +421,32 @@ int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream strea
     if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
         b->cu_count = cus;
     (void)hipGetLastError();
-    if (hipMalloc((void **)&b->descs, sizeof(Desc) * count) != hipSuccess) {
-        (void)hipGetLastError();
+    std::vector<Geo> geos;
+    try {
+        geos.resize(count);
+    } catch (...) {
         delete b;
         return IDX_ERR_NOMEM;
     }
-    const hipError_t e = hipMemcpyAsync(b->descs, host.data(), sizeof(Desc) * count, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && hipStreamSynchronize(s) == hipSuccess) {
+    for (uint32_t i = 0; i < count; ++i) geos[i] = indexes[i]->geo;
+    if (hipMalloc((void **)&b->descs, sizeof(Desc) * count) != hipSuccess ||
+        hipMalloc((void **)&b->geos, sizeof(Geo) * count) != hipSuccess) {
+        (void)hipGetLastError();
+        if (b->descs) (void)hipFree(b->descs);
+        delete b;
+        return IDX_ERR_NOMEM;
+    }
+    hipError_t e = hipMemcpyAsync(b->descs, host.data(), sizeof(Desc) * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->geos, geos.data(), sizeof(Geo) * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
         *out = b;
         return IDX_OK;
     }
     (void)hipFree(b->descs);
+    (void)hipFree(b->geos);
     delete b;
-    return hip_fail(e != hipSuccess ? e : hipErrorUnknown);
+    return hip_fail(e);
 }
 
 int idx_batch_point(idx_batch_t b, const void *queries, const uint64_t *offsets, uint32_t *out_rowid, uint32_t flags,
@@ -293,10 +480,71 @@ int idx_batch_point(idx_batch_t b, const void *queries, const uint64_t *offsets,
     return IDX_OK;
 }
 
+int idx_batch_mixed(idx_batch_t b, uint64_t m, const void *lo, const void *hi, const uint8_t *kind,
+                    const uint64_t *offsets, uint32_t *out_rowid, uint64_t *range_offsets, uint32_t *range_rowids,
+                    uint64_t capacity, uint64_t *total, idx_stream stream) {
+    if (!b || !offsets || !range_offsets) return IDX_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (m == 0) {
+        IDX_HIP(hipMemsetAsync(range_offsets, 0, sizeof(uint64_t), s));
+        if (total) *total = 0;
+        return IDX_OK;
+    }
+    if (!lo || !hi || !kind || !out_rowid || m > 0xFFFFFFFFull) return IDX_ERR_ARG;
+    const uint64_t parts = scan_partials_for(m);
+    char *tmp = nullptr;
+    const size_t first_b = ((size_t)m * 4 + 255) & ~(size_t)255;
+    IDX_HIP(hipMallocAsync((void **)&tmp, first_b + parts * 8, s));
+    uint32_t *first = (uint32_t *)tmp;
+    uint64_t *partial = (uint64_t *)(tmp + first_b);
+    const uint32_t grid = (uint32_t)b->cu_count * 8;
+    int rc = IDX_OK;
+    do {
+        if (b->u64)
+            hipLaunchKernelGGL(k_batch_mixed_count<uint64_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count,
+                               offsets, m, (const uint64_t *)lo, (const uint64_t *)hi, kind, out_rowid, first,
+                               range_offsets);
+        else
+            hipLaunchKernelGGL(k_batch_mixed_count<uint32_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count,
+                               offsets, m, (const uint32_t *)lo, (const uint32_t *)hi, kind, out_rowid, first,
+                               range_offsets);
+        if (hipGetLastError() != hipSuccess) {
+            rc = IDX_ERR_HIP;
+            break;
+        }
+        rc = exclusive_scan_u64(range_offsets, m, partial, s);
+        if (rc != IDX_OK) break;
+        uint64_t tot = 0;
+        if (hipMemcpyAsync(&tot, range_offsets + m, sizeof(tot), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = IDX_ERR_HIP;
+            break;
+        }
+        if (total) *total = tot;
+        if (tot == 0 || !range_rowids) break;  // nothing to write, or counts only
+        if (tot > capacity) {
+            rc = IDX_ERR_CAPACITY;
+            break;
+        }
+        if (b->u64)
+            hipLaunchKernelGGL(k_batch_mixed_fill<uint64_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count,
+                               offsets, m, (const uint64_t *)lo, (const uint64_t *)hi, kind, first, range_offsets,
+                               range_rowids);
+        else
+            hipLaunchKernelGGL(k_batch_mixed_fill<uint32_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count,
+                               offsets, m, (const uint32_t *)lo, (const uint32_t *)hi, kind, first, range_offsets,
+                               range_rowids);
+        if (hipGetLastError() != hipSuccess) rc = IDX_ERR_HIP;
+    } while (0);
+    (void)hipFreeAsync(tmp, s);
+    return rc;
+}
+
 int idx_batch_destroy(idx_batch_t b) {
     if (!b) return IDX_OK;
     (void)hipDeviceSynchronize();
     drop_graph(b);
+    if (b->geos) (void)hipFree(b->geos);
     if (b->descs) (void)hipFree(b->descs);
     (void)hipGetLastError();
     delete b;

@@ -68,7 +68,10 @@ struct idx_index {
     float ms_sort = 0.f, ms_permute = 0.f;
     hipStream_t last_stream = nullptr;
     int cu_count = 256;
+    size_t lds_max = 64 * 1024;  // LDS bytes one workgroup may use on this device
     idx::LearnedModel *learned = nullptr;  // attached rank model (BS layout only)
+    void *split = nullptr;       // rank-bucket splitter keys for partitioned lookups
+    uint32_t split_buckets = 0;  // buckets those splitters define (0 = none built)
 };
 
 namespace idx {
@@ -98,24 +101,48 @@ int build_pin(idx_index *h, uint32_t levels, hipStream_t s);
 __host__ __device__ inline uint64_t slot_rank(const Geo &G, uint64_t t);
 
 // ---- point.hip --------------------------------------------------------------
+// Where one point-lookup launch reads its queries and writes its answers.
+struct PointIO {
+    const void *q;
+    uint64_t m;
+    uint32_t *out;
+    bool local_sort;       // sort each tile of lookups in LDS first (Section 7.4)
+    bool xcd;              // walk tiles XCD by XCD
+};
 int point_lookup(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s);
+// One launch of the handle's point-lookup form over `io`.
+int point_run(idx_index *h, const PointIO &io, hipStream_t s);
 // Resolve defaults and validate a parameter set for h.
 int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_params *out);
 // Largest number of top levels whose keys fit in `bytes` of LDS.
 uint32_t pin_levels_for(const idx_index *h, size_t bytes);
+// Pin-table entries (keys) for `levels` top levels.
+uint32_t pin_entries_for(const idx_index *h, uint32_t levels);
+
+// ---- reorder.hip ------------------------------------------------------------
+// Point lookups on a batch partitioned by rank bucket first.
+int point_partitioned(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s);
+void drop_splitters(idx_index *h, hipStream_t s);
 
 // ---- range.hip --------------------------------------------------------------
+// Exclusive scan of v[0..m) in place, v[m] = total; partial holds
+// ceil(m / 4096) entries.
+int exclusive_scan_u64(uint64_t *v, uint64_t m, uint64_t *partial, hipStream_t s);
+uint64_t scan_partials_for(uint64_t m);
 int range_lookup(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
                  uint64_t capacity, uint64_t *total, hipStream_t s);
 
 // ---- learned.hip ------------------------------------------------------------
 int learn(idx_index *h, uint32_t leaves, uint32_t epochs, uint32_t feature, hipStream_t s);
+// learn_batch.hip: models of many indexes trained by one launch sequence.
+int learn_batch(idx_index *const *hs, uint32_t count, const uint32_t *leaves, uint32_t epochs, uint32_t feature,
+                hipStream_t s);
 void drop_model(idx_index *h, hipStream_t s);
 int learn_stats(const idx_index *h, idx_learn_stats *out);
 int learn_export(const idx_index *h, void *leaves_out, hipStream_t s);
 int learn_eval(idx_index *h, uint32_t feature, const float *root_ab, uint32_t leaves, const float *leaf_ab,
                double *root_acc, double *leaf_acc, hipStream_t s);
-int point_learned(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s);
+int point_learned(idx_index *h, const PointIO &io, hipStream_t s);
 // first-match ranks and counts of ranges through the model
 int range_count_learned(idx_index *h, const void *lo, const void *hi, uint64_t m, uint32_t *first, uint64_t *count,
                         hipStream_t s);

@@ -182,7 +182,7 @@ int export_layout(const idx_index *h, void *ko, uint32_t *ro, hipStream_t s) {
 // Number of pin-table entries for `levels` top levels.  BS and EBS use heap
 // numbering with an unused entry 0 (2^L entries); EKS uses slots
 // [0, k^L - 1).
-static uint32_t pin_entries(const idx_index *h, uint32_t levels) {
+uint32_t pin_entries_for(const idx_index *h, uint32_t levels) {
     if (levels == 0) return 0;
     if (h->layout == IDX_EKS) return (uint32_t)h->geo.start[levels];
     return 1u << levels;
@@ -202,7 +202,7 @@ uint32_t pin_levels_for(const idx_index *h, size_t bytes) {
         }
     }
     for (uint32_t l = 1; l <= maxl && l < 24; ++l)
-        if ((size_t)pin_entries(h, l) * kb <= bytes) best = l;
+        if ((size_t)pin_entries_for(h, l) * kb <= bytes) best = l;
     return best;
 }
 
@@ -215,7 +215,7 @@ int build_pin(idx_index *h, uint32_t levels, hipStream_t s) {
         h->pin_levels_built = 0;
     }
     if (levels == 0) return IDX_OK;
-    const uint32_t count = pin_entries(h, levels);
+    const uint32_t count = pin_entries_for(h, levels);
     h->pin = h->alloc.get((size_t)count * (h->u64 ? 8 : 4), s);
     if (!h->pin) return IDX_ERR_NOMEM;
     int rc;

@@ -1,0 +1,462 @@
+// Batched training of learned rank models: the models of many sorted-array
+// indexes are trained by one sequence of launches whose every kernel spans
+// all of them, so a thousand small indexes cost what one large one does
+// (same stages, same arithmetic and same Newton steps as the single-index
+// trainer in learned.hip; only the work split differs).
+//
+// The keys of every index are cut into units of UNIT consecutive keys (one
+// workgroup each; a unit never straddles two indexes).  Root sums for both
+// key features are accumulated in one pass; the feature with the lower loss
+// is picked on the device, so the whole sequence synchronises the host once,
+// at the end, to read back the roots and statistics.
+#include <climits>
+
+#include <new>
+#include <unordered_set>
+#include <vector>
+
+#include "internal.hpp"
+#include "learned_model.hpp"
+
+namespace idx {
+namespace {
+
+constexpr int BT = 256;                      // threads per workgroup
+constexpr int BCH = 32;                      // consecutive keys per thread in the leaf passes
+constexpr uint64_t UNIT = (uint64_t)BT * BCH;  // keys per unit
+constexpr int NST = 4;                       // per-index stats: sum w*size, max w, leaf loss, root loss
+
+struct TDesc {
+    const void *keys;
+    uint64_t n;
+    LeafRec *leaves;    // the index's model table
+    uint64_t leaf_off;  // its first leaf in the accumulator arrays
+    uint32_t L;
+    uint32_t pad;
+};
+
+struct Unit {
+    uint64_t begin, end;  // key range of one index
+    uint32_t index;
+    uint32_t pad;
+};
+
+template <typename K>
+__global__ __launch_bounds__(BT) void k_bt_root_accum(const Unit *__restrict__ units, const TDesc *__restrict__ d,
+                                                      const RootRec *__restrict__ roots2, uint32_t fmask,
+                                                      double *__restrict__ acc) {
+    __shared__ double s[BT / kWave][2 * NACC];
+    const Unit u = units[blockIdx.x];
+    const TDesc D = d[u.index];
+    const K *keys = (const K *)D.keys;
+    const RootRec R0 = roots2[2 * u.index], R1 = roots2[2 * u.index + 1];
+    const double scale = (double)D.L / (double)D.n;
+    double a[2 * NACC];
+#pragma unroll
+    for (int j = 0; j < 2 * NACC; ++j) a[j] = 0.0;
+    for (uint64_t i = u.begin + threadIdx.x; i < u.end; i += BT) {
+        const uint64_t key = (uint64_t)keys[i];
+        const float t = (float)((double)i * scale);
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            if (!(fmask & (1u << f))) continue;
+            const RootRec &R = f ? R1 : R0;
+            const float x = key_feature(key, R.mode);
+            const float r = __fsub_rn(__fadd_rn(__fmul_rn(R.a1, x), R.a0), t);
+            double *b = a + f * NACC;
+            b[0] += 1.0;
+            b[1] += x;
+            b[2] += (double)x * x;
+            b[3] += r;
+            b[4] += (double)r * x;
+            b[5] += (double)r * r;
+        }
+    }
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < 2 * NACC; ++j) {
+        const double v = wave_sum(a[j]);
+        if (lane == 0) s[wave][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * NACC && (fmask & (1u << (threadIdx.x / NACC)))) {
+        double v = 0;
+        for (int w = 0; w < BT / kWave; ++w) v += s[w][threadIdx.x];
+        atomicAdd(&acc[(uint64_t)u.index * 2 * NACC + threadIdx.x], v);
+    }
+}
+
+__global__ void k_bt_root_update(RootRec *__restrict__ roots2, const double *__restrict__ acc, uint32_t count,
+                                 uint32_t fmask) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * count || !(fmask & (1u << (t & 1)))) return;
+    RootRec R = roots2[t];
+    newton_linear(acc + (uint64_t)t * NACC, R.a0, R.a1);
+    roots2[t].a0 = R.a0;
+    roots2[t].a1 = R.a1;
+}
+
+// Lower final loss wins; LINEAR on a tie.
+__global__ void k_bt_root_pick(const RootRec *__restrict__ roots2, const double *__restrict__ acc, uint32_t count,
+                               uint32_t fmask, RootRec *__restrict__ best, double *__restrict__ stats) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    uint32_t f = (fmask & 1u) ? 0u : 1u;
+    if (fmask == 3u && acc[((uint64_t)2 * i + 1) * NACC + 5] < acc[(uint64_t)2 * i * NACC + 5]) f = 1u;
+    best[i] = roots2[2 * i + f];
+    stats[(uint64_t)i * NST + 3] = acc[((uint64_t)2 * i + f) * NACC + 5];
+}
+
+__global__ void k_bt_zero(double *p, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ void k_bt_zero_u32(uint32_t *p, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// This thread's BCH-key chunk of the unit.
+__device__ __forceinline__ bool chunk_of(const Unit &u, uint64_t &b, uint64_t &e) {
+    b = u.begin + (uint64_t)threadIdx.x * BCH;
+    e = b + BCH < u.end ? b + BCH : u.end;
+    return b < u.end;
+}
+
+template <typename K>
+__global__ __launch_bounds__(BT) void k_bt_leaf_count(const Unit *__restrict__ units, const TDesc *__restrict__ d,
+                                                      const RootRec *__restrict__ best, uint32_t *__restrict__ cnt) {
+    const Unit u = units[blockIdx.x];
+    uint64_t b, e;
+    if (!chunk_of(u, b, e)) return;
+    const TDesc D = d[u.index];
+    const K *keys = (const K *)D.keys;
+    const RootRec R = best[u.index];
+    uint32_t *c = cnt + D.leaf_off;
+    uint32_t cur = leaf_of(R, keys[b]), run = 0;
+    for (uint64_t i = b; i < e; ++i) {
+        const uint32_t l = leaf_of(R, keys[i]);
+        if (l != cur) {
+            atomicAdd(&c[cur], run);
+            cur = l;
+            run = 0;
+        }
+        ++run;
+    }
+    atomicAdd(&c[cur], run);
+}
+
+// One workgroup per index: leaf bases (exclusive scan of the counts), sizes,
+// first keys; parameters start at zero.
+template <typename K>
+__global__ __launch_bounds__(1024) void k_bt_leaf_layout(const TDesc *__restrict__ d, const uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t s_tot[1024 / kWave];
+    __shared__ uint32_t s_run;
+    const TDesc D = d[blockIdx.x];
+    const K *keys = (const K *)D.keys;
+    const uint32_t *c = cnt + D.leaf_off;
+    if (threadIdx.x == 0) s_run = 0;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    for (uint32_t c0 = 0; c0 < D.L; c0 += 1024) {
+        const uint32_t l = c0 + threadIdx.x;
+        const uint32_t v = l < D.L ? c[l] : 0;
+        uint32_t incl = v;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t x = __shfl_up(incl, off, kWave);
+            if (lane >= (uint32_t)off) incl += x;
+        }
+        if (lane == kWave - 1) s_tot[wave] = incl;
+        __syncthreads();
+        uint32_t before = s_run;
+        for (uint32_t w = 0; w < wave; ++w) before += s_tot[w];
+        if (l < D.L) {
+            LeafRec r{};
+            r.base = before + incl - v;
+            r.size = v;
+            r.kmin = v ? (uint64_t)keys[r.base] : 0ull;
+            r.b0 = 0.f;
+            r.b1 = 0.f;
+            r.elo = INT_MAX;
+            r.ehi = INT_MIN;
+            D.leaves[l] = r;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) {
+            uint32_t tot = 0;
+            for (int w = 0; w < 1024 / kWave; ++w) tot += s_tot[w];
+            s_run += tot;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename K>
+__global__ __launch_bounds__(BT) void k_bt_leaf_accum(const Unit *__restrict__ units, const TDesc *__restrict__ d,
+                                                      const RootRec *__restrict__ best, double *__restrict__ acc) {
+    const Unit u = units[blockIdx.x];
+    uint64_t b, e;
+    const bool active = chunk_of(u, b, e);
+    const TDesc D = d[u.index];
+    const K *keys = (const K *)D.keys;
+    const RootRec R = best[u.index];
+    double *A = acc + D.leaf_off * NACC;
+    auto add = [&](uint32_t l, double *v) {
+#pragma unroll
+        for (int j = 0; j < NACC; ++j) atomicAdd(&A[(uint64_t)l * NACC + j], v[j]);
+    };
+    double a[NACC] = {0, 0, 0, 0, 0, 0};
+    uint32_t cur = active ? leaf_of(R, keys[b]) : 0;
+    LeafRec L = D.leaves[cur];
+    for (uint64_t i = b; active && i < e; ++i) {
+        const uint64_t key = (uint64_t)keys[i];
+        const uint32_t l = leaf_of(R, key);
+        if (l != cur) {
+            add(cur, a);
+#pragma unroll
+            for (int j = 0; j < NACC; ++j) a[j] = 0;
+            cur = l;
+            L = D.leaves[cur];
+        }
+        const float dd = local_feature(L, key);
+        const float y = (float)(uint32_t)(i - L.base);
+        const float r = __fsub_rn(__fadd_rn(__fmul_rn(L.b1, dd), L.b0), y);
+        a[0] += 1.0;
+        a[1] += dd;
+        a[2] += (double)dd * dd;
+        a[3] += r;
+        a[4] += (double)r * dd;
+        a[5] += (double)r * r;
+    }
+    flush<NACC>(cur, a, active, add);
+}
+
+// Index owning global leaf g: the last i with d[i].leaf_off <= g.
+__device__ __forceinline__ uint32_t leaf_owner(const TDesc *__restrict__ d, uint32_t count, uint64_t g) {
+    uint32_t lo = 0, hi = count;
+    while (hi - lo > 1) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if (d[mid].leaf_off <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_bt_leaf_update(const TDesc *__restrict__ d, uint32_t count, uint64_t total,
+                                 const double *__restrict__ acc) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const TDesc D = d[leaf_owner(d, count, g)];
+    LeafRec *r = &D.leaves[g - D.leaf_off];
+    float b0 = r->b0, b1 = r->b1;
+    newton_linear(acc + g * NACC, b0, b1);
+    r->b0 = b0;
+    r->b1 = b1;
+}
+
+template <typename K>
+__global__ __launch_bounds__(BT) void k_bt_leaf_errors(const Unit *__restrict__ units, const TDesc *__restrict__ d,
+                                                       const RootRec *__restrict__ best) {
+    const Unit u = units[blockIdx.x];
+    uint64_t b, e;
+    const bool active = chunk_of(u, b, e);
+    const TDesc D = d[u.index];
+    const K *keys = (const K *)D.keys;
+    const RootRec R = best[u.index];
+    int64_t mm[2] = {INT_MAX, INT_MIN};
+    uint32_t cur = active ? leaf_of(R, keys[b]) : 0;
+    LeafRec L = D.leaves[cur];
+    auto add = [&](uint32_t l) {
+        atomicMin(&D.leaves[l].elo, (int32_t)mm[0]);
+        atomicMax(&D.leaves[l].ehi, (int32_t)mm[1]);
+    };
+    for (uint64_t i = b; active && i < e; ++i) {
+        const uint64_t key = (uint64_t)keys[i];
+        const uint32_t l = leaf_of(R, key);
+        if (l != cur) {
+            add(cur);
+            mm[0] = INT_MAX;
+            mm[1] = INT_MIN;
+            cur = l;
+            L = D.leaves[cur];
+        }
+        const int64_t err = (int64_t)(i - L.base) - (int64_t)pred_local(L, key);
+        mm[0] = err < mm[0] ? err : mm[0];
+        mm[1] = err > mm[1] ? err : mm[1];
+    }
+    if (active) add(cur);
+}
+
+// Empty leaves get a zero window; per-index window statistics and leaf loss.
+__global__ __launch_bounds__(256) void k_bt_leaf_finish(const TDesc *__restrict__ d, uint32_t count, uint64_t total,
+                                                        const double *__restrict__ acc, double *__restrict__ stats) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const uint32_t i = leaf_owner(d, count, g);
+    const TDesc D = d[i];
+    LeafRec *r = &D.leaves[g - D.leaf_off];
+    const LeafRec v = *r;
+    double *st = stats + (uint64_t)i * NST;
+    if (v.size == 0 || v.elo > v.ehi) {
+        r->elo = 0;
+        r->ehi = -1;
+    } else {
+        const double w = (double)v.ehi - (double)v.elo + 2.0;  // window slots incl. one past
+        atomicAdd(&st[0], w * v.size);
+        unsigned long long *p = (unsigned long long *)&st[1];
+        unsigned long long old = *p;
+        while (__longlong_as_double(old) < w) {
+            const unsigned long long prev = atomicCAS(p, old, __double_as_longlong(w));
+            if (prev == old) break;
+            old = prev;
+        }
+    }
+    atomicAdd(&st[2], acc[g * NACC + 5]);
+}
+
+uint32_t blocks_for(uint64_t threads, uint32_t block) {
+    uint64_t b = (threads + block - 1) / block;
+    if (b == 0) b = 1;
+    if (b > 0x7FFFFFFFull) b = 0x7FFFFFFFull;
+    return (uint32_t)b;
+}
+
+template <typename K>
+int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, uint32_t epochs, uint32_t feature,
+                  hipStream_t s) {
+    std::vector<TDesc> desc(count);
+    std::vector<Unit> units;
+    uint64_t total_leaves = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        const idx_index *h = hs[i];
+        desc[i] = TDesc{h->keys, h->n, h->learned->leaves, total_leaves, leaves[i], 0};
+        total_leaves += leaves[i];
+        for (uint64_t b = 0; b < h->n; b += UNIT) units.push_back(Unit{b, b + UNIT < h->n ? b + UNIT : h->n, i, 0});
+    }
+    if (units.size() > 0x7FFFFFFFull) return IDX_ERR_ARG;
+    const uint32_t nunits = (uint32_t)units.size();
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t b_desc = up(sizeof(TDesc) * count), b_units = up(sizeof(Unit) * nunits);
+    const size_t b_roots2 = up(sizeof(RootRec) * 2 * count), b_best = up(sizeof(RootRec) * count);
+    const size_t b_racc = up(sizeof(double) * 2 * NACC * count), b_stats = up(sizeof(double) * NST * count);
+    const size_t b_lacc = up(sizeof(double) * NACC * total_leaves), b_cnt = up(sizeof(uint32_t) * total_leaves);
+    const Alloc &A = hs[0]->alloc;
+    char *tmp = (char *)A.get(b_desc + b_units + b_roots2 + b_best + b_racc + b_stats + b_lacc + b_cnt, s);
+    if (!tmp) return IDX_ERR_NOMEM;
+    TDesc *d_desc = (TDesc *)tmp;
+    Unit *d_units = (Unit *)(tmp + b_desc);
+    RootRec *d_roots2 = (RootRec *)(tmp + b_desc + b_units);
+    RootRec *d_best = (RootRec *)((char *)d_roots2 + b_roots2);
+    double *d_racc = (double *)((char *)d_best + b_best);
+    double *d_stats = (double *)((char *)d_racc + b_racc);
+    double *d_lacc = (double *)((char *)d_stats + b_stats);
+    uint32_t *d_cnt = (uint32_t *)((char *)d_lacc + b_lacc);
+    std::vector<RootRec> roots2(2 * count);
+    for (uint32_t i = 0; i < count; ++i) {
+        roots2[2 * i] = RootRec{0.f, 0.f, IDX_FEATURE_LINEAR, leaves[i]};
+        roots2[2 * i + 1] = RootRec{0.f, 0.f, IDX_FEATURE_LOG, leaves[i]};
+    }
+    const uint32_t fmask = feature == IDX_FEATURE_AUTO ? 3u : (feature == IDX_FEATURE_LINEAR ? 1u : 2u);
+    std::vector<RootRec> best(count);
+    std::vector<double> stats((size_t)NST * count);
+    int rc = IDX_OK;
+    do {
+        if (hipMemcpyAsync(d_desc, desc.data(), sizeof(TDesc) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(d_units, units.data(), sizeof(Unit) * nunits, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(d_roots2, roots2.data(), sizeof(RootRec) * 2 * count, hipMemcpyHostToDevice, s) !=
+                hipSuccess) {
+            rc = IDX_ERR_HIP;
+            break;
+        }
+        // ---- stage 1: roots of both features, epochs Newton steps, final loss
+        for (uint32_t ep = 0; ep <= epochs; ++ep) {
+            hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for(2ull * NACC * count, 256)), dim3(256), 0, s, d_racc,
+                               (uint64_t)2 * NACC * count);
+            hipLaunchKernelGGL((k_bt_root_accum<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_roots2, fmask,
+                               d_racc);
+            if (ep < epochs)
+                hipLaunchKernelGGL(k_bt_root_update, dim3(blocks_for(2ull * count, 256)), dim3(256), 0, s, d_roots2,
+                                   d_racc, count, fmask);
+        }
+        hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for((uint64_t)NST * count, 256)), dim3(256), 0, s, d_stats,
+                           (uint64_t)NST * count);
+        hipLaunchKernelGGL(k_bt_root_pick, dim3(blocks_for(count, 256)), dim3(256), 0, s, d_roots2, d_racc, count,
+                           fmask, d_best, d_stats);
+        // ---- stage 2: leaves
+        hipLaunchKernelGGL(k_bt_zero_u32, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, d_cnt, total_leaves);
+        hipLaunchKernelGGL((k_bt_leaf_count<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_best, d_cnt);
+        hipLaunchKernelGGL((k_bt_leaf_layout<K>), dim3(count), dim3(1024), 0, s, d_desc, d_cnt);
+        for (uint32_t ep = 0; ep <= epochs; ++ep) {
+            hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for((uint64_t)NACC * total_leaves, 256)), dim3(256), 0, s,
+                               d_lacc, (uint64_t)NACC * total_leaves);
+            hipLaunchKernelGGL((k_bt_leaf_accum<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_best, d_lacc);
+            if (ep < epochs)
+                hipLaunchKernelGGL(k_bt_leaf_update, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, d_desc,
+                                   count, total_leaves, d_lacc);
+        }
+        hipLaunchKernelGGL((k_bt_leaf_errors<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_best);
+        hipLaunchKernelGGL(k_bt_leaf_finish, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, d_desc, count,
+                           total_leaves, d_lacc, d_stats);
+        if (hipGetLastError() != hipSuccess) {
+            rc = IDX_ERR_HIP;
+            break;
+        }
+        if (hipMemcpyAsync(best.data(), d_best, sizeof(RootRec) * count, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(stats.data(), d_stats, sizeof(double) * NST * count, hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = IDX_ERR_HIP;
+            break;
+        }
+    } while (0);
+    A.put(tmp, s);
+    if (rc != IDX_OK) return rc;
+    for (uint32_t i = 0; i < count; ++i) {
+        LearnedModel *M = hs[i]->learned;
+        M->root = best[i];
+        M->stats.leaves = leaves[i];
+        M->stats.epochs = epochs;
+        M->stats.feature = best[i].mode;
+        M->stats.root_a0 = best[i].a0;
+        M->stats.root_a1 = best[i].a1;
+        M->stats.root_loss = stats[(size_t)i * NST + 3];
+        M->stats.leaf_loss = stats[(size_t)i * NST + 2];
+        M->stats.mean_window = stats[(size_t)i * NST + 0] / (double)hs[i]->n;
+        M->stats.max_window = stats[(size_t)i * NST + 1];
+    }
+    return IDX_OK;
+}
+
+}  // namespace
+
+int learn_batch(idx_index *const *hs, uint32_t count, const uint32_t *leaves, uint32_t epochs, uint32_t feature,
+                hipStream_t s) {
+    if (!hs || !leaves || count == 0 || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_LOG) return IDX_ERR_ARG;
+    std::unordered_set<const idx_index *> seen;
+    for (uint32_t i = 0; i < count; ++i) {
+        const idx_index *h = hs[i];
+        if (!h || h->layout != IDX_BS || h->aos || h->n == 0 || h->u64 != hs[0]->u64) return IDX_ERR_ARG;
+        if (leaves[i] == 0 || leaves[i] > (1u << 22)) return IDX_ERR_ARG;
+        if (!seen.insert(h).second) return IDX_ERR_ARG;  // each index once
+    }
+    for (uint32_t i = 0; i < count; ++i) {
+        idx_index *h = hs[i];
+        drop_model(h, s);
+        LearnedModel *M = new (std::nothrow) LearnedModel();
+        if (M) M->leaves = (LeafRec *)h->alloc.get((size_t)leaves[i] * sizeof(LeafRec), s);
+        if (!M || !M->leaves) {
+            delete M;
+            for (uint32_t j = 0; j < i; ++j) drop_model(hs[j], s);
+            return IDX_ERR_NOMEM;
+        }
+        h->learned = M;
+    }
+    const int rc = hs[0]->u64 ? train_batch_t<uint64_t>(hs, count, leaves, epochs, feature, s)
+                              : train_batch_t<uint32_t>(hs, count, leaves, epochs, feature, s);
+    if (rc != IDX_OK)
+        for (uint32_t i = 0; i < count; ++i) drop_model(hs[i], s);
+    return rc;
+}
+
+}  // namespace idx

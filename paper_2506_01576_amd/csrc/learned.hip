@@ -28,6 +28,7 @@
 
 #include "internal.hpp"
 #include "learned_model.hpp"
+#include "qio.hpp"
 
 namespace idx {
 
@@ -35,15 +36,6 @@ namespace {
 
 constexpr int LT = 256;  // threads per block in the training kernels
 constexpr int CHUNK = 32;  // consecutive keys per thread in the per-leaf passes
-
-// Accumulator layout per model: N, Sx, Sxx, Sr, Srx, Srr (FP64).
-constexpr int NACC = 6;
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-    return v;
-}
 
 template <typename K>
 __global__ __launch_bounds__(LT) void k_root_accum(const K *__restrict__ keys, uint64_t n, const RootRec *Rp,
@@ -75,38 +67,6 @@ __global__ __launch_bounds__(LT) void k_root_accum(const K *__restrict__ keys, u
         for (int w = 0; w < LT / kWave; ++w) v += s[w][threadIdx.x];
         atomicAdd(&acc[threadIdx.x], v);
     }
-}
-
-// Newton step on a linear model from its accumulated sums; a non-negative
-// slope is enforced (the fitted slope of rank against a non-decreasing
-// feature is non-negative up to rounding).
-__device__ __forceinline__ void newton_linear(const double *a, float &c0, float &c1) {
-    const double N = a[0], Sx = a[1], Sxx = a[2], Sr = a[3], Srx = a[4];
-    if (N < 1.0) {
-        c0 = 0.f;
-        c1 = 0.f;
-        return;
-    }
-    const double det = Sxx * N - Sx * Sx;
-    double n1 = c1, n0 = c0;
-    if (N >= 2.0 && det > 1e-12 * Sxx * N && det > 0.0) {
-        // [d1, d0] = H^-1 g with g = (Srx, Sr), H = [[Sxx, Sx], [Sx, N]] (the 2s cancel)
-        const double d1 = (N * Srx - Sx * Sr) / det;
-        const double d0 = (Sxx * Sr - Sx * Srx) / det;
-        n1 -= d1;
-        n0 -= d0;
-    } else {
-        n1 = 0.0;
-        n0 = (double)c0 + (double)c1 * (Sx / N) - Sr / N;  // the mean target
-    }
-    if (n1 < 0.0) {
-        // keep the model monotone: best constant
-        const double mean_t = (double)c0 + (double)c1 * (Sx / N) - Sr / N;
-        n1 = 0.0;
-        n0 = mean_t;
-    }
-    c1 = (float)n1;
-    c0 = (float)n0;
 }
 
 __global__ void k_root_update(RootRec *R, const double *acc) {
@@ -186,22 +146,6 @@ __global__ __launch_bounds__(1024) void k_leaf_layout(const K *__restrict__ keys
             s_run += tot;
         }
         __syncthreads();
-    }
-}
-
-// Flush a thread's running sums for leaf `l`: when the whole wave holds the
-// same leaf, reduce across the wave first and add once.
-template <int NV, typename T, typename F>
-__device__ __forceinline__ void flush(uint32_t l, T *v, bool active, F &&add) {
-    const uint64_t act = __ballot(active);
-    const uint32_t lead = __shfl((int)l, __builtin_ctzll(act ? act : 1ull), kWave);
-    const bool uniform = act != 0 && __ballot(active && l == lead) == act && act == __ballot(true);
-    if (uniform) {
-#pragma unroll
-        for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
-        if ((threadIdx.x & (kWave - 1)) == 0) add(l, v);
-    } else if (active) {
-        add(l, v);
     }
 }
 
@@ -474,25 +418,26 @@ int learn_export(const idx_index *h, void *leaves_out, hipStream_t s) {
 
 namespace {
 
-template <typename K, int R>
+template <typename K, int R, bool SORT>
 __global__ __launch_bounds__(1024) void k_point_learned(const K *__restrict__ keys, const uint32_t *__restrict__ rows,
                                                         uint64_t n, RootRec root,
-                                                        const LeafRec *__restrict__ leaves, const K *__restrict__ q,
-                                                        uint64_t m, uint32_t *__restrict__ out) {
+                                                        const LeafRec *__restrict__ leaves, QueryIO<K> io) {
+    extern __shared__ __align__(16) char smem[];
     const uint64_t tile = (uint64_t)blockDim.x * R;
-    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < m; t0 += (uint64_t)gridDim.x * tile) {
+    for (uint64_t it = blockIdx.x; it < io.iters; it += gridDim.x) {
+        const uint64_t tl = tile_of(it, io.ntiles, io.xcd);
+        if (tl >= io.ntiles) continue;
+        const uint64_t t0 = tl * tile;
         K x[R];
-        uint64_t b[R], len[R];
+        uint32_t src[R];
+        uint32_t b[R], len[R];  // ranks: n < 2^32
+        tile_load<K, R, SORT>(io, smem, t0, x, src);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
-            x[r] = qi < m ? q[qi] : K(0);
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            learned_window(root, leaves, (uint64_t)x[r], b[r], len[r]);
-            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
-            if (qi >= m) len[r] = 0;
+            uint64_t w0, wl;
+            learned_window(root, leaves, (uint64_t)x[r], w0, wl);
+            b[r] = (uint32_t)w0;
+            len[r] = tile_valid(io.m, t0, src_of<R, SORT>(src, r)) ? (uint32_t)wl : 0u;
         }
         // The lower bound lies in [b, b + len].  Narrow wide windows with
         // binary-search steps, then read the last <= 15 keys and the key after
@@ -503,7 +448,7 @@ __global__ __launch_bounds__(1024) void k_point_learned(const K *__restrict__ ke
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 if (len[r] > 15) {
-                    const uint64_t half = len[r] >> 1;
+                    const uint32_t half = len[r] >> 1;
                     b[r] = keys[b[r] + half - 1] < x[r] ? b[r] + half : b[r];
                     len[r] -= half;
                     more |= len[r] > 15;
@@ -512,33 +457,51 @@ __global__ __launch_bounds__(1024) void k_point_learned(const K *__restrict__ ke
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
-            if (qi >= m) continue;
             uint32_t res = kMiss;
-            const uint64_t sl = (len[r] + 1) < (n - b[r]) ? (len[r] + 1) : (n - b[r]);
-            bool eq;
-            const uint32_t c = count_below<K, 16>(keys, b[r], (uint32_t)sl, x[r], eq);
-            if (eq) res = rows[b[r] + c];
-            out[qi] = res;
+            if (tile_valid(io.m, t0, src_of<R, SORT>(src, r))) {
+                const uint64_t sl = ((uint64_t)len[r] + 1) < (n - b[r]) ? ((uint64_t)len[r] + 1) : (n - b[r]);
+                bool eq;
+                const uint32_t c = count_below<K, 16>(keys, b[r], (uint32_t)sl, x[r], eq);
+                if (eq) res = rows[(uint64_t)b[r] + c];
+            }
+            tile_put<K, SORT>(io, smem, t0, src_of<R, SORT>(src, r), res);
         }
+        tile_flush<K, R, SORT>(io, smem, t0);
     }
 }
 
 }  // namespace
 
-int point_learned(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
+int point_learned(idx_index *h, const PointIO &pio, hipStream_t s) {
     const LearnedModel *M = h->learned;
     const uint32_t block = h->params.block;
     const uint32_t R = h->params.per_lane;
-    uint64_t grid = (m + (uint64_t)block * R - 1) / ((uint64_t)block * R);
-    if (h->params.persistent) {
-        const uint64_t cap = (uint64_t)h->cu_count * h->params.persistent;
-        if (grid > cap) grid = cap;
-    }
-    const uint32_t g = (uint32_t)(grid ? (grid > 0x7FFFFFFFull ? 0x7FFFFFFFull : grid) : 1);
+    const uint64_t tile = (uint64_t)block * R;
 #define IDX_LEARNED_LAUNCH(KT, RR)                                                                          \
-    hipLaunchKernelGGL((k_point_learned<KT, RR>), dim3(g), dim3(block), 0, s, (const KT *)h->keys, h->rowids, \
-                       h->n, M->root, M->leaves, (const KT *)q, m, out)
+    do {                                                                                                    \
+        QueryIO<KT> io{};                                                                                   \
+        io.q = (const KT *)pio.q;                                                                           \
+        io.out = pio.out;                                                                                   \
+        io.m = pio.m;                                                                                       \
+        io.local_sort = pio.local_sort ? 1u : 0u;                                                           \
+        io.xcd = pio.xcd ? 1u : 0u;                                                                         \
+        io.sort_off = 0;                                                                                    \
+        set_tiles(io, tile);                                                                                \
+        uint64_t grid = io.iters;                                                                           \
+        if (h->params.persistent) {                                                                         \
+            uint64_t cap = (uint64_t)h->cu_count * h->params.persistent;                                    \
+            if (io.xcd && cap >= kXcds) cap -= cap % kXcds;                                                 \
+            if (grid > cap) grid = cap;                                                                     \
+        }                                                                                                   \
+        const uint32_t g = (uint32_t)(grid ? (grid > 0x7FFFFFFFull ? 0x7FFFFFFFull : grid) : 1);            \
+        const size_t smem = io.local_sort ? sort_lds_bytes((uint32_t)tile, sizeof(KT)) : 0;                 \
+        if (io.local_sort)                                                                                  \
+            hipLaunchKernelGGL((k_point_learned<KT, RR, true>), dim3(g), dim3(block), smem, s,              \
+                               (const KT *)h->keys, h->rowids, h->n, M->root, M->leaves, io);               \
+        else                                                                                                \
+            hipLaunchKernelGGL((k_point_learned<KT, RR, false>), dim3(g), dim3(block), smem, s,             \
+                               (const KT *)h->keys, h->rowids, h->n, M->root, M->leaves, io);               \
+    } while (0)
     if (h->u64) {
         switch (R) {
             case 1: IDX_LEARNED_LAUNCH(uint64_t, 1); break;

@@ -90,4 +90,63 @@ __device__ __forceinline__ uint64_t learned_lower_rank(const K *__restrict__ key
     return b + count_below<K, 16>(keys, b, (uint32_t)len, x, eq);
 }
 
+// ---- training helpers shared by the single-index and batched trainers
+
+// Accumulator layout per linear model: N, Sx, Sxx, Sr, Srx, Srr (FP64).
+constexpr int NACC = 6;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Newton step on a linear model from its accumulated sums; a non-negative
+// slope is enforced (the fitted slope of rank against a non-decreasing
+// feature is non-negative up to rounding).
+__device__ __forceinline__ void newton_linear(const double *a, float &c0, float &c1) {
+    const double N = a[0], Sx = a[1], Sxx = a[2], Sr = a[3], Srx = a[4];
+    if (N < 1.0) {
+        c0 = 0.f;
+        c1 = 0.f;
+        return;
+    }
+    const double det = Sxx * N - Sx * Sx;
+    double n1 = c1, n0 = c0;
+    if (N >= 2.0 && det > 1e-12 * Sxx * N && det > 0.0) {
+        // [d1, d0] = H^-1 g with g = (Srx, Sr), H = [[Sxx, Sx], [Sx, N]] (the 2s cancel)
+        const double d1 = (N * Srx - Sx * Sr) / det;
+        const double d0 = (Sxx * Sr - Sx * Srx) / det;
+        n1 -= d1;
+        n0 -= d0;
+    } else {
+        n1 = 0.0;
+        n0 = (double)c0 + (double)c1 * (Sx / N) - Sr / N;  // the mean target
+    }
+    if (n1 < 0.0) {
+        // keep the model monotone: best constant
+        const double mean_t = (double)c0 + (double)c1 * (Sx / N) - Sr / N;
+        n1 = 0.0;
+        n0 = mean_t;
+    }
+    c1 = (float)n1;
+    c0 = (float)n0;
+}
+
+// Flush a thread's running sums for leaf `l`: when the whole wave holds the
+// same leaf, reduce across the wave first and add once.
+template <int NV, typename T, typename F>
+__device__ __forceinline__ void flush(uint32_t l, T *v, bool active, F &&add) {
+    const uint64_t act = __ballot(active);
+    const uint32_t lead = __shfl((int)l, __builtin_ctzll(act ? act : 1ull), kWave);
+    const bool uniform = act != 0 && __ballot(active && l == lead) == act && act == __ballot(true);
+    if (uniform) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
+        if ((threadIdx.x & (kWave - 1)) == 0) add(l, v);
+    } else if (active) {
+        add(l, v);
+    }
+}
+
 }  // namespace idx

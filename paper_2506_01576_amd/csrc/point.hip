@@ -20,10 +20,13 @@
 // workgroup; with a persistent grid (Section 7.2, limited concurrency) the
 // copy is amortised over many tiles.  The lower bound is tracked during the
 // descent (deepest candidate), so only the row ID needs one more load.
+// Queries enter and answers leave through qio.hpp (plain, locally sorted per
+// tile, or a batch partitioned by rank bucket with XCD-contiguous tiles).
 #include <type_traits>
 
 #include "internal.hpp"
 #include "access.hpp"
+#include "qio.hpp"
 #include "search.hpp"
 
 namespace idx {
@@ -33,9 +36,7 @@ template <typename K, bool AOS>
 struct PointArgs {
     Load<K, AOS> L;
     Geo G;
-    const K *__restrict__ q;
-    uint64_t m;
-    uint32_t *__restrict__ out;
+    QueryIO<K> io;
     const K *__restrict__ pin;
     uint32_t pin_entries;
     uint32_t pin_levels;
@@ -52,22 +53,23 @@ __device__ __forceinline__ void load_pin(K *s_pin, const K *__restrict__ pin, ui
 
 // ----------------------------------------------------------------------- BS
 
-template <typename K, bool AOS, int R>
+template <typename K, bool AOS, int R, bool SORT>
 __global__ __launch_bounds__(1024) void k_point_bs(PointArgs<K, AOS> a) {
     extern __shared__ __align__(16) char smem[];
     K *s_pin = (K *)smem;
     if (a.pin_levels) load_pin(s_pin, a.pin, a.pin_entries);
     const uint64_t n = a.G.n;
     const uint64_t tile = (uint64_t)blockDim.x * R;
-    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < a.m; t0 += (uint64_t)gridDim.x * tile) {
+    for (uint64_t it = blockIdx.x; it < a.io.iters; it += gridDim.x) {
+        const uint64_t tl = tile_of(it, a.io.ntiles, a.io.xcd);
+        if (tl >= a.io.ntiles) continue;
+        const uint64_t t0 = tl * tile;
         K x[R];
+        uint32_t src[R];
+        tile_load<K, R, SORT>(a.io, smem, t0, x, src);
         uint64_t base[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
-            x[r] = qi < a.m ? a.q[qi] : K(0);
-            base[r] = 0;
-        }
+        for (int r = 0; r < R; ++r) base[r] = 0;
         uint64_t len = n;
         if (a.pin_levels) {
             uint32_t v[R];
@@ -93,43 +95,33 @@ __global__ __launch_bounds__(1024) void k_point_bs(PointArgs<K, AOS> a) {
             for (int r = 0; r < R; ++r) base[r] = (a.L.key(base[r] + half) < x[r]) ? base[r] + half : base[r];
             len -= half;
         }
-        if constexpr (!AOS) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
-                if (qi >= a.m) continue;
-                uint32_t res = kMiss;
-                if (n > 0) {
+        for (int r = 0; r < R; ++r) {
+            uint32_t res = kMiss;
+            if (n > 0 && tile_valid(a.io.m, t0, src_of<R, SORT>(src, r))) {
+                if constexpr (!AOS) {
                     const uint64_t sl = (len + 1) < (n - base[r]) ? (len + 1) : (n - base[r]);
                     bool eq;
                     const uint32_t c = count_below<K, 16>(a.L.k, base[r], (uint32_t)sl, x[r], eq);
                     if (eq) res = a.L.row(base[r] + c);
-                }
-                a.out[qi] = res;
-            }
-            continue;
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
-            if (qi >= a.m) continue;
-            uint32_t res = kMiss;
-            if (n > 0) {
-                const K kb = a.L.key(base[r]);
-                const uint64_t pos = base[r] + (kb < x[r] ? 1 : 0);
-                if (pos < n) {
-                    const K kp = kb < x[r] ? a.L.key(pos) : kb;
-                    if (kp == x[r]) res = a.L.row(pos);
+                } else {
+                    const K kb = a.L.key(base[r]);
+                    const uint64_t pos = base[r] + (kb < x[r] ? 1 : 0);
+                    if (pos < n) {
+                        const K kp = kb < x[r] ? a.L.key(pos) : kb;
+                        if (kp == x[r]) res = a.L.row(pos);
+                    }
                 }
             }
-            a.out[qi] = res;
+            tile_put<K, SORT>(a.io, smem, t0, src_of<R, SORT>(src, r), res);
         }
+        tile_flush<K, R, SORT>(a.io, smem, t0);
     }
 }
 
 // ---------------------------------------------------------------------- EBS
 
-template <typename K, bool AOS, int R>
+template <typename K, bool AOS, int R, bool SORT>
 __global__ __launch_bounds__(1024) void k_point_ebs(PointArgs<K, AOS> a) {
     extern __shared__ __align__(16) char smem[];
     K *s_pin = (K *)smem;
@@ -137,13 +129,16 @@ __global__ __launch_bounds__(1024) void k_point_ebs(PointArgs<K, AOS> a) {
     const uint64_t n = a.G.n;
     const uint32_t m_full = a.G.m;
     const uint64_t tile = (uint64_t)blockDim.x * R;
-    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < a.m; t0 += (uint64_t)gridDim.x * tile) {
+    for (uint64_t it = blockIdx.x; it < a.io.iters; it += gridDim.x) {
+        const uint64_t tl = tile_of(it, a.io.ntiles, a.io.xcd);
+        if (tl >= a.io.ntiles) continue;
+        const uint64_t t0 = tl * tile;
         K x[R], ck[R];
+        uint32_t src[R];
         uint64_t i[R];
+        tile_load<K, R, SORT>(a.io, smem, t0, x, src);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
-            x[r] = qi < a.m ? a.q[qi] : K(0);
             i[r] = 1;
             ck[r] = key_max<K>();
         }
@@ -177,11 +172,11 @@ __global__ __launch_bounds__(1024) void k_point_ebs(PointArgs<K, AOS> a) {
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
-            if (qi >= a.m) continue;
             const uint64_t j = i[r] >> (__builtin_ctzll(~i[r]) + 1);
-            a.out[qi] = (j != 0 && ck[r] == x[r]) ? a.L.row(j) : kMiss;
+            const uint32_t res = (tile_valid(a.io.m, t0, src_of<R, SORT>(src, r)) && j != 0 && ck[r] == x[r]) ? a.L.row(j) : kMiss;
+            tile_put<K, SORT>(a.io, smem, t0, src_of<R, SORT>(src, r), res);
         }
+        tile_flush<K, R, SORT>(a.io, smem, t0);
     }
 }
 
@@ -206,7 +201,10 @@ __global__ __launch_bounds__(1024) void k_point_eks_group(PointArgs<K, AOS> a) {
     const uint32_t waves = blockDim.x / kWave;
     const uint32_t wave = threadIdx.x / kWave;
     const uint64_t tile = (uint64_t)waves * GPW * R;
-    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < a.m; t0 += (uint64_t)gridDim.x * tile) {
+    for (uint64_t it = blockIdx.x; it < a.io.iters; it += gridDim.x) {
+        const uint64_t tl = tile_of(it, a.io.ntiles, a.io.xcd);
+        if (tl >= a.io.ntiles) continue;
+        const uint64_t t0 = tl * tile;
         const uint64_t wbase = t0 + (uint64_t)wave * GPW * R;
         K x[R];
         uint64_t c[R], cand[R];
@@ -214,8 +212,8 @@ __global__ __launch_bounds__(1024) void k_point_eks_group(PointArgs<K, AOS> a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint64_t qi = wbase + (uint64_t)r * GPW + grp;
-            x[r] = qi < a.m ? a.q[qi] : K(0);
-            c[r] = qi < a.m ? 0 : ~0ull;  // node index; ~0 = finished
+            x[r] = qi < a.io.m ? a.io.q[qi] : K(0);
+            c[r] = qi < a.io.m ? 0 : ~0ull;  // node index; ~0 = finished
             cand[r] = 0;
             ceq[r] = false;
         }
@@ -247,7 +245,7 @@ __global__ __launch_bounds__(1024) void k_point_eks_group(PointArgs<K, AOS> a) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const uint64_t qi = wbase + (uint64_t)r * GPW + grp;
-                if (qi < a.m) a.out[qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
+                if (qi < a.io.m) a.io.out[qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
             }
         }
     }
@@ -278,7 +276,10 @@ __global__ __launch_bounds__(1024) void k_point_eks_vgroup(PointArgs<K, AOS> a) 
     const uint32_t waves = blockDim.x / kWave;
     const uint32_t wave = threadIdx.x / kWave;
     const uint64_t tile = (uint64_t)waves * GPW * R;
-    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < a.m; t0 += (uint64_t)gridDim.x * tile) {
+    for (uint64_t it = blockIdx.x; it < a.io.iters; it += gridDim.x) {
+        const uint64_t tl = tile_of(it, a.io.ntiles, a.io.xcd);
+        if (tl >= a.io.ntiles) continue;
+        const uint64_t t0 = tl * tile;
         const uint64_t wbase = t0 + (uint64_t)wave * GPW * R;
         K x[R];
         uint64_t c[R], cand[R];
@@ -286,8 +287,8 @@ __global__ __launch_bounds__(1024) void k_point_eks_vgroup(PointArgs<K, AOS> a) 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const uint64_t qi = wbase + (uint64_t)r * GPW + grp;
-            x[r] = qi < a.m ? a.q[qi] : K(0);
-            c[r] = qi < a.m ? 0 : ~0ull;
+            x[r] = qi < a.io.m ? a.io.q[qi] : K(0);
+            c[r] = qi < a.io.m ? 0 : ~0ull;
             cand[r] = 0;
             ceq[r] = false;
         }
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(1024) void k_point_eks_vgroup(PointArgs<K, AOS> a) 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const uint64_t qi = wbase + (uint64_t)r * GPW + grp;
-                if (qi < a.m) a.out[qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
+                if (qi < a.io.m) a.io.out[qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
             }
         }
     }
@@ -349,7 +350,7 @@ __global__ __launch_bounds__(1024) void k_point_eks_vgroup(PointArgs<K, AOS> a) 
 
 // One lane per lookup.  GMAX = pivots read per node (>= k-1); VEC = nodes are
 // exactly GMAX keys, 16-byte aligned, read with 16-byte loads (SoA only).
-template <typename K, bool AOS, int GMAX, bool VEC, int R>
+template <typename K, bool AOS, int GMAX, bool VEC, int R, bool SORT>
 __global__ __launch_bounds__(1024) void k_point_eks_single(PointArgs<K, AOS> a) {
     extern __shared__ __align__(16) char smem[];
     K *s_pin = (K *)smem;
@@ -358,15 +359,18 @@ __global__ __launch_bounds__(1024) void k_point_eks_single(PointArgs<K, AOS> a) 
     const uint32_t g = a.G.g;
     const uint32_t kf = a.G.k;
     const uint64_t tile = (uint64_t)blockDim.x * R;
-    for (uint64_t t0 = (uint64_t)blockIdx.x * tile; t0 < a.m; t0 += (uint64_t)gridDim.x * tile) {
+    for (uint64_t it = blockIdx.x; it < a.io.iters; it += gridDim.x) {
+        const uint64_t tl = tile_of(it, a.io.ntiles, a.io.xcd);
+        if (tl >= a.io.ntiles) continue;
+        const uint64_t t0 = tl * tile;
         K x[R];
+        uint32_t src[R];
         uint64_t c[R], cand[R];
         bool ceq[R];
+        tile_load<K, R, SORT>(a.io, smem, t0, x, src);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
-            x[r] = qi < a.m ? a.q[qi] : K(0);
-            c[r] = qi < a.m ? 0 : ~0ull;
+            c[r] = tile_valid(a.io.m, t0, src_of<R, SORT>(src, r)) ? 0 : ~0ull;
             cand[r] = 0;
             ceq[r] = false;
         }
@@ -421,24 +425,23 @@ __global__ __launch_bounds__(1024) void k_point_eks_single(PointArgs<K, AOS> a) 
             }
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint64_t qi = t0 + (uint64_t)r * blockDim.x + threadIdx.x;
-            if (qi < a.m) a.out[qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
-        }
+        for (int r = 0; r < R; ++r) tile_put<K, SORT>(a.io, smem, t0, src_of<R, SORT>(src, r), ceq[r] ? a.L.row(cand[r]) : kMiss);
+        tile_flush<K, R, SORT>(a.io, smem, t0);
     }
 }
 
 // ---------------------------------------------------------------- dispatch
 
 template <typename K, bool AOS>
-PointArgs<K, AOS> make_args(const idx_index *h, const void *q, uint64_t m, uint32_t *out, uint32_t pin_levels,
-                            bool early) {
+PointArgs<K, AOS> make_args(const idx_index *h, const PointIO &io, uint32_t pin_levels, bool early) {
     PointArgs<K, AOS> a{};
     a.L = make_load<K, AOS>(h);
     a.G = h->geo;
-    a.q = (const K *)q;
-    a.m = m;
-    a.out = out;
+    a.io.q = (const K *)io.q;
+    a.io.out = io.out;
+    a.io.m = io.m;
+    a.io.local_sort = io.local_sort ? 1u : 0u;
+    a.io.xcd = io.xcd ? 1u : 0u;
     a.pin = (const K *)h->pin;
     a.pin_entries = pin_levels ? h->pin_keys : 0;
     a.pin_levels = pin_levels;
@@ -452,14 +455,22 @@ struct Launch {
     size_t smem;
 };
 
-Launch plan(const idx_index *h, const idx_lookup_params &p, uint64_t m, uint64_t lookups_per_block) {
+// Grid, block and LDS of a launch whose workgroups each take tiles of
+// `lookups_per_block`; fills the tile walk of `io`.
+template <typename K>
+Launch plan(const idx_index *h, const idx_lookup_params &p, QueryIO<K> &io, uint64_t lookups_per_block) {
     Launch L{};
     L.block = p.block;
-    L.smem = p.lds_levels ? (size_t)h->pin_keys * (h->u64 ? 8 : 4) : 0;
-    const uint64_t tiles = (m + lookups_per_block - 1) / lookups_per_block;
-    uint64_t grid = tiles;
+    const size_t pin_bytes = p.lds_levels ? (size_t)h->pin_keys * (h->u64 ? 8 : 4) : 0;
+    io.sort_off = (uint32_t)((pin_bytes + 15) & ~(size_t)15);
+    L.smem = io.local_sort ? io.sort_off + sort_lds_bytes((uint32_t)lookups_per_block, sizeof(K)) : pin_bytes;
+    set_tiles(io, lookups_per_block);
+    uint64_t grid = io.iters;
     if (p.persistent) {
-        const uint64_t cap = (uint64_t)h->cu_count * p.persistent;
+        uint64_t cap = (uint64_t)h->cu_count * p.persistent;
+        // a persistent grid that is a multiple of the XCD count keeps every
+        // workgroup on one XCD's share of the tiles
+        if (io.xcd && cap >= kXcds) cap -= cap % kXcds;
         if (grid > cap) grid = cap;
     }
     if (grid > 0x7FFFFFFFull) grid = 0x7FFFFFFFull;
@@ -468,55 +479,67 @@ Launch plan(const idx_index *h, const idx_lookup_params &p, uint64_t m, uint64_t
 }
 
 template <typename K, bool AOS, int R>
-int run_bs(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
-    auto a = make_args<K, AOS>(h, q, m, out, p.lds_levels, false);
-    const Launch L = plan(h, p, m, (uint64_t)p.block * R);
-    hipLaunchKernelGGL((k_point_bs<K, AOS, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+int run_bs(const idx_index *h, const idx_lookup_params &p, const PointIO &io, hipStream_t s) {
+    auto a = make_args<K, AOS>(h, io, p.lds_levels, false);
+    const Launch L = plan(h, p, a.io, (uint64_t)p.block * R);
+    if (a.io.local_sort)
+        hipLaunchKernelGGL((k_point_bs<K, AOS, R, true>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+    else
+        hipLaunchKernelGGL((k_point_bs<K, AOS, R, false>), dim3(L.grid), dim3(L.block), L.smem, s, a);
     IDX_LAUNCH_CHECK();
     return IDX_OK;
 }
 
 template <typename K, bool AOS, int R>
-int run_ebs(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
-    auto a = make_args<K, AOS>(h, q, m, out, p.lds_levels, false);
-    const Launch L = plan(h, p, m, (uint64_t)p.block * R);
-    hipLaunchKernelGGL((k_point_ebs<K, AOS, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+int run_ebs(const idx_index *h, const idx_lookup_params &p, const PointIO &io, hipStream_t s) {
+    auto a = make_args<K, AOS>(h, io, p.lds_levels, false);
+    const Launch L = plan(h, p, a.io, (uint64_t)p.block * R);
+    if (a.io.local_sort)
+        hipLaunchKernelGGL((k_point_ebs<K, AOS, R, true>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+    else
+        hipLaunchKernelGGL((k_point_ebs<K, AOS, R, false>), dim3(L.grid), dim3(L.block), L.smem, s, a);
     IDX_LAUNCH_CHECK();
     return IDX_OK;
 }
 
 template <typename K, bool AOS, int GL, int R>
-int run_group(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out,
-              hipStream_t s) {
-    auto a = make_args<K, AOS>(h, q, m, out, p.lds_levels, p.early_exit == 1 && h->unique);
-    const Launch L = plan(h, p, m, (uint64_t)(p.block / kWave) * (kWave / GL) * R);
+int run_group(const idx_index *h, const idx_lookup_params &p, const PointIO &io, hipStream_t s) {
+    auto a = make_args<K, AOS>(h, io, p.lds_levels, p.early_exit == 1 && h->unique);
+    const Launch L = plan(h, p, a.io, (uint64_t)(p.block / kWave) * (kWave / GL) * R);
     hipLaunchKernelGGL((k_point_eks_group<K, AOS, GL, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
     IDX_LAUNCH_CHECK();
     return IDX_OK;
 }
 
 template <typename K, bool AOS, int VG, int R>
-int run_vgroup(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out,
-               hipStream_t s) {
-    auto a = make_args<K, AOS>(h, q, m, out, p.lds_levels, p.early_exit == 1 && h->unique);
-    const Launch L = plan(h, p, m, (uint64_t)(p.block / kWave) * (kWave / VG) * R);
+int run_vgroup(const idx_index *h, const idx_lookup_params &p, const PointIO &io, hipStream_t s) {
+    auto a = make_args<K, AOS>(h, io, p.lds_levels, p.early_exit == 1 && h->unique);
+    const Launch L = plan(h, p, a.io, (uint64_t)(p.block / kWave) * (kWave / VG) * R);
     hipLaunchKernelGGL((k_point_eks_vgroup<K, AOS, VG, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
     IDX_LAUNCH_CHECK();
     return IDX_OK;
 }
 
 template <typename K, bool AOS, int GMAX, int R>
-int run_single(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out,
-               hipStream_t s) {
-    auto a = make_args<K, AOS>(h, q, m, out, p.lds_levels, p.early_exit == 1 && h->unique);
-    const Launch L = plan(h, p, m, (uint64_t)p.block * R);
+int run_single(const idx_index *h, const idx_lookup_params &p, const PointIO &io, hipStream_t s) {
+    auto a = make_args<K, AOS>(h, io, p.lds_levels, p.early_exit == 1 && h->unique);
+    const Launch L = plan(h, p, a.io, (uint64_t)p.block * R);
     // 16-byte node loads need 16-byte aligned nodes: SoA nodes of GMAX keys,
     // or AoS blocks whose stride is a multiple of 16
     constexpr bool vec_ok = (GMAX * sizeof(K)) % 16 == 0;
-    if (vec_ok && h->geo.g == GMAX && (!AOS || h->stride % 16 == 0))
-        hipLaunchKernelGGL((k_point_eks_single<K, AOS, GMAX, vec_ok, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+    const bool vec = vec_ok && h->geo.g == GMAX && (!AOS || h->stride % 16 == 0);
+    if (vec && a.io.local_sort)
+        hipLaunchKernelGGL((k_point_eks_single<K, AOS, GMAX, vec_ok, R, true>), dim3(L.grid), dim3(L.block), L.smem, s,
+                           a);
+    else if (vec)
+        hipLaunchKernelGGL((k_point_eks_single<K, AOS, GMAX, vec_ok, R, false>), dim3(L.grid), dim3(L.block), L.smem, s,
+                           a);
+    else if (a.io.local_sort)
+        hipLaunchKernelGGL((k_point_eks_single<K, AOS, GMAX, false, R, true>), dim3(L.grid), dim3(L.block), L.smem, s,
+                           a);
     else
-        hipLaunchKernelGGL((k_point_eks_single<K, AOS, GMAX, false, R>), dim3(L.grid), dim3(L.block), L.smem, s, a);
+        hipLaunchKernelGGL((k_point_eks_single<K, AOS, GMAX, false, R, false>), dim3(L.grid), dim3(L.block), L.smem, s,
+                           a);
     IDX_LAUNCH_CHECK();
     return IDX_OK;
 }
@@ -533,30 +556,30 @@ int with_r(uint32_t r, F &&f) {
 }
 
 template <typename K, bool AOS>
-int point_t(const idx_index *h, const idx_lookup_params &p, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
+int point_t(const idx_index *h, const idx_lookup_params &p, const PointIO &io, hipStream_t s) {
     if (h->layout == IDX_BS)
-        return with_r<0>(p.per_lane, [&](auto R) { return run_bs<K, AOS, decltype(R)::value>(h, p, q, m, out, s); });
+        return with_r<0>(p.per_lane, [&](auto R) { return run_bs<K, AOS, decltype(R)::value>(h, p, io, s); });
     if (h->layout == IDX_EBS)
-        return with_r<0>(p.per_lane, [&](auto R) { return run_ebs<K, AOS, decltype(R)::value>(h, p, q, m, out, s); });
+        return with_r<0>(p.per_lane, [&](auto R) { return run_ebs<K, AOS, decltype(R)::value>(h, p, io, s); });
     if (p.group <= 1) {
         const uint32_t g = h->geo.g;
         return with_r<0>(p.per_lane, [&](auto R) {
             constexpr int RR = decltype(R)::value;
-            if (g <= 4) return run_single<K, AOS, 4, RR>(h, p, q, m, out, s);
-            if (g <= 8) return run_single<K, AOS, 8, RR>(h, p, q, m, out, s);
-            if (g <= 16) return run_single<K, AOS, 16, RR>(h, p, q, m, out, s);
-            return run_single<K, AOS, 32, RR>(h, p, q, m, out, s);
+            if (g <= 4) return run_single<K, AOS, 4, RR>(h, p, io, s);
+            if (g <= 8) return run_single<K, AOS, 8, RR>(h, p, io, s);
+            if (g <= 16) return run_single<K, AOS, 16, RR>(h, p, io, s);
+            return run_single<K, AOS, 32, RR>(h, p, io, s);
         });
     }
     if (p.group < h->geo.g) {
         return with_r<0>(p.per_lane, [&](auto R) {
             constexpr int RR = decltype(R)::value;
             switch (p.group) {
-                case 2: return run_vgroup<K, AOS, 2, RR>(h, p, q, m, out, s);
-                case 4: return run_vgroup<K, AOS, 4, RR>(h, p, q, m, out, s);
-                case 8: return run_vgroup<K, AOS, 8, RR>(h, p, q, m, out, s);
-                case 16: return run_vgroup<K, AOS, 16, RR>(h, p, q, m, out, s);
-                case 32: return run_vgroup<K, AOS, 32, RR>(h, p, q, m, out, s);
+                case 2: return run_vgroup<K, AOS, 2, RR>(h, p, io, s);
+                case 4: return run_vgroup<K, AOS, 4, RR>(h, p, io, s);
+                case 8: return run_vgroup<K, AOS, 8, RR>(h, p, io, s);
+                case 16: return run_vgroup<K, AOS, 16, RR>(h, p, io, s);
+                case 32: return run_vgroup<K, AOS, 32, RR>(h, p, io, s);
                 default: return IDX_ERR_ARG;
             }
         });
@@ -564,12 +587,12 @@ int point_t(const idx_index *h, const idx_lookup_params &p, const void *q, uint6
     return with_r<0>(p.per_lane, [&](auto R) {
         constexpr int RR = decltype(R)::value;
         switch (p.group) {
-            case 2: return run_group<K, AOS, 2, RR>(h, p, q, m, out, s);
-            case 4: return run_group<K, AOS, 4, RR>(h, p, q, m, out, s);
-            case 8: return run_group<K, AOS, 8, RR>(h, p, q, m, out, s);
-            case 16: return run_group<K, AOS, 16, RR>(h, p, q, m, out, s);
-            case 32: return run_group<K, AOS, 32, RR>(h, p, q, m, out, s);
-            case 64: return run_group<K, AOS, 64, RR>(h, p, q, m, out, s);
+            case 2: return run_group<K, AOS, 2, RR>(h, p, io, s);
+            case 4: return run_group<K, AOS, 4, RR>(h, p, io, s);
+            case 8: return run_group<K, AOS, 8, RR>(h, p, io, s);
+            case 16: return run_group<K, AOS, 16, RR>(h, p, io, s);
+            case 32: return run_group<K, AOS, 32, RR>(h, p, io, s);
+            case 64: return run_group<K, AOS, 64, RR>(h, p, io, s);
             default: return IDX_ERR_ARG;
         }
     });
@@ -614,10 +637,17 @@ int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_p
     const size_t kb = h->u64 ? 8 : 4;
     const uint32_t max_levels = pin_levels_for(h, 64 * 1024);
     if (p.lds_levels > max_levels) return IDX_ERR_ARG;
-    (void)kb;
     if (p.persistent > 64) return IDX_ERR_ARG;
-    if (p.reorder > 1) return IDX_ERR_ARG;
-    if (p.reorder) return IDX_ERR_ARG;  // local reordering: not offered by this build
+    // lookup reordering: 0 = none; 1 = sort each tile of block * per_lane
+    // lookups in LDS (one lookup per lane only); 2 = partition the batch by
+    // rank bucket first
+    if (p.reorder > 2) return IDX_ERR_ARG;
+    if (p.reorder == 1) {
+        const uint64_t T = (uint64_t)p.block * p.per_lane;
+        if (p.group > 1 || T > kMaxSortTile) return IDX_ERR_ARG;
+        const size_t pin_bytes = p.lds_levels ? (((size_t)pin_entries_for(h, p.lds_levels) * kb + 15) & ~(size_t)15) : 0;
+        if (pin_bytes + sort_lds_bytes((uint32_t)T, kb) > h->lds_max) return IDX_ERR_ARG;
+    }
     // early exit: 0 = default (on), 1 = on, 2 = off; only effective for unique keys
     if (p.early_exit == 0) p.early_exit = 1;
     if (p.early_exit > 2) return IDX_ERR_ARG;
@@ -626,16 +656,22 @@ int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_p
     return IDX_OK;
 }
 
-int point_lookup(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
-    if (m == 0) return IDX_OK;
+int point_run(idx_index *h, const PointIO &io, hipStream_t s) {
     const idx_lookup_params &p = h->params;
-    if (h->learned && p.model != 2) return point_learned(h, q, m, out, s);
+    if (h->learned && p.model != 2) return point_learned(h, io, s);
     if (p.lds_levels) {
         const int rc = build_pin(h, p.lds_levels, s);
         if (rc != IDX_OK) return rc;
     }
-    if (h->u64) return h->aos ? point_t<uint64_t, true>(h, p, q, m, out, s) : point_t<uint64_t, false>(h, p, q, m, out, s);
-    return h->aos ? point_t<uint32_t, true>(h, p, q, m, out, s) : point_t<uint32_t, false>(h, p, q, m, out, s);
+    if (h->u64) return h->aos ? point_t<uint64_t, true>(h, p, io, s) : point_t<uint64_t, false>(h, p, io, s);
+    return h->aos ? point_t<uint32_t, true>(h, p, io, s) : point_t<uint32_t, false>(h, p, io, s);
+}
+
+int point_lookup(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
+    if (m == 0) return IDX_OK;
+    if (h->params.reorder == 2) return point_partitioned(h, q, m, out, s);
+    PointIO io{q, m, out, h->params.reorder == 1, false};
+    return point_run(h, io, s);
 }
 
 }  // namespace idx

@@ -295,4 +295,10 @@ int range_lookup(idx_index *h, const void *lo, const void *hi, uint64_t m, uint6
                   : range_t<uint32_t, false>(h, lo, hi, m, offsets, out, capacity, total, s);
 }
 
+int exclusive_scan_u64(uint64_t *v, uint64_t m, uint64_t *partial, hipStream_t s) {
+    return exclusive_scan(v, m, partial, s);
+}
+
+uint64_t scan_partials_for(uint64_t m) { return (m + SC_TILE - 1) / SC_TILE; }
+
 }  // namespace idx

@@ -1,0 +1,225 @@
+"""GPU parity of the combined path: models of many indexes trained by one
+launch sequence (idx_learn_batch), and a mixed stream of point and range
+lookups over a batch of indexes in every form (idx_batch_mixed), against the
+oracle element by element."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import rows_host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+idx = pytest.importorskip("paper_2506_01576_amd")
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+MISS = 0xFFFFFFFF
+AUTO, LINEAR, LOG = 0, 1, 2
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def key_set(kind, n, seed, bits):
+    rng = np.random.default_rng(seed)
+    dt = np.uint64 if bits == 64 else np.uint32
+    if kind == "uniform":
+        keys, _ = gen.unique_keys(seed, n, bits, 63 if bits == 64 else 32)
+    elif kind == "lognormal":
+        keys, _ = gen.lognormal_keys(seed, n)
+        if bits == 32:
+            keys = np.unique((keys >> np.uint64(31)).astype(np.uint32))[:n]
+            rng.shuffle(keys)
+            n = len(keys)
+    elif kind == "dup":
+        keys = rng.integers(0, max(1, n // 5), size=n, dtype=np.uint64).astype(dt)
+    else:
+        raise ValueError(kind)
+    rows = (rng.permutation(n).astype(np.uint64) * 7 + 1).astype(np.uint32)
+    return keys.astype(dt), rows
+
+
+def point_queries(keys, m, seed):
+    rng = np.random.default_rng(seed)
+    dt = keys.dtype
+    top = int(np.iinfo(dt).max)
+    if len(keys) == 0:
+        return rng.integers(0, top, size=m, dtype=np.uint64, endpoint=True).astype(dt)
+    q = np.where(rng.random(m) < 0.9, keys[rng.integers(0, len(keys), m)],
+                 rng.integers(0, top, size=m, dtype=np.uint64, endpoint=True).astype(dt))
+    return q.astype(dt)
+
+
+# ------------------------------------------------------- batched training
+
+SETS = [("uniform", 1), ("uniform", 2), ("dup", 5), ("uniform", 100), ("lognormal", 4097), ("dup", 20011),
+        ("uniform", 65539), ("lognormal", 300007), ("uniform", 20011), ("lognormal", 8191)]
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("feature", [AUTO, LINEAR, LOG])
+def test_learn_batch_exact(bits, feature):
+    """Every batch-trained model answers point lookups exactly; its leaf
+    partition equals the oracle's under the exported root; its windows are
+    those of the single-index trainer up to FP32 rounding of the weights."""
+    built = []
+    for j, (kind, n) in enumerate(SETS):
+        keys, rows = key_set(kind, n, 900 + j, bits)
+        built.append((keys, rows, idx.Index(to_dev(keys), to_dev(rows), layout="bs")))
+    leaves = [max(1, len(k) // 64) if j % 3 else min(4096, max(1, len(k))) for j, (k, _, _) in enumerate(built)]
+    say(f"learn_batch bits={bits} feature={feature} leaves={leaves}")
+    stats = idx.learn_batch([ix for _, _, ix in built], leaves, 2, feature)
+    for j, ((keys, rows, ix), st) in enumerate(zip(built, stats)):
+        sk, sr = oracle.stable_sort(keys, rows)
+        L = leaves[j]
+        assert st["leaves"] == L and st["epochs"] == 2
+        if feature != AUTO:
+            assert st["feature"] == feature
+        # exact lookups through the model
+        q = point_queries(keys, 20000, j)
+        want = oracle.point(sk, sr, q, nthreads=4)
+        got = rows_host(ix.point(to_dev(q)))
+        assert np.array_equal(got, want), f"set {j}"
+        # leaf partition under the exported root
+        table = ix.learn_export().cpu().numpy().view(np.uint8).reshape(L, 32)
+        leaf, _ = oracle.assign_leaves(sk, st["feature"], st["root_a0"], st["root_a1"], L)
+        _, _, base, size = oracle.leaf_frame(sk, leaf, L)
+        assert np.array_equal(table[:, 12:16].copy().view(np.uint32).ravel(), size.astype(np.uint32))
+        assert np.array_equal(table[:, 8:12].copy().view(np.uint32).ravel(), base.astype(np.uint32))
+        # every build key's rank lies inside its leaf's window
+        elo = table[:, 24:28].copy().view(np.int32).ravel()
+        ehi = table[:, 28:32].copy().view(np.int32).ravel()
+        assert np.all((size == 0) | (elo <= ehi))
+        # the single-index trainer on the same keys
+        with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as one:
+            s1 = one.learn(L, 2, feature)
+        assert s1["feature"] == st["feature"] or abs(s1["root_loss"] - st["root_loss"]) <= 1e-6 * max(
+            1.0, s1["root_loss"])
+        assert st["mean_window"] == pytest.approx(s1["mean_window"], rel=0.05, abs=1.0)
+    for _, _, ix in built:
+        ix.close()
+
+
+def test_learn_batch_rejects():
+    keys, rows = key_set("uniform", 1000, 3, 64)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as a, \
+            idx.Index(to_dev(keys), to_dev(rows), layout="eks", k=9) as e, \
+            idx.Index(to_dev(keys), to_dev(rows), layout="bs", aos=True) as s:
+        for bad, lv in (([a, a], [4, 4]), ([a, e], [4, 4]), ([s], [4]), ([a], [0]), ([a], [1 << 23])):
+            with pytest.raises(idx.IdxError):
+                idx.learn_batch(bad, lv)
+        k32, r32 = key_set("uniform", 1000, 3, 32)
+        with idx.Index(to_dev(k32), to_dev(r32), layout="bs") as b32:
+            with pytest.raises(idx.IdxError):
+                idx.learn_batch([a, b32], [4, 4])
+
+
+# ------------------------------------------------------------ mixed stream
+
+FORMS = [("bs", 1), ("ebs", 2), ("eks", 9), ("eks", 17), ("eks", 4), ("learned", 1)]
+
+
+def mixed_stream(indexes_keys, seed, bits, per_index):
+    """Per index: point lookups (90% hits) and ranges of 1-256 matches plus
+    empty, inverted and unbounded ranges, interleaved; kind 0 = point."""
+    rng = np.random.default_rng(seed)
+    dt = np.uint64 if bits == 64 else np.uint32
+    top = int(np.iinfo(dt).max)
+    los, his, kinds, counts = [], [], [], []
+    for j, keys in enumerate(indexes_keys):
+        m = int(per_index[j])
+        sk = np.sort(keys)
+        kind = (rng.random(m) < 0.3).astype(np.uint8)
+        lo = point_queries(keys, m, seed * 31 + j)
+        hi = lo.copy()
+        nr = int(kind.sum())
+        if nr and len(sk):
+            c = rng.integers(1, 257, nr)
+            r = rng.integers(0, len(sk), nr)
+            e = np.minimum(r + c - 1, len(sk) - 1)
+            rl, rh = sk[r], sk[e]
+            special = rng.random(nr)
+            rl = np.where(special < 0.05, rh, rl)          # inverted when rl > rh after the swap below
+            rh = np.where(special < 0.05, sk[r], rh)
+            rl = np.where((special >= 0.05) & (special < 0.07), 0, rl)
+            rh = np.where((special >= 0.07) & (special < 0.09), top, rh)
+            lo[kind == 1] = rl.astype(dt)
+            hi[kind == 1] = rh.astype(dt)
+        elif nr:
+            lo[kind == 1] = 0
+            hi[kind == 1] = top
+        los.append(lo)
+        his.append(hi)
+        kinds.append(kind)
+        counts.append(m)
+    off = np.zeros(len(indexes_keys) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(counts)
+    return los, his, kinds, off
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_batch_mixed_parity(bits):
+    sizes = [0, 1, 3, 64, 1000, 4097, 20011, 65536, 131071, 5000, 300, 99991]
+    rng = np.random.default_rng(bits)
+    per_index = [0 if j == 5 else int(x) for j, x in enumerate(rng.integers(1, 6000, len(sizes)))]
+    made, ixs = [], []
+    for j, n in enumerate(sizes):
+        kind = ("uniform", "dup", "lognormal")[j % 3] if n > 10 else "uniform"
+        keys, rows = key_set(kind, n, 1700 + j, bits)
+        layout, k = FORMS[j % len(FORMS)]
+        if layout == "learned":
+            ix = idx.Index(to_dev(keys), to_dev(rows), layout="bs")
+            if len(keys):
+                ix.learn(max(1, len(keys) // 64), 2)
+        else:
+            ix = idx.Index(to_dev(keys), to_dev(rows), layout=layout, k=k)
+        made.append((keys, rows))
+        ixs.append(ix)
+    los, his, kinds, off = mixed_stream([k for k, _ in made], 77 + bits, bits, per_index)
+    lo, hi, kind = np.concatenate(los), np.concatenate(his), np.concatenate(kinds)
+    say(f"mixed bits={bits} m={len(lo)} ranges={int(kind.sum())}")
+    with idx.Batch(ixs) as bt:
+        rowid, offs, rr = bt.mixed(to_dev(lo), to_dev(hi), torch.from_numpy(kind).cuda(), to_dev(off))
+        rowid, offs, rr = rows_host(rowid), offs.cpu().numpy().view(np.uint64), rows_host(rr)
+        # capacity one short of the total is refused, offsets still written
+        if offs[-1] > 0:
+            with pytest.raises(idx.IdxError) as ei:
+                bt.mixed(to_dev(lo), to_dev(hi), torch.from_numpy(kind).cuda(), to_dev(off),
+                         capacity=int(offs[-1]) - 1)
+            assert ei.value.status == idx.IDX_ERR_CAPACITY
+    want_off = np.zeros(len(lo) + 1, dtype=np.uint64)
+    want_rows = []
+    for j, (keys, rows) in enumerate(made):
+        a, b = int(off[j]), int(off[j + 1])
+        if a == b:
+            continue
+        sk, sr = oracle.stable_sort(keys, rows)
+        kd = kind[a:b]
+        pts = np.nonzero(kd == 0)[0]
+        rgs = np.nonzero(kd == 1)[0]
+        want_p = np.full(b - a, MISS, dtype=np.uint32)
+        if len(pts):
+            want_p[pts] = oracle.point(sk, sr, lo[a:b][pts], nthreads=4)
+        assert np.array_equal(rowid[a:b], want_p), f"index {j} points"
+        counts = np.zeros(b - a, dtype=np.uint64)
+        per_q = [np.zeros(0, dtype=np.uint32)] * (b - a)
+        if len(rgs):
+            ro, rrows = oracle.range_lookup(sk, sr, lo[a:b][rgs], hi[a:b][rgs], nthreads=4)
+            for t, qi in enumerate(rgs):
+                per_q[qi] = rrows[ro[t]:ro[t + 1]]
+                counts[qi] = ro[t + 1] - ro[t]
+        want_rows.extend(per_q)
+        want_off[a + 1:b + 1] = counts
+    want_off = np.cumsum(want_off).astype(np.uint64)
+    assert np.array_equal(offs, want_off)
+    want = np.concatenate(want_rows) if want_rows else np.zeros(0, dtype=np.uint32)
+    assert np.array_equal(rr, want)
+    for ix in ixs:
+        ix.close()
