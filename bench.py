@@ -204,6 +204,136 @@ def run_batched(args, idx, gen, np, torch, dev, log, table):
     return res
 
 
+def run_combined(args, idx, gen, np, torch, dev, log):
+    """Many learned indexes with a mixed stream: `combined_indexes` uint64
+    indexes with n log-uniform in [2^16, 2^24], half with uniform keys and
+    half with lognormal-mixture keys; their models are trained by one batched
+    launch sequence (against a loop of per-index training); then a stream of
+    2^26 * indexes / 1024 lookups -- 70% point lookups with 10% misses, 30%
+    ranges of 1-256 matches -- runs through the batch in the learned form and
+    in plain EKS (k = 17, 16 keys per node); both must agree, and sampled
+    indexes are checked against the oracle."""
+    import oracle
+
+    count = args.combined_indexes
+    seed = gen.BASE_SEED + 4
+    t0 = time.time()
+    sizes = gen.log_uniform(seed, 1, 1 << 16, 1 << 24, count)
+    m_total = max(count, (1 << 26) * count // 1024)
+    per = np.full(count, m_total // count, dtype=np.int64)
+    per[: m_total - int(per.sum())] += 1
+    ixs, dev_keys = [], []
+    for j in range(count):
+        n = int(sizes[j])
+        if j % 2 == 0:
+            kh, rh = gen.unique_keys(seed * 1009 + j, n, 64, 63)
+        else:
+            kh, rh = gen.lognormal_keys(seed * 1009 + j, n)
+        ixs.append(idx.Index(torch.from_numpy(kh.view(np.int64)).to(dev), torch.from_numpy(rh.view(np.int32)).to(dev),
+                             layout="bs"))
+    torch.cuda.synchronize()
+    keys_total = int(sum(ix.n for ix in ixs))
+    log(f"combined: built {count} indexes ({keys_total} keys) in {time.time() - t0:.1f}s")
+
+    # mixed stream on the device (seeded): per index, kinds, points, ranges
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    los, his, kinds = [], [], []
+    for j, ix in enumerate(ixs):
+        sk, _ = ix.export()
+        n, m = ix.n, int(per[j])
+        kind = (torch.rand(m, generator=g, device=dev) < 0.3).to(torch.uint8)
+        hit = sk[torch.randint(0, n, (m,), generator=g, device=dev)]
+        miss = torch.randint(0, 1 << 62, (m,), generator=g, device=dev) * 2 + 1
+        lo = torch.where(torch.rand(m, generator=g, device=dev) < 0.9, hit, miss)
+        c = torch.randint(1, 257, (m,), generator=g, device=dev)
+        r = torch.randint(0, n, (m,), generator=g, device=dev)
+        e = torch.clamp(r + c - 1, max=n - 1)
+        rk = kind.bool()
+        lo = torch.where(rk, sk[r], lo)
+        hi = torch.where(rk, sk[e], lo)
+        los.append(lo)
+        his.append(hi)
+        kinds.append(kind)
+        del sk
+    lo, hi, kind = torch.cat(los), torch.cat(his), torch.cat(kinds)
+    del los, his, kinds
+    off = np.zeros(count + 1, dtype=np.int64)
+    off[1:] = np.cumsum(per)
+    doff = torch.from_numpy(off).to(dev)
+    n_ranges = int(kind.sum().item())
+    res = {"indexes": count, "keys": keys_total, "queries": m_total, "ranges": n_ranges,
+           "workload": "uint64 keys, n log-uniform in [2^16, 2^24], half uniform in [0, 2^63), half 64-cluster "
+                       "lognormal; 70% point lookups (10% misses), 30% ranges of 1-256 matches"}
+
+    leaves = [max(1, ix.n // 64) for ix in ixs]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for ix, L in zip(ixs, leaves):
+        ix.learn(L, 2)
+    torch.cuda.synchronize()
+    ms_loop = (time.perf_counter() - t1) * 1e3
+    t1 = time.perf_counter()
+    stats = idx.learn_batch(ixs, leaves, 2)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t1) * 1e3
+    res.update({"train_batched_ms": round(ms_batch, 3), "train_per_index_loop_ms": round(ms_loop, 3),
+                "train_keys_per_s": keys_total / ms_batch * 1e3,
+                "mean_window": float(np.average([s["mean_window"] for s in stats], weights=sizes))})
+    log(f"combined: batched training {ms_batch:.1f} ms, per-index loop {ms_loop:.1f} ms")
+
+    def timed_mixed(bt, reps=3):
+        out = bt.mixed(lo, hi, kind, doff)
+        cap = int(out[1][-1].item())
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            bt.mixed(lo, hi, kind, doff, capacity=cap)
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts)), out
+
+    with idx.Batch(ixs) as bt:
+        ms_learned, got_l = timed_mixed(bt)
+    eks = [ix.relayout("eks", 17) for ix in ixs]
+    with idx.Batch(eks) as bt:
+        ms_eks, got_e = timed_mixed(bt)
+    agree = all(bool(torch.equal(a, b)) for a, b in zip(got_l, got_e))
+    for e in eks:
+        e.close()
+    # sampled indexes against the oracle
+    sample_ok = True
+    for j in sorted({0, 1, count // 2, count - 1}):
+        sk, sr = ixs[j].export()
+        skh = sk.cpu().numpy().view(np.uint64)
+        srh = sr.cpu().numpy().view(np.uint32)
+        a, b = int(off[j]), int(off[j + 1])
+        kd = kind[a:b].cpu().numpy()
+        lh = lo[a:b].cpu().numpy().view(np.uint64)
+        hh = hi[a:b].cpu().numpy().view(np.uint64)
+        pts, rgs = np.nonzero(kd == 0)[0], np.nonzero(kd == 1)[0]
+        want = oracle.point(skh, srh, lh[pts], nthreads=8)
+        sample_ok &= bool(np.array_equal(got_l[0][a:b].cpu().numpy().view(np.uint32)[pts], want))
+        wo, wr = oracle.range_lookup(skh, srh, lh[rgs], hh[rgs], nthreads=8)
+        go = got_l[1].cpu().numpy().view(np.uint64)
+        grows = got_l[2].cpu().numpy().view(np.uint32)
+        for t, qi in enumerate(rgs[:2000]):
+            s0, s1 = int(go[a + qi]), int(go[a + qi + 1])
+            sample_ok &= bool(np.array_equal(grows[s0:s1], wr[wo[t]:wo[t + 1]]))
+    matches = int(got_l[1][-1].item())
+    res.update({"matches": matches, "mixed_learned_ms": round(ms_learned, 4), "mixed_eks17_ms": round(ms_eks, 4),
+                "lookups_per_s_learned": m_total / ms_learned * 1e3, "lookups_per_s_eks17": m_total / ms_eks * 1e3,
+                "learned_vs_eks": ms_eks / ms_learned, "learned_equals_eks": agree, "oracle_sample_exact": sample_ok})
+    log(f"combined: mixed stream learned {ms_learned:.3f} ms, EKS {ms_eks:.3f} ms, agree={agree} "
+        f"oracle sample={sample_ok}")
+    for ix in ixs:
+        ix.close()
+    return res
+
+
 # --------------------------------------------------------------------------
 
 
@@ -219,6 +349,10 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="leave the learned form out")
     ap.add_argument("--no-batched", action="store_true", help="leave the many-index batched workload out")
     ap.add_argument("--batch-indexes", type=int, default=8192)
+    ap.add_argument("--no-combined", action="store_true", help="leave the combined learned/mixed workload out")
+    ap.add_argument("--combined-indexes", type=int, default=128,
+                    help="indexes in the combined workload (1024 = the full configuration; the query count scales "
+                         "with it, 2^26 at 1024)")
     ap.add_argument("--sweep", action="store_true",
                     help="re-measure every candidate form (autotuner) instead of using the tuned table")
     ap.add_argument("--write-table", action="store_true", help="with --sweep: store the winners in the tuned table")
@@ -320,23 +454,24 @@ def main():
     lrec = None
     if not args.no_learned:
         if args.sweep:
-            cands = [(L, r) for L in (1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20) for r in (4, 8)]
+            cands = [(L, r, 0) for L in (1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 21, 1 << 22) for r in (4, 8)]
+            cands += [(1 << 20, 8, 1), (1 << 20, 4, 2)]
         else:
             _, _, _, lp = autotune.choose(n, 64, "learned")
-            cands = [(lp.get("leaves", 1 << 16), lp.get("per_lane", 4))]
+            cands = [(lp.get("leaves", 1 << 16), lp.get("per_lane", 4), lp.get("reorder", 0))]
         trained = None
-        for L, r in cands:
+        for L, r, ro in cands:
             if trained != L:
                 st = base.learn(L, 2)
                 trained = L
-            base.set_params(per_lane=r, model=0)
+            base.set_params(per_lane=r, model=0, reorder=ro)
             ms, ok = time_point(base, reps=3, check=True)
             rec = {"layout": "learned", "k": 1, "aos": False, "params": dict(base.params(), leaves=L), "ms": round(ms, 4),
                    "lookups_per_s": m / ms * 1e3, "bit_exact": ok, "mean_window": st["mean_window"],
                    "max_window": st["max_window"]}
             if args.sweep:
                 sweep.append(rec)
-            log(f"learned leaves={L} R={r}: {ms:.3f} ms exact={ok} mean window {st['mean_window']:.1f}")
+            log(f"learned leaves={L} R={r} reorder={ro}: {ms:.3f} ms exact={ok} mean window {st['mean_window']:.1f}")
             if ok and (lrec is None or ms < lrec["ms"]):
                 lrec = rec
         base.unlearn()
@@ -493,6 +628,10 @@ def main():
         batched = run_batched(args, idx, gen, np, torch, dev, log, table)
         if args.sweep:
             batched["class_sweep"] = table.get("batch")
+    combined = None
+    if not args.no_combined:
+        torch.cuda.empty_cache()
+        combined = run_combined(args, idx, gen, np, torch, dev, log)
 
     line = {
         "metric": METRIC,
@@ -522,6 +661,7 @@ def main():
         "bit_exact": all(r["bit_exact"] for r in checked),
         "random_access": probe,
         "batched": batched,
+        "combined": combined,
         "sweep": [{kk: r[kk] for kk in ("layout", "k", "aos", "params", "ms", "lookups_per_s", "bit_exact")}
                   for r in sweep],
     }

@@ -62,6 +62,18 @@ def candidates(key_bits: int, n: int):
                     out.append(("eks", k, aos, {"group": 1, "per_lane": 4, "lds_levels": lev, "persistent": 2,
                                                 "block": 1024}))
             out.append(("eks", k, "padded", {"group": 1, "per_lane": 4}))
+    # lookup reordering (Section 7.4): the tile-local sort, and the batch
+    # partitioned by rank bucket, which pays once the index is far larger
+    # than one XCD's L2
+    out.append(("bs", 1, False, {"reorder": 1, "per_lane": 4, "block": 1024}))
+    out.append(("ebs", 2, False, {"reorder": 1, "per_lane": 8, "block": 512}))
+    if n >= 1 << 20:
+        out.append(("bs", 1, False, {"reorder": 2, "per_lane": 4}))
+        out.append(("bs", 1, False, {"reorder": 2, "per_lane": 8}))
+        out.append(("ebs", 2, False, {"reorder": 2, "per_lane": 8}))
+        out.append(("ebs", 2, False, {"reorder": 2, "per_lane": 4}))
+        out.append(("eks", 9, False, {"group": 1, "per_lane": 4, "reorder": 2}))
+        out.append(("eks", 17, "padded", {"group": 1, "per_lane": 4, "reorder": 2}))
     return out
 
 
