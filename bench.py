@@ -57,16 +57,21 @@ def levels_eytzinger(n: int, k: int):
 
 
 def algo_bytes(form: str, n: int, k: int, key_bytes: int, early_exit: bool = True, window: float = 0.0,
-               leaves: int = 0) -> dict:
+               leaves: int = 0, aos=False) -> dict:
     stream = key_bytes + 4
     uncached = 0.0
+    rowid = GRANULE
     if form == "learned":
         # leaf record (32 B each; counted only if the table exceeds on-chip
         # capacity) + binary search over the mean window: one granule per
-        # step until the remaining interval fits one granule
+        # step until the remaining interval fits one granule; with the array
+        # of structures each slot holds the row ID too (no separate granule)
         if leaves * 32 > ONCHIP_BYTES:
             uncached += GRANULE
-        span = max(window, 1.0) * key_bytes
+        slot = key_bytes if not aos else (16 if aos == "padded" else key_bytes + 4)
+        if aos:
+            rowid = 0
+        span = max(window, 1.0) * slot
         uncached += GRANULE * max(0.0, math.ceil(math.log2(max(span / GRANULE, 1.0))))
         if span > 0:
             uncached += GRANULE  # the final granule holding the answer
@@ -91,7 +96,6 @@ def algo_bytes(form: str, n: int, k: int, key_bytes: int, early_exit: bool = Tru
                                                                              else (b - a) / ((kk - 1) * kk ** lvl))
             if cum > ONCHIP_BYTES:
                 uncached += reach * node_g
-    rowid = GRANULE
     return {"stream": stream, "tree": uncached, "rowid": rowid, "total": stream + uncached + rowid}
 
 
@@ -454,26 +458,37 @@ def main():
     lrec = None
     if not args.no_learned:
         if args.sweep:
-            cands = [(L, r, 0) for L in (1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 21, 1 << 22) for r in (4, 8)]
-            cands += [(1 << 20, 8, 1), (1 << 20, 4, 2)]
+            cands = [(L, r, 0, False) for L in (1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 21, 1 << 22)
+                     for r in (4, 8)]
+            cands += [(1 << 20, 8, 1, False), (1 << 20, 4, 2, False)]
+            # the array of structures: the window scan reads each key with its row ID
+            cands += [(L, r, 0, a) for a in ("padded", True) for L in (1 << 21, 1 << 22) for r in (2, 4, 8)]
         else:
-            _, _, _, lp = autotune.choose(n, 64, "learned")
-            cands = [(lp.get("leaves", 1 << 16), lp.get("per_lane", 4), lp.get("reorder", 0))]
+            _, _, laos, lp = autotune.choose(n, 64, "learned")
+            cands = [(lp.get("leaves", 1 << 16), lp.get("per_lane", 4), lp.get("reorder", 0), laos)]
         trained = None
-        for L, r, ro in cands:
-            if trained != L:
-                st = base.learn(L, 2)
-                trained = L
-            base.set_params(per_lane=r, model=0, reorder=ro)
-            ms, ok = time_point(base, reps=3, check=True)
-            rec = {"layout": "learned", "k": 1, "aos": False, "params": dict(base.params(), leaves=L), "ms": round(ms, 4),
+        arrays = {False: base}
+        for L, r, ro, la in cands:
+            if la not in arrays:
+                arrays[la] = base.relayout("bs", 1, la)
+            arr = arrays[la]
+            if trained != (L, la):
+                st = arr.learn(L, 2)
+                trained = (L, la)
+            arr.set_params(per_lane=r, model=0, reorder=ro)
+            ms, ok = time_point(arr, reps=3, check=True)
+            rec = {"layout": "learned", "k": 1, "aos": la, "params": dict(arr.params(), leaves=L), "ms": round(ms, 4),
                    "lookups_per_s": m / ms * 1e3, "bit_exact": ok, "mean_window": st["mean_window"],
                    "max_window": st["max_window"]}
             if args.sweep:
                 sweep.append(rec)
-            log(f"learned leaves={L} R={r} reorder={ro}: {ms:.3f} ms exact={ok} mean window {st['mean_window']:.1f}")
+            log(f"learned leaves={L} R={r} reorder={ro} aos={la}: {ms:.3f} ms exact={ok} "
+                f"mean window {st['mean_window']:.1f}")
             if ok and (lrec is None or ms < lrec["ms"]):
                 lrec = rec
+        for la, arr in arrays.items():
+            if arr is not base:
+                arr.close()
         base.unlearn()
         base.reset_params()
         if args.sweep and args.write_table and lrec:
@@ -486,7 +501,7 @@ def main():
 
     def form_name(r):
         if r["layout"] == "learned":
-            return f"LEARNED(leaves={r['params']['leaves']})"
+            return f"LEARNED(leaves={r['params']['leaves']}{',' + ('aos' if r['aos'] is True else str(r['aos'])) if r['aos'] else ''})"
         if r["layout"] != "eks":
             return r["layout"].upper()
         mode = "single" if r["params"]["group"] == 1 else f"group{r['params']['group']}"
@@ -512,11 +527,13 @@ def main():
         marks = [("build_sort", a, b)]
         for name, rec in forms[1:]:
             if rec["layout"] == "learned":
-                # the model attaches to the sorted array itself
+                # the model attaches to the sorted array itself (copied into
+                # the array of structures first when the form uses it)
                 a = ev()
-                bs.learn(rec["params"]["leaves"], 2)
+                arr = bs if not rec["aos"] else bs.relayout("bs", 1, rec["aos"])
+                arr.learn(rec["params"]["leaves"], 2)
                 b = ev()
-                hs[name] = bs
+                hs[name] = arr
                 marks.append((f"train_{name}", a, b))
                 continue
             a = ev()
@@ -564,7 +581,8 @@ def main():
 
     # ------------------------------------------------------------ roofline
     ab = algo_bytes(hrec["layout"], n, hrec["k"], 8, early_exit=hrec["params"].get("early_exit", 1) == 1,
-                    window=hrec.get("mean_window", 0.0), leaves=hrec["params"].get("leaves", 0))
+                    window=hrec.get("mean_window", 0.0), leaves=hrec["params"].get("leaves", 0),
+                    aos=hrec["aos"] if hrec["layout"] == "learned" else False)
     t_kernel = mean[f"point_{headline}"] / 1e3
     achieved = ab["total"] * m / t_kernel / 1e9
     hp = hrec["params"]

@@ -273,7 +273,9 @@ typedef struct idx_learn_stats {
  * rank) are measured over all build keys.  Afterwards idx_point and idx_range
  * on h search only the predicted window; their answers are unchanged.
  *
- *   h        an IDX_BS index with SoA layout and n >= 1 (IDX_ERR_ARG otherwise)
+ *   h        an IDX_BS index (any storage: SoA, AoS or line-padded AoS, where
+ *            the window scan reads each key with its row ID) with n >= 1
+ *            (IDX_ERR_ARG otherwise)
  *   leaves   1 <= leaves <= 2^22;  epochs 1..16;  feature IDX_FEATURE_*
  * Synchronises `stream`.  Errors: IDX_ERR_ARG, IDX_ERR_NOMEM, IDX_ERR_HIP.
  */

@@ -27,6 +27,7 @@
 #include <new>
 
 #include "internal.hpp"
+#include "access.hpp"
 #include "learned_model.hpp"
 #include "qio.hpp"
 
@@ -37,15 +38,15 @@ namespace {
 constexpr int LT = 256;  // threads per block in the training kernels
 constexpr int CHUNK = 32;  // consecutive keys per thread in the per-leaf passes
 
-template <typename K>
-__global__ __launch_bounds__(LT) void k_root_accum(const K *__restrict__ keys, uint64_t n, const RootRec *Rp,
+template <typename K, bool AOS>
+__global__ __launch_bounds__(LT) void k_root_accum(Load<K, AOS> keys, uint64_t n, const RootRec *Rp,
                                                    double *__restrict__ acc) {
     __shared__ double s[LT / kWave][NACC];
     const RootRec R = *Rp;
     double a[NACC] = {0, 0, 0, 0, 0, 0};
     const double scale = (double)R.L / (double)n;
     for (uint64_t i = (uint64_t)blockIdx.x * LT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * LT) {
-        const float x = key_feature((uint64_t)keys[i], R.mode);
+        const float x = key_feature((uint64_t)keys.key(i), R.mode);
         const float t = (float)((double)i * scale);
         const float r = __fsub_rn(__fadd_rn(__fmul_rn(R.a1, x), R.a0), t);  // forward residual
         a[0] += 1.0;
@@ -78,6 +79,11 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t count, uint32_t v) {
         p[i] = v;
 }
 
+__global__ void k_fill_u64(uint64_t *p, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
 __global__ void k_fill_f64(double *p, uint64_t count) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
@@ -85,72 +91,48 @@ __global__ void k_fill_f64(double *p, uint64_t count) {
 
 // Keys per leaf.  Keys are sorted and leaf_of is non-decreasing, so a thread's
 // chunk holds few runs; each run adds its length once.
-template <typename K>
-__global__ __launch_bounds__(LT) void k_leaf_count(const K *__restrict__ keys, uint64_t n, const RootRec *Rp,
-                                                   uint32_t *__restrict__ count) {
+template <typename K, bool AOS>
+__global__ __launch_bounds__(LT) void k_leaf_count(Load<K, AOS> keys, uint64_t n, const RootRec *Rp,
+                                                   unsigned long long *__restrict__ count) {
     const RootRec R = *Rp;
     const uint64_t t = (uint64_t)blockIdx.x * LT + threadIdx.x;
     const uint64_t b = t * CHUNK;
     if (b >= n) return;
     const uint64_t e = b + CHUNK < n ? b + CHUNK : n;
-    uint32_t cur = leaf_of(R, keys[b]), run = 0;
+    uint32_t cur = leaf_of(R, keys.key(b)), run = 0;
     for (uint64_t i = b; i < e; ++i) {
-        const uint32_t l = leaf_of(R, keys[i]);
+        const uint32_t l = leaf_of(R, keys.key(i));
         if (l != cur) {
-            atomicAdd(&count[cur], run);
+            atomicAdd(&count[cur], (unsigned long long)run);
             cur = l;
             run = 0;
         }
         ++run;
     }
-    atomicAdd(&count[cur], run);
+    atomicAdd(&count[cur], (unsigned long long)run);
 }
 
-// Single workgroup: base ranks (exclusive scan of the counts), sizes, kmin;
-// leaf parameters start at zero.
-template <typename K>
-__global__ __launch_bounds__(1024) void k_leaf_layout(const K *__restrict__ keys, const uint32_t *__restrict__ count,
-                                                      uint32_t L, LeafRec *__restrict__ leaves) {
-    __shared__ uint32_t s_tot[1024 / kWave];
-    __shared__ uint32_t s_run;
-    if (threadIdx.x == 0) s_run = 0;
-    __syncthreads();
-    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    for (uint32_t c0 = 0; c0 < L; c0 += 1024) {
-        const uint32_t l = c0 + threadIdx.x;
-        const uint32_t v = l < L ? count[l] : 0;
-        uint32_t incl = v;
-        for (int off = 1; off < kWave; off <<= 1) {
-            const uint32_t x = __shfl_up(incl, off, kWave);
-            if (lane >= (uint32_t)off) incl += x;
-        }
-        if (lane == kWave - 1) s_tot[wave] = incl;
-        __syncthreads();
-        uint32_t before = s_run;
-        for (uint32_t w = 0; w < wave; ++w) before += s_tot[w];
-        if (l < L) {
-            LeafRec r{};
-            r.base = before + incl - v;
-            r.size = v;
-            r.kmin = v ? (uint64_t)keys[r.base] : 0ull;
-            r.b0 = 0.f;
-            r.b1 = 0.f;
-            r.elo = INT_MAX;
-            r.ehi = INT_MIN;
-            leaves[l] = r;
-        }
-        __syncthreads();
-        if (threadIdx.x == 1023) {
-            uint32_t tot = 0;
-            for (int w = 0; w < 1024 / kWave; ++w) tot += s_tot[w];
-            s_run += tot;
-        }
-        __syncthreads();
-    }
+// Leaf records from the exclusive scan of the per-leaf counts (base[l] =
+// keys before leaf l, base[L] = n): base rank, size, first key; parameters
+// start at zero and error bounds empty.
+template <typename K, bool AOS>
+__global__ void k_leaf_init(Load<K, AOS> keys, const unsigned long long *__restrict__ base, uint32_t L,
+                            LeafRec *__restrict__ leaves) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    LeafRec r{};
+    r.base = (uint32_t)base[l];
+    r.size = (uint32_t)(base[l + 1] - base[l]);
+    r.kmin = r.size ? (uint64_t)keys.key(r.base) : 0ull;
+    r.b0 = 0.f;
+    r.b1 = 0.f;
+    r.elo = INT_MAX;
+    r.ehi = INT_MIN;
+    leaves[l] = r;
 }
 
-template <typename K>
-__global__ __launch_bounds__(LT) void k_leaf_accum(const K *__restrict__ keys, uint64_t n, const RootRec *Rp,
+template <typename K, bool AOS>
+__global__ __launch_bounds__(LT) void k_leaf_accum(Load<K, AOS> keys, uint64_t n, const RootRec *Rp,
                                                    const LeafRec *__restrict__ leaves, double *__restrict__ acc) {
     const RootRec R = *Rp;
     const uint64_t t = (uint64_t)blockIdx.x * LT + threadIdx.x;
@@ -161,10 +143,10 @@ __global__ __launch_bounds__(LT) void k_leaf_accum(const K *__restrict__ keys, u
         for (int j = 0; j < NACC; ++j) atomicAdd(&acc[(uint64_t)l * NACC + j], v[j]);
     };
     double a[NACC] = {0, 0, 0, 0, 0, 0};
-    uint32_t cur = b < n ? leaf_of(R, keys[b]) : 0;
+    uint32_t cur = b < n ? leaf_of(R, keys.key(b)) : 0;
     LeafRec L = leaves[cur];
     for (uint64_t i = b; i < e; ++i) {
-        const uint64_t key = (uint64_t)keys[i];
+        const uint64_t key = (uint64_t)keys.key(i);
         const uint32_t l = leaf_of(R, key);
         if (l != cur) {
             add(cur, a);
@@ -195,8 +177,8 @@ __global__ void k_leaf_update(LeafRec *__restrict__ leaves, const double *__rest
     leaves[l].b1 = r.b1;
 }
 
-template <typename K>
-__global__ __launch_bounds__(LT) void k_leaf_errors(const K *__restrict__ keys, uint64_t n, const RootRec *Rp,
+template <typename K, bool AOS>
+__global__ __launch_bounds__(LT) void k_leaf_errors(Load<K, AOS> keys, uint64_t n, const RootRec *Rp,
                                                     LeafRec *__restrict__ leaves) {
     const RootRec R = *Rp;
     const uint64_t t = (uint64_t)blockIdx.x * LT + threadIdx.x;
@@ -207,10 +189,10 @@ __global__ __launch_bounds__(LT) void k_leaf_errors(const K *__restrict__ keys, 
         atomicMax(&leaves[l].ehi, (int32_t)v[1]);
     };
     int64_t mm[2] = {INT_MAX, INT_MIN};
-    uint32_t cur = b < n ? leaf_of(R, keys[b]) : 0;
+    uint32_t cur = b < n ? leaf_of(R, keys.key(b)) : 0;
     LeafRec L = leaves[cur];
     for (uint64_t i = b; i < e; ++i) {
-        const uint64_t key = (uint64_t)keys[i];
+        const uint64_t key = (uint64_t)keys.key(i);
         const uint32_t l = leaf_of(R, key);
         if (l != cur) {
             add(cur, mm);
@@ -289,23 +271,47 @@ uint32_t grid_for(uint64_t threads, uint32_t block) {
     return (uint32_t)b;
 }
 
-template <typename K>
+// Per-leaf key counts, their exclusive scan and the leaf records.
+template <typename K, bool AOS>
+int leaf_layout(Load<K, AOS> keys, uint64_t n, const RootRec *d_root, uint32_t L, unsigned long long *count,
+                uint64_t *partial, LeafRec *leaves, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for((uint64_t)L + 1, 256)), dim3(256), 0, s, (uint64_t *)count,
+                       (uint64_t)L + 1);
+    hipLaunchKernelGGL((k_leaf_count<K, AOS>), dim3(grid_for((n + CHUNK - 1) / CHUNK, LT)), dim3(LT), 0, s, keys, n,
+                       d_root, count);
+    IDX_LAUNCH_CHECK();
+    const int rc = exclusive_scan_u64((uint64_t *)count, L, partial, s);
+    if (rc != IDX_OK) return rc;
+    hipLaunchKernelGGL((k_leaf_init<K, AOS>), dim3(grid_for(L, 256)), dim3(256), 0, s, keys,
+                       (const unsigned long long *)count, L, leaves);
+    IDX_LAUNCH_CHECK();
+    return IDX_OK;
+}
+
+// Bytes of the leaf counters and scan partials for L leaves.
+size_t layout_scratch_bytes(uint32_t L) {
+    auto up256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    return up256(((size_t)L + 1) * 8) + up256(scan_partials_for(L) * 8);
+}
+
+template <typename K, bool AOS>
 int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream_t s) {
     const uint64_t n = h->n;
-    const K *keys = (const K *)h->keys;
+    const Load<K, AOS> keys = make_load<K, AOS>(h);
     LearnedModel *M = h->learned;
-    // device scratch: root record, root acc, leaf acc, counts, stats; every
-    // region starts on a 256-byte boundary (FP64 atomics need 8-byte alignment)
+    // device scratch: root record, root acc, leaf acc, stats, counts and scan
+    // partials; every region starts on a 256-byte boundary (FP64 atomics need
+    // 8-byte alignment)
     auto up256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t leaf_acc_b = up256((size_t)L * NACC * sizeof(double));
-    const size_t cnt_b = up256((size_t)L * 4);
-    char *tmp = (char *)h->alloc.get(256 + 256 + leaf_acc_b + cnt_b + 256, s);
+    char *tmp = (char *)h->alloc.get(256 + 256 + leaf_acc_b + 256 + layout_scratch_bytes(L), s);
     if (!tmp) return IDX_ERR_NOMEM;
     RootRec *d_root = (RootRec *)tmp;
     double *root_acc = (double *)(tmp + 256);
     double *leaf_acc = (double *)(tmp + 512);
-    uint32_t *count = (uint32_t *)(tmp + 512 + leaf_acc_b);
-    double *stats = (double *)(tmp + 512 + leaf_acc_b + cnt_b);
+    double *stats = (double *)(tmp + 512 + leaf_acc_b);
+    unsigned long long *count = (unsigned long long *)(tmp + 512 + leaf_acc_b + 256);
+    uint64_t *partial = (uint64_t *)((char *)count + up256(((size_t)L + 1) * 8));
     int rc = IDX_OK;
     const uint32_t rblocks = (uint32_t)((n + LT * 8 - 1) / (LT * 8)) > 2048 ? 2048u
                                                                              : (uint32_t)((n + LT * 8 - 1) / (LT * 8));
@@ -320,7 +326,7 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
             if (hipMemcpyAsync(d_root, &R, sizeof(R), hipMemcpyHostToDevice, s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
             for (uint32_t ep = 0; ep <= epochs; ++ep) {
                 hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, root_acc, (uint64_t)NACC);
-                hipLaunchKernelGGL((k_root_accum<K>), dim3(rblocks ? rblocks : 1), dim3(LT), 0, s, keys, n, d_root,
+                hipLaunchKernelGGL((k_root_accum<K, AOS>), dim3(rblocks ? rblocks : 1), dim3(LT), 0, s, keys, n, d_root,
                                    root_acc);
                 if (ep < epochs) hipLaunchKernelGGL(k_root_update, dim3(1), dim3(64), 0, s, d_root, root_acc);
             }
@@ -340,19 +346,19 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
         if (hipMemcpyAsync(d_root, &best, sizeof(best), hipMemcpyHostToDevice, s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
 
         // ---- stage 2: leaves
-        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L, 256)), dim3(256), 0, s, count, (uint64_t)L, 0u);
-        hipLaunchKernelGGL((k_leaf_count<K>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, count);
-        hipLaunchKernelGGL((k_leaf_layout<K>), dim3(1), dim3(1024), 0, s, keys, count, L, M->leaves);
+        rc = leaf_layout<K, AOS>(keys, n, d_root, L, count, partial, M->leaves, s);
+        if (rc != IDX_OK) break;
         for (uint32_t ep = 0; ep <= epochs; ++ep) {
             hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((uint64_t)L * NACC, 256)), dim3(256), 0, s, leaf_acc,
                                (uint64_t)L * NACC);
-            hipLaunchKernelGGL((k_leaf_accum<K>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, M->leaves, leaf_acc);
+            hipLaunchKernelGGL((k_leaf_accum<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, M->leaves,
+                               leaf_acc);
             if (ep < epochs)
                 hipLaunchKernelGGL(k_leaf_update, dim3(grid_for(L, 256)), dim3(256), 0, s, M->leaves, leaf_acc, L);
         }
         hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, stats, (uint64_t)4);
         hipLaunchKernelGGL(k_sum_leaf_loss, dim3(64), dim3(256), 0, s, leaf_acc, L, stats + 2);
-        hipLaunchKernelGGL((k_leaf_errors<K>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, M->leaves);
+        hipLaunchKernelGGL((k_leaf_errors<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, M->leaves);
         hipLaunchKernelGGL(k_leaf_finish, dim3(grid_for(L, 256)), dim3(256), 0, s, M->leaves, L, stats);
         if (hipGetLastError() != hipSuccess) { rc = IDX_ERR_HIP; break; }
         double st[4];
@@ -369,7 +375,7 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
 }  // namespace
 
 int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream_t s) {
-    if (h->layout != IDX_BS || h->aos || h->n == 0) return IDX_ERR_ARG;
+    if (h->layout != IDX_BS || h->n == 0) return IDX_ERR_ARG;
     if (L == 0 || L > (1u << 22) || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_LOG) return IDX_ERR_ARG;
     drop_model(h, s);
     LearnedModel *M = new (std::nothrow) LearnedModel();
@@ -382,7 +388,9 @@ int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream
     h->learned = M;
     M->stats.leaves = L;
     M->stats.epochs = epochs;
-    const int rc = h->u64 ? train_t<uint64_t>(h, L, epochs, feature, s) : train_t<uint32_t>(h, L, epochs, feature, s);
+    int rc;
+    if (h->u64) rc = h->aos ? train_t<uint64_t, true>(h, L, epochs, feature, s) : train_t<uint64_t, false>(h, L, epochs, feature, s);
+    else rc = h->aos ? train_t<uint32_t, true>(h, L, epochs, feature, s) : train_t<uint32_t, false>(h, L, epochs, feature, s);
     if (rc != IDX_OK) {
         drop_model(h, s);
         return rc;
@@ -418,11 +426,62 @@ int learn_export(const idx_index *h, void *leaves_out, hipStream_t s) {
 
 namespace {
 
-template <typename K, int R, bool SORT>
-__global__ __launch_bounds__(1024) void k_point_learned(const K *__restrict__ keys, const uint32_t *__restrict__ rows,
-                                                        uint64_t n, RootRec root,
+// Window scan on the array-of-structures sorted array (one key and its row
+// ID per slot): keys of slots [b, b + len) (len <= W) below x, and the row ID
+// of the first slot equal to x.  Slots are read with independent loads; the
+// row ID comes with its key, so a hit costs no further line.  A 16-byte slot
+// holding a 64-bit key is one 16-byte vector load.
+template <typename K, int W>
+__device__ __forceinline__ uint32_t count_below_slots(const Load<K, true> &L, uint64_t b, uint32_t len, K x,
+                                                      bool &eq, uint32_t &row) {
+    uint32_t cnt = 0;
+    bool e = false;
+    uint32_t rw = kMiss;
+    if (sizeof(K) == 8 && L.stride == 16) {
+        uint4 w[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            if ((uint32_t)j < len) w[j] = *(const uint4 *)(L.base + (b + j) * 16);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            if ((uint32_t)j >= len) continue;
+            const K k = (K)(((uint64_t)w[j].y << 32) | w[j].x);
+            cnt += k < x ? 1u : 0u;
+            if (!e && k == x) {
+                e = true;
+                rw = w[j].z;
+            }
+        }
+    } else {
+        K k[W];
+#pragma unroll
+        for (int j = 0; j < W; ++j) k[j] = (uint32_t)j < len ? L.key(b + j) : K(0);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            if ((uint32_t)j >= len) continue;
+            cnt += k[j] < x ? 1u : 0u;
+            e |= k[j] == x;
+        }
+        if (e) rw = L.row(b + cnt);
+    }
+    eq = e;
+    row = rw;
+    return cnt;
+}
+
+// Windows are narrowed with binary-search steps down to STOP keys: 15 on the
+// structure-of-arrays layout (its scan reads 16 keys in 9 vector loads), 7
+// on the array of structures (8 slots, each with its row ID).
+template <bool AOS>
+constexpr uint32_t window_stop() {
+    return AOS ? 7u : 15u;
+}
+
+template <typename K, int R, bool SORT, bool AOS>
+__global__ __launch_bounds__(1024) void k_point_learned(Load<K, AOS> keys, uint64_t n, RootRec root,
                                                         const LeafRec *__restrict__ leaves, QueryIO<K> io) {
     extern __shared__ __align__(16) char smem[];
+    constexpr uint32_t STOP = window_stop<AOS>();
     const uint64_t tile = (uint64_t)blockDim.x * R;
     for (uint64_t it = blockIdx.x; it < io.iters; it += gridDim.x) {
         const uint64_t tl = tile_of(it, io.ntiles, io.xcd);
@@ -440,18 +499,18 @@ __global__ __launch_bounds__(1024) void k_point_learned(const K *__restrict__ ke
             len[r] = tile_valid(io.m, t0, src_of<R, SORT>(src, r)) ? (uint32_t)wl : 0u;
         }
         // The lower bound lies in [b, b + len].  Narrow wide windows with
-        // binary-search steps, then read the last <= 15 keys and the key after
-        // them in one round of independent loads.
+        // binary-search steps, then read the last <= STOP keys and the key
+        // after them in one round of independent loads.
         bool more = true;
         while (more) {
             more = false;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (len[r] > 15) {
+                if (len[r] > STOP) {
                     const uint32_t half = len[r] >> 1;
-                    b[r] = keys[b[r] + half - 1] < x[r] ? b[r] + half : b[r];
+                    b[r] = keys.key(b[r] + half - 1) < x[r] ? b[r] + half : b[r];
                     len[r] -= half;
-                    more |= len[r] > 15;
+                    more |= len[r] > STOP;
                 }
             }
         }
@@ -461,8 +520,14 @@ __global__ __launch_bounds__(1024) void k_point_learned(const K *__restrict__ ke
             if (tile_valid(io.m, t0, src_of<R, SORT>(src, r))) {
                 const uint64_t sl = ((uint64_t)len[r] + 1) < (n - b[r]) ? ((uint64_t)len[r] + 1) : (n - b[r]);
                 bool eq;
-                const uint32_t c = count_below<K, 16>(keys, b[r], (uint32_t)sl, x[r], eq);
-                if (eq) res = rows[(uint64_t)b[r] + c];
+                if constexpr (AOS) {
+                    uint32_t row;
+                    (void)count_below_slots<K, STOP + 1>(keys, b[r], (uint32_t)sl, x[r], eq, row);
+                    if (eq) res = row;
+                } else {
+                    const uint32_t c = count_below<K, 16>(keys.k, b[r], (uint32_t)sl, x[r], eq);
+                    if (eq) res = keys.r[(uint64_t)b[r] + c];
+                }
             }
             tile_put<K, SORT>(io, smem, t0, src_of<R, SORT>(src, r), res);
         }
@@ -495,12 +560,18 @@ int point_learned(idx_index *h, const PointIO &pio, hipStream_t s) {
         }                                                                                                   \
         const uint32_t g = (uint32_t)(grid ? (grid > 0x7FFFFFFFull ? 0x7FFFFFFFull : grid) : 1);            \
         const size_t smem = io.local_sort ? sort_lds_bytes((uint32_t)tile, sizeof(KT)) : 0;                 \
-        if (io.local_sort)                                                                                  \
-            hipLaunchKernelGGL((k_point_learned<KT, RR, true>), dim3(g), dim3(block), smem, s,              \
-                               (const KT *)h->keys, h->rowids, h->n, M->root, M->leaves, io);               \
+        if (h->aos && io.local_sort)                                                                        \
+            hipLaunchKernelGGL((k_point_learned<KT, RR, true, true>), dim3(g), dim3(block), smem, s,        \
+                               make_load<KT, true>(h), h->n, M->root, M->leaves, io);                       \
+        else if (h->aos)                                                                                    \
+            hipLaunchKernelGGL((k_point_learned<KT, RR, false, true>), dim3(g), dim3(block), smem, s,       \
+                               make_load<KT, true>(h), h->n, M->root, M->leaves, io);                       \
+        else if (io.local_sort)                                                                             \
+            hipLaunchKernelGGL((k_point_learned<KT, RR, true, false>), dim3(g), dim3(block), smem, s,       \
+                               make_load<KT, false>(h), h->n, M->root, M->leaves, io);                      \
         else                                                                                                \
-            hipLaunchKernelGGL((k_point_learned<KT, RR, false>), dim3(g), dim3(block), smem, s,             \
-                               (const KT *)h->keys, h->rowids, h->n, M->root, M->leaves, io);               \
+            hipLaunchKernelGGL((k_point_learned<KT, RR, false, false>), dim3(g), dim3(block), smem, s,      \
+                               make_load<KT, false>(h), h->n, M->root, M->leaves, io);                      \
     } while (0)
     if (h->u64) {
         switch (R) {
@@ -523,8 +594,28 @@ int point_learned(idx_index *h, const PointIO &pio, hipStream_t s) {
 }
 
 namespace {
-template <typename K>
-__global__ __launch_bounds__(256) void k_range_count_learned(const K *__restrict__ keys, uint64_t n, RootRec root,
+// Rank of the first key >= x through the model (the window holds it).
+template <typename K, bool AOS>
+__device__ __forceinline__ uint64_t model_lower_rank(const Load<K, AOS> &keys, uint64_t n, const RootRec &root,
+                                                     const LeafRec *__restrict__ leaves, K x) {
+    if constexpr (!AOS) {
+        return learned_lower_rank(keys.k, n, root, leaves, x);
+    } else {
+        uint64_t b, len;
+        learned_window(root, leaves, (uint64_t)x, b, len);
+        while (len > window_stop<true>()) {
+            const uint64_t half = len >> 1;
+            b = keys.key(b + half - 1) < x ? b + half : b;
+            len -= half;
+        }
+        bool eq;
+        uint32_t row;
+        return b + count_below_slots<K, window_stop<true>() + 1>(keys, b, (uint32_t)len, x, eq, row);
+    }
+}
+
+template <typename K, bool AOS>
+__global__ __launch_bounds__(256) void k_range_count_learned(Load<K, AOS> keys, uint64_t n, RootRec root,
                                                              const LeafRec *__restrict__ leaves,
                                                              const K *__restrict__ lo, const K *__restrict__ hi,
                                                              uint64_t m, uint32_t *__restrict__ first,
@@ -534,24 +625,31 @@ __global__ __launch_bounds__(256) void k_range_count_learned(const K *__restrict
     const K L = lo[q], U = hi[q];
     uint64_t r0 = 0, r1 = 0;
     if (L <= U) {
-        r0 = learned_lower_rank(keys, n, root, leaves, L);
-        r1 = (U == ~K(0)) ? n : learned_lower_rank(keys, n, root, leaves, (K)(U + 1));
+        r0 = model_lower_rank(keys, n, root, leaves, L);
+        r1 = (U == ~K(0)) ? n : model_lower_rank(keys, n, root, leaves, (K)(U + 1));
     }
     first[q] = (uint32_t)r0;
     count[q] = r1 > r0 ? r1 - r0 : 0;
+}
+
+template <typename K, bool AOS>
+void launch_range_count(const idx_index *h, const void *lo, const void *hi, uint64_t m, uint32_t *first,
+                        uint64_t *count, hipStream_t s) {
+    const LearnedModel *M = h->learned;
+    hipLaunchKernelGGL((k_range_count_learned<K, AOS>), dim3(grid_for(m, 256)), dim3(256), 0, s, make_load<K, AOS>(h),
+                       h->n, M->root, M->leaves, (const K *)lo, (const K *)hi, m, first, count);
 }
 }  // namespace
 
 int range_count_learned(idx_index *h, const void *lo, const void *hi, uint64_t m, uint32_t *first, uint64_t *count,
                         hipStream_t s) {
-    const LearnedModel *M = h->learned;
-    const uint32_t blocks = grid_for(m, 256);
-    if (h->u64)
-        hipLaunchKernelGGL(k_range_count_learned<uint64_t>, dim3(blocks), dim3(256), 0, s, (const uint64_t *)h->keys,
-                           h->n, M->root, M->leaves, (const uint64_t *)lo, (const uint64_t *)hi, m, first, count);
-    else
-        hipLaunchKernelGGL(k_range_count_learned<uint32_t>, dim3(blocks), dim3(256), 0, s, (const uint32_t *)h->keys,
-                           h->n, M->root, M->leaves, (const uint32_t *)lo, (const uint32_t *)hi, m, first, count);
+    if (h->u64) {
+        if (h->aos) launch_range_count<uint64_t, true>(h, lo, hi, m, first, count, s);
+        else launch_range_count<uint64_t, false>(h, lo, hi, m, first, count, s);
+    } else {
+        if (h->aos) launch_range_count<uint32_t, true>(h, lo, hi, m, first, count, s);
+        else launch_range_count<uint32_t, false>(h, lo, hi, m, first, count, s);
+    }
     IDX_LAUNCH_CHECK();
     return IDX_OK;
 }
@@ -567,18 +665,20 @@ __global__ void k_set_leaf_params(LeafRec *leaves, const float *ab, uint32_t L) 
     leaves[l].b1 = ab[2 * l + 1];
 }
 
-template <typename K>
+template <typename K, bool AOS>
 int eval_t(idx_index *h, uint32_t mode, const float *root_ab, uint32_t L, const float *leaf_ab, double *root_acc_h,
            double *leaf_acc_d, hipStream_t s) {
     const uint64_t n = h->n;
-    const K *keys = (const K *)h->keys;
-    const size_t leaf_b = (size_t)L * sizeof(LeafRec);
-    char *tmp = (char *)h->alloc.get(512 + leaf_b + (size_t)L * 4, s);
+    const Load<K, AOS> keys = make_load<K, AOS>(h);
+    auto up256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t leaf_b = up256((size_t)L * sizeof(LeafRec));
+    char *tmp = (char *)h->alloc.get(512 + leaf_b + layout_scratch_bytes(L), s);
     if (!tmp) return IDX_ERR_NOMEM;
     RootRec *d_root = (RootRec *)tmp;
     double *racc = (double *)(tmp + 256);
     LeafRec *leaves = (LeafRec *)(tmp + 512);
-    uint32_t *count = (uint32_t *)(tmp + 512 + leaf_b);
+    unsigned long long *count = (unsigned long long *)(tmp + 512 + leaf_b);
+    uint64_t *partial = (uint64_t *)((char *)count + up256(((size_t)L + 1) * 8));
     int rc = IDX_OK;
     do {
         RootRec R{root_ab[0], root_ab[1], mode, L};
@@ -586,16 +686,16 @@ int eval_t(idx_index *h, uint32_t mode, const float *root_ab, uint32_t L, const 
         hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, racc, (uint64_t)NACC);
         const uint32_t rblocks = grid_for((n + LT * 8 - 1) / (LT * 8), 1) > 2048 ? 2048u
                                                                                 : grid_for((n + LT * 8 - 1) / (LT * 8), 1);
-        hipLaunchKernelGGL((k_root_accum<K>), dim3(rblocks), dim3(LT), 0, s, keys, n, d_root, racc);
+        hipLaunchKernelGGL((k_root_accum<K, AOS>), dim3(rblocks), dim3(LT), 0, s, keys, n, d_root, racc);
         if (leaf_ab && leaf_acc_d) {
             const uint32_t cblocks = grid_for((n + CHUNK - 1) / CHUNK, LT);
-            hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(L, 256)), dim3(256), 0, s, count, (uint64_t)L, 0u);
-            hipLaunchKernelGGL((k_leaf_count<K>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, count);
-            hipLaunchKernelGGL((k_leaf_layout<K>), dim3(1), dim3(1024), 0, s, keys, count, L, leaves);
+            rc = leaf_layout<K, AOS>(keys, n, d_root, L, count, partial, leaves, s);
+            if (rc != IDX_OK) break;
             hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((uint64_t)L * NACC, 256)), dim3(256), 0, s, leaf_acc_d,
                                (uint64_t)L * NACC);
             hipLaunchKernelGGL(k_set_leaf_params, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_ab, L);
-            hipLaunchKernelGGL((k_leaf_accum<K>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves, leaf_acc_d);
+            hipLaunchKernelGGL((k_leaf_accum<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
+                               leaf_acc_d);
         }
         if (hipGetLastError() != hipSuccess) { rc = IDX_ERR_HIP; break; }
         if (hipMemcpyAsync(root_acc_h, racc, NACC * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -608,11 +708,14 @@ int eval_t(idx_index *h, uint32_t mode, const float *root_ab, uint32_t L, const 
 
 int learn_eval(idx_index *h, uint32_t mode, const float *root_ab, uint32_t L, const float *leaf_ab, double *root_acc,
                double *leaf_acc, hipStream_t s) {
-    if (h->layout != IDX_BS || h->aos || h->n == 0) return IDX_ERR_ARG;
+    if (h->layout != IDX_BS || h->n == 0) return IDX_ERR_ARG;
     if (mode != IDX_FEATURE_LINEAR && mode != IDX_FEATURE_LOG) return IDX_ERR_ARG;
     if (L == 0 || L > (1u << 22) || !root_ab || !root_acc) return IDX_ERR_ARG;
-    return h->u64 ? eval_t<uint64_t>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s)
-                  : eval_t<uint32_t>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s);
+    if (h->u64)
+        return h->aos ? eval_t<uint64_t, true>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s)
+                      : eval_t<uint64_t, false>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s);
+    return h->aos ? eval_t<uint32_t, true>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s)
+                  : eval_t<uint32_t, false>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s);
 }
 
 }  // namespace idx

@@ -55,18 +55,21 @@ def queries(keys, m, seed):
     return q.astype(dt)
 
 
+@pytest.mark.parametrize("aos", [False, True, "padded"])
 @pytest.mark.parametrize("kind", ["uniform32", "uniform64", "lognormal", "dup"])
 @pytest.mark.parametrize("leaves,epochs,feature", [(1, 1, AUTO), (7, 2, LINEAR), (4096, 2, AUTO), (4096, 1, LOG),
                                                    (65536, 2, AUTO)])
-def test_learned_lookup_parity(kind, leaves, epochs, feature):
+def test_learned_lookup_parity(kind, leaves, epochs, feature, aos):
+    """The model on the sorted array in each storage (SoA, AoS, line-padded
+    AoS): points, ranges and the answers without the model equal the oracle's."""
     n = 50021
     keys, rows = make(kind, n, seed=leaves + epochs)
     sk, sr = oracle.stable_sort(keys, rows)
     q = queries(keys, 20011, seed=7)
     want = oracle.point(sk, sr, q, nthreads=4)
     bits = keys.dtype.itemsize * 8
-    say(f"learned {kind} leaves={leaves} epochs={epochs} feature={feature}")
-    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+    say(f"learned {kind} leaves={leaves} epochs={epochs} feature={feature} aos={aos}")
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs", aos=aos) as ix:
         st = ix.learn(leaves, epochs, feature)
         assert st["leaves"] == leaves and st["mean_window"] >= 1 and st["max_window"] <= n + 1
         for R in (1, 4, 8):
@@ -95,9 +98,32 @@ def test_learned_tiny_sets():
         keys, rows = make("uniform64", n, seed=n)
         sk, sr = oracle.stable_sort(keys, rows)
         q = queries(keys, 64, seed=n)
-        with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
-            ix.learn(16, 2, AUTO)
-            assert np.array_equal(rows_host(ix.point(to_dev(q))), oracle.point(sk, sr, q))
+        for aos in (False, "padded"):
+            with idx.Index(to_dev(keys), to_dev(rows), layout="bs", aos=aos) as ix:
+                ix.learn(16, 2, AUTO)
+                assert np.array_equal(rows_host(ix.point(to_dev(q))), oracle.point(sk, sr, q))
+
+
+@pytest.mark.parametrize("aos", [True, "padded"])
+def test_learned_aos_same_model_as_soa(aos):
+    """Training reads the keys through the layout's accessor: the model on an
+    AoS copy of the sorted array is the SoA model up to the order of FP64
+    atomic additions (same feature, same weights to FP32 rounding, the
+    oracle's leaf partition under its own root)."""
+    n = 1 << 17
+    keys, rows = make("lognormal", n, seed=4)
+    sk, _ = oracle.stable_sort(keys, rows)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as a, \
+            idx.Index(to_dev(keys), to_dev(rows), layout="bs", aos=aos) as b:
+        sa, sb = a.learn(2048, 2), b.learn(2048, 2)
+        assert sa["feature"] == sb["feature"]
+        assert sb["root_a1"] == pytest.approx(sa["root_a1"], rel=1e-5)
+        assert sb["mean_window"] == pytest.approx(sa["mean_window"], rel=1e-2)
+        tb = b.learn_export().cpu().numpy().view(np.uint8).reshape(2048, 32)
+        leaf, _ = oracle.assign_leaves(sk, sb["feature"], sb["root_a0"], sb["root_a1"], 2048)
+        _, _, base, size = oracle.leaf_frame(sk, leaf, 2048)
+        assert np.array_equal(tb[:, 8:12].copy().view(np.uint32).ravel(), base.astype(np.uint32))
+        assert np.array_equal(tb[:, 12:16].copy().view(np.uint32).ravel(), size.astype(np.uint32))
 
 
 def test_learn_rejects_other_layouts():
