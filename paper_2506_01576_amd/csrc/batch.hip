@@ -23,7 +23,9 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "access.hpp"
 #include "learned_model.hpp"
+#include "range_scan.hpp"
 
 namespace idx {
 namespace {
@@ -277,6 +279,9 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
             // wave below; an Eytzinger range is scanned by its own lane
             const uint32_t *run_rows = nullptr;
             uint64_t run_first = 0, run_out = 0, run_len = 0;
+            bool paused = false;
+            ScanState st{};
+            uint64_t scan_o = 0, scan_cnt = 0;
             if (live && kind[p] == Q_RANGE) {
                 const uint64_t o = offs[p], cnt = offs[p + 1] - o;
                 const Desc d = descs[ii];
@@ -286,29 +291,39 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
                     run_out = o;
                     run_len = cnt;
                 } else if (cnt > 0) {
-                    const Geo &G = geos[ii];
-                    const K *keys = (const K *)d.keys;
-                    const uint64_t base = d.form == F_EBS ? 1 : 0;
-                    const K L = lo[p], U = hi[p];
-                    const uint64_t r0 = first[p], n = d.n;
-                    const uint32_t g = G.g, kf = G.k;
-                    uint64_t c = 0;
-                    uint32_t lvl = 0;
-                    while (c * g < n) {
-                        const uint64_t i = c * g;
-                        const uint64_t nv = (n - i) < g ? (n - i) : g;
-                        uint32_t j = 0;
-                        for (uint32_t e = 0; e < nv; ++e) j += keys[base + i + e] < L ? 1u : 0u;
-                        const uint64_t level_end = G.start[lvl + 1] < n ? G.start[lvl + 1] : n;
-                        for (uint64_t t = i + j; t < level_end; ++t) {
-                            if (keys[base + t] > U) break;
-                            const uint64_t dd = slot_rank(G, t) - r0;  // position in key order
-                            if (dd < cnt) rows_out[o + dd] = d.rows[base + t];
-                        }
-                        c = c * kf + 1 + j;
-                        ++lvl;
+                    Load<K, false> Ld{};
+                    Ld.k = (const K *)d.keys;
+                    Ld.r = d.rows;
+                    Ld.node = 1;
+                    paused = eyt_scan_lane(Ld, geos[ii], d.form == F_EBS ? 1 : 0, lo[p], hi[p], (uint64_t)first[p],
+                                           cnt, rows_out + o, st);
+                    if (paused) {
+                        scan_o = o;
+                        scan_cnt = cnt;
                     }
                 }
+            }
+            // paused Eytzinger scans continue with the whole wave, one at a time
+            uint64_t pend = __ballot(paused);
+            while (pend) {
+                const int src = __builtin_ctzll(pend);
+                pend &= pend - 1;
+                const uint32_t wi = (uint32_t)__shfl((int)ii, src, kWave);
+                const uint64_t wp = (uint64_t)__shfl((long long)p, src, kWave);
+                ScanState w;
+                w.c = (uint64_t)__shfl((long long)st.c, src, kWave);
+                w.t = (uint64_t)__shfl((long long)st.t, src, kWave);
+                w.lvl = (uint32_t)__shfl((int)st.lvl, src, kWave);
+                w.j = (uint32_t)__shfl((int)st.j, src, kWave);
+                const uint64_t wo = (uint64_t)__shfl((long long)scan_o, src, kWave);
+                const uint64_t wcnt = (uint64_t)__shfl((long long)scan_cnt, src, kWave);
+                const Desc dw = descs[wi];
+                Load<K, false> Lw{};
+                Lw.k = (const K *)dw.keys;
+                Lw.r = dw.rows;
+                Lw.node = 1;
+                eyt_scan_wave(Lw, geos[wi], dw.form == F_EBS ? 1 : 0, lo[wp], hi[wp], (uint64_t)first[wp], wcnt,
+                              rows_out + wo, w);
             }
             // wave-cooperative copies of the sorted-array runs, one lane's run at a time
             uint64_t pending = __ballot(run_len > 0);

@@ -16,6 +16,7 @@
 // EBS is handled as the k = 2 level-order tree shifted by its empty slot.
 #include "internal.hpp"
 #include "access.hpp"
+#include "range_scan.hpp"
 
 namespace idx {
 namespace {
@@ -88,35 +89,39 @@ __global__ __launch_bounds__(256) void k_range_fill_bs(RangeArgs<K, AOS> a) {
     for (uint64_t e = sub; e < cnt; e += GL) a.out[o + e] = a.L.row(r0 + e);
 }
 
-// EBS/EKS: single-lane level scan along the lower-bound path of lo.
+// EBS/EKS: level scan along the lower-bound path of lo, one lane per range,
+// switching to the whole wave for ranges with many matches per level
+// (hybrid coalesced scanning, range_scan.hpp).
 template <typename K, bool AOS>
 __global__ __launch_bounds__(256) void k_range_fill_eyt(RangeArgs<K, AOS> a) {
     const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.m) return;
-    const uint64_t o = a.offsets[q];
-    const uint64_t cnt = a.offsets[q + 1] - o;
-    if (cnt == 0) return;
-    const K L = a.lo[q], U = a.hi[q];
-    const uint64_t r0 = a.first_rank[q];
-    const uint64_t n = a.G.n;
-    const uint32_t g = a.G.g, kf = a.G.k;
-    uint64_t c = 0;
-    uint32_t lvl = 0;
-    while (c * g < n) {
-        const uint64_t i = c * g;
-        const uint64_t nv = (n - i) < g ? (n - i) : g;
-        uint32_t j = 0;
-        for (uint32_t e = 0; e < nv; ++e) j += a.L.key(a.off + i + e) < L ? 1u : 0u;
-        const uint64_t level_end = a.G.start[lvl + 1] < n ? a.G.start[lvl + 1] : n;
-        for (uint64_t t = i + j; t < level_end; ++t) {
-            const uint64_t s = a.off + t;
-            const K kk = a.L.key(s);
-            if (kk > U) break;
-            const uint64_t d = slot_rank(a.G, t) - r0;  // position in key order
-            if (d < cnt) a.out[o + d] = a.L.row(s);
-        }
-        c = c * kf + 1 + j;
-        ++lvl;
+    uint64_t o = 0, cnt = 0, r0 = 0;
+    K L = 0, U = 0;
+    if (q < a.m) {
+        o = a.offsets[q];
+        cnt = a.offsets[q + 1] - o;
+        L = a.lo[q];
+        U = a.hi[q];
+        r0 = a.first_rank[q];
+    }
+    ScanState st{};
+    const bool paused = cnt > 0 && eyt_scan_lane(a.L, a.G, a.off, L, U, r0, cnt, a.out + o, st);
+    // every lane of the wave reaches this point: continue paused scans together
+    uint64_t pend = __ballot(paused);
+    while (pend) {
+        const int src = __builtin_ctzll(pend);
+        pend &= pend - 1;
+        ScanState w;
+        w.c = (uint64_t)__shfl((long long)st.c, src, kWave);
+        w.t = (uint64_t)__shfl((long long)st.t, src, kWave);
+        w.lvl = (uint32_t)__shfl((int)st.lvl, src, kWave);
+        w.j = (uint32_t)__shfl((int)st.j, src, kWave);
+        const K wl = (K)__shfl((long long)(uint64_t)L, src, kWave);
+        const K wu = (K)__shfl((long long)(uint64_t)U, src, kWave);
+        const uint64_t wr0 = (uint64_t)__shfl((long long)r0, src, kWave);
+        const uint64_t wcnt = (uint64_t)__shfl((long long)cnt, src, kWave);
+        const uint64_t wo = (uint64_t)__shfl((long long)o, src, kWave);
+        eyt_scan_wave(a.L, a.G, a.off, wl, wu, wr0, wcnt, a.out + wo, w);
     }
 }
 

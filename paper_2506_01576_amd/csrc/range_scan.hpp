@@ -1,0 +1,115 @@
+// Level scan of a range lookup on the Eytzinger layouts (Section 5) with the
+// hybrid coalesced scanning of Section 5.1, shared by the per-index range
+// kernel (range.hip) and the batched mixed stream (batch.hip).
+//
+// The matches of [lo, hi] on one level of the level-order tree are
+// consecutive and start where the lower-bound search path of lo enters the
+// level; every match at level-order slot t goes to position
+// slot_rank(t) - (rank of lo's lower bound) of the range's output, which
+// puts the row IDs in key order.
+//
+// Each lane first scans its own range alone.  When it meets kWave matches on
+// one level it pauses (by the property noted in Section 5.1, every deeper
+// level then holds more matches still), and once every lane of the wave has
+// finished or paused, the wave takes over the paused scans one at a time:
+// all 64 lanes read 64 consecutive entries of a level per step, and the
+// lower-bound path continues with one pivot per lane and a ballot.
+#pragma once
+
+#include "internal.hpp"
+#include "access.hpp"
+
+namespace idx {
+
+// Sorted rank of level-order slot t known to lie on level l (t < n).
+__host__ __device__ inline uint64_t slot_rank_on(const Geo &G, uint64_t t, uint32_t l) {
+    const uint64_t bottom_start = G.start[G.m];
+    if (t >= bottom_start) {
+        const uint64_t i = t - bottom_start;
+        return i + div_g(G, i);
+    }
+    const uint64_t i = t - G.start[l];
+    const uint64_t p = (G.start[G.m - l - 1] + 1) * (1 + i + div_g(G, i)) - 1;
+    const uint64_t skip = G.g * (p + 1);
+    return p + (skip < G.b ? skip : G.b);
+}
+
+// Where a paused scan continues: node c on level lvl (its pivot count below
+// lo is j) and the next slot t of that level.
+struct ScanState {
+    uint64_t c;
+    uint64_t t;
+    uint32_t lvl;
+    uint32_t j;
+};
+
+// Single-lane level scan of [lo, hi] (first rank r0, cnt matches, output at
+// out).  Keys and row IDs of level-order slot t are at layout slot off + t.
+// Returns true when it paused (state in st) with kWave matches on a level.
+template <typename K, bool AOS>
+__device__ __forceinline__ bool eyt_scan_lane(const Load<K, AOS> &L, const Geo &G, uint64_t off, K lo, K hi,
+                                              uint64_t r0, uint64_t cnt, uint32_t *__restrict__ out, ScanState &st) {
+    const uint64_t n = G.n;
+    const uint32_t g = G.g, kf = G.k;
+    uint64_t c = 0;
+    uint32_t lvl = 0;
+    while (c * g < n) {
+        const uint64_t i = c * g;
+        const uint64_t nv = (n - i) < g ? (n - i) : g;
+        uint32_t j = 0;
+        for (uint32_t e = 0; e < nv; ++e) j += L.key(off + i + e) < lo ? 1u : 0u;
+        const uint64_t level_end = G.start[lvl + 1] < n ? G.start[lvl + 1] : n;
+        uint32_t seen = 0;
+        for (uint64_t t = i + j; t < level_end; ++t) {
+            if (L.key(off + t) > hi) break;
+            const uint64_t d = slot_rank_on(G, t, lvl) - r0;  // position in key order
+            if (d < cnt) out[d] = L.row(off + t);
+            if (++seen == (uint32_t)kWave) {
+                st = ScanState{c, t + 1, lvl, j};
+                return true;
+            }
+        }
+        c = c * kf + 1 + j;
+        ++lvl;
+    }
+    return false;
+}
+
+// The whole wave continues one paused scan (every lane passes the same
+// arguments).  Pivots per node g <= kWave.
+template <typename K, bool AOS>
+__device__ __forceinline__ void eyt_scan_wave(const Load<K, AOS> &L, const Geo &G, uint64_t off, K lo, K hi,
+                                              uint64_t r0, uint64_t cnt, uint32_t *__restrict__ out, ScanState st) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint64_t n = G.n;
+    const uint32_t g = G.g, kf = G.k;
+    uint64_t c = st.c, t = st.t;
+    uint32_t lvl = st.lvl, j = st.j;
+    bool resume = true;
+    while (c * g < n) {
+        const uint64_t i = c * g;
+        if (!resume) {
+            const uint64_t nv = (n - i) < g ? (n - i) : g;
+            const bool below = lane < nv && L.key(off + i + lane) < lo;
+            j = (uint32_t)__popcll(__ballot(below));
+            t = i + j;
+        }
+        resume = false;
+        const uint64_t level_end = G.start[lvl + 1] < n ? G.start[lvl + 1] : n;
+        for (uint64_t b = t; b < level_end; b += kWave) {
+            const uint64_t s = b + lane;
+            bool match = false;
+            if (s < level_end && L.key(off + s) <= hi) {
+                match = true;
+                const uint64_t d = slot_rank_on(G, s, lvl) - r0;
+                if (d < cnt) out[d] = L.row(off + s);
+            }
+            // keys ascend along a level: done once a lane saw a larger key or the level end
+            if (__ballot(!match) != 0) break;
+        }
+        c = c * kf + 1 + j;
+        ++lvl;
+    }
+}
+
+}  // namespace idx

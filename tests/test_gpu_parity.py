@@ -205,6 +205,10 @@ def check_range(ix, keys, rows, bits, seed, m=5003):
     top = int(np.iinfo(dt).max)
     if len(keys):
         L, U, _ = gen.ranges(seed, keys, m, 1, 64)
+        # wide ranges: many matches per level, where each lane hands its scan to the whole wave
+        if len(keys) > 65:
+            Lw, Uw, _ = gen.ranges(seed + 1, keys, 301, 65, min(len(keys), 8192))
+            L, U = np.concatenate([L, Lw]), np.concatenate([U, Uw])
     else:
         L = np.zeros(m, dtype=dt)
         U = np.zeros(m, dtype=dt)
