@@ -405,14 +405,24 @@ def main():
         e.record(stream)
         return e
 
-    def time_point(ix, reps=3, check=False):
+    flush_buf = None
+
+    def time_point(ix, reps=3, check=False, cold=False):
+        """Median event time of one point launch over the batch; cold: each
+        timed launch follows a 1 GiB write that evicts L2 and the 256 MiB
+        Infinity Cache."""
+        nonlocal flush_buf
         ix.point(q, out)
         ok = None
         if check:
             torch.cuda.synchronize()
             ok = bool(torch.equal(out, expect))
+        if cold and flush_buf is None:
+            flush_buf = torch.empty(1 << 28, dtype=torch.int32, device=dev)
         ts = []
-        for _ in range(reps):
+        for rep in range(reps):
+            if cold:
+                flush_buf.fill_(rep)
             a = ev()
             ix.point(q, out)
             b = ev()
@@ -447,8 +457,9 @@ def main():
         ix = base if (lay == "bs" and not aos) else base.relayout(lay, k, aos)
         ix.set_params(**params)
         ms, ok = time_point(ix, reps=3, check=True)
+        ms_cold, _ = time_point(ix, reps=3, cold=True)
         best_by_layout[layout] = {"layout": lay, "k": k, "aos": aos, "params": ix.params(), "ms": round(ms, 4),
-                                  "lookups_per_s": m / ms * 1e3, "bit_exact": ok}
+                                  "ms_cold": round(ms_cold, 4), "lookups_per_s": m / ms * 1e3, "bit_exact": ok}
         log(f"tuned {lay} k={k} aos={aos} {params}: {ms:.3f} ms exact={ok}")
         if ix is not base:
             ix.close()
@@ -480,6 +491,8 @@ def main():
             rec = {"layout": "learned", "k": 1, "aos": la, "params": dict(arr.params(), leaves=L), "ms": round(ms, 4),
                    "lookups_per_s": m / ms * 1e3, "bit_exact": ok, "mean_window": st["mean_window"],
                    "max_window": st["max_window"]}
+            if not args.sweep:
+                rec["ms_cold"] = round(time_point(arr, reps=3, cold=True)[0], 4)
             if args.sweep:
                 sweep.append(rec)
             log(f"learned leaves={L} R={r} reorder={ro} aos={la}: {ms:.3f} ms exact={ok} "
@@ -671,6 +684,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "forms": {name: {"lookups_per_s": point_rates[name], "ms": round(mean[f"point_{name}"], 4),
+                         "ms_isolated_warm": rec.get("ms"), "ms_isolated_cold": rec.get("ms_cold"),
                          "layout": rec["layout"], "k": rec["k"], "aos": rec["aos"], "params": rec["params"],
                          **({"mean_window": rec["mean_window"], "max_window": rec["max_window"]}
                             if "mean_window" in rec else {})} for name, rec in forms},
