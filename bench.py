@@ -208,6 +208,91 @@ def run_batched(args, idx, gen, np, torch, dev, log, table):
     return res
 
 
+def run_skewed(args, idx, gen, np, torch, dev, log):
+    """The learned-model configuration: n = 2^log2n_skew unique uint64 keys from
+    the 64-cluster lognormal mixture, 2^27 lookups: Zipf(1.1)-popular hits
+    plus 10% uniform misses.  The learned form with 4096 leaves (the
+    configuration's model) and with the tuned leaf count, against EKS with
+    16 keys per node (k = 17) and k = 16; all must agree, hits must return
+    the generator's rowids."""
+    from paper_2506_01576_amd import autotune
+
+    n, m = 1 << args.log2n_skew, 1 << 27
+    seed = gen.BASE_SEED + 3
+    t0 = time.time()
+    kh, rh = gen.lognormal_keys(seed, n)
+    qh, eh = gen.zipf_queries(seed, 1.1, n, m, 0.1, 64, 63, keys=kh)
+    keys = torch.from_numpy(kh.view(np.int64)).to(dev)
+    rows = torch.from_numpy(rh.view(np.int32)).to(dev)
+    q = torch.from_numpy(qh.view(np.int64)).to(dev)
+    expect = torch.from_numpy(eh.view(np.int32)).to(dev)
+    del kh, rh, qh, eh
+    hit = expect != -1
+    out = torch.empty(m, dtype=torch.int32, device=dev)
+    log(f"skewed: {n} lognormal keys, {m} Zipf(1.1) lookups generated in {time.time() - t0:.1f}s")
+
+    def timed(ix, reps=3):
+        ix.point(q, out)
+        torch.cuda.synchronize()
+        res = out.clone()
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            ix.point(q, out)
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts)), res
+
+    forms, answers = {}, {}
+    base = idx.Index(keys, rows, layout="bs")
+    _, _, laos, lp = autotune.choose(1 << 26, 64, "learned")
+    for name, L, aos, params in (("learned_4096", 4096, False, {"per_lane": 8}),
+                                 ("learned_tuned", lp.get("leaves", 1 << 22), laos,
+                                  {"per_lane": lp.get("per_lane", 8)})):
+        arr = base if not aos else base.relayout("bs", 1, aos)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        st = arr.learn(L, 2)
+        b.record()
+        b.synchronize()
+        arr.set_params(model=0, **params)
+        ms, res = timed(arr)
+        forms[name] = {"leaves": L, "aos": aos, "ms": round(ms, 4), "lookups_per_s": m / ms * 1e3,
+                       "train_ms": round(a.elapsed_time(b), 3), "mean_window": st["mean_window"],
+                       "max_window": st["max_window"]}
+        answers[name] = res
+        if arr is not base:
+            arr.close()
+        else:
+            arr.unlearn()
+            arr.reset_params()
+    for name, k, params in (("eks_k17", 17, {"group": 1, "per_lane": 4, "lds_levels": 3, "persistent": 2,
+                                             "block": 1024}),
+                            ("eks_k16", 16, {})):
+        with base.relayout("eks", k) as e:
+            try:
+                e.set_params(**params)
+            except idx.IdxError:
+                e.reset_params()
+            ms, res = timed(e)
+            forms[name] = {"k": k, "params": e.params(), "ms": round(ms, 4), "lookups_per_s": m / ms * 1e3}
+            answers[name] = res
+    base.close()
+    ref = answers["eks_k17"]
+    agree = all(bool(torch.equal(v, ref)) for v in answers.values())
+    hits_exact = bool(torch.equal(ref[hit], expect[hit]))
+    best_l = min((v["ms"] for k2, v in forms.items() if k2.startswith("learned")))
+    best_e = min((v["ms"] for k2, v in forms.items() if k2.startswith("eks")))
+    log("skewed: " + ", ".join(f"{k2} {v['ms']:.3f} ms" for k2, v in forms.items()) + f"; agree={agree} hits={hits_exact}")
+    return {"n": n, "queries": m, "workload": "lognormal mixture keys, Zipf(1.1) hits + 10% uniform misses",
+            "forms": forms, "all_forms_agree": agree, "hits_equal_generator": hits_exact,
+            "learned_vs_eks": best_e / best_l}
+
+
 def run_combined(args, idx, gen, np, torch, dev, log):
     """Many learned indexes with a mixed stream: `combined_indexes` uint64
     indexes with n log-uniform in [2^16, 2^24], half with uniform keys and
@@ -354,6 +439,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="leave the many-index batched workload out")
     ap.add_argument("--batch-indexes", type=int, default=8192)
     ap.add_argument("--no-combined", action="store_true", help="leave the combined learned/mixed workload out")
+    ap.add_argument("--no-skewed", action="store_true", help="leave the lognormal / Zipf learned-vs-EKS workload out")
+    ap.add_argument("--log2n-skew", type=int, default=28, help="keys in the lognormal / Zipf workload (log2)")
     ap.add_argument("--combined-indexes", type=int, default=128,
                     help="indexes in the combined workload (1024 = the full configuration; the query count scales "
                          "with it, 2^26 at 1024)")
@@ -659,6 +746,11 @@ def main():
         batched = run_batched(args, idx, gen, np, torch, dev, log, table)
         if args.sweep:
             batched["class_sweep"] = table.get("batch")
+    skewed = None
+    if not args.no_skewed:
+        torch.cuda.empty_cache()
+        skewed = run_skewed(args, idx, gen, np, torch, dev, log)
+        torch.cuda.empty_cache()
     combined = None
     if not args.no_combined:
         torch.cuda.empty_cache()
@@ -694,6 +786,7 @@ def main():
         "random_access": probe,
         "batched": batched,
         "combined": combined,
+        "skewed": skewed,
         "sweep": [{kk: r[kk] for kk in ("layout", "k", "aos", "params", "ms", "lookups_per_s", "bit_exact")}
                   for r in sweep],
     }
