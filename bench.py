@@ -293,6 +293,136 @@ def run_skewed(args, idx, gen, np, torch, dev, log):
             "learned_vs_eks": best_e / best_l}
 
 
+def run_study(args, idx, gen, np, torch, dev, log):
+    """Skew and duplicates (Sections 8.9 and 8.11), n = 2^26 uint64 keys.
+    Skew: 2^27 lookups drawn Zipf(s) over the build keys (s = 0 is uniform)
+    and the uniform batch sorted ascending, through each form.  Duplicates:
+    2^24 keys, each distinct value replicated r times, and 2^24 equality
+    ranges [x, x] (every replica in key order, the paper's treatment of point
+    lookups on duplicated keys).  Every answer is checked against the
+    generator (skew) or the oracle on a sample (duplicates)."""
+    import oracle
+    from paper_2506_01576_amd import autotune
+
+    res = {"skew": {}, "duplicates": {}}
+    n, m = 1 << 26, 1 << 27
+    seed = gen.BASE_SEED + 1
+    kh, rh = gen.unique_keys(seed, n, 64, 63)
+    keys = torch.from_numpy(kh.view(np.int64)).to(dev)
+    rows = torch.from_numpy(rh.view(np.int32)).to(dev)
+    del kh, rh
+    base = idx.Index(keys, rows, layout="bs")
+    forms = {}
+    for layout in ("bs", "ebs", "eks"):
+        lay, k, aos, params = autotune.choose(n, 64, layout)
+        ix = base.relayout(lay, k, aos)
+        ix.set_params(**params)
+        forms[layout.upper() if layout != "eks" else f"EKS(k={k},single)"] = ix
+    g8 = base.relayout("eks", 9)
+    g8.set_params(group=8, per_lane=2)
+    forms["EKS(k=9,group8)"] = g8
+    v4 = base.relayout("eks", 9)
+    v4.set_params(group=4, per_lane=4)
+    forms["EKS(k=9,vgroup4)"] = v4
+    _, _, laos, lp = autotune.choose(n, 64, "learned")
+    ln = base.relayout("bs", 1, laos) if laos else base.relayout("bs", 1, False)
+    ln.learn(lp.get("leaves", 1 << 22), 2)
+    ln.set_params(model=0, per_lane=lp.get("per_lane", 8))
+    forms["LEARNED"] = ln
+    out = torch.empty(m, dtype=torch.int32, device=dev)
+
+    def timed(ix, q, reps=3):
+        ix.point(q, out)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            ix.point(q, out)
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    cases = [(f"zipf_{s_}", s_) for s_ in (0.0, 0.5, 1.0, 1.25, 1.5, 2.0)] + [("sorted", None)]
+    for name, s_ in cases:
+        if s_ is None or s_ == 0.0:
+            qh, eh = gen.point_queries(seed, n, m, 1.0, 64, 63)
+        else:
+            qh, eh = gen.zipf_queries(seed, s_, n, m, 0.0, 64, 63)
+        q = torch.from_numpy(qh.view(np.int64)).to(dev)
+        e = torch.from_numpy(eh.view(np.int32)).to(dev)
+        if s_ is None:
+            q, order = torch.sort(q)
+            e = e[order]
+        row = {"distinct_fraction": float(torch.unique(q).numel()) / m}
+        for fname, ix in forms.items():
+            ms = timed(ix, q)
+            ok = bool(torch.equal(out, e))
+            row[fname] = {"ms": round(ms, 4), "lookups_per_s": m / ms * 1e3, "exact": ok}
+        res["skew"][name] = row
+        log(f"study skew {name}: " + ", ".join(f"{f} {v['ms']:.2f}" for f, v in row.items() if isinstance(v, dict)))
+        del q, e
+    for ix in forms.values():
+        ix.close()
+    base.close()
+    del keys, rows
+    torch.cuda.empty_cache()
+
+    # duplicates: equality ranges over replicated keys
+    nd = 1 << 24
+    for r in (1, 4, 16, 64, 256):
+        md = min(1 << 24, (1 << 28) // r)  # at most 2^28 row IDs out
+        distinct = nd // r
+        vh, _ = gen.unique_keys(seed + r, distinct, 64, 63)
+        kh = np.repeat(vh, r)
+        rng = np.random.default_rng(r)
+        perm = rng.permutation(nd)
+        kh = kh[perm]
+        rh = perm.astype(np.uint32)
+        qh = vh[rng.integers(0, distinct, md)]
+        dk = torch.from_numpy(kh.view(np.int64)).to(dev)
+        dr = torch.from_numpy(rh.view(np.int32)).to(dev)
+        dq = torch.from_numpy(qh.view(np.int64)).to(dev)
+        sk, sr = oracle.stable_sort(kh, rh)
+        sample = rng.integers(0, md, 256)
+        wo, wrows = oracle.range_lookup(sk, sr, qh[sample], qh[sample], nthreads=8)
+        row = {}
+        with idx.Index(dk, dr, layout="bs") as b2:
+            hs = {"BS": b2, "EBS": b2.relayout("ebs", 2), "EKS(k=9,single)": b2.relayout("eks", 9),
+                  "EKS(k=17,single)": b2.relayout("eks", 17)}
+            lb = b2.relayout("bs", 1, False)
+            lb.learn(max(1, nd // 16), 2)
+            hs["LEARNED"] = lb
+            for fname, ix in hs.items():
+                ix.range(dq, dq, capacity=md * r)
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                off, rr = ix.range(dq, dq, capacity=md * r)
+                b.record()
+                b.synchronize()
+                ms = a.elapsed_time(b)
+                offh = off.cpu().numpy().view(np.uint64)
+                ok = bool(np.all(np.diff(offh) == r))
+                for j, s2 in enumerate(sample):
+                    got = rr[int(offh[s2]):int(offh[s2 + 1])].cpu().numpy().view(np.uint32)
+                    ok &= bool(np.array_equal(got, wrows[wo[j]:wo[j + 1]]))
+                row[fname] = {"ms": round(ms, 4), "lookups_per_s": md / ms * 1e3, "rowids_per_s": md * r / ms * 1e3,
+                              "exact": ok}
+                del off, rr
+            for fname, ix in hs.items():
+                if ix is not b2:
+                    ix.close()
+        res["duplicates"][f"r{r}"] = row
+        log(f"study dup r={r}: " + ", ".join(f"{f} {v['ms']:.2f}" for f, v in row.items()))
+        del dk, dr, dq
+        torch.cuda.empty_cache()
+    return res
+
+
 def run_combined(args, idx, gen, np, torch, dev, log):
     """Many learned indexes with a mixed stream: `combined_indexes` uint64
     indexes with n log-uniform in [2^16, 2^24], half with uniform keys and
@@ -440,6 +570,8 @@ def main():
     ap.add_argument("--batch-indexes", type=int, default=8192)
     ap.add_argument("--no-combined", action="store_true", help="leave the combined learned/mixed workload out")
     ap.add_argument("--no-skewed", action="store_true", help="leave the lognormal / Zipf learned-vs-EKS workload out")
+    ap.add_argument("--study", action="store_true",
+                    help="also run the skew (Zipf, sorted) and duplicate-key studies (a few minutes)")
     ap.add_argument("--log2n-skew", type=int, default=28, help="keys in the lognormal / Zipf workload (log2)")
     ap.add_argument("--combined-indexes", type=int, default=128,
                     help="indexes in the combined workload (1024 = the full configuration; the query count scales "
@@ -751,6 +883,10 @@ def main():
         torch.cuda.empty_cache()
         skewed = run_skewed(args, idx, gen, np, torch, dev, log)
         torch.cuda.empty_cache()
+    study = None
+    if args.study:
+        torch.cuda.empty_cache()
+        study = run_study(args, idx, gen, np, torch, dev, log)
     combined = None
     if not args.no_combined:
         torch.cuda.empty_cache()
@@ -787,6 +923,7 @@ def main():
         "batched": batched,
         "combined": combined,
         "skewed": skewed,
+        "study": study,
         "sweep": [{kk: r[kk] for kk in ("layout", "k", "aos", "params", "ms", "lookups_per_s", "bit_exact")}
                   for r in sweep],
     }
