@@ -423,6 +423,62 @@ def run_study(args, idx, gen, np, torch, dev, log):
     return res
 
 
+def run_update(args, idx, gen, np, torch, dev, log):
+    """The read-mostly update path (Section 8.5): an index of 2^26 uint64
+    keys takes a batch of 2^20 new pairs by merging (sort the batch, merge,
+    lay out) against rebuilding from all pairs; the merged and rebuilt
+    layouts must be identical.  Also the size and the time of saving and
+    loading the merged handle."""
+    n, m = 1 << 26, 1 << 20
+    seed = gen.BASE_SEED + 1
+    kh, rh = gen.unique_keys(seed, n + m, 64, 63)
+    keys = torch.from_numpy(kh[:n].view(np.int64)).to(dev)
+    rows = torch.from_numpy(rh[:n].view(np.int32)).to(dev)
+    nk = torch.from_numpy(kh[n:].view(np.int64)).to(dev)
+    nr = torch.from_numpy(rh[n:].view(np.int32)).to(dev)
+    allk = torch.from_numpy(kh.view(np.int64)).to(dev)
+    allr = torch.from_numpy(rh.view(np.int32)).to(dev)
+    del kh, rh
+    res = {"n": n, "new": m}
+
+    def wall(fn, reps=3):
+        fn().close()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            h = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+            h.close()
+        return float(np.median(ts))
+
+    with idx.Index(keys, rows, layout="bs") as old:
+        for layout, k in (("bs", 1), ("eks", 9)):
+            ms_merge = wall(lambda: old.merge(nk, nr, layout, k))
+            ms_build = wall(lambda: idx.Index(allk, allr, layout=layout, k=k))
+            with old.merge(nk, nr, layout, k) as a, idx.Index(allk, allr, layout=layout, k=k) as b:
+                ak, ar = a.export()
+                bk, br = b.export()
+                same = bool(torch.equal(ak, bk) and torch.equal(ar, br))
+                t0 = time.perf_counter()
+                blob = a.save()
+                ms_save = (time.perf_counter() - t0) * 1e3
+                t0 = time.perf_counter()
+                c = idx.Index.load(blob)
+                torch.cuda.synchronize()
+                ms_load = (time.perf_counter() - t0) * 1e3
+                ck, cr = c.export()
+                same_loaded = bool(torch.equal(ck, ak) and torch.equal(cr, ar))
+                c.close()
+            res[layout] = {"merge_ms": round(ms_merge, 3), "rebuild_ms": round(ms_build, 3),
+                           "merge_equals_rebuild": same, "blob_bytes": len(blob), "save_ms": round(ms_save, 1),
+                           "load_ms": round(ms_load, 1), "load_equals": same_loaded}
+            log(f"update {layout}: merge {ms_merge:.2f} ms, rebuild {ms_build:.2f} ms, equal={same}; "
+                f"save {ms_save:.0f} ms load {ms_load:.0f} ms ({len(blob) >> 20} MiB)")
+    return res
+
+
 def run_combined(args, idx, gen, np, torch, dev, log):
     """Many learned indexes with a mixed stream: `combined_indexes` uint64
     indexes with n log-uniform in [2^16, 2^24], half with uniform keys and
@@ -570,6 +626,7 @@ def main():
     ap.add_argument("--batch-indexes", type=int, default=8192)
     ap.add_argument("--no-combined", action="store_true", help="leave the combined learned/mixed workload out")
     ap.add_argument("--no-skewed", action="store_true", help="leave the lognormal / Zipf learned-vs-EKS workload out")
+    ap.add_argument("--no-update", action="store_true", help="leave the merge / save / load measurement out")
     ap.add_argument("--study", action="store_true",
                     help="also run the skew (Zipf, sorted) and duplicate-key studies (a few minutes)")
     ap.add_argument("--log2n-skew", type=int, default=28, help="keys in the lognormal / Zipf workload (log2)")
@@ -883,6 +940,10 @@ def main():
         torch.cuda.empty_cache()
         skewed = run_skewed(args, idx, gen, np, torch, dev, log)
         torch.cuda.empty_cache()
+    update = None
+    if not args.no_update:
+        torch.cuda.empty_cache()
+        update = run_update(args, idx, gen, np, torch, dev, log)
     study = None
     if args.study:
         torch.cuda.empty_cache()
@@ -924,6 +985,7 @@ def main():
         "combined": combined,
         "skewed": skewed,
         "study": study,
+        "update": update,
         "sweep": [{kk: r[kk] for kk in ("layout", "k", "aos", "params", "ms", "lookups_per_s", "bit_exact")}
                   for r in sweep],
     }

@@ -134,6 +134,38 @@ int idx_relayout(idx_handle src, int layout, uint32_t k, uint32_t flags, const i
                  idx_stream stream, idx_handle *out);
 
 /*
+ * idx_merge -- the read-mostly update path (Section 8.5 rebuilds for a batch
+ * of updates): a new index over src's pairs plus m new (key, rowid) pairs,
+ * laid out as (layout, k, flags) exactly like idx_build.  Only the new pairs
+ * are sorted; they are merged into src's sorted array, src's pairs first on
+ * equal keys, which is the index idx_build gives for src's pairs followed by
+ * the new ones.
+ *
+ *   src     an IDX_BS index with SoA layout (IDX_ERR_ARG otherwise); unchanged
+ *   keys, rowids   m new pairs (device), key width as in flags
+ * Synchronises `stream` once.  Errors as idx_build (IDX_ERR_RESERVED_ROWID
+ * for a new rowid equal to IDX_MISS).
+ */
+int idx_merge(idx_handle src, const void *keys, const uint32_t *rowids, uint64_t m, int layout, uint32_t k,
+              uint32_t flags, const idx_allocator *alloc, idx_stream stream, idx_handle *out);
+
+/*
+ * idx_save -- write the handle (its layout buffers, key order facts and any
+ * learned model) to one host byte blob.  *size receives the bytes needed;
+ * blob = NULL only asks for the size.  IDX_ERR_CAPACITY when capacity is
+ * smaller.  The format belongs to this library build: load it with the same
+ * build.  Synchronises `stream`.
+ */
+int idx_save(idx_handle h, void *blob, uint64_t capacity, uint64_t *size, idx_stream stream);
+
+/*
+ * idx_load -- a new handle from a blob written by idx_save (host memory of
+ * `size` bytes).  Lookup parameters start at their defaults.  IDX_ERR_ARG for
+ * bytes that are not such a blob (marker, sizes).  Synchronises `stream`.
+ */
+int idx_load(const void *blob, uint64_t size, const idx_allocator *alloc, idx_stream stream, idx_handle *out);
+
+/*
  * idx_point -- batched point lookups (Section 1; search procedures of
  * Sections 3 and 6.2).
  *

@@ -119,6 +119,9 @@ SIGNATURES = {
     "idx_batch_create": (_I, [ctypes.POINTER(_P), _U32, _P, ctypes.POINTER(_P)]),
     "idx_batch_point": (_I, [_P, _P, _P, _P, _U32, _P]),
     "idx_batch_destroy": (_I, [_P]),
+    "idx_merge": (_I, [_P, _P, _P, _U64, _I, _U32, _U32, ctypes.POINTER(idx_allocator), _P, ctypes.POINTER(_P)]),
+    "idx_save": (_I, [_P, _P, _U64, ctypes.POINTER(_U64), _P]),
+    "idx_load": (_I, [_P, _U64, ctypes.POINTER(idx_allocator), _P, ctypes.POINTER(_P)]),
     "idx_batch_mixed": (_I, [_P, _U64, _P, _P, _P, _P, _P, _P, _P, _U64, ctypes.POINTER(_U64), _P]),
     "idx_learn_batch": (_I, [ctypes.POINTER(_P), _U32, ctypes.POINTER(_U32), _U32, _U32, _P]),
     "idx_learn": (_I, [_P, _U32, _U32, _U32, _P]),
@@ -230,6 +233,45 @@ class Index:
         h = ctypes.c_void_p()
         _check(lib().idx_relayout(self._h, lay, kk, flags, None, _stream(stream), ctypes.byref(h)), "idx_relayout")
         return Index._wrap(h, self.n, kk, layout, self.key_bits, self.key_dtype)
+
+    def merge(self, keys: torch.Tensor, rowids: torch.Tensor, layout: str = "bs", k: int = 9,
+              aos: bool | str = False, stream=None) -> "Index":
+        """A new index over this (BS, SoA) index's pairs plus (keys, rowids),
+        laid out as asked (idx_merge); this index is unchanged."""
+        _dev(keys, "keys")
+        _dev(rowids, "rowids")
+        if len(keys) != len(rowids):
+            raise ValueError("keys and rowids differ in length")
+        lay = LAYOUTS[layout]
+        kk = {IDX_BS: 1, IDX_EBS: 2, IDX_EKS: k}[lay]
+        flags = (IDX_KEY_U64 if self.key_bits == 64 else IDX_KEY_U32) | _aos_flags(aos)
+        h = ctypes.c_void_p()
+        _check(lib().idx_merge(self._h, keys.data_ptr() if len(keys) else None,
+                               rowids.data_ptr() if len(keys) else None, len(keys), lay, kk, flags, None,
+                               _stream(stream), ctypes.byref(h)), "idx_merge")
+        return Index._wrap(h, self.n + len(keys), kk, layout, self.key_bits, self.key_dtype)
+
+    def save(self, stream=None) -> bytes:
+        """The handle as a host byte blob (idx_save)."""
+        size = ctypes.c_uint64(0)
+        _check(lib().idx_save(self._h, None, 0, ctypes.byref(size), _stream(stream)), "idx_save(size)")
+        buf = ctypes.create_string_buffer(size.value)
+        _check(lib().idx_save(self._h, buf, size.value, ctypes.byref(size), _stream(stream)), "idx_save")
+        return buf.raw
+
+    @classmethod
+    def load(cls, blob: bytes, stream=None) -> "Index":
+        """A handle from a blob written by save() (idx_load)."""
+        h = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(lib().idx_load(buf, len(blob), None, _stream(stream), ctypes.byref(h)), "idx_load")
+        ix = cls._wrap(h, 0, 1, "bs", 32, torch.int32)
+        info = ix.info()
+        ix.n, ix.k = info["n"], info["k"]
+        ix.layout = {v: name for name, v in LAYOUTS.items()}[info["layout"]]
+        ix.key_bits = 64 if info["flags"] & IDX_KEY_U64 else 32
+        ix.key_dtype = torch.int64 if ix.key_bits == 64 else torch.int32
+        return ix
 
     # -- lifecycle
     def close(self):

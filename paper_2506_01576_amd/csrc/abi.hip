@@ -196,6 +196,24 @@ int finish_handle(idx_index *h, hipStream_t s, idx_handle *out) {
 
 }  // namespace
 
+namespace idx {
+
+// Handle life cycle for the other entry-point files (update.hip).
+int handle_new(uint64_t n, int layout, uint32_t k, uint32_t flags, const idx_allocator *alloc, hipStream_t s,
+               idx_index **out) {
+    return new_handle(n, layout, k, flags, alloc, s, out);
+}
+
+int handle_finish(idx_index *h, hipStream_t s, idx_handle *out) { return finish_handle(h, s, out); }
+
+void handle_discard(idx_index *h, hipStream_t s) {
+    (void)hipStreamSynchronize(s);
+    free_handle_buffers(h, s);
+    delete h;
+}
+
+}  // namespace idx
+
 extern "C" {
 
 int idx_build(const void *keys, const uint32_t *rowids, uint64_t n, int layout, uint32_t k, uint32_t flags,

@@ -147,6 +147,15 @@ int point_learned(idx_index *h, const PointIO &io, hipStream_t s);
 int range_count_learned(idx_index *h, const void *lo, const void *hi, uint64_t m, uint32_t *first, uint64_t *count,
                         hipStream_t s);
 
+// ---- abi.hip: handle life cycle ----------------------------------------------
+// A handle with its layout buffers allocated (validates layout, k, flags).
+int handle_new(uint64_t n, int layout, uint32_t k, uint32_t flags, const idx_allocator *alloc, hipStream_t s,
+               idx_index **out);
+// Resolves the default lookup parameters and hands the handle out.
+int handle_finish(idx_index *h, hipStream_t s, idx_handle *out);
+// Frees a handle that is not handed out (waits for its stream first).
+void handle_discard(idx_index *h, hipStream_t s);
+
 // ---- error plumbing ----------------------------------------------------------
 int hip_fail(hipError_t e);
 
