@@ -902,6 +902,16 @@ def main():
         del buf
     except Exception as e:  # pragma: no cover - measurement only
         probe["error"] = str(e)
+    # the random-access roofline of the survey's measurement plan: the probe's
+    # rate of independent random requests that miss the caches, A_rand,
+    # divided by the lookup's algorithmic granules beyond on-chip capacity, D
+    if "group1" in probe:
+        a_rand = probe["group1"]["granules_per_s"]
+        d_gran = (ab["tree"] + ab["rowid"]) / GRANULE
+        bound = a_rand / d_gran if d_gran > 0 else None
+        roofline["random_access"] = {"a_rand_per_s": a_rand, "granules_per_lookup": d_gran,
+                                     "bound_lookups_per_s": bound,
+                                     "frac": (value / bound) if bound else None}
 
     # ------------------------------------------------------------ CPU oracle
     cpu = None

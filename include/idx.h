@@ -283,6 +283,10 @@ int idx_get_params(idx_handle h, idx_lookup_params *out);
 #define IDX_FEATURE_AUTO 0u   /* train both root features, keep the lower loss */
 #define IDX_FEATURE_LINEAR 1u /* root feature: the key scaled to [0, 1] */
 #define IDX_FEATURE_LOG 2u    /* root feature: bit pattern of the key rounded to FP32 (log-like) */
+#define IDX_FEATURE_SPLINE 3u /* piecewise-linear root through G + 1 equally spaced rank quantiles of
+                                 the keys (G <= 4096 segments with at least 64 keys and 8 leaves
+                                 each): leaves are spread by rank, so clustered key distributions
+                                 get even leaves */
 
 typedef struct idx_learn_stats {
     uint32_t leaves;     /* L */
@@ -293,6 +297,8 @@ typedef struct idx_learn_stats {
     double leaf_loss;    /* sum of squared leaf residuals (target local rank) */
     double mean_window;  /* key-weighted mean search window (slots) */
     double max_window;   /* largest window of any leaf (slots) */
+    uint32_t segments;   /* spline root: segments G (0 for a linear root) */
+    uint32_t pad;
 } idx_learn_stats;
 
 /*
@@ -308,7 +314,8 @@ typedef struct idx_learn_stats {
  *   h        an IDX_BS index (any storage: SoA, AoS or line-padded AoS, where
  *            the window scan reads each key with its row ID) with n >= 1
  *            (IDX_ERR_ARG otherwise)
- *   leaves   1 <= leaves <= 2^22;  epochs 1..16;  feature IDX_FEATURE_*
+ *   leaves   1 <= leaves <= 2^22;  epochs 1..16;  feature IDX_FEATURE_* (AUTO
+ *            trains LINEAR and LOG and builds SPLINE, keeping the lowest root loss)
  * Synchronises `stream`.  Errors: IDX_ERR_ARG, IDX_ERR_NOMEM, IDX_ERR_HIP.
  */
 int idx_learn(idx_handle h, uint32_t leaves, uint32_t epochs, uint32_t feature, idx_stream stream);

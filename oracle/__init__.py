@@ -65,6 +65,8 @@ def lib():
         L.orc_root_grad.argtypes = [_p, _p, _u64, _p, _p, _p, _p]
         L.orc_key_feature.restype = ctypes.c_float
         L.orc_key_feature.argtypes = [_u64, ctypes.c_uint32]
+        L.orc_spline_leaves.argtypes = [_p, _u64, ctypes.c_uint32, ctypes.c_uint32, _p, _u64, _p]
+        L.orc_spline_leaves.restype = None
         L.orc_assign_leaves.argtypes = [_p, _u64, ctypes.c_uint32, ctypes.c_float, ctypes.c_float, ctypes.c_uint32,
                                         _p, _p]
         _lib = L
@@ -175,6 +177,25 @@ def assign_leaves(sorted_keys, mode: int, a0: float, a1: float, L: int):
     x = np.empty(len(K), dtype=np.float32)
     lib().orc_assign_leaves(_ptr(K), len(K), mode, a0, a1, L, _ptr(leaf), _ptr(x))
     return leaf, x
+
+
+def spline_segments(n: int, L: int) -> int:
+    """Segments of the spline root for n keys and L leaves: the largest power
+    of two G <= 4096 with G * 64 <= n and G * 8 <= L (1 for tiny sets)."""
+    G = 1
+    while G < 4096 and G * 2 * 64 <= n and G * 2 * 8 <= L:
+        G *= 2
+    return G
+
+
+def spline_leaves(sorted_keys, L: int, G: int, keys=None):
+    """Leaf of each key (default: the sorted keys themselves) under the spline
+    root built from `sorted_keys` with G segments and L leaves."""
+    S = _u64arr(sorted_keys)
+    K = S if keys is None else _u64arr(keys)
+    leaf = np.empty(len(K), dtype=np.uint32)
+    lib().orc_spline_leaves(_ptr(S), len(S), L, G, _ptr(K), len(K), _ptr(leaf))
+    return leaf
 
 
 def leaf_frame(sorted_keys, leaf, L: int):

@@ -284,6 +284,67 @@ void orc_assign_leaves(const uint64_t *keys, uint64_t n, uint32_t mode, float a0
     }
 }
 
+/* Spline root, written from its definition: knot j (j = 0..G) is the sorted
+ * build key at rank floor(j (n - 1) / G); segment j owns the leaves
+ * [floor(j L / G), floor((j + 1) L / G)).  A key k with knot_j <= k <
+ * knot_(j+1) goes to leaf first_j + min(span_j - 1, trunc(f32(k - knot_j) *
+ * s_j)), s_j = f32(span_j) / f32(knot_(j+1) - knot_j), every operation
+ * rounded to single precision.  Keys below knot_0 go to leaf 0, keys at or
+ * above knot_G to leaf L - 1, keys of a segment without leaves to its first
+ * leaf index (capped at L - 1).  Leaves of the m keys `keys` are written. */
+void orc_spline_leaves(const uint64_t *sorted_keys, uint64_t n, uint32_t L, uint32_t G, const uint64_t *keys,
+                       uint64_t m, uint32_t *leaf_out)
+{
+    uint64_t *knot = (uint64_t *)malloc(((size_t)G + 1) * sizeof(uint64_t));
+    float *scale = (float *)malloc(((size_t)G + 1) * sizeof(float));
+    if (!knot || !scale) {
+        free(knot);
+        free(scale);
+        return;
+    }
+    for (uint32_t j = 0; j <= G; ++j) knot[j] = sorted_keys[((uint64_t)j * (n - 1)) / G];
+    for (uint32_t j = 0; j < G; ++j) {
+        const uint32_t first = (uint32_t)(((uint64_t)j * L) / G);
+        const uint32_t next = (uint32_t)(((uint64_t)(j + 1) * L) / G);
+        const uint64_t gap = knot[j + 1] - knot[j];
+        volatile float num = (float)(next - first);
+        volatile float den = (float)gap;
+        scale[j] = gap ? num / den : 0.0f;
+    }
+    for (uint64_t i = 0; i < m; ++i) {
+        const uint64_t k = keys[i];
+        uint32_t leaf;
+        if (k < knot[0]) {
+            leaf = 0;
+        } else {
+            /* last knot <= k: binary search over knot[0..G] */
+            uint32_t lo = 0, hi = G + 1; /* knot[lo] <= k, and every index >= hi is > k */
+            while (hi - lo > 1) {
+                const uint32_t mid = lo + (hi - lo) / 2;
+                if (knot[mid] <= k) lo = mid;
+                else hi = mid;
+            }
+            if (lo >= G) {
+                leaf = L - 1;
+            } else {
+                const uint32_t first = (uint32_t)(((uint64_t)lo * L) / G);
+                const uint32_t next = (uint32_t)(((uint64_t)(lo + 1) * L) / G);
+                if (next == first) {
+                    leaf = first < L ? first : L - 1;
+                } else {
+                    volatile float off = (float)(k - knot[lo]);
+                    volatile float f = off * scale[lo];
+                    const uint32_t span = next - first;
+                    leaf = first + (f < (float)span ? (uint32_t)f : span - 1);
+                }
+            }
+        }
+        leaf_out[i] = leaf;
+    }
+    free(knot);
+    free(scale);
+}
+
 /* Root line fit: loss, gradient and Hessian of sum (a*x + b - t)^2. */
 void orc_root_grad(const double *x, const double *t, uint64_t n, const double *params, double *loss, double *grad,
                    double *hess)

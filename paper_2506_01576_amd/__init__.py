@@ -10,7 +10,7 @@ from ._binding import (IDX_AOS, IDX_BS, IDX_EBS, IDX_EKS, IDX_ERR_ARG, IDX_ERR_C
                        IDX_ERR_NOMEM, IDX_ERR_RESERVED_ROWID, IDX_KEY_U32, IDX_KEY_U64, IDX_MISS, IDX_OK,
                        IDX_SOA, IDX_AOS_PADDED, LIB_PATH, SIGNATURES, IdxError, Index, idx_allocator, idx_info,
                        idx_lookup_params, lib, probe_random, IDX_FEATURE_AUTO, IDX_FEATURE_LINEAR,
-                       IDX_FEATURE_LOG, idx_learn_stats, Batch, IDX_BATCH_GRAPH, learn_batch)
+                       IDX_FEATURE_LOG, IDX_FEATURE_SPLINE, idx_learn_stats, Batch, IDX_BATCH_GRAPH, learn_batch)
 
 __all__ = [
     "Index", "IdxError", "lib", "LIB_PATH", "SIGNATURES", "idx_allocator", "idx_info", "idx_lookup_params",

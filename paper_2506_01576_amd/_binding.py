@@ -78,7 +78,7 @@ class idx_lookup_params(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-IDX_FEATURE_AUTO, IDX_FEATURE_LINEAR, IDX_FEATURE_LOG = 0, 1, 2
+IDX_FEATURE_AUTO, IDX_FEATURE_LINEAR, IDX_FEATURE_LOG, IDX_FEATURE_SPLINE = 0, 1, 2, 3
 
 
 class idx_learn_stats(ctypes.Structure):
@@ -92,6 +92,8 @@ class idx_learn_stats(ctypes.Structure):
         ("leaf_loss", ctypes.c_double),
         ("mean_window", ctypes.c_double),
         ("max_window", ctypes.c_double),
+        ("segments", ctypes.c_uint32),
+        ("pad", ctypes.c_uint32),
     ]
 
 

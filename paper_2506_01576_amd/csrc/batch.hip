@@ -41,7 +41,7 @@ struct __align__(16) Desc {
     uint32_t m_full, early, gshift, pad0;
     RootRec root;           // learned form only
 };
-static_assert(sizeof(Desc) == 80, "descriptor layout");
+static_assert(sizeof(Desc) == 112, "descriptor layout");
 
 constexpr int BT = 256;     // threads per workgroup
 constexpr int BR = 4;       // lookups per lane

@@ -5,10 +5,11 @@
 // trainer in learned.hip; only the work split differs).
 //
 // The keys of every index are cut into units of UNIT consecutive keys (one
-// workgroup each; a unit never straddles two indexes).  Root sums for both
-// key features are accumulated in one pass; the feature with the lower loss
-// is picked on the device, so the whole sequence synchronises the host once,
-// at the end, to read back the roots and statistics.
+// workgroup each; a unit never straddles two indexes).  Root sums of all root
+// candidates (linear over either key feature, spline) are accumulated in one
+// pass; the candidate with the lowest loss is picked on the device, so the
+// whole sequence synchronises the host once, at the end, to read back the
+// roots and statistics.
 #include <climits>
 
 #include <new>
@@ -41,29 +42,41 @@ struct Unit {
     uint32_t pad;
 };
 
+// Root candidates per index: 0 = linear over the LINEAR feature, 1 = linear
+// over the LOG feature, 2 = spline (bit c of cmask enables candidate c).
+constexpr int NCAND = 3;
+
 template <typename K>
 __global__ __launch_bounds__(BT) void k_bt_root_accum(const Unit *__restrict__ units, const TDesc *__restrict__ d,
-                                                      const RootRec *__restrict__ roots2, uint32_t fmask,
+                                                      const RootRec *__restrict__ roots, uint32_t cmask,
                                                       double *__restrict__ acc) {
-    __shared__ double s[BT / kWave][2 * NACC];
+    __shared__ double s[BT / kWave][NCAND * NACC];
     const Unit u = units[blockIdx.x];
     const TDesc D = d[u.index];
     const K *keys = (const K *)D.keys;
-    const RootRec R0 = roots2[2 * u.index], R1 = roots2[2 * u.index + 1];
-    const double scale = (double)D.L / (double)D.n;
-    double a[2 * NACC];
+    RootRec R[NCAND];
 #pragma unroll
-    for (int j = 0; j < 2 * NACC; ++j) a[j] = 0.0;
+    for (int c = 0; c < NCAND; ++c) R[c] = roots[NCAND * u.index + c];
+    const double scale = (double)D.L / (double)D.n;
+    double a[NCAND * NACC];
+#pragma unroll
+    for (int j = 0; j < NCAND * NACC; ++j) a[j] = 0.0;
     for (uint64_t i = u.begin + threadIdx.x; i < u.end; i += BT) {
         const uint64_t key = (uint64_t)keys[i];
         const float t = (float)((double)i * scale);
 #pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            if (!(fmask & (1u << f))) continue;
-            const RootRec &R = f ? R1 : R0;
-            const float x = key_feature(key, R.mode);
-            const float r = __fsub_rn(__fadd_rn(__fmul_rn(R.a1, x), R.a0), t);
-            double *b = a + f * NACC;
+        for (int c = 0; c < NCAND; ++c) {
+            if (!(cmask & (1u << c))) continue;
+            float x, pred;
+            if (c == 2) {
+                x = 0.f;
+                (void)spline_leaf(R[c], key, &pred);
+            } else {
+                x = key_feature(key, R[c].mode);
+                pred = __fadd_rn(__fmul_rn(R[c].a1, x), R[c].a0);
+            }
+            const float r = __fsub_rn(pred, t);
+            double *b = a + c * NACC;
             b[0] += 1.0;
             b[1] += x;
             b[2] += (double)x * x;
@@ -74,37 +87,67 @@ __global__ __launch_bounds__(BT) void k_bt_root_accum(const Unit *__restrict__ u
     }
     const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
-    for (int j = 0; j < 2 * NACC; ++j) {
+    for (int j = 0; j < NCAND * NACC; ++j) {
         const double v = wave_sum(a[j]);
         if (lane == 0) s[wave][j] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 2 * NACC && (fmask & (1u << (threadIdx.x / NACC)))) {
+    if (threadIdx.x < NCAND * NACC && (cmask & (1u << (threadIdx.x / NACC)))) {
         double v = 0;
         for (int w = 0; w < BT / kWave; ++w) v += s[w][threadIdx.x];
-        atomicAdd(&acc[(uint64_t)u.index * 2 * NACC + threadIdx.x], v);
+        atomicAdd(&acc[(uint64_t)u.index * NCAND * NACC + threadIdx.x], v);
     }
 }
 
-__global__ void k_bt_root_update(RootRec *__restrict__ roots2, const double *__restrict__ acc, uint32_t count,
-                                 uint32_t fmask) {
+// Newton steps for the two linear candidates.
+__global__ void k_bt_root_update(RootRec *__restrict__ roots, const double *__restrict__ acc, uint32_t count,
+                                 uint32_t cmask) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * count || !(fmask & (1u << (t & 1)))) return;
-    RootRec R = roots2[t];
-    newton_linear(acc + (uint64_t)t * NACC, R.a0, R.a1);
-    roots2[t].a0 = R.a0;
-    roots2[t].a1 = R.a1;
+    const uint32_t i = t / 2, c = t % 2;
+    if (i >= count || !(cmask & (1u << c))) return;
+    RootRec R = roots[NCAND * i + c];
+    newton_linear(acc + ((uint64_t)NCAND * i + c) * NACC, R.a0, R.a1);
+    roots[NCAND * i + c].a0 = R.a0;
+    roots[NCAND * i + c].a1 = R.a1;
 }
 
-// Lower final loss wins; LINEAR on a tie.
-__global__ void k_bt_root_pick(const RootRec *__restrict__ roots2, const double *__restrict__ acc, uint32_t count,
-                               uint32_t fmask, RootRec *__restrict__ best, double *__restrict__ stats) {
+// Lowest final loss wins; the lower candidate number on a tie.
+__global__ void k_bt_root_pick(const RootRec *__restrict__ roots, const double *__restrict__ acc, uint32_t count,
+                               uint32_t cmask, RootRec *__restrict__ best, double *__restrict__ stats) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    uint32_t f = (fmask & 1u) ? 0u : 1u;
-    if (fmask == 3u && acc[((uint64_t)2 * i + 1) * NACC + 5] < acc[(uint64_t)2 * i * NACC + 5]) f = 1u;
-    best[i] = roots2[2 * i + f];
-    stats[(uint64_t)i * NST + 3] = acc[((uint64_t)2 * i + f) * NACC + 5];
+    int f = -1;
+    double fl = 0.0;
+    for (int c = 0; c < NCAND; ++c) {
+        if (!(cmask & (1u << c))) continue;
+        const double l = acc[((uint64_t)NCAND * i + c) * NACC + 5];
+        if (f < 0 || l < fl) {
+            f = c;
+            fl = l;
+        }
+    }
+    best[i] = roots[NCAND * i + f];
+    stats[(uint64_t)i * NST + 3] = fl;
+}
+
+// Spline knots and scales of every index with a spline candidate (one
+// workgroup per index).
+template <typename K>
+__global__ void k_bt_spline(const TDesc *__restrict__ d, const RootRec *__restrict__ roots) {
+    const TDesc D = d[blockIdx.x];
+    const RootRec R = roots[NCAND * blockIdx.x + 2];
+    if (R.G == 0) return;
+    const K *keys = (const K *)D.keys;
+    uint64_t *knots = (uint64_t *)R.knots;
+    float *scale = (float *)R.scale;
+    for (uint32_t j = threadIdx.x; j <= R.G; j += blockDim.x)
+        knots[j] = (uint64_t)keys[((uint64_t)j * (D.n - 1)) / R.G];
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < R.G; j += blockDim.x) {
+        const uint64_t gap = knots[j + 1] - knots[j];
+        const uint32_t span = seg_leaf(j + 1, R.L, R.G) - seg_leaf(j, R.L, R.G);
+        scale[j] = gap ? __fdiv_rn((float)span, (float)gap) : 0.f;
+    }
 }
 
 __global__ void k_bt_zero(double *p, uint64_t count) {
@@ -338,8 +381,8 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
     const uint32_t nunits = (uint32_t)units.size();
     auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t b_desc = up(sizeof(TDesc) * count), b_units = up(sizeof(Unit) * nunits);
-    const size_t b_roots2 = up(sizeof(RootRec) * 2 * count), b_best = up(sizeof(RootRec) * count);
-    const size_t b_racc = up(sizeof(double) * 2 * NACC * count), b_stats = up(sizeof(double) * NST * count);
+    const size_t b_roots2 = up(sizeof(RootRec) * NCAND * count), b_best = up(sizeof(RootRec) * count);
+    const size_t b_racc = up(sizeof(double) * NCAND * NACC * count), b_stats = up(sizeof(double) * NST * count);
     const size_t b_lacc = up(sizeof(double) * NACC * total_leaves), b_cnt = up(sizeof(uint32_t) * total_leaves);
     const Alloc &A = hs[0]->alloc;
     char *tmp = (char *)A.get(b_desc + b_units + b_roots2 + b_best + b_racc + b_stats + b_lacc + b_cnt, s);
@@ -352,37 +395,47 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
     double *d_stats = (double *)((char *)d_racc + b_racc);
     double *d_lacc = (double *)((char *)d_stats + b_stats);
     uint32_t *d_cnt = (uint32_t *)((char *)d_lacc + b_lacc);
-    std::vector<RootRec> roots2(2 * count);
+    const uint32_t cmask = feature == IDX_FEATURE_AUTO ? 7u : (1u << (feature - 1));
+    std::vector<RootRec> roots2((size_t)NCAND * count);
     for (uint32_t i = 0; i < count; ++i) {
-        roots2[2 * i] = RootRec{0.f, 0.f, IDX_FEATURE_LINEAR, leaves[i]};
-        roots2[2 * i + 1] = RootRec{0.f, 0.f, IDX_FEATURE_LOG, leaves[i]};
+        roots2[NCAND * i] = RootRec{0.f, 0.f, IDX_FEATURE_LINEAR, leaves[i], nullptr, nullptr, 0, 0};
+        roots2[NCAND * i + 1] = RootRec{0.f, 0.f, IDX_FEATURE_LOG, leaves[i], nullptr, nullptr, 0, 0};
+        RootRec sp{0.f, 0.f, IDX_FEATURE_SPLINE, leaves[i], nullptr, nullptr, 0, 0};
+        if (hs[i]->learned->spline) {
+            sp.G = spline_segments(hs[i]->n, leaves[i]);
+            sp.knots = (const uint64_t *)hs[i]->learned->spline;
+            sp.scale = (const float *)((const char *)hs[i]->learned->spline + spline_knot_bytes(sp.G));
+        }
+        roots2[NCAND * i + 2] = sp;
     }
-    const uint32_t fmask = feature == IDX_FEATURE_AUTO ? 3u : (feature == IDX_FEATURE_LINEAR ? 1u : 2u);
     std::vector<RootRec> best(count);
     std::vector<double> stats((size_t)NST * count);
     int rc = IDX_OK;
     do {
         if (hipMemcpyAsync(d_desc, desc.data(), sizeof(TDesc) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(d_units, units.data(), sizeof(Unit) * nunits, hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipMemcpyAsync(d_roots2, roots2.data(), sizeof(RootRec) * 2 * count, hipMemcpyHostToDevice, s) !=
+            hipMemcpyAsync(d_roots2, roots2.data(), sizeof(RootRec) * NCAND * count, hipMemcpyHostToDevice, s) !=
                 hipSuccess) {
             rc = IDX_ERR_HIP;
             break;
         }
-        // ---- stage 1: roots of both features, epochs Newton steps, final loss
+        // ---- stage 1: root candidates -- the two linear roots take `epochs`
+        // Newton steps, the spline is built from rank quantiles -- and the
+        // final loss of each
+        if (cmask & 4u) hipLaunchKernelGGL((k_bt_spline<K>), dim3(count), dim3(256), 0, s, d_desc, d_roots2);
         for (uint32_t ep = 0; ep <= epochs; ++ep) {
-            hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for(2ull * NACC * count, 256)), dim3(256), 0, s, d_racc,
-                               (uint64_t)2 * NACC * count);
-            hipLaunchKernelGGL((k_bt_root_accum<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_roots2, fmask,
+            hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for((uint64_t)NCAND * NACC * count, 256)), dim3(256), 0, s,
+                               d_racc, (uint64_t)NCAND * NACC * count);
+            hipLaunchKernelGGL((k_bt_root_accum<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_roots2, cmask,
                                d_racc);
-            if (ep < epochs)
+            if (ep < epochs && (cmask & 3u))
                 hipLaunchKernelGGL(k_bt_root_update, dim3(blocks_for(2ull * count, 256)), dim3(256), 0, s, d_roots2,
-                                   d_racc, count, fmask);
+                                   d_racc, count, cmask);
         }
         hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for((uint64_t)NST * count, 256)), dim3(256), 0, s, d_stats,
                            (uint64_t)NST * count);
         hipLaunchKernelGGL(k_bt_root_pick, dim3(blocks_for(count, 256)), dim3(256), 0, s, d_roots2, d_racc, count,
-                           fmask, d_best, d_stats);
+                           cmask, d_best, d_stats);
         // ---- stage 2: leaves
         hipLaunchKernelGGL(k_bt_zero_u32, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, d_cnt, total_leaves);
         hipLaunchKernelGGL((k_bt_leaf_count<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_best, d_cnt);
@@ -424,6 +477,11 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
         M->stats.leaf_loss = stats[(size_t)i * NST + 2];
         M->stats.mean_window = stats[(size_t)i * NST + 0] / (double)hs[i]->n;
         M->stats.max_window = stats[(size_t)i * NST + 1];
+        M->stats.segments = best[i].mode == IDX_FEATURE_SPLINE ? best[i].G : 0;
+        if (best[i].mode != IDX_FEATURE_SPLINE && M->spline) {
+            hs[i]->alloc.put(M->spline, s);
+            M->spline = nullptr;
+        }
     }
     return IDX_OK;
 }
@@ -432,7 +490,7 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
 
 int learn_batch(idx_index *const *hs, uint32_t count, const uint32_t *leaves, uint32_t epochs, uint32_t feature,
                 hipStream_t s) {
-    if (!hs || !leaves || count == 0 || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_LOG) return IDX_ERR_ARG;
+    if (!hs || !leaves || count == 0 || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_SPLINE) return IDX_ERR_ARG;
     std::unordered_set<const idx_index *> seen;
     for (uint32_t i = 0; i < count; ++i) {
         const idx_index *h = hs[i];
@@ -445,7 +503,12 @@ int learn_batch(idx_index *const *hs, uint32_t count, const uint32_t *leaves, ui
         drop_model(h, s);
         LearnedModel *M = new (std::nothrow) LearnedModel();
         if (M) M->leaves = (LeafRec *)h->alloc.get((size_t)leaves[i] * sizeof(LeafRec), s);
-        if (!M || !M->leaves) {
+        if (M && M->leaves && (feature == IDX_FEATURE_AUTO || feature == IDX_FEATURE_SPLINE)) {
+            const uint32_t G = spline_segments(h->n, leaves[i]);
+            M->spline = h->alloc.get(spline_knot_bytes(G) + (size_t)G * sizeof(float), s);
+        }
+        if (!M || !M->leaves || ((feature == IDX_FEATURE_AUTO || feature == IDX_FEATURE_SPLINE) && !M->spline)) {
+            if (M && M->leaves) h->alloc.put(M->leaves, s);
             delete M;
             for (uint32_t j = 0; j < i; ++j) drop_model(hs[j], s);
             return IDX_ERR_NOMEM;

@@ -46,9 +46,17 @@ __global__ __launch_bounds__(LT) void k_root_accum(Load<K, AOS> keys, uint64_t n
     double a[NACC] = {0, 0, 0, 0, 0, 0};
     const double scale = (double)R.L / (double)n;
     for (uint64_t i = (uint64_t)blockIdx.x * LT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * LT) {
-        const float x = key_feature((uint64_t)keys.key(i), R.mode);
+        const uint64_t key = (uint64_t)keys.key(i);
         const float t = (float)((double)i * scale);
-        const float r = __fsub_rn(__fadd_rn(__fmul_rn(R.a1, x), R.a0), t);  // forward residual
+        float x, pred;
+        if (R.mode == IDX_FEATURE_SPLINE) {
+            x = 0.f;  // no parameters to fit: only the loss is wanted
+            (void)spline_leaf(R, key, &pred);
+        } else {
+            x = key_feature(key, R.mode);
+            pred = __fadd_rn(__fmul_rn(R.a1, x), R.a0);
+        }
+        const float r = __fsub_rn(pred, t);  // forward residual
         a[0] += 1.0;
         a[1] += x;
         a[2] += (double)x * x;
@@ -264,6 +272,24 @@ __global__ void k_sum_leaf_loss(const double *__restrict__ acc, uint32_t L, doub
     if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(out, s);
 }
 
+// Spline root: knot j is the sorted key at rank floor(j (n - 1) / G).
+template <typename K, bool AOS>
+__global__ void k_spline_knots(Load<K, AOS> keys, uint64_t n, uint32_t G, uint64_t *__restrict__ knots) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > G) return;
+    knots[j] = (uint64_t)keys.key(((uint64_t)j * (n - 1)) / G);
+}
+
+// Leaves of segment j per unit of key offset: span / f32(knot j+1 - knot j),
+// correctly rounded; 0 for an empty segment (equal knots).
+__global__ void k_spline_scale(const uint64_t *__restrict__ knots, uint32_t G, uint32_t L, float *__restrict__ scale) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= G) return;
+    const uint64_t d = knots[j + 1] - knots[j];
+    const uint32_t span = seg_leaf(j + 1, L, G) - seg_leaf(j, L, G);
+    scale[j] = d ? __fdiv_rn((float)span, (float)d) : 0.f;
+}
+
 uint32_t grid_for(uint64_t threads, uint32_t block) {
     uint64_t b = (threads + block - 1) / block;
     if (b == 0) b = 1;
@@ -317,18 +343,31 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
                                                                              : (uint32_t)((n + LT * 8 - 1) / (LT * 8));
     const uint32_t cblocks = grid_for((n + CHUNK - 1) / CHUNK, LT);
     do {
-        // ---- stage 1: the root, for each candidate feature; keep the lower loss
+        // ---- stage 1: the root, for each candidate; keep the lower loss.  A
+        // linear root takes `epochs` Newton steps; the spline root is built
+        // from the keys' rank quantiles and only its loss is measured.
         RootRec best{};
         double best_loss = -1.0;
-        for (uint32_t mode = IDX_FEATURE_LINEAR; mode <= IDX_FEATURE_LOG; ++mode) {
+        for (uint32_t mode = IDX_FEATURE_LINEAR; mode <= IDX_FEATURE_SPLINE; ++mode) {
             if (feature != IDX_FEATURE_AUTO && feature != mode) continue;
-            RootRec R{0.f, 0.f, mode, L};
+            RootRec R{0.f, 0.f, mode, L, nullptr, nullptr, 0, 0};
+            uint32_t ep_n = epochs;
+            if (mode == IDX_FEATURE_SPLINE) {
+                R.G = spline_segments(n, L);
+                R.knots = (const uint64_t *)M->spline;
+                R.scale = (const float *)((const char *)M->spline + spline_knot_bytes(R.G));
+                hipLaunchKernelGGL((k_spline_knots<K, AOS>), dim3(grid_for((uint64_t)R.G + 1, 256)), dim3(256), 0, s,
+                                   keys, n, R.G, (uint64_t *)R.knots);
+                hipLaunchKernelGGL(k_spline_scale, dim3(grid_for(R.G, 256)), dim3(256), 0, s, R.knots, R.G, L,
+                                   (float *)R.scale);
+                ep_n = 0;
+            }
             if (hipMemcpyAsync(d_root, &R, sizeof(R), hipMemcpyHostToDevice, s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
-            for (uint32_t ep = 0; ep <= epochs; ++ep) {
+            for (uint32_t ep = 0; ep <= ep_n; ++ep) {
                 hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, root_acc, (uint64_t)NACC);
                 hipLaunchKernelGGL((k_root_accum<K, AOS>), dim3(rblocks ? rblocks : 1), dim3(LT), 0, s, keys, n, d_root,
                                    root_acc);
-                if (ep < epochs) hipLaunchKernelGGL(k_root_update, dim3(1), dim3(64), 0, s, d_root, root_acc);
+                if (ep < ep_n) hipLaunchKernelGGL(k_root_update, dim3(1), dim3(64), 0, s, d_root, root_acc);
             }
             double acc[NACC];
             RootRec R2;
@@ -376,11 +415,19 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
 
 int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream_t s) {
     if (h->layout != IDX_BS || h->n == 0) return IDX_ERR_ARG;
-    if (L == 0 || L > (1u << 22) || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_LOG) return IDX_ERR_ARG;
+    if (L == 0 || L > (1u << 22) || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_SPLINE) return IDX_ERR_ARG;
     drop_model(h, s);
     LearnedModel *M = new (std::nothrow) LearnedModel();
     if (!M) return IDX_ERR_NOMEM;
     M->leaves = (LeafRec *)h->alloc.get((size_t)L * sizeof(LeafRec), s);
+    if (M->leaves && (feature == IDX_FEATURE_AUTO || feature == IDX_FEATURE_SPLINE)) {
+        const uint32_t G = spline_segments(h->n, L);
+        M->spline = h->alloc.get(spline_knot_bytes(G) + (size_t)G * sizeof(float), s);
+        if (!M->spline) {
+            h->alloc.put(M->leaves, s);
+            M->leaves = nullptr;
+        }
+    }
     if (!M->leaves) {
         delete M;
         return IDX_ERR_NOMEM;
@@ -398,12 +445,18 @@ int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream
     M->stats.feature = M->root.mode;
     M->stats.root_a0 = M->root.a0;
     M->stats.root_a1 = M->root.a1;
+    M->stats.segments = M->root.mode == IDX_FEATURE_SPLINE ? M->root.G : 0;
+    if (M->root.mode != IDX_FEATURE_SPLINE && M->spline) {
+        h->alloc.put(M->spline, s);
+        M->spline = nullptr;
+    }
     return IDX_OK;
 }
 
 void drop_model(idx_index *h, hipStream_t s) {
     if (!h->learned) return;
     h->alloc.put(h->learned->leaves, s);
+    if (h->learned->spline) h->alloc.put(h->learned->spline, s);
     delete h->learned;
     h->learned = nullptr;
 }

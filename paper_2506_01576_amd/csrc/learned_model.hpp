@@ -8,10 +8,15 @@
 namespace idx {
 
 struct RootRec {
-    float a0, a1;    // t = a1 * x + a0, leaf = clamp(floor(t), 0, L - 1)
-    uint32_t mode;   // IDX_FEATURE_LINEAR / IDX_FEATURE_LOG
+    float a0, a1;           // linear roots: t = a1 * x + a0, leaf = clamp(floor(t), 0, L - 1)
+    uint32_t mode;          // IDX_FEATURE_LINEAR / IDX_FEATURE_LOG / IDX_FEATURE_SPLINE
     uint32_t L;
+    const uint64_t *knots;  // spline: G + 1 keys, the sorted keys at ranks floor(j (n - 1) / G)
+    const float *scale;     // spline: per segment, its leaves per unit of key offset
+    uint32_t G;             // spline: segments, a power of two
+    uint32_t pad;
 };
+static_assert(sizeof(RootRec) == 40, "root record is 40 bytes");
 
 struct __align__(16) LeafRec {
     uint64_t kmin;     // smallest build key of the leaf (0 when empty)
@@ -25,6 +30,7 @@ static_assert(sizeof(LeafRec) == 32, "leaf record is 32 bytes");
 struct LearnedModel {
     RootRec root{};
     LeafRec *leaves = nullptr;  // device, L records
+    void *spline = nullptr;     // device: G + 1 knot keys, then G scales (spline root only)
     idx_learn_stats stats{};
 };
 
@@ -41,9 +47,55 @@ __device__ __forceinline__ float key_feature(uint64_t key, uint32_t mode) {
     return (float)__float_as_uint(f) * 0x1p-31f;
 }
 
+// Spline segments for n keys and L leaves: the largest power of two G <= 4096
+// with at least 64 keys and 8 leaves per segment (1 for tiny sets).
+inline uint32_t spline_segments(uint64_t n, uint32_t L) {
+    uint32_t G = 1;
+    while (G < 4096 && (uint64_t)G * 2 * 64 <= n && (uint64_t)G * 2 * 8 <= L) G <<= 1;
+    return G;
+}
+
+// Bytes of the G + 1 knot keys (256-byte aligned, the scales follow).
+inline size_t spline_knot_bytes(uint32_t G) { return (((size_t)G + 1) * 8 + 255) & ~(size_t)255; }
+
+// First leaf of spline segment j: segments share the L leaves as evenly as
+// integers allow.
+__host__ __device__ __forceinline__ uint32_t seg_leaf(uint32_t j, uint32_t L, uint32_t G) {
+    return (uint32_t)(((uint64_t)j * L) / G);
+}
+
+// Spline root: the segment j of the last knot <= key gives leaves
+// [seg_leaf(j), seg_leaf(j + 1)); inside it the leaf offset is
+// f32(key - knot j) * scale[j], truncated (one rounding each).  Non-decreasing
+// in the key, so each leaf's keys are one rank interval.
+__device__ __forceinline__ uint32_t spline_leaf(const RootRec &R, uint64_t key, float *coord = nullptr) {
+    const uint64_t *K = R.knots;
+    if (key < K[0]) {
+        if (coord) *coord = 0.f;
+        return 0;
+    }
+    uint32_t j = 0;
+    for (uint32_t h = R.G; h > 0; h >>= 1)
+        if (j + h <= R.G && K[j + h] <= key) j += h;
+    if (j >= R.G) {
+        if (coord) *coord = (float)R.L;
+        return R.L - 1;
+    }
+    const uint32_t f0 = seg_leaf(j, R.L, R.G), f1 = seg_leaf(j + 1, R.L, R.G);
+    if (f1 == f0) {
+        if (coord) *coord = (float)f0;
+        return f0 < R.L ? f0 : R.L - 1;
+    }
+    const float f = __fmul_rn((float)(key - K[j]), R.scale[j]);
+    const uint32_t span = f1 - f0;
+    if (coord) *coord = __fadd_rn((float)f0, f < (float)span ? f : (float)span);
+    return f0 + (f < (float)span ? (uint32_t)f : span - 1);
+}
+
 // Multiply, then add, each rounded on its own (no contraction), so the same
 // key always lands in the same leaf wherever this is evaluated.
 __device__ __forceinline__ uint32_t leaf_of(const RootRec &R, uint64_t key) {
+    if (R.mode == IDX_FEATURE_SPLINE) return spline_leaf(R, key);
     const float x = key_feature(key, R.mode);
     const float t = __fadd_rn(__fmul_rn(R.a1, x), R.a0);
     if (!(t > 0.f)) return 0;

@@ -116,9 +116,14 @@ struct BlobHeader {
     idx_learn_stats stats;
 };
 
+// Bytes of a spline root's table (knot keys, then scales); 0 for a linear root.
+uint64_t spline_bytes(const RootRec &R) {
+    return R.mode == IDX_FEATURE_SPLINE ? spline_knot_bytes(R.G) + (uint64_t)R.G * sizeof(float) : 0;
+}
+
 uint64_t blob_size(const idx_index *h) {
     uint64_t s = sizeof(BlobHeader) + h->key_bytes + h->row_bytes;
-    if (h->learned) s += (uint64_t)h->learned->root.L * sizeof(LeafRec);
+    if (h->learned) s += (uint64_t)h->learned->root.L * sizeof(LeafRec) + spline_bytes(h->learned->root);
     return s;
 }
 
@@ -227,8 +232,12 @@ int idx_save(idx_handle h, void *blob, uint64_t capacity, uint64_t *size, idx_st
     p += h->key_bytes;
     if (h->row_bytes) IDX_HIP(hipMemcpyAsync(p, h->rowids, h->row_bytes, hipMemcpyDeviceToHost, s));
     p += h->row_bytes;
-    if (h->learned)
+    if (h->learned) {
         IDX_HIP(hipMemcpyAsync(p, h->learned->leaves, (size_t)hd.leaves * sizeof(LeafRec), hipMemcpyDeviceToHost, s));
+        p += (size_t)hd.leaves * sizeof(LeafRec);
+        if (spline_bytes(hd.root))
+            IDX_HIP(hipMemcpyAsync(p, h->learned->spline, spline_bytes(hd.root), hipMemcpyDeviceToHost, s));
+    }
     IDX_HIP(hipStreamSynchronize(s));
     return IDX_OK;
 }
@@ -241,15 +250,19 @@ int idx_load(const void *blob, uint64_t size, const idx_allocator *alloc, idx_st
     std::memcpy(&hd, blob, sizeof(hd));
     if (std::memcmp(hd.magic, kMagic, sizeof(kMagic)) != 0) return IDX_ERR_ARG;
     if (hd.has_model > 1 || (hd.has_model && (hd.layout != IDX_BS || hd.leaves == 0 || hd.leaves > (1u << 22) ||
-                                              hd.root.L != hd.leaves)))
+                                              hd.root.L != hd.leaves || hd.root.mode == 0 ||
+                                              hd.root.mode > IDX_FEATURE_SPLINE ||
+                                              (hd.root.mode == IDX_FEATURE_SPLINE &&
+                                               hd.root.G != spline_segments(hd.n, hd.leaves)))))
         return IDX_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
     idx_index *h = nullptr;
     int rc = handle_new(hd.n, hd.layout, hd.k, hd.flags, alloc, s, &h);
     if (rc != IDX_OK) return rc;
     const uint64_t leaf_b = hd.has_model ? (uint64_t)hd.leaves * sizeof(LeafRec) : 0;
+    const uint64_t spl_b = hd.has_model ? spline_bytes(hd.root) : 0;
     if (h->key_bytes != hd.key_bytes || h->row_bytes != hd.row_bytes ||
-        size != sizeof(BlobHeader) + hd.key_bytes + hd.row_bytes + leaf_b) {
+        size != sizeof(BlobHeader) + hd.key_bytes + hd.row_bytes + leaf_b + spl_b) {
         handle_discard(h, s);
         return IDX_ERR_ARG;
     }
@@ -261,15 +274,24 @@ int idx_load(const void *blob, uint64_t size, const idx_allocator *alloc, idx_st
     if (e == hipSuccess && hd.has_model) {
         LearnedModel *M = new (std::nothrow) LearnedModel();
         if (M) M->leaves = (LeafRec *)h->alloc.get(leaf_b, s);
-        if (!M || !M->leaves) {
+        if (M && M->leaves && spl_b) M->spline = h->alloc.get(spl_b, s);
+        if (!M || !M->leaves || (spl_b && !M->spline)) {
+            if (M && M->leaves) h->alloc.put(M->leaves, s);
             delete M;
             handle_discard(h, s);
             return IDX_ERR_NOMEM;
         }
         M->root = hd.root;
+        M->root.knots = nullptr;
+        M->root.scale = nullptr;
+        if (spl_b) {
+            M->root.knots = (const uint64_t *)M->spline;
+            M->root.scale = (const float *)((const char *)M->spline + spline_knot_bytes(M->root.G));
+        }
         M->stats = hd.stats;
         h->learned = M;
         e = hipMemcpyAsync(M->leaves, p, leaf_b, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && spl_b) e = hipMemcpyAsync(M->spline, p + leaf_b, spl_b, hipMemcpyHostToDevice, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {

@@ -64,7 +64,7 @@ SETS = [("uniform", 1), ("uniform", 2), ("dup", 5), ("uniform", 100), ("lognorma
 
 
 @pytest.mark.parametrize("bits", [32, 64])
-@pytest.mark.parametrize("feature", [AUTO, LINEAR, LOG])
+@pytest.mark.parametrize("feature", [AUTO, LINEAR, LOG, 3])
 def test_learn_batch_exact(bits, feature):
     """Every batch-trained model answers point lookups exactly; its leaf
     partition equals the oracle's under the exported root; its windows are
@@ -89,7 +89,11 @@ def test_learn_batch_exact(bits, feature):
         assert np.array_equal(got, want), f"set {j}"
         # leaf partition under the exported root
         table = ix.learn_export().cpu().numpy().view(np.uint8).reshape(L, 32)
-        leaf, _ = oracle.assign_leaves(sk, st["feature"], st["root_a0"], st["root_a1"], L)
+        if st["feature"] == 3:  # spline root
+            assert st["segments"] == oracle.spline_segments(len(sk), L)
+            leaf = oracle.spline_leaves(sk, L, st["segments"])
+        else:
+            leaf, _ = oracle.assign_leaves(sk, st["feature"], st["root_a0"], st["root_a1"], L)
         _, _, base, size = oracle.leaf_frame(sk, leaf, L)
         assert np.array_equal(table[:, 12:16].copy().view(np.uint32).ravel(), size.astype(np.uint32))
         assert np.array_equal(table[:, 8:12].copy().view(np.uint32).ravel(), base.astype(np.uint32))

@@ -20,7 +20,7 @@ idx = pytest.importorskip("paper_2506_01576_amd")
 if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
-AUTO, LINEAR, LOG = idx.IDX_FEATURE_AUTO, idx.IDX_FEATURE_LINEAR, idx.IDX_FEATURE_LOG
+AUTO, LINEAR, LOG, SPLINE = idx.IDX_FEATURE_AUTO, idx.IDX_FEATURE_LINEAR, idx.IDX_FEATURE_LOG, idx.IDX_FEATURE_SPLINE
 
 
 def say(*a):
@@ -43,6 +43,14 @@ def make(kind, n, seed):
     return keys, rows
 
 
+def oracle_leaves(sk, st, L):
+    """The oracle's leaf of every sorted key under the trained root described
+    by the model statistics st (linear root or spline)."""
+    if st["feature"] == SPLINE:
+        return oracle.spline_leaves(sk, L, st["segments"])
+    return oracle.assign_leaves(sk, st["feature"], st["root_a0"], st["root_a1"], L)[0]
+
+
 def queries(keys, m, seed):
     rng = np.random.default_rng(seed)
     dt = keys.dtype
@@ -58,7 +66,7 @@ def queries(keys, m, seed):
 @pytest.mark.parametrize("aos", [False, True, "padded"])
 @pytest.mark.parametrize("kind", ["uniform32", "uniform64", "lognormal", "dup"])
 @pytest.mark.parametrize("leaves,epochs,feature", [(1, 1, AUTO), (7, 2, LINEAR), (4096, 2, AUTO), (4096, 1, LOG),
-                                                   (65536, 2, AUTO)])
+                                                   (65536, 2, AUTO), (4096, 2, SPLINE), (100, 1, SPLINE)])
 def test_learned_lookup_parity(kind, leaves, epochs, feature, aos):
     """The model on the sorted array in each storage (SoA, AoS, line-padded
     AoS): points, ranges and the answers without the model equal the oracle's."""
@@ -120,7 +128,7 @@ def test_learned_aos_same_model_as_soa(aos):
         assert sb["root_a1"] == pytest.approx(sa["root_a1"], rel=1e-5)
         assert sb["mean_window"] == pytest.approx(sa["mean_window"], rel=1e-2)
         tb = b.learn_export().cpu().numpy().view(np.uint8).reshape(2048, 32)
-        leaf, _ = oracle.assign_leaves(sk, sb["feature"], sb["root_a0"], sb["root_a1"], 2048)
+        leaf = oracle_leaves(sk, sb, 2048)
         _, _, base, size = oracle.leaf_frame(sk, leaf, 2048)
         assert np.array_equal(tb[:, 8:12].copy().view(np.uint32).ravel(), base.astype(np.uint32))
         assert np.array_equal(tb[:, 12:16].copy().view(np.uint32).ravel(), size.astype(np.uint32))
@@ -132,7 +140,7 @@ def test_learn_rejects_other_layouts():
         with pytest.raises(idx.IdxError):
             ix.learn(64)
     with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
-        for bad in ((0, 2, AUTO), (1 << 23, 2, AUTO), (64, 0, AUTO), (64, 2, 3)):
+        for bad in ((0, 2, AUTO), (1 << 23, 2, AUTO), (64, 0, AUTO), (64, 2, 4)):
             with pytest.raises(idx.IdxError):
                 ix.learn(*bad)
 
@@ -258,3 +266,40 @@ def test_model_narrows_the_search():
         f"steps {steps_plain:.1f} -> {steps_model:.1f}")
     assert steps_model < steps_plain - 10
     assert t_model < t_plain
+
+
+@pytest.mark.parametrize("kind", ["uniform64", "lognormal", "dup", "uniform32"])
+@pytest.mark.parametrize("leaves", [1, 64, 5000, 1 << 15])
+def test_spline_root_partition_matches_oracle(kind, leaves):
+    """The spline root's leaf partition (base rank and size of every leaf)
+    equals the oracle's evaluation of the same definition; the segment count
+    follows its rule."""
+    n = 200003
+    keys, rows = make(kind, n, seed=leaves)
+    sk, _ = oracle.stable_sort(keys, rows)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        st = ix.learn(leaves, 2, SPLINE)
+        assert st["feature"] == SPLINE
+        G = oracle.spline_segments(n, leaves)
+        assert st["segments"] == G
+        table = ix.learn_export().cpu().numpy().view(np.uint8).reshape(leaves, 32)
+    leaf = oracle.spline_leaves(sk, leaves, G)
+    _, _, base, size = oracle.leaf_frame(sk, leaf, leaves)
+    assert np.array_equal(table[:, 12:16].copy().view(np.uint32).ravel(), size.astype(np.uint32))
+    assert np.array_equal(table[:, 8:12].copy().view(np.uint32).ravel(), base.astype(np.uint32))
+
+
+def test_spline_root_gain_on_clustered_keys():
+    """On the 64-cluster lognormal mixture a linear root leaves most leaves
+    empty and a few huge; the spline root spreads the keys by rank, so the
+    mean search window shrinks by far (the model's gain over the plain
+    linear root), and AUTO keeps the spline."""
+    n = 1 << 20
+    keys, rows = make("lognormal", n, seed=3)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        lin = min(ix.learn(n // 64, 2, LINEAR)["mean_window"], ix.learn(n // 64, 2, LOG)["mean_window"])
+        spl = ix.learn(n // 64, 2, SPLINE)["mean_window"]
+        auto = ix.learn(n // 64, 2, AUTO)
+    say(f"lognormal mean window: best linear root {lin:.1f}, spline {spl:.1f}, auto {auto['feature']}")
+    assert spl * 10 < lin
+    assert auto["feature"] == SPLINE

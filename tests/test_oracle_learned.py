@@ -109,3 +109,63 @@ def test_leaf_assignment_monotone(mode):
         # each leaf's first key has local feature 0 and local target 0
         first = base[size > 0].astype(np.int64)
         assert np.all(d[first] == 0) and np.all(y[first] == 0)
+
+
+# ------------------------------------------------------------ spline root
+
+def test_spline_segments_rule():
+    """The largest power of two G <= 4096 with G * 64 <= n and G * 8 <= L."""
+    big = 1 << 30
+    assert [oracle.spline_segments(n, big) for n in (1, 127, 128, 255, 256, 64 * 4096, 1 << 40)] == [1, 1, 2, 2, 4,
+                                                                                                      4096, 4096]
+    assert [oracle.spline_segments(big, L) for L in (1, 15, 16, 1000, 8 * 4096, 1 << 22)] == [1, 1, 2, 64, 4096,
+                                                                                              4096]
+
+
+def test_spline_leaves_pins():
+    """Knot keys land on the first leaf of their segment, the key list maps
+    monotonically onto [0, L), keys below the first knot go to leaf 0 and keys
+    above the last to L - 1, and evenly spaced keys fill every leaf with
+    n / L keys up to rounding."""
+    n, L = 1 << 16, 1000
+    sk = np.arange(1, n + 1, dtype=np.uint64) * np.uint64(977)
+    G = oracle.spline_segments(n, L)
+    leaf = oracle.spline_leaves(sk, L, G)
+    assert leaf[0] == 0 and leaf[-1] == L - 1
+    assert np.all(np.diff(leaf.astype(np.int64)) >= 0)
+    sizes = np.bincount(leaf, minlength=L)
+    # each segment holds n / G keys over floor or ceil of L / G (>= 8) leaves
+    per = n / L
+    assert sizes.min() >= per * (1 - 1 / 8) - 1 and sizes.max() <= per * (1 + 1 / 8) + 1
+    knot_ranks = (np.arange(G + 1, dtype=np.uint64) * np.uint64(n - 1)) // np.uint64(G)
+    first = (np.arange(G, dtype=np.uint64) * np.uint64(L)) // np.uint64(G)
+    assert np.array_equal(leaf[knot_ranks[:-1]], first.astype(np.uint32))
+    out = oracle.spline_leaves(sk, L, G, np.array([0, 976, sk[-1] + 1, (1 << 64) - 1], dtype=np.uint64))
+    assert list(out) == [0, 0, L - 1, L - 1]
+
+
+def test_spline_leaves_match_brute_force():
+    """Against the definition evaluated with numpy's float32 arithmetic, key
+    by key, on clustered keys with repeated knots."""
+    rng = np.random.default_rng(5)
+    sk = np.sort(np.concatenate([rng.integers(0, 1000, 3000), rng.integers(10 ** 12, 10 ** 12 + 50, 2000),
+                                 rng.integers(1 << 60, 1 << 61, 3000)]).astype(np.uint64))
+    n, L = len(sk), 333
+    G = oracle.spline_segments(n, L)
+    got = oracle.spline_leaves(sk, L, G)
+    knots = sk[(np.arange(G + 1, dtype=np.uint64) * np.uint64(n - 1)) // np.uint64(G)]
+    want = np.empty(n, dtype=np.uint32)
+    for i, k in enumerate(sk):
+        j = int(np.searchsorted(knots, k, side="right")) - 1
+        if j >= G:
+            want[i] = L - 1
+            continue
+        f0, f1 = (j * L) // G, ((j + 1) * L) // G
+        if f1 == f0:
+            want[i] = min(f0, L - 1)
+            continue
+        gap = int(knots[j + 1]) - int(knots[j])
+        s = np.float32(f1 - f0) / np.float32(gap)
+        f = np.float32(np.float32(int(k) - int(knots[j])) * s)
+        want[i] = f0 + (int(f) if f < np.float32(f1 - f0) else f1 - f0 - 1)
+    assert np.array_equal(got, want)
