@@ -280,13 +280,14 @@ int idx_get_params(idx_handle h, idx_lookup_params *out);
  * expensive step (Section 9) are the anchors.
  * ------------------------------------------------------------------------- */
 
-#define IDX_FEATURE_AUTO 0u   /* train both root features, keep the lower loss */
-#define IDX_FEATURE_LINEAR 1u /* root feature: the key scaled to [0, 1] */
-#define IDX_FEATURE_LOG 2u    /* root feature: bit pattern of the key rounded to FP32 (log-like) */
-#define IDX_FEATURE_SPLINE 3u /* piecewise-linear root through G + 1 equally spaced rank quantiles of
-                                 the keys (G <= 4096 segments with at least 64 keys and 8 leaves
-                                 each): leaves are spread by rank, so clustered key distributions
-                                 get even leaves */
+#define IDX_FEATURE_AUTO 0u   /* train a linear and a spline root, keep the lower estimated lookup cost */
+#define IDX_FEATURE_LINEAR 1u /* linear root over the key scaled to [0, 1] */
+#define IDX_FEATURE_LOG 2u    /* linear root over the bit pattern of the key rounded to FP32 (log-like) */
+#define IDX_FEATURE_SPLINE 3u /* piecewise-linear root over up to 2^16 equal bins of an exact integer
+                                 key feature (the key, or a log-like code), at least 64 keys per
+                                 bin; each bin takes leaves in proportion to its keys, so clustered
+                                 key distributions get even leaves.  One 16-byte bin record per
+                                 lookup. */
 
 typedef struct idx_learn_stats {
     uint32_t leaves;     /* L */
@@ -297,8 +298,8 @@ typedef struct idx_learn_stats {
     double leaf_loss;    /* sum of squared leaf residuals (target local rank) */
     double mean_window;  /* key-weighted mean search window (slots) */
     double max_window;   /* largest window of any leaf (slots) */
-    uint32_t segments;   /* spline root: segments G (0 for a linear root) */
-    uint32_t pad;
+    uint32_t segments;     /* spline root: bins in use (0 for a linear root) */
+    uint32_t bin_feature;  /* spline root: IDX_FEATURE_LINEAR or IDX_FEATURE_LOG bins (0 otherwise) */
 } idx_learn_stats;
 
 /*
@@ -314,8 +315,12 @@ typedef struct idx_learn_stats {
  *   h        an IDX_BS index (any storage: SoA, AoS or line-padded AoS, where
  *            the window scan reads each key with its row ID) with n >= 1
  *            (IDX_ERR_ARG otherwise)
- *   leaves   1 <= leaves <= 2^22;  epochs 1..16;  feature IDX_FEATURE_* (AUTO
- *            trains LINEAR and LOG and builds SPLINE, keeping the lowest root loss)
+ *   leaves   1 <= leaves <= 2^22;  epochs 1..16;  feature IDX_FEATURE_* (LINEAR
+ *            and LOG: that linear root; SPLINE: the spline root whose bin
+ *            feature has the lower root loss; AUTO: the better linear root and
+ *            the spline root each get trained leaves, and the one with the
+ *            lower log2(1 + mean window), plus 1 for the spline's bin record,
+ *            is kept -- a tie keeps the linear root)
  * Synchronises `stream`.  Errors: IDX_ERR_ARG, IDX_ERR_NOMEM, IDX_ERR_HIP.
  */
 int idx_learn(idx_handle h, uint32_t leaves, uint32_t epochs, uint32_t feature, idx_stream stream);

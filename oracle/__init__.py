@@ -65,8 +65,10 @@ def lib():
         L.orc_root_grad.argtypes = [_p, _p, _u64, _p, _p, _p, _p]
         L.orc_key_feature.restype = ctypes.c_float
         L.orc_key_feature.argtypes = [_u64, ctypes.c_uint32]
-        L.orc_spline_leaves.argtypes = [_p, _u64, ctypes.c_uint32, ctypes.c_uint32, _p, _u64, _p]
-        L.orc_spline_leaves.restype = None
+        L.orc_spline_build.argtypes = [_p, _u64, ctypes.c_uint32, ctypes.c_uint32, _p, _p, _p, _p, _p]
+        L.orc_spline_build.restype = None
+        L.orc_spline_assign.argtypes = [_p, ctypes.c_uint32, ctypes.c_uint32, _p, _p, _p, _p, _p, _u64, _p]
+        L.orc_spline_assign.restype = None
         L.orc_assign_leaves.argtypes = [_p, _u64, ctypes.c_uint32, ctypes.c_float, ctypes.c_float, ctypes.c_uint32,
                                         _p, _p]
         _lib = L
@@ -179,22 +181,35 @@ def assign_leaves(sorted_keys, mode: int, a0: float, a1: float, L: int):
     return leaf, x
 
 
-def spline_segments(n: int, L: int) -> int:
-    """Segments of the spline root for n keys and L leaves: the largest power
-    of two G <= 4096 with G * 64 <= n and G * 8 <= L (1 for tiny sets)."""
-    G = 1
-    while G < 4096 and G * 2 * 64 <= n and G * 2 * 8 <= L:
-        G *= 2
-    return G
+def spline_bins(n: int) -> int:
+    """Bins available to the spline root for n keys: the largest power of two
+    <= 65536 with at least 64 keys per bin (1 for tiny sets)."""
+    B = 1
+    while B < 65536 and B * 2 * 64 <= n:
+        B *= 2
+    return B
 
 
-def spline_leaves(sorted_keys, L: int, G: int, keys=None):
-    """Leaf of each key (default: the sorted keys themselves) under the spline
-    root built from `sorted_keys` with G segments and L leaves."""
+def spline_root(sorted_keys, L: int, bfeat: int) -> dict:
+    """The spline root over the sorted build keys with L leaves and bin feature
+    bfeat (1 = the key, 2 = the log-like code): geometry and bin records."""
     S = _u64arr(sorted_keys)
-    K = S if keys is None else _u64arr(keys)
-    leaf = np.empty(len(K), dtype=np.uint32)
-    lib().orc_spline_leaves(_ptr(S), len(S), L, G, _ptr(K), len(K), _ptr(leaf))
+    B = spline_bins(len(S))
+    geo = np.zeros(3, dtype=np.uint64)
+    anchor = np.zeros(B, dtype=np.uint64)
+    mul, first, sh = (np.zeros(B, dtype=np.uint32) for _ in range(3))
+    lib().orc_spline_build(_ptr(S), len(S), L, bfeat, _ptr(geo), _ptr(anchor), _ptr(mul), _ptr(first), _ptr(sh))
+    nb = int(geo[2])
+    return {"L": L, "bfeat": bfeat, "f_lo": int(geo[0]), "shift": int(geo[1]), "nb": nb, "geo": geo,
+            "anchor": anchor[:nb].copy(), "mul": mul[:nb].copy(), "first": first[:nb].copy(), "sh": sh[:nb].copy()}
+
+
+def spline_leaves(root: dict, keys):
+    """Leaf of each key under a spline root from spline_root."""
+    K = _u64arr(keys)
+    leaf = np.zeros(len(K), dtype=np.uint32)
+    lib().orc_spline_assign(_ptr(root["geo"]), root["bfeat"], root["L"], _ptr(root["anchor"]), _ptr(root["mul"]),
+                            _ptr(root["first"]), _ptr(root["sh"]), _ptr(K), len(K), _ptr(leaf))
     return leaf
 
 

@@ -284,65 +284,111 @@ void orc_assign_leaves(const uint64_t *keys, uint64_t n, uint32_t mode, float a0
     }
 }
 
-/* Spline root, written from its definition: knot j (j = 0..G) is the sorted
- * build key at rank floor(j (n - 1) / G); segment j owns the leaves
- * [floor(j L / G), floor((j + 1) L / G)).  A key k with knot_j <= k <
- * knot_(j+1) goes to leaf first_j + min(span_j - 1, trunc(f32(k - knot_j) *
- * s_j)), s_j = f32(span_j) / f32(knot_(j+1) - knot_j), every operation
- * rounded to single precision.  Keys below knot_0 go to leaf 0, keys at or
- * above knot_G to leaf L - 1, keys of a segment without leaves to its first
- * leaf index (capped at L - 1).  Leaves of the m keys `keys` are written. */
-void orc_spline_leaves(const uint64_t *sorted_keys, uint64_t n, uint32_t L, uint32_t G, const uint64_t *keys,
-                       uint64_t m, uint32_t *leaf_out)
+/* Spline root (our reading: a linear spline with knots at equal steps of an
+ * exact integer key feature; the paper's learned baseline fixes only the
+ * predict-then-search-the-window scheme, Section 8).
+ *
+ * Bin feature u(x): LINEAR u = x.  LOG u = e * 2^58 + floor((x - 2^e) * 2^58
+ * / 2^e) with e = floor(log2 x), and u(0) = 0.
+ * Geometry: B = the largest power of two <= 65536 with 64 B <= n; shift s =
+ * the smallest s with floor((u(kmax) - u(kmin)) / 2^s) < B; nb =
+ * floor((u(kmax) - u(kmin)) / 2^s) + 1.  bin(x) = 0 for u(x) <= u(kmin), else
+ * min(nb - 1, floor((u(x) - u(kmin)) / 2^s)).
+ * Bin b holds the build keys of ranks [r_b, r_(b+1)) and takes the leaves
+ * [f_b, f_(b+1)), f_b = floor(r_b L / n).  With keys and f_(b+1) > f_b, its
+ * anchor is its smallest key, w the distance from the anchor to the last key
+ * of the 64-bit range that still falls in bin b, sh the smallest shift with
+ * floor(w / 2^sh) < 2^32, and mul = min(2^32 - 1, floor((f_(b+1) - f_b) 2^32
+ * / (floor(w / 2^sh) + 1))); otherwise mul = 0.
+ * A key x of bin b goes to leaf min(L - 1, f_b + floor(floor(max(x - anchor,
+ * 0) / 2^sh) * mul / 2^32)). */
+static uint64_t orc_bin_feature(uint64_t x, uint32_t bfeat)
 {
-    uint64_t *knot = (uint64_t *)malloc(((size_t)G + 1) * sizeof(uint64_t));
-    float *scale = (float *)malloc(((size_t)G + 1) * sizeof(float));
-    if (!knot || !scale) {
-        free(knot);
-        free(scale);
-        return;
+    if (bfeat == 1 || x == 0) return x;
+    uint32_t e = 0;
+    while (e < 63 && (x >> (e + 1)) != 0) ++e; /* floor(log2 x) */
+    const uint64_t frac = x - ((uint64_t)1 << e); /* < 2^e */
+    const uint64_t m = e <= 58 ? frac << (58 - e) : frac >> (e - 58);
+    return ((uint64_t)e << 58) + m;
+}
+
+static uint32_t orc_bin(uint64_t x, uint32_t bfeat, uint64_t f_lo, uint32_t sh, uint32_t nb)
+{
+    const uint64_t u = orc_bin_feature(x, bfeat);
+    if (u <= f_lo || sh >= 64) return 0;
+    const uint64_t b = (u - f_lo) >> sh;
+    return b < nb ? (uint32_t)b : nb - 1;
+}
+
+/* The smallest key x with u(x) >= P (P <= u(2^64 - 1)), by inverting u. */
+static uint64_t orc_feature_floor_key(uint64_t P, uint32_t bfeat)
+{
+    if (bfeat == 1) return P;
+    const uint32_t e = (uint32_t)(P >> 58);
+    const uint64_t t = P & (((uint64_t)1 << 58) - 1);
+    const uint64_t lead = (uint64_t)1 << e;
+    if (e > 58) return lead + (t << (e - 58));
+    /* e <= 58: u is injective on [2^e, 2^(e+1)), x = 2^e + ceil(t / 2^(58 - e)) */
+    const uint32_t d = 58 - e;
+    uint64_t q = t >> d;
+    if (q << d != t) ++q;
+    if (q >= lead) return lead << 1; /* first key of the next binade */
+    return lead + q;
+}
+
+/* Build the spline root over the n sorted build keys with L leaves and bin
+ * feature bfeat (1 LINEAR, 2 LOG).  geo receives f_lo, shift, nb; anchor,
+ * mul, first and sh (bins records) must hold spline_bins(n) entries. */
+void orc_spline_build(const uint64_t *sorted_keys, uint64_t n, uint32_t L, uint32_t bfeat, uint64_t *geo,
+                      uint64_t *anchor, uint32_t *mul, uint32_t *first, uint32_t *shs)
+{
+    uint32_t B = 1;
+    while (B < 65536u && (uint64_t)B * 2 * 64 <= n) B <<= 1;
+    const uint64_t f_lo = orc_bin_feature(sorted_keys[0], bfeat);
+    const uint64_t span = orc_bin_feature(sorted_keys[n - 1], bfeat) - f_lo;
+    uint32_t sh = 0;
+    while (sh < 64 && (span >> sh) >= B) ++sh;
+    const uint32_t nb = sh >= 64 ? 1u : (uint32_t)(span >> sh) + 1u;
+    geo[0] = f_lo;
+    geo[1] = sh;
+    geo[2] = nb;
+    /* r_b by counting the keys of every bin */
+    uint64_t *r = (uint64_t *)calloc((size_t)nb + 1, sizeof(uint64_t));
+    if (!r) return;
+    for (uint64_t i = 0; i < n; ++i) r[orc_bin(sorted_keys[i], bfeat, f_lo, sh, nb) + 1] += 1;
+    for (uint32_t b = 0; b < nb; ++b) r[b + 1] += r[b];
+    for (uint32_t b = 0; b < nb; ++b) {
+        const uint64_t f0 = (r[b] * L) / n, f1 = (r[b + 1] * L) / n;
+        anchor[b] = r[b + 1] > r[b] ? sorted_keys[r[b]] : 0;
+        mul[b] = 0;
+        first[b] = (uint32_t)f0;
+        shs[b] = 0;
+        if (r[b + 1] == r[b] || f1 == f0) continue;
+        uint64_t w; /* distance from the anchor to the last key in bin b */
+        if (b + 1 == nb) w = UINT64_MAX - anchor[b];
+        else w = orc_feature_floor_key(f_lo + ((uint64_t)(b + 1) << sh), bfeat) - 1 - anchor[b];
+        uint32_t k = 0;
+        while ((w >> k) > 0xFFFFFFFFull) ++k;
+        const unsigned __int128 num = (unsigned __int128)(f1 - f0) << 32;
+        const unsigned __int128 m = num / ((w >> k) + 1);
+        mul[b] = m > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)m;
+        shs[b] = k;
     }
-    for (uint32_t j = 0; j <= G; ++j) knot[j] = sorted_keys[((uint64_t)j * (n - 1)) / G];
-    for (uint32_t j = 0; j < G; ++j) {
-        const uint32_t first = (uint32_t)(((uint64_t)j * L) / G);
-        const uint32_t next = (uint32_t)(((uint64_t)(j + 1) * L) / G);
-        const uint64_t gap = knot[j + 1] - knot[j];
-        volatile float num = (float)(next - first);
-        volatile float den = (float)gap;
-        scale[j] = gap ? num / den : 0.0f;
-    }
+    free(r);
+}
+
+/* Leaves of the m keys `keys` under a spline root built by orc_spline_build. */
+void orc_spline_assign(const uint64_t *geo, uint32_t bfeat, uint32_t L, const uint64_t *anchor, const uint32_t *mul,
+                       const uint32_t *first, const uint32_t *shs, const uint64_t *keys, uint64_t m,
+                       uint32_t *leaf_out)
+{
     for (uint64_t i = 0; i < m; ++i) {
-        const uint64_t k = keys[i];
-        uint32_t leaf;
-        if (k < knot[0]) {
-            leaf = 0;
-        } else {
-            /* last knot <= k: binary search over knot[0..G] */
-            uint32_t lo = 0, hi = G + 1; /* knot[lo] <= k, and every index >= hi is > k */
-            while (hi - lo > 1) {
-                const uint32_t mid = lo + (hi - lo) / 2;
-                if (knot[mid] <= k) lo = mid;
-                else hi = mid;
-            }
-            if (lo >= G) {
-                leaf = L - 1;
-            } else {
-                const uint32_t first = (uint32_t)(((uint64_t)lo * L) / G);
-                const uint32_t next = (uint32_t)(((uint64_t)(lo + 1) * L) / G);
-                if (next == first) {
-                    leaf = first < L ? first : L - 1;
-                } else {
-                    volatile float off = (float)(k - knot[lo]);
-                    volatile float f = off * scale[lo];
-                    const uint32_t span = next - first;
-                    leaf = first + (f < (float)span ? (uint32_t)f : span - 1);
-                }
-            }
-        }
-        leaf_out[i] = leaf;
+        const uint32_t b = orc_bin(keys[i], bfeat, geo[0], (uint32_t)geo[1], (uint32_t)geo[2]);
+        const uint64_t d = keys[i] > anchor[b] ? keys[i] - anchor[b] : 0;
+        const unsigned __int128 prod = (unsigned __int128)(d >> shs[b]) * mul[b];
+        const unsigned __int128 leaf = (unsigned __int128)first[b] + (prod >> 32);
+        leaf_out[i] = leaf < L ? (uint32_t)leaf : L - 1;
     }
-    free(knot);
-    free(scale);
 }
 
 /* Root line fit: loss, gradient and Hessian of sum (a*x + b - t)^2. */

@@ -93,7 +93,7 @@ class idx_learn_stats(ctypes.Structure):
         ("mean_window", ctypes.c_double),
         ("max_window", ctypes.c_double),
         ("segments", ctypes.c_uint32),
-        ("pad", ctypes.c_uint32),
+        ("bin_feature", ctypes.c_uint32),
     ]
 
 

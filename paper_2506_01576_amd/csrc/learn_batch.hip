@@ -6,9 +6,11 @@
 //
 // The keys of every index are cut into units of UNIT consecutive keys (one
 // workgroup each; a unit never straddles two indexes).  Root sums of all root
-// candidates (linear over either key feature, spline) are accumulated in one
-// pass; the candidate with the lowest loss is picked on the device, so the
-// whole sequence synchronises the host once, at the end, to read back the
+// candidates (linear over either key feature, spline over either bin feature)
+// are accumulated in one pass; within each family the lower loss is picked on
+// the device, and with both families the leaves are trained under each root
+// and the lower estimated lookup cost is kept, per index, also on the device.
+// The whole sequence synchronises the host once, at the end, to read back the
 // roots and statistics.
 #include <climits>
 
@@ -32,6 +34,7 @@ struct TDesc {
     uint64_t n;
     LeafRec *leaves;    // the index's model table
     uint64_t leaf_off;  // its first leaf in the accumulator arrays
+    SplineBin *spline;  // the index's spline bins (when a spline root may be kept)
     uint32_t L;
     uint32_t pad;
 };
@@ -43,8 +46,9 @@ struct Unit {
 };
 
 // Root candidates per index: 0 = linear over the LINEAR feature, 1 = linear
-// over the LOG feature, 2 = spline (bit c of cmask enables candidate c).
-constexpr int NCAND = 3;
+// over the LOG feature, 2 = spline over LINEAR bins, 3 = spline over LOG bins
+// (bit c of cmask enables candidate c).
+constexpr int NCAND = 4;
 
 template <typename K>
 __global__ __launch_bounds__(BT) void k_bt_root_accum(const Unit *__restrict__ units, const TDesc *__restrict__ d,
@@ -68,7 +72,7 @@ __global__ __launch_bounds__(BT) void k_bt_root_accum(const Unit *__restrict__ u
         for (int c = 0; c < NCAND; ++c) {
             if (!(cmask & (1u << c))) continue;
             float x, pred;
-            if (c == 2) {
+            if (c >= 2) {
                 x = 0.f;
                 (void)spline_leaf(R[c], key, &pred);
             } else {
@@ -111,43 +115,72 @@ __global__ void k_bt_root_update(RootRec *__restrict__ roots, const double *__re
     roots[NCAND * i + c].a1 = R.a1;
 }
 
-// Lowest final loss wins; the lower candidate number on a tie.
-__global__ void k_bt_root_pick(const RootRec *__restrict__ roots, const double *__restrict__ acc, uint32_t count,
-                               uint32_t cmask, RootRec *__restrict__ best, double *__restrict__ stats) {
+// Per family, the lowest final loss wins (the lower candidate number on a
+// tie): best_lin / best_sp and their losses in stats entry 3.  The spline
+// winner will read its bins from the index's own table; src gets the
+// scratch table they are copied from.
+__global__ void k_bt_root_pick(const RootRec *__restrict__ roots, const double *__restrict__ acc,
+                               const TDesc *__restrict__ d, uint32_t count, uint32_t cmask,
+                               RootRec *__restrict__ best_lin, RootRec *__restrict__ best_sp,
+                               const SplineBin **__restrict__ src, double *__restrict__ st_lin,
+                               double *__restrict__ st_sp) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    int f = -1;
-    double fl = 0.0;
-    for (int c = 0; c < NCAND; ++c) {
-        if (!(cmask & (1u << c))) continue;
-        const double l = acc[((uint64_t)NCAND * i + c) * NACC + 5];
-        if (f < 0 || l < fl) {
-            f = c;
-            fl = l;
+    for (int fam = 0; fam < 2; ++fam) {
+        int f = -1;
+        double fl = 0.0;
+        for (int c = 2 * fam; c < 2 * fam + 2; ++c) {
+            if (!(cmask & (1u << c))) continue;
+            const double l = acc[((uint64_t)NCAND * i + c) * NACC + 5];
+            if (f < 0 || l < fl) {
+                f = c;
+                fl = l;
+            }
+        }
+        if (f < 0) continue;
+        RootRec R = roots[NCAND * i + f];
+        if (fam == 0) {
+            best_lin[i] = R;
+            st_lin[(uint64_t)i * NST + 3] = fl;
+        } else {
+            src[i] = R.bins;
+            R.bins = d[i].spline;
+            best_sp[i] = R;
+            st_sp[(uint64_t)i * NST + 3] = fl;
         }
     }
-    best[i] = roots[NCAND * i + f];
-    stats[(uint64_t)i * NST + 3] = fl;
 }
 
-// Spline knots and scales of every index with a spline candidate (one
-// workgroup per index).
+// Spline geometry of candidates 2 and 3 of every index (one thread each).
 template <typename K>
-__global__ void k_bt_spline(const TDesc *__restrict__ d, const RootRec *__restrict__ roots) {
-    const TDesc D = d[blockIdx.x];
-    const RootRec R = roots[NCAND * blockIdx.x + 2];
-    if (R.G == 0) return;
-    const K *keys = (const K *)D.keys;
-    uint64_t *knots = (uint64_t *)R.knots;
-    float *scale = (float *)R.scale;
-    for (uint32_t j = threadIdx.x; j <= R.G; j += blockDim.x)
-        knots[j] = (uint64_t)keys[((uint64_t)j * (D.n - 1)) / R.G];
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < R.G; j += blockDim.x) {
-        const uint64_t gap = knots[j + 1] - knots[j];
-        const uint32_t span = seg_leaf(j + 1, R.L, R.G) - seg_leaf(j, R.L, R.G);
-        scale[j] = gap ? __fdiv_rn((float)span, (float)gap) : 0.f;
-    }
+__global__ void k_bt_spline_geometry(const TDesc *__restrict__ d, RootRec *__restrict__ roots, uint32_t count,
+                                     uint32_t cmask) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = t / 2, c = 2 + t % 2;
+    if (i >= count || !(cmask & (1u << c))) return;
+    const K *keys = (const K *)d[i].keys;
+    spline_geometry(roots[NCAND * i + c], (uint64_t)keys[0], (uint64_t)keys[d[i].n - 1], d[i].n);
+}
+
+// Bins of spline candidate 2 + blockIdx.z of index blockIdx.x, one thread per
+// bin, into the candidate's scratch table.
+template <typename K>
+__global__ void k_bt_spline_bins(const TDesc *__restrict__ d, const RootRec *__restrict__ roots, uint32_t cmask) {
+    const uint32_t i = blockIdx.x, c = 2 + blockIdx.z;
+    if (!(cmask & (1u << c))) return;
+    const RootRec R = roots[NCAND * i + c];
+    const uint32_t b = blockIdx.y * blockDim.x + threadIdx.x;
+    if (b >= R.nb) return;
+    const K *keys = (const K *)d[i].keys;
+    ((SplineBin *)R.bins)[b] = spline_bin([&](uint64_t r) { return (uint64_t)keys[r]; }, d[i].n, R, b);
+}
+
+// The winning spline bins into each index's own table.
+__global__ void k_bt_copy_bins(const RootRec *__restrict__ best_sp, const SplineBin *const *__restrict__ src) {
+    const uint32_t i = blockIdx.x;
+    const uint32_t b = blockIdx.y * blockDim.x + threadIdx.x;
+    const RootRec R = best_sp[i];
+    if (b < R.nb) ((SplineBin *)R.bins)[b] = src[i][b];
 }
 
 __global__ void k_bt_zero(double *p, uint64_t count) {
@@ -358,6 +391,30 @@ __global__ __launch_bounds__(256) void k_bt_leaf_finish(const TDesc *__restrict_
     atomicAdd(&st[2], acc[g * NACC + 5]);
 }
 
+// With both root families: per index, the lower estimated lookup cost wins
+// (a tie keeps the linear root); the final root and statistics.
+__global__ void k_bt_choose(const TDesc *__restrict__ d, uint32_t count, const RootRec *__restrict__ best_lin,
+                            const RootRec *__restrict__ best_sp, const double *__restrict__ st_lin,
+                            const double *__restrict__ st_sp, RootRec *__restrict__ best, double *__restrict__ stats,
+                            uint32_t *__restrict__ pick) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const double n = (double)d[i].n;
+    const bool sp = window_cost(st_sp[(uint64_t)i * NST] / n, true) < window_cost(st_lin[(uint64_t)i * NST] / n, false);
+    pick[i] = sp ? 1u : 0u;
+    best[i] = sp ? best_sp[i] : best_lin[i];
+    for (int j = 0; j < NST; ++j) stats[(uint64_t)i * NST + j] = sp ? st_sp[(uint64_t)i * NST + j] : st_lin[(uint64_t)i * NST + j];
+}
+
+// Leaves trained under a chosen spline root replace the linear root's.
+__global__ void k_bt_copy_leaves(const TDesc *__restrict__ d, uint32_t count, uint64_t total,
+                                 const LeafRec *__restrict__ alt, const uint32_t *__restrict__ pick) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const uint32_t i = leaf_owner(d, count, g);
+    if (pick[i]) d[i].leaves[g - d[i].leaf_off] = alt[g];
+}
+
 uint32_t blocks_for(uint64_t threads, uint32_t block) {
     uint64_t b = (threads + block - 1) / block;
     if (b == 0) b = 1;
@@ -368,95 +425,158 @@ uint32_t blocks_for(uint64_t threads, uint32_t block) {
 template <typename K>
 int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, uint32_t epochs, uint32_t feature,
                   hipStream_t s) {
-    std::vector<TDesc> desc(count);
+    const bool want_lin = feature != IDX_FEATURE_SPLINE, want_sp = feature == IDX_FEATURE_AUTO ||
+                                                                   feature == IDX_FEATURE_SPLINE;
+    const bool both = want_lin && want_sp;
+    std::vector<TDesc> desc(count), desc_alt;
     std::vector<Unit> units;
-    uint64_t total_leaves = 0;
+    std::vector<uint64_t> bin_off(count);
+    uint64_t total_leaves = 0, total_bins = 0;
+    uint32_t max_bins = 1;
     for (uint32_t i = 0; i < count; ++i) {
         const idx_index *h = hs[i];
-        desc[i] = TDesc{h->keys, h->n, h->learned->leaves, total_leaves, leaves[i], 0};
+        desc[i] = TDesc{h->keys, h->n, h->learned->leaves, total_leaves, h->learned->spline, leaves[i], 0};
         total_leaves += leaves[i];
+        bin_off[i] = total_bins;
+        if (want_sp) {
+            total_bins += spline_bins(h->n);
+            max_bins = spline_bins(h->n) > max_bins ? spline_bins(h->n) : max_bins;
+        }
         for (uint64_t b = 0; b < h->n; b += UNIT) units.push_back(Unit{b, b + UNIT < h->n ? b + UNIT : h->n, i, 0});
     }
     if (units.size() > 0x7FFFFFFFull) return IDX_ERR_ARG;
     const uint32_t nunits = (uint32_t)units.size();
     auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t b_desc = up(sizeof(TDesc) * count), b_units = up(sizeof(Unit) * nunits);
-    const size_t b_roots2 = up(sizeof(RootRec) * NCAND * count), b_best = up(sizeof(RootRec) * count);
+    const size_t b_roots = up(sizeof(RootRec) * NCAND * count), b_best = up(sizeof(RootRec) * count);
     const size_t b_racc = up(sizeof(double) * NCAND * NACC * count), b_stats = up(sizeof(double) * NST * count);
     const size_t b_lacc = up(sizeof(double) * NACC * total_leaves), b_cnt = up(sizeof(uint32_t) * total_leaves);
+    const size_t b_bins = up(sizeof(SplineBin) * 2 * total_bins), b_src = up(sizeof(void *) * count);
+    const size_t b_alt = both ? up(sizeof(LeafRec) * total_leaves) : 0, b_pick = up(sizeof(uint32_t) * count);
     const Alloc &A = hs[0]->alloc;
-    char *tmp = (char *)A.get(b_desc + b_units + b_roots2 + b_best + b_racc + b_stats + b_lacc + b_cnt, s);
+    const size_t total_b = 2 * b_desc + b_units + b_roots + 3 * b_best + b_racc + 3 * b_stats + b_lacc + b_cnt +
+                           b_bins + b_src + b_alt + b_pick;
+    char *tmp = (char *)A.get(total_b, s);
     if (!tmp) return IDX_ERR_NOMEM;
-    TDesc *d_desc = (TDesc *)tmp;
-    Unit *d_units = (Unit *)(tmp + b_desc);
-    RootRec *d_roots2 = (RootRec *)(tmp + b_desc + b_units);
-    RootRec *d_best = (RootRec *)((char *)d_roots2 + b_roots2);
-    double *d_racc = (double *)((char *)d_best + b_best);
-    double *d_stats = (double *)((char *)d_racc + b_racc);
-    double *d_lacc = (double *)((char *)d_stats + b_stats);
-    uint32_t *d_cnt = (uint32_t *)((char *)d_lacc + b_lacc);
-    const uint32_t cmask = feature == IDX_FEATURE_AUTO ? 7u : (1u << (feature - 1));
-    std::vector<RootRec> roots2((size_t)NCAND * count);
+    char *p = tmp;
+    auto take = [&](size_t b) { char *q = p; p += b; return q; };
+    TDesc *d_desc = (TDesc *)take(b_desc);
+    TDesc *d_desc_alt = (TDesc *)take(b_desc);
+    Unit *d_units = (Unit *)take(b_units);
+    RootRec *d_roots = (RootRec *)take(b_roots);
+    RootRec *d_best = (RootRec *)take(b_best);
+    RootRec *d_best_lin = (RootRec *)take(b_best);
+    RootRec *d_best_sp = (RootRec *)take(b_best);
+    double *d_racc = (double *)take(b_racc);
+    double *d_stats = (double *)take(b_stats);
+    double *d_st_lin = (double *)take(b_stats);
+    double *d_st_sp = (double *)take(b_stats);
+    double *d_lacc = (double *)take(b_lacc);
+    uint32_t *d_cnt = (uint32_t *)take(b_cnt);
+    SplineBin *d_bins = (SplineBin *)take(b_bins);
+    const SplineBin **d_src = (const SplineBin **)take(b_src);
+    LeafRec *d_alt = (LeafRec *)take(b_alt);
+    uint32_t *d_pick = (uint32_t *)take(b_pick);
+    uint32_t cmask = 0;
+    if (feature == IDX_FEATURE_AUTO) cmask = 15u;
+    else if (feature == IDX_FEATURE_SPLINE) cmask = 12u;
+    else cmask = 1u << (feature - 1);
+    std::vector<RootRec> roots((size_t)NCAND * count);
     for (uint32_t i = 0; i < count; ++i) {
-        roots2[NCAND * i] = RootRec{0.f, 0.f, IDX_FEATURE_LINEAR, leaves[i], nullptr, nullptr, 0, 0};
-        roots2[NCAND * i + 1] = RootRec{0.f, 0.f, IDX_FEATURE_LOG, leaves[i], nullptr, nullptr, 0, 0};
-        RootRec sp{0.f, 0.f, IDX_FEATURE_SPLINE, leaves[i], nullptr, nullptr, 0, 0};
-        if (hs[i]->learned->spline) {
-            sp.G = spline_segments(hs[i]->n, leaves[i]);
-            sp.knots = (const uint64_t *)hs[i]->learned->spline;
-            sp.scale = (const float *)((const char *)hs[i]->learned->spline + spline_knot_bytes(sp.G));
+        for (int c = 0; c < NCAND; ++c) {
+            RootRec R{};
+            R.L = leaves[i];
+            if (c < 2) {
+                R.mode = c == 0 ? IDX_FEATURE_LINEAR : IDX_FEATURE_LOG;
+            } else {
+                R.mode = IDX_FEATURE_SPLINE;
+                R.bfeat = c == 2 ? IDX_FEATURE_LINEAR : IDX_FEATURE_LOG;
+                R.bins = d_bins + (c == 2 ? 0 : total_bins) + bin_off[i];
+            }
+            roots[(size_t)NCAND * i + c] = R;
         }
-        roots2[NCAND * i + 2] = sp;
+    }
+    if (both) {
+        desc_alt = desc;
+        for (uint32_t i = 0; i < count; ++i) desc_alt[i].leaves = d_alt + desc[i].leaf_off;
     }
     std::vector<RootRec> best(count);
     std::vector<double> stats((size_t)NST * count);
+    // the leaf stage under the roots `br` into the tables of `dd`, statistics
+    // (entries 0-2) into `st`
+    auto leaf_stage = [&](const TDesc *dd, const RootRec *br, double *st) {
+        hipLaunchKernelGGL(k_bt_zero_u32, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, d_cnt, total_leaves);
+        hipLaunchKernelGGL((k_bt_leaf_count<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br, d_cnt);
+        hipLaunchKernelGGL((k_bt_leaf_layout<K>), dim3(count), dim3(1024), 0, s, dd, d_cnt);
+        for (uint32_t ep = 0; ep <= epochs; ++ep) {
+            hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for((uint64_t)NACC * total_leaves, 256)), dim3(256), 0, s,
+                               d_lacc, (uint64_t)NACC * total_leaves);
+            hipLaunchKernelGGL((k_bt_leaf_accum<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br, d_lacc);
+            if (ep < epochs)
+                hipLaunchKernelGGL(k_bt_leaf_update, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd, count,
+                                   total_leaves, d_lacc);
+        }
+        hipLaunchKernelGGL((k_bt_leaf_errors<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br);
+        hipLaunchKernelGGL(k_bt_leaf_finish, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd, count,
+                           total_leaves, d_lacc, st);
+    };
     int rc = IDX_OK;
     do {
         if (hipMemcpyAsync(d_desc, desc.data(), sizeof(TDesc) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(d_units, units.data(), sizeof(Unit) * nunits, hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipMemcpyAsync(d_roots2, roots2.data(), sizeof(RootRec) * NCAND * count, hipMemcpyHostToDevice, s) !=
-                hipSuccess) {
+            hipMemcpyAsync(d_roots, roots.data(), sizeof(RootRec) * NCAND * count, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            (both && hipMemcpyAsync(d_desc_alt, desc_alt.data(), sizeof(TDesc) * count, hipMemcpyHostToDevice, s) !=
+                         hipSuccess)) {
             rc = IDX_ERR_HIP;
             break;
         }
         // ---- stage 1: root candidates -- the two linear roots take `epochs`
-        // Newton steps, the spline is built from rank quantiles -- and the
-        // final loss of each
-        if (cmask & 4u) hipLaunchKernelGGL((k_bt_spline<K>), dim3(count), dim3(256), 0, s, d_desc, d_roots2);
+        // Newton steps, the two spline roots are built from the keys' ranks
+        // -- and the final loss of each
+        if (want_sp) {
+            hipLaunchKernelGGL((k_bt_spline_geometry<K>), dim3(blocks_for(2ull * count, 256)), dim3(256), 0, s, d_desc,
+                               d_roots, count, cmask);
+            hipLaunchKernelGGL((k_bt_spline_bins<K>), dim3(count, (max_bins + 255) / 256, 2), dim3(256), 0, s, d_desc,
+                               d_roots, cmask);
+        }
         for (uint32_t ep = 0; ep <= epochs; ++ep) {
             hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for((uint64_t)NCAND * NACC * count, 256)), dim3(256), 0, s,
                                d_racc, (uint64_t)NCAND * NACC * count);
-            hipLaunchKernelGGL((k_bt_root_accum<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_roots2, cmask,
+            hipLaunchKernelGGL((k_bt_root_accum<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_roots, cmask,
                                d_racc);
             if (ep < epochs && (cmask & 3u))
-                hipLaunchKernelGGL(k_bt_root_update, dim3(blocks_for(2ull * count, 256)), dim3(256), 0, s, d_roots2,
+                hipLaunchKernelGGL(k_bt_root_update, dim3(blocks_for(2ull * count, 256)), dim3(256), 0, s, d_roots,
                                    d_racc, count, cmask);
         }
-        hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for((uint64_t)NST * count, 256)), dim3(256), 0, s, d_stats,
+        hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for((uint64_t)NST * count, 256)), dim3(256), 0, s, d_st_lin,
                            (uint64_t)NST * count);
-        hipLaunchKernelGGL(k_bt_root_pick, dim3(blocks_for(count, 256)), dim3(256), 0, s, d_roots2, d_racc, count,
-                           cmask, d_best, d_stats);
-        // ---- stage 2: leaves
-        hipLaunchKernelGGL(k_bt_zero_u32, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, d_cnt, total_leaves);
-        hipLaunchKernelGGL((k_bt_leaf_count<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_best, d_cnt);
-        hipLaunchKernelGGL((k_bt_leaf_layout<K>), dim3(count), dim3(1024), 0, s, d_desc, d_cnt);
-        for (uint32_t ep = 0; ep <= epochs; ++ep) {
-            hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for((uint64_t)NACC * total_leaves, 256)), dim3(256), 0, s,
-                               d_lacc, (uint64_t)NACC * total_leaves);
-            hipLaunchKernelGGL((k_bt_leaf_accum<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_best, d_lacc);
-            if (ep < epochs)
-                hipLaunchKernelGGL(k_bt_leaf_update, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, d_desc,
-                                   count, total_leaves, d_lacc);
+        hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for((uint64_t)NST * count, 256)), dim3(256), 0, s, d_st_sp,
+                           (uint64_t)NST * count);
+        hipLaunchKernelGGL(k_bt_root_pick, dim3(blocks_for(count, 256)), dim3(256), 0, s, d_roots, d_racc, d_desc,
+                           count, cmask, d_best_lin, d_best_sp, d_src, d_st_lin, d_st_sp);
+        if (want_sp)
+            hipLaunchKernelGGL(k_bt_copy_bins, dim3(count, (max_bins + 255) / 256), dim3(256), 0, s, d_best_sp, d_src);
+        // ---- stage 2: leaves under each family's root; with both, the lower
+        // estimated lookup cost wins per index
+        RootRec *d_final = want_lin ? d_best_lin : d_best_sp;
+        double *d_final_st = want_lin ? d_st_lin : d_st_sp;
+        leaf_stage(d_desc, d_final, d_final_st);
+        if (both) {
+            leaf_stage(d_desc_alt, d_best_sp, d_st_sp);
+            hipLaunchKernelGGL(k_bt_choose, dim3(blocks_for(count, 256)), dim3(256), 0, s, d_desc, count, d_best_lin,
+                               d_best_sp, d_st_lin, d_st_sp, d_best, d_stats, d_pick);
+            hipLaunchKernelGGL(k_bt_copy_leaves, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, d_desc, count,
+                               total_leaves, d_alt, d_pick);
+            d_final = d_best;
+            d_final_st = d_stats;
         }
-        hipLaunchKernelGGL((k_bt_leaf_errors<K>), dim3(nunits), dim3(BT), 0, s, d_units, d_desc, d_best);
-        hipLaunchKernelGGL(k_bt_leaf_finish, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, d_desc, count,
-                           total_leaves, d_lacc, d_stats);
         if (hipGetLastError() != hipSuccess) {
             rc = IDX_ERR_HIP;
             break;
         }
-        if (hipMemcpyAsync(best.data(), d_best, sizeof(RootRec) * count, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipMemcpyAsync(stats.data(), d_stats, sizeof(double) * NST * count, hipMemcpyDeviceToHost, s) !=
+        if (hipMemcpyAsync(best.data(), d_final, sizeof(RootRec) * count, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(stats.data(), d_final_st, sizeof(double) * NST * count, hipMemcpyDeviceToHost, s) !=
                 hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             rc = IDX_ERR_HIP;
@@ -477,7 +597,8 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
         M->stats.leaf_loss = stats[(size_t)i * NST + 2];
         M->stats.mean_window = stats[(size_t)i * NST + 0] / (double)hs[i]->n;
         M->stats.max_window = stats[(size_t)i * NST + 1];
-        M->stats.segments = best[i].mode == IDX_FEATURE_SPLINE ? best[i].G : 0;
+        M->stats.segments = best[i].mode == IDX_FEATURE_SPLINE ? best[i].nb : 0;
+        M->stats.bin_feature = best[i].mode == IDX_FEATURE_SPLINE ? best[i].bfeat : 0;
         if (best[i].mode != IDX_FEATURE_SPLINE && M->spline) {
             hs[i]->alloc.put(M->spline, s);
             M->spline = nullptr;
@@ -503,10 +624,8 @@ int learn_batch(idx_index *const *hs, uint32_t count, const uint32_t *leaves, ui
         drop_model(h, s);
         LearnedModel *M = new (std::nothrow) LearnedModel();
         if (M) M->leaves = (LeafRec *)h->alloc.get((size_t)leaves[i] * sizeof(LeafRec), s);
-        if (M && M->leaves && (feature == IDX_FEATURE_AUTO || feature == IDX_FEATURE_SPLINE)) {
-            const uint32_t G = spline_segments(h->n, leaves[i]);
-            M->spline = h->alloc.get(spline_knot_bytes(G) + (size_t)G * sizeof(float), s);
-        }
+        if (M && M->leaves && (feature == IDX_FEATURE_AUTO || feature == IDX_FEATURE_SPLINE))
+            M->spline = (SplineBin *)h->alloc.get((size_t)spline_bins(h->n) * sizeof(SplineBin), s);
         if (!M || !M->leaves || ((feature == IDX_FEATURE_AUTO || feature == IDX_FEATURE_SPLINE) && !M->spline)) {
             if (M && M->leaves) h->alloc.put(M->leaves, s);
             delete M;

@@ -272,22 +272,19 @@ __global__ void k_sum_leaf_loss(const double *__restrict__ acc, uint32_t L, doub
     if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(out, s);
 }
 
-// Spline root: knot j is the sorted key at rank floor(j (n - 1) / G).
+// Spline root geometry from the smallest and largest build key (one thread).
 template <typename K, bool AOS>
-__global__ void k_spline_knots(Load<K, AOS> keys, uint64_t n, uint32_t G, uint64_t *__restrict__ knots) {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j > G) return;
-    knots[j] = (uint64_t)keys.key(((uint64_t)j * (n - 1)) / G);
+__global__ void k_spline_geometry(Load<K, AOS> keys, uint64_t n, RootRec *R) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) spline_geometry(*R, (uint64_t)keys.key(0), (uint64_t)keys.key(n - 1), n);
 }
 
-// Leaves of segment j per unit of key offset: span / f32(knot j+1 - knot j),
-// correctly rounded; 0 for an empty segment (equal knots).
-__global__ void k_spline_scale(const uint64_t *__restrict__ knots, uint32_t G, uint32_t L, float *__restrict__ scale) {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= G) return;
-    const uint64_t d = knots[j + 1] - knots[j];
-    const uint32_t span = seg_leaf(j + 1, L, G) - seg_leaf(j, L, G);
-    scale[j] = d ? __fdiv_rn((float)span, (float)d) : 0.f;
+// Spline root bins, one thread per bin.
+template <typename K, bool AOS>
+__global__ void k_spline_bins(Load<K, AOS> keys, uint64_t n, const RootRec *Rp, SplineBin *__restrict__ bins) {
+    const RootRec R = *Rp;
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= R.nb) return;
+    bins[b] = spline_bin([&](uint64_t i) { return (uint64_t)keys.key(i); }, n, R, b);
 }
 
 uint32_t grid_for(uint64_t threads, uint32_t block) {
@@ -325,12 +322,16 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
     const uint64_t n = h->n;
     const Load<K, AOS> keys = make_load<K, AOS>(h);
     LearnedModel *M = h->learned;
+    const bool want_lin = feature != IDX_FEATURE_SPLINE, want_sp = feature == IDX_FEATURE_AUTO ||
+                                                                   feature == IDX_FEATURE_SPLINE;
+    const bool both = want_lin && want_sp;
     // device scratch: root record, root acc, leaf acc, stats, counts and scan
-    // partials; every region starts on a 256-byte boundary (FP64 atomics need
-    // 8-byte alignment)
+    // partials, and (both root families) a second leaf table; every region
+    // starts on a 256-byte boundary (FP64 atomics need 8-byte alignment)
     auto up256 = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t leaf_acc_b = up256((size_t)L * NACC * sizeof(double));
-    char *tmp = (char *)h->alloc.get(256 + 256 + leaf_acc_b + 256 + layout_scratch_bytes(L), s);
+    const size_t alt_b = both ? up256((size_t)L * sizeof(LeafRec)) : 0;
+    char *tmp = (char *)h->alloc.get(256 + 256 + leaf_acc_b + 256 + layout_scratch_bytes(L) + alt_b, s);
     if (!tmp) return IDX_ERR_NOMEM;
     RootRec *d_root = (RootRec *)tmp;
     double *root_acc = (double *)(tmp + 256);
@@ -338,71 +339,113 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
     double *stats = (double *)(tmp + 512 + leaf_acc_b);
     unsigned long long *count = (unsigned long long *)(tmp + 512 + leaf_acc_b + 256);
     uint64_t *partial = (uint64_t *)((char *)count + up256(((size_t)L + 1) * 8));
-    int rc = IDX_OK;
+    LeafRec *alt = both ? (LeafRec *)(tmp + 512 + leaf_acc_b + 256 + layout_scratch_bytes(L)) : nullptr;
     const uint32_t rblocks = (uint32_t)((n + LT * 8 - 1) / (LT * 8)) > 2048 ? 2048u
                                                                              : (uint32_t)((n + LT * 8 - 1) / (LT * 8));
     const uint32_t cblocks = grid_for((n + CHUNK - 1) / CHUNK, LT);
-    do {
-        // ---- stage 1: the root, for each candidate; keep the lower loss.  A
-        // linear root takes `epochs` Newton steps; the spline root is built
-        // from the keys' rank quantiles and only its loss is measured.
-        RootRec best{};
-        double best_loss = -1.0;
-        for (uint32_t mode = IDX_FEATURE_LINEAR; mode <= IDX_FEATURE_SPLINE; ++mode) {
-            if (feature != IDX_FEATURE_AUTO && feature != mode) continue;
-            RootRec R{0.f, 0.f, mode, L, nullptr, nullptr, 0, 0};
-            uint32_t ep_n = epochs;
-            if (mode == IDX_FEATURE_SPLINE) {
-                R.G = spline_segments(n, L);
-                R.knots = (const uint64_t *)M->spline;
-                R.scale = (const float *)((const char *)M->spline + spline_knot_bytes(R.G));
-                hipLaunchKernelGGL((k_spline_knots<K, AOS>), dim3(grid_for((uint64_t)R.G + 1, 256)), dim3(256), 0, s,
-                                   keys, n, R.G, (uint64_t *)R.knots);
-                hipLaunchKernelGGL(k_spline_scale, dim3(grid_for(R.G, 256)), dim3(256), 0, s, R.knots, R.G, L,
-                                   (float *)R.scale);
-                ep_n = 0;
-            }
-            if (hipMemcpyAsync(d_root, &R, sizeof(R), hipMemcpyHostToDevice, s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
-            for (uint32_t ep = 0; ep <= ep_n; ++ep) {
-                hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, root_acc, (uint64_t)NACC);
-                hipLaunchKernelGGL((k_root_accum<K, AOS>), dim3(rblocks ? rblocks : 1), dim3(LT), 0, s, keys, n, d_root,
-                                   root_acc);
-                if (ep < ep_n) hipLaunchKernelGGL(k_root_update, dim3(1), dim3(64), 0, s, d_root, root_acc);
-            }
-            double acc[NACC];
-            RootRec R2;
-            if (hipMemcpyAsync(acc, root_acc, sizeof(acc), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipMemcpyAsync(&R2, d_root, sizeof(R2), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
-            if (best_loss < 0 || acc[5] < best_loss) {
-                best_loss = acc[5];
-                best = R2;
-            }
-        }
-        if (rc != IDX_OK) break;
-        M->root = best;
-        M->stats.root_loss = best_loss;
-        if (hipMemcpyAsync(d_root, &best, sizeof(best), hipMemcpyHostToDevice, s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
 
-        // ---- stage 2: leaves
-        rc = leaf_layout<K, AOS>(keys, n, d_root, L, count, partial, M->leaves, s);
-        if (rc != IDX_OK) break;
+    // One root candidate: place R on the device (a spline candidate also gets
+    // its geometry and bins), take `ep_n` Newton steps, measure the loss.
+    auto candidate = [&](RootRec R, uint32_t ep_n, RootRec &out, double &loss) -> int {
+        if (hipMemcpyAsync(d_root, &R, sizeof(R), hipMemcpyHostToDevice, s) != hipSuccess) return IDX_ERR_HIP;
+        if (R.mode == IDX_FEATURE_SPLINE) {
+            hipLaunchKernelGGL((k_spline_geometry<K, AOS>), dim3(1), dim3(64), 0, s, keys, n, d_root);
+            hipLaunchKernelGGL((k_spline_bins<K, AOS>), dim3(grid_for(spline_bins(n), 256)), dim3(256), 0, s, keys, n,
+                               d_root, M->spline);
+        }
+        for (uint32_t ep = 0; ep <= ep_n; ++ep) {
+            hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, root_acc, (uint64_t)NACC);
+            hipLaunchKernelGGL((k_root_accum<K, AOS>), dim3(rblocks ? rblocks : 1), dim3(LT), 0, s, keys, n, d_root,
+                               root_acc);
+            if (ep < ep_n) hipLaunchKernelGGL(k_root_update, dim3(1), dim3(64), 0, s, d_root, root_acc);
+        }
+        double acc[NACC];
+        if (hipMemcpyAsync(acc, root_acc, sizeof(acc), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&out, d_root, sizeof(out), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return IDX_ERR_HIP;
+        loss = acc[5];
+        return IDX_OK;
+    };
+    // Leaves under root R into `leaves`: layout, Newton steps, error bounds;
+    // st = {sum of window * size, max window, leaf loss}.
+    auto leaves_for = [&](const RootRec &R, LeafRec *leaves, double st[4]) -> int {
+        if (hipMemcpyAsync(d_root, &R, sizeof(R), hipMemcpyHostToDevice, s) != hipSuccess) return IDX_ERR_HIP;
+        int rc = leaf_layout<K, AOS>(keys, n, d_root, L, count, partial, leaves, s);
+        if (rc != IDX_OK) return rc;
         for (uint32_t ep = 0; ep <= epochs; ++ep) {
             hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((uint64_t)L * NACC, 256)), dim3(256), 0, s, leaf_acc,
                                (uint64_t)L * NACC);
-            hipLaunchKernelGGL((k_leaf_accum<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, M->leaves,
+            hipLaunchKernelGGL((k_leaf_accum<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
                                leaf_acc);
             if (ep < epochs)
-                hipLaunchKernelGGL(k_leaf_update, dim3(grid_for(L, 256)), dim3(256), 0, s, M->leaves, leaf_acc, L);
+                hipLaunchKernelGGL(k_leaf_update, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_acc, L);
         }
         hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, stats, (uint64_t)4);
         hipLaunchKernelGGL(k_sum_leaf_loss, dim3(64), dim3(256), 0, s, leaf_acc, L, stats + 2);
-        hipLaunchKernelGGL((k_leaf_errors<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, M->leaves);
-        hipLaunchKernelGGL(k_leaf_finish, dim3(grid_for(L, 256)), dim3(256), 0, s, M->leaves, L, stats);
-        if (hipGetLastError() != hipSuccess) { rc = IDX_ERR_HIP; break; }
-        double st[4];
-        if (hipMemcpyAsync(st, stats, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) { rc = IDX_ERR_HIP; break; }
+        hipLaunchKernelGGL((k_leaf_errors<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves);
+        hipLaunchKernelGGL(k_leaf_finish, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, L, stats);
+        if (hipGetLastError() != hipSuccess) return IDX_ERR_HIP;
+        if (hipMemcpyAsync(st, stats, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return IDX_ERR_HIP;
+        return IDX_OK;
+    };
+
+    int rc = IDX_OK;
+    do {
+        // ---- stage 1: roots.  A linear root takes `epochs` Newton steps over
+        // either key feature; a spline root is built from the keys' ranks over
+        // either bin feature.  Within each family the lower loss wins.
+        RootRec best_lin{}, best_sp{};
+        double loss_lin = -1.0, loss_sp = -1.0;
+        for (uint32_t f = IDX_FEATURE_LINEAR; f <= IDX_FEATURE_LOG && rc == IDX_OK; ++f) {
+            RootRec R{}, got;
+            double loss;
+            R.L = L;
+            if (want_lin && (feature == IDX_FEATURE_AUTO || feature == f)) {
+                R.mode = f;
+                if ((rc = candidate(R, epochs, got, loss)) != IDX_OK) break;
+                if (loss_lin < 0 || loss < loss_lin) { loss_lin = loss; best_lin = got; }
+            }
+            if (want_sp) {
+                R.mode = IDX_FEATURE_SPLINE;
+                R.bins = M->spline;
+                R.bfeat = f;
+                if ((rc = candidate(R, 0, got, loss)) != IDX_OK) break;
+                if (loss_sp < 0 || loss < loss_sp) { loss_sp = loss; best_sp = got; }
+            }
+        }
+        if (rc != IDX_OK) break;
+        if (want_sp && best_sp.bfeat != IDX_FEATURE_LOG) {  // the table holds the last bins built: rebuild the winner
+            if (hipMemcpyAsync(d_root, &best_sp, sizeof(best_sp), hipMemcpyHostToDevice, s) != hipSuccess) {
+                rc = IDX_ERR_HIP;
+                break;
+            }
+            hipLaunchKernelGGL((k_spline_bins<K, AOS>), dim3(grid_for(spline_bins(n), 256)), dim3(256), 0, s, keys, n,
+                               d_root, M->spline);
+        }
+
+        // ---- stage 2: leaves under each family's root; with both, the lower
+        // estimated lookup cost wins
+        double st[4], st2[4];
+        bool sp = !want_lin;
+        if ((rc = leaves_for(want_lin ? best_lin : best_sp, M->leaves, st)) != IDX_OK) break;
+        if (both) {
+            if ((rc = leaves_for(best_sp, alt, st2)) != IDX_OK) break;
+            if (window_cost(st2[0] / (double)n, true) < window_cost(st[0] / (double)n, false)) {
+                sp = true;
+                for (int j = 0; j < 4; ++j) st[j] = st2[j];
+                if (hipMemcpyAsync(M->leaves, alt, (size_t)L * sizeof(LeafRec), hipMemcpyDeviceToDevice, s) !=
+                        hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess) {
+                    rc = IDX_ERR_HIP;
+                    break;
+                }
+            }
+        }
+        M->root = sp ? best_sp : best_lin;
+        M->stats.root_loss = sp ? loss_sp : loss_lin;
         M->stats.leaf_loss = st[2];
         M->stats.mean_window = n ? st[0] / (double)n : 0.0;
         M->stats.max_window = st[1];
@@ -421,8 +464,7 @@ int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream
     if (!M) return IDX_ERR_NOMEM;
     M->leaves = (LeafRec *)h->alloc.get((size_t)L * sizeof(LeafRec), s);
     if (M->leaves && (feature == IDX_FEATURE_AUTO || feature == IDX_FEATURE_SPLINE)) {
-        const uint32_t G = spline_segments(h->n, L);
-        M->spline = h->alloc.get(spline_knot_bytes(G) + (size_t)G * sizeof(float), s);
+        M->spline = (SplineBin *)h->alloc.get((size_t)spline_bins(h->n) * sizeof(SplineBin), s);
         if (!M->spline) {
             h->alloc.put(M->leaves, s);
             M->leaves = nullptr;
@@ -445,7 +487,8 @@ int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream
     M->stats.feature = M->root.mode;
     M->stats.root_a0 = M->root.a0;
     M->stats.root_a1 = M->root.a1;
-    M->stats.segments = M->root.mode == IDX_FEATURE_SPLINE ? M->root.G : 0;
+    M->stats.segments = M->root.mode == IDX_FEATURE_SPLINE ? M->root.nb : 0;
+    M->stats.bin_feature = M->root.mode == IDX_FEATURE_SPLINE ? M->root.bfeat : 0;
     if (M->root.mode != IDX_FEATURE_SPLINE && M->spline) {
         h->alloc.put(M->spline, s);
         M->spline = nullptr;

@@ -7,16 +7,27 @@
 
 namespace idx {
 
+// One bin of the spline root: a key x of the bin goes to leaf
+// first + ((max(x - anchor, 0) >> shift) * mul) >> 32, at most L - 1.
+struct __align__(16) SplineBin {
+    uint64_t anchor;       // smallest build key of the bin (0 for an empty bin)
+    uint32_t mul;          // leaves per key offset, 32-bit fixed point
+    uint32_t first_shift;  // bits 0-23: first leaf of the bin; bits 24-31: shift
+};
+static_assert(sizeof(SplineBin) == 16, "spline bin is 16 bytes");
+
 struct RootRec {
     float a0, a1;           // linear roots: t = a1 * x + a0, leaf = clamp(floor(t), 0, L - 1)
     uint32_t mode;          // IDX_FEATURE_LINEAR / IDX_FEATURE_LOG / IDX_FEATURE_SPLINE
     uint32_t L;
-    const uint64_t *knots;  // spline: G + 1 keys, the sorted keys at ranks floor(j (n - 1) / G)
-    const float *scale;     // spline: per segment, its leaves per unit of key offset
-    uint32_t G;             // spline: segments, a power of two
+    const SplineBin *bins;  // spline: nb bin records
+    uint64_t f_lo;          // spline: bin feature of the smallest build key
+    uint32_t shift;         // spline: bin = (feature - f_lo) >> shift (64: a single bin)
+    uint32_t nb;            // spline: bins in use
+    uint32_t bfeat;         // spline: bin feature, IDX_FEATURE_LINEAR or IDX_FEATURE_LOG
     uint32_t pad;
 };
-static_assert(sizeof(RootRec) == 40, "root record is 40 bytes");
+static_assert(sizeof(RootRec) == 48, "root record is 48 bytes");
 
 struct __align__(16) LeafRec {
     uint64_t kmin;     // smallest build key of the leaf (0 when empty)
@@ -30,7 +41,7 @@ static_assert(sizeof(LeafRec) == 32, "leaf record is 32 bytes");
 struct LearnedModel {
     RootRec root{};
     LeafRec *leaves = nullptr;  // device, L records
-    void *spline = nullptr;     // device: G + 1 knot keys, then G scales (spline root only)
+    SplineBin *spline = nullptr;  // device: the spline root's bins (spline root only)
     idx_learn_stats stats{};
 };
 
@@ -47,49 +58,113 @@ __device__ __forceinline__ float key_feature(uint64_t key, uint32_t mode) {
     return (float)__float_as_uint(f) * 0x1p-31f;
 }
 
-// Spline segments for n keys and L leaves: the largest power of two G <= 4096
-// with at least 64 keys and 8 leaves per segment (1 for tiny sets).
-inline uint32_t spline_segments(uint64_t n, uint32_t L) {
-    uint32_t G = 1;
-    while (G < 4096 && (uint64_t)G * 2 * 64 <= n && (uint64_t)G * 2 * 8 <= L) G <<= 1;
-    return G;
+// Bins of the spline root for n keys: the largest power of two <= 65536 with
+// at least 64 keys per bin (1 for tiny sets).
+__host__ __device__ inline uint32_t spline_bins(uint64_t n) {
+    uint32_t B = 1;
+    while (B < 65536u && (uint64_t)B * 2 * 64 <= n) B <<= 1;
+    return B;
 }
 
-// Bytes of the G + 1 knot keys (256-byte aligned, the scales follow).
-inline size_t spline_knot_bytes(uint32_t G) { return (((size_t)G + 1) * 8 + 255) & ~(size_t)255; }
-
-// First leaf of spline segment j: segments share the L leaves as evenly as
-// integers allow.
-__host__ __device__ __forceinline__ uint32_t seg_leaf(uint32_t j, uint32_t L, uint32_t G) {
-    return (uint32_t)(((uint64_t)j * L) / G);
+// Integer key features of the spline bins, both exact and non-decreasing.
+// LINEAR: the key.  LOG: floor(log2 key) in bits 58-63, then the 58 bits
+// below the key's leading one (a 64-bit float-like code; 0 and 1 map to 0).
+__host__ __device__ __forceinline__ uint64_t bin_feature(uint64_t key, uint32_t bfeat) {
+    if (bfeat == IDX_FEATURE_LINEAR || key == 0) return key;
+    const uint32_t e = 63u - (uint32_t)__builtin_clzll(key);
+    return ((uint64_t)e << 58) | (((key << (63 - e)) << 1) >> 6);
 }
 
-// Spline root: the segment j of the last knot <= key gives leaves
-// [seg_leaf(j), seg_leaf(j + 1)); inside it the leaf offset is
-// f32(key - knot j) * scale[j], truncated (one rounding each).  Non-decreasing
-// in the key, so each leaf's keys are one rank interval.
+__host__ __device__ __forceinline__ uint32_t bin_of(const RootRec &R, uint64_t key) {
+    const uint64_t u = bin_feature(key, R.bfeat);
+    if (u <= R.f_lo || R.shift >= 64) return 0;
+    const uint64_t b = (u - R.f_lo) >> R.shift;
+    return b < R.nb ? (uint32_t)b : R.nb - 1;
+}
+
+// The bin geometry for build keys kmin..kmax: nb = ((f(kmax) - f(kmin)) >>
+// shift) + 1 bins with the smallest shift that keeps nb <= spline_bins(n).
+__host__ __device__ inline void spline_geometry(RootRec &R, uint64_t kmin, uint64_t kmax, uint64_t n) {
+    const uint32_t B = spline_bins(n);
+    R.f_lo = bin_feature(kmin, R.bfeat);
+    const uint64_t span = bin_feature(kmax, R.bfeat) - R.f_lo;
+    uint32_t sh = 0;
+    while (sh < 64 && (span >> sh) >= B) ++sh;
+    R.shift = sh;
+    R.nb = sh >= 64 ? 1u : (uint32_t)(span >> sh) + 1u;
+}
+
+// Spline root: one bin record, then a fixed-point product.  Non-decreasing in
+// the key: inside a bin by construction, and across bins because the bin's
+// multiplier keeps every key below the bin's upper boundary under the next
+// bin's first leaf.  coord, when asked for, is the unrounded leaf coordinate.
 __device__ __forceinline__ uint32_t spline_leaf(const RootRec &R, uint64_t key, float *coord = nullptr) {
-    const uint64_t *K = R.knots;
-    if (key < K[0]) {
-        if (coord) *coord = 0.f;
-        return 0;
+    const SplineBin r = R.bins[bin_of(R, key)];
+    const uint64_t d = key > r.anchor ? key - r.anchor : 0ull;
+    const uint32_t sh = r.first_shift >> 24;
+    const uint64_t prod = (uint64_t)(uint32_t)(d >> sh) * (uint64_t)r.mul;
+    const uint64_t leaf = (uint64_t)(r.first_shift & 0xFFFFFFu) + (prod >> 32);
+    if (coord) *coord = __fadd_rn((float)(r.first_shift & 0xFFFFFFu), __fmul_rn((float)prod, 0x1p-32f));
+    return leaf < R.L ? (uint32_t)leaf : R.L - 1;
+}
+
+// Estimated lookup cost of a trained model, to choose between a linear and a
+// spline root: the binary-search steps over the key-weighted mean window, plus
+// one for the spline root's bin record.  A tie keeps the linear root.
+__host__ __device__ inline double window_cost(double mean_window, bool spline) {
+    return log2(1.0 + mean_window) + (spline ? 1.0 : 0.0);
+}
+
+// Smallest key whose bin is at least b (1 <= b < nb): a binary search over the
+// 64-bit key range of the non-decreasing bin function.
+__host__ __device__ inline uint64_t bin_lower_key(const RootRec &R, uint32_t b) {
+    uint64_t lo = 0, hi = ~0ull;  // bin(hi) >= b always (b < nb)
+    while (lo < hi) {
+        const uint64_t mid = lo + ((hi - lo) >> 1);
+        if (bin_of(R, mid) >= b) hi = mid;
+        else lo = mid + 1;
     }
-    uint32_t j = 0;
-    for (uint32_t h = R.G; h > 0; h >>= 1)
-        if (j + h <= R.G && K[j + h] <= key) j += h;
-    if (j >= R.G) {
-        if (coord) *coord = (float)R.L;
-        return R.L - 1;
+    return lo;
+}
+
+// Record of bin b over n sorted keys (key(i) reads rank i).  Ranks r_b (keys
+// in bins below b) come from binary searches; the bin takes the leaves
+// [floor(r_b L / n), floor(r_b+1 L / n)).  Its multiplier is the largest
+// 32-bit fixed-point value that maps the bin's whole key range, up to the
+// next bin's lower boundary, below that span.
+template <typename KeyAt>
+__host__ __device__ inline SplineBin spline_bin(const KeyAt &key, uint64_t n, const RootRec &R, uint32_t b) {
+    auto rank_below = [&](uint32_t bin) -> uint64_t {  // keys with bin < `bin`
+        if (bin == 0) return 0;
+        if (bin >= R.nb) return n;
+        uint64_t lo = 0, len = n;
+        while (len > 0) {
+            const uint64_t half = len >> 1;
+            if (bin_of(R, key(lo + half)) < bin) {
+                lo += half + 1;
+                len -= half + 1;
+            } else {
+                len = half;
+            }
+        }
+        return lo;
+    };
+    const uint64_t r0 = rank_below(b), r1 = rank_below(b + 1);
+    const uint64_t f0 = (r0 * R.L) / n, f1 = (r1 * R.L) / n;
+    SplineBin out{0ull, 0u, (uint32_t)f0};
+    if (r1 == r0 || f1 == f0) {
+        if (r1 > r0) out.anchor = key(r0);
+        return out;
     }
-    const uint32_t f0 = seg_leaf(j, R.L, R.G), f1 = seg_leaf(j + 1, R.L, R.G);
-    if (f1 == f0) {
-        if (coord) *coord = (float)f0;
-        return f0 < R.L ? f0 : R.L - 1;
-    }
-    const float f = __fmul_rn((float)(key - K[j]), R.scale[j]);
-    const uint32_t span = f1 - f0;
-    if (coord) *coord = __fadd_rn((float)f0, f < (float)span ? f : (float)span);
-    return f0 + (f < (float)span ? (uint32_t)f : span - 1);
+    out.anchor = key(r0);
+    const uint64_t wm1 = b + 1 >= R.nb ? ~out.anchor : bin_lower_key(R, b + 1) - 1 - out.anchor;
+    uint32_t sh = 0;
+    while ((wm1 >> sh) > 0xFFFFFFFFull) ++sh;
+    const uint64_t ws = (wm1 >> sh) + 1;  // <= 2^32
+    const uint64_t m = ((f1 - f0) << 32) / ws;
+    out.mul = m > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)m;
+    out.first_shift = (uint32_t)f0 | (sh << 24);
+    return out;
 }
 
 // Multiply, then add, each rounded on its own (no contraction), so the same

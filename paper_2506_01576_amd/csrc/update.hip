@@ -116,9 +116,9 @@ struct BlobHeader {
     idx_learn_stats stats;
 };
 
-// Bytes of a spline root's table (knot keys, then scales); 0 for a linear root.
+// Bytes of a spline root's bin records; 0 for a linear root.
 uint64_t spline_bytes(const RootRec &R) {
-    return R.mode == IDX_FEATURE_SPLINE ? spline_knot_bytes(R.G) + (uint64_t)R.G * sizeof(float) : 0;
+    return R.mode == IDX_FEATURE_SPLINE ? (uint64_t)R.nb * sizeof(SplineBin) : 0;
 }
 
 uint64_t blob_size(const idx_index *h) {
@@ -253,7 +253,10 @@ int idx_load(const void *blob, uint64_t size, const idx_allocator *alloc, idx_st
                                               hd.root.L != hd.leaves || hd.root.mode == 0 ||
                                               hd.root.mode > IDX_FEATURE_SPLINE ||
                                               (hd.root.mode == IDX_FEATURE_SPLINE &&
-                                               hd.root.G != spline_segments(hd.n, hd.leaves)))))
+                                               (hd.root.nb == 0 || hd.root.nb > spline_bins(hd.n) ||
+                                                hd.root.shift > 64 || (hd.root.shift == 64 && hd.root.nb != 1) ||
+                                                (hd.root.bfeat != IDX_FEATURE_LINEAR &&
+                                                 hd.root.bfeat != IDX_FEATURE_LOG))))))
         return IDX_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
     idx_index *h = nullptr;
@@ -274,7 +277,7 @@ int idx_load(const void *blob, uint64_t size, const idx_allocator *alloc, idx_st
     if (e == hipSuccess && hd.has_model) {
         LearnedModel *M = new (std::nothrow) LearnedModel();
         if (M) M->leaves = (LeafRec *)h->alloc.get(leaf_b, s);
-        if (M && M->leaves && spl_b) M->spline = h->alloc.get(spl_b, s);
+        if (M && M->leaves && spl_b) M->spline = (SplineBin *)h->alloc.get(spl_b, s);
         if (!M || !M->leaves || (spl_b && !M->spline)) {
             if (M && M->leaves) h->alloc.put(M->leaves, s);
             delete M;
@@ -282,12 +285,7 @@ int idx_load(const void *blob, uint64_t size, const idx_allocator *alloc, idx_st
             return IDX_ERR_NOMEM;
         }
         M->root = hd.root;
-        M->root.knots = nullptr;
-        M->root.scale = nullptr;
-        if (spl_b) {
-            M->root.knots = (const uint64_t *)M->spline;
-            M->root.scale = (const float *)((const char *)M->spline + spline_knot_bytes(M->root.G));
-        }
+        M->root.bins = spl_b ? M->spline : nullptr;
         M->stats = hd.stats;
         h->learned = M;
         e = hipMemcpyAsync(M->leaves, p, leaf_b, hipMemcpyHostToDevice, s);

@@ -90,8 +90,9 @@ def test_learn_batch_exact(bits, feature):
         # leaf partition under the exported root
         table = ix.learn_export().cpu().numpy().view(np.uint8).reshape(L, 32)
         if st["feature"] == 3:  # spline root
-            assert st["segments"] == oracle.spline_segments(len(sk), L)
-            leaf = oracle.spline_leaves(sk, L, st["segments"])
+            root = oracle.spline_root(sk, L, st["bin_feature"])
+            assert st["segments"] == root["nb"]
+            leaf = oracle.spline_leaves(root, sk)
         else:
             leaf, _ = oracle.assign_leaves(sk, st["feature"], st["root_a0"], st["root_a1"], L)
         _, _, base, size = oracle.leaf_frame(sk, leaf, L)

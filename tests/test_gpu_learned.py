@@ -47,7 +47,9 @@ def oracle_leaves(sk, st, L):
     """The oracle's leaf of every sorted key under the trained root described
     by the model statistics st (linear root or spline)."""
     if st["feature"] == SPLINE:
-        return oracle.spline_leaves(sk, L, st["segments"])
+        root = oracle.spline_root(sk, L, st["bin_feature"])
+        assert root["nb"] == st["segments"]
+        return oracle.spline_leaves(root, sk)
     return oracle.assign_leaves(sk, st["feature"], st["root_a0"], st["root_a1"], L)[0]
 
 
@@ -270,23 +272,25 @@ def test_model_narrows_the_search():
 
 @pytest.mark.parametrize("kind", ["uniform64", "lognormal", "dup", "uniform32"])
 @pytest.mark.parametrize("leaves", [1, 64, 5000, 1 << 15])
-def test_spline_root_partition_matches_oracle(kind, leaves):
+@pytest.mark.parametrize("aos", [False, True])
+def test_spline_root_partition_matches_oracle(kind, leaves, aos):
     """The spline root's leaf partition (base rank and size of every leaf)
-    equals the oracle's evaluation of the same definition; the segment count
-    follows its rule."""
+    equals the oracle's evaluation of the same definition over the bin feature
+    the trainer kept, with the same number of bins; lookups stay exact."""
     n = 200003
     keys, rows = make(kind, n, seed=leaves)
-    sk, _ = oracle.stable_sort(keys, rows)
-    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+    sk, sr = oracle.stable_sort(keys, rows)
+    q = queries(keys, 20000, leaves)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs", aos=aos) as ix:
         st = ix.learn(leaves, 2, SPLINE)
-        assert st["feature"] == SPLINE
-        G = oracle.spline_segments(n, leaves)
-        assert st["segments"] == G
+        assert st["feature"] == SPLINE and st["bin_feature"] in (LINEAR, LOG)
         table = ix.learn_export().cpu().numpy().view(np.uint8).reshape(leaves, 32)
-    leaf = oracle.spline_leaves(sk, leaves, G)
+        got = rows_host(ix.point(to_dev(q)))
+    leaf = oracle_leaves(sk, st, leaves)
     _, _, base, size = oracle.leaf_frame(sk, leaf, leaves)
     assert np.array_equal(table[:, 12:16].copy().view(np.uint32).ravel(), size.astype(np.uint32))
     assert np.array_equal(table[:, 8:12].copy().view(np.uint32).ravel(), base.astype(np.uint32))
+    assert np.array_equal(got, oracle.point(sk, sr, q, nthreads=4))
 
 
 def test_spline_root_gain_on_clustered_keys():
@@ -302,4 +306,18 @@ def test_spline_root_gain_on_clustered_keys():
         auto = ix.learn(n // 64, 2, AUTO)
     say(f"lognormal mean window: best linear root {lin:.1f}, spline {spl:.1f}, auto {auto['feature']}")
     assert spl * 10 < lin
-    assert auto["feature"] == SPLINE
+    assert auto["feature"] == SPLINE and auto["mean_window"] == spl
+
+
+def test_auto_keeps_linear_root_on_uniform_keys():
+    """On uniform keys a linear root already gives the spline's windows, so
+    AUTO keeps the root without the bin record (a tie keeps the linear root)."""
+    n = 1 << 20
+    keys, rows = make("uniform64", n, seed=4)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        lin = ix.learn(n // 64, 2, LINEAR)["mean_window"]
+        spl = ix.learn(n // 64, 2, SPLINE)["mean_window"]
+        auto = ix.learn(n // 64, 2, AUTO)
+    say(f"uniform mean window: linear {lin:.2f}, spline {spl:.2f}, auto {auto['feature']}")
+    assert np.log2(1 + lin) <= np.log2(1 + spl) + 1
+    assert auto["feature"] == LINEAR and auto["segments"] == 0

@@ -2,6 +2,8 @@
 reports are checked against central finite differences of its loss, and
 against numpy's least-squares solver (where the gradient must vanish); the
 root feature and leaf assignment against their defining properties."""
+import struct
+
 import numpy as np
 import pytest
 
@@ -113,59 +115,133 @@ def test_leaf_assignment_monotone(mode):
 
 # ------------------------------------------------------------ spline root
 
-def test_spline_segments_rule():
-    """The largest power of two G <= 4096 with G * 64 <= n and G * 8 <= L."""
-    big = 1 << 30
-    assert [oracle.spline_segments(n, big) for n in (1, 127, 128, 255, 256, 64 * 4096, 1 << 40)] == [1, 1, 2, 2, 4,
-                                                                                                      4096, 4096]
-    assert [oracle.spline_segments(big, L) for L in (1, 15, 16, 1000, 8 * 4096, 1 << 22)] == [1, 1, 2, 64, 4096,
-                                                                                              4096]
+def test_spline_bins_rule():
+    """The largest power of two <= 65536 with at least 64 keys per bin."""
+    assert [oracle.spline_bins(n) for n in (1, 127, 128, 255, 256, 64 * 4096, 64 * 65536, 1 << 40)] == [
+        1, 1, 2, 2, 4, 4096, 65536, 65536]
 
 
-def test_spline_leaves_pins():
-    """Knot keys land on the first leaf of their segment, the key list maps
-    monotonically onto [0, L), keys below the first knot go to leaf 0 and keys
-    above the last to L - 1, and evenly spaced keys fill every leaf with
-    n / L keys up to rounding."""
-    n, L = 1 << 16, 1000
-    sk = np.arange(1, n + 1, dtype=np.uint64) * np.uint64(977)
-    G = oracle.spline_segments(n, L)
-    leaf = oracle.spline_leaves(sk, L, G)
-    assert leaf[0] == 0 and leaf[-1] == L - 1
-    assert np.all(np.diff(leaf.astype(np.int64)) >= 0)
-    sizes = np.bincount(leaf, minlength=L)
-    # each segment holds n / G keys over floor or ceil of L / G (>= 8) leaves
-    per = n / L
-    assert sizes.min() >= per * (1 - 1 / 8) - 1 and sizes.max() <= per * (1 + 1 / 8) + 1
-    knot_ranks = (np.arange(G + 1, dtype=np.uint64) * np.uint64(n - 1)) // np.uint64(G)
-    first = (np.arange(G, dtype=np.uint64) * np.uint64(L)) // np.uint64(G)
-    assert np.array_equal(leaf[knot_ranks[:-1]], first.astype(np.uint32))
-    out = oracle.spline_leaves(sk, L, G, np.array([0, 976, sk[-1] + 1, (1 << 64) - 1], dtype=np.uint64))
-    assert list(out) == [0, 0, L - 1, L - 1]
+def _double_code(x):
+    """The log-like bin feature read off the IEEE-754 double encoding of x
+    (exact for x < 2^53 and for x with at most 53 significant bits): the
+    unbiased exponent above 58 bits of fraction."""
+    if x == 0:
+        return 0
+    bits = struct.unpack("<Q", struct.pack("<d", float(x)))[0]
+    assert int(float(x)) == x
+    return (((bits >> 52) - 1023) << 58) | ((bits & ((1 << 52) - 1)) << 6)
 
 
-def test_spline_leaves_match_brute_force():
-    """Against the definition evaluated with numpy's float32 arithmetic, key
-    by key, on clustered keys with repeated knots."""
-    rng = np.random.default_rng(5)
-    sk = np.sort(np.concatenate([rng.integers(0, 1000, 3000), rng.integers(10 ** 12, 10 ** 12 + 50, 2000),
-                                 rng.integers(1 << 60, 1 << 61, 3000)]).astype(np.uint64))
-    n, L = len(sk), 333
-    G = oracle.spline_segments(n, L)
-    got = oracle.spline_leaves(sk, L, G)
-    knots = sk[(np.arange(G + 1, dtype=np.uint64) * np.uint64(n - 1)) // np.uint64(G)]
-    want = np.empty(n, dtype=np.uint32)
-    for i, k in enumerate(sk):
-        j = int(np.searchsorted(knots, k, side="right")) - 1
-        if j >= G:
-            want[i] = L - 1
+def test_spline_log_feature_is_the_double_encoding():
+    """f_lo of a one-key root is the bin feature of that key; for LOG it must
+    equal the exponent and fraction bits of the key as an IEEE double."""
+    rng = np.random.default_rng(3)
+    xs = [0, 1, 2, 3, 5, 1000, (1 << 52) + 1, (1 << 53) - 1, 1 << 63, ((1 << 53) - 1) << 11]
+    xs += [int(v) for v in rng.integers(1, 1 << 53, 200, dtype=np.uint64)]
+    xs += [int(v) << int(e) for v, e in zip(rng.integers(1, 1 << 53, 100, dtype=np.uint64), rng.integers(0, 11, 100))]
+    for x in xs:
+        r = oracle.spline_root(np.array([x], dtype=np.uint64), 4, 2)
+        assert r["f_lo"] == _double_code(x), x
+        assert oracle.spline_root(np.array([x], dtype=np.uint64), 4, 1)["f_lo"] == x
+
+
+def _brute_spline(sk, L, bfeat, queries, domain):
+    """The spline root on a small key domain: bins of every key of the domain
+    by scanning, bin boundaries and ranks by counting, then the bin records."""
+    n = len(sk)
+    B = 1
+    while B < 65536 and B * 2 * 64 <= n:
+        B *= 2
+    u = (lambda x: x) if bfeat == 1 else _double_code
+    f_lo = u(int(sk[0]))
+    span = u(int(sk[-1])) - f_lo
+    sh = next(t for t in range(65) if t == 64 or (span >> t) < B)
+    nb = 1 if sh == 64 else (span >> sh) + 1
+
+    def bin_of(x):
+        v = u(x)
+        if v <= f_lo or sh == 64:
+            return 0
+        return min(nb - 1, (v - f_lo) >> sh)
+
+    bins = [bin_of(x) for x in range(domain)]
+    lower = {}
+    for x, b in enumerate(bins):
+        for c in range(1, b + 1):
+            lower.setdefault(c, x)
+    rank = [sum(1 for k in sk if bin_of(int(k)) < b) for b in range(nb + 1)]
+    out = []
+    for q in queries:
+        q = int(q)
+        b = bin_of(q)
+        f0, f1 = rank[b] * L // n, rank[b + 1] * L // n
+        if rank[b + 1] == rank[b] or f1 == f0:
+            out.append(min(f0, L - 1))
             continue
-        f0, f1 = (j * L) // G, ((j + 1) * L) // G
-        if f1 == f0:
-            want[i] = min(f0, L - 1)
-            continue
-        gap = int(knots[j + 1]) - int(knots[j])
-        s = np.float32(f1 - f0) / np.float32(gap)
-        f = np.float32(np.float32(int(k) - int(knots[j])) * s)
-        want[i] = f0 + (int(f) if f < np.float32(f1 - f0) else f1 - f0 - 1)
-    assert np.array_equal(got, want)
+        anchor = int(sk[rank[b]])
+        w = (1 << 64) - 1 - anchor if b + 1 == nb else lower[b + 1] - 1 - anchor
+        k = 0
+        while (w >> k) >= 1 << 32:
+            k += 1
+        mul = min((1 << 32) - 1, ((f1 - f0) << 32) // ((w >> k) + 1))
+        d = max(q - anchor, 0)
+        out.append(min(L - 1, f0 + (((d >> k) * mul) >> 32)))
+    return np.array(out, dtype=np.uint32), nb
+
+
+@pytest.mark.parametrize("bfeat", [1, 2])
+@pytest.mark.parametrize("case", ["uniform", "clusters", "tiny", "equal"])
+def test_spline_leaves_match_brute_force(bfeat, case):
+    rng = np.random.default_rng(11)
+    domain = 1 << 12
+    if case == "uniform":
+        sk = np.sort(rng.integers(0, domain, 3000))
+    elif case == "clusters":
+        sk = np.sort(np.concatenate([rng.integers(3, 40, 900), rng.integers(700, 760, 1500),
+                                     rng.integers(3000, 4095, 600)]))
+    elif case == "tiny":
+        sk = np.sort(rng.integers(1, domain, 9))
+    else:
+        sk = np.full(500, 1234)
+    sk = sk.astype(np.uint64)
+    for L in (1, 5, 64, 333):
+        root = oracle.spline_root(sk, L, bfeat)
+        want, nb = _brute_spline(sk, L, bfeat, range(domain), domain)
+        assert root["nb"] == nb
+        assert np.array_equal(oracle.spline_leaves(root, np.arange(domain, dtype=np.uint64)), want)
+
+
+@pytest.mark.parametrize("bfeat", [1, 2])
+def test_spline_partition_invariants(bfeat):
+    """On lognormal-mixture keys (n = 2^18) and uniform keys: the leaf is
+    non-decreasing over build keys and over arbitrary keys between them; each
+    bin's keys stay inside the leaves it owns, [floor(r_b L / n),
+    floor(r_(b+1) L / n)), so the leaf of the key at rank i is at most
+    floor(i L / n) + the bins it shares; and the largest leaf is within a small
+    factor of n / L where the bins resolve the distribution."""
+    for kind in ("lognormal", "uniform"):
+        if kind == "lognormal":
+            keys, _ = gen.lognormal_keys(7, 1 << 18)
+        else:
+            keys, _ = gen.unique_keys(7, 1 << 18, 64, 63)
+        sk = np.sort(keys)
+        n = len(sk)
+        for L in (1 << 10, 1 << 12):
+            root = oracle.spline_root(sk, L, bfeat)
+            leaf = oracle.spline_leaves(root, sk)
+            assert leaf[0] == 0 and int(leaf.max()) <= L - 1
+            assert np.all(np.diff(leaf.astype(np.int64)) >= 0)
+            rng = np.random.default_rng(L)
+            q = np.sort(np.concatenate([sk - np.uint64(1), sk + np.uint64(1), rng.integers(0, 1 << 63, 5000,
+                                                                                          dtype=np.uint64),
+                                        np.array([0, (1 << 64) - 1], dtype=np.uint64)]))
+            ql = oracle.spline_leaves(root, q)
+            assert np.all(np.diff(ql.astype(np.int64)) >= 0)
+            # rank-proportional: the first key of leaf l has rank within one
+            # bin's keys of l n / L
+            sizes = np.bincount(leaf, minlength=L)
+            starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+            ideal = np.arange(L) * n / L
+            if kind == "uniform" or bfeat == 2:
+                assert sizes.max() <= 4 * n / L, (kind, bfeat, L, sizes.max())
+                assert np.max(np.abs(starts[sizes > 0] - ideal[sizes > 0])) <= 4 * n / L
