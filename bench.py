@@ -249,9 +249,11 @@ def run_skewed(args, idx, gen, np, torch, dev, log):
     forms, answers = {}, {}
     base = idx.Index(keys, rows, layout="bs")
     _, _, laos, lp = autotune.choose(1 << 26, 64, "learned")
-    for name, L, aos, params in (("learned_4096", 4096, False, {"per_lane": 8}),
-                                 ("learned_tuned", lp.get("leaves", 1 << 22), laos,
-                                  {"per_lane": lp.get("per_lane", 8)})):
+    cands = [("learned_4096", 4096, False, {"per_lane": 8}),
+             ("learned_tuned", lp.get("leaves", 1 << 22), laos, {"per_lane": lp.get("per_lane", 8)})]
+    if laos:  # the tuned leaf count on the plain sorted array too
+        cands.append(("learned_tuned_soa", lp.get("leaves", 1 << 22), False, {"per_lane": lp.get("per_lane", 8)}))
+    for name, L, aos, params in cands:
         arr = base if not aos else base.relayout("bs", 1, aos)
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
@@ -263,7 +265,10 @@ def run_skewed(args, idx, gen, np, torch, dev, log):
         ms, res = timed(arr)
         forms[name] = {"leaves": L, "aos": aos, "ms": round(ms, 4), "lookups_per_s": m / ms * 1e3,
                        "train_ms": round(a.elapsed_time(b), 3), "mean_window": st["mean_window"],
-                       "max_window": st["max_window"]}
+                       "max_window": st["max_window"],
+                       "root": {1: "linear", 2: "log", 3: "spline"}[st["feature"]] +
+                       (f"({st['segments']} {'log' if st['bin_feature'] == 2 else 'linear'} bins)"
+                        if st["feature"] == 3 else "")}
         answers[name] = res
         if arr is not base:
             arr.close()
