@@ -737,8 +737,8 @@ def main():
         lay, k, aos, params = autotune.choose(n, 64, layout)
         ix = base if (lay == "bs" and not aos) else base.relayout(lay, k, aos)
         ix.set_params(**params)
-        ms, ok = time_point(ix, reps=3, check=True)
-        ms_cold, _ = time_point(ix, reps=3, cold=True)
+        ms, ok = time_point(ix, reps=10, check=True)
+        ms_cold, _ = time_point(ix, reps=10, cold=True)
         best_by_layout[layout] = {"layout": lay, "k": k, "aos": aos, "params": ix.params(), "ms": round(ms, 4),
                                   "ms_cold": round(ms_cold, 4), "lookups_per_s": m / ms * 1e3, "bit_exact": ok}
         log(f"tuned {lay} k={k} aos={aos} {params}: {ms:.3f} ms exact={ok}")
@@ -768,12 +768,12 @@ def main():
                 st = arr.learn(L, 2)
                 trained = (L, la)
             arr.set_params(per_lane=r, model=0, reorder=ro)
-            ms, ok = time_point(arr, reps=3, check=True)
+            ms, ok = time_point(arr, reps=3 if args.sweep else 10, check=True)
             rec = {"layout": "learned", "k": 1, "aos": la, "params": dict(arr.params(), leaves=L), "ms": round(ms, 4),
                    "lookups_per_s": m / ms * 1e3, "bit_exact": ok, "mean_window": st["mean_window"],
                    "max_window": st["max_window"]}
             if not args.sweep:
-                rec["ms_cold"] = round(time_point(arr, reps=3, cold=True)[0], 4)
+                rec["ms_cold"] = round(time_point(arr, reps=10, cold=True)[0], 4)
             if args.sweep:
                 sweep.append(rec)
             log(f"learned leaves={L} R={r} reorder={ro} aos={la}: {ms:.3f} ms exact={ok} "
@@ -932,7 +932,13 @@ def main():
         got = oracle.point(sk, sr, qs, nthreads=cores)
         t_pt = time.perf_counter() - t0
         cpu_exact = bool(np.array_equal(got, expect_h[:ms_]))
+        m1 = ms_ // 8  # the same lookups on one thread
+        t0 = time.perf_counter()
+        got1 = oracle.point(sk, sr, qs[:m1], nthreads=1)
+        t_1 = time.perf_counter() - t0
+        cpu_exact = cpu_exact and bool(np.array_equal(got1, expect_h[:m1]))
         cpu = {"value": ms_ / t_pt, "unit": "lookups/s", "cores": cores, "kind": "oracle",
+               "value_1thread": m1 / t_1,
                "sample": f"first {ms_} of the {m} queries against the full n={n} build sorted by the oracle's "
                          f"stable sort ({t_sort:.1f} s, 1 thread); lower_bound + equality per query, "
                          f"{cores} threads; answers equal the generator's: {cpu_exact}"}

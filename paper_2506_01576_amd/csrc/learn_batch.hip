@@ -193,11 +193,10 @@ __global__ void k_bt_zero_u32(uint32_t *p, uint64_t count) {
         p[i] = 0u;
 }
 
-// This thread's BCH-key chunk of the unit.
-__device__ __forceinline__ bool chunk_of(const Unit &u, uint64_t &b, uint64_t &e) {
-    b = u.begin + (uint64_t)threadIdx.x * BCH;
-    e = b + BCH < u.end ? b + BCH : u.end;
-    return b < u.end;
+// This wave's BCH * 64 consecutive keys of the unit.
+__device__ __forceinline__ void wave_range(const Unit &u, uint64_t &b, uint64_t &e) {
+    b = u.begin + (uint64_t)(threadIdx.x & ~(uint32_t)(kWave - 1)) * BCH;
+    e = b + (uint64_t)kWave * BCH < u.end ? b + (uint64_t)kWave * BCH : u.end;
 }
 
 template <typename K>
@@ -205,22 +204,18 @@ __global__ __launch_bounds__(BT) void k_bt_leaf_count(const Unit *__restrict__ u
                                                       const RootRec *__restrict__ best, uint32_t *__restrict__ cnt) {
     const Unit u = units[blockIdx.x];
     uint64_t b, e;
-    if (!chunk_of(u, b, e)) return;
+    wave_range(u, b, e);
     const TDesc D = d[u.index];
     const K *keys = (const K *)D.keys;
     const RootRec R = best[u.index];
     uint32_t *c = cnt + D.leaf_off;
-    uint32_t cur = leaf_of(R, keys[b]), run = 0;
-    for (uint64_t i = b; i < e; ++i) {
-        const uint32_t l = leaf_of(R, keys[i]);
-        if (l != cur) {
-            atomicAdd(&c[cur], run);
-            cur = l;
-            run = 0;
-        }
-        ++run;
-    }
-    atomicAdd(&c[cur], run);
+    wave_leaf_sums<1>(
+        b, e, [&](uint64_t i, uint32_t &l, double *a) {
+            l = leaf_of(R, (uint64_t)keys[i]);
+            a[0] = 1.0;
+            return true;
+        },
+        [&](uint32_t l, const double *v) { atomicAdd(&c[l], (uint32_t)v[0]); });
 }
 
 // One workgroup per index: leaf bases (exclusive scan of the counts), sizes,
@@ -268,46 +263,6 @@ __global__ __launch_bounds__(1024) void k_bt_leaf_layout(const TDesc *__restrict
     }
 }
 
-template <typename K>
-__global__ __launch_bounds__(BT) void k_bt_leaf_accum(const Unit *__restrict__ units, const TDesc *__restrict__ d,
-                                                      const RootRec *__restrict__ best, double *__restrict__ acc) {
-    const Unit u = units[blockIdx.x];
-    uint64_t b, e;
-    const bool active = chunk_of(u, b, e);
-    const TDesc D = d[u.index];
-    const K *keys = (const K *)D.keys;
-    const RootRec R = best[u.index];
-    double *A = acc + D.leaf_off * NACC;
-    auto add = [&](uint32_t l, double *v) {
-#pragma unroll
-        for (int j = 0; j < NACC; ++j) atomicAdd(&A[(uint64_t)l * NACC + j], v[j]);
-    };
-    double a[NACC] = {0, 0, 0, 0, 0, 0};
-    uint32_t cur = active ? leaf_of(R, keys[b]) : 0;
-    LeafRec L = D.leaves[cur];
-    for (uint64_t i = b; active && i < e; ++i) {
-        const uint64_t key = (uint64_t)keys[i];
-        const uint32_t l = leaf_of(R, key);
-        if (l != cur) {
-            add(cur, a);
-#pragma unroll
-            for (int j = 0; j < NACC; ++j) a[j] = 0;
-            cur = l;
-            L = D.leaves[cur];
-        }
-        const float dd = local_feature(L, key);
-        const float y = (float)(uint32_t)(i - L.base);
-        const float r = __fsub_rn(__fadd_rn(__fmul_rn(L.b1, dd), L.b0), y);
-        a[0] += 1.0;
-        a[1] += dd;
-        a[2] += (double)dd * dd;
-        a[3] += r;
-        a[4] += (double)r * dd;
-        a[5] += (double)r * r;
-    }
-    flush<NACC>(cur, a, active, add);
-}
-
 // Index owning global leaf g: the last i with d[i].leaf_off <= g.
 __device__ __forceinline__ uint32_t leaf_owner(const TDesc *__restrict__ d, uint32_t count, uint64_t g) {
     uint32_t lo = 0, hi = count;
@@ -317,6 +272,54 @@ __device__ __forceinline__ uint32_t leaf_owner(const TDesc *__restrict__ d, uint
         else hi = mid;
     }
     return lo;
+}
+
+// Per-leaf sums, one thread per leaf (global leaf g) over its key range; a
+// leaf of more than kLeafCap keys gets zero sums and raises *big.
+template <typename K>
+__global__ __launch_bounds__(256) void k_bt_leaf_accum_small(const TDesc *__restrict__ d, uint32_t count,
+                                                             uint64_t total, double *__restrict__ acc,
+                                                             uint32_t *big) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const TDesc D = d[leaf_owner(d, count, g)];
+    const K *keys = (const K *)D.keys;
+    const LeafRec r = D.leaves[g - D.leaf_off];
+    double a[NACC] = {0, 0, 0, 0, 0, 0};
+    if (r.size <= kLeafCap) leaf_sums_thread([&](uint64_t i) { return (uint64_t)keys[i]; }, r, a);
+    else *big = 1u;
+#pragma unroll
+    for (int j = 0; j < NACC; ++j) acc[g * NACC + j] = a[j];
+}
+
+// The keys of leaves larger than kLeafCap: the wave walk over the units,
+// skipping every step without such a key.
+template <typename K>
+__global__ __launch_bounds__(BT) void k_bt_leaf_accum_big(const Unit *__restrict__ units, const TDesc *__restrict__ d,
+                                                          const RootRec *__restrict__ best, double *__restrict__ acc,
+                                                          const uint32_t *big) {
+    if (*big == 0u) return;
+    const Unit u = units[blockIdx.x];
+    uint64_t b, e;
+    wave_range(u, b, e);
+    const TDesc D = d[u.index];
+    const K *keys = (const K *)D.keys;
+    const RootRec R = best[u.index];
+    double *A = acc + D.leaf_off * NACC;
+    wave_leaf_sums<NACC>(
+        b, e,
+        [&](uint64_t i, uint32_t &l, double *a) {
+            const uint64_t key = (uint64_t)keys[i];
+            l = leaf_of(R, key);
+            const LeafRec L = D.leaves[l];
+            if (L.size <= kLeafCap) return false;
+            leaf_terms(L, i, key, a);
+            return true;
+        },
+        [&](uint32_t l, const double *v) {
+#pragma unroll
+            for (int j = 0; j < NACC; ++j) atomicAdd(&A[(uint64_t)l * NACC + j], v[j]);
+        });
 }
 
 __global__ void k_bt_leaf_update(const TDesc *__restrict__ d, uint32_t count, uint64_t total,
@@ -331,64 +334,98 @@ __global__ void k_bt_leaf_update(const TDesc *__restrict__ d, uint32_t count, ui
     r->b1 = b1;
 }
 
+// Per-leaf error bounds, one thread per leaf of at most kLeafCap keys.
 template <typename K>
-__global__ __launch_bounds__(BT) void k_bt_leaf_errors(const Unit *__restrict__ units, const TDesc *__restrict__ d,
-                                                       const RootRec *__restrict__ best) {
+__global__ __launch_bounds__(256) void k_bt_leaf_errors_small(const TDesc *__restrict__ d, uint32_t count,
+                                                              uint64_t total) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total) return;
+    const TDesc D = d[leaf_owner(d, count, g)];
+    const K *keys = (const K *)D.keys;
+    LeafRec *p = &D.leaves[g - D.leaf_off];
+    const LeafRec r = *p;
+    if (r.size == 0 || r.size > kLeafCap) return;
+    long long lo, hi;
+    leaf_errs_thread([&](uint64_t i) { return (uint64_t)keys[i]; }, r, lo, hi);
+    p->elo = (int32_t)lo;
+    p->ehi = (int32_t)hi;
+}
+
+// Error bounds of the leaves larger than kLeafCap (the wave walk).
+template <typename K>
+__global__ __launch_bounds__(BT) void k_bt_leaf_errors_big(const Unit *__restrict__ units, const TDesc *__restrict__ d,
+                                                           const RootRec *__restrict__ best, const uint32_t *big) {
+    if (*big == 0u) return;
     const Unit u = units[blockIdx.x];
     uint64_t b, e;
-    const bool active = chunk_of(u, b, e);
+    wave_range(u, b, e);
     const TDesc D = d[u.index];
     const K *keys = (const K *)D.keys;
     const RootRec R = best[u.index];
-    int64_t mm[2] = {INT_MAX, INT_MIN};
-    uint32_t cur = active ? leaf_of(R, keys[b]) : 0;
-    LeafRec L = D.leaves[cur];
-    auto add = [&](uint32_t l) {
-        atomicMin(&D.leaves[l].elo, (int32_t)mm[0]);
-        atomicMax(&D.leaves[l].ehi, (int32_t)mm[1]);
-    };
-    for (uint64_t i = b; active && i < e; ++i) {
-        const uint64_t key = (uint64_t)keys[i];
-        const uint32_t l = leaf_of(R, key);
-        if (l != cur) {
-            add(cur);
-            mm[0] = INT_MAX;
-            mm[1] = INT_MIN;
-            cur = l;
-            L = D.leaves[cur];
-        }
-        const int64_t err = (int64_t)(i - L.base) - (int64_t)pred_local(L, key);
-        mm[0] = err < mm[0] ? err : mm[0];
-        mm[1] = err > mm[1] ? err : mm[1];
-    }
-    if (active) add(cur);
+    wave_leaf_maxes(
+        b, e,
+        [&](uint64_t i, uint32_t &l, long long *a) {
+            const uint64_t key = (uint64_t)keys[i];
+            l = leaf_of(R, key);
+            const LeafRec L = D.leaves[l];
+            if (L.size <= kLeafCap) return false;
+            const long long err = leaf_err(L, i, key);
+            a[0] = -err;
+            a[1] = err;
+            return true;
+        },
+        [&](uint32_t l, const long long *v) {
+            atomicMin(&D.leaves[l].elo, (int32_t)(-v[0]));
+            atomicMax(&D.leaves[l].ehi, (int32_t)v[1]);
+        });
 }
 
 // Empty leaves get a zero window; per-index window statistics and leaf loss.
 __global__ __launch_bounds__(256) void k_bt_leaf_finish(const TDesc *__restrict__ d, uint32_t count, uint64_t total,
                                                         const double *__restrict__ acc, double *__restrict__ stats) {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total) return;
-    const uint32_t i = leaf_owner(d, count, g);
-    const TDesc D = d[i];
-    LeafRec *r = &D.leaves[g - D.leaf_off];
-    const LeafRec v = *r;
-    double *st = stats + (uint64_t)i * NST;
-    if (v.size == 0 || v.elo > v.ehi) {
-        r->elo = 0;
-        r->ehi = -1;
-    } else {
-        const double w = (double)v.ehi - (double)v.elo + 2.0;  // window slots incl. one past
-        atomicAdd(&st[0], w * v.size);
-        unsigned long long *p = (unsigned long long *)&st[1];
+    const bool live = g < total;
+    const uint32_t i = live ? leaf_owner(d, count, g) : 0xFFFFFFFFu;
+    double ws = 0.0, wmax = 0.0, loss = 0.0;
+    if (live) {
+        const TDesc D = d[i];
+        LeafRec *r = &D.leaves[g - D.leaf_off];
+        const LeafRec v = *r;
+        if (v.size == 0 || v.elo > v.ehi) {
+            r->elo = 0;
+            r->ehi = -1;
+        } else {
+            wmax = (double)v.ehi - (double)v.elo + 2.0;  // window slots incl. one past
+            ws = wmax * v.size;
+        }
+        loss = acc[g * NACC + 5];
+    }
+    auto put = [&](uint32_t ix, double s0, double m, double s2) {
+        double *st = stats + (uint64_t)ix * NST;
+        atomicAdd(&st[0], s0);
+        atomicAdd(&st[2], s2);
+        unsigned long long *p = (unsigned long long *)&st[1];  // max via CAS (values >= 0)
         unsigned long long old = *p;
-        while (__longlong_as_double(old) < w) {
-            const unsigned long long prev = atomicCAS(p, old, __double_as_longlong(w));
+        while (__longlong_as_double(old) < m) {
+            const unsigned long long prev = atomicCAS(p, old, __double_as_longlong(m));
             if (prev == old) break;
             old = prev;
         }
+    };
+    // leaves of one index are consecutive: most waves hold a single index
+    const uint64_t act = __ballot(live);
+    const uint32_t lead = (uint32_t)__shfl((int)i, __builtin_ctzll(act ? act : 1ull), kWave);
+    if (act != 0 && __ballot(live && i == lead) == act) {
+        ws = wave_sum(ws);
+        loss = wave_sum(loss);
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const double o = __shfl_xor(wmax, off, kWave);
+            wmax = o > wmax ? o : wmax;
+        }
+        if ((threadIdx.x & (kWave - 1)) == 0) put(lead, ws, wmax, loss);
+    } else if (live) {
+        put(i, ws, wmax, loss);
     }
-    atomicAdd(&st[2], acc[g * NACC + 5]);
 }
 
 // With both root families: per index, the lower estimated lookup cost wins
@@ -453,9 +490,10 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
     const size_t b_lacc = up(sizeof(double) * NACC * total_leaves), b_cnt = up(sizeof(uint32_t) * total_leaves);
     const size_t b_bins = up(sizeof(SplineBin) * 2 * total_bins), b_src = up(sizeof(void *) * count);
     const size_t b_alt = both ? up(sizeof(LeafRec) * total_leaves) : 0, b_pick = up(sizeof(uint32_t) * count);
+    const size_t b_flag = 256;
     const Alloc &A = hs[0]->alloc;
     const size_t total_b = 2 * b_desc + b_units + b_roots + 3 * b_best + b_racc + 3 * b_stats + b_lacc + b_cnt +
-                           b_bins + b_src + b_alt + b_pick;
+                           b_bins + b_src + b_alt + b_pick + b_flag;
     char *tmp = (char *)A.get(total_b, s);
     if (!tmp) return IDX_ERR_NOMEM;
     char *p = tmp;
@@ -477,6 +515,7 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
     const SplineBin **d_src = (const SplineBin **)take(b_src);
     LeafRec *d_alt = (LeafRec *)take(b_alt);
     uint32_t *d_pick = (uint32_t *)take(b_pick);
+    uint32_t *d_big = (uint32_t *)take(b_flag);  // a leaf larger than kLeafCap exists
     uint32_t cmask = 0;
     if (feature == IDX_FEATURE_AUTO) cmask = 15u;
     else if (feature == IDX_FEATURE_SPLINE) cmask = 12u;
@@ -508,15 +547,18 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
         hipLaunchKernelGGL(k_bt_zero_u32, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, d_cnt, total_leaves);
         hipLaunchKernelGGL((k_bt_leaf_count<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br, d_cnt);
         hipLaunchKernelGGL((k_bt_leaf_layout<K>), dim3(count), dim3(1024), 0, s, dd, d_cnt);
+        hipLaunchKernelGGL(k_bt_zero_u32, dim3(1), dim3(64), 0, s, d_big, (uint64_t)1);
         for (uint32_t ep = 0; ep <= epochs; ++ep) {
-            hipLaunchKernelGGL(k_bt_zero, dim3(blocks_for((uint64_t)NACC * total_leaves, 256)), dim3(256), 0, s,
-                               d_lacc, (uint64_t)NACC * total_leaves);
-            hipLaunchKernelGGL((k_bt_leaf_accum<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br, d_lacc);
+            hipLaunchKernelGGL((k_bt_leaf_accum_small<K>), dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd,
+                               count, total_leaves, d_lacc, d_big);
+            hipLaunchKernelGGL((k_bt_leaf_accum_big<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br, d_lacc, d_big);
             if (ep < epochs)
                 hipLaunchKernelGGL(k_bt_leaf_update, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd, count,
                                    total_leaves, d_lacc);
         }
-        hipLaunchKernelGGL((k_bt_leaf_errors<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br);
+        hipLaunchKernelGGL((k_bt_leaf_errors_small<K>), dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd, count,
+                           total_leaves);
+        hipLaunchKernelGGL((k_bt_leaf_errors_big<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br, d_big);
         hipLaunchKernelGGL(k_bt_leaf_finish, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd, count,
                            total_leaves, d_lacc, st);
     };

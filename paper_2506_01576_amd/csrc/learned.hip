@@ -103,21 +103,15 @@ template <typename K, bool AOS>
 __global__ __launch_bounds__(LT) void k_leaf_count(Load<K, AOS> keys, uint64_t n, const RootRec *Rp,
                                                    unsigned long long *__restrict__ count) {
     const RootRec R = *Rp;
-    const uint64_t t = (uint64_t)blockIdx.x * LT + threadIdx.x;
-    const uint64_t b = t * CHUNK;
-    if (b >= n) return;
-    const uint64_t e = b + CHUNK < n ? b + CHUNK : n;
-    uint32_t cur = leaf_of(R, keys.key(b)), run = 0;
-    for (uint64_t i = b; i < e; ++i) {
-        const uint32_t l = leaf_of(R, keys.key(i));
-        if (l != cur) {
-            atomicAdd(&count[cur], (unsigned long long)run);
-            cur = l;
-            run = 0;
-        }
-        ++run;
-    }
-    atomicAdd(&count[cur], (unsigned long long)run);
+    const uint64_t b = ((uint64_t)blockIdx.x * LT + (threadIdx.x & ~(uint32_t)(kWave - 1))) * CHUNK;
+    const uint64_t e = b + (uint64_t)kWave * CHUNK < n ? b + (uint64_t)kWave * CHUNK : n;
+    wave_leaf_sums<1>(
+        b, e, [&](uint64_t i, uint32_t &l, double *a) {
+            l = leaf_of(R, (uint64_t)keys.key(i));
+            a[0] = 1.0;
+            return true;
+        },
+        [&](uint32_t l, const double *v) { atomicAdd(&count[l], (unsigned long long)v[0]); });
 }
 
 // Leaf records from the exclusive scan of the per-leaf counts (base[l] =
@@ -139,41 +133,46 @@ __global__ void k_leaf_init(Load<K, AOS> keys, const unsigned long long *__restr
     leaves[l] = r;
 }
 
+// Per-leaf sums, one thread per leaf over its key range; a leaf of more than
+// kLeafCap keys gets zero sums here and raises *big for k_leaf_accum_big.
 template <typename K, bool AOS>
-__global__ __launch_bounds__(LT) void k_leaf_accum(Load<K, AOS> keys, uint64_t n, const RootRec *Rp,
-                                                   const LeafRec *__restrict__ leaves, double *__restrict__ acc) {
-    const RootRec R = *Rp;
-    const uint64_t t = (uint64_t)blockIdx.x * LT + threadIdx.x;
-    const uint64_t b = t * CHUNK;
-    const uint64_t e = b + CHUNK < n ? b + CHUNK : n;
-    auto add = [&](uint32_t l, double *v) {
-#pragma unroll
-        for (int j = 0; j < NACC; ++j) atomicAdd(&acc[(uint64_t)l * NACC + j], v[j]);
-    };
+__global__ __launch_bounds__(256) void k_leaf_accum_small(Load<K, AOS> keys, const LeafRec *__restrict__ leaves,
+                                                          uint32_t L, double *__restrict__ acc, uint32_t *big) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    const LeafRec r = leaves[l];
     double a[NACC] = {0, 0, 0, 0, 0, 0};
-    uint32_t cur = b < n ? leaf_of(R, keys.key(b)) : 0;
-    LeafRec L = leaves[cur];
-    for (uint64_t i = b; i < e; ++i) {
-        const uint64_t key = (uint64_t)keys.key(i);
-        const uint32_t l = leaf_of(R, key);
-        if (l != cur) {
-            add(cur, a);
+    if (r.size <= kLeafCap) leaf_sums_thread([&](uint64_t i) { return (uint64_t)keys.key(i); }, r, a);
+    else *big = 1u;
 #pragma unroll
-            for (int j = 0; j < NACC; ++j) a[j] = 0;
-            cur = l;
-            L = leaves[cur];
-        }
-        const float d = local_feature(L, key);
-        const float y = (float)(uint32_t)(i - L.base);
-        const float r = __fsub_rn(__fadd_rn(__fmul_rn(L.b1, d), L.b0), y);
-        a[0] += 1.0;
-        a[1] += d;
-        a[2] += (double)d * d;
-        a[3] += r;
-        a[4] += (double)r * d;
-        a[5] += (double)r * r;
-    }
-    flush<NACC>(cur, a, b < n, add);
+    for (int j = 0; j < NACC; ++j) acc[(uint64_t)l * NACC + j] = a[j];
+}
+
+// The keys of leaves larger than kLeafCap: the wave walk over all keys,
+// skipping every step without such a key (nothing to do when *big is 0).
+template <typename K, bool AOS>
+__global__ __launch_bounds__(LT) void k_leaf_accum_big(Load<K, AOS> keys, uint64_t n, const RootRec *Rp,
+                                                       const LeafRec *__restrict__ leaves, double *__restrict__ acc,
+                                                       const uint32_t *big) {
+    if (*big == 0u) return;
+    const RootRec R = *Rp;
+    // this wave's CHUNK * 64 consecutive keys
+    const uint64_t b = ((uint64_t)blockIdx.x * LT + (threadIdx.x & ~(uint32_t)(kWave - 1))) * CHUNK;
+    const uint64_t e = b + (uint64_t)kWave * CHUNK < n ? b + (uint64_t)kWave * CHUNK : n;
+    wave_leaf_sums<NACC>(
+        b, e,
+        [&](uint64_t i, uint32_t &l, double *a) {
+            const uint64_t key = (uint64_t)keys.key(i);
+            l = leaf_of(R, key);
+            const LeafRec L = leaves[l];
+            if (L.size <= kLeafCap) return false;
+            leaf_terms(L, i, key, a);
+            return true;
+        },
+        [&](uint32_t l, const double *v) {
+#pragma unroll
+            for (int j = 0; j < NACC; ++j) atomicAdd(&acc[(uint64_t)l * NACC + j], v[j]);
+        });
 }
 
 __global__ void k_leaf_update(LeafRec *__restrict__ leaves, const double *__restrict__ acc, uint32_t L) {
@@ -185,65 +184,60 @@ __global__ void k_leaf_update(LeafRec *__restrict__ leaves, const double *__rest
     leaves[l].b1 = r.b1;
 }
 
+// Per-leaf error bounds, one thread per leaf of at most kLeafCap keys.
 template <typename K, bool AOS>
-__global__ __launch_bounds__(LT) void k_leaf_errors(Load<K, AOS> keys, uint64_t n, const RootRec *Rp,
-                                                    LeafRec *__restrict__ leaves) {
+__global__ __launch_bounds__(256) void k_leaf_errors_small(Load<K, AOS> keys, LeafRec *__restrict__ leaves,
+                                                           uint32_t L) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    const LeafRec r = leaves[l];
+    if (r.size == 0 || r.size > kLeafCap) return;
+    long long lo, hi;
+    leaf_errs_thread([&](uint64_t i) { return (uint64_t)keys.key(i); }, r, lo, hi);
+    leaves[l].elo = (int32_t)lo;
+    leaves[l].ehi = (int32_t)hi;
+}
+
+// Error bounds of the leaves larger than kLeafCap (the wave walk).
+template <typename K, bool AOS>
+__global__ __launch_bounds__(LT) void k_leaf_errors_big(Load<K, AOS> keys, uint64_t n, const RootRec *Rp,
+                                                        LeafRec *__restrict__ leaves, const uint32_t *big) {
+    if (*big == 0u) return;
     const RootRec R = *Rp;
-    const uint64_t t = (uint64_t)blockIdx.x * LT + threadIdx.x;
-    const uint64_t b = t * CHUNK;
-    const uint64_t e = b + CHUNK < n ? b + CHUNK : n;
-    auto add = [&](uint32_t l, int64_t *v) {
-        atomicMin(&leaves[l].elo, (int32_t)v[0]);
-        atomicMax(&leaves[l].ehi, (int32_t)v[1]);
-    };
-    int64_t mm[2] = {INT_MAX, INT_MIN};
-    uint32_t cur = b < n ? leaf_of(R, keys.key(b)) : 0;
-    LeafRec L = leaves[cur];
-    for (uint64_t i = b; i < e; ++i) {
-        const uint64_t key = (uint64_t)keys.key(i);
-        const uint32_t l = leaf_of(R, key);
-        if (l != cur) {
-            add(cur, mm);
-            mm[0] = INT_MAX;
-            mm[1] = INT_MIN;
-            cur = l;
-            L = leaves[cur];
-        }
-        const int64_t err = (int64_t)(i - L.base) - (int64_t)pred_local(L, key);
-        mm[0] = err < mm[0] ? err : mm[0];
-        mm[1] = err > mm[1] ? err : mm[1];
-    }
-    // wave-uniform flush with min/max instead of sums
-    const bool active = b < n;
-    const uint64_t act = __ballot(active);
-    const uint32_t lead = __shfl((int)cur, __builtin_ctzll(act ? act : 1ull), kWave);
-    const bool uniform = act != 0 && __ballot(active && cur == lead) == act && act == __ballot(true);
-    if (uniform) {
-        for (int off = kWave / 2; off > 0; off >>= 1) {
-            const int64_t o0 = __shfl_xor(mm[0], off, kWave), o1 = __shfl_xor(mm[1], off, kWave);
-            mm[0] = o0 < mm[0] ? o0 : mm[0];
-            mm[1] = o1 > mm[1] ? o1 : mm[1];
-        }
-        if ((threadIdx.x & (kWave - 1)) == 0) add(cur, mm);
-    } else if (active) {
-        add(cur, mm);
-    }
+    const uint64_t b = ((uint64_t)blockIdx.x * LT + (threadIdx.x & ~(uint32_t)(kWave - 1))) * CHUNK;
+    const uint64_t e = b + (uint64_t)kWave * CHUNK < n ? b + (uint64_t)kWave * CHUNK : n;
+    wave_leaf_maxes(
+        b, e,
+        [&](uint64_t i, uint32_t &l, long long *a) {
+            const uint64_t key = (uint64_t)keys.key(i);
+            l = leaf_of(R, key);
+            const LeafRec L = leaves[l];
+            if (L.size <= kLeafCap) return false;
+            const long long err = leaf_err(L, i, key);
+            a[0] = -err;
+            a[1] = err;
+            return true;
+        },
+        [&](uint32_t l, const long long *v) {
+            atomicMin(&leaves[l].elo, (int32_t)(-v[0]));
+            atomicMax(&leaves[l].ehi, (int32_t)v[1]);
+        });
 }
 
 // Empty leaves get a zero window; statistics of the windows.
 __global__ __launch_bounds__(256) void k_leaf_finish(LeafRec *__restrict__ leaves, uint32_t L,
                                                      double *__restrict__ stats /* sum_w*size, max_w, sum loss */) {
-    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double s_ws[256 / kWave], s_wm[256 / kWave];
     double ws = 0, wmax = 0;
-    if (l < L) {
+    for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < L; l += gridDim.x * blockDim.x) {
         LeafRec r = leaves[l];
         if (r.size == 0 || r.elo > r.ehi) {
             leaves[l].elo = 0;
             leaves[l].ehi = -1;
         } else {
             const double w = (double)r.ehi - (double)r.elo + 2.0;  // window slots incl. one past
-            ws = w * r.size;
-            wmax = w;
+            ws += w * r.size;
+            wmax = w > wmax ? w : wmax;
         }
     }
     ws = wave_sum(ws);
@@ -251,7 +245,17 @@ __global__ __launch_bounds__(256) void k_leaf_finish(LeafRec *__restrict__ leave
         const double o = __shfl_xor(wmax, off, kWave);
         wmax = o > wmax ? o : wmax;
     }
+    const uint32_t wave = threadIdx.x / kWave;
     if ((threadIdx.x & (kWave - 1)) == 0) {
+        s_ws[wave] = ws;
+        s_wm[wave] = wmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (uint32_t w = 1; w < blockDim.x / kWave; ++w) {
+            ws += s_ws[w];
+            wmax = s_wm[w] > wmax ? s_wm[w] : wmax;
+        }
         atomicAdd(&stats[0], ws);
         // max via compare-and-swap on the bit pattern (values are >= 0)
         unsigned long long *p = (unsigned long long *)&stats[1];
@@ -340,6 +344,7 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
     unsigned long long *count = (unsigned long long *)(tmp + 512 + leaf_acc_b + 256);
     uint64_t *partial = (uint64_t *)((char *)count + up256(((size_t)L + 1) * 8));
     LeafRec *alt = both ? (LeafRec *)(tmp + 512 + leaf_acc_b + 256 + layout_scratch_bytes(L)) : nullptr;
+    uint32_t *d_big = (uint32_t *)(stats + 8);  // a leaf larger than kLeafCap exists
     const uint32_t rblocks = (uint32_t)((n + LT * 8 - 1) / (LT * 8)) > 2048 ? 2048u
                                                                              : (uint32_t)((n + LT * 8 - 1) / (LT * 8));
     const uint32_t cblocks = grid_for((n + CHUNK - 1) / CHUNK, LT);
@@ -373,18 +378,21 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
         if (hipMemcpyAsync(d_root, &R, sizeof(R), hipMemcpyHostToDevice, s) != hipSuccess) return IDX_ERR_HIP;
         int rc = leaf_layout<K, AOS>(keys, n, d_root, L, count, partial, leaves, s);
         if (rc != IDX_OK) return rc;
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, d_big, (uint64_t)1, 0u);
         for (uint32_t ep = 0; ep <= epochs; ++ep) {
-            hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((uint64_t)L * NACC, 256)), dim3(256), 0, s, leaf_acc,
-                               (uint64_t)L * NACC);
-            hipLaunchKernelGGL((k_leaf_accum<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
-                               leaf_acc);
+            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS>), dim3(grid_for(L, 256)), dim3(256), 0, s, keys, leaves, L,
+                               leaf_acc, d_big);
+            hipLaunchKernelGGL((k_leaf_accum_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
+                               leaf_acc, d_big);
             if (ep < epochs)
                 hipLaunchKernelGGL(k_leaf_update, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_acc, L);
         }
         hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, stats, (uint64_t)4);
         hipLaunchKernelGGL(k_sum_leaf_loss, dim3(64), dim3(256), 0, s, leaf_acc, L, stats + 2);
-        hipLaunchKernelGGL((k_leaf_errors<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves);
-        hipLaunchKernelGGL(k_leaf_finish, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, L, stats);
+        hipLaunchKernelGGL((k_leaf_errors_small<K, AOS>), dim3(grid_for(L, 256)), dim3(256), 0, s, keys, leaves, L);
+        hipLaunchKernelGGL((k_leaf_errors_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves, d_big);
+        hipLaunchKernelGGL(k_leaf_finish, dim3(grid_for(L, 256) < 1024 ? grid_for(L, 256) : 1024), dim3(256), 0, s,
+                           leaves, L, stats);
         if (hipGetLastError() != hipSuccess) return IDX_ERR_HIP;
         if (hipMemcpyAsync(st, stats, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
@@ -787,11 +795,13 @@ int eval_t(idx_index *h, uint32_t mode, const float *root_ab, uint32_t L, const 
             const uint32_t cblocks = grid_for((n + CHUNK - 1) / CHUNK, LT);
             rc = leaf_layout<K, AOS>(keys, n, d_root, L, count, partial, leaves, s);
             if (rc != IDX_OK) break;
-            hipLaunchKernelGGL(k_fill_f64, dim3(grid_for((uint64_t)L * NACC, 256)), dim3(256), 0, s, leaf_acc_d,
-                               (uint64_t)L * NACC);
+            uint32_t *d_big = (uint32_t *)(tmp + 256 + 128);
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, d_big, (uint64_t)1, 0u);
             hipLaunchKernelGGL(k_set_leaf_params, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_ab, L);
-            hipLaunchKernelGGL((k_leaf_accum<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
-                               leaf_acc_d);
+            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS>), dim3(grid_for(L, 256)), dim3(256), 0, s, keys, leaves, L,
+                               leaf_acc_d, d_big);
+            hipLaunchKernelGGL((k_leaf_accum_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
+                               leaf_acc_d, d_big);
         }
         if (hipGetLastError() != hipSuccess) { rc = IDX_ERR_HIP; break; }
         if (hipMemcpyAsync(root_acc_h, racc, NACC * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||

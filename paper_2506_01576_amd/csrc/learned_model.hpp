@@ -2,6 +2,8 @@
 // training/lookup kernels (learned.hip) and the batched launch (batch.hip).
 #pragma once
 
+#include <climits>
+
 #include "internal.hpp"
 #include "search.hpp"
 
@@ -260,20 +262,116 @@ __device__ __forceinline__ void newton_linear(const double *a, float &c0, float 
     c0 = (float)n0;
 }
 
-// Flush a thread's running sums for leaf `l`: when the whole wave holds the
-// same leaf, reduce across the wave first and add once.
-template <int NV, typename T, typename F>
-__device__ __forceinline__ void flush(uint32_t l, T *v, bool active, F &&add) {
-    const uint64_t act = __ballot(active);
-    const uint32_t lead = __shfl((int)l, __builtin_ctzll(act ? act : 1ull), kWave);
-    const bool uniform = act != 0 && __ballot(active && l == lead) == act && act == __ballot(true);
-    if (uniform) {
+// Per-leaf reductions over the consecutive keys [b, e) walked by one wave, 64
+// keys per step (lane j takes key b + 64 s + j), so every load is coalesced.
+// For key i, step(i, leaf, v) sets its leaf and its NV values and returns
+// whether the key takes part (keys that do not are skipped).  Leaf ids never
+// decrease along the keys, so a step holds few distinct leaves: each is
+// reduced across the wave with comb and merged into a carry that all lanes
+// hold; a finished carry goes to add(leaf, values), called by lane 0 (once per
+// leaf the wave touches instead of once per lane and leaf).
+template <int NV, typename T, typename Comb, typename Step, typename Add>
+__device__ __forceinline__ void wave_leaf_reduce(uint64_t b, uint64_t e, T ident, Comb &&comb, Step &&step,
+                                                 Add &&add) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    uint32_t carry_leaf = 0xFFFFFFFFu;
+    T carry[NV];
 #pragma unroll
-        for (int j = 0; j < NV; ++j) v[j] = wave_sum(v[j]);
-        if ((threadIdx.x & (kWave - 1)) == 0) add(l, v);
-    } else if (active) {
-        add(l, v);
+    for (int j = 0; j < NV; ++j) carry[j] = ident;
+    for (uint64_t s0 = b; s0 < e; s0 += kWave) {
+        const uint64_t i = s0 + lane;
+        const bool live = i < e;
+        uint32_t l = 0xFFFFFFFFu;
+        T v[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) v[j] = ident;
+        const bool part = live && step(i, l, v);
+        uint64_t todo = __ballot(part);
+        while (todo) {
+            const uint32_t lead = (uint32_t)__shfl((int)l, __builtin_ctzll(todo), kWave);
+            const bool mine = part && l == lead;
+            todo &= ~__ballot(mine);
+            T sv[NV];
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                T x = mine ? v[j] : ident;
+#pragma unroll
+                for (int off = kWave / 2; off > 0; off >>= 1) x = comb(x, __shfl_xor(x, off, kWave));
+                sv[j] = x;
+            }
+            if (lead != carry_leaf) {
+                if (carry_leaf != 0xFFFFFFFFu && lane == 0) add(carry_leaf, carry);
+                carry_leaf = lead;
+#pragma unroll
+                for (int j = 0; j < NV; ++j) carry[j] = sv[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < NV; ++j) carry[j] = comb(carry[j], sv[j]);
+            }
+        }
     }
+    if (carry_leaf != 0xFFFFFFFFu && lane == 0) add(carry_leaf, carry);
+}
+
+// Leaves of at most kLeafCap keys are walked by one thread each in the
+// per-leaf passes (their key ranges are known after the layout); larger
+// leaves go through the wave walk.
+constexpr uint32_t kLeafCap = 512;
+
+// A key's terms of the leaf line fit: count, d, d^2, r, r d, r^2, with d the
+// leaf-local key offset and r the residual of the leaf's prediction at rank i.
+__device__ __forceinline__ void leaf_terms(const LeafRec &L, uint64_t i, uint64_t key, double *a) {
+    const float d = local_feature(L, key);
+    const float y = (float)(uint32_t)(i - L.base);
+    const float r = __fsub_rn(__fadd_rn(__fmul_rn(L.b1, d), L.b0), y);
+    a[0] = 1.0;
+    a[1] = d;
+    a[2] = (double)d * d;
+    a[3] = r;
+    a[4] = (double)r * d;
+    a[5] = (double)r * r;
+}
+
+// A key's error: true local rank minus the predicted local rank.
+__device__ __forceinline__ long long leaf_err(const LeafRec &L, uint64_t i, uint64_t key) {
+    return (long long)(i - L.base) - (long long)pred_local(L, key);
+}
+
+// The sums of one leaf, walked by one thread (key(i) reads rank i).
+template <typename KeyAt>
+__device__ __forceinline__ void leaf_sums_thread(const KeyAt &key, const LeafRec &L, double *a) {
+    for (int j = 0; j < NACC; ++j) a[j] = 0.0;
+    for (uint64_t i = L.base; i < (uint64_t)L.base + L.size; ++i) {
+        double t[NACC];
+        leaf_terms(L, i, key(i), t);
+#pragma unroll
+        for (int j = 0; j < NACC; ++j) a[j] += t[j];
+    }
+}
+
+// The error bounds of one leaf, walked by one thread.
+template <typename KeyAt>
+__device__ __forceinline__ void leaf_errs_thread(const KeyAt &key, const LeafRec &L, long long &lo, long long &hi) {
+    lo = INT_MAX;
+    hi = INT_MIN;
+    for (uint64_t i = L.base; i < (uint64_t)L.base + L.size; ++i) {
+        const long long e = leaf_err(L, i, key(i));
+        lo = e < lo ? e : lo;
+        hi = e > hi ? e : hi;
+    }
+}
+
+template <int NV, typename Step, typename Add>
+__device__ __forceinline__ void wave_leaf_sums(uint64_t b, uint64_t e, Step &&step, Add &&add) {
+    wave_leaf_reduce<NV, double>(b, e, 0.0, [](double x, double y) { return x + y; }, step, add);
+}
+
+// Error bounds: per leaf the max of -err and of err (err = true local rank -
+// predicted local rank), as int64.
+template <typename Step, typename Add>
+__device__ __forceinline__ void wave_leaf_maxes(uint64_t b, uint64_t e, Step &&step, Add &&add) {
+    wave_leaf_reduce<2, long long>(b, e, (long long)INT64_MIN,
+                                   [](long long x, long long y) { return x > y ? x : y; }, step, add);
 }
 
 }  // namespace idx
