@@ -262,6 +262,11 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
                                                          const uint32_t *__restrict__ first,
                                                          const uint64_t *__restrict__ offs,
                                                          uint32_t *__restrict__ rows_out) {
+    // per wave: the start of each lane's run in the wave's concatenation of
+    // runs, and source / destination pointers offset by that start
+    __shared__ uint32_t s_start[BT / kWave][kWave + 1];
+    __shared__ const uint32_t *s_src[BT / kWave][kWave];
+    __shared__ uint32_t *s_dst[BT / kWave][kWave];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t wave_global = ((uint64_t)blockIdx.x * BT + threadIdx.x) / kWave;
     const uint64_t waves = (uint64_t)gridDim.x * (BT / kWave);
@@ -325,17 +330,51 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
                 eyt_scan_wave(Lw, geos[wi], dw.form == F_EBS ? 1 : 0, lo[wp], hi[wp], (uint64_t)first[wp], wcnt,
                               rows_out + wo, w);
             }
-            // wave-cooperative copies of the sorted-array runs, one lane's run at a time
-            uint64_t pending = __ballot(run_len > 0);
-            while (pending) {
-                const int src = __builtin_ctzll(pending);
-                pending &= pending - 1;
-                const uint64_t rr = (uint64_t)__shfl((long long)(uintptr_t)run_rows, src, kWave);
-                const uint64_t f0 = (uint64_t)__shfl((long long)run_first, src, kWave);
-                const uint64_t o0 = (uint64_t)__shfl((long long)run_out, src, kWave);
-                const uint64_t len = (uint64_t)__shfl((long long)run_len, src, kWave);
-                const uint32_t *rows = (const uint32_t *)(uintptr_t)rr;
-                for (uint64_t e = lane; e < len; e += kWave) rows_out[o0 + e] = rows[f0 + e];
+            // wave-cooperative copy of the lanes' sorted-array runs: every
+            // element finds its run by a binary search over the runs' starts
+            // (per wave, in LDS), so the wave copies 64 elements per step with
+            // CU independent loads per lane in flight
+            {
+                const uint32_t w = threadIdx.x / kWave;
+                uint32_t len32 = (uint32_t)run_len, incl = len32;
+#pragma unroll
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const uint32_t x = (uint32_t)__shfl_up((int)incl, off, kWave);
+                    if (lane >= (uint32_t)off) incl += x;
+                }
+                const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+                if (total > 0) {
+                    const uint32_t start = incl - len32;
+                    s_start[w][lane] = start;
+                    if (lane == kWave - 1) s_start[w][kWave] = total;
+                    s_src[w][lane] = (const uint32_t *)run_rows + run_first - start;
+                    s_dst[w][lane] = rows_out + run_out - start;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    constexpr int CU = 4;
+                    for (uint32_t t0 = lane; t0 < total; t0 += kWave * CU) {
+                        uint32_t v[CU], q[CU];
+#pragma unroll
+                        for (int u = 0; u < CU; ++u) {
+                            const uint32_t t = t0 + (uint32_t)u * kWave;
+                            uint32_t lo = 0;
+#pragma unroll
+                            for (uint32_t step = kWave / 2; step > 0; step >>= 1)
+                                if (s_start[w][lo + step] <= t) lo += step;
+                            q[u] = lo;
+                            if (t < total) v[u] = s_src[w][lo][t];
+                        }
+#pragma unroll
+                        for (int u = 0; u < CU; ++u) {
+                            const uint32_t t = t0 + (uint32_t)u * kWave;
+                            if (t < total) s_dst[w][q[u]][t] = v[u];
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
             }
         }
     }
