@@ -51,6 +51,20 @@ __device__ __forceinline__ uint64_t lower_rank(const RangeArgs<K, AOS> &a, K x) 
     }
     const uint32_t g = a.G.g, kf = a.G.k;
     uint64_t c = 0, cand = ~0ull;
+    if constexpr (!AOS) {
+        if (scan_vec_ok(a.G, a.off, sizeof(K), false)) {  // whole nodes in registers
+            K kk[kScanNodeBytes / sizeof(K)];
+            while (c * g < n) {
+                const uint64_t i = c * g;
+                const uint32_t nv = (n - i) < g ? (uint32_t)(n - i) : g;
+                node_keys(a.L.k, i, g, kk);
+                const uint32_t j = node_below(kk, nv, x);
+                if (j < nv) cand = i + j;
+                c = c * kf + 1 + j;
+            }
+            return cand == ~0ull ? n : slot_rank(a.G, cand);
+        }
+    }
     while (c * g < n) {
         const uint64_t i = c * g;
         const uint64_t nv = (n - i) < g ? (n - i) : g;
@@ -105,7 +119,17 @@ __global__ __launch_bounds__(256) void k_range_fill_eyt(RangeArgs<K, AOS> a) {
         r0 = a.first_rank[q];
     }
     ScanState st{};
-    const bool paused = cnt > 0 && eyt_scan_lane(a.L, a.G, a.off, L, U, r0, cnt, a.out + o, st);
+    bool paused = false;
+    if (cnt > 0) {
+        if constexpr (!AOS) {
+            if (scan_vec_ok(a.G, a.off, sizeof(K), false))
+                paused = eyt_scan_lane_vec(a.L.k, a.L.r, a.G, L, U, r0, cnt, a.out + o, st);
+            else
+                paused = eyt_scan_lane(a.L, a.G, a.off, L, U, r0, cnt, a.out + o, st);
+        } else {
+            paused = eyt_scan_lane(a.L, a.G, a.off, L, U, r0, cnt, a.out + o, st);
+        }
+    }
     // every lane of the wave reaches this point: continue paused scans together
     uint64_t pend = __ballot(paused);
     while (pend) {

@@ -75,6 +75,113 @@ __device__ __forceinline__ bool eyt_scan_lane(const Load<K, AOS> &L, const Geo &
     return false;
 }
 
+// ---- vector form for SoA nodes of 16 to 128 bytes starting on 16-byte
+// boundaries (EKS with off = 0): a node is read once with independent 16-byte
+// loads and counted in registers, and the row IDs of a node's matches come
+// from one vector read of the node's row IDs, instead of one dependent load
+// per pivot and per match (whose lines L2 evicts between the probes when
+// hundreds of thousands of scans are in flight).
+constexpr uint32_t kScanNodeBytes = 128;
+
+__host__ __device__ inline bool scan_vec_ok(const Geo &G, uint64_t off, uint32_t key_bytes, bool aos) {
+    const uint32_t nb = G.g * key_bytes;
+    return !aos && off == 0 && nb % 16 == 0 && nb <= kScanNodeBytes && G.g % 4 == 0;
+}
+
+// The g keys of the node starting at slot i (16-byte chunks; padding past n
+// is read but never counted).
+template <typename K>
+__device__ __forceinline__ void node_keys(const K *__restrict__ keys, uint64_t i, uint32_t g, K *kk) {
+    constexpr int V = 16 / sizeof(K);
+    constexpr int MC = kScanNodeBytes / 16;
+    const uint4 *q = (const uint4 *)(keys + i);
+    const uint32_t chunks = g / V;
+#pragma unroll
+    for (int c = 0; c < MC; ++c) {
+        uint4 w = make_uint4(0u, 0u, 0u, 0u);
+        if ((uint32_t)c < chunks) w = q[c];
+        if constexpr (sizeof(K) == 8) {
+            kk[2 * c] = ((uint64_t)w.y << 32) | w.x;
+            kk[2 * c + 1] = ((uint64_t)w.w << 32) | w.z;
+        } else {
+            kk[4 * c] = w.x;
+            kk[4 * c + 1] = w.y;
+            kk[4 * c + 2] = w.z;
+            kk[4 * c + 3] = w.w;
+        }
+    }
+}
+
+// Pivots of a node (valid slots only) below x.
+template <typename K>
+__device__ __forceinline__ uint32_t node_below(const K *kk, uint32_t valid, K x) {
+    constexpr int NK = kScanNodeBytes / sizeof(K);
+    uint32_t j = 0;
+#pragma unroll
+    for (int e = 0; e < NK; ++e) j += ((uint32_t)e < valid && kk[e] < x) ? 1u : 0u;
+    return j;
+}
+
+template <typename K>
+__device__ __forceinline__ bool eyt_scan_lane_vec(const K *__restrict__ keys, const uint32_t *__restrict__ rows,
+                                                  const Geo &G, K lo, K hi, uint64_t r0, uint64_t cnt,
+                                                  uint32_t *__restrict__ out, ScanState &st) {
+    constexpr int NK = kScanNodeBytes / sizeof(K);
+    constexpr int NR = kScanNodeBytes / sizeof(K) / 4;  // 16-byte row chunks of the largest node
+    const uint64_t n = G.n;
+    const uint32_t g = G.g, kf = G.k;
+    const uint64_t bottom_start = G.start[G.m];
+    uint64_t c = 0;
+    uint32_t lvl = 0;
+    K kk[NK];
+    while (c * g < n) {
+        const uint64_t i = c * g;
+        const uint64_t level_end = G.start[lvl + 1] < n ? G.start[lvl + 1] : n;
+        node_keys(keys, i, g, kk);
+        uint32_t valid = (n - i) < g ? (uint32_t)(n - i) : g;
+        const uint32_t j = node_below(kk, valid, lo);
+        uint32_t seen = 0;
+        uint64_t nb = i;     // start slot of the node in registers
+        uint32_t from = j;   // first match within it
+        for (;;) {
+            // matches of this node: slots nb + [from, upto)
+            // keys ascend along a level: slots [from, upto) hold the keys in [lo, hi]
+            const uint32_t upto = hi == key_max<K>() ? valid : node_below(kk, valid, (K)(hi + 1));
+            if (upto > from) {
+                uint4 rw[NR];
+                const uint4 *rq = (const uint4 *)(rows + nb);
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    if ((uint32_t)q < g / 4) rw[q] = rq[q];
+                const uint64_t d0 = slot_rank_on(G, nb + from, lvl) - r0;
+                const bool bottom = nb >= bottom_start;
+#pragma unroll
+                for (int e = 0; e < NK; ++e) {
+                    if ((uint32_t)e < from || (uint32_t)e >= upto) continue;
+                    if (seen == (uint32_t)kWave) {
+                        st = ScanState{c, nb + (uint64_t)e, lvl, j};
+                        return true;
+                    }
+                    const uint4 w = rw[e / 4];
+                    const uint32_t r = (e & 3) == 0 ? w.x : (e & 3) == 1 ? w.y : (e & 3) == 2 ? w.z : w.w;
+                    const uint64_t d = bottom ? d0 + (uint64_t)(e - from) : slot_rank_on(G, nb + e, lvl) - r0;
+                    if (d < cnt) out[d] = r;
+                    ++seen;
+                }
+            }
+            // the run goes on in the next node of the level only if it reached this node's end
+            if (upto < valid || nb + g >= level_end) break;
+            nb += g;
+            node_keys(keys, nb, g, kk);
+            valid = (n - nb) < g ? (uint32_t)(n - nb) : g;
+            from = 0;
+        }
+        c = c * kf + 1 + j;
+        ++lvl;
+    }
+    return false;
+}
+
 // The whole wave continues one paused scan (every lane passes the same
 // arguments).  Pivots per node g <= kWave.
 template <typename K, bool AOS>
