@@ -76,6 +76,26 @@ __device__ __forceinline__ uint64_t lower_rank(const RangeArgs<K, AOS> &a, K x) 
     return cand == ~0ull ? n : slot_rank(a.G, cand);
 }
 
+// Sorted array: rank of the first key > U, given that every key before r0 is
+// <= U.  Gallops forward from r0 (the first probes fall in the lines the
+// search for r0 just read), then halves the last step.
+template <typename K, bool AOS>
+__device__ __forceinline__ uint64_t upper_rank_from(const RangeArgs<K, AOS> &a, uint64_t r0, K U) {
+    const uint64_t n = a.G.n;
+    uint64_t lo = r0, step = 16;
+    while (lo + step < n && a.L.key(lo + step) <= U) {
+        lo += step;
+        step <<= 1;
+    }
+    uint64_t hi = lo + step < n ? lo + step : n;  // key(hi) > U, or hi == n
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (a.L.key(mid) <= U) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 template <typename K, bool AOS>
 __global__ __launch_bounds__(256) void k_range_count(RangeArgs<K, AOS> a) {
     const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -84,7 +104,9 @@ __global__ __launch_bounds__(256) void k_range_count(RangeArgs<K, AOS> a) {
     uint64_t r0 = 0, r1 = 0;
     if (L <= U) {
         r0 = lower_rank(a, L);
-        r1 = (U == key_max<K>()) ? a.G.n : lower_rank(a, (K)(U + 1));
+        if (U == key_max<K>()) r1 = a.G.n;
+        else if (a.layout == IDX_BS) r1 = upper_rank_from(a, r0, U);
+        else r1 = lower_rank(a, (K)(U + 1));
     }
     a.first_rank[q] = (uint32_t)r0;
     a.offsets[q] = r1 > r0 ? r1 - r0 : 0;
