@@ -155,8 +155,9 @@ __global__ __launch_bounds__(kPartThreads) void k_starts(const uint32_t *__restr
 
 // 4./5./7. One scatter pass: entry i goes to run run_of(i) of NB runs.  Per
 // tile a workgroup reserves one contiguous piece of every run the tile feeds
-// (one global atomic per run), then places entries with LDS atomics, so each
-// run's piece fills front to back.  The grid is one workgroup per compute
+// (one global atomic per run), then fills the pieces front to back in rounds
+// of kSub entries sorted by run in LDS, so consecutive lanes write
+// consecutive addresses.  The grid is one workgroup per compute
 // unit, each walking its own tiles, which bounds the partially written lines
 // in flight per XCD to about 32 workgroups x NB runs x 2 per output array.
 struct FwdCoarse {};
@@ -188,46 +189,176 @@ __device__ __forceinline__ uint32_t run_of(const ScatterArgs<K, Pass> &a, uint64
     else return a.p_in[i] >> a.shift;
 }
 
+// Entries of one staged round: each thread loads kSubPer of them, they are
+// sorted by run in LDS, and every run's piece leaves with consecutive lanes
+// writing consecutive addresses.  A tile whose runs span more than kSpan run
+// ids (a fine pass over a small batch) places entries directly instead.
+constexpr uint32_t kSubPer = 2;
+constexpr uint32_t kSub = kPartThreads * kSubPer;
+constexpr uint32_t kSpan = 256;
+
+template <typename K, typename Pass>
+struct Staged {
+    static constexpr bool bwd = std::is_same_v<Pass, Bwd>;
+    // per entry: query key, batch position, fine bucket (forward) or the
+    // (position, answer) pair (backward); and its run relative to the tile's
+    // smallest run
+    static constexpr size_t entry_bytes = (bwd ? 8 : sizeof(K) + 4 + 2) + 2;
+};
+
+template <typename K, typename Pass>
+size_t scatter_lds_bytes(uint32_t NB) {
+    return (((size_t)NB * 4 + 15) & ~(size_t)15) + (size_t)kSub * Staged<K, Pass>::entry_bytes;
+}
+
 template <typename K, typename Pass>
 __global__ __launch_bounds__(kPartThreads) void k_scatter(ScatterArgs<K, Pass> a) {
+    constexpr bool BWD = std::is_same_v<Pass, Bwd>;
+    constexpr bool COARSE = std::is_same_v<Pass, FwdCoarse>;
     extern __shared__ __align__(16) char smem[];
     uint32_t *s_cnt = (uint32_t *)smem;  // per run: count, then cursor
+    char *st = smem + (((size_t)a.NB * 4 + 15) & ~(size_t)15);
+    uint64_t *st_pk = (uint64_t *)st;               // backward
+    K *st_q = (K *)st;                              // forward
+    uint32_t *st_p = (uint32_t *)(st + (size_t)kSub * sizeof(K));
+    uint16_t *st_b = (uint16_t *)((char *)st_p + (size_t)kSub * 4);
+    uint16_t *st_r = BWD ? (uint16_t *)(st + (size_t)kSub * 8) : (uint16_t *)((char *)st_b + (size_t)kSub * 2);
+    __shared__ uint32_t s_sub[kSpan], s_off[kSpan], s_wsum[kSpan / kWave];
+    __shared__ uint32_t s_lo, s_hi;
     for (uint64_t tl = blockIdx.x; tl < a.ntiles; tl += gridDim.x) {
         for (uint32_t b = threadIdx.x; b < a.NB; b += blockDim.x) s_cnt[b] = 0;
+        if (threadIdx.x == 0) {
+            s_lo = 0xFFFFFFFFu;
+            s_hi = 0;
+        }
         __syncthreads();
         const uint64_t lo = tl * kPartTile, hi = tile_end(lo, a.m);
-        for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&s_cnt[run_of(a, i)], 1u);
+        uint32_t rmin = 0xFFFFFFFFu, rmax = 0;
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const uint32_t r = run_of(a, i);
+            atomicAdd(&s_cnt[r], 1u);
+            rmin = r < rmin ? r : rmin;
+            rmax = r > rmax ? r : rmax;
+        }
+        if (rmin != 0xFFFFFFFFu) {
+            atomicMin(&s_lo, rmin);
+            atomicMax(&s_hi, rmax);
+        }
         __syncthreads();
         for (uint32_t b = threadIdx.x; b < a.NB; b += blockDim.x) {
             const uint32_t c = s_cnt[b];
             s_cnt[b] = c ? atomicAdd(&a.cur[b], c) : 0u;
         }
         __syncthreads();
-        // four entries per thread per round, so their loads overlap
-        for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += 4 * (uint64_t)blockDim.x) {
-            uint32_t d[4];
+        const uint32_t r_lo = s_lo;
+        if (s_hi - r_lo >= kSpan) {
+            // direct placement: four entries per thread per round, so their loads overlap
+            for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += 4 * (uint64_t)blockDim.x) {
+                uint32_t d[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint64_t i = i0 + (uint64_t)u * blockDim.x;
-                d[u] = i < hi ? atomicAdd(&s_cnt[run_of(a, i)], 1u) : 0u;
-            }
+                for (int u = 0; u < 4; ++u) {
+                    const uint64_t i = i0 + (uint64_t)u * blockDim.x;
+                    d[u] = i < hi ? atomicAdd(&s_cnt[run_of(a, i)], 1u) : 0u;
+                }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint64_t i = i0 + (uint64_t)u * blockDim.x;
-                if (i >= hi) continue;
-                if constexpr (std::is_same_v<Pass, FwdCoarse>) {
-                    a.q_out[d[u]] = a.q_in[i];
-                    a.p_out[d[u]] = (uint32_t)i;
-                    a.b_out[d[u]] = a.b_in[i];
-                } else if constexpr (std::is_same_v<Pass, FwdFine>) {
-                    a.q_out[d[u]] = a.q_in[i];
-                    a.p_out[d[u]] = a.p_in[i];
-                } else {
-                    a.pk_out[d[u]] = ((uint64_t)a.p_in[i] << 32) | a.r_in[i];
+                for (int u = 0; u < 4; ++u) {
+                    const uint64_t i = i0 + (uint64_t)u * blockDim.x;
+                    if (i >= hi) continue;
+                    if constexpr (COARSE) {
+                        a.q_out[d[u]] = a.q_in[i];
+                        a.p_out[d[u]] = (uint32_t)i;
+                        a.b_out[d[u]] = a.b_in[i];
+                    } else if constexpr (!BWD) {
+                        a.q_out[d[u]] = a.q_in[i];
+                        a.p_out[d[u]] = a.p_in[i];
+                    } else {
+                        a.pk_out[d[u]] = ((uint64_t)a.p_in[i] << 32) | a.r_in[i];
+                    }
                 }
             }
+            __syncthreads();  // before the next tile clears the counters
+            continue;
         }
-        __syncthreads();  // before the next tile clears the counters
+        // staged rounds of kSub entries
+        for (uint64_t s0 = lo; s0 < hi; s0 += kSub) {
+            const uint32_t ns = hi - s0 < kSub ? (uint32_t)(hi - s0) : kSub;
+            if (threadIdx.x < kSpan) s_sub[threadIdx.x] = 0;
+            __syncthreads();
+            uint32_t rr[kSubPer], rk[kSubPer], pp[kSubPer];
+            K qq[kSubPer];
+            uint16_t bb[kSubPer];
+            uint64_t pk[kSubPer];
+#pragma unroll
+            for (uint32_t u = 0; u < kSubPer; ++u) {
+                const uint32_t j = u * kPartThreads + threadIdx.x;
+                rr[u] = kSpan;
+                if (j >= ns) continue;
+                const uint64_t i = s0 + j;
+                rr[u] = run_of(a, i) - r_lo;
+                rk[u] = atomicAdd(&s_sub[rr[u]], 1u);
+                if constexpr (BWD) {
+                    pk[u] = ((uint64_t)a.p_in[i] << 32) | a.r_in[i];
+                } else {
+                    qq[u] = a.q_in[i];
+                    pp[u] = COARSE ? (uint32_t)i : a.p_in[i];
+                    bb[u] = COARSE ? a.b_in[i] : (uint16_t)0;
+                }
+            }
+            __syncthreads();
+            // exclusive scan of the run counts of this round
+            if (threadIdx.x < kSpan) {
+                const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+                const uint32_t v = s_sub[threadIdx.x];
+                uint32_t inc = v;
+#pragma unroll
+                for (int off = 1; off < kWave; off <<= 1) {
+                    const uint32_t x = (uint32_t)__shfl_up((int)inc, off, kWave);
+                    if (lane >= (uint32_t)off) inc += x;
+                }
+                if (lane == kWave - 1) s_wsum[w] = inc;
+                s_off[threadIdx.x] = inc - v;
+            }
+            __syncthreads();
+            if (threadIdx.x < kSpan) {
+                uint32_t add = 0;
+                for (uint32_t w = 0; w < threadIdx.x / kWave; ++w) add += s_wsum[w];
+                s_off[threadIdx.x] += add;
+            }
+            __syncthreads();
+            // entries into the staging area, sorted by run
+#pragma unroll
+            for (uint32_t u = 0; u < kSubPer; ++u) {
+                if (rr[u] >= kSpan) continue;
+                const uint32_t j = s_off[rr[u]] + rk[u];
+                st_r[j] = (uint16_t)rr[u];
+                if constexpr (BWD) {
+                    st_pk[j] = pk[u];
+                } else {
+                    st_q[j] = qq[u];
+                    st_p[j] = pp[u];
+                    if constexpr (COARSE) st_b[j] = bb[u];
+                }
+            }
+            __syncthreads();
+            // every run's piece: consecutive staged entries to consecutive addresses
+#pragma unroll
+            for (uint32_t u = 0; u < kSubPer; ++u) {
+                const uint32_t j = u * kPartThreads + threadIdx.x;
+                if (j >= ns) continue;
+                const uint32_t r = st_r[j];
+                const uint32_t d = s_cnt[r_lo + r] + (j - s_off[r]);
+                if constexpr (BWD) {
+                    a.pk_out[d] = st_pk[j];
+                } else {
+                    a.q_out[d] = st_q[j];
+                    a.p_out[d] = st_p[j];
+                    if constexpr (COARSE) a.b_out[d] = st_b[j];
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x < kSpan && r_lo + threadIdx.x < a.NB) s_cnt[r_lo + threadIdx.x] += s_sub[threadIdx.x];
+            __syncthreads();
+        }
     }
 }
 
@@ -370,7 +501,8 @@ int partition_chunk(idx_index *h, const K *q, uint64_t m, uint32_t *out, uint32_
         a.ntiles = tiles;
         a.B2 = B2;
         a.NB = B1;
-        hipLaunchKernelGGL((k_scatter<K, FwdCoarse>), dim3(sgrid), dim3(kPartThreads), (size_t)B1 * 4, s, a);
+        const size_t lds = scatter_lds_bytes<K, FwdCoarse>(B1);
+        hipLaunchKernelGGL((k_scatter<K, FwdCoarse>), dim3(sgrid), dim3(kPartThreads), lds, s, a);
         IDX_LAUNCH_CHECK();
     }
     {
@@ -385,7 +517,8 @@ int partition_chunk(idx_index *h, const K *q, uint64_t m, uint32_t *out, uint32_
         a.ntiles = tiles;
         a.B2 = B2;
         a.NB = B;
-        hipLaunchKernelGGL((k_scatter<K, FwdFine>), dim3(sgrid), dim3(kPartThreads), (size_t)B * 4, s, a);
+        const size_t lds = scatter_lds_bytes<K, FwdFine>(B);
+        hipLaunchKernelGGL((k_scatter<K, FwdFine>), dim3(sgrid), dim3(kPartThreads), lds, s, a);
         IDX_LAUNCH_CHECK();
     }
     // answers in partitioned order go to p1 (free after the fine pass)
@@ -402,7 +535,8 @@ int partition_chunk(idx_index *h, const K *q, uint64_t m, uint32_t *out, uint32_
         a.ntiles = tiles;
         a.NB = D;
         a.shift = shift;
-        hipLaunchKernelGGL((k_scatter<K, Bwd>), dim3(sgrid), dim3(kPartThreads), (size_t)D * 4, s, a);
+        const size_t lds = scatter_lds_bytes<K, Bwd>(D);
+        hipLaunchKernelGGL((k_scatter<K, Bwd>), dim3(sgrid), dim3(kPartThreads), lds, s, a);
         IDX_LAUNCH_CHECK();
     }
     const uint64_t ptile = (uint64_t)kPlaceThreads * kPlacePer;
