@@ -169,12 +169,16 @@ __global__ __launch_bounds__(BT) void k_batch_point(const Desc *__restrict__ des
 enum : uint8_t { Q_POINT = 0, Q_RANGE = 1 };
 
 // Sorted rank of the first key >= x in the index of descriptor d.
-template <typename K>
+// Lower-bound rank of x in index d.  EYT selects the forms compiled in:
+// false = BS and learned, true = EBS and EKS (the caller routes each index to
+// the matching kind).
+template <typename K, bool EYT>
 __device__ __forceinline__ uint64_t form_lower_rank(const Desc &d, const Geo &G, K x) {
     const K *keys = (const K *)d.keys;
     const uint64_t n = d.n;
     if (n == 0) return 0;
-    if (d.form == F_BS) {
+    if constexpr (!EYT) {
+        if (d.form == F_LEARNED) return learned_lower_rank(keys, n, d.root, d.leaves, x);
         uint64_t base = 0, len = n;
         while (len > 1) {
             const uint64_t half = len >> 1;
@@ -182,21 +186,46 @@ __device__ __forceinline__ uint64_t form_lower_rank(const Desc &d, const Geo &G,
             len -= half;
         }
         return base + (keys[base] < x ? 1 : 0);
+    } else {
+        // Eytzinger layouts: deepest path position of the lower bound, then its rank
+        const uint64_t off = d.form == F_EBS ? 1 : 0;
+        const uint32_t g = G.g, kf = G.k;
+        uint64_t c = 0, cand = ~0ull;
+        if (scan_vec_ok(G, off, sizeof(K), false)) {  // whole nodes in registers
+            K kk[kScanNodeBytes / sizeof(K)];
+            while (c * g < n) {
+                const uint64_t i = c * g;
+                const uint32_t nv = (n - i) < g ? (uint32_t)(n - i) : g;
+                node_keys(keys, i, g, kk);
+                const uint32_t j = node_below(kk, nv, x);
+                if (j < nv) cand = i + j;
+                c = c * kf + 1 + j;
+            }
+            return cand == ~0ull ? n : slot_rank(G, cand);
+        }
+        while (c * g < n) {
+            const uint64_t i = c * g;
+            const uint64_t nv = (n - i) < g ? (n - i) : g;
+            uint32_t j = 0;
+            for (uint32_t e = 0; e < nv; ++e) j += keys[off + i + e] < x ? 1u : 0u;
+            if (j < nv) cand = i + j;
+            c = c * kf + 1 + j;
+        }
+        return cand == ~0ull ? n : slot_rank(G, cand);
     }
-    if (d.form == F_LEARNED) return learned_lower_rank(keys, n, d.root, d.leaves, x);
-    // Eytzinger layouts: deepest path position of the lower bound, then its rank
-    const uint64_t off = d.form == F_EBS ? 1 : 0;
-    const uint32_t g = G.g, kf = G.k;
-    uint64_t c = 0, cand = ~0ull;
-    while (c * g < n) {
-        const uint64_t i = c * g;
-        const uint64_t nv = (n - i) < g ? (n - i) : g;
-        uint32_t j = 0;
-        for (uint32_t e = 0; e < nv; ++e) j += keys[off + i + e] < x ? 1u : 0u;
-        if (j < nv) cand = i + j;
-        c = c * kf + 1 + j;
+}
+
+// Point answer in index d, with the forms of one kind compiled in (as above).
+template <typename K, bool EYT>
+__device__ __forceinline__ uint32_t form_find_kind(const Desc &d, K x) {
+    const K *keys = (const K *)d.keys;
+    if constexpr (!EYT) {
+        if (d.form == F_BS) return bs_find<K>(keys, d.rows, d.n, x);
+        return learned_find<K>(keys, d.rows, d, x);
+    } else {
+        if (d.form == F_EBS) return ebs_find<K>(keys, d.rows, d.n, d.m_full, x);
+        return eks_find<K>(keys, d.rows, d, x);
     }
-    return cand == ~0ull ? n : slot_rank(G, cand);
 }
 
 template <typename K>
@@ -212,7 +241,12 @@ __device__ __forceinline__ uint32_t form_find(const Desc &d, K x) {
 
 // Pass 1: point answers; range sizes into offs (scanned afterwards) and the
 // first rank of every range.
-template <typename K>
+// Both passes come in two kinds, each launched only when the batch holds
+// such indexes, so neither carries the other's registers: EYT = false serves
+// the sorted-array forms (BS, learned), EYT = true the Eytzinger forms.
+__device__ __forceinline__ bool is_eyt(uint32_t form) { return form == F_EBS || form == F_EKS; }
+
+template <typename K, bool EYT>
 __global__ __launch_bounds__(BT) void k_batch_mixed_count(const Desc *__restrict__ descs, const Geo *__restrict__ geos,
                                                           uint32_t count, const uint64_t *__restrict__ off, uint64_t m,
                                                           const K *__restrict__ lo, const K *__restrict__ hi,
@@ -233,8 +267,9 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_count(const Desc *__restrict
             if (p >= c1) continue;
             const uint32_t ii = (i0 == i1) ? i0 : owner(off, i0, i1 + 1, p);
             const Desc d = descs[ii];
+            if (is_eyt(d.form) != EYT) continue;
             if (kind[p] == Q_POINT) {
-                out[p] = form_find<K>(d, lo[p]);
+                out[p] = form_find_kind<K, EYT>(d, lo[p]);
                 first[p] = 0;
                 offs[p] = 0;
                 continue;
@@ -244,8 +279,8 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_count(const Desc *__restrict
             uint64_t r0 = 0, r1 = 0;
             if (L <= U) {
                 const Geo &G = geos[ii];
-                r0 = form_lower_rank<K>(d, G, L);
-                r1 = (U == ~K(0)) ? d.n : form_lower_rank<K>(d, G, (K)(U + 1));
+                r0 = form_lower_rank<K, EYT>(d, G, L);
+                r1 = (U == ~K(0)) ? d.n : form_lower_rank<K, EYT>(d, G, (K)(U + 1));
             }
             first[p] = (uint32_t)r0;
             offs[p] = r1 > r0 ? r1 - r0 : 0;
@@ -254,7 +289,7 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_count(const Desc *__restrict
 }
 
 // Pass 2: row IDs of every range in key order at its offset.
-template <typename K>
+template <typename K, bool EYT>
 __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict__ descs, const Geo *__restrict__ geos,
                                                          uint32_t count, const uint64_t *__restrict__ off, uint64_t m,
                                                          const K *__restrict__ lo, const K *__restrict__ hi,
@@ -290,18 +325,26 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
             if (live && kind[p] == Q_RANGE) {
                 const uint64_t o = offs[p], cnt = offs[p + 1] - o;
                 const Desc d = descs[ii];
-                if (cnt > 0 && (d.form == F_BS || d.form == F_LEARNED)) {
-                    run_rows = d.rows;
-                    run_first = first[p];
-                    run_out = o;
-                    run_len = cnt;
-                } else if (cnt > 0) {
-                    Load<K, false> Ld{};
-                    Ld.k = (const K *)d.keys;
-                    Ld.r = d.rows;
-                    Ld.node = 1;
-                    paused = eyt_scan_lane(Ld, geos[ii], d.form == F_EBS ? 1 : 0, lo[p], hi[p], (uint64_t)first[p],
-                                           cnt, rows_out + o, st);
+                if constexpr (!EYT) {
+                    if (cnt > 0 && !is_eyt(d.form)) {
+                        run_rows = d.rows;
+                        run_first = first[p];
+                        run_out = o;
+                        run_len = cnt;
+                    }
+                } else if (cnt > 0 && is_eyt(d.form)) {
+                    const Geo &Gi = geos[ii];
+                    const uint64_t eoff = d.form == F_EBS ? 1 : 0;
+                    if (scan_vec_ok(Gi, eoff, sizeof(K), false)) {
+                        paused = eyt_scan_lane_vec((const K *)d.keys, d.rows, Gi, lo[p], hi[p], (uint64_t)first[p],
+                                                   cnt, rows_out + o, st);
+                    } else {
+                        Load<K, false> Ld{};
+                        Ld.k = (const K *)d.keys;
+                        Ld.r = d.rows;
+                        Ld.node = 1;
+                        paused = eyt_scan_lane(Ld, Gi, eoff, lo[p], hi[p], (uint64_t)first[p], cnt, rows_out + o, st);
+                    }
                     if (paused) {
                         scan_o = o;
                         scan_cnt = cnt;
@@ -309,7 +352,7 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
                 }
             }
             // paused Eytzinger scans continue with the whole wave, one at a time
-            uint64_t pend = __ballot(paused);
+            uint64_t pend = EYT ? __ballot(paused) : 0ull;
             while (pend) {
                 const int src = __builtin_ctzll(pend);
                 pend &= pend - 1;
@@ -334,7 +377,7 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
             // element finds its run by a binary search over the runs' starts
             // (per wave, in LDS), so the wave copies 64 elements per step with
             // CU independent loads per lane in flight
-            {
+            if constexpr (!EYT) {
                 const uint32_t w = threadIdx.x / kWave;
                 uint32_t len32 = (uint32_t)run_len, incl = len32;
 #pragma unroll
@@ -388,6 +431,8 @@ struct idx_batch {
     idx::Geo *geos = nullptr;    // device, one per index (tree geometry for range lookups)
     uint32_t count = 0;
     bool u64 = false;
+    bool has_sorted = false;  // holds BS or learned indexes
+    bool has_eyt = false;     // holds EBS or EKS indexes
     int cu_count = 256;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -470,6 +515,10 @@ int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream strea
     if (!b) return IDX_ERR_NOMEM;
     b->count = count;
     b->u64 = u64;
+    for (uint32_t i = 0; i < count; ++i) {
+        if (host[i].form == F_EBS || host[i].form == F_EKS) b->has_eyt = true;
+        else b->has_sorted = true;
+    }
     hipStream_t s = (hipStream_t)stream;
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
@@ -554,14 +603,18 @@ int idx_batch_mixed(idx_batch_t b, uint64_t m, const void *lo, const void *hi, c
     const uint32_t grid = (uint32_t)b->cu_count * 8;
     int rc = IDX_OK;
     do {
-        if (b->u64)
-            hipLaunchKernelGGL(k_batch_mixed_count<uint64_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count,
-                               offsets, m, (const uint64_t *)lo, (const uint64_t *)hi, kind, out_rowid, first,
-                               range_offsets);
-        else
-            hipLaunchKernelGGL(k_batch_mixed_count<uint32_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count,
-                               offsets, m, (const uint32_t *)lo, (const uint32_t *)hi, kind, out_rowid, first,
-                               range_offsets);
+        for (int e = 0; e < 2; ++e) {
+            if (!(e ? b->has_eyt : b->has_sorted)) continue;
+            if (b->u64) {
+                const auto kern = e ? k_batch_mixed_count<uint64_t, true> : k_batch_mixed_count<uint64_t, false>;
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count, offsets, m,
+                                   (const uint64_t *)lo, (const uint64_t *)hi, kind, out_rowid, first, range_offsets);
+            } else {
+                const auto kern = e ? k_batch_mixed_count<uint32_t, true> : k_batch_mixed_count<uint32_t, false>;
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count, offsets, m,
+                                   (const uint32_t *)lo, (const uint32_t *)hi, kind, out_rowid, first, range_offsets);
+            }
+        }
         if (hipGetLastError() != hipSuccess) {
             rc = IDX_ERR_HIP;
             break;
@@ -580,14 +633,18 @@ int idx_batch_mixed(idx_batch_t b, uint64_t m, const void *lo, const void *hi, c
             rc = IDX_ERR_CAPACITY;
             break;
         }
-        if (b->u64)
-            hipLaunchKernelGGL(k_batch_mixed_fill<uint64_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count,
-                               offsets, m, (const uint64_t *)lo, (const uint64_t *)hi, kind, first, range_offsets,
-                               range_rowids);
-        else
-            hipLaunchKernelGGL(k_batch_mixed_fill<uint32_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count,
-                               offsets, m, (const uint32_t *)lo, (const uint32_t *)hi, kind, first, range_offsets,
-                               range_rowids);
+        for (int e = 0; e < 2; ++e) {
+            if (!(e ? b->has_eyt : b->has_sorted)) continue;
+            if (b->u64) {
+                const auto kern = e ? k_batch_mixed_fill<uint64_t, true> : k_batch_mixed_fill<uint64_t, false>;
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count, offsets, m,
+                                   (const uint64_t *)lo, (const uint64_t *)hi, kind, first, range_offsets, range_rowids);
+            } else {
+                const auto kern = e ? k_batch_mixed_fill<uint32_t, true> : k_batch_mixed_fill<uint32_t, false>;
+                hipLaunchKernelGGL(kern, dim3(grid), dim3(BT), 0, s, b->descs, b->geos, b->count, offsets, m,
+                                   (const uint32_t *)lo, (const uint32_t *)hi, kind, first, range_offsets, range_rowids);
+            }
+        }
         if (hipGetLastError() != hipSuccess) rc = IDX_ERR_HIP;
     } while (0);
     (void)hipFreeAsync(tmp, s);
