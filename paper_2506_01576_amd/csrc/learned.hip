@@ -557,15 +557,34 @@ __device__ __forceinline__ uint32_t count_below_slots(const Load<K, true> &L, ui
             }
         }
     } else {
+        // Two rounds: first the slots whose key lies in the 128-byte line of
+        // the window's first key; the rest only when all of those are below x
+        // (keys ascend, so otherwise the lower bound is already among them).
+        // A window within one line costs that line alone.
         K k[W];
-#pragma unroll
-        for (int j = 0; j < W; ++j) k[j] = (uint32_t)j < len ? L.key(b + j) : K(0);
+        bool got[W];
+        const uint64_t line0 = (uint64_t)(uintptr_t)(L.base + b * (uint64_t)L.stride) >> 7;
+        uint32_t n1 = 0;
 #pragma unroll
         for (int j = 0; j < W; ++j) {
-            if ((uint32_t)j >= len) continue;
-            cnt += k[j] < x ? 1u : 0u;
-            e |= k[j] == x;
+            const uint64_t a = (uint64_t)(uintptr_t)(L.base + (b + j) * (uint64_t)L.stride);
+            got[j] = (uint32_t)j < len && ((a + sizeof(K) - 1) >> 7) == line0;
+            k[j] = got[j] ? L.key(b + j) : K(0);
+            n1 += got[j] ? 1u : 0u;
         }
+#pragma unroll
+        for (int j = 0; j < W; ++j) cnt += (got[j] && k[j] < x) ? 1u : 0u;
+        if (cnt == n1 && n1 < len) {
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                if ((uint32_t)j >= len || got[j]) continue;
+                k[j] = L.key(b + j);
+                got[j] = true;
+                cnt += k[j] < x ? 1u : 0u;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < W; ++j) e |= got[j] && k[j] == x;
         if (e) rw = L.row(b + cnt);
     }
     eq = e;

@@ -21,16 +21,47 @@ __device__ __forceinline__ uint32_t count_below(const K *__restrict__ keys, uint
     const uint64_t a0 = b & ~(uint64_t)(V - 1);
     const uint64_t end = b + len;
     const uint4 *p = (const uint4 *)(keys + a0);
+    // Two rounds: first the chunks in the 128-byte line of the window's first
+    // chunk, the rest only when every window key among them is below x (keys
+    // ascend, so otherwise the lower bound is among them).
+    const uint64_t line0 = (uint64_t)(uintptr_t)p >> 7;
     uint4 w[CH];
+    bool got[CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c)
-        if (a0 + (uint64_t)c * V < end) w[c] = p[c];
+    for (int c = 0; c < CH; ++c) {
+        got[c] = a0 + (uint64_t)c * V < end && ((uint64_t)(uintptr_t)(p + c) >> 7) == line0;
+        if (got[c]) w[c] = p[c];
+    }
+    uint32_t below = 0, in1 = 0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        if (!got[c]) continue;
+        const uint64_t s = a0 + (uint64_t)c * V;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const uint64_t slot = s + v;
+            const bool in = slot >= b && slot < end;
+            uint64_t kv;
+            if constexpr (sizeof(K) == 8) kv = v == 0 ? (((uint64_t)w[c].y << 32) | w[c].x) : (((uint64_t)w[c].w << 32) | w[c].z);
+            else kv = v == 0 ? w[c].x : v == 1 ? w[c].y : v == 2 ? w[c].z : w[c].w;
+            in1 += in ? 1u : 0u;
+            below += (in && (K)kv < x) ? 1u : 0u;
+        }
+    }
+    if (below == in1) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+            if (!got[c] && a0 + (uint64_t)c * V < end) {
+                w[c] = p[c];
+                got[c] = true;
+            }
+    }
     uint32_t cnt = 0;
     bool e = false;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
         const uint64_t s = a0 + (uint64_t)c * V;
-        if (s >= end) continue;
+        if (s >= end || !got[c]) continue;
         K kk[V];
         if constexpr (sizeof(K) == 8) {
             kk[0] = ((uint64_t)w[c].y << 32) | w[c].x;
