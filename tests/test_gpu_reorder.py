@@ -129,3 +129,26 @@ def test_partitioned_many_buckets(layout, k, aos, bits):
             # a second call reuses the cached splitters
             got2 = ix.point(to_dev(q[: m // 3]))
             assert torch.equal(got2, to_dev(expect[: m // 3]))
+
+
+@pytest.mark.parametrize("m", [(1 << 17) + 5, (1 << 22) + 7])
+def test_partitioned_scatter_paths(m):
+    """n = 2^24 + 3 keys (512 rank buckets: 64 coarse x 8 fine).  With 2^17
+    lookups every partition tile spans all coarse buckets, so the fine pass
+    places entries directly; with 2^22 a tile spans few of them and every
+    pass stages its rounds in LDS.  Both must give the generator's answers."""
+    n = (1 << 24) + 3
+    seed = gen.BASE_SEED + 47
+    keys, rows = gen.unique_keys(seed, n, 64, 63)
+    q, expect = gen.point_queries(seed, n, m, 0.8, 64, 63)
+    sk, sr = oracle.stable_sort(keys, rows)
+    sample = np.random.default_rng(m).integers(0, m, 2048)
+    want_s = oracle.point(sk, sr, q[sample], nthreads=8)
+    for layout, k in (("bs", 1), ("ebs", 2)):
+        with idx.Index(to_dev(keys), to_dev(rows), layout=layout, k=k) as ix:
+            ix.set_params(reorder=2)
+            say(f"partitioned paths {layout} n={n} m={m}")
+            got = ix.point(to_dev(q))
+            torch.cuda.synchronize()
+            assert torch.equal(got, to_dev(expect))
+            assert np.array_equal(rows_host(got)[sample], want_s)
