@@ -251,8 +251,9 @@ def run_skewed(args, idx, gen, np, torch, dev, log):
     _, _, laos, lp = autotune.choose(1 << 26, 64, "learned")
     cands = [("learned_4096", 4096, False, {"per_lane": 8}),
              ("learned_tuned", lp.get("leaves", 1 << 22), laos, {"per_lane": lp.get("per_lane", 8)})]
-    if laos:  # the tuned leaf count on the plain sorted array too
+    if laos:  # the tuned leaf count on the plain sorted array too, at 8 and 4 lookups per lane
         cands.append(("learned_tuned_soa", lp.get("leaves", 1 << 22), False, {"per_lane": lp.get("per_lane", 8)}))
+        cands.append(("learned_tuned_soa_r4", lp.get("leaves", 1 << 22), False, {"per_lane": 4}))
     for name, L, aos, params in cands:
         arr = base if not aos else base.relayout("bs", 1, aos)
         a = torch.cuda.Event(enable_timing=True)
@@ -366,6 +367,12 @@ def run_study(args, idx, gen, np, torch, dev, log):
             ms = timed(ix, q)
             ok = bool(torch.equal(out, e))
             row[fname] = {"ms": round(ms, 4), "lookups_per_s": m / ms * 1e3, "exact": ok}
+        # the learned form reading each window in one round (cached windows)
+        ln.set_params(**dict(ln.params(), window_rounds=1))
+        ms = timed(ln, q)
+        row["LEARNED(1 round)"] = {"ms": round(ms, 4), "lookups_per_s": m / ms * 1e3,
+                                   "exact": bool(torch.equal(out, e))}
+        ln.set_params(**dict(ln.params(), window_rounds=2))
         res["skew"][name] = row
         log(f"study skew {name}: " + ", ".join(f"{f} {v['ms']:.2f}" for f, v in row.items() if isinstance(v, dict)))
         del q, e

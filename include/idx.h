@@ -264,6 +264,11 @@ typedef struct idx_lookup_params {
     uint32_t reorder;    /* 1 = sort each workgroup's lookups locally before searching */
     uint32_t early_exit; /* 1 = stop at an equal key (only used when keys are unique) */
     uint32_t model;      /* 0/1 = use the learned model when one is trained (idx_learn), 2 = ignore it */
+    uint32_t window_rounds; /* short-window scan (BS and learned forms): 0 = default (2); 2 = read the
+                               128-byte line of the window's first key, the rest only when all its
+                               keys are below the query (fewer lines when they come from HBM);
+                               1 = read the whole window at once (shorter chains when it is cached,
+                               e.g. skewed or sorted batches) */
 } idx_lookup_params;
 
 /* Set (p != NULL) or reset to defaults (p == NULL).  Errors: IDX_ERR_ARG for an

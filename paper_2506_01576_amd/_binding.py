@@ -72,6 +72,7 @@ class idx_lookup_params(ctypes.Structure):
         ("reorder", ctypes.c_uint32),
         ("early_exit", ctypes.c_uint32),
         ("model", ctypes.c_uint32),
+        ("window_rounds", ctypes.c_uint32),
     ]
 
     def as_dict(self):

@@ -537,7 +537,7 @@ namespace {
 // holding a 64-bit key is one 16-byte vector load.
 template <typename K, int W>
 __device__ __forceinline__ uint32_t count_below_slots(const Load<K, true> &L, uint64_t b, uint32_t len, K x,
-                                                      bool &eq, uint32_t &row) {
+                                                      bool &eq, uint32_t &row, bool two = true) {
     uint32_t cnt = 0;
     bool e = false;
     uint32_t rw = kMiss;
@@ -568,13 +568,13 @@ __device__ __forceinline__ uint32_t count_below_slots(const Load<K, true> &L, ui
 #pragma unroll
         for (int j = 0; j < W; ++j) {
             const uint64_t a = (uint64_t)(uintptr_t)(L.base + (b + j) * (uint64_t)L.stride);
-            got[j] = (uint32_t)j < len && ((a + sizeof(K) - 1) >> 7) == line0;
+            got[j] = (uint32_t)j < len && (!two || ((a + sizeof(K) - 1) >> 7) == line0);
             k[j] = got[j] ? L.key(b + j) : K(0);
             n1 += got[j] ? 1u : 0u;
         }
 #pragma unroll
         for (int j = 0; j < W; ++j) cnt += (got[j] && k[j] < x) ? 1u : 0u;
-        if (cnt == n1 && n1 < len) {
+        if (two && cnt == n1 && n1 < len) {
 #pragma unroll
             for (int j = 0; j < W; ++j) {
                 if ((uint32_t)j >= len || got[j]) continue;
@@ -645,10 +645,10 @@ __global__ __launch_bounds__(1024) void k_point_learned(Load<K, AOS> keys, uint6
                 bool eq;
                 if constexpr (AOS) {
                     uint32_t row;
-                    (void)count_below_slots<K, STOP + 1>(keys, b[r], (uint32_t)sl, x[r], eq, row);
+                    (void)count_below_slots<K, STOP + 1>(keys, b[r], (uint32_t)sl, x[r], eq, row, io.rounds == 2);
                     if (eq) res = row;
                 } else {
-                    const uint32_t c = count_below<K, 16>(keys.k, b[r], (uint32_t)sl, x[r], eq);
+                    const uint32_t c = count_below<K, 16>(keys.k, b[r], (uint32_t)sl, x[r], eq, io.rounds == 2);
                     if (eq) res = keys.r[(uint64_t)b[r] + c];
                 }
             }
@@ -674,6 +674,7 @@ int point_learned(idx_index *h, const PointIO &pio, hipStream_t s) {
         io.local_sort = pio.local_sort ? 1u : 0u;                                                           \
         io.xcd = pio.xcd ? 1u : 0u;                                                                         \
         io.sort_off = 0;                                                                                    \
+        io.rounds = h->params.window_rounds == 1 ? 1u : 2u;                                                 \
         set_tiles(io, tile);                                                                                \
         uint64_t grid = io.iters;                                                                           \
         if (h->params.persistent) {                                                                         \

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(1024) void k_point_bs(PointArgs<K, AOS> a) {
                 if constexpr (!AOS) {
                     const uint64_t sl = (len + 1) < (n - base[r]) ? (len + 1) : (n - base[r]);
                     bool eq;
-                    const uint32_t c = count_below<K, 16>(a.L.k, base[r], (uint32_t)sl, x[r], eq);
+                    const uint32_t c = count_below<K, 16>(a.L.k, base[r], (uint32_t)sl, x[r], eq, a.io.rounds == 2);
                     if (eq) res = a.L.row(base[r] + c);
                 } else {
                     const K kb = a.L.key(base[r]);
@@ -442,6 +442,7 @@ PointArgs<K, AOS> make_args(const idx_index *h, const PointIO &io, uint32_t pin_
     a.io.m = io.m;
     a.io.local_sort = io.local_sort ? 1u : 0u;
     a.io.xcd = io.xcd ? 1u : 0u;
+    a.io.rounds = h->params.window_rounds == 1 ? 1u : 2u;
     a.pin = (const K *)h->pin;
     a.pin_entries = pin_levels ? h->pin_keys : 0;
     a.pin_levels = pin_levels;
@@ -652,6 +653,9 @@ int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_p
     if (p.early_exit == 0) p.early_exit = 1;
     if (p.early_exit > 2) return IDX_ERR_ARG;
     if (p.model > 2) return IDX_ERR_ARG;
+    // short-window scan: 0 = default (two rounds), 1 = one round, 2 = two rounds
+    if (p.window_rounds == 0) p.window_rounds = 2;
+    if (p.window_rounds > 2) return IDX_ERR_ARG;
     *out = p;
     return IDX_OK;
 }

@@ -39,7 +39,7 @@ struct QueryIO {
     uint32_t local_sort;  // 1: sort each tile in LDS first
     uint32_t xcd;         // 1: XCD-contiguous tile order
     uint32_t sort_off;    // byte offset of the sort buffer in dynamic LDS
-    uint32_t pad;
+    uint32_t rounds;      // short-window scan: 1 = whole window at once, 2 = first line first
 };
 
 // Tile of loop slot `it`; >= ntiles for the padding slots of the remap.

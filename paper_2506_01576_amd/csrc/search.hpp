@@ -15,21 +15,23 @@ namespace idx {
 // them equals x.  Reads whole 16-byte chunks covering the window: up to one
 // chunk beyond b + len, which the padded layout allocations keep in bounds.
 template <typename K, int W>
-__device__ __forceinline__ uint32_t count_below(const K *__restrict__ keys, uint64_t b, uint32_t len, K x, bool &eq) {
+__device__ __forceinline__ uint32_t count_below(const K *__restrict__ keys, uint64_t b, uint32_t len, K x, bool &eq,
+                                                bool two = true) {
     constexpr int V = 16 / sizeof(K);
     constexpr int CH = W / V + 1;
     const uint64_t a0 = b & ~(uint64_t)(V - 1);
     const uint64_t end = b + len;
     const uint4 *p = (const uint4 *)(keys + a0);
-    // Two rounds: first the chunks in the 128-byte line of the window's first
-    // chunk, the rest only when every window key among them is below x (keys
-    // ascend, so otherwise the lower bound is among them).
+    // Two rounds (two = true): first the chunks in the 128-byte line of the
+    // window's first chunk, the rest only when every window key among them is
+    // below x (keys ascend, so otherwise the lower bound is among them).  One
+    // round reads every chunk at once.
     const uint64_t line0 = (uint64_t)(uintptr_t)p >> 7;
     uint4 w[CH];
     bool got[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-        got[c] = a0 + (uint64_t)c * V < end && ((uint64_t)(uintptr_t)(p + c) >> 7) == line0;
+        got[c] = a0 + (uint64_t)c * V < end && (!two || ((uint64_t)(uintptr_t)(p + c) >> 7) == line0);
         if (got[c]) w[c] = p[c];
     }
     uint32_t below = 0, in1 = 0;
@@ -48,7 +50,7 @@ __device__ __forceinline__ uint32_t count_below(const K *__restrict__ keys, uint
             below += (in && (K)kv < x) ? 1u : 0u;
         }
     }
-    if (below == in1) {
+    if (two && below == in1) {
 #pragma unroll
         for (int c = 0; c < CH; ++c)
             if (!got[c] && a0 + (uint64_t)c * V < end) {
