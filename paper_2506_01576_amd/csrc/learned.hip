@@ -600,7 +600,7 @@ constexpr uint32_t window_stop() {
     return AOS ? 7u : 15u;
 }
 
-template <typename K, int R, bool SORT, bool AOS>
+template <typename K, int R, bool SORT, bool AOS, bool TWO>
 __global__ __launch_bounds__(1024) void k_point_learned(Load<K, AOS> keys, uint64_t n, RootRec root,
                                                         const LeafRec *__restrict__ leaves, QueryIO<K> io) {
     extern __shared__ __align__(16) char smem[];
@@ -645,10 +645,10 @@ __global__ __launch_bounds__(1024) void k_point_learned(Load<K, AOS> keys, uint6
                 bool eq;
                 if constexpr (AOS) {
                     uint32_t row;
-                    (void)count_below_slots<K, STOP + 1>(keys, b[r], (uint32_t)sl, x[r], eq, row, io.rounds == 2);
+                    (void)count_below_slots<K, STOP + 1>(keys, b[r], (uint32_t)sl, x[r], eq, row, TWO);
                     if (eq) res = row;
                 } else {
-                    const uint32_t c = count_below<K, 16>(keys.k, b[r], (uint32_t)sl, x[r], eq, io.rounds == 2);
+                    const uint32_t c = count_below<K, 16>(keys.k, b[r], (uint32_t)sl, x[r], eq, TWO);
                     if (eq) res = keys.r[(uint64_t)b[r] + c];
                 }
             }
@@ -665,6 +665,21 @@ int point_learned(idx_index *h, const PointIO &pio, hipStream_t s) {
     const uint32_t block = h->params.block;
     const uint32_t R = h->params.per_lane;
     const uint64_t tile = (uint64_t)block * R;
+#define IDX_LEARNED_KERNELS(KT, RR, TW)                                                                     \
+    do {                                                                                                    \
+        if (h->aos && io.local_sort)                                                                        \
+            hipLaunchKernelGGL((k_point_learned<KT, RR, true, true, TW>), dim3(g), dim3(block), smem, s,    \
+                               make_load<KT, true>(h), h->n, M->root, M->leaves, io);                       \
+        else if (h->aos)                                                                                    \
+            hipLaunchKernelGGL((k_point_learned<KT, RR, false, true, TW>), dim3(g), dim3(block), smem, s,   \
+                               make_load<KT, true>(h), h->n, M->root, M->leaves, io);                       \
+        else if (io.local_sort)                                                                             \
+            hipLaunchKernelGGL((k_point_learned<KT, RR, true, false, TW>), dim3(g), dim3(block), smem, s,   \
+                               make_load<KT, false>(h), h->n, M->root, M->leaves, io);                      \
+        else                                                                                                \
+            hipLaunchKernelGGL((k_point_learned<KT, RR, false, false, TW>), dim3(g), dim3(block), smem, s,  \
+                               make_load<KT, false>(h), h->n, M->root, M->leaves, io);                      \
+    } while (0)
 #define IDX_LEARNED_LAUNCH(KT, RR)                                                                          \
     do {                                                                                                    \
         QueryIO<KT> io{};                                                                                   \
@@ -684,18 +699,8 @@ int point_learned(idx_index *h, const PointIO &pio, hipStream_t s) {
         }                                                                                                   \
         const uint32_t g = (uint32_t)(grid ? (grid > 0x7FFFFFFFull ? 0x7FFFFFFFull : grid) : 1);            \
         const size_t smem = io.local_sort ? sort_lds_bytes((uint32_t)tile, sizeof(KT)) : 0;                 \
-        if (h->aos && io.local_sort)                                                                        \
-            hipLaunchKernelGGL((k_point_learned<KT, RR, true, true>), dim3(g), dim3(block), smem, s,        \
-                               make_load<KT, true>(h), h->n, M->root, M->leaves, io);                       \
-        else if (h->aos)                                                                                    \
-            hipLaunchKernelGGL((k_point_learned<KT, RR, false, true>), dim3(g), dim3(block), smem, s,       \
-                               make_load<KT, true>(h), h->n, M->root, M->leaves, io);                       \
-        else if (io.local_sort)                                                                             \
-            hipLaunchKernelGGL((k_point_learned<KT, RR, true, false>), dim3(g), dim3(block), smem, s,       \
-                               make_load<KT, false>(h), h->n, M->root, M->leaves, io);                      \
-        else                                                                                                \
-            hipLaunchKernelGGL((k_point_learned<KT, RR, false, false>), dim3(g), dim3(block), smem, s,      \
-                               make_load<KT, false>(h), h->n, M->root, M->leaves, io);                      \
+        if (io.rounds == 2) IDX_LEARNED_KERNELS(KT, RR, true);                                              \
+        else IDX_LEARNED_KERNELS(KT, RR, false);                                                            \
     } while (0)
     if (h->u64) {
         switch (R) {
@@ -713,6 +718,7 @@ int point_learned(idx_index *h, const PointIO &pio, hipStream_t s) {
         }
     }
 #undef IDX_LEARNED_LAUNCH
+#undef IDX_LEARNED_KERNELS
     IDX_LAUNCH_CHECK();
     return IDX_OK;
 }

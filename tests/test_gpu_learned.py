@@ -321,3 +321,26 @@ def test_auto_keeps_linear_root_on_uniform_keys():
     say(f"uniform mean window: linear {lin:.2f}, spline {spl:.2f}, auto {auto['feature']}")
     assert np.log2(1 + lin) <= np.log2(1 + spl) + 1
     assert auto["feature"] == LINEAR and auto["segments"] == 0
+
+
+@pytest.mark.parametrize("aos", [False, True])
+@pytest.mark.parametrize("rounds", [1, 2])
+def test_window_rounds_parity(aos, rounds):
+    """Both short-window scan modes (whole window at once, or its first line
+    first) give the oracle's answers for the learned form and plain BS, on
+    uniform and duplicate-heavy keys; an unknown mode is refused."""
+    for kind in ("uniform64", "dup"):
+        n = 70001
+        keys, rows = make(kind, n, seed=rounds + 10)
+        sk, sr = oracle.stable_sort(keys, rows)
+        q = queries(keys, 30000, 17 + rounds)
+        want = oracle.point(sk, sr, q, nthreads=4)
+        with idx.Index(to_dev(keys), to_dev(rows), layout="bs", aos=aos) as ix:
+            ix.set_params(window_rounds=rounds, model=2)
+            assert np.array_equal(rows_host(ix.point(to_dev(q))), want)
+            ix.learn(n // 16, 2)
+            ix.set_params(window_rounds=rounds, model=0)
+            assert ix.params()["window_rounds"] == rounds
+            assert np.array_equal(rows_host(ix.point(to_dev(q))), want)
+            with pytest.raises(idx.IdxError):
+                ix.set_params(window_rounds=3)
