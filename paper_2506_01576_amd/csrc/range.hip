@@ -112,17 +112,60 @@ __global__ __launch_bounds__(256) void k_range_count(RangeArgs<K, AOS> a) {
     a.offsets[q] = r1 > r0 ? r1 - r0 : 0;
 }
 
-// BS: one 16-lane group per query copies the contiguous rowid run.
+// BS (and the learned form): each wave takes 64 consecutive queries, whose
+// row-ID runs are consecutive in the output, and copies their concatenation:
+// every element finds its run by a binary search over the runs' starts (per
+// wave, in LDS), so stores are coalesced and each lane has several loads in
+// flight.
 template <typename K, bool AOS>
 __global__ __launch_bounds__(256) void k_range_fill_bs(RangeArgs<K, AOS> a) {
-    constexpr int GL = 16;
-    const uint64_t q = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL;
-    const uint32_t sub = threadIdx.x & (GL - 1);
-    if (q >= a.m) return;
-    const uint64_t o = a.offsets[q];
-    const uint64_t cnt = a.offsets[q + 1] - o;
-    const uint64_t r0 = a.first_rank[q];
-    for (uint64_t e = sub; e < cnt; e += GL) a.out[o + e] = a.L.row(r0 + e);
+    constexpr int WPB = 256 / kWave;
+    __shared__ uint64_t s_start[WPB][kWave + 1];
+    __shared__ uint64_t s_src[WPB][kWave];  // first rank of the run minus its start
+    const uint32_t lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    const uint64_t q0 = ((uint64_t)blockIdx.x * WPB + w) * kWave;
+    if (q0 >= a.m) return;  // whole wave: q0 is wave-uniform
+    const uint64_t q = q0 + lane;
+    uint64_t len = 0, r0 = 0;
+    if (q < a.m) {
+        len = a.offsets[q + 1] - a.offsets[q];
+        r0 = a.first_rank[q];
+    }
+    uint64_t incl = len;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint64_t x = (uint64_t)__shfl_up((long long)incl, off, kWave);
+        if (lane >= (uint32_t)off) incl += x;
+    }
+    const uint64_t total = (uint64_t)__shfl((long long)incl, kWave - 1, kWave);
+    if (total == 0) return;
+    const uint64_t start = incl - len;
+    s_start[w][lane] = start;
+    if (lane == kWave - 1) s_start[w][kWave] = total;
+    s_src[w][lane] = r0 - start;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint32_t *out = a.out + a.offsets[q0];
+    constexpr int CU = 4;
+    for (uint64_t t0 = lane; t0 < total; t0 += (uint64_t)kWave * CU) {
+        uint32_t v[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const uint64_t t = t0 + (uint64_t)u * kWave;
+            if (t >= total) continue;
+            uint32_t lo = 0;
+#pragma unroll
+            for (uint32_t step = kWave / 2; step > 0; step >>= 1)
+                if (s_start[w][lo + step] <= t) lo += step;
+            v[u] = a.L.row(s_src[w][lo] + t);
+        }
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const uint64_t t = t0 + (uint64_t)u * kWave;
+            if (t < total) out[t] = v[u];
+        }
+    }
 }
 
 // EBS/EKS: level scan along the lower-bound path of lo, one lane per range,
@@ -318,8 +361,8 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
             break;
         }
         if (h->layout == IDX_BS) {
-            const uint64_t threads = m * 16;
-            hipLaunchKernelGGL((k_range_fill_bs<K, AOS>), dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, s, a);
+            const uint64_t waves = (m + kWave - 1) / kWave;
+            hipLaunchKernelGGL((k_range_fill_bs<K, AOS>), dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, a);
         } else {
             hipLaunchKernelGGL((k_range_fill_eyt<K, AOS>), dim3(blocks), dim3(256), 0, s, a);
         }
