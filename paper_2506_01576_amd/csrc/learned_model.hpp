@@ -315,8 +315,9 @@ __device__ __forceinline__ void wave_leaf_reduce(uint64_t b, uint64_t e, T ident
 
 // Leaves of at most kLeafCap keys are walked by one thread each in the
 // per-leaf passes (their key ranges are known after the layout); larger
-// leaves go through the wave walk.
-constexpr uint32_t kLeafCap = 512;
+// leaves go through the wave walk.  The cap keeps the edge leaves of a linear
+// root (where the fitted line leaves the key range) on the cheap path.
+constexpr uint32_t kLeafCap = 4096;
 
 // A key's terms of the leaf line fit: count, d, d^2, r, r d, r^2, with d the
 // leaf-local key offset and r the residual of the leaf's prediction at rank i.
@@ -337,15 +338,27 @@ __device__ __forceinline__ long long leaf_err(const LeafRec &L, uint64_t i, uint
     return (long long)(i - L.base) - (long long)pred_local(L, key);
 }
 
+// Keys a leaf-walking thread loads before using any of them, so that its
+// loads are in flight together.
+constexpr int kLeafBatch = 8;
+
 // The sums of one leaf, walked by one thread (key(i) reads rank i).
 template <typename KeyAt>
 __device__ __forceinline__ void leaf_sums_thread(const KeyAt &key, const LeafRec &L, double *a) {
     for (int j = 0; j < NACC; ++j) a[j] = 0.0;
-    for (uint64_t i = L.base; i < (uint64_t)L.base + L.size; ++i) {
-        double t[NACC];
-        leaf_terms(L, i, key(i), t);
+    const uint64_t end = (uint64_t)L.base + L.size;
+    for (uint64_t i0 = L.base; i0 < end; i0 += kLeafBatch) {
+        uint64_t kb[kLeafBatch];
 #pragma unroll
-        for (int j = 0; j < NACC; ++j) a[j] += t[j];
+        for (int u = 0; u < kLeafBatch; ++u) kb[u] = i0 + u < end ? key(i0 + u) : 0ull;
+#pragma unroll
+        for (int u = 0; u < kLeafBatch; ++u) {
+            if (i0 + u >= end) continue;
+            double t[NACC];
+            leaf_terms(L, i0 + u, kb[u], t);
+#pragma unroll
+            for (int j = 0; j < NACC; ++j) a[j] += t[j];
+        }
     }
 }
 
@@ -354,10 +367,18 @@ template <typename KeyAt>
 __device__ __forceinline__ void leaf_errs_thread(const KeyAt &key, const LeafRec &L, long long &lo, long long &hi) {
     lo = INT_MAX;
     hi = INT_MIN;
-    for (uint64_t i = L.base; i < (uint64_t)L.base + L.size; ++i) {
-        const long long e = leaf_err(L, i, key(i));
-        lo = e < lo ? e : lo;
-        hi = e > hi ? e : hi;
+    const uint64_t end = (uint64_t)L.base + L.size;
+    for (uint64_t i0 = L.base; i0 < end; i0 += kLeafBatch) {
+        uint64_t kb[kLeafBatch];
+#pragma unroll
+        for (int u = 0; u < kLeafBatch; ++u) kb[u] = i0 + u < end ? key(i0 + u) : 0ull;
+#pragma unroll
+        for (int u = 0; u < kLeafBatch; ++u) {
+            if (i0 + u >= end) continue;
+            const long long e = leaf_err(L, i0 + u, kb[u]);
+            lo = e < lo ? e : lo;
+            hi = e > hi ? e : hi;
+        }
     }
 }
 
