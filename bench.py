@@ -254,6 +254,9 @@ def run_skewed(args, idx, gen, np, torch, dev, log):
     if laos:  # the tuned leaf count on the plain sorted array too, at 8 and 4 lookups per lane
         cands.append(("learned_tuned_soa", lp.get("leaves", 1 << 22), False, {"per_lane": lp.get("per_lane", 8)}))
         cands.append(("learned_tuned_soa_r4", lp.get("leaves", 1 << 22), False, {"per_lane": 4}))
+        # skewed batches keep many windows cached: the scan in one round as well
+        cands.append(("learned_tuned_soa_r4_1round", lp.get("leaves", 1 << 22), False,
+                      {"per_lane": 4, "window_rounds": 1}))
     for name, L, aos, params in cands:
         arr = base if not aos else base.relayout("bs", 1, aos)
         a = torch.cuda.Event(enable_timing=True)
