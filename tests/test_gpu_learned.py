@@ -339,8 +339,9 @@ def test_window_rounds_parity(aos, rounds):
             ix.set_params(window_rounds=rounds, model=2)
             assert np.array_equal(rows_host(ix.point(to_dev(q))), want)
             ix.learn(n // 16, 2)
-            ix.set_params(window_rounds=rounds, model=0)
-            assert ix.params()["window_rounds"] == rounds
-            assert np.array_equal(rows_host(ix.point(to_dev(q))), want)
+            for per_lane in (4, 8):
+                ix.set_params(window_rounds=rounds, model=0, per_lane=per_lane)
+                assert ix.params()["window_rounds"] == rounds
+                assert np.array_equal(rows_host(ix.point(to_dev(q))), want)
             with pytest.raises(idx.IdxError):
                 ix.set_params(window_rounds=3)
