@@ -261,6 +261,78 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_count(const Desc *__restrict
         const uint64_t c1 = c0 + CH < m ? c0 + CH : m;
         const uint32_t i0 = owner(off, 0, count, c0);
         const uint32_t i1 = owner(off, i0, count, c1 - 1);
+        if constexpr (!EYT) {
+            // A chunk of one learned index (the usual case): every model
+            // lookup of the lane's queries -- one per point, two per range --
+            // runs in lockstep, so their leaf records, narrowing probes and
+            // window reads are in flight together.
+            if (i0 == i1 && descs[i0].form == F_LEARNED) {
+                const Desc d = descs[i0];
+                const K *keys = (const K *)d.keys;
+                constexpr int NL = 2 * BR;
+                K xs[NL];
+                bool act[NL], eq[NL];
+                uint32_t b[NL], len[NL];  // ranks: n < 2^32
+                bool live[BR], rng[BR];
+#pragma unroll
+                for (int r = 0; r < BR; ++r) {
+                    const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+                    live[r] = p < c1;
+                    rng[r] = live[r] && kind[p] == Q_RANGE;
+                    const K L = live[r] ? lo[p] : K(0), U = rng[r] ? hi[p] : K(0);
+                    xs[2 * r] = L;
+                    act[2 * r] = live[r] && (!rng[r] || L <= U);
+                    xs[2 * r + 1] = (K)(U + 1);
+                    act[2 * r + 1] = rng[r] && L <= U && U != ~K(0);
+                }
+#pragma unroll
+                for (int j = 0; j < NL; ++j) {
+                    b[j] = 0;
+                    len[j] = 0;
+                    if (act[j]) {
+                        uint64_t wb, wl;
+                        learned_window(d.root, d.leaves, (uint64_t)xs[j], wb, wl);
+                        b[j] = (uint32_t)wb;
+                        len[j] = (uint32_t)wl;
+                    }
+                }
+                for (;;) {
+                    bool more = false;
+#pragma unroll
+                    for (int j = 0; j < NL; ++j) {
+                        if (len[j] > 15) {
+                            const uint32_t half = len[j] >> 1;
+                            b[j] = keys[(uint64_t)b[j] + half - 1] < xs[j] ? b[j] + half : b[j];
+                            len[j] -= half;
+                        }
+                        more |= len[j] > 15;
+                    }
+                    if (!more) break;
+                }
+#pragma unroll
+                for (int j = 0; j < NL; ++j) {
+                    eq[j] = false;
+                    if (act[j]) b[j] += count_below<K, 16>(keys, b[j], len[j], xs[j], eq[j]);
+                }
+#pragma unroll
+                for (int r = 0; r < BR; ++r) {
+                    if (!live[r]) continue;
+                    const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+                    if (!rng[r]) {
+                        out[p] = eq[2 * r] ? d.rows[b[2 * r]] : kMiss;
+                        first[p] = 0;
+                        offs[p] = 0;
+                        continue;
+                    }
+                    out[p] = kMiss;
+                    const uint64_t r0 = act[2 * r] ? b[2 * r] : 0;
+                    const uint64_t r1 = !act[2 * r] ? 0 : act[2 * r + 1] ? b[2 * r + 1] : d.n;
+                    first[p] = (uint32_t)r0;
+                    offs[p] = r1 > r0 ? r1 - r0 : 0;
+                }
+                continue;
+            }
+        }
 #pragma unroll
         for (int r = 0; r < BR; ++r) {
             const uint64_t p = c0 + (uint64_t)r * kWave + lane;
