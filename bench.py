@@ -917,7 +917,7 @@ def main():
         del buf
     except Exception as e:  # pragma: no cover - measurement only
         probe["error"] = str(e)
-    # the random-access roofline of the survey's measurement plan: the probe's
+    # the random-access roofline (the paper's Fig. 9 probe design): the probe's
     # rate of independent random requests that miss the caches, A_rand,
     # divided by the lookup's algorithmic granules beyond on-chip capacity, D
     if "group1" in probe:
