@@ -24,6 +24,18 @@ constexpr int RS_WAVES = RS_THREADS / kWave;
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;  // 4096 keys
 constexpr int RS_SCAN_ITEMS = 16;
+constexpr uint32_t RS_XCDS = 8;  // workgroups are dealt round-robin over the 8 XCDs
+
+// The tile that workgroup b scatters: XCD x (b % 8) takes a contiguous share
+// of the tiles, in order.  A digit's runs from consecutive tiles are adjacent
+// in the output, so the partial 128 B lines at their ends are completed in
+// one XCD's L2 instead of being written back in pieces from several.
+// A bijection of [0, tiles): XCD x holds tiles/8 + (x < tiles%8) workgroups.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t tiles) {
+    const uint32_t per = tiles / RS_XCDS, rem = tiles % RS_XCDS;
+    const uint32_t x = b % RS_XCDS, i = b / RS_XCDS;
+    return x * per + (x < rem ? x : rem) + i;
+}
 
 static_assert(RS_THREADS == RS_BINS, "one thread per digit value in the scan phases");
 
@@ -142,7 +154,8 @@ __global__ __launch_bounds__(RS_THREADS) void k_scatter(const K *__restrict__ ke
     // Items of a wave are consecutive keys: item j of lane l is key
     // base + j*64 + l, so taking items j = 0, 1, ... with lanes in order
     // visits the wave's keys in index order (stability).
-    const uint64_t tile_base = (uint64_t)blockIdx.x * RS_TILE;
+    const uint32_t tile = xcd_tile(blockIdx.x, tiles);
+    const uint64_t tile_base = (uint64_t)tile * RS_TILE;
     const uint64_t wave_base = tile_base + (uint64_t)wave * (RS_ITEMS * kWave);
     K key[RS_ITEMS];
     uint32_t row[RS_ITEMS];
@@ -193,7 +206,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_scatter(const K *__restrict__ ke
         sm.digit_start[d] = start;
         uint32_t dig_total_all;
         const uint32_t dbase = block_exclusive_scan(digit_total[d], sm.scan_tmp, &dig_total_all);
-        sm.global_base[d] = dbase + tile_hist[(uint64_t)d * tiles + blockIdx.x];
+        sm.global_base[d] = dbase + tile_hist[(uint64_t)d * tiles + tile];
     }
     __syncthreads();
 
