@@ -193,11 +193,7 @@ __host__ __device__ inline uint64_t slot_rank(const Geo &G, uint64_t t) {
     }
     uint32_t l = 0;
     if (G.k == 2) {
-#ifdef __HIP_DEVICE_COMPILE__
-        l = 63u - (uint32_t)__clzll((long long)(t + 1));
-#else
         l = 63u - (uint32_t)__builtin_clzll(t + 1);
-#endif
     } else {
         while (G.start[l + 1] <= t) ++l;
     }
@@ -206,6 +202,26 @@ __host__ __device__ inline uint64_t slot_rank(const Geo &G, uint64_t t) {
     const uint64_t p = (G.start[G.m - l - 1] + 1) * (1 + i + div_g(G, i)) - 1;
     const uint64_t skip = G.g * (p + 1);
     return p + (skip < G.b ? skip : G.b);
+}
+
+// Level-order slot of sorted rank r < n, the inverse of slot_rank, for the
+// binary layout (k = 2).  The first 2b ranks alternate: even ranks are the b
+// bottom-level entries (slot start[m] + r/2), odd ranks upper-level keys of
+// perfect-tree rank p = (r - 1)/2; later ranks are upper-level keys with
+// p = r - b.  In the perfect tree of m levels, p + 1 = 2^e * u with u odd
+// puts the key on level m - 1 - e at position (u - 1)/2.
+__host__ __device__ inline uint64_t rank_slot_binary(const Geo &G, uint64_t r) {
+    uint64_t p;
+    if (r < 2 * G.b) {
+        if ((r & 1) == 0) return G.start[G.m] + (r >> 1);
+        p = r >> 1;
+    } else {
+        p = r - G.b;
+    }
+    const uint64_t v = p + 1;
+    const uint32_t e = (uint32_t)__builtin_ctzll(v);
+    const uint32_t l = G.m - 1 - e;
+    return G.start[l] + ((v >> e) >> 1);
 }
 
 }  // namespace idx

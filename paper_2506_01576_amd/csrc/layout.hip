@@ -45,6 +45,27 @@ __global__ __launch_bounds__(256) void k_permute(const K *__restrict__ sk, const
     dst.put(t + off, sk[r], sr[r]);
 }
 
+// The binary layout read in rank order: thread r loads sorted entry r (the
+// read is consecutive per wave, each line of the sorted arrays fetched once)
+// and stores it at slot rank_slot_binary(r) + off.  A wave's 64 ranks land
+// on runs of consecutive slots, one per level (32, 16, 8, ... slots); the
+// workgroups of one XCD take a contiguous share of the ranks, so the short
+// runs of the upper levels from neighbouring waves complete their lines in
+// one L2.  The slot-order gather above fetches every line of the sorted
+// arrays once per level on the lowest levels, whose stride is below a line.
+constexpr uint32_t kPermXcds = 8;  // workgroups are dealt round-robin over the 8 XCDs
+
+template <typename K, bool AOS>
+__global__ __launch_bounds__(256) void k_permute_rank2(const K *__restrict__ sk, const uint32_t *__restrict__ sr,
+                                                       Geo G, uint32_t off, Store<K, AOS> dst) {
+    const uint32_t per = gridDim.x / kPermXcds, rem = gridDim.x % kPermXcds;
+    const uint32_t x = blockIdx.x % kPermXcds, i = blockIdx.x / kPermXcds;
+    const uint32_t blk = x * per + (x < rem ? x : rem) + i;  // a bijection of [0, gridDim.x)
+    const uint64_t r = (uint64_t)blk * blockDim.x + threadIdx.x;
+    if (r >= G.n) return;
+    dst.put(rank_slot_binary(G, r) + off, sk[r], sr[r]);
+}
+
 template <typename K, bool AOS>
 __global__ void k_empty_slot0(Store<K, AOS> dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) dst.put(0, K(0), kMiss);
@@ -118,6 +139,8 @@ int build_layout_t(idx_index *h, const K *sk, const uint32_t *sr, hipStream_t s)
     const uint32_t blocks = (uint32_t)((n + 255) / 256);
     if (h->layout == IDX_BS) {
         hipLaunchKernelGGL((k_permute<K, AOS, false>), dim3(blocks), dim3(256), 0, s, sk, sr, h->geo, 0u, dst);
+    } else if (h->geo.k == 2) {
+        hipLaunchKernelGGL((k_permute_rank2<K, AOS>), dim3(blocks), dim3(256), 0, s, sk, sr, h->geo, off, dst);
     } else {
         hipLaunchKernelGGL((k_permute<K, AOS, true>), dim3(blocks), dim3(256), 0, s, sk, sr, h->geo, off, dst);
     }
