@@ -86,17 +86,28 @@ __global__ __launch_bounds__(RS_THREADS) void k_tile_hist(const K *__restrict__ 
     const uint32_t wave = threadIdx.x / kWave;
     for (int w = 0; w < RS_WAVES; ++w) h[w][threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * RS_TILE;
-#pragma unroll 4
+    // XCD-contiguous tiles, as in the scatter: the per-digit counts of
+    // neighbouring tiles share lines of tile_hist.
+    const uint32_t tile = xcd_tile(blockIdx.x, tiles);
+    const uint64_t base = (uint64_t)tile * RS_TILE;
+    // all of a thread's keys are loaded before the first LDS atomic, so the
+    // 16 loads are in flight together
+    K kk[RS_ITEMS];
+#pragma unroll
     for (int j = 0; j < RS_ITEMS; ++j) {
         const uint64_t i = base + (uint64_t)j * RS_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&h[wave][(keys[i] >> shift) & (RS_BINS - 1)], 1u);
+        kk[j] = i < n ? keys[i] : K(0);
+    }
+#pragma unroll
+    for (int j = 0; j < RS_ITEMS; ++j) {
+        const uint64_t i = base + (uint64_t)j * RS_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&h[wave][(kk[j] >> shift) & (RS_BINS - 1)], 1u);
     }
     __syncthreads();
     uint32_t c = 0;
 #pragma unroll
     for (int w = 0; w < RS_WAVES; ++w) c += h[w][threadIdx.x];
-    tile_hist[(uint64_t)threadIdx.x * tiles + blockIdx.x] = c;
+    tile_hist[(uint64_t)threadIdx.x * tiles + tile] = c;
 }
 
 // One workgroup per digit: exclusive scan of that digit's per-tile counts
