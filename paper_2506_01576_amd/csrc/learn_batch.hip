@@ -209,13 +209,9 @@ __global__ __launch_bounds__(BT) void k_bt_leaf_count(const Unit *__restrict__ u
     const K *keys = (const K *)D.keys;
     const RootRec R = best[u.index];
     uint32_t *c = cnt + D.leaf_off;
-    wave_leaf_sums<1>(
-        b, e, [&](uint64_t i, uint32_t &l, double *a) {
-            l = leaf_of(R, (uint64_t)keys[i]);
-            a[0] = 1.0;
-            return true;
-        },
-        [&](uint32_t l, const double *v) { atomicAdd(&c[l], (uint32_t)v[0]); });
+    wave_leaf_counts(
+        b, e, [&](uint64_t i) { return leaf_of(R, (uint64_t)keys[i]); },
+        [&](uint32_t l, uint32_t n) { atomicAdd(&c[l], n); });
 }
 
 // One workgroup per index: leaf bases (exclusive scan of the counts), sizes,

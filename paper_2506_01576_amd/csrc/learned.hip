@@ -97,21 +97,17 @@ __global__ void k_fill_f64(double *p, uint64_t count) {
         p[i] = 0.0;
 }
 
-// Keys per leaf.  Keys are sorted and leaf_of is non-decreasing, so a thread's
-// chunk holds few runs; each run adds its length once.
+// Keys per leaf: each wave counts the leaf runs of its 64 * CHUNK
+// consecutive keys, one atomic per run and step.
 template <typename K, bool AOS>
 __global__ __launch_bounds__(LT) void k_leaf_count(Load<K, AOS> keys, uint64_t n, const RootRec *Rp,
                                                    unsigned long long *__restrict__ count) {
     const RootRec R = *Rp;
     const uint64_t b = ((uint64_t)blockIdx.x * LT + (threadIdx.x & ~(uint32_t)(kWave - 1))) * CHUNK;
     const uint64_t e = b + (uint64_t)kWave * CHUNK < n ? b + (uint64_t)kWave * CHUNK : n;
-    wave_leaf_sums<1>(
-        b, e, [&](uint64_t i, uint32_t &l, double *a) {
-            l = leaf_of(R, (uint64_t)keys.key(i));
-            a[0] = 1.0;
-            return true;
-        },
-        [&](uint32_t l, const double *v) { atomicAdd(&count[l], (unsigned long long)v[0]); });
+    wave_leaf_counts(
+        b, e, [&](uint64_t i) { return leaf_of(R, (uint64_t)keys.key(i)); },
+        [&](uint32_t l, uint32_t c) { atomicAdd(&count[l], (unsigned long long)c); });
 }
 
 // Leaf records from the exclusive scan of the per-leaf counts (base[l] =

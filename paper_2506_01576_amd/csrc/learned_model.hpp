@@ -382,6 +382,38 @@ __device__ __forceinline__ void leaf_errs_thread(const KeyAt &key, const LeafRec
     }
 }
 
+// Keys per leaf over the wave's keys [b, e), 64 consecutive keys per step:
+// a step's leaves form runs of equal values, and the last lane of each run
+// calls add(leaf, run length), the start of the run coming from the ballot of
+// run ends.  The runs partition the step's keys, so every key is counted
+// once; with ascending keys and a monotone leaf map a leaf appears in at
+// most one run per step.  Integer work only (no cross-lane FP64).
+template <typename LeafAt, typename Add>
+__device__ __forceinline__ void wave_leaf_counts(uint64_t b, uint64_t e, LeafAt &&leaf_at, Add &&add) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    constexpr int U = 4;  // steps whose keys are loaded before any atomic
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    for (uint64_t s0 = b; s0 < e; s0 += (uint64_t)U * kWave) {
+        uint32_t l[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = s0 + (uint64_t)u * kWave + lane;
+            l[u] = i < e ? leaf_at(i) : kNone;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t next = __shfl_down(l[u], 1);
+            const bool last = l[u] != kNone && (lane == kWave - 1 || next != l[u]);
+            const uint64_t ends = __ballot(last);
+            if (last) {
+                const uint64_t before = ends & ((1ull << lane) - 1ull);
+                const uint32_t start = before ? 64u - (uint32_t)__builtin_clzll(before) : 0u;
+                add(l[u], lane + 1u - start);
+            }
+        }
+    }
+}
+
 template <int NV, typename Step, typename Add>
 __device__ __forceinline__ void wave_leaf_sums(uint64_t b, uint64_t e, Step &&step, Add &&add) {
     wave_leaf_reduce<NV, double>(b, e, 0.0, [](double x, double y) { return x + y; }, step, add);
