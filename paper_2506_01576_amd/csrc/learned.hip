@@ -129,17 +129,56 @@ __global__ void k_leaf_init(Load<K, AOS> keys, const unsigned long long *__restr
     leaves[l] = r;
 }
 
+// The 256 leaves of a workgroup cover one contiguous rank range (bases are
+// the exclusive scan of the sizes).  When it holds at most kStageKeys keys
+// the workgroup loads it into LDS with consecutive reads, and each thread
+// walks its leaf there; a thread walking its leaf in global memory issues
+// loads that touch 64 different lines per wave.
+constexpr uint32_t kStageKeys = 8192;
+constexpr uint32_t kLeafBlock = 256;  // leaves (threads) per workgroup of the per-leaf passes
+
+template <typename K, bool AOS>
+__device__ __forceinline__ bool stage_leaf_keys(Load<K, AOS> keys, const LeafRec *__restrict__ leaves, uint32_t L,
+                                                K *s_key, uint64_t &kb) {
+    const uint32_t l0 = blockIdx.x * kLeafBlock;
+    if (l0 >= L) return false;  // workgroup-uniform (a launch over no leaves)
+    const uint32_t l1 = l0 + kLeafBlock < L ? l0 + kLeafBlock : L;
+    kb = leaves[l0].base;
+    const uint64_t ke = (uint64_t)leaves[l1 - 1].base + leaves[l1 - 1].size;
+    if (ke - kb > kStageKeys) return false;  // workgroup-uniform
+    constexpr int U = 8;
+    for (uint64_t i0 = kb; i0 < ke; i0 += (uint64_t)U * kLeafBlock) {
+        K v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kLeafBlock + threadIdx.x;
+            v[u] = i < ke ? keys.key(i) : K(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kLeafBlock + threadIdx.x;
+            if (i < ke) s_key[i - kb] = v[u];
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
 // Per-leaf sums, one thread per leaf over its key range; a leaf of more than
 // kLeafCap keys gets zero sums here and raises *big for k_leaf_accum_big.
 template <typename K, bool AOS>
-__global__ __launch_bounds__(256) void k_leaf_accum_small(Load<K, AOS> keys, const LeafRec *__restrict__ leaves,
-                                                          uint32_t L, double *__restrict__ acc, uint32_t *big) {
-    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kLeafBlock) void k_leaf_accum_small(Load<K, AOS> keys, const LeafRec *__restrict__ leaves,
+                                                                 uint32_t L, double *__restrict__ acc, uint32_t *big) {
+    __shared__ K s_key[kStageKeys];
+    uint64_t kb;
+    const bool staged = stage_leaf_keys(keys, leaves, L, s_key, kb);
+    const uint32_t l = blockIdx.x * kLeafBlock + threadIdx.x;
     if (l >= L) return;
     const LeafRec r = leaves[l];
     double a[NACC] = {0, 0, 0, 0, 0, 0};
-    if (r.size <= kLeafCap) leaf_sums_thread([&](uint64_t i) { return (uint64_t)keys.key(i); }, r, a);
-    else *big = 1u;
+    if (r.size > kLeafCap) *big = 1u;
+    else if (staged) leaf_sums_thread([&](uint64_t i) { return (uint64_t)s_key[i - kb]; }, r, a);
+    else leaf_sums_thread([&](uint64_t i) { return (uint64_t)keys.key(i); }, r, a);
 #pragma unroll
     for (int j = 0; j < NACC; ++j) acc[(uint64_t)l * NACC + j] = a[j];
 }
@@ -182,14 +221,18 @@ __global__ void k_leaf_update(LeafRec *__restrict__ leaves, const double *__rest
 
 // Per-leaf error bounds, one thread per leaf of at most kLeafCap keys.
 template <typename K, bool AOS>
-__global__ __launch_bounds__(256) void k_leaf_errors_small(Load<K, AOS> keys, LeafRec *__restrict__ leaves,
-                                                           uint32_t L) {
-    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kLeafBlock) void k_leaf_errors_small(Load<K, AOS> keys, LeafRec *__restrict__ leaves,
+                                                                  uint32_t L) {
+    __shared__ K s_key[kStageKeys];
+    uint64_t kb;
+    const bool staged = stage_leaf_keys(keys, leaves, L, s_key, kb);
+    const uint32_t l = blockIdx.x * kLeafBlock + threadIdx.x;
     if (l >= L) return;
     const LeafRec r = leaves[l];
     if (r.size == 0 || r.size > kLeafCap) return;
     long long lo, hi;
-    leaf_errs_thread([&](uint64_t i) { return (uint64_t)keys.key(i); }, r, lo, hi);
+    if (staged) leaf_errs_thread([&](uint64_t i) { return (uint64_t)s_key[i - kb]; }, r, lo, hi);
+    else leaf_errs_thread([&](uint64_t i) { return (uint64_t)keys.key(i); }, r, lo, hi);
     leaves[l].elo = (int32_t)lo;
     leaves[l].ehi = (int32_t)hi;
 }
