@@ -270,20 +270,44 @@ __device__ __forceinline__ uint32_t leaf_owner(const TDesc *__restrict__ d, uint
     return lo;
 }
 
+// The workgroup's leaves' keys into LDS, when all its leaves belong to one
+// index and their range holds at most kStageKeys keys (else false).
+template <typename K>
+__device__ __forceinline__ bool bt_stage_leaf_keys(const TDesc *__restrict__ d, uint32_t count, uint64_t total,
+                                                   K *s_key, uint64_t &kb) {
+    const uint64_t g0 = (uint64_t)blockIdx.x * kLeafBlock;
+    if (g0 >= total) return false;  // workgroup-uniform, as every test below
+    const uint64_t g1 = g0 + kLeafBlock < total ? g0 + kLeafBlock : total;
+    const uint32_t o = leaf_owner(d, count, g0);
+    if (leaf_owner(d, count, g1 - 1) != o) return false;
+    const TDesc D = d[o];
+    kb = D.leaves[g0 - D.leaf_off].base;
+    const LeafRec last = D.leaves[g1 - 1 - D.leaf_off];
+    const uint64_t ke = (uint64_t)last.base + last.size;
+    if (ke - kb > kStageKeys) return false;
+    const K *keys = (const K *)D.keys;
+    stage_keys<K>([&](uint64_t i) { return keys[i]; }, kb, ke, s_key);
+    return true;
+}
+
 // Per-leaf sums, one thread per leaf (global leaf g) over its key range; a
 // leaf of more than kLeafCap keys gets zero sums and raises *big.
 template <typename K>
-__global__ __launch_bounds__(256) void k_bt_leaf_accum_small(const TDesc *__restrict__ d, uint32_t count,
-                                                             uint64_t total, double *__restrict__ acc,
-                                                             uint32_t *big) {
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kLeafBlock) void k_bt_leaf_accum_small(const TDesc *__restrict__ d, uint32_t count,
+                                                                    uint64_t total, double *__restrict__ acc,
+                                                                    uint32_t *big) {
+    __shared__ K s_key[kStageKeys];
+    uint64_t kb;
+    const bool staged = bt_stage_leaf_keys(d, count, total, s_key, kb);
+    const uint64_t g = (uint64_t)blockIdx.x * kLeafBlock + threadIdx.x;
     if (g >= total) return;
     const TDesc D = d[leaf_owner(d, count, g)];
     const K *keys = (const K *)D.keys;
     const LeafRec r = D.leaves[g - D.leaf_off];
     double a[NACC] = {0, 0, 0, 0, 0, 0};
-    if (r.size <= kLeafCap) leaf_sums_thread([&](uint64_t i) { return (uint64_t)keys[i]; }, r, a);
-    else *big = 1u;
+    if (r.size > kLeafCap) *big = 1u;
+    else if (staged) leaf_sums_thread([&](uint64_t i) { return (uint64_t)s_key[i - kb]; }, r, a);
+    else leaf_sums_thread([&](uint64_t i) { return (uint64_t)keys[i]; }, r, a);
 #pragma unroll
     for (int j = 0; j < NACC; ++j) acc[g * NACC + j] = a[j];
 }
@@ -332,9 +356,12 @@ __global__ void k_bt_leaf_update(const TDesc *__restrict__ d, uint32_t count, ui
 
 // Per-leaf error bounds, one thread per leaf of at most kLeafCap keys.
 template <typename K>
-__global__ __launch_bounds__(256) void k_bt_leaf_errors_small(const TDesc *__restrict__ d, uint32_t count,
-                                                              uint64_t total) {
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kLeafBlock) void k_bt_leaf_errors_small(const TDesc *__restrict__ d, uint32_t count,
+                                                                     uint64_t total) {
+    __shared__ K s_key[kStageKeys];
+    uint64_t kb;
+    const bool staged = bt_stage_leaf_keys(d, count, total, s_key, kb);
+    const uint64_t g = (uint64_t)blockIdx.x * kLeafBlock + threadIdx.x;
     if (g >= total) return;
     const TDesc D = d[leaf_owner(d, count, g)];
     const K *keys = (const K *)D.keys;
@@ -342,7 +369,8 @@ __global__ __launch_bounds__(256) void k_bt_leaf_errors_small(const TDesc *__res
     const LeafRec r = *p;
     if (r.size == 0 || r.size > kLeafCap) return;
     long long lo, hi;
-    leaf_errs_thread([&](uint64_t i) { return (uint64_t)keys[i]; }, r, lo, hi);
+    if (staged) leaf_errs_thread([&](uint64_t i) { return (uint64_t)s_key[i - kb]; }, r, lo, hi);
+    else leaf_errs_thread([&](uint64_t i) { return (uint64_t)keys[i]; }, r, lo, hi);
     p->elo = (int32_t)lo;
     p->ehi = (int32_t)hi;
 }
@@ -545,14 +573,14 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
         hipLaunchKernelGGL((k_bt_leaf_layout<K>), dim3(count), dim3(1024), 0, s, dd, d_cnt);
         hipLaunchKernelGGL(k_bt_zero_u32, dim3(1), dim3(64), 0, s, d_big, (uint64_t)1);
         for (uint32_t ep = 0; ep <= epochs; ++ep) {
-            hipLaunchKernelGGL((k_bt_leaf_accum_small<K>), dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd,
+            hipLaunchKernelGGL((k_bt_leaf_accum_small<K>), dim3(blocks_for(total_leaves, kLeafBlock)), dim3(kLeafBlock), 0, s, dd,
                                count, total_leaves, d_lacc, d_big);
             hipLaunchKernelGGL((k_bt_leaf_accum_big<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br, d_lacc, d_big);
             if (ep < epochs)
                 hipLaunchKernelGGL(k_bt_leaf_update, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd, count,
                                    total_leaves, d_lacc);
         }
-        hipLaunchKernelGGL((k_bt_leaf_errors_small<K>), dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd, count,
+        hipLaunchKernelGGL((k_bt_leaf_errors_small<K>), dim3(blocks_for(total_leaves, kLeafBlock)), dim3(kLeafBlock), 0, s, dd, count,
                            total_leaves);
         hipLaunchKernelGGL((k_bt_leaf_errors_big<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br, d_big);
         hipLaunchKernelGGL(k_bt_leaf_finish, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd, count,

@@ -129,14 +129,7 @@ __global__ void k_leaf_init(Load<K, AOS> keys, const unsigned long long *__restr
     leaves[l] = r;
 }
 
-// The 256 leaves of a workgroup cover one contiguous rank range (bases are
-// the exclusive scan of the sizes).  When it holds at most kStageKeys keys
-// the workgroup loads it into LDS with consecutive reads, and each thread
-// walks its leaf there; a thread walking its leaf in global memory issues
-// loads that touch 64 different lines per wave.
-constexpr uint32_t kStageKeys = 8192;
-constexpr uint32_t kLeafBlock = 256;  // leaves (threads) per workgroup of the per-leaf passes
-
+// The workgroup's leaves' keys into LDS (false: the range is too large).
 template <typename K, bool AOS>
 __device__ __forceinline__ bool stage_leaf_keys(Load<K, AOS> keys, const LeafRec *__restrict__ leaves, uint32_t L,
                                                 K *s_key, uint64_t &kb) {
@@ -146,21 +139,7 @@ __device__ __forceinline__ bool stage_leaf_keys(Load<K, AOS> keys, const LeafRec
     kb = leaves[l0].base;
     const uint64_t ke = (uint64_t)leaves[l1 - 1].base + leaves[l1 - 1].size;
     if (ke - kb > kStageKeys) return false;  // workgroup-uniform
-    constexpr int U = 8;
-    for (uint64_t i0 = kb; i0 < ke; i0 += (uint64_t)U * kLeafBlock) {
-        K v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t i = i0 + (uint64_t)u * kLeafBlock + threadIdx.x;
-            v[u] = i < ke ? keys.key(i) : K(0);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint64_t i = i0 + (uint64_t)u * kLeafBlock + threadIdx.x;
-            if (i < ke) s_key[i - kb] = v[u];
-        }
-    }
-    __syncthreads();
+    stage_keys<K>([&](uint64_t i) { return keys.key(i); }, kb, ke, s_key);
     return true;
 }
 
@@ -419,7 +398,7 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
         if (rc != IDX_OK) return rc;
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, d_big, (uint64_t)1, 0u);
         for (uint32_t ep = 0; ep <= epochs; ++ep) {
-            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS>), dim3(grid_for(L, 256)), dim3(256), 0, s, keys, leaves, L,
+            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s, keys, leaves, L,
                                leaf_acc, d_big);
             hipLaunchKernelGGL((k_leaf_accum_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
                                leaf_acc, d_big);
@@ -428,7 +407,7 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
         }
         hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, stats, (uint64_t)4);
         hipLaunchKernelGGL(k_sum_leaf_loss, dim3(64), dim3(256), 0, s, leaf_acc, L, stats + 2);
-        hipLaunchKernelGGL((k_leaf_errors_small<K, AOS>), dim3(grid_for(L, 256)), dim3(256), 0, s, keys, leaves, L);
+        hipLaunchKernelGGL((k_leaf_errors_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s, keys, leaves, L);
         hipLaunchKernelGGL((k_leaf_errors_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves, d_big);
         hipLaunchKernelGGL(k_leaf_finish, dim3(grid_for(L, 256) < 1024 ? grid_for(L, 256) : 1024), dim3(256), 0, s,
                            leaves, L, stats);
@@ -863,7 +842,7 @@ int eval_t(idx_index *h, uint32_t mode, const float *root_ab, uint32_t L, const 
             uint32_t *d_big = (uint32_t *)(tmp + 256 + 128);
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, d_big, (uint64_t)1, 0u);
             hipLaunchKernelGGL(k_set_leaf_params, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_ab, L);
-            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS>), dim3(grid_for(L, 256)), dim3(256), 0, s, keys, leaves, L,
+            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s, keys, leaves, L,
                                leaf_acc_d, d_big);
             hipLaunchKernelGGL((k_leaf_accum_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
                                leaf_acc_d, d_big);

@@ -342,6 +342,35 @@ __device__ __forceinline__ long long leaf_err(const LeafRec &L, uint64_t i, uint
 // loads are in flight together.
 constexpr int kLeafBatch = 8;
 
+// Per-leaf passes run one thread per leaf, kLeafBlock leaves per workgroup;
+// those leaves cover one contiguous rank range (the bases are the exclusive
+// scan of the sizes).  When it holds at most kStageKeys keys the workgroup
+// copies it into LDS with consecutive loads and each thread walks its leaf
+// there: a thread walking its leaf in global memory issues loads that touch
+// 64 different lines per wave.
+constexpr uint32_t kLeafBlock = 256;
+constexpr uint32_t kStageKeys = 8192;
+
+// Copies keys [kb, ke) (ke - kb <= kStageKeys) into s_key, then a barrier.
+template <typename K, typename KeyAt>
+__device__ __forceinline__ void stage_keys(const KeyAt &key, uint64_t kb, uint64_t ke, K *s_key) {
+    constexpr int U = 8;
+    for (uint64_t i0 = kb; i0 < ke; i0 += (uint64_t)U * kLeafBlock) {
+        K v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kLeafBlock + threadIdx.x;
+            v[u] = i < ke ? key(i) : K(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kLeafBlock + threadIdx.x;
+            if (i < ke) s_key[i - kb] = v[u];
+        }
+    }
+    __syncthreads();
+}
+
 // The sums of one leaf, walked by one thread (key(i) reads rank i).
 template <typename KeyAt>
 __device__ __forceinline__ void leaf_sums_thread(const KeyAt &key, const LeafRec &L, double *a) {
