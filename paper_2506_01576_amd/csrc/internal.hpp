@@ -224,4 +224,32 @@ __host__ __device__ inline uint64_t rank_slot_binary(const Geo &G, uint64_t r) {
     return G.start[l] + ((v >> e) >> 1);
 }
 
+// floor(x / k) for x < 2^32 and 2 <= k < 2^32, given kinv = ceil(2^64 / k):
+// the high half of x * kinv (exact, since x * (kinv * k - 2^64) < 2^64).
+__host__ __device__ inline uint64_t div_small(uint64_t x, uint64_t kinv) {
+    return (uint64_t)(((unsigned __int128)x * kinv) >> 64);
+}
+
+// The inverse of slot_rank for any k (n < 2^32).  Ranks come in groups of k
+// while bottom-level keys last: k - 1 bottom entries, then one upper-level
+// key.  An upper-level key has perfect-tree rank p (p = r / k in a group,
+// p = r - b after the groups); p + 1 = k^e * u with u not a multiple of k
+// puts it on level m - 1 - e at position (u - 1) - (u - 1) / k.
+__host__ __device__ inline uint64_t rank_slot_general(const Geo &G, uint64_t r, uint64_t kinv) {
+    const uint64_t q = div_small(r, kinv);
+    const uint64_t j = r - q * G.k;
+    if (j < G.g && q * G.g + j < G.b) return G.start[G.m] + q * G.g + j;
+    const uint64_t p = (j == G.g && G.g * (q + 1) <= G.b) ? q : r - G.b;
+    uint64_t v = p + 1;
+    uint32_t e = 0;
+    for (;;) {
+        const uint64_t w = div_small(v, kinv);
+        if (w * G.k != v) break;
+        v = w;
+        ++e;
+    }
+    const uint32_t l = G.m - 1 - e;
+    return G.start[l] + (v - 1) - div_small(v - 1, kinv);
+}
+
 }  // namespace idx

@@ -66,6 +66,20 @@ __global__ __launch_bounds__(256) void k_permute_rank2(const K *__restrict__ sk,
     dst.put(rank_slot_binary(G, r) + off, sk[r], sr[r]);
 }
 
+// The same in rank order for any k: slot rank_slot_general(r).  A wave's
+// ranks land on a run of consecutive leaf slots (k - 1 of every k ranks) and
+// short runs on the levels above.
+template <typename K, bool AOS>
+__global__ __launch_bounds__(256) void k_permute_rank(const K *__restrict__ sk, const uint32_t *__restrict__ sr, Geo G,
+                                                      uint64_t kinv, Store<K, AOS> dst) {
+    const uint32_t per = gridDim.x / kPermXcds, rem = gridDim.x % kPermXcds;
+    const uint32_t x = blockIdx.x % kPermXcds, i = blockIdx.x / kPermXcds;
+    const uint32_t blk = x * per + (x < rem ? x : rem) + i;  // a bijection of [0, gridDim.x)
+    const uint64_t r = (uint64_t)blk * blockDim.x + threadIdx.x;
+    if (r >= G.n) return;
+    dst.put(rank_slot_general(G, r, kinv), sk[r], sr[r]);
+}
+
 template <typename K, bool AOS>
 __global__ void k_empty_slot0(Store<K, AOS> dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) dst.put(0, K(0), kMiss);
@@ -141,6 +155,11 @@ int build_layout_t(idx_index *h, const K *sk, const uint32_t *sr, hipStream_t s)
         hipLaunchKernelGGL((k_permute<K, AOS, false>), dim3(blocks), dim3(256), 0, s, sk, sr, h->geo, 0u, dst);
     } else if (h->geo.k == 2) {
         hipLaunchKernelGGL((k_permute_rank2<K, AOS>), dim3(blocks), dim3(256), 0, s, sk, sr, h->geo, off, dst);
+    } else if (off == 0) {
+        // ceil(2^64 / k) for the exact divisions of the inverse slot map
+        const uint64_t k = h->geo.k;
+        const uint64_t kinv = ~0ull / k + 1;
+        hipLaunchKernelGGL((k_permute_rank<K, AOS>), dim3(blocks), dim3(256), 0, s, sk, sr, h->geo, kinv, dst);
     } else {
         hipLaunchKernelGGL((k_permute<K, AOS, true>), dim3(blocks), dim3(256), 0, s, sk, sr, h->geo, off, dst);
     }
