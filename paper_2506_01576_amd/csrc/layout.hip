@@ -32,27 +32,25 @@ Geo make_geo(uint64_t n, uint32_t k) {
 
 namespace {
 
-// One thread per target slot t: load the sorted entry of rank slot_rank(t)
-// and store it at slot t + off (off = 1 for the binary layout's empty slot 0).
-// Writes are consecutive per wave; reads are strided on the upper levels and
-// nearly consecutive on the lowest level, which holds most keys.
-template <typename K, bool AOS, bool PERMUTE>
-__global__ __launch_bounds__(256) void k_permute(const K *__restrict__ sk, const uint32_t *__restrict__ sr, Geo G,
-                                                 uint32_t off, Store<K, AOS> dst) {
+// The sorted-array layout: entry t to slot t (a copy, or the interleaving
+// of keys and row IDs for the array of structures).
+template <typename K, bool AOS>
+__global__ __launch_bounds__(256) void k_copy_sorted(const K *__restrict__ sk, const uint32_t *__restrict__ sr,
+                                                     uint64_t n, Store<K, AOS> dst) {
     const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= G.n) return;
-    const uint64_t r = PERMUTE ? slot_rank(G, t) : t;
-    dst.put(t + off, sk[r], sr[r]);
+    if (t >= n) return;
+    dst.put(t, sk[t], sr[t]);
 }
 
-// The binary layout read in rank order: thread r loads sorted entry r (the
-// read is consecutive per wave, each line of the sorted arrays fetched once)
-// and stores it at slot rank_slot_binary(r) + off.  A wave's 64 ranks land
-// on runs of consecutive slots, one per level (32, 16, 8, ... slots); the
-// workgroups of one XCD take a contiguous share of the ranks, so the short
-// runs of the upper levels from neighbouring waves complete their lines in
-// one L2.  The slot-order gather above fetches every line of the sorted
-// arrays once per level on the lowest levels, whose stride is below a line.
+// The Eytzinger layouts, built in rank order: thread r loads sorted entry r
+// (the read is consecutive per wave, each line of the sorted arrays fetched
+// once) and stores it at its level-order slot, + off (off = 1 for the binary
+// layout's empty slot 0).  A wave's 64 ranks land on runs of consecutive
+// slots, one per level (32, 16, 8, ... slots for k = 2); the workgroups of
+// one XCD take a contiguous share of the ranks, so the short runs of the
+// upper levels from neighbouring waves complete their lines in one L2.  A
+// gather in slot order would fetch every line of the sorted arrays once per
+// level wherever a level's stride is below a line.
 constexpr uint32_t kPermXcds = 8;  // workgroups are dealt round-robin over the 8 XCDs
 
 template <typename K, bool AOS>
@@ -66,9 +64,9 @@ __global__ __launch_bounds__(256) void k_permute_rank2(const K *__restrict__ sk,
     dst.put(rank_slot_binary(G, r) + off, sk[r], sr[r]);
 }
 
-// The same in rank order for any k: slot rank_slot_general(r).  A wave's
-// ranks land on a run of consecutive leaf slots (k - 1 of every k ranks) and
-// short runs on the levels above.
+// The same for any k (the k-ary layout, no empty slot): slot
+// rank_slot_general(r).  k - 1 of every k ranks go to consecutive slots of
+// the lowest level while it lasts.
 template <typename K, bool AOS>
 __global__ __launch_bounds__(256) void k_permute_rank(const K *__restrict__ sk, const uint32_t *__restrict__ sr, Geo G,
                                                       uint64_t kinv, Store<K, AOS> dst) {
@@ -152,16 +150,14 @@ int build_layout_t(idx_index *h, const K *sk, const uint32_t *sr, hipStream_t s)
     if (n == 0) return IDX_OK;
     const uint32_t blocks = (uint32_t)((n + 255) / 256);
     if (h->layout == IDX_BS) {
-        hipLaunchKernelGGL((k_permute<K, AOS, false>), dim3(blocks), dim3(256), 0, s, sk, sr, h->geo, 0u, dst);
-    } else if (h->geo.k == 2) {
+        hipLaunchKernelGGL((k_copy_sorted<K, AOS>), dim3(blocks), dim3(256), 0, s, sk, sr, n, dst);
+    } else if (h->geo.k == 2) {  // EBS (k = 2 always, off = 1) or EKS with k = 2
         hipLaunchKernelGGL((k_permute_rank2<K, AOS>), dim3(blocks), dim3(256), 0, s, sk, sr, h->geo, off, dst);
-    } else if (off == 0) {
+    } else {  // EKS, k in [3, IDX_MAX_FANOUT], off = 0
         // ceil(2^64 / k) for the exact divisions of the inverse slot map
         const uint64_t k = h->geo.k;
         const uint64_t kinv = ~0ull / k + 1;
         hipLaunchKernelGGL((k_permute_rank<K, AOS>), dim3(blocks), dim3(256), 0, s, sk, sr, h->geo, kinv, dst);
-    } else {
-        hipLaunchKernelGGL((k_permute<K, AOS, true>), dim3(blocks), dim3(256), 0, s, sk, sr, h->geo, off, dst);
     }
     IDX_LAUNCH_CHECK();
     return IDX_OK;
