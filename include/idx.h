@@ -242,10 +242,21 @@ int idx_export(idx_handle h, void *keys_out, uint32_t *rowids_out, idx_stream st
  * rank of the entry stored at 0-based level-order slot `slot` of the k-ary
  * Eytzinger layout over n keys (k = 2 is the binary layout, whose 1-based
  * slot s is level-order slot s - 1).  This is the inverse permutation p'(t)
- * of Sections 4 and 6.1 that the build kernel evaluates for every slot.
- * Returns UINT64_MAX when k < 2 or slot >= n.  Pure function, no device use.
+ * of Sections 4 and 6.1, which the range level scan evaluates for the slots
+ * it visits.  Returns UINT64_MAX when k < 2 or slot >= n.  Pure function, no
+ * device use.
  */
 uint64_t idx_slot_rank(uint64_t n, uint32_t k, uint64_t slot);
+
+/*
+ * idx_rank_slot -- host-side evaluation of the map the layout build kernels
+ * evaluate for every sorted rank (Sections 4 and 6.1 read in the other
+ * direction): the 0-based level-order slot of the k-ary Eytzinger layout
+ * over n keys that holds the key of sorted rank `rank`, the inverse of
+ * idx_slot_rank.  Returns UINT64_MAX when k < 2, k > IDX_MAX_FANOUT,
+ * n > IDX_MAX_KEYS or rank >= n.  Pure function, no device use.
+ */
+uint64_t idx_rank_slot(uint64_t n, uint32_t k, uint64_t rank);
 
 /* ---------------------------------------------------------------------------
  * Lookup tuning (Section 7: limiting concurrency, cache pinning, local

@@ -116,6 +116,7 @@ SIGNATURES = {
     "idx_get_info": (_I, [_P, ctypes.POINTER(idx_info)]),
     "idx_export": (_I, [_P, _P, _P, _P]),
     "idx_slot_rank": (_U64, [_U64, _U32, _U64]),
+    "idx_rank_slot": (_U64, [_U64, _U32, _U64]),
     "idx_set_params": (_I, [_P, ctypes.POINTER(idx_lookup_params)]),
     "idx_get_params": (_I, [_P, ctypes.POINTER(idx_lookup_params)]),
     "idx_probe_random": (_I, [_P, _U64, _U32, _U64, _U32, _U64, _P, _P]),

@@ -416,6 +416,13 @@ uint64_t idx_slot_rank(uint64_t n, uint32_t k, uint64_t slot) {
     return slot_rank(G, slot);
 }
 
+uint64_t idx_rank_slot(uint64_t n, uint32_t k, uint64_t rank) {
+    if (k < 2 || k > IDX_MAX_FANOUT || n > IDX_MAX_KEYS || rank >= n) return ~0ull;
+    const Geo G = make_geo(n, k);
+    if (k == 2) return rank_slot_binary(G, rank);
+    return rank_slot_general(G, rank, ~0ull / k + 1);
+}
+
 int idx_set_params(idx_handle h, const idx_lookup_params *p) {
     if (!h) return IDX_ERR_ARG;
     idx_lookup_params r{};

@@ -109,6 +109,26 @@ def test_build_permutation_matches_oracle(k):
     assert L.idx_slot_rank(5, 2, 5) == 2**64 - 1
 
 
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 8, 9, 16, 17, 32, 33, 64, 65])
+def test_build_rank_slot_matches_oracle(k):
+    """The rank-to-slot map the layout build kernels evaluate (host copy of
+    the same function) places every sorted rank where the oracle's
+    in-order-walk layout holds it."""
+    L = idx.lib()
+    ns = list(range(0, 300)) + [k ** 2 - 1, k ** 2, k ** 3 - 1, k ** 3 + 1, 4097, 65535, 65536]
+    for n in ns:
+        if n > 70000:
+            continue
+        ranks = oracle.eytzinger_ranks(n, k)  # rank held by each slot
+        want = np.empty(n, dtype=np.uint64)
+        want[ranks.astype(np.int64)] = np.arange(n, dtype=np.uint64)
+        got = np.fromiter((L.idx_rank_slot(n, k, r) for r in range(n)), dtype=np.uint64, count=n)
+        assert np.array_equal(got, want), (k, n)
+    assert L.idx_rank_slot(5, 1, 0) == 2**64 - 1
+    assert L.idx_rank_slot(5, 66, 0) == 2**64 - 1
+    assert L.idx_rank_slot(5, 2, 5) == 2**64 - 1
+
+
 def test_build_permutation_large_sampled():
     L = idx.lib()
     rng = np.random.default_rng(9)
