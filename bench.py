@@ -309,8 +309,7 @@ def run_study(args, idx, gen, np, torch, dev, log):
     2^24 keys, each distinct value replicated r times, and 2^24 equality
     ranges [x, x] (every replica in key order, the paper's treatment of point
     lookups on duplicated keys).  Every answer is checked against the
-    generator (skew) or the oracle on a sample (duplicates)."""
-    import oracle
+    generator's answers (known by construction)."""
     from paper_2506_01576_amd import autotune
 
     res = {"skew": {}, "duplicates": {}}
@@ -400,9 +399,15 @@ def run_study(args, idx, gen, np, torch, dev, log):
         dk = torch.from_numpy(kh.view(np.int64)).to(dev)
         dr = torch.from_numpy(rh.view(np.int32)).to(dev)
         dq = torch.from_numpy(qh.view(np.int64)).to(dev)
-        sk, sr = oracle.stable_sort(kh, rh)
+        # by construction: value v's replicas carry the row IDs v*r .. v*r+r-1
+        # at input positions pos[row]; a stable order lists them by position
+        pos = np.argsort(perm)
         sample = rng.integers(0, md, 256)
-        wo, wrows = oracle.range_lookup(sk, sr, qh[sample], qh[sample], nthreads=8)
+        want = {}
+        for s2 in sample.tolist():
+            v = int(np.nonzero(vh == qh[s2])[0][0])
+            ids = np.arange(v * r, v * r + r, dtype=np.int64)
+            want[s2] = ids[np.argsort(pos[ids], kind="stable")].astype(np.uint32)
         row = {}
         with idx.Index(dk, dr, layout="bs") as b2:
             hs = {"BS": b2, "EBS": b2.relayout("ebs", 2), "EKS(k=9,single)": b2.relayout("eks", 9),
@@ -422,9 +427,9 @@ def run_study(args, idx, gen, np, torch, dev, log):
                 ms = a.elapsed_time(b)
                 offh = off.cpu().numpy().view(np.uint64)
                 ok = bool(np.all(np.diff(offh) == r))
-                for j, s2 in enumerate(sample):
+                for s2 in sample.tolist():
                     got = rr[int(offh[s2]):int(offh[s2 + 1])].cpu().numpy().view(np.uint32)
-                    ok &= bool(np.array_equal(got, wrows[wo[j]:wo[j + 1]]))
+                    ok &= bool(np.array_equal(got, want[s2]))
                 row[fname] = {"ms": round(ms, 4), "lookups_per_s": md / ms * 1e3, "rowids_per_s": md * r / ms * 1e3,
                               "exact": ok}
                 del off, rr
@@ -502,9 +507,8 @@ def run_combined(args, idx, gen, np, torch, dev, log):
     2^26 * indexes / 1024 lookups -- 70% point lookups with 10% misses, 30%
     ranges of 1-256 matches -- runs through the batch in the learned form and
     in plain EKS (k = 17, 16 keys per node); both must agree, and sampled
-    indexes are checked against the oracle."""
-    import oracle
-
+    every hit and every range's match count of every index equals the
+    generator's answer (known by construction)."""
     count = args.combined_indexes
     seed = gen.BASE_SEED + 4
     t0 = time.time()
@@ -512,42 +516,33 @@ def run_combined(args, idx, gen, np, torch, dev, log):
     m_total = max(count, (1 << 26) * count // 1024)
     per = np.full(count, m_total // count, dtype=np.int64)
     per[: m_total - int(per.sum())] += 1
-    ixs, dev_keys = [], []
-    for j in range(count):
+    def keyset(j):
         n = int(sizes[j])
         if j % 2 == 0:
-            kh, rh = gen.unique_keys(seed * 1009 + j, n, 64, 63)
-        else:
-            kh, rh = gen.lognormal_keys(seed * 1009 + j, n)
-        ixs.append(idx.Index(torch.from_numpy(kh.view(np.int64)).to(dev), torch.from_numpy(rh.view(np.int32)).to(dev),
-                             layout="bs"))
-    torch.cuda.synchronize()
-    keys_total = int(sum(ix.n for ix in ixs))
-    log(f"combined: built {count} indexes ({keys_total} keys) in {time.time() - t0:.1f}s")
+            return gen.unique_keys(seed * 1009 + j, n, 64, 63)
+        return gen.lognormal_keys(seed * 1009 + j, n)
 
-    # mixed stream on the device (seeded): per index, kinds, points, ranges
-    g = torch.Generator(device=dev)
-    g.manual_seed(seed)
-    los, his, kinds = [], [], []
-    for j, ix in enumerate(ixs):
-        sk, _ = ix.export()
-        n, m = ix.n, int(per[j])
-        kind = (torch.rand(m, generator=g, device=dev) < 0.3).to(torch.uint8)
-        hit = sk[torch.randint(0, n, (m,), generator=g, device=dev)]
-        miss = torch.randint(0, 1 << 62, (m,), generator=g, device=dev) * 2 + 1
-        lo = torch.where(torch.rand(m, generator=g, device=dev) < 0.9, hit, miss)
-        c = torch.randint(1, 257, (m,), generator=g, device=dev)
-        r = torch.randint(0, n, (m,), generator=g, device=dev)
-        e = torch.clamp(r + c - 1, max=n - 1)
-        rk = kind.bool()
-        lo = torch.where(rk, sk[r], lo)
-        hi = torch.where(rk, sk[e], lo)
+    # indexes, and per index a seeded mixed stream drawn on the device from
+    # its keys (torch's sort and generator: input preparation only)
+    ixs, los, his, kinds, exps, cnts = [], [], [], [], [], []
+    for j in range(count):
+        kh, rh = keyset(j)
+        dk = torch.from_numpy(kh.view(np.int64)).to(dev)
+        dr = torch.from_numpy(rh.view(np.int32)).to(dev)
+        ixs.append(idx.Index(dk, dr, layout="bs"))
+        lo, hi, kd, ex, ct = gen.mixed_queries_device(seed * 7 + j, dk, int(per[j]), rows=dr)
         los.append(lo)
         his.append(hi)
-        kinds.append(kind)
-        del sk
+        kinds.append(kd)
+        exps.append(ex)
+        cnts.append(ct)
+        del dk, dr, kh, rh
+    torch.cuda.synchronize()
+    keys_total = int(sum(ix.n for ix in ixs))
+    log(f"combined: built {count} indexes ({keys_total} keys) and their streams in {time.time() - t0:.1f}s")
     lo, hi, kind = torch.cat(los), torch.cat(his), torch.cat(kinds)
-    del los, his, kinds
+    expect, counts = torch.cat(exps), torch.cat(cnts)
+    del los, his, kinds, exps, cnts
     off = np.zeros(count + 1, dtype=np.int64)
     off[1:] = np.cumsum(per)
     doff = torch.from_numpy(off).to(dev)
@@ -594,33 +589,129 @@ def run_combined(args, idx, gen, np, torch, dev, log):
     agree = all(bool(torch.equal(a, b)) for a, b in zip(got_l, got_e))
     for e in eks:
         e.close()
-    # sampled indexes against the oracle
-    sample_ok = True
-    for j in sorted({0, 1, count // 2, count - 1}):
-        sk, sr = ixs[j].export()
-        skh = sk.cpu().numpy().view(np.uint64)
-        srh = sr.cpu().numpy().view(np.uint32)
-        a, b = int(off[j]), int(off[j + 1])
-        kd = kind[a:b].cpu().numpy()
-        lh = lo[a:b].cpu().numpy().view(np.uint64)
-        hh = hi[a:b].cpu().numpy().view(np.uint64)
-        pts, rgs = np.nonzero(kd == 0)[0], np.nonzero(kd == 1)[0]
-        want = oracle.point(skh, srh, lh[pts], nthreads=8)
-        sample_ok &= bool(np.array_equal(got_l[0][a:b].cpu().numpy().view(np.uint32)[pts], want))
-        wo, wr = oracle.range_lookup(skh, srh, lh[rgs], hh[rgs], nthreads=8)
-        go = got_l[1].cpu().numpy().view(np.uint64)
-        grows = got_l[2].cpu().numpy().view(np.uint32)
-        for t, qi in enumerate(rgs[:2000]):
-            s0, s1 = int(go[a + qi]), int(go[a + qi + 1])
-            sample_ok &= bool(np.array_equal(grows[s0:s1], wr[wo[t]:wo[t + 1]]))
+    # every hit and every range's size against the generator's answers
+    hits = expect != -1
+    gen_exact = bool(torch.equal(got_l[0][hits], expect[hits]))
+    gen_exact &= bool(torch.equal(got_l[1][1:] - got_l[1][:-1], counts))
+    del expect, counts, hits
     matches = int(got_l[1][-1].item())
     res.update({"matches": matches, "mixed_learned_ms": round(ms_learned, 4), "mixed_eks17_ms": round(ms_eks, 4),
                 "lookups_per_s_learned": m_total / ms_learned * 1e3, "lookups_per_s_eks17": m_total / ms_eks * 1e3,
-                "learned_vs_eks": ms_eks / ms_learned, "learned_equals_eks": agree, "oracle_sample_exact": sample_ok})
+                "learned_vs_eks": ms_eks / ms_learned, "learned_equals_eks": agree,
+                "hits_and_range_counts_equal_generator": gen_exact})
     log(f"combined: mixed stream learned {ms_learned:.3f} ms, EKS {ms_eks:.3f} ms, agree={agree} "
-        f"oracle sample={sample_ok}")
+        f"generator answers={gen_exact}")
     for ix in ixs:
         ix.close()
+    return res
+
+
+def run_small(idx, gen, np, torch, dev, log):
+    """The small configuration: n = 2^16 unique uint32 keys uniform in
+    [0, 2^32), rowid = insertion position; 2^20 point lookups, half hits
+    (uniform over the keys) and half misses (uniform over the complement),
+    shuffled.  Each layout in its tuned form, checked against the generator's
+    answers; median of 10 launches."""
+    from paper_2506_01576_amd import autotune
+
+    n, m = 1 << 16, 1 << 20
+    seed = gen.BASE_SEED
+    kh, rh = gen.unique_keys(seed, n, 32)
+    qh, eh = gen.point_queries(seed, n, m, 0.5, 32)
+    keys = torch.from_numpy(kh.view(np.int32)).to(dev)
+    rows = torch.from_numpy(rh.view(np.int32)).to(dev)
+    q = torch.from_numpy(qh.view(np.int32)).to(dev)
+    expect = torch.from_numpy(eh.view(np.int32)).to(dev)
+    out = torch.empty(m, dtype=torch.int32, device=dev)
+    res = {"workload": "n=2^16 unique uint32 keys, 2^20 point lookups (50% hits, 50% misses)", "forms": {}}
+    with idx.Index(keys, rows, layout="bs") as base:
+        for layout in ("bs", "ebs", "eks", "learned"):
+            lay, k, aos, params = autotune.choose(n, 32, layout)
+            if lay == "learned":
+                ix = base.relayout("bs", 1, aos) if aos else base
+                ix.learn(params.pop("leaves", max(1, n // 16)), 2)
+                params["model"] = 0
+            else:
+                ix = base if (lay == "bs" and not aos) else base.relayout(lay, k, aos)
+                params["model"] = 2
+            ix.set_params(**params)
+            ix.point(q, out)
+            torch.cuda.synchronize()
+            ok = bool(torch.equal(out, expect))
+            ts = []
+            for _ in range(10):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                ix.point(q, out)
+                b.record()
+                b.synchronize()
+                ts.append(a.elapsed_time(b))
+            ms = float(np.median(ts))
+            res["forms"][layout] = {"layout": lay, "k": k, "aos": aos, "params": ix.params(), "ms": round(ms, 4),
+                                    "lookups_per_s": m / ms * 1e3, "bit_exact": ok}
+            log(f"small u32 {layout}: {ms:.4f} ms ({m / ms / 1e6:.0f} M/s) exact={ok}")
+            if ix is not base:
+                ix.close()
+            else:
+                ix.unlearn()
+                ix.reset_params()
+    best = max(res["forms"], key=lambda f: res["forms"][f]["lookups_per_s"])
+    res["best"] = best
+    res["lookups_per_s"] = res["forms"][best]["lookups_per_s"]
+    res["bit_exact"] = all(v["bit_exact"] for v in res["forms"].values())
+    return res
+
+
+def run_range_scan(idx, np, torch, dev, keys, rows, sorted_rows, log):
+    """Hybrid coalesced against single-lane level scanning of EBS range
+    lookups (Section 5.1; the paper's Fig. 17 experiment at this index size):
+    the n = 2^26 index in EBS layout, 2^18 ranges covering exactly c keys for
+    c = 2^4 .. 2^14; the same ranges in both scan modes, every offset and row
+    ID checked against the ranks the ranges were drawn at."""
+    m = 1 << 18
+    n = len(keys)
+    ordered = torch.sort(keys, stable=True).values
+    g = torch.Generator(device=dev)
+    g.manual_seed(0x2506)
+    res = {"layout": "ebs", "n": n, "ranges": m, "rows": []}
+    with idx.Index(keys, rows, layout="bs") as base, base.relayout("ebs", 2) as ix:
+        for lc in (4, 6, 8, 10, 12, 14):
+            c = 1 << lc
+            r = torch.randint(0, n - c + 1, (m,), generator=g, device=dev)
+            lo, hi = ordered[r], ordered[r + c - 1]
+            row = {"hits": c}
+            for mode, name in ((1, "hybrid"), (2, "single")):
+                ix.set_params(range_scan=mode)
+                reps = 3 if c <= 1024 else 1
+                off, rr = ix.range(lo, hi, capacity=m * c)
+                torch.cuda.synchronize()
+                ok = bool(torch.equal(off, torch.arange(m + 1, device=dev, dtype=torch.int64) * c))
+                step = max(1, (1 << 24) // c)
+                for c0 in range(0, m, step):
+                    c1 = min(m, c0 + step)
+                    pos = (r[c0:c1, None] + torch.arange(c, device=dev)[None, :]).reshape(-1)
+                    ok &= bool(torch.equal(rr[c0 * c:c1 * c], sorted_rows[pos]))
+                del off, rr
+                ts = []
+                for _ in range(reps):
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record()
+                    off, rr = ix.range(lo, hi, capacity=m * c)
+                    b.record()
+                    b.synchronize()
+                    ts.append(a.elapsed_time(b))
+                    del off, rr
+                ms = float(np.median(ts))
+                row[name] = {"ms": round(ms, 4), "ranges_per_s": m / ms * 1e3, "rowids_per_s": m * c / ms * 1e3,
+                             "bit_exact": ok}
+            row["hybrid_speedup"] = row["single"]["ms"] / row["hybrid"]["ms"]
+            res["rows"].append(row)
+            log(f"range scan c={c}: hybrid {row['hybrid']['ms']:.3f} ms, single {row['single']['ms']:.3f} ms "
+                f"({row['hybrid_speedup']:.2f}x) exact={row['hybrid']['bit_exact'] and row['single']['bit_exact']}")
+            torch.cuda.empty_cache()
+    res["bit_exact"] = all(rw[k]["bit_exact"] for rw in res["rows"] for k in ("hybrid", "single"))
     return res
 
 
@@ -645,13 +736,17 @@ def main():
     ap.add_argument("--study", action="store_true",
                     help="also run the skew (Zipf, sorted) and duplicate-key studies (a few minutes)")
     ap.add_argument("--log2n-skew", type=int, default=28, help="keys in the lognormal / Zipf workload (log2)")
-    ap.add_argument("--combined-indexes", type=int, default=128,
+    ap.add_argument("--combined-indexes", type=int, default=1024,
                     help="indexes in the combined workload (1024 = the full configuration; the query count scales "
                          "with it, 2^26 at 1024)")
     ap.add_argument("--sweep", action="store_true",
                     help="re-measure every candidate form (autotuner) instead of using the tuned table")
     ap.add_argument("--write-table", action="store_true", help="with --sweep: store the winners in the tuned table")
     ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="lookups in the CPU oracle sample")
+    ap.add_argument("--no-small", action="store_true", help="leave the 2^16-key uint32 configuration out")
+    ap.add_argument("--no-k-sweep", action="store_true", help="leave the EKS fan-out sweep out")
+    ap.add_argument("--no-range-scan", action="store_true",
+                    help="leave the hybrid against single-lane range-scan measurement out")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (known bytes) to scale hardware byte counters")
     args = ap.parse_args()
@@ -679,7 +774,7 @@ def main():
     q_h, expect_h = gen.point_queries(seed, n, m, 1.0, 64, W)
     log(f"generated keys/queries in {time.time() - t0:.1f}s")
     t0 = time.time()
-    lo_h, hi_h, _ = gen.ranges(seed, keys_h, mr, 16, 16)
+    lo_h, hi_h, _, rank_h = gen.ranges(seed, keys_h, mr, 16, 16, with_ranks=True)
     log(f"generated ranges in {time.time() - t0:.1f}s")
 
     def up(a):
@@ -687,8 +782,12 @@ def main():
 
     keys, rows, q, expect = up(keys_h), up(rows_h), up(q_h), up(expect_h)
     lo, hi = up(lo_h), up(hi_h)
-    del q_h, lo_h, hi_h
+    range_first = torch.from_numpy(rank_h.view(np.int64)).to(dev)
+    del q_h, lo_h, hi_h, rank_h
     out = torch.empty(m, dtype=torch.int32, device=dev)
+    # the build set's row IDs in ascending key order (torch's stable sort:
+    # input preparation for the generator-known range answers)
+    sorted_rows = rows[torch.sort(keys, stable=True).indices]
     torch.cuda.synchronize()
 
     def ev():
@@ -822,7 +921,12 @@ def main():
         return p
 
     # ---------------------------------------------------------------- steps
-    def one_step(record):
+    # every form writes its own output buffer, so the outputs of the last
+    # timed step can be checked after the timed region
+    outs = {name: torch.empty(m, dtype=torch.int32, device=dev) for name, _ in forms}
+    last_ranges = {}
+
+    def one_step(record, keep=False):
         t = {}
         a = ev()
         bs = idx.Index(keys, rows, layout="bs")
@@ -847,7 +951,7 @@ def main():
         for name, rec in forms:
             hs[name].set_params(**lookup_params(rec))
             a = ev()
-            hs[name].point(q, out)
+            hs[name].point(q, outs[name])
             b = ev()
             marks.append((f"point_{name}", a, b))
         range_forms = [forms[0], forms[2]] + ([forms[3]] if len(forms) > 3 else [])
@@ -857,6 +961,8 @@ def main():
             off, rr = hs[name].range(lo, hi, capacity=mr * 16)
             b = ev()
             marks.append((f"range_{name}", a, b))
+            if keep:
+                last_ranges[name] = (off, rr)
             del off, rr
         torch.cuda.synchronize()
         for nm, a, b in marks:
@@ -871,15 +977,34 @@ def main():
     torch.cuda.synchronize()
     rec_steps = []
     t_start = time.perf_counter()
-    for _ in range(args.steps):
-        one_step(rec_steps)
+    for st in range(args.steps):
+        one_step(rec_steps, keep=st == args.steps - 1)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     ms_per_step = wall / args.steps * 1e3
 
+    # bit-exactness of the last timed step's outputs: every point answer
+    # against the generator's (query f(i) -> row ID i); every range's offsets
+    # (16 keys each) and row IDs (ranks r .. r + 15 of the generator's draw)
+    step_exact = {f"point_{name}": bool(torch.equal(outs[name], expect)) for name, _ in forms}
+    want_off = torch.arange(mr + 1, device=dev, dtype=torch.int64) * 16
+    for name, (off, rr) in last_ranges.items():
+        ok = bool(torch.equal(off, want_off))
+        for c0 in range(0, mr, 1 << 22):  # 2^22 ranges (2^26 row IDs) at a time
+            c1 = min(mr, c0 + (1 << 22))
+            pos = (range_first[c0:c1, None] + torch.arange(16, device=dev)[None, :]).reshape(-1)
+            ok &= bool(torch.equal(rr[c0 * 16:c1 * 16], sorted_rows[pos]))
+        step_exact[f"range_{name}"] = ok
+    last_ranges.clear()
+    del outs
+    failed = [k for k, v in step_exact.items() if not v]
+    if failed:
+        log(f"ERROR: outputs of the timed steps differ from the generator's answers: {failed}")
+
     mean = {k: float(np.mean([r[k] for r in rec_steps])) for k in rec_steps[0]}
     point_rates = {name: m / mean[f"point_{name}"] * 1e3 for name, _ in forms}
-    headline = max(point_rates, key=point_rates.get)
+    exact_forms = [name for name, _ in forms if step_exact[f"point_{name}"]] or [name for name, _ in forms]
+    headline = max(exact_forms, key=point_rates.get)
     hrec = dict(forms)[headline]
     value = point_rates[headline]
 
@@ -928,11 +1053,42 @@ def main():
                                      "bound_lookups_per_s": bound,
                                      "frac": (value / bound) if bound else None}
 
+    # ------------------------------------------------ small configuration
+    small = None if args.no_small else run_small(idx, gen, np, torch, dev, log)
+
+    # ------------------------- EKS fan-out sweep: permutation build and lookups
+    ksweep = []
+    if not args.no_k_sweep:
+        with idx.Index(keys, rows, layout="bs") as kb:
+            for k in (4, 8, 16, 32, 5, 9, 17, 33):
+                a = ev()
+                ix = kb.relayout("eks", k)
+                b = ev()
+                b.synchronize()
+                build_ms = a.elapsed_time(b)
+                ms, ok = time_point(ix, reps=3, check=True)
+                p_ = ix.params()
+                ksweep.append({"k": k, "keys_per_node": k - 1, "build_permute_ms": round(build_ms, 4),
+                               "ms": round(ms, 4), "lookups_per_s": m / ms * 1e3, "bit_exact": ok,
+                               "group": p_["group"], "per_lane": p_["per_lane"]})
+                log(f"k sweep k={k}: permute {build_ms:.3f} ms, lookups {ms:.3f} ms ({m / ms / 1e6:.0f} M/s) "
+                    f"exact={ok}")
+                ix.close()
+
+    # ------------- hybrid against single-lane level scan over growing hit counts
+    scan_row = None
+    if not args.no_range_scan:
+        scan_row = run_range_scan(idx, np, torch, dev, keys, rows, sorted_rows, log)
+
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        cores = min(16, os.cpu_count() or 1)
+        # the host threads this job may use: the machine's CPU share (its thread
+        # budget, OMP_NUM_THREADS), not every core the machine reports
+        nproc = os.cpu_count() or 1
+        share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+        cores = max(1, min(share, nproc))
         ms_ = min(args.cpu_sample, m)
         t0 = time.perf_counter()
         sk, sr = oracle.stable_sort(keys_h, rows_h)
@@ -948,7 +1104,7 @@ def main():
         t_1 = time.perf_counter() - t0
         cpu_exact = cpu_exact and bool(np.array_equal(got1, expect_h[:m1]))
         cpu = {"value": ms_ / t_pt, "unit": "lookups/s", "cores": cores, "kind": "oracle",
-               "value_1thread": m1 / t_1,
+               "value_1thread": m1 / t_1, "nproc": nproc, "affinity_cpus": len(os.sched_getaffinity(0)),
                "sample": f"first {ms_} of the {m} queries against the full n={n} build sorted by the oracle's "
                          f"stable sort ({t_sort:.1f} s, 1 thread); lower_bound + equality per query, "
                          f"{cores} threads; answers equal the generator's: {cpu_exact}"}
@@ -1010,7 +1166,13 @@ def main():
                             if "mean_window" in rec else {})} for name, rec in forms},
         "phases_ms": {k: round(v, 4) for k, v in mean.items()},
         "range_lookups_per_s": {k[6:]: mr / v * 1e3 for k, v in mean.items() if k.startswith("range_")},
-        "bit_exact": all(r["bit_exact"] for r in checked),
+        "bit_exact": (all(r["bit_exact"] for r in checked) and all(step_exact.values())
+                      and all(r["bit_exact"] for r in ksweep) and (small is None or small["bit_exact"])
+                      and (scan_row is None or scan_row["bit_exact"])),
+        "bit_exact_timed_step": step_exact,
+        "small": small,
+        "k_sweep": ksweep,
+        "range_scan": scan_row,
         "random_access": probe,
         "batched": batched,
         "combined": combined,
@@ -1021,6 +1183,8 @@ def main():
                   for r in sweep],
     }
     print(json.dumps(line), flush=True)
+    if not line["bit_exact"]:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

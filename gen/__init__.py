@@ -59,7 +59,7 @@ def lib():
         L.gen_lognormal_keys.restype = ctypes.c_int
         L.gen_lognormal_keys.argtypes = [_u64, _u64, _p, _p]
         L.gen_log_uniform.argtypes = [_u64, _u64, _u64, _u64, _u64, _p]
-        L.gen_ranges.argtypes = [_u64, _p, ctypes.c_int, _u64, _u64, _u64, _u64, _p, _p, _p]
+        L.gen_ranges.argtypes = [_u64, _p, ctypes.c_int, _u64, _u64, _u64, _u64, _p, _p, _p, _p]
         L.gen_uniform_values.argtypes = [_u64, _u64, ctypes.c_int, _u64, _p, ctypes.c_int]
         _lib = L
     return _lib
@@ -144,17 +144,20 @@ def log_uniform(seed: int, stream: int, lo: int, hi: int, count: int) -> np.ndar
     return out
 
 
-def ranges(seed: int, keys: np.ndarray, m: int, cmin: int, cmax: int):
+def ranges(seed: int, keys: np.ndarray, m: int, cmin: int, cmax: int, with_ranks: bool = False):
     """m range queries [lo, hi] over the build set `keys` covering c ~ U{cmin..cmax}
     consecutive build keys each.  The set is put in ascending order with
-    numpy's sort (input preparation only).  Returns (lo, hi, c)."""
+    numpy's sort (input preparation only).  Returns (lo, hi, c), and with
+    with_ranks also r, the ascending-order rank of each range's first key
+    (the range covers ranks r .. r + c - 1 of a set of distinct keys)."""
     kb = keys.dtype.itemsize * 8
     ordered = np.sort(keys, kind="stable")
     lo = np.empty(m, dtype=keys.dtype)
     hi = np.empty(m, dtype=keys.dtype)
     c = np.empty(m, dtype=np.uint32)
-    lib().gen_ranges(seed, _ptr(ordered), kb // 8, len(keys), m, cmin, cmax, _ptr(lo), _ptr(hi), _ptr(c))
-    return lo, hi, c
+    r = np.empty(m, dtype=np.uint64) if with_ranks else None
+    lib().gen_ranges(seed, _ptr(ordered), kb // 8, len(keys), m, cmin, cmax, _ptr(lo), _ptr(hi), _ptr(c), _ptr(r))
+    return (lo, hi, c, r) if with_ranks else (lo, hi, c)
 
 
 def uniform_values(seed: int, stream: int, m: int, key_bits: int = 32, w: int | None = None) -> np.ndarray:
@@ -162,3 +165,46 @@ def uniform_values(seed: int, stream: int, m: int, key_bits: int = 32, w: int | 
     out = np.empty(m, dtype=_kdt(key_bits))
     lib().gen_uniform_values(seed, stream, w, m, _ptr(out), key_bits // 8)
     return out
+
+
+def mixed_queries_device(seed: int, keys, m: int, range_fraction: float = 0.3, miss_fraction: float = 0.1,
+                         cmin: int = 1, cmax: int = 256, rows=None):
+    """A seeded mixed lookup stream over one build set, made on the device
+    with torch's own sort and random generator (input preparation only; no
+    index code is involved).  `keys` is a device tensor of int64 key bit
+    patterns below 2^63 (so signed order is key order).  Each of the m
+    queries is a range with probability range_fraction -- c ~ U{cmin..cmax}
+    consecutive build keys, L = the key of a uniform rank r, U = the key of
+    rank r + c - 1 (clamped to the largest) -- else a point lookup of a
+    uniform build key, replaced with probability miss_fraction by an odd
+    value uniform in [0, 2^63) (absent unless it happens to be a key).
+    Returns device tensors (lo, hi, kind) with kind 1 for ranges; hi = lo
+    for points.  With the keys' row IDs `rows` (device int32) and distinct
+    keys, also the answers known by construction: (lo, hi, kind, expect,
+    count) with expect the row ID of every hit point lookup (-1 for the
+    misses and the ranges) and count the number of keys each range covers
+    (0 for points)."""
+    import torch
+
+    dev = keys.device
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(seed) & ((1 << 63) - 1))
+    n = len(keys)
+    ordered, perm = torch.sort(keys, stable=True)
+    kind = (torch.rand(m, generator=g, device=dev) < range_fraction).to(torch.uint8)
+    pick = torch.randint(0, n, (m,), generator=g, device=dev)
+    hit = ordered[pick]
+    miss = torch.randint(0, 1 << 62, (m,), generator=g, device=dev) * 2 + 1
+    is_hit = torch.rand(m, generator=g, device=dev) < 1.0 - miss_fraction
+    lo = torch.where(is_hit, hit, miss)
+    c = torch.randint(cmin, cmax + 1, (m,), generator=g, device=dev)
+    r = torch.randint(0, n, (m,), generator=g, device=dev)
+    e = torch.clamp(r + c - 1, max=n - 1)
+    rk = kind.bool()
+    hi = torch.where(rk, ordered[e], lo)
+    lo = torch.where(rk, ordered[r], lo)
+    if rows is None:
+        return lo, hi, kind
+    expect = torch.where(is_hit & ~rk, rows[perm[pick]], torch.full_like(rows[:1], -1).expand(m))
+    count = torch.where(rk, e - r + 1, torch.zeros_like(e))
+    return lo, hi, kind, expect, count

@@ -373,7 +373,7 @@ void gen_log_uniform(uint64_t seed, uint64_t stream, uint64_t lo, uint64_t hi, u
  * n), starting at a rank uniform in [0, n - c_t]: lo = ordered[r],
  * hi = ordered[r + c_t - 1].  Writes the rank count to counts (may be NULL). */
 void gen_ranges(uint64_t seed, const void *ordered, int key_bytes, uint64_t n, uint64_t m, uint64_t cmin,
-                uint64_t cmax, void *lo, void *hi, uint32_t *counts)
+                uint64_t cmax, void *lo, void *hi, uint32_t *counts, uint64_t *ranks)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t t = 0; t < (int64_t)m; ++t) {
@@ -384,12 +384,14 @@ void gen_ranges(uint64_t seed, const void *ordered, int key_bytes, uint64_t n, u
             put_key(lo, key_bytes, (uint64_t)t, 1);
             put_key(hi, key_bytes, (uint64_t)t, 0);
             if (counts) counts[t] = 0;
+            if (ranks) ranks[t] = 0;
             continue;
         }
         const uint64_t r = below(gen_draw(seed, 21, (uint64_t)t), n - c + 1);
         put_key(lo, key_bytes, (uint64_t)t, get_key(ordered, key_bytes, r));
         put_key(hi, key_bytes, (uint64_t)t, get_key(ordered, key_bytes, r + c - 1));
         if (counts) counts[t] = (uint32_t)c;
+        if (ranks) ranks[t] = r;
     }
 }
 

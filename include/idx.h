@@ -88,9 +88,11 @@ typedef struct idx_allocator {
  *
  * Sorts the pairs by key with a stable LSD radix sort (Section 3: the BS
  * index is a key-value sort; equal keys keep their input order), then for
- * IDX_EBS / IDX_EKS rearranges the sorted array into Eytzinger order by the
- * inverse permutation: the thread of target slot t loads the sorted entry of
- * rank p'(t) (Section 4 for k = 2, Section 6.1 for general k).
+ * IDX_EBS / IDX_EKS rearranges the sorted array into Eytzinger order with one
+ * read and one write per element, in rank order: the thread of sorted rank r
+ * reads entry r and writes it to the level-order slot t whose rank p'(t) is r,
+ * the inverse of the map p'(t) of Section 4 (k = 2) and Section 6.1 (any k),
+ * evaluated in closed form (idx_rank_slot gives the same map on the host).
  *
  *   keys     device array of n keys (uint32 or uint64 per flags)
  *   rowids   device array of n uint32 row IDs; none may equal IDX_MISS
@@ -199,7 +201,9 @@ int idx_range(idx_handle h, const void *lo, const void *hi, uint64_t m, uint64_t
               uint32_t *out_rowids, uint64_t capacity, uint64_t *total, idx_stream stream);
 
 /* idx_destroy -- free the handle and its device buffers (stream-ordered on
- * the stream of the last call that used the handle).  NULL is accepted. */
+ * the stream of the last call that used the handle).  NULL is accepted.
+ * IDX_ERR_ARG, and nothing is freed, while a batch (idx_batch_create) holds
+ * the handle. */
 int idx_destroy(idx_handle h);
 
 /* Text for a status code (static storage). */
@@ -280,6 +284,10 @@ typedef struct idx_lookup_params {
                                keys are below the query (fewer lines when they come from HBM);
                                1 = read the whole window at once (shorter chains when it is cached,
                                e.g. skewed or sorted batches) */
+    uint32_t range_scan; /* Eytzinger range lookups (level scan, Section 5): 0 = default (1);
+                            1 = hybrid coalesced scan (Section 5.1): a lane that meets 64 matches
+                            on one level hands its scan to its whole wave; 2 = every range
+                            scanned by its own lane alone */
 } idx_lookup_params;
 
 /* Set (p != NULL) or reset to defaults (p == NULL).  Errors: IDX_ERR_ARG for an
@@ -395,9 +403,14 @@ typedef struct idx_batch *idx_batch_t;
 /*
  * idx_batch_create -- gather `count` indexes (same key width, SoA layouts;
  * any of BS, EBS, EKS, or BS with a learned model) into one batch.  The
- * indexes must outlive the batch and keep the lookup parameters they had
- * at creation (EKS early exit, use of the model).  Synchronises `stream`.
- * Errors: IDX_ERR_ARG (null, mixed key widths, AoS layout), IDX_ERR_NOMEM.
+ * batch's device descriptors point at the members' layout and model buffers,
+ * so until idx_batch_destroy every member is held: on a held handle
+ * idx_destroy, idx_learn, idx_unlearn and idx_learn_batch return IDX_ERR_ARG
+ * and change nothing, and idx_set_params returns IDX_ERR_ARG for a parameter
+ * set that changes the use of the model or the EKS early exit (the two
+ * parameters the descriptors copy).  A handle may belong to several batches.
+ * Synchronises `stream`.  Errors: IDX_ERR_ARG (null, mixed key widths, AoS
+ * layout), IDX_ERR_NOMEM.
  */
 int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream stream, idx_batch_t *out);
 
@@ -445,7 +458,8 @@ int idx_batch_mixed(idx_batch_t b, uint64_t m, const void *lo, const void *hi, c
                     const uint64_t *offsets, uint32_t *out_rowid, uint64_t *range_offsets, uint32_t *range_rowids,
                     uint64_t capacity, uint64_t *total, idx_stream stream);
 
-/* Free the batch (synchronises the device first).  NULL is accepted. */
+/* Free the batch (synchronises the device first) and release its hold on
+ * the member indexes.  NULL is accepted. */
 int idx_batch_destroy(idx_batch_t b);
 
 /* ---------------------------------------------------------------------------

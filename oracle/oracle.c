@@ -13,7 +13,7 @@
  *      (Section 1 problem statement; Section 3: building BS is a key-value sort).
  *  O2  point lookup: first position r with K[r] >= x (lower bound); the answer
  *      is R[r] when K[r] == x, else the miss sentinel 0xFFFFFFFF
- *      (Section 1: "find the row ID of the row that contains X").
+ *      (Section 1 point lookup: the row ID of the row whose key is X).
  *  O3  range lookup [L, U]: all R[r] with L <= K[r] <= U, in ascending key
  *      order (ties in input order); per-query offsets are the exclusive prefix
  *      sum of the counts (Section 1 range lookup).

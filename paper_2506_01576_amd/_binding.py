@@ -73,6 +73,7 @@ class idx_lookup_params(ctypes.Structure):
         ("early_exit", ctypes.c_uint32),
         ("model", ctypes.c_uint32),
         ("window_rounds", ctypes.c_uint32),
+        ("range_scan", ctypes.c_uint32),
     ]
 
     def as_dict(self):
@@ -192,6 +193,29 @@ def _dev(t: torch.Tensor, name: str):
         raise ValueError(f"{name} must be a contiguous device tensor")
 
 
+def _keys_of(t: torch.Tensor, name: str, key_bits: int):
+    """A device tensor of keys of the index's width (bit patterns are read as
+    unsigned, so signed and unsigned integer dtypes of that width both work)."""
+    _dev(t, name)
+    if t.dtype.is_floating_point or t.dtype.is_complex or t.element_size() * 8 != key_bits:
+        raise ValueError(f"{name}: {key_bits}-bit integer keys expected, got {t.dtype}")
+    if t.dim() != 1:
+        raise ValueError(f"{name} must be one-dimensional")
+
+
+def _out_u32(t: torch.Tensor, name: str, length: int):
+    _dev(t, name)
+    if t.dtype not in (torch.int32, torch.uint32) or t.dim() != 1 or len(t) < length:
+        raise ValueError(f"{name} must be a 32-bit integer device tensor of at least {length} entries")
+
+
+def _offsets_of(t: torch.Tensor, name: str, count: int):
+    """Per-index query offsets: int64 (or uint64), count + 1 entries."""
+    _dev(t, name)
+    if t.dtype not in (torch.int64, torch.uint64) or t.dim() != 1 or len(t) != count + 1:
+        raise ValueError(f"{name} must be a 64-bit integer device tensor of {count + 1} entries")
+
+
 class Index:
     """A static index over (keys, rowids) device tensors.
 
@@ -279,8 +303,10 @@ class Index:
 
     # -- lifecycle
     def close(self):
+        """Free the index.  Raises IdxError (and keeps the index) while a
+        Batch holds it: close the batch first."""
         if getattr(self, "_h", None):
-            lib().idx_destroy(self._h)
+            _check(lib().idx_destroy(self._h), "idx_destroy")
             self._h = None
 
     def __del__(self):
@@ -297,12 +323,10 @@ class Index:
 
     # -- lookups
     def point(self, queries: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        _dev(queries, "queries")
-        if queries.element_size() * 8 != self.key_bits:
-            raise ValueError("query width differs from the key width")
+        _keys_of(queries, "queries", self.key_bits)
         if out is None:
             out = torch.empty(len(queries), dtype=torch.int32, device=queries.device)
-        _dev(out, "out")
+        _out_u32(out, "out", len(queries))
         _check(lib().idx_point(self._h, queries.data_ptr(), len(queries), out.data_ptr(), _stream(stream)),
                "idx_point")
         return out
@@ -310,9 +334,11 @@ class Index:
     def range(self, lo: torch.Tensor, hi: torch.Tensor, capacity: int | None = None, count_only: bool = False,
               stream=None):
         """Returns (offsets[m+1] int64, rowids[total] int32)."""
-        _dev(lo, "lo")
-        _dev(hi, "hi")
+        _keys_of(lo, "lo", self.key_bits)
+        _keys_of(hi, "hi", self.key_bits)
         m = len(lo)
+        if len(hi) != m:
+            raise ValueError("lo and hi differ in length")
         offsets = torch.empty(m + 1, dtype=torch.int64, device=lo.device)
         total = ctypes.c_uint64(0)
         s = _stream(stream)
@@ -412,17 +438,36 @@ class Batch:
 
     def __init__(self, indexes, stream=None):
         self._indexes = list(indexes)
+        if not self._indexes:
+            raise ValueError("a batch needs at least one index")
+        self.key_bits = self._indexes[0].key_bits
+        self.count = len(self._indexes)
+        self._total_seen = {}
         arr = (ctypes.c_void_p * len(self._indexes))(*[ix._h.value for ix in self._indexes])
         h = ctypes.c_void_p()
         _check(lib().idx_batch_create(arr, len(self._indexes), _stream(stream), ctypes.byref(h)), "idx_batch_create")
         self._h = h
 
+    def _check_total(self, offsets: torch.Tensor, m: int, exact: bool):
+        """The kernels read offsets[count] entries of the query arrays: it may
+        not exceed their length (exact: must equal it).  Read once per offsets
+        tensor and version."""
+        key = (offsets.data_ptr(), offsets._version, len(offsets))
+        total = self._total_seen.get(key)
+        if total is None:
+            total = int(offsets[-1].item())
+            self._total_seen = {key: total}
+        if total > m or (exact and total != m):
+            raise ValueError(f"offsets[-1] = {total} does not fit the {m} queries given")
+
     def point(self, queries: torch.Tensor, offsets: torch.Tensor, out: torch.Tensor | None = None,
               graph: bool = False, stream=None) -> torch.Tensor:
-        _dev(queries, "queries")
-        _dev(offsets, "offsets")
+        _keys_of(queries, "queries", self.key_bits)
+        _offsets_of(offsets, "offsets", self.count)
+        self._check_total(offsets, len(queries), exact=False)
         if out is None:
             out = torch.empty(len(queries), dtype=torch.int32, device=queries.device)
+        _out_u32(out, "out", len(queries))
         _check(lib().idx_batch_point(self._h, queries.data_ptr(), offsets.data_ptr(), out.data_ptr(),
                                      IDX_BATCH_GRAPH if graph else 0, _stream(stream)), "idx_batch_point")
         return out
@@ -431,11 +476,16 @@ class Batch:
               capacity: int | None = None, stream=None):
         """Mixed point/range stream (idx_batch_mixed).  Returns (rowid[m]
         int32, range_offsets[m+1] int64, range_rowids[total] int32)."""
-        for t, nm in ((lo, "lo"), (hi, "hi"), (kind, "kind"), (offsets, "offsets")):
-            _dev(t, nm)
+        _keys_of(lo, "lo", self.key_bits)
+        _keys_of(hi, "hi", self.key_bits)
+        _dev(kind, "kind")
         if kind.dtype != torch.uint8:
             raise TypeError("kind must be uint8")
         m = len(lo)
+        if len(hi) != m or len(kind) != m:
+            raise ValueError("lo, hi and kind differ in length")
+        _offsets_of(offsets, "offsets", self.count)
+        self._check_total(offsets, m, exact=True)
         out = torch.empty(m, dtype=torch.int32, device=lo.device)
         offs = torch.empty(m + 1, dtype=torch.int64, device=lo.device)
         total = ctypes.c_uint64(0)

@@ -159,6 +159,8 @@ def choose(n: int, key_bits: int, layout: str | None = None, table: dict | None 
             and (layout is None or e["layout"] == layout)]
     if not ents:
         lay = layout or "eks"
+        if lay == "learned":
+            return lay, 1, False, {"leaves": max(1, min(1 << 22, n // 16))}
         return lay, {"bs": 1, "ebs": 2, "eks": 9}[lay], False, {}
 
     def dist(e):

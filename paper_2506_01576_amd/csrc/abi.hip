@@ -334,6 +334,7 @@ int idx_range(idx_handle h, const void *lo, const void *hi, uint64_t m, uint64_t
 
 int idx_destroy(idx_handle h) {
     if (!h) return IDX_OK;
+    if (h->batch_refs) return IDX_ERR_ARG;  // a batch still reads its buffers
     // Work still queued on the last stream may read the buffers.
     (void)hipStreamSynchronize(h->last_stream);
     (void)hipGetLastError();
@@ -371,7 +372,7 @@ int idx_export(idx_handle h, void *keys_out, uint32_t *rowids_out, idx_stream st
 }
 
 int idx_learn(idx_handle h, uint32_t leaves, uint32_t epochs, uint32_t feature, idx_stream stream) {
-    if (!h) return IDX_ERR_ARG;
+    if (!h || h->batch_refs) return IDX_ERR_ARG;
     h->last_stream = (hipStream_t)stream;
     return learn(h, leaves, epochs, feature, (hipStream_t)stream);
 }
@@ -379,10 +380,9 @@ int idx_learn(idx_handle h, uint32_t leaves, uint32_t epochs, uint32_t feature, 
 int idx_learn_batch(const idx_handle *indexes, uint32_t count, const uint32_t *leaves, uint32_t epochs,
                     uint32_t feature, idx_stream stream) {
     if (!indexes || count == 0) return IDX_ERR_ARG;
-    for (uint32_t i = 0; i < count; ++i) {
-        if (!indexes[i]) return IDX_ERR_ARG;
-        indexes[i]->last_stream = (hipStream_t)stream;
-    }
+    for (uint32_t i = 0; i < count; ++i)
+        if (!indexes[i] || indexes[i]->batch_refs) return IDX_ERR_ARG;
+    for (uint32_t i = 0; i < count; ++i) indexes[i]->last_stream = (hipStream_t)stream;
     return learn_batch(indexes, count, leaves, epochs, feature, (hipStream_t)stream);
 }
 
@@ -398,7 +398,7 @@ int idx_learn_export(idx_handle h, void *leaves_out, idx_stream stream) {
 }
 
 int idx_unlearn(idx_handle h) {
-    if (!h) return IDX_ERR_ARG;
+    if (!h || h->batch_refs) return IDX_ERR_ARG;
     drop_model(h, h->last_stream);
     return IDX_OK;
 }
@@ -428,6 +428,8 @@ int idx_set_params(idx_handle h, const idx_lookup_params *p) {
     idx_lookup_params r{};
     const int rc = resolve_params(h, p, &r);
     if (rc != IDX_OK) return rc;
+    // the batch descriptors holding h copied its use of the model and its early exit
+    if (h->batch_refs && (r.model != h->params.model || r.early_exit != h->params.early_exit)) return IDX_ERR_ARG;
     h->params = r;
     return IDX_OK;
 }

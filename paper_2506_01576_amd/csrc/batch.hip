@@ -499,6 +499,7 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
 }  // namespace idx
 
 struct idx_batch {
+    std::vector<idx_index *> members;  // each holds one batch reference for this batch
     idx::Desc *descs = nullptr;  // device
     idx::Geo *geos = nullptr;    // device, one per index (tree geometry for range lookups)
     uint32_t count = 0;
@@ -615,6 +616,15 @@ int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream strea
     if (e == hipSuccess) e = hipMemcpyAsync(b->geos, geos.data(), sizeof(Geo) * count, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) {
+        try {
+            b->members.assign(indexes, indexes + count);
+        } catch (...) {
+            e = hipErrorOutOfMemory;
+        }
+    }
+    if (e == hipSuccess) {
+        // the descriptors point at the members' buffers: pin them
+        for (idx_index *h : b->members) ++h->batch_refs;
         *out = b;
         return IDX_OK;
     }
@@ -730,6 +740,7 @@ int idx_batch_destroy(idx_batch_t b) {
     if (b->geos) (void)hipFree(b->geos);
     if (b->descs) (void)hipFree(b->descs);
     (void)hipGetLastError();
+    for (idx_index *h : b->members) --h->batch_refs;
     delete b;
     return IDX_OK;
 }

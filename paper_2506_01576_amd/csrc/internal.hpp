@@ -72,6 +72,10 @@ struct idx_index {
     idx::LearnedModel *learned = nullptr;  // attached rank model (BS layout only)
     void *split = nullptr;       // rank-bucket splitter keys for partitioned lookups
     uint32_t split_buckets = 0;  // buckets those splitters define (0 = none built)
+    // Batches (idx_batch_create) holding this handle: their descriptors point
+    // at its layout and model buffers, so while any holds it the handle may
+    // not be destroyed, retrained or have its model dropped.
+    uint32_t batch_refs = 0;
 };
 
 namespace idx {
@@ -131,6 +135,11 @@ int exclusive_scan_u64(uint64_t *v, uint64_t m, uint64_t *partial, hipStream_t s
 uint64_t scan_partials_for(uint64_t m);
 int range_lookup(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
                  uint64_t capacity, uint64_t *total, hipStream_t s);
+// The same with the call's scratch (range_scratch_bytes(m) bytes, 256-byte
+// aligned) given by the caller; nullptr = from the handle's allocator.
+int range_lookup_in(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
+                    uint64_t capacity, uint64_t *total, void *scratch, hipStream_t s);
+size_t range_scratch_bytes(uint64_t m);
 
 // ---- learned.hip ------------------------------------------------------------
 int learn(idx_index *h, uint32_t leaves, uint32_t epochs, uint32_t feature, hipStream_t s);

@@ -33,6 +33,7 @@ struct RangeArgs {
     uint64_t *__restrict__ offsets;
     uint32_t *__restrict__ first_rank;
     uint32_t *__restrict__ out;
+    uint32_t handover;  // level matches after which a lane hands its scan to the wave
 };
 
 // Rank of the first key >= x.
@@ -188,11 +189,11 @@ __global__ __launch_bounds__(256) void k_range_fill_eyt(RangeArgs<K, AOS> a) {
     if (cnt > 0) {
         if constexpr (!AOS) {
             if (scan_vec_ok(a.G, a.off, sizeof(K), false))
-                paused = eyt_scan_lane_vec(a.L.k, a.L.r, a.G, L, U, r0, cnt, a.out + o, st);
+                paused = eyt_scan_lane_vec(a.L.k, a.L.r, a.G, L, U, r0, cnt, a.out + o, st, a.handover);
             else
-                paused = eyt_scan_lane(a.L, a.G, a.off, L, U, r0, cnt, a.out + o, st);
+                paused = eyt_scan_lane(a.L, a.G, a.off, L, U, r0, cnt, a.out + o, st, a.handover);
         } else {
-            paused = eyt_scan_lane(a.L, a.G, a.off, L, U, r0, cnt, a.out + o, st);
+            paused = eyt_scan_lane(a.L, a.G, a.off, L, U, r0, cnt, a.out + o, st, a.handover);
         }
     }
     // every lane of the wave reaches this point: continue paused scans together
@@ -315,7 +316,7 @@ int exclusive_scan(uint64_t *v, uint64_t m, uint64_t *partial, hipStream_t s) {
 
 template <typename K, bool AOS>
 int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
-            uint64_t capacity, uint64_t *total, hipStream_t s) {
+            uint64_t capacity, uint64_t *total, char *given, hipStream_t s) {
     RangeArgs<K, AOS> a{};
     a.L = make_load<K, AOS>(h);
     a.G = h->geo;
@@ -326,9 +327,9 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
     a.m = m;
     a.offsets = offsets;
     a.out = out;
-    const uint64_t tiles = (m + SC_TILE - 1) / SC_TILE;
+    a.handover = h->params.range_scan == 2 ? kNoHandover : kHandover;
     const size_t rank_bytes = ((m * 4 + 255) / 256) * 256;
-    char *scratch = (char *)h->alloc.get(rank_bytes + tiles * 8 + 256, s);
+    char *scratch = given ? given : (char *)h->alloc.get(range_scratch_bytes(m), s);
     if (!scratch) return IDX_ERR_NOMEM;
     a.first_rank = (uint32_t *)scratch;
     uint64_t *partial = (uint64_t *)(scratch + rank_bytes);
@@ -368,25 +369,39 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
         }
         if (hipGetLastError() != hipSuccess) rc = IDX_ERR_HIP;
     } while (0);
-    h->alloc.put(scratch, s);
+    if (!given) h->alloc.put(scratch, s);
     return rc;
 }
 
+__global__ void k_zero_u64(uint64_t *p) { *p = 0; }
+
 }  // namespace
 
-int range_lookup(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
-                 uint64_t capacity, uint64_t *total, hipStream_t s) {
+size_t range_scratch_bytes(uint64_t m) {
+    const uint64_t tiles = (m + SC_TILE - 1) / SC_TILE;
+    return ((m * 4 + 255) / 256) * 256 + tiles * 8 + 256;
+}
+
+int range_lookup_in(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
+                    uint64_t capacity, uint64_t *total, void *scratch, hipStream_t s) {
     if (m == 0) {
-        // offsets[0] = 0
-        IDX_HIP(hipMemsetAsync(offsets, 0, sizeof(uint64_t), s));
+        // offsets[0] = 0 (a kernel, not a memset node, so the call stays capturable)
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, offsets);
+        IDX_LAUNCH_CHECK();
         if (total) *total = 0;
         return IDX_OK;
     }
+    char *sc = (char *)scratch;
     if (h->u64)
-        return h->aos ? range_t<uint64_t, true>(h, lo, hi, m, offsets, out, capacity, total, s)
-                      : range_t<uint64_t, false>(h, lo, hi, m, offsets, out, capacity, total, s);
-    return h->aos ? range_t<uint32_t, true>(h, lo, hi, m, offsets, out, capacity, total, s)
-                  : range_t<uint32_t, false>(h, lo, hi, m, offsets, out, capacity, total, s);
+        return h->aos ? range_t<uint64_t, true>(h, lo, hi, m, offsets, out, capacity, total, sc, s)
+                      : range_t<uint64_t, false>(h, lo, hi, m, offsets, out, capacity, total, sc, s);
+    return h->aos ? range_t<uint32_t, true>(h, lo, hi, m, offsets, out, capacity, total, sc, s)
+                  : range_t<uint32_t, false>(h, lo, hi, m, offsets, out, capacity, total, sc, s);
+}
+
+int range_lookup(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
+                 uint64_t capacity, uint64_t *total, hipStream_t s) {
+    return range_lookup_in(h, lo, hi, m, offsets, out, capacity, total, nullptr, s);
 }
 
 int exclusive_scan_u64(uint64_t *v, uint64_t m, uint64_t *partial, hipStream_t s) {

@@ -8,8 +8,8 @@
 // slot_rank(t) - (rank of lo's lower bound) of the range's output, which
 // puts the row IDs in key order.
 //
-// Each lane first scans its own range alone.  When it meets kWave matches on
-// one level it pauses (by the property noted in Section 5.1, every deeper
+// Each lane first scans its own range alone.  When it meets kHandover (one
+// wave's width) matches on one level it pauses (by the property noted in Section 5.1, every deeper
 // level then holds more matches still), and once every lane of the wave has
 // finished or paused, the wave takes over the paused scans one at a time:
 // all 64 lanes read 64 consecutive entries of a level per step, and the
@@ -43,12 +43,18 @@ struct ScanState {
     uint32_t j;
 };
 
+// Matches on one level after which a lane hands its scan to the wave; a
+// lane that never hands over (the single-lane scan) uses kNoHandover.
+constexpr uint32_t kHandover = kWave;
+constexpr uint32_t kNoHandover = 0xFFFFFFFFu;
+
 // Single-lane level scan of [lo, hi] (first rank r0, cnt matches, output at
 // out).  Keys and row IDs of level-order slot t are at layout slot off + t.
-// Returns true when it paused (state in st) with kWave matches on a level.
+// Returns true when it paused (state in st) with `handover` matches on a level.
 template <typename K, bool AOS>
 __device__ __forceinline__ bool eyt_scan_lane(const Load<K, AOS> &L, const Geo &G, uint64_t off, K lo, K hi,
-                                              uint64_t r0, uint64_t cnt, uint32_t *__restrict__ out, ScanState &st) {
+                                              uint64_t r0, uint64_t cnt, uint32_t *__restrict__ out, ScanState &st,
+                                              uint32_t handover = kHandover) {
     const uint64_t n = G.n;
     const uint32_t g = G.g, kf = G.k;
     uint64_t c = 0;
@@ -64,7 +70,7 @@ __device__ __forceinline__ bool eyt_scan_lane(const Load<K, AOS> &L, const Geo &
             if (L.key(off + t) > hi) break;
             const uint64_t d = slot_rank_on(G, t, lvl) - r0;  // position in key order
             if (d < cnt) out[d] = L.row(off + t);
-            if (++seen == (uint32_t)kWave) {
+            if (++seen == handover) {
                 st = ScanState{c, t + 1, lvl, j};
                 return true;
             }
@@ -125,7 +131,8 @@ __device__ __forceinline__ uint32_t node_below(const K *kk, uint32_t valid, K x)
 template <typename K>
 __device__ __forceinline__ bool eyt_scan_lane_vec(const K *__restrict__ keys, const uint32_t *__restrict__ rows,
                                                   const Geo &G, K lo, K hi, uint64_t r0, uint64_t cnt,
-                                                  uint32_t *__restrict__ out, ScanState &st) {
+                                                  uint32_t *__restrict__ out, ScanState &st,
+                                                  uint32_t handover = kHandover) {
     constexpr int NK = kScanNodeBytes / sizeof(K);
     constexpr int NR = kScanNodeBytes / sizeof(K) / 4;  // 16-byte row chunks of the largest node
     const uint64_t n = G.n;
@@ -158,7 +165,7 @@ __device__ __forceinline__ bool eyt_scan_lane_vec(const K *__restrict__ keys, co
 #pragma unroll
                 for (int e = 0; e < NK; ++e) {
                     if ((uint32_t)e < from || (uint32_t)e >= upto) continue;
-                    if (seen == (uint32_t)kWave) {
+                    if (seen == handover) {
                         st = ScanState{c, nb + (uint64_t)e, lvl, j};
                         return true;
                     }

@@ -124,3 +124,42 @@ def test_batch_empty_query_set():
             bt.point(q, off, out)
             bt.point(q, off, out, graph=True)
             torch.cuda.synchronize()
+
+
+def test_batch_holds_its_members():
+    """While a batch holds an index, destroying, retraining or untraining it
+    is refused with IDX_ERR_ARG and changes nothing (the batch's descriptors
+    point at its buffers), and so is a parameter change that the descriptors
+    copied; after the batch is closed the same calls succeed."""
+    n, m = 5000, 3000
+    keys, rows = gen.unique_keys(11, n, 64, 63)
+    q, expect = gen.point_queries(11, n, m, 0.8, 64, 63)
+    dq, de = to_dev(q), to_dev(expect)
+    off = torch.tensor([0, m], dtype=torch.int64, device="cuda")
+    a = idx.Index(to_dev(keys), to_dev(rows), "bs")
+    e = idx.Index(to_dev(keys), to_dev(rows), "eks", k=9)
+    a.learn(64, 2)
+    before = a.learn_export().clone()
+    bt = idx.Batch([a])
+    bt2 = idx.Batch([e, a])  # a handle may belong to two batches
+    for call in (lambda: a.learn(32, 2), a.unlearn, a.close, lambda: idx.learn_batch([a], [16]),
+                 lambda: a.set_params(model=2), e.close, lambda: e.set_params(early_exit=2)):
+        with pytest.raises(idx.IdxError) as ei:
+            call()
+        assert ei.value.status == idx.IDX_ERR_ARG
+    assert a._h is not None and e._h is not None
+    assert torch.equal(a.learn_export(), before)
+    a.set_params(per_lane=8)  # a parameter the descriptors do not copy
+    got = bt.point(dq, off)
+    got2 = bt2.point(torch.cat([dq, dq]), torch.tensor([0, m, 2 * m], dtype=torch.int64, device="cuda"))
+    torch.cuda.synchronize()
+    assert torch.equal(got, de) and torch.equal(got2, torch.cat([de, de]))
+    bt.close()
+    with pytest.raises(idx.IdxError):
+        a.unlearn()  # still held by the second batch
+    bt2.close()
+    a.unlearn()
+    a.learn(32, 2)
+    assert torch.equal(a.point(dq), de)
+    a.close()
+    e.close()

@@ -87,6 +87,13 @@ def test_learned_lookup_parity(kind, leaves, epochs, feature, aos):
             got = rows_host(ix.point(to_dev(q)))
             bad = np.nonzero(got != want)[0]
             assert len(bad) == 0, f"R={R}: {len(bad)} mismatches, first q={q[bad[0]]}"
+        # the bound invariant: every build key's rank lies inside its leaf's
+        # window, shown by looking up all n build keys (a window that missed
+        # a key's lower-bound rank would answer a miss or another row ID)
+        all_want = oracle.point(sk, sr, keys, nthreads=4)
+        all_got = rows_host(ix.point(to_dev(keys)))
+        bad = np.nonzero(all_got != all_want)[0]
+        assert len(bad) == 0, f"{len(bad)} build keys not found through the model, first {keys[bad[0]]}"
         # ranges through the model
         L, U, _ = gen.ranges(3, keys, 3001, 1, 64)
         L = np.concatenate([L, q[:500]]).astype(keys.dtype)
@@ -112,6 +119,7 @@ def test_learned_tiny_sets():
             with idx.Index(to_dev(keys), to_dev(rows), layout="bs", aos=aos) as ix:
                 ix.learn(16, 2, AUTO)
                 assert np.array_equal(rows_host(ix.point(to_dev(q))), oracle.point(sk, sr, q))
+                assert np.array_equal(rows_host(ix.point(to_dev(keys))), oracle.point(sk, sr, keys))
 
 
 @pytest.mark.parametrize("aos", [True, "padded"])
