@@ -1116,12 +1116,13 @@ def main():
         torch.cuda.empty_cache()
         from paper_2506_01576_amd import autotune as _at
         table = _at.load_table()
+        batch_records = None
         if args.sweep:
-            batch_sweep = _at.tune_batch(gen, 32, log=log)
+            batch_sweep, batch_records = _at.tune_batch(gen, 32, log=log)
             table = _at.record_batch(table, 32, batch_sweep)
         batched = run_batched(args, idx, gen, np, torch, dev, log, table)
         if args.sweep:
-            batched["class_sweep"] = table.get("batch")
+            batched["class_sweep"] = batch_records
     skewed = None
     if not args.no_skewed:
         torch.cuda.empty_cache()

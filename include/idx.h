@@ -402,15 +402,25 @@ typedef struct idx_batch *idx_batch_t;
 
 /*
  * idx_batch_create -- gather `count` indexes (same key width, SoA layouts;
- * any of BS, EBS, EKS, or BS with a learned model) into one batch.  The
- * batch's device descriptors point at the members' layout and model buffers,
- * so until idx_batch_destroy every member is held: on a held handle
+ * any of BS, EBS, EKS, or BS with a learned model) into one batch.  Each
+ * member's descriptor copies four of its lookup parameters (idx_set_params),
+ * so the autotuner can choose them per size class:
+ *   model       whether its learned model is used;
+ *   early_exit  the EKS early exit on an equal key;
+ *   group       EKS lanes per lookup: 1 = one lane reads the whole node
+ *               (16-byte loads when nodes are 16-byte aligned), >= k - 1 =
+ *               one pivot per lane, fewer = one 16-byte chunk per lane;
+ *   lds_levels  top levels served from LDS (cache pinning, Section 7.3): a
+ *               workgroup whose chunk of lookups belongs to one member copies
+ *               that member's pin table into LDS first (not for the learned
+ *               form); the launch reserves LDS for the largest table.
+ * The batch's device descriptors point at the members' layout, pin and model
+ * buffers, so until idx_batch_destroy every member is held: on a held handle
  * idx_destroy, idx_learn, idx_unlearn and idx_learn_batch return IDX_ERR_ARG
  * and change nothing, and idx_set_params returns IDX_ERR_ARG for a parameter
- * set that changes the use of the model or the EKS early exit (the two
- * parameters the descriptors copy).  A handle may belong to several batches.
- * Synchronises `stream`.  Errors: IDX_ERR_ARG (null, mixed key widths, AoS
- * layout), IDX_ERR_NOMEM.
+ * set that changes any of the four copied parameters.  A handle may belong to
+ * several batches.  Synchronises `stream`.  Errors: IDX_ERR_ARG (null, mixed
+ * key widths, AoS layout), IDX_ERR_NOMEM.
  */
 int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream stream, idx_batch_t *out);
 
@@ -419,6 +429,9 @@ int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream strea
  * persistent launch (the static scheduling of Section 7.2 applied across
  * indexes).  Index i's queries are queries[offsets[i] .. offsets[i+1]) and
  * its answers land at the same positions of out_rowid (rowid or IDX_MISS).
+ * Workgroups walk chunks of consecutive queries; within a chunk of one
+ * member every lane advances four lookups together (their dependent loads in
+ * flight at once), in that member's form and parameters.
  *
  *   queries    device array of offsets[count] keys
  *   offsets    device array of count + 1 non-decreasing uint64, offsets[0] = 0

@@ -174,30 +174,67 @@ def choose(n: int, key_bits: int, layout: str | None = None, table: dict | None 
 
 
 # --------------------------------------------------------------- batched
-# Forms the batched launch supports (per-lane descents): (layout, k, learned
-# leaves per key or 0).
-BATCH_FORMS = [("bs", 1, 0), ("ebs", 2, 0), ("eks", 5, 0), ("eks", 9, 0), ("eks", 17, 0), ("bs", 1, 64)]
+# Forms the batched launch supports: (layout, k, learned keys per leaf or 0,
+# lookup parameters the batch takes from each member: "group" = EKS lanes
+# per lookup (1 = whole node per lane; >= k-1 = one pivot per lane; fewer =
+# one 16-byte chunk per lane), "lds_levels" = top levels pinned in LDS, cut to
+# what the member's size allows).
+BATCH_FORMS = [
+    ("bs", 1, 0, {}), ("bs", 1, 0, {"lds_levels": 10}),
+    ("ebs", 2, 0, {}), ("ebs", 2, 0, {"lds_levels": 10}),
+    ("eks", 5, 0, {"group": 1}), ("eks", 5, 0, {"group": 4}), ("eks", 5, 0, {"group": 1, "lds_levels": 4}),
+    ("eks", 9, 0, {"group": 1}), ("eks", 9, 0, {"group": 8}), ("eks", 9, 0, {"group": 2}),
+    ("eks", 9, 0, {"group": 1, "lds_levels": 3}),
+    ("eks", 17, 0, {"group": 1}), ("eks", 17, 0, {"group": 16}), ("eks", 17, 0, {"group": 4}),
+    ("eks", 17, 0, {"group": 1, "lds_levels": 2}),
+    ("bs", 1, 64, {}), ("bs", 1, 16, {}),
+]
 BATCH_CLASSES = [(6, 8), (9, 11), (12, 14), (15, 17), (18, 20), (21, 22)]
 
 
+def _form(form):
+    """(layout, k, keys per leaf, params) from a table or list entry (older
+    three-field entries carry no parameters)."""
+    if isinstance(form, dict):
+        return form["layout"], form["k"], form["keys_per_leaf"], dict(form.get("params", {}))
+    if len(form) == 3:
+        return form[0], form[1], form[2], {}
+    return form[0], form[1], form[2], dict(form[3])
+
+
 def build_form(keys: torch.Tensor, rows: torch.Tensor, form) -> Index:
-    """Build one index in a batch form (layout, k, keys-per-leaf or 0)."""
-    layout, k, per_leaf = form
+    """Build one index in a batch form and set the lookup parameters the
+    batch takes from it; pinned levels are cut to what the index allows."""
+    layout, k, per_leaf, params = _form(form)
     ix = Index(keys, rows, layout=layout, k=k)
     if per_leaf:
         ix.learn(max(1, len(keys) // per_leaf), 2)
+    if params:
+        lev = params.get("lds_levels", 0)
+        while True:
+            try:
+                ix.set_params(**{**params, "lds_levels": lev})
+                break
+            except IdxError:
+                if lev == 0:
+                    ix.close()
+                    raise
+                lev -= 1
     return ix
 
 
 def tune_batch(gen_module, key_bits: int = 32, per_class: int = 48, queries_per_index: int = 1 << 13,
-               seed: int = 7, log=None):
+               seed: int = 7, forms=None, log=None):
     """For every size class, time the batched launch over `per_class`
-    indexes built in each candidate form; returns {class_lo: best record}."""
+    indexes built in each candidate form (layout, k, model, lanes per lookup,
+    pinned levels); returns ({class_lo: best record}, all records).  A form
+    whose answers differ from the generator's can never win."""
     from ._binding import Batch
     import numpy as np
 
-    best = {}
+    best, records = {}, []
     dev = torch.device("cuda")
+    forms = forms if forms is not None else BATCH_FORMS
     for lo, hi in BATCH_CLASSES:
         sizes = gen_module.log_uniform(seed + lo, 3, 1 << lo, 1 << hi, per_class)
         sets, qs, ex = [], [], []
@@ -214,31 +251,38 @@ def tune_batch(gen_module, key_bits: int = 32, per_class: int = 48, queries_per_
         off[1:] = np.cumsum([len(q) for q in qs])
         doff = torch.from_numpy(off).to(dev)
         out = torch.empty(len(dq), dtype=torch.int32, device=dev)
-        for form in BATCH_FORMS:
+        for form in forms:
+            layout, k, per_leaf, params = _form(form)
             idxs = [build_form(torch.from_numpy(kh.view(view)).to(dev), torch.from_numpy(rh.view(np.int32)).to(dev),
                                form) for kh, rh in sets]
+            used = idxs[0].params()
             with Batch(idxs) as bt:
+                out.fill_(-1)
                 bt.point(dq, doff, out)
                 torch.cuda.synchronize()
                 exact = bool(torch.equal(out, de))
-                a = torch.cuda.Event(enable_timing=True)
-                b = torch.cuda.Event(enable_timing=True)
-                a.record()
+                ts = []
                 for _ in range(5):
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    a.record()
                     bt.point(dq, doff, out)
-                b.record()
-                b.synchronize()
-                ms = a.elapsed_time(b) / 5
+                    b.record()
+                    b.synchronize()
+                    ts.append(a.elapsed_time(b))
+                ms = sorted(ts)[len(ts) // 2]
             for ix in idxs:
                 ix.close()
-            rec = {"log2n_lo": lo, "log2n_hi": hi, "layout": form[0], "k": form[1], "keys_per_leaf": form[2],
+            rec = {"log2n_lo": lo, "log2n_hi": hi, "layout": layout, "k": k, "keys_per_leaf": per_leaf,
+                   "params": {f: used[f] for f in ("group", "lds_levels") if f in params},
                    "ms": round(ms, 4), "lookups_per_s": len(dq) / ms * 1e3, "bit_exact": exact}
+            records.append(rec)
             if log:
-                log(f"batch class 2^{lo}-2^{hi} form {form}: {ms:.3f} ms {rec['lookups_per_s'] / 1e9:.2f} G/s "
-                    f"exact={exact}")
+                log(f"batch class 2^{lo}-2^{hi} {layout} k={k} leaf={per_leaf} {params}: {ms:.4f} ms "
+                    f"{rec['lookups_per_s'] / 1e9:.2f} G/s exact={exact}")
             if exact and (lo not in best or ms < best[lo]["ms"]):
                 best[lo] = rec
-    return best
+    return best, records
 
 
 def record_batch(table: dict, key_bits: int, best: dict):
@@ -249,17 +293,16 @@ def record_batch(table: dict, key_bits: int, best: dict):
 
 
 def batch_form(n: int, key_bits: int, table: dict | None = None):
-    """(layout, k, keys per leaf) for an index of n keys in a batch."""
+    """(layout, k, keys per leaf, params) for an index of n keys in a batch."""
     table = table if table is not None else load_table()
     lg = max(0, math.ceil(math.log2(max(n, 1))))
     ents = [e for e in table.get("batch", []) if e["key_bits"] == key_bits]
     if not ents:
-        return ("ebs", 2, 0) if lg <= 16 else ("eks", 9, 0)
+        return ("ebs", 2, 0, {}) if lg <= 16 else ("eks", 9, 0, {})
 
     def dist(e):
         if e["log2n_lo"] <= lg <= e["log2n_hi"]:
             return 0
         return min(abs(lg - e["log2n_lo"]), abs(lg - e["log2n_hi"]))
 
-    e = min(ents, key=dist)
-    return e["layout"], e["k"], e["keys_per_leaf"]
+    return _form(min(ents, key=dist))

@@ -428,8 +428,12 @@ int idx_set_params(idx_handle h, const idx_lookup_params *p) {
     idx_lookup_params r{};
     const int rc = resolve_params(h, p, &r);
     if (rc != IDX_OK) return rc;
-    // the batch descriptors holding h copied its use of the model and its early exit
-    if (h->batch_refs && (r.model != h->params.model || r.early_exit != h->params.early_exit)) return IDX_ERR_ARG;
+    // the batch descriptors holding h copied its use of the model, its early
+    // exit, its EKS lanes per lookup and its pinned levels (and point at its
+    // pin table)
+    if (h->batch_refs && (r.model != h->params.model || r.early_exit != h->params.early_exit ||
+                          r.group != h->params.group || r.lds_levels != h->params.lds_levels))
+        return IDX_ERR_ARG;
     h->params = r;
     return IDX_OK;
 }

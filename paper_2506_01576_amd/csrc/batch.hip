@@ -38,13 +38,19 @@ struct __align__(16) Desc {
     uint64_t n;
     const LeafRec *leaves;  // learned form only
     uint32_t form, k, g, levels;
-    uint32_t m_full, early, gshift, pad0;
+    uint32_t m_full, early, gshift, lanes;  // lanes: EKS lanes per lookup (1 = whole node per lane)
+    const void *pin;        // top levels in LDS order (BS heap order; Eytzinger slot prefix), or null
+    uint32_t pin_levels;    // levels served from LDS (0 = none)
+    uint32_t pin_keys;      // entries of `pin`
     RootRec root;           // learned form only
+    uint32_t vec, pad1, pad2, pad3;  // vec: EKS nodes read with 16-byte loads
 };
-static_assert(sizeof(Desc) == 112, "descriptor layout");
+static_assert(sizeof(Desc) == 144, "descriptor layout");
 
 constexpr int BT = 256;     // threads per workgroup
 constexpr int BR = 4;       // lookups per lane
+constexpr uint64_t CW = (uint64_t)kWave * BR;  // queries per wave chunk
+constexpr uint64_t CB = (uint64_t)BT * BR;     // queries per workgroup chunk
 
 template <typename K>
 __device__ __forceinline__ uint32_t bs_find(const K *__restrict__ keys, const uint32_t *__restrict__ rows,
@@ -130,25 +136,405 @@ __device__ __forceinline__ uint32_t owner(const uint64_t *__restrict__ off, uint
     return lo;
 }
 
+// ---- one index per wave chunk: every lane holds up to BR lookups of the
+// chunk and advances them level by level together, so their dependent loads
+// are in flight at once (the per-lane chains of the single-index kernels).
+// `pin` (LDS) holds the index's top `pl` levels, or pl = 0.
+
+// BS: lockstep binary search to a window of at most 15 keys, then the
+// short-window scan (independent 16-byte loads counted in registers).
+template <typename K>
+__device__ __forceinline__ void wave_bs(const Desc &d, const K *__restrict__ q, uint32_t *__restrict__ out,
+                                        uint64_t c0, uint64_t c1, const K *pin, uint32_t pl) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const K *__restrict__ keys = (const K *)d.keys;
+    const uint64_t n = d.n;
+    K x[BR];
+    uint64_t base[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+        const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+        x[r] = p < c1 ? q[p] : K(0);
+        base[r] = 0;
+    }
+    if (n == 0) {
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+            if (p < c1) out[p] = kMiss;
+        }
+        return;
+    }
+    uint64_t len = n;
+    if (pl) {
+        uint32_t v[BR];
+#pragma unroll
+        for (int r = 0; r < BR; ++r) v[r] = 1;
+        for (uint32_t l = 0; l < pl; ++l) {
+            const uint64_t half = len >> 1;
+#pragma unroll
+            for (int r = 0; r < BR; ++r) {
+                const bool go = pin[v[r]] < x[r];
+                base[r] += go ? half : 0;
+                v[r] = 2 * v[r] + (go ? 1u : 0u);
+            }
+            len -= half;
+        }
+    }
+    while (len > 15) {
+        const uint64_t half = len >> 1;
+#pragma unroll
+        for (int r = 0; r < BR; ++r) base[r] = keys[base[r] + half] < x[r] ? base[r] + half : base[r];
+        len -= half;
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+        const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+        if (p >= c1) continue;
+        const uint64_t sl = (len + 1) < (n - base[r]) ? (len + 1) : (n - base[r]);
+        bool eq;
+        const uint32_t c = count_below<K, 16>(keys, base[r], (uint32_t)sl, x[r], eq);
+        out[p] = eq ? d.rows[base[r] + c] : kMiss;
+    }
+}
+
+// EBS: lockstep descent; the lower-bound slot is recovered from the final
+// position (drop the trailing right turns and the last left turn).
+template <typename K>
+__device__ __forceinline__ void wave_ebs(const Desc &d, const K *__restrict__ q, uint32_t *__restrict__ out,
+                                         uint64_t c0, uint64_t c1, const K *pin, uint32_t pl) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const K *__restrict__ keys = (const K *)d.keys;
+    const uint64_t n = d.n;
+    K x[BR], ck[BR];
+    uint64_t i[BR];
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+        const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+        x[r] = p < c1 ? q[p] : K(0);
+        ck[r] = ~K(0);
+        i[r] = 1;
+    }
+    uint32_t l = 0;
+    for (; l < pl; ++l) {
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            const K kk = pin[i[r]];
+            const bool right = kk < x[r];
+            ck[r] = right ? ck[r] : kk;
+            i[r] = 2 * i[r] + (right ? 1 : 0);
+        }
+    }
+    for (; l < d.m_full; ++l) {
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            const K kk = keys[i[r]];
+            const bool right = kk < x[r];
+            ck[r] = right ? ck[r] : kk;
+            i[r] = 2 * i[r] + (right ? 1 : 0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+        if (i[r] <= n) {
+            const K kk = keys[i[r]];
+            const bool right = kk < x[r];
+            ck[r] = right ? ck[r] : kk;
+            i[r] = 2 * i[r] + (right ? 1 : 0);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+        const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+        if (p >= c1) continue;
+        const uint64_t j = i[r] >> (__builtin_ctzll(~i[r]) + 1);
+        out[p] = (j != 0 && ck[r] == x[r]) ? d.rows[j] : kMiss;
+    }
+}
+
+// EKS (single): one lane per lookup reads a whole node of at most NK keys
+// (16-byte loads when the descriptor says the nodes allow it) and counts in
+// registers; R lookups per lane in lockstep (NK * R bounds the registers).
+template <typename K, int NK, int R>
+__device__ __forceinline__ void wave_eks_single(const Desc &d, const K *__restrict__ q, uint32_t *__restrict__ out,
+                                                uint64_t c0, uint64_t c1, const K *pin, uint32_t pl) {
+    constexpr int V = 16 / sizeof(K);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const K *__restrict__ keys = (const K *)d.keys;
+    const uint64_t n = d.n;
+    const uint32_t g = d.g, kf = d.k;
+    const uint64_t pin_end = pl ? (uint64_t)d.pin_keys : 0;  // slots below come from LDS
+    for (uint64_t p0 = c0; p0 < c1; p0 += (uint64_t)kWave * R) {
+        K x[R];
+        uint64_t c[R], cand[R];
+        bool ceq[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t p = p0 + (uint64_t)r * kWave + lane;
+            x[r] = p < c1 ? q[p] : K(0);
+            c[r] = p < c1 ? 0 : ~0ull;
+            cand[r] = 0;
+            ceq[r] = false;
+        }
+        for (uint32_t lvl = 0; lvl < d.levels; ++lvl) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (c[r] == ~0ull) continue;
+                const uint64_t i = c[r] * g;
+                const uint32_t nv = (n - i) < g ? (uint32_t)(n - i) : g;
+                K kk[NK];
+                if (i < pin_end) {
+#pragma unroll
+                    for (int e = 0; e < NK; ++e) kk[e] = (uint32_t)e < nv ? pin[i + e] : ~K(0);
+                } else if (d.vec) {
+                    // whole 16-byte chunks of the node; a partial last node's
+                    // chunks stay inside the padded allocation and are masked
+                    const uint4 *pp = (const uint4 *)(keys + i);
+#pragma unroll
+                    for (int v = 0; v < NK / V; ++v) {
+                        uint4 w = make_uint4(0u, 0u, 0u, 0u);
+                        if ((uint32_t)(v * V) < g) w = pp[v];
+                        if constexpr (sizeof(K) == 8) {
+                            kk[2 * v] = ((uint64_t)w.y << 32) | w.x;
+                            kk[2 * v + 1] = ((uint64_t)w.w << 32) | w.z;
+                        } else {
+                            kk[4 * v] = w.x;
+                            kk[4 * v + 1] = w.y;
+                            kk[4 * v + 2] = w.z;
+                            kk[4 * v + 3] = w.w;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < NK; ++e) kk[e] = (uint32_t)e < nv ? keys[i + e] : ~K(0);
+                }
+                uint32_t j = 0;
+                bool eq = false;
+#pragma unroll
+                for (int e = 0; e < NK; ++e) {
+                    const bool in = (uint32_t)e < nv;
+                    j += (in && kk[e] < x[r]) ? 1u : 0u;
+                    eq |= in && kk[e] == x[r];
+                }
+                if (j < nv) {
+                    cand[r] = i + j;
+                    ceq[r] = eq;
+                }
+                const uint64_t child = c[r] * kf + 1 + j;
+                c[r] = ((d.early && eq) || child * g >= n) ? ~0ull : child;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t p = p0 + (uint64_t)r * kWave + lane;
+            if (p < c1) out[p] = ceq[r] ? d.rows[cand[r]] : kMiss;
+        }
+    }
+}
+
+// EKS (group): GL = d.lanes lanes per lookup, each reading VL consecutive
+// pivots (VL = 1: one pivot per lane, GL >= k - 1; VL = 16 / sizeof(K): one
+// 16-byte chunk per lane); j = popcount of the group's ballot of pivot < x.
+template <typename K, int VL>
+__device__ __forceinline__ void wave_eks_group(const Desc &d, const K *__restrict__ q, uint32_t *__restrict__ out,
+                                               uint64_t c0, uint64_t c1, const K *pin, uint32_t pl) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t GL = d.lanes;
+    const uint32_t gpw = kWave / GL;  // lookups per wave per slot
+    const uint32_t sub = lane & (GL - 1), grp = lane / GL;
+    const uint64_t gmask = GL == kWave ? ~0ull : (((1ull << GL) - 1ull) << (grp * GL));
+    const K *__restrict__ keys = (const K *)d.keys;
+    const uint64_t n = d.n;
+    const uint32_t g = d.g, kf = d.k;
+    const uint32_t first = sub * VL;
+    const uint64_t pin_end = pl ? (uint64_t)d.pin_keys : 0;
+    constexpr int R = BR;
+    for (uint64_t p0 = c0; p0 < c1; p0 += (uint64_t)gpw * R) {
+        K x[R];
+        uint64_t c[R], cand[R];
+        bool ceq[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t p = p0 + (uint64_t)r * gpw + grp;
+            x[r] = p < c1 ? q[p] : K(0);
+            c[r] = p < c1 ? 0 : ~0ull;
+            cand[r] = 0;
+            ceq[r] = false;
+        }
+        for (uint32_t lvl = 0; lvl < d.levels; ++lvl) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const bool live = c[r] != ~0ull;
+                const uint64_t i = live ? c[r] * g : n;
+                const bool lane_live = live && first < g && i + first < n;
+                K kk[VL];
+#pragma unroll
+                for (int e = 0; e < VL; ++e) kk[e] = ~K(0);
+                if (lane_live) {
+                    const uint64_t s = i + first;
+                    if constexpr (VL == 1) {
+                        kk[0] = s < pin_end ? pin[s] : keys[s];
+                    } else {
+                        const uint4 w = s < pin_end ? *(const uint4 *)(pin + s) : *(const uint4 *)(keys + s);
+                        if constexpr (sizeof(K) == 8) {
+                            kk[0] = ((uint64_t)w.y << 32) | w.x;
+                            kk[1] = ((uint64_t)w.w << 32) | w.z;
+                        } else {
+                            kk[0] = w.x;
+                            kk[1] = w.y;
+                            kk[2] = w.z;
+                            kk[3] = w.w;
+                        }
+                    }
+                }
+                uint32_t j = 0;
+                bool eql = false;
+#pragma unroll
+                for (int e = 0; e < VL; ++e) {
+                    const bool valid = lane_live && first + e < g && i + first + e < n;
+                    j += (uint32_t)__popcll(__ballot(valid && kk[e] < x[r]) & gmask);
+                    eql |= valid && kk[e] == x[r];
+                }
+                const uint64_t eq = __ballot(eql) & gmask;
+                if (live) {
+                    const uint64_t nv = (n - i) < g ? (n - i) : g;
+                    if (j < nv) {
+                        cand[r] = i + j;
+                        ceq[r] = eq != 0;
+                    }
+                    const uint64_t child = c[r] * kf + 1 + j;
+                    c[r] = ((d.early && eq != 0) || child * g >= n) ? ~0ull : child;
+                }
+            }
+        }
+        if (sub == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t p = p0 + (uint64_t)r * gpw + grp;
+                if (p < c1) out[p] = ceq[r] ? d.rows[cand[r]] : kMiss;
+            }
+        }
+    }
+}
+
+// Learned: every lookup's root and leaf evaluation, then the window halving
+// while any window spans more than 15 keys, then the short-window scans, in
+// lockstep over the lane's lookups.
+template <typename K>
+__device__ __forceinline__ void wave_learned(const Desc &d, const K *__restrict__ q, uint32_t *__restrict__ out,
+                                             uint64_t c0, uint64_t c1) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const K *__restrict__ keys = (const K *)d.keys;
+    K x[BR];
+    uint32_t b[BR], len[BR];  // ranks: n < 2^32
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+        const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+        x[r] = p < c1 ? q[p] : K(0);
+        b[r] = 0;
+        len[r] = 0;
+        if (p < c1) {
+            uint64_t wb, wl;
+            learned_window(d.root, d.leaves, (uint64_t)x[r], wb, wl);
+            b[r] = (uint32_t)wb;
+            len[r] = (uint32_t)wl;
+        }
+    }
+    for (;;) {
+        bool more = false;
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            if (len[r] > 15) {
+                const uint32_t half = len[r] >> 1;
+                b[r] = keys[(uint64_t)b[r] + half - 1] < x[r] ? b[r] + half : b[r];
+                len[r] -= half;
+            }
+            more |= len[r] > 15;
+        }
+        if (!more) break;
+    }
+#pragma unroll
+    for (int r = 0; r < BR; ++r) {
+        const uint64_t p = c0 + (uint64_t)r * kWave + lane;
+        if (p >= c1) continue;
+        bool eq;
+        const uint32_t c = count_below<K, 16>(keys, b[r], len[r], x[r], eq);
+        out[p] = eq ? d.rows[(uint64_t)b[r] + c] : kMiss;
+    }
+}
+
+template <typename K>
+__device__ __forceinline__ void wave_one_index(const Desc &d, const K *__restrict__ q, uint32_t *__restrict__ out,
+                                               uint64_t c0, uint64_t c1, const K *pin, uint32_t pl) {
+    switch (d.form) {
+        case F_BS: wave_bs<K>(d, q, out, c0, c1, pin, pl); return;
+        case F_EBS: wave_ebs<K>(d, q, out, c0, c1, pin, pl); return;
+        case F_EKS:
+            if (d.lanes > 1) {
+                if (d.lanes >= d.g) wave_eks_group<K, 1>(d, q, out, c0, c1, pin, pl);
+                else wave_eks_group<K, 16 / sizeof(K)>(d, q, out, c0, c1, pin, pl);
+            } else if (d.g <= 4) {
+                wave_eks_single<K, 4, 4>(d, q, out, c0, c1, pin, pl);
+            } else if (d.g <= 8) {
+                wave_eks_single<K, 8, 4>(d, q, out, c0, c1, pin, pl);
+            } else if (d.g <= 16) {
+                wave_eks_single<K, 16, 2>(d, q, out, c0, c1, pin, pl);
+            } else {
+                wave_eks_single<K, 32, 1>(d, q, out, c0, c1, pin, pl);
+            }
+            return;
+        default: wave_learned<K>(d, q, out, c0, c1); return;
+    }
+}
+
+// The persistent walk: each workgroup takes chunks of CB consecutive flat
+// query positions, CW per wave.  A chunk inside one index (the usual case:
+// the large batches hold most queries) runs that index's form in lockstep,
+// with its top levels copied to LDS once per workgroup chunk when the member
+// asked for cache pinning; a wave chunk spanning several (small) indexes
+// runs each lookup on its own.
 template <typename K>
 __global__ __launch_bounds__(BT) void k_batch_point(const Desc *__restrict__ descs, uint32_t count,
                                                     const uint64_t *__restrict__ off, const K *__restrict__ q,
                                                     uint32_t *__restrict__ out) {
+    extern __shared__ __align__(16) char smem[];
+    K *s_pin = (K *)smem;
     const uint64_t total = off[count];
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint64_t wave_global = ((uint64_t)blockIdx.x * BT + threadIdx.x) / kWave;
-    const uint64_t waves = (uint64_t)gridDim.x * (BT / kWave);
-    constexpr uint64_t CH = (uint64_t)kWave * BR;  // queries per wave chunk
-    for (uint64_t c0 = wave_global * CH; c0 < total; c0 += waves * CH) {
-        const uint64_t c1 = c0 + CH < total ? c0 + CH : total;
-        // wave-uniform owners of the chunk's first and last query
-        const uint32_t i0 = owner(off, 0, count, c0);
-        const uint32_t i1 = owner(off, i0, count, c1 - 1);
+    const uint32_t wave = threadIdx.x / kWave;
+    uint32_t pinned = 0xFFFFFFFFu;  // member whose top levels s_pin holds (workgroup-uniform)
+    for (uint64_t b0 = (uint64_t)blockIdx.x * CB; b0 < total; b0 += (uint64_t)gridDim.x * CB) {
+        const uint64_t b1 = b0 + CB < total ? b0 + CB : total;
+        // workgroup-uniform owners of the chunk's first and last query
+        const uint32_t j0 = owner(off, 0, count, b0);
+        const uint32_t j1 = owner(off, j0, count, b1 - 1);
+        uint32_t pl = 0;
+        if (j0 == j1 && descs[j0].pin_levels) {
+            if (pinned != j0) {
+                const Desc &dp = descs[j0];
+                const K *src = (const K *)dp.pin;
+                __syncthreads();  // every wave is done with the previous member's levels
+                for (uint32_t e = threadIdx.x; e < dp.pin_keys; e += BT) s_pin[e] = src[e];
+                __syncthreads();
+                pinned = j0;
+            }
+            pl = descs[j0].pin_levels;
+        }
+        const uint64_t c0 = b0 + (uint64_t)wave * CW;
+        if (c0 >= b1) continue;
+        const uint64_t c1 = c0 + CW < b1 ? c0 + CW : b1;
+        const uint32_t i0 = j0 == j1 ? j0 : owner(off, j0, j1 + 1, c0);
+        const uint32_t i1 = j0 == j1 ? j0 : owner(off, i0, j1 + 1, c1 - 1);
+        if (i0 == i1) {
+            const Desc d = descs[i0];
+            wave_one_index<K>(d, q, out, c0, c1, s_pin, pl);
+            continue;
+        }
 #pragma unroll
         for (int r = 0; r < BR; ++r) {
             const uint64_t p = c0 + (uint64_t)r * kWave + lane;
             if (p >= c1) continue;
-            const uint32_t ii = (i0 == i1) ? i0 : owner(off, i0, i1 + 1, p);
+            const uint32_t ii = owner(off, i0, i1 + 1, p);
             const Desc d = descs[ii];
             const K x = q[p];
             const K *keys = (const K *)d.keys;
@@ -506,6 +892,7 @@ struct idx_batch {
     bool u64 = false;
     bool has_sorted = false;  // holds BS or learned indexes
     bool has_eyt = false;     // holds EBS or EKS indexes
+    size_t pin_bytes = 0;     // LDS of the largest member pin table (point launch)
     int cu_count = 256;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -522,11 +909,12 @@ namespace {
 int launch_batch(idx_batch *b, const void *q, const uint64_t *off, uint32_t *out, hipStream_t s) {
     // persistent grid: 8 workgroups of 4 waves per CU
     const uint32_t grid = (uint32_t)b->cu_count * 8;
+    const size_t lds = (b->pin_bytes + 15) & ~(size_t)15;
     if (b->u64)
-        hipLaunchKernelGGL(k_batch_point<uint64_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->count, off,
+        hipLaunchKernelGGL(k_batch_point<uint64_t>, dim3(grid), dim3(BT), lds, s, b->descs, b->count, off,
                            (const uint64_t *)q, out);
     else
-        hipLaunchKernelGGL(k_batch_point<uint32_t>, dim3(grid), dim3(BT), 0, s, b->descs, b->count, off,
+        hipLaunchKernelGGL(k_batch_point<uint32_t>, dim3(grid), dim3(BT), lds, s, b->descs, b->count, off,
                            (const uint32_t *)q, out);
     IDX_LAUNCH_CHECK();
     return IDX_OK;
@@ -558,7 +946,7 @@ int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream strea
         return IDX_ERR_NOMEM;
     }
     for (uint32_t i = 0; i < count; ++i) {
-        const idx_index *h = indexes[i];
+        idx_index *h = indexes[i];
         if (!h || h->u64 != u64 || h->aos) return IDX_ERR_ARG;
         Desc d{};
         d.keys = h->keys;
@@ -570,6 +958,17 @@ int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream strea
         d.m_full = h->geo.m;
         d.gshift = (uint32_t)h->geo.gshift;
         d.early = (h->unique && h->params.early_exit == 1) ? 1u : 0u;
+        // lookup parameters the batch takes from the member: EKS lanes per
+        // lookup, and the top levels pinned in LDS (its pin table)
+        d.lanes = h->layout == IDX_EKS ? h->params.group : 1u;
+        d.vec = (h->layout == IDX_EKS && scan_vec_ok(h->geo, 0, h->u64 ? 8 : 4, false)) ? 1u : 0u;
+        if (h->params.lds_levels && !(h->learned && h->params.model != 2)) {
+            const int rc = build_pin(h, h->params.lds_levels, (hipStream_t)stream);
+            if (rc != IDX_OK) return rc;
+            d.pin = h->pin;
+            d.pin_levels = h->params.lds_levels;
+            d.pin_keys = h->pin_keys;
+        }
         if (h->layout == IDX_BS) {
             d.form = F_BS;
             if (h->learned && h->params.model != 2) {
@@ -591,6 +990,8 @@ int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream strea
     for (uint32_t i = 0; i < count; ++i) {
         if (host[i].form == F_EBS || host[i].form == F_EKS) b->has_eyt = true;
         else b->has_sorted = true;
+        const size_t pb = (size_t)host[i].pin_keys * (u64 ? 8 : 4);
+        if (pb > b->pin_bytes) b->pin_bytes = pb;
     }
     hipStream_t s = (hipStream_t)stream;
     int dev = 0, cus = 0;

@@ -103,6 +103,72 @@ def test_batch_matches_loop_and_oracle(bits):
         ix.close()
 
 
+# forms with the lookup parameters the batch takes from each member: EKS
+# lanes per lookup (group) and LDS-pinned top levels (cut to what each
+# member's size allows)
+KNOB_FORMS = [("bs", 1, None, {}), ("bs", 1, None, {"lds_levels": 10}), ("ebs", 2, None, {"lds_levels": 8}),
+              ("eks", 5, None, {"group": 4}), ("eks", 5, None, {"group": 1, "lds_levels": 4}),
+              ("eks", 9, None, {"group": 8}), ("eks", 9, None, {"group": "vec"}),
+              ("eks", 9, None, {"group": 1, "lds_levels": 3}), ("eks", 17, None, {"group": 16, "lds_levels": 2}),
+              ("eks", 17, None, {"group": 1}), ("eks", 33, None, {"group": 1}), ("eks", 4, None, {"group": 4}),
+              ("eks", 4, None, {"group": 1, "lds_levels": 3}), ("eks", 65, None, {"group": 64}), ("bs", 1, 64, {})]
+
+
+def _set_knobs(ix, params, bits, k):
+    params = dict(params)
+    if params.get("group") == "vec":  # 16-byte pivot chunks per lane
+        params["group"] = max(1, (k - 1) // (16 // (bits // 8)))
+    lev = params.get("lds_levels", 0)
+    while True:
+        try:
+            ix.set_params(**{**params, "lds_levels": lev})
+            return
+        except idx.IdxError:
+            assert lev > 0, params
+            lev -= 1
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_batch_lanes_and_pinned_levels(bits):
+    """Indexes large enough that whole wave and workgroup chunks belong to
+    one index (the lockstep per-lane chains, lane groups and LDS-pinned
+    levels) mixed with small ones: every answer equals the oracle's, eager
+    and replayed."""
+    count = 90
+    sets, qs = make_batch(count, bits, seed=100 + bits, max_log2n=16, max_log2q=13)
+    idxs, used = [], set()
+    for i, (keys, rows) in enumerate(sets):
+        layout, k, learned, params = KNOB_FORMS[i % len(KNOB_FORMS)]
+        if learned and len(keys) == 0:
+            layout, learned, params = "bs", None, {}
+        ix = idx.Index(to_dev(keys), to_dev(rows), layout=layout, k=k)
+        if learned:
+            ix.learn(max(1, len(keys) // learned), 2)
+        if params and len(keys):
+            _set_knobs(ix, params, bits, k)
+            p = ix.params()
+            used.add((layout, k, p["group"], p["lds_levels"] > 0))
+        idxs.append(ix)
+    say(f"batch knobs ({bits}-bit): {sorted(used)}")
+    counts = np.array([len(q) for q in qs], dtype=np.uint64)
+    offsets = np.zeros(count + 1, dtype=np.uint64)
+    offsets[1:] = np.cumsum(counts)
+    allq = np.concatenate(qs)
+    dq, doff = to_dev(allq), to_dev(offsets)
+    want = np.concatenate([oracle.point(*oracle.stable_sort(*sets[i]), qs[i]) if len(qs[i]) else
+                           np.zeros(0, np.uint32) for i in range(count)])
+    with idx.Batch(idxs) as bt:
+        assert np.array_equal(rows_host(bt.point(dq, doff)), want)
+        out = torch.empty(len(allq), dtype=torch.int32, device="cuda")
+        for rep in range(3):
+            out.fill_(-7)
+            bt.point(dq, doff, out, graph=True)
+            torch.cuda.synchronize()
+            assert np.array_equal(rows_host(out), want), f"replay {rep}"
+    for ix in idxs:
+        ix.close()
+
+
 def test_batch_rejects_bad_sets():
     k32, r32 = gen.unique_keys(1, 100, 32)
     k64, r64 = gen.unique_keys(1, 100, 64)
@@ -143,7 +209,8 @@ def test_batch_holds_its_members():
     bt = idx.Batch([a])
     bt2 = idx.Batch([e, a])  # a handle may belong to two batches
     for call in (lambda: a.learn(32, 2), a.unlearn, a.close, lambda: idx.learn_batch([a], [16]),
-                 lambda: a.set_params(model=2), e.close, lambda: e.set_params(early_exit=2)):
+                 lambda: a.set_params(model=2), e.close, lambda: e.set_params(early_exit=2),
+                 lambda: e.set_params(group=8), lambda: e.set_params(lds_levels=2)):
         with pytest.raises(idx.IdxError) as ei:
             call()
         assert ei.value.status == idx.IDX_ERR_ARG
