@@ -63,6 +63,7 @@ typedef void *idx_stream;             /* hipStream_t */
 #define IDX_ERR_NOMEM (-3)          /* device allocation failed */
 #define IDX_ERR_HIP (-4)            /* a HIP runtime call or kernel launch failed */
 #define IDX_ERR_CAPACITY (-5)       /* range output does not fit the given capacity */
+#define IDX_ERR_SCRATCH (-6)        /* request larger than the fixed scratch of idx_range_noalloc */
 
 /* Largest supported number of build keys. */
 #define IDX_MAX_KEYS 0xFFFFFFFEull
@@ -199,6 +200,23 @@ int idx_point(idx_handle h, const void *queries, uint64_t m, uint32_t *out_rowid
  */
 int idx_range(idx_handle h, const void *lo, const void *hi, uint64_t m, uint64_t *out_offsets,
               uint32_t *out_rowids, uint64_t capacity, uint64_t *total, idx_stream stream);
+
+/*
+ * idx_range_noalloc -- idx_range for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, outputs, kernels and errors as
+ * idx_range; the call's scratch (4 bytes per range plus one 8-byte partial
+ * per 4096 ranges) comes from one statically sized device array instead of
+ * the handle's allocator, so no hipMalloc, hipFree or allocating library
+ * routine runs.  Each device holds its own array (about 32 MiB, kept until
+ * the process ends).  All calls on one device share it: calls that overlap
+ * on one device (concurrent streams or threads) race and must be ordered by
+ * the caller.  IDX_ERR_SCRATCH when m > IDX_NOALLOC_MAX_RANGES (nothing is
+ * enqueued).  Synchronises `stream` once, like idx_range.
+ */
+#define IDX_NOALLOC_MAX_RANGES (1ull << 23)
+int idx_range_noalloc(idx_handle h, const void *lo, const void *hi, uint64_t m, uint64_t *out_offsets,
+                      uint32_t *out_rowids, uint64_t capacity, uint64_t *total, idx_stream stream);
 
 /* idx_destroy -- free the handle and its device buffers (stream-ordered on
  * the stream of the last call that used the handle).  NULL is accepted.

@@ -24,6 +24,8 @@ IDX_ERR_RESERVED_ROWID = -2
 IDX_ERR_NOMEM = -3
 IDX_ERR_HIP = -4
 IDX_ERR_CAPACITY = -5
+IDX_ERR_SCRATCH = -6
+IDX_NOALLOC_MAX_RANGES = 1 << 23
 
 LAYOUTS = {"bs": IDX_BS, "ebs": IDX_EBS, "eks": IDX_EKS}
 
@@ -111,6 +113,7 @@ SIGNATURES = {
     "idx_relayout": (_I, [_P, _I, _U32, _U32, ctypes.POINTER(idx_allocator), _P, ctypes.POINTER(_P)]),
     "idx_point": (_I, [_P, _P, _U64, _P, _P]),
     "idx_range": (_I, [_P, _P, _P, _U64, _P, _P, _U64, ctypes.POINTER(_U64), _P]),
+    "idx_range_noalloc": (_I, [_P, _P, _P, _U64, _P, _P, _U64, ctypes.POINTER(_U64), _P]),
     "idx_destroy": (_I, [_P]),
     "idx_strerror": (ctypes.c_char_p, [_I]),
     "idx_last_hip_error": (_I, []),
@@ -352,6 +355,28 @@ class Index:
         _check(lib().idx_range(self._h, lo.data_ptr(), hi.data_ptr(), m, offsets.data_ptr(), out.data_ptr(),
                                capacity, ctypes.byref(total), s), "idx_range")
         return offsets, out[: total.value]
+
+    def range_noalloc(self, lo: torch.Tensor, hi: torch.Tensor, offsets: torch.Tensor,
+                      rowids: torch.Tensor | None = None, stream=None) -> int:
+        """Range lookups into caller-given outputs with no device allocation
+        (idx_range_noalloc): offsets int64[m + 1]; rowids a 32-bit tensor
+        whose length is the capacity, or None to count only.  At most
+        IDX_NOALLOC_MAX_RANGES ranges.  Returns the total number of matches."""
+        _keys_of(lo, "lo", self.key_bits)
+        _keys_of(hi, "hi", self.key_bits)
+        m = len(lo)
+        if len(hi) != m:
+            raise ValueError("lo and hi differ in length")
+        _offsets_of(offsets, "offsets", m)
+        cap = 0
+        if rowids is not None:
+            _out_u32(rowids, "rowids", 0)
+            cap = len(rowids)
+        total = ctypes.c_uint64(0)
+        _check(lib().idx_range_noalloc(self._h, lo.data_ptr(), hi.data_ptr(), m, offsets.data_ptr(),
+                                       rowids.data_ptr() if rowids is not None and cap else None, cap,
+                                       ctypes.byref(total), _stream(stream)), "idx_range_noalloc")
+        return total.value
 
     # -- introspection and tuning
     def info(self) -> dict:

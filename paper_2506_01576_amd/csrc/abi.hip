@@ -102,6 +102,7 @@ const char *idx_strerror(int status) {
         case IDX_ERR_NOMEM: return "device memory allocation failed";
         case IDX_ERR_HIP: return "HIP runtime or kernel launch error";
         case IDX_ERR_CAPACITY: return "range output exceeds the given capacity";
+        case IDX_ERR_SCRATCH: return "request exceeds the library's fixed scratch (IDX_NOALLOC_MAX_RANGES ranges)";
         default: return "unknown status";
     }
 }

@@ -139,7 +139,13 @@ int range_lookup(idx_index *h, const void *lo, const void *hi, uint64_t m, uint6
 // aligned) given by the caller; nullptr = from the handle's allocator.
 int range_lookup_in(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
                     uint64_t capacity, uint64_t *total, void *scratch, hipStream_t s);
-size_t range_scratch_bytes(uint64_t m);
+// Queries per tile of the u64 exclusive scan (one partial sum per tile).
+constexpr uint64_t kScanTile = 4096;
+// Scratch of one range call over m ranges: the first matching rank of every
+// range (u32, rounded up to 256 bytes), then one u64 partial per scan tile.
+constexpr size_t range_scratch_bytes(uint64_t m) {
+    return (size_t)(((m * 4 + 255) / 256) * 256 + ((m + kScanTile - 1) / kScanTile) * 8 + 256);
+}
 
 // ---- learned.hip ------------------------------------------------------------
 int learn(idx_index *h, uint32_t leaves, uint32_t epochs, uint32_t feature, hipStream_t s);

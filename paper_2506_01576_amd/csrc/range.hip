@@ -220,6 +220,7 @@ __global__ __launch_bounds__(256) void k_range_fill_eyt(RangeArgs<K, AOS> a) {
 constexpr int SC_THREADS = 256;
 constexpr int SC_ITEMS = 16;
 constexpr int SC_TILE = SC_THREADS * SC_ITEMS;
+static_assert(SC_TILE == kScanTile, "range_scratch_bytes sizes the scan partials by this tile");
 
 __device__ __forceinline__ uint64_t block_scan_u64(uint64_t v, uint64_t *s_wave, uint64_t *total) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -376,11 +377,6 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
 __global__ void k_zero_u64(uint64_t *p) { *p = 0; }
 
 }  // namespace
-
-size_t range_scratch_bytes(uint64_t m) {
-    const uint64_t tiles = (m + SC_TILE - 1) / SC_TILE;
-    return ((m * 4 + 255) / 256) * 256 + tiles * 8 + 256;
-}
 
 int range_lookup_in(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *offsets, uint32_t *out,
                     uint64_t capacity, uint64_t *total, void *scratch, hipStream_t s) {

@@ -1,0 +1,102 @@
+"""idx_range_noalloc (range lookups whose scratch is the library's static
+device array) against idx_range on the same handle: offsets and row IDs
+bit-identical, and equal to the oracle, on two calls in a row with the
+second smaller (the array keeps the first call's contents)."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import rows_host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+idx = pytest.importorskip("paper_2506_01576_amd")
+
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2506_01576_amd import _binding as B  # noqa: E402
+
+
+def _ranges(keys, m, max_width, seed):
+    """m ranges of 1..max_width build keys, plus an inverted range, one over
+    the whole key space and one between two adjacent keys."""
+    lo, hi, _ = gen.ranges(seed, keys, m, 1, max_width)
+    top = np.iinfo(keys.dtype).max
+    ordered = np.sort(keys)
+    lo[0], hi[0] = hi[0], lo[0]
+    if lo[0] == hi[0]:
+        hi[0] = lo[0] - 1
+    lo[1], hi[1] = 0, top
+    a, b = ordered[10], ordered[11]
+    lo[2], hi[2] = a + 1, b - 1 if b - a > 1 else a + 1
+    return lo, hi
+
+
+def _both(ix, lo, hi):
+    dlo, dhi = to_dev(lo), to_dev(hi)
+    off_a, rows_a = ix.range(dlo, dhi)
+    m = len(lo)
+    off_b = torch.empty(m + 1, dtype=torch.int64, device="cuda")
+    cap = int(off_a[-1].item())
+    rows_b = torch.empty(max(1, cap), dtype=torch.int32, device="cuda")
+    total = ix.range_noalloc(dlo, dhi, off_b, rows_b)
+    torch.cuda.synchronize()
+    return (off_a.cpu().numpy(), rows_host(rows_a)), (off_b.cpu().numpy(), rows_host(rows_b[:total])), total
+
+
+@pytest.mark.parametrize("layout,k,bits,learn", [("bs", 1, 64, False), ("eks", 9, 32, False),
+                                                 ("ebs", 2, 64, False), ("bs", 1, 64, True)])
+def test_noalloc_matches_idx_range(layout, k, bits, learn):
+    n = 30011
+    seed = gen.BASE_SEED + 77
+    keys, rows = gen.unique_keys(seed, n, bits)
+    sk, sr = oracle.stable_sort(keys, rows)
+    with idx.Index(to_dev(keys), to_dev(rows), layout=layout, k=k) as ix:
+        if learn:
+            ix.learn(256, 2)
+        # two calls in a row, the second smaller
+        for call, (m, width) in enumerate(((9000, 300), (1500, 40))):
+            lo, hi = _ranges(keys, m, width, seed + call)
+            (oa, ra), (ob, rb), total = _both(ix, lo, hi)
+            want_off, want_rows = oracle.range_lookup(sk, sr, lo, hi)
+            assert total == int(want_off[-1])
+            assert np.array_equal(ob.view(np.uint64), oa.view(np.uint64))
+            assert np.array_equal(rb, ra)
+            assert np.array_equal(ob.view(np.uint64), want_off)
+            assert np.array_equal(rb, want_rows)
+
+
+def test_noalloc_counts_only_and_empty():
+    n = 4099
+    seed = gen.BASE_SEED + 78
+    keys, rows = gen.unique_keys(seed, n, 32)
+    sk, sr = oracle.stable_sort(keys, rows)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="eks", k=17) as ix:
+        lo, hi = _ranges(keys, 3000, 64, seed)
+        off = torch.empty(len(lo) + 1, dtype=torch.int64, device="cuda")
+        total = ix.range_noalloc(to_dev(lo), to_dev(hi), off)
+        want_off, _ = oracle.range_lookup(sk, sr, lo, hi)
+        assert total == int(want_off[-1])
+        assert np.array_equal(off.cpu().numpy().view(np.uint64), want_off)
+        empty = torch.empty(0, dtype=torch.int32, device="cuda")
+        off0 = torch.full((1,), 7, dtype=torch.int64, device="cuda")
+        assert ix.range_noalloc(empty, empty, off0) == 0
+        assert int(off0.item()) == 0
+
+
+def test_noalloc_rejects_more_than_its_scratch():
+    """m above IDX_NOALLOC_MAX_RANGES is refused on the host before any
+    work is enqueued (the bound buffers are never read)."""
+    keys = np.arange(1, 1025, dtype=np.uint32)
+    rows = np.arange(1024, dtype=np.uint32)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        lo = to_dev(keys[:4])
+        off = torch.empty(5, dtype=torch.int64, device="cuda")
+        total = B.ctypes.c_uint64(0)
+        st = B.lib().idx_range_noalloc(ix._h, lo.data_ptr(), lo.data_ptr(), B.IDX_NOALLOC_MAX_RANGES + 1,
+                                       off.data_ptr(), None, 0, B.ctypes.byref(total), B._stream(None))
+        assert st == B.IDX_ERR_SCRATCH
+        assert "scratch" in B.lib().idx_strerror(st).decode()
