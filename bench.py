@@ -665,10 +665,11 @@ def run_small(idx, gen, np, torch, dev, log):
 
 def run_range_scan(idx, np, torch, dev, keys, rows, sorted_rows, log):
     """Hybrid coalesced against single-lane level scanning of EBS range
-    lookups (Section 5.1; the paper's Fig. 17 experiment at this index size):
-    the n = 2^26 index in EBS layout, 2^18 ranges covering exactly c keys for
-    c = 2^4 .. 2^14; the same ranges in both scan modes, every offset and row
-    ID checked against the ranks the ranges were drawn at."""
+    lookups (Section 5.1; the paper's Fig. 17 experiment at this index size),
+    and the library's default, the gather by rank: the n = 2^26 index in EBS
+    layout, 2^18 ranges covering exactly c keys for c = 2^4 .. 2^14; the same
+    ranges in every mode, every offset and row ID checked against the ranks
+    the ranges were drawn at."""
     m = 1 << 18
     n = len(keys)
     ordered = torch.sort(keys, stable=True).values
@@ -681,7 +682,7 @@ def run_range_scan(idx, np, torch, dev, keys, rows, sorted_rows, log):
             r = torch.randint(0, n - c + 1, (m,), generator=g, device=dev)
             lo, hi = ordered[r], ordered[r + c - 1]
             row = {"hits": c}
-            for mode, name in ((1, "hybrid"), (2, "single")):
+            for mode, name in ((1, "hybrid"), (2, "single"), (3, "rank_gather")):
                 ix.set_params(range_scan=mode)
                 reps = 3 if c <= 1024 else 1
                 off, rr = ix.range(lo, hi, capacity=m * c)
@@ -709,9 +710,10 @@ def run_range_scan(idx, np, torch, dev, keys, rows, sorted_rows, log):
             row["hybrid_speedup"] = row["single"]["ms"] / row["hybrid"]["ms"]
             res["rows"].append(row)
             log(f"range scan c={c}: hybrid {row['hybrid']['ms']:.3f} ms, single {row['single']['ms']:.3f} ms "
-                f"({row['hybrid_speedup']:.2f}x) exact={row['hybrid']['bit_exact'] and row['single']['bit_exact']}")
+                f"({row['hybrid_speedup']:.2f}x), rank gather {row['rank_gather']['ms']:.3f} ms "
+                f"exact={all(row[k]['bit_exact'] for k in ('hybrid', 'single', 'rank_gather'))}")
             torch.cuda.empty_cache()
-    res["bit_exact"] = all(rw[k]["bit_exact"] for rw in res["rows"] for k in ("hybrid", "single"))
+    res["bit_exact"] = all(rw[k]["bit_exact"] for rw in res["rows"] for k in ("hybrid", "single", "rank_gather"))
     return res
 
 
@@ -1071,7 +1073,7 @@ def main():
                 ksweep.append({"k": k, "keys_per_node": k - 1, "build_permute_ms": round(build_ms, 4),
                                "ms": round(ms, 4), "lookups_per_s": m / ms * 1e3, "bit_exact": ok,
                                "group": p_["group"], "per_lane": p_["per_lane"]})
-                log(f"k sweep k={k}: permute {build_ms:.3f} ms, lookups {ms:.3f} ms ({m / ms / 1e6:.0f} M/s) "
+                log(f"k sweep k={k}: permute {build_ms:.3f} ms, lookups {ms:.3f} ms ({m / ms / 1e6:.1f} G/s) "
                     f"exact={ok}")
                 ix.close()
 

@@ -302,10 +302,13 @@ typedef struct idx_lookup_params {
                                keys are below the query (fewer lines when they come from HBM);
                                1 = read the whole window at once (shorter chains when it is cached,
                                e.g. skewed or sorted batches) */
-    uint32_t range_scan; /* Eytzinger range lookups (level scan, Section 5): 0 = default (1);
-                            1 = hybrid coalesced scan (Section 5.1): a lane that meets 64 matches
-                            on one level hands its scan to its whole wave; 2 = every range
-                            scanned by its own lane alone */
+    uint32_t range_scan; /* Eytzinger range lookups, how the row IDs are collected: 0 = default (3);
+                            1 = level scan (Section 5) with the hybrid coalesced scan of
+                            Section 5.1: a lane that meets 64 matches on one level hands its scan
+                            to its whole wave; 2 = level scan, every range by its own lane alone;
+                            3 = gather by rank: the matches are the ranks [first, first + count)
+                            of the count phase, each read at the slot the layout build wrote
+                            that rank to (the inverse permutation, no key reads) */
 } idx_lookup_params;
 
 /* Set (p != NULL) or reset to defaults (p == NULL).  Errors: IDX_ERR_ARG for an

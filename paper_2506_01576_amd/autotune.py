@@ -77,6 +77,53 @@ def candidates(key_bits: int, n: int):
     return out
 
 
+def learned_candidates(n: int):
+    """Learned forms worth measuring: (leaves, lookups per lane, storage)."""
+    out = []
+    for per_leaf in (64, 16, 8):
+        L = max(1, min(1 << 22, n // per_leaf))
+        for r in (4, 8):
+            for aos in (False, True):
+                out.append((L, r, aos))
+    return sorted(set(out), key=lambda c: (c[0], c[1], str(c[2])))
+
+
+def tune_learned(base: Index, q: torch.Tensor, expect: torch.Tensor, cands=None, reps: int = 3, log=None):
+    """Train the rank model on `base`'s sorted array (and on its packed
+    array-of-structures copy) for every candidate leaf count and time the
+    model lookups; returns (records, best record)."""
+    cands = cands if cands is not None else learned_candidates(base.n)
+    out = torch.empty(len(q), dtype=torch.int32, device=q.device)
+    arrays, records, best, trained = {False: base}, [], None, {}
+    try:
+        for L, r, aos in cands:
+            if aos not in arrays:
+                arrays[aos] = base.relayout("bs", 1, aos)
+            arr = arrays[aos]
+            if trained.get(aos) != L:
+                st = arr.learn(L, 2)
+                trained[aos] = L
+            arr.set_params(per_lane=r, model=0)
+            ms = _time_point(arr, q, out, reps)
+            exact = bool(torch.equal(out, expect))
+            rec = {"layout": "learned", "k": 1, "aos": aos, "params": dict(arr.params(), leaves=L),
+                   "ms": round(ms, 4), "lookups_per_s": len(q) / ms * 1e3, "bit_exact": exact,
+                   "mean_window": st["mean_window"]}
+            records.append(rec)
+            if log:
+                log(f"tune learned leaves={L} R={r} aos={aos}: {ms:.3f} ms {rec['lookups_per_s'] / 1e9:.2f} G/s "
+                    f"exact={exact}")
+            if exact and (best is None or ms < best["ms"]):
+                best = rec
+    finally:
+        for aos, arr in arrays.items():
+            if arr is not base:
+                arr.close()
+        base.unlearn()
+        base.reset_params()
+    return records, best
+
+
 def _time_point(ix: Index, q: torch.Tensor, out: torch.Tensor, reps: int) -> float:
     stream = torch.cuda.current_stream()
     ix.point(q, out)
@@ -223,7 +270,7 @@ def build_form(keys: torch.Tensor, rows: torch.Tensor, form) -> Index:
     return ix
 
 
-def tune_batch(gen_module, key_bits: int = 32, per_class: int = 48, queries_per_index: int = 1 << 13,
+def tune_batch(gen_module, key_bits: int = 32, per_class: int = 64, queries_per_index: int = 1 << 14,
                seed: int = 7, forms=None, log=None):
     """For every size class, time the batched launch over `per_class`
     indexes built in each candidate form (layout, k, model, lanes per lookup,
@@ -261,15 +308,17 @@ def tune_batch(gen_module, key_bits: int = 32, per_class: int = 48, queries_per_
                 bt.point(dq, doff, out)
                 torch.cuda.synchronize()
                 exact = bool(torch.equal(out, de))
+                # median over 5 samples of 10 back-to-back launches each
                 ts = []
                 for _ in range(5):
                     a = torch.cuda.Event(enable_timing=True)
                     b = torch.cuda.Event(enable_timing=True)
                     a.record()
-                    bt.point(dq, doff, out)
+                    for _ in range(10):
+                        bt.point(dq, doff, out)
                     b.record()
                     b.synchronize()
-                    ts.append(a.elapsed_time(b))
+                    ts.append(a.elapsed_time(b) / 10)
                 ms = sorted(ts)[len(ts) // 2]
             for ix in idxs:
                 ix.close()
@@ -306,3 +355,79 @@ def batch_form(n: int, key_bits: int, table: dict | None = None):
         return min(abs(lg - e["log2n_lo"]), abs(lg - e["log2n_hi"]))
 
     return _form(min(ents, key=dist))
+
+
+# --------------------------------------------------------------- command line
+def _main(argv=None):
+    """python -m paper_2506_01576_amd.autotune [--point] [--batch] [--bits 32,64]
+    [--log2n 12,16,...] [--log2m 24] [--write]: measure the candidate forms on
+    the GPU (seeded synthetic keys, uniform unique; half of the point lookups
+    miss) and, with --write, store the winners in the tuned table."""
+    import argparse
+    import sys
+    import time
+
+    import numpy as np
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if root not in sys.path:
+        sys.path.insert(0, root)
+    import gen
+
+    ap = argparse.ArgumentParser(prog="python -m paper_2506_01576_amd.autotune")
+    ap.add_argument("--point", action="store_true", help="single-index forms per size class")
+    ap.add_argument("--batch", action="store_true", help="batched-launch forms per size class")
+    ap.add_argument("--bits", default="32,64")
+    ap.add_argument("--log2n", default="12,16,20,23,25,26,29",
+                    help="one measured size per class (log2 of the key count)")
+    ap.add_argument("--log2m", type=int, default=24, help="point lookups per measurement (log2)")
+    ap.add_argument("--write", action="store_true")
+    ap.add_argument("--out", default=TABLE_PATH, help="table file read and written (default: the package's table)")
+    args = ap.parse_args(argv)
+    t_start = time.time()
+
+    def log(msg):
+        print(f"[{time.time() - t_start:7.1f}s] {msg}", flush=True)
+
+    dev = torch.device("cuda")
+    table = load_table(args.out if os.path.exists(args.out) else TABLE_PATH)
+    for bits in [int(b) for b in args.bits.split(",")]:
+        view = np.int32 if bits == 32 else np.int64
+        if args.point:
+            for lg in [int(x) for x in args.log2n.split(",")]:
+                n, m = 1 << lg, 1 << args.log2m
+                seed = 0x2506_01576 + 100 + lg
+                kh, rh = gen.unique_keys(seed, n, bits)
+                qh, eh = gen.point_queries(seed, n, m, 0.5, bits)
+                keys = torch.from_numpy(kh.view(view)).to(dev)
+                rows = torch.from_numpy(rh.view(np.int32)).to(dev)
+                q = torch.from_numpy(qh.view(view)).to(dev)
+                expect = torch.from_numpy(eh.view(np.int32)).to(dev)
+                del kh, rh, qh, eh
+                log(f"point: {bits}-bit keys, n = 2^{lg}, {m} lookups")
+                with Index(keys, rows, layout="bs") as base:
+                    _, best = tune(base, q, expect, log=log)
+                    _, lbest = tune_learned(base, q, expect, log=log)
+                if lbest:
+                    best["learned"] = lbest
+                for lay, rec in sorted(best.items()):
+                    log(f"point {bits}-bit 2^{lg} best {lay}: k={rec['k']} aos={rec['aos']} "
+                        f"{rec['lookups_per_s'] / 1e9:.2f} G/s")
+                table = record_best(table, bits, n, best)
+                del keys, rows, q, expect
+                torch.cuda.empty_cache()
+                if args.write:
+                    save_table(table, args.out)
+        if args.batch:
+            best, _ = tune_batch(gen, bits, log=log)
+            table = record_batch(table, bits, best)
+            for lo, rec in sorted(best.items()):
+                log(f"batch {bits}-bit class 2^{lo}: {rec['layout']} k={rec['k']} leaf={rec['keys_per_leaf']} "
+                    f"{rec['params']} {rec['lookups_per_s'] / 1e9:.2f} G/s")
+            if args.write:
+                save_table(table, args.out)
+    log("done")
+
+
+if __name__ == "__main__":
+    _main()

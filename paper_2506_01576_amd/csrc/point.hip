@@ -656,9 +656,10 @@ int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_p
     // short-window scan: 0 = default (two rounds), 1 = one round, 2 = two rounds
     if (p.window_rounds == 0) p.window_rounds = 2;
     if (p.window_rounds > 2) return IDX_ERR_ARG;
-    // range level scan: 0 = default (hybrid), 1 = hybrid, 2 = single lane
-    if (p.range_scan == 0) p.range_scan = 1;
-    if (p.range_scan > 2) return IDX_ERR_ARG;
+    // Eytzinger range fill: 0 = default (gather by rank), 1 = hybrid level
+    // scan, 2 = single-lane level scan, 3 = gather by rank
+    if (p.range_scan == 0) p.range_scan = 3;
+    if (p.range_scan > 3) return IDX_ERR_ARG;
     *out = p;
     return IDX_OK;
 }

@@ -6,17 +6,24 @@
 //     layouts the rank of the descent's slot t is slot_rank(t)), giving the
 //     match count; the first rank is kept in a scratch array;
 //  2. exclusive scan of the counts into the caller's offsets (u64);
-//  3. fill: BS copies the contiguous rowid run; EBS/EKS run the level scan of
+//  3. fill: BS copies the contiguous rowid run.  EBS/EKS either gather by
+//     rank (default): the matches are the ranks [first, first + count), and
+//     rank r sits at the level-order slot the layout build wrote it to (the
+//     inverse of slot_rank, evaluated in closed form), so each row ID is read
+//     from that slot without reading a key; or run the level scan of
 //     Section 5: follow the lower-bound path of lo and, on every level, scan
 //     right from the path position while keys are <= hi and the level has not
 //     ended (qualifying entries of a level are contiguous, and at most two
 //     extra entries per level are read).  The scan meets the matches in level
 //     order; each is written at offset + slot_rank(t) - first rank, which puts
 //     the query's rowids in key order.
+// The count searches both bounds of a range in lockstep: the two descents
+// read the same nodes (or keys) until their paths part, near the bottom.
 // EBS is handled as the k = 2 level-order tree shifted by its empty slot.
 #include "internal.hpp"
 #include "access.hpp"
 #include "range_scan.hpp"
+#include "search.hpp"
 
 namespace idx {
 namespace {
@@ -34,67 +41,113 @@ struct RangeArgs {
     uint32_t *__restrict__ first_rank;
     uint32_t *__restrict__ out;
     uint32_t handover;  // level matches after which a lane hands its scan to the wave
+    uint64_t kinv;      // ceil(2^64 / k) for the rank-to-slot map (k > 2)
 };
 
-// Rank of the first key >= x.
+// Sorted array: lower-bound ranks of x0 and x1 >= x0 by two binary searches
+// in lockstep; while their intervals coincide the second reads nothing of
+// its own.  The SoA array stops at a window of at most 15 keys and reads it
+// with independent 16-byte loads (the short-window scan).
 template <typename K, bool AOS>
-__device__ __forceinline__ uint64_t lower_rank(const RangeArgs<K, AOS> &a, K x) {
+__device__ __forceinline__ void bs_ranks(const RangeArgs<K, AOS> &a, K x0, K x1, uint64_t &r0, uint64_t &r1) {
     const uint64_t n = a.G.n;
-    if (n == 0) return 0;
-    if (a.layout == IDX_BS) {
-        uint64_t base = 0, len = n;
-        while (len > 1) {
-            const uint64_t half = len >> 1;
-            base = (a.L.key(base + half) < x) ? base + half : base;
-            len -= half;
-        }
-        return base + (a.L.key(base) < x ? 1 : 0);
+    uint64_t b0 = 0, b1 = 0, len = n;
+    const uint64_t stop = AOS ? 1 : 15;
+    while (len > stop) {
+        const uint64_t half = len >> 1;
+        const K k0 = a.L.key(b0 + half);
+        const K k1 = b1 == b0 ? k0 : a.L.key(b1 + half);
+        b0 = k0 < x0 ? b0 + half : b0;
+        b1 = k1 < x1 ? b1 + half : b1;
+        len -= half;
     }
-    const uint32_t g = a.G.g, kf = a.G.k;
-    uint64_t c = 0, cand = ~0ull;
     if constexpr (!AOS) {
-        if (scan_vec_ok(a.G, a.off, sizeof(K), false)) {  // whole nodes in registers
-            K kk[kScanNodeBytes / sizeof(K)];
-            while (c * g < n) {
-                const uint64_t i = c * g;
-                const uint32_t nv = (n - i) < g ? (uint32_t)(n - i) : g;
-                node_keys(a.L.k, i, g, kk);
-                const uint32_t j = node_below(kk, nv, x);
-                if (j < nv) cand = i + j;
-                c = c * kf + 1 + j;
-            }
-            return cand == ~0ull ? n : slot_rank(a.G, cand);
-        }
+        bool eq;
+        const uint64_t s0 = (len + 1) < (n - b0) ? (len + 1) : (n - b0);
+        const uint64_t s1 = (len + 1) < (n - b1) ? (len + 1) : (n - b1);
+        r0 = b0 + count_below<K, 16>(a.L.k, b0, (uint32_t)s0, x0, eq);
+        r1 = b1 + count_below<K, 16>(a.L.k, b1, (uint32_t)s1, x1, eq);
+    } else {
+        r0 = b0 + (a.L.key(b0) < x0 ? 1 : 0);
+        r1 = b1 + (a.L.key(b1) < x1 ? 1 : 0);
     }
-    while (c * g < n) {
-        const uint64_t i = c * g;
-        const uint64_t nv = (n - i) < g ? (n - i) : g;
-        uint32_t j = 0;
-        for (uint32_t e = 0; e < nv; ++e) j += a.L.key(a.off + i + e) < x ? 1u : 0u;
-        if (j < nv) cand = i + j;
-        c = c * kf + 1 + j;
-    }
-    return cand == ~0ull ? n : slot_rank(a.G, cand);
 }
 
-// Sorted array: rank of the first key > U, given that every key before r0 is
-// <= U.  Gallops forward from r0 (the first probes fall in the lines the
-// search for r0 just read), then halves the last step.
+// Eytzinger layouts: lower-bound ranks of x0 and of x1 >= x0 (when `two`),
+// as the rank of the deepest path position whose pivot is >= the bound.  The
+// two descents share each node until their paths part; a node is read once
+// with 16-byte loads when the nodes allow it.
 template <typename K, bool AOS>
-__device__ __forceinline__ uint64_t upper_rank_from(const RangeArgs<K, AOS> &a, uint64_t r0, K U) {
+__device__ __forceinline__ void eyt_ranks(const RangeArgs<K, AOS> &a, K x0, K x1, bool two, uint64_t &r0,
+                                          uint64_t &r1) {
     const uint64_t n = a.G.n;
-    uint64_t lo = r0, step = 16;
-    while (lo + step < n && a.L.key(lo + step) <= U) {
-        lo += step;
-        step <<= 1;
+    const uint32_t g = a.G.g, kf = a.G.k;
+    uint64_t c0 = 0, c1 = 0, cand0 = ~0ull, cand1 = ~0ull;
+    if constexpr (!AOS) {
+        if (scan_vec_ok(a.G, a.off, sizeof(K), false)) {  // whole nodes in registers
+            constexpr int NK = kScanNodeBytes / sizeof(K);
+            K kk0[NK], kk1[NK];
+            for (;;) {
+                const uint64_t i0 = c0 * g, i1 = c1 * g;
+                const bool l0 = i0 < n, l1 = two && i1 < n;
+                if (!l0 && !l1) break;
+                if (l0) node_keys(a.L.k, i0, g, kk0);
+                if (l1 && c1 != c0) node_keys(a.L.k, i1, g, kk1);
+                if (l0) {
+                    const uint32_t nv = (n - i0) < g ? (uint32_t)(n - i0) : g;
+                    const uint32_t j = node_below(kk0, nv, x0);
+                    if (l1 && c1 == c0) {
+                        const uint32_t j1 = node_below(kk0, nv, x1);
+                        if (j1 < nv) cand1 = i1 + j1;
+                        c1 = c1 * kf + 1 + j1;
+                    }
+                    if (j < nv) cand0 = i0 + j;
+                    c0 = c0 * kf + 1 + j;
+                    if (l1 && i1 != i0) {
+                        const uint32_t nv1 = (n - i1) < g ? (uint32_t)(n - i1) : g;
+                        const uint32_t j1 = node_below(kk1, nv1, x1);
+                        if (j1 < nv1) cand1 = i1 + j1;
+                        c1 = c1 * kf + 1 + j1;
+                    }
+                } else {
+                    const uint32_t nv1 = (n - i1) < g ? (uint32_t)(n - i1) : g;
+                    const uint32_t j1 = node_below(kk1, nv1, x1);
+                    if (j1 < nv1) cand1 = i1 + j1;
+                    c1 = c1 * kf + 1 + j1;
+                }
+            }
+            r0 = cand0 == ~0ull ? n : slot_rank(a.G, cand0);
+            r1 = cand1 == ~0ull ? n : slot_rank(a.G, cand1);
+            return;
+        }
     }
-    uint64_t hi = lo + step < n ? lo + step : n;  // key(hi) > U, or hi == n
-    while (lo < hi) {
-        const uint64_t mid = lo + (hi - lo) / 2;
-        if (a.L.key(mid) <= U) lo = mid + 1;
-        else hi = mid;
+    for (;;) {
+        const uint64_t i0 = c0 * g, i1 = c1 * g;
+        const bool l0 = i0 < n, l1 = two && i1 < n;
+        if (!l0 && !l1) break;
+        const uint64_t nv0 = l0 ? ((n - i0) < g ? (n - i0) : g) : 0;
+        const uint64_t nv1 = l1 ? ((n - i1) < g ? (n - i1) : g) : 0;
+        const bool same = l1 && c1 == c0;
+        uint32_t j0 = 0, j1 = 0;
+        for (uint32_t e = 0; e < g; ++e) {
+            if (e < nv0) {
+                const K k = a.L.key(a.off + i0 + e);
+                j0 += k < x0 ? 1u : 0u;
+                if (same) j1 += k < x1 ? 1u : 0u;
+            }
+            if (!same && e < nv1) j1 += a.L.key(a.off + i1 + e) < x1 ? 1u : 0u;
+        }
+        if (l0) {
+            if (j0 < nv0) cand0 = i0 + j0;
+            c0 = c0 * kf + 1 + j0;
+        }
+        if (l1) {
+            if (j1 < nv1) cand1 = i1 + j1;
+            c1 = c1 * kf + 1 + j1;
+        }
     }
-    return lo;
+    r0 = cand0 == ~0ull ? n : slot_rank(a.G, cand0);
+    r1 = cand1 == ~0ull ? n : slot_rank(a.G, cand1);
 }
 
 template <typename K, bool AOS>
@@ -103,23 +156,38 @@ __global__ __launch_bounds__(256) void k_range_count(RangeArgs<K, AOS> a) {
     if (q >= a.m) return;
     const K L = a.lo[q], U = a.hi[q];
     uint64_t r0 = 0, r1 = 0;
-    if (L <= U) {
-        r0 = lower_rank(a, L);
-        if (U == key_max<K>()) r1 = a.G.n;
-        else if (a.layout == IDX_BS) r1 = upper_rank_from(a, r0, U);
-        else r1 = lower_rank(a, (K)(U + 1));
+    if (L <= U && a.G.n > 0) {
+        const bool top = U == key_max<K>();  // nothing is above U: r1 = n
+        const K x1 = top ? U : (K)(U + 1);
+        if (a.layout == IDX_BS) {
+            bs_ranks(a, L, x1, r0, r1);
+        } else {
+            eyt_ranks(a, L, x1, !top, r0, r1);
+        }
+        if (top) r1 = a.G.n;
     }
     a.first_rank[q] = (uint32_t)r0;
     a.offsets[q] = r1 > r0 ? r1 - r0 : 0;
 }
 
-// BS (and the learned form): each wave takes 64 consecutive queries, whose
-// row-ID runs are consecutive in the output, and copies their concatenation:
-// every element finds its run by a binary search over the runs' starts (per
-// wave, in LDS), so stores are coalesced and each lane has several loads in
-// flight.
-template <typename K, bool AOS>
-__global__ __launch_bounds__(256) void k_range_fill_bs(RangeArgs<K, AOS> a) {
+// Where the entry of sorted rank r sits: the sorted array itself (BS and the
+// learned form), or the level-order slot the layout build wrote it to.
+enum : int { MAP_SORTED = 0, MAP_BINARY = 1, MAP_KARY = 2 };
+
+template <int MAP, typename K, bool AOS>
+__device__ __forceinline__ uint64_t slot_of_rank(const RangeArgs<K, AOS> &a, uint64_t r) {
+    if constexpr (MAP == MAP_SORTED) return r;
+    else if constexpr (MAP == MAP_BINARY) return a.off + rank_slot_binary(a.G, r);
+    else return a.off + rank_slot_general(a.G, r, a.kinv);
+}
+
+// Each wave takes 64 consecutive queries, whose row-ID runs are consecutive
+// in the output, and copies their concatenation: every element finds its run
+// by a binary search over the runs' starts (per wave, in LDS), so stores are
+// coalesced and each lane has several loads in flight.  The run of a range
+// is its ranks [first, first + count); MAP says where each rank is stored.
+template <typename K, bool AOS, int MAP>
+__global__ __launch_bounds__(256) void k_range_fill_rank(RangeArgs<K, AOS> a) {
     constexpr int WPB = 256 / kWave;
     __shared__ uint64_t s_start[WPB][kWave + 1];
     __shared__ uint64_t s_src[WPB][kWave];  // first rank of the run minus its start
@@ -159,7 +227,7 @@ __global__ __launch_bounds__(256) void k_range_fill_bs(RangeArgs<K, AOS> a) {
 #pragma unroll
             for (uint32_t step = kWave / 2; step > 0; step >>= 1)
                 if (s_start[w][lo + step] <= t) lo += step;
-            v[u] = a.L.row(s_src[w][lo] + t);
+            v[u] = a.L.row(slot_of_rank<MAP>(a, s_src[w][lo] + t));
         }
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
@@ -329,6 +397,7 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
     a.offsets = offsets;
     a.out = out;
     a.handover = h->params.range_scan == 2 ? kNoHandover : kHandover;
+    a.kinv = h->geo.k > 2 ? ~0ull / h->geo.k + 1 : 0;  // ceil(2^64 / k)
     const size_t rank_bytes = ((m * 4 + 255) / 256) * 256;
     char *scratch = given ? given : (char *)h->alloc.get(range_scratch_bytes(m), s);
     if (!scratch) return IDX_ERR_NOMEM;
@@ -362,9 +431,14 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
             rc = IDX_ERR_CAPACITY;
             break;
         }
+        const uint32_t wblocks = (uint32_t)(((m + kWave - 1) / kWave + 3) / 4);
         if (h->layout == IDX_BS) {
-            const uint64_t waves = (m + kWave - 1) / kWave;
-            hipLaunchKernelGGL((k_range_fill_bs<K, AOS>), dim3((uint32_t)((waves + 3) / 4)), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_range_fill_rank<K, AOS, MAP_SORTED>), dim3(wblocks), dim3(256), 0, s, a);
+        } else if (h->params.range_scan == 3) {
+            if (h->geo.k == 2)
+                hipLaunchKernelGGL((k_range_fill_rank<K, AOS, MAP_BINARY>), dim3(wblocks), dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_range_fill_rank<K, AOS, MAP_KARY>), dim3(wblocks), dim3(256), 0, s, a);
         } else {
             hipLaunchKernelGGL((k_range_fill_eyt<K, AOS>), dim3(blocks), dim3(256), 0, s, a);
         }

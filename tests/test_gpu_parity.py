@@ -244,15 +244,18 @@ def test_range_parity(layout, k, aos, bits):
         with build(keys, rows, layout, k, aos) as ix:
             check_range(ix, keys, rows, bits, seed=n + 3 * k)
             if layout != "bs" and n > 1000:
-                # the level scan with every range scanned by its own lane (no
-                # hand-over to the wave) gives the same answers
-                ix.set_params(range_scan=2)
-                check_range(ix, keys, rows, bits, seed=n + 3 * k)
+                # the default gathers by rank; the level scan, with the hybrid
+                # hand-over to the wave and with every range scanned by its own
+                # lane, gives the same answers
+                for mode in (1, 2):
+                    ix.set_params(range_scan=mode)
+                    check_range(ix, keys, rows, bits, seed=n + 3 * k)
 
 
 def test_range_scan_modes_on_wide_ranges():
     """Ranges of 1 to 8192 matches (every level past the hand-over threshold)
-    in both level-scan modes equal the oracle, EBS and EKS."""
+    in both level-scan modes and gathered by rank equal the oracle, EBS and
+    EKS."""
     n = 200003
     keys, rows = key_set(5, n, 64, "unique")
     sk, sr = oracle.stable_sort(keys, rows)
@@ -260,7 +263,7 @@ def test_range_scan_modes_on_wide_ranges():
     want_off, want_rows = oracle.range_lookup(sk, sr, lo, hi, nthreads=4)
     for layout, k in (("ebs", 2), ("eks", 9), ("eks", 17)):
         with build(keys, rows, layout, k, False) as ix:
-            for mode in (1, 2):
+            for mode in (1, 2, 3):
                 ix.set_params(range_scan=mode)
                 off, rr = ix.range(to_dev(lo), to_dev(hi))
                 assert np.array_equal(off.cpu().numpy().view(np.uint64), want_off), (layout, k, mode)
@@ -283,7 +286,7 @@ def test_bad_params_rejected():
     with build(keys, rows, "eks", 9) as ix:
         before = ix.params()
         for bad in ({"group": 128}, {"group": 3}, {"block": 96}, {"per_lane": 3}, {"lds_levels": 30},
-                    {"early_exit": 3}, {"reorder": 3}, {"reorder": 1, "group": 8}, {"range_scan": 3}):
+                    {"early_exit": 3}, {"reorder": 3}, {"reorder": 1, "group": 8}, {"range_scan": 4}):
             with pytest.raises(idx.IdxError):
                 ix.set_params(**bad)
             assert ix.params() == before
