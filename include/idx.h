@@ -212,7 +212,9 @@ int idx_range(idx_handle h, const void *lo, const void *hi, uint64_t m, uint64_t
  * the process ends).  All calls on one device share it: calls that overlap
  * on one device (concurrent streams or threads) race and must be ordered by
  * the caller.  IDX_ERR_SCRATCH when m > IDX_NOALLOC_MAX_RANGES (nothing is
- * enqueued).  Synchronises `stream` once, like idx_range.
+ * enqueued).  The rank-bucket partition (lookup parameter reorder = 2) needs
+ * scratch proportional to the batch, so these calls count unpartitioned;
+ * the answers are the same.  Synchronises `stream` once, like idx_range.
  */
 #define IDX_NOALLOC_MAX_RANGES (1ull << 23)
 int idx_range_noalloc(idx_handle h, const void *lo, const void *hi, uint64_t m, uint64_t *out_offsets,
@@ -294,7 +296,10 @@ typedef struct idx_lookup_params {
     uint32_t lds_levels; /* top tree levels served from LDS (cache pinning); 0 = none */
     uint32_t persistent; /* 0 = one workgroup per tile of lookups; c > 0 = persistent
                             grid of c workgroups per compute unit (limited concurrency) */
-    uint32_t reorder;    /* 1 = sort each workgroup's lookups locally before searching */
+    uint32_t reorder;    /* 1 = sort each workgroup's point lookups locally before searching;
+                            2 = partition the batch by rank bucket of the index first (point
+                            lookups, and the count phase of range lookups by their lower bounds),
+                            answers returned to the caller's order */
     uint32_t early_exit; /* 1 = stop at an equal key (only used when keys are unique) */
     uint32_t model;      /* 0/1 = use the learned model when one is trained (idx_learn), 2 = ignore it */
     uint32_t window_rounds; /* short-window scan (BS and learned forms): 0 = default (2); 2 = read the

@@ -127,6 +127,21 @@ uint32_t pin_entries_for(const idx_index *h, uint32_t levels);
 // Point lookups on a batch partitioned by rank bucket first.
 int point_partitioned(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s);
 void drop_splitters(idx_index *h, hipStream_t s);
+// The partition for other lookups: one chunk of m <= 2^31 query keys
+// partitioned by rank bucket (keys q, batch positions pos, both in
+// partitioned order; ans is a free u32 array of m entries), and answers in
+// partitioned order placed back at their positions (may run several times).
+struct PartView {
+    const void *q;
+    const uint32_t *pos;
+    uint32_t *ans;
+    uint64_t m;
+    void *scratch;
+};
+constexpr uint64_t kPartChunk = 1ull << 31;
+size_t partition_scratch_bytes(const idx_index *h, uint64_t m);
+int partition_forward(idx_index *h, const void *q, uint64_t m, void *scratch, PartView *out, hipStream_t s);
+int partition_place(idx_index *h, const PartView &v, const uint32_t *ans, uint32_t *out, hipStream_t s);
 
 // ---- range.hip --------------------------------------------------------------
 // Exclusive scan of v[0..m) in place, v[m] = total; partial holds

@@ -24,6 +24,7 @@
 #include "access.hpp"
 #include "range_scan.hpp"
 #include "search.hpp"
+#include "qio.hpp"
 
 namespace idx {
 namespace {
@@ -150,24 +151,98 @@ __device__ __forceinline__ void eyt_ranks(const RangeArgs<K, AOS> &a, K x0, K x1
     r1 = cand1 == ~0ull ? n : slot_rank(a.G, cand1);
 }
 
+// First rank r0 of the range [L, U] and the rank r1 past its last match
+// (r0 = r1 = 0 when L > U).
+template <typename K, bool AOS>
+__device__ __forceinline__ void range_ranks(const RangeArgs<K, AOS> &a, K L, K U, uint64_t &r0, uint64_t &r1) {
+    r0 = 0;
+    r1 = 0;
+    if (L > U || a.G.n == 0) return;
+    const bool top = U == key_max<K>();  // nothing is above U: r1 = n
+    const K x1 = top ? U : (K)(U + 1);
+    if (a.layout == IDX_BS) bs_ranks(a, L, x1, r0, r1);
+    else eyt_ranks(a, L, x1, !top, r0, r1);
+    if (top) r1 = a.G.n;
+}
+
 template <typename K, bool AOS>
 __global__ __launch_bounds__(256) void k_range_count(RangeArgs<K, AOS> a) {
     const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.m) return;
-    const K L = a.lo[q], U = a.hi[q];
-    uint64_t r0 = 0, r1 = 0;
-    if (L <= U && a.G.n > 0) {
-        const bool top = U == key_max<K>();  // nothing is above U: r1 = n
-        const K x1 = top ? U : (K)(U + 1);
-        if (a.layout == IDX_BS) {
-            bs_ranks(a, L, x1, r0, r1);
-        } else {
-            eyt_ranks(a, L, x1, !top, r0, r1);
-        }
-        if (top) r1 = a.G.n;
-    }
+    uint64_t r0, r1;
+    range_ranks(a, a.lo[q], a.hi[q], r0, r1);
     a.first_rank[q] = (uint32_t)r0;
     a.offsets[q] = r1 > r0 ? r1 - r0 : 0;
+}
+
+// The same on a batch of ranges partitioned by the rank bucket of their
+// lower bounds (lookup parameter reorder = 2): entry j holds lower bound
+// q2[j] of the range at batch position pos[j], whose upper bound is read
+// there.  The tiles are walked XCD by XCD, so the ranges one XCD has in
+// flight fall in a few buckets whose slice of the index stays in its L2.
+// Both ranks go out in partitioned order.
+template <typename K, bool AOS>
+__global__ __launch_bounds__(256) void k_range_count_part(RangeArgs<K, AOS> a, const K *__restrict__ q2,
+                                                          const uint32_t *__restrict__ pos, uint64_t ntiles,
+                                                          uint64_t iters, uint32_t *__restrict__ r0o,
+                                                          uint32_t *__restrict__ r1o) {
+    for (uint64_t it = blockIdx.x; it < iters; it += gridDim.x) {
+        const uint64_t tl = tile_of(it, ntiles, 1);
+        if (tl >= ntiles) continue;
+        const uint64_t j = tl * 256 + threadIdx.x;
+        if (j >= a.m) continue;
+        uint64_t r0, r1;
+        range_ranks(a, q2[j], a.hi[pos[j]], r0, r1);
+        r0o[j] = (uint32_t)r0;
+        r1o[j] = (uint32_t)r1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_range_combine(const uint32_t *__restrict__ r0, const uint32_t *__restrict__ r1,
+                                                       uint64_t m, uint64_t *__restrict__ counts) {
+    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < m) counts[q] = r1[q] > r0[q] ? (uint64_t)(r1[q] - r0[q]) : 0ull;
+}
+
+// Counts through the partition: per chunk of at most 2^31 ranges, partition
+// the lower bounds, count in partitioned order, then place both ranks back
+// at the ranges' positions and take their difference.
+template <typename K, bool AOS>
+int range_count_partitioned(idx_index *h, const RangeArgs<K, AOS> &a, hipStream_t s) {
+    const uint64_t m = a.m;
+    const uint64_t chunk = m < kPartChunk ? m : kPartChunk;
+    const size_t pb = (partition_scratch_bytes(h, chunk) + 255) & ~(size_t)255;
+    const size_t ab = ((chunk * 4 + 255) / 256) * 256;
+    char *t = (char *)h->alloc.get(pb + 2 * ab, s);
+    if (!t) return IDX_ERR_NOMEM;
+    uint32_t *r1p = (uint32_t *)(t + pb);       // past-the-end ranks, partitioned order
+    uint32_t *r1c = (uint32_t *)(t + pb + ab);  // the same at the ranges' positions
+    int rc = IDX_OK;
+    for (uint64_t c0 = 0; c0 < m && rc == IDX_OK; c0 += chunk) {
+        const uint64_t mc = (m - c0) < chunk ? (m - c0) : chunk;
+        PartView v{};
+        rc = partition_forward(h, a.lo + c0, mc, t, &v, s);
+        if (rc != IDX_OK) break;
+        RangeArgs<K, AOS> b = a;
+        b.hi = a.hi + c0;
+        b.m = mc;
+        const uint64_t tiles = (mc + 255) / 256;
+        const uint64_t iters = ((tiles + kXcds - 1) / kXcds) * kXcds;
+        hipLaunchKernelGGL((k_range_count_part<K, AOS>), dim3((uint32_t)iters), dim3(256), 0, s, b, (const K *)v.q,
+                           v.pos, tiles, iters, v.ans, r1p);
+        if (hipGetLastError() != hipSuccess) {
+            rc = IDX_ERR_HIP;
+            break;
+        }
+        rc = partition_place(h, v, v.ans, a.first_rank + c0, s);
+        if (rc == IDX_OK) rc = partition_place(h, v, r1p, r1c, s);
+        if (rc != IDX_OK) break;
+        hipLaunchKernelGGL(k_range_combine, dim3((uint32_t)((mc + 255) / 256)), dim3(256), 0, s, a.first_rank + c0,
+                           r1c, mc, a.offsets + c0);
+        if (hipGetLastError() != hipSuccess) rc = IDX_ERR_HIP;
+    }
+    h->alloc.put(t, s);
+    return rc;
 }
 
 // Where the entry of sorted rank r sits: the sorted array itself (BS and the
@@ -409,6 +484,11 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
     do {
         if (h->learned && h->params.model != 2) {
             rc = range_count_learned(h, lo, hi, m, a.first_rank, offsets, s);
+            if (rc != IDX_OK) break;
+        } else if (h->params.reorder == 2 && !given && h->n >= 4) {
+            // the caller-given scratch (no-allocation entry point) has no room
+            // for the partition: those calls count unpartitioned
+            rc = range_count_partitioned(h, a, s);
             if (rc != IDX_OK) break;
         } else {
             hipLaunchKernelGGL((k_range_count<K, AOS>), dim3(blocks), dim3(256), 0, s, a);

@@ -153,6 +153,13 @@ __global__ __launch_bounds__(kPartThreads) void k_starts(const uint32_t *__restr
     for (uint32_t d = threadIdx.x; d < D; d += blockDim.x) dcur[d] = d << shift;
 }
 
+// Window cursors of the backward scatter (also set by k_starts): window d
+// starts at position d << shift.
+__global__ void k_window_cursors(uint32_t *__restrict__ dcur, uint32_t D, uint32_t shift) {
+    const uint32_t d = threadIdx.x;
+    if (d < D) dcur[d] = d << shift;
+}
+
 // 4./5./7. One scatter pass: entry i goes to run run_of(i) of NB runs.  Per
 // tile a workgroup reserves one contiguous piece of every run the tile feeds
 // (one global atomic per run), then fills the pieces front to back in rounds
@@ -470,9 +477,11 @@ PartBufs carve(char *t, uint64_t m, size_t kb) {
     return p;
 }
 
+// Forward passes (steps 2-5): fine buckets, their starts, then the coarse
+// and fine scatters; the partitioned queries land in P.q2 with their batch
+// positions in P.p2.
 template <typename K>
-int partition_chunk(idx_index *h, const K *q, uint64_t m, uint32_t *out, uint32_t B, const PartBufs &P,
-                    hipStream_t s) {
+int partition_fwd(idx_index *h, const K *q, uint64_t m, uint32_t B, const PartBufs &P, hipStream_t s) {
     const uint32_t B1 = B < kCoarse ? B : kCoarse;
     const uint32_t B2 = B / B1;
     const uint64_t tiles = (m + kPartTile - 1) / kPartTile;
@@ -521,22 +530,33 @@ int partition_chunk(idx_index *h, const K *q, uint64_t m, uint32_t *out, uint32_
         hipLaunchKernelGGL((k_scatter<K, FwdFine>), dim3(sgrid), dim3(kPartThreads), lds, s, a);
         IDX_LAUNCH_CHECK();
     }
-    // answers in partitioned order go to p1 (free after the fine pass)
-    PointIO io{P.q2, m, P.p1, false, true};
-    int rc = point_run(h, io, s);
-    if (rc != IDX_OK) return rc;
+    return IDX_OK;
+}
+
+// Backward passes (steps 7-8): answers `ans` in partitioned order (positions
+// P.p2) to out[position].  Uses P.q1 for the (position, answer) pairs and
+// the window cursors P.dcur, which k_starts set; a second placement over the
+// same partition resets them first.
+int place_back(idx_index *h, const PartBufs &P, uint64_t m, const uint32_t *ans, uint32_t *out, hipStream_t s) {
+    const uint64_t tiles = (m + kPartTile - 1) / kPartTile;
+    const uint32_t sgrid = (uint32_t)(tiles < (uint64_t)h->cu_count ? tiles : (uint64_t)h->cu_count);
+    uint32_t shift = kWindowShift;
+    while (((m - 1) >> shift) + 1 > kMaxWindows) ++shift;
+    const uint32_t D = (uint32_t)(((m - 1) >> shift) + 1);
+    hipLaunchKernelGGL(k_window_cursors, dim3(1), dim3(kMaxWindows), 0, s, P.dcur, D, shift);
+    IDX_LAUNCH_CHECK();
     {
-        ScatterArgs<K, Bwd> a{};
+        ScatterArgs<uint32_t, Bwd> a{};
         a.p_in = P.p2;
-        a.r_in = P.p1;
+        a.r_in = ans;
         a.pk_out = (uint64_t *)P.q1;
         a.cur = P.dcur;
         a.m = m;
         a.ntiles = tiles;
         a.NB = D;
         a.shift = shift;
-        const size_t lds = scatter_lds_bytes<K, Bwd>(D);
-        hipLaunchKernelGGL((k_scatter<K, Bwd>), dim3(sgrid), dim3(kPartThreads), lds, s, a);
+        const size_t lds = scatter_lds_bytes<uint32_t, Bwd>(D);
+        hipLaunchKernelGGL((k_scatter<uint32_t, Bwd>), dim3(sgrid), dim3(kPartThreads), lds, s, a);
         IDX_LAUNCH_CHECK();
     }
     const uint64_t ptile = (uint64_t)kPlaceThreads * kPlacePer;
@@ -551,7 +571,48 @@ int partition_chunk(idx_index *h, const K *q, uint64_t m, uint32_t *out, uint32_
     return IDX_OK;
 }
 
+template <typename K>
+int partition_chunk(idx_index *h, const K *q, uint64_t m, uint32_t *out, uint32_t B, const PartBufs &P,
+                    hipStream_t s) {
+    int rc = partition_fwd<K>(h, q, m, B, P, s);
+    if (rc != IDX_OK) return rc;
+    // answers in partitioned order go to p1 (free after the fine pass)
+    PointIO io{P.q2, m, P.p1, false, true};
+    rc = point_run(h, io, s);
+    if (rc != IDX_OK) return rc;
+    return place_back(h, P, m, P.p1, out, s);
+}
+
 }  // namespace
+
+// ---- the partition as a service for other lookups (range counts): the
+// forward passes and the answer placement of one chunk, on scratch the
+// caller provides.
+size_t partition_scratch_bytes(const idx_index *h, uint64_t m) { return part_bytes(m, h->u64 ? 8 : 4); }
+
+int partition_forward(idx_index *h, const void *q, uint64_t m, void *scratch, PartView *out, hipStream_t s) {
+    if (m == 0 || m > kChunk) return IDX_ERR_ARG;
+    const uint32_t B = buckets_for(h);
+    int rc = build_splitters(h, B, s);
+    if (rc != IDX_OK) return rc;
+    const size_t kb = h->u64 ? 8 : 4;
+    const PartBufs P = carve((char *)scratch, m, kb);
+    rc = h->u64 ? partition_fwd<uint64_t>(h, (const uint64_t *)q, m, B, P, s)
+                : partition_fwd<uint32_t>(h, (const uint32_t *)q, m, B, P, s);
+    if (rc != IDX_OK) return rc;
+    out->q = P.q2;
+    out->pos = P.p2;
+    out->ans = P.p1;
+    out->m = m;
+    out->scratch = scratch;
+    return IDX_OK;
+}
+
+int partition_place(idx_index *h, const PartView &v, const uint32_t *ans, uint32_t *out, hipStream_t s) {
+    const size_t kb = h->u64 ? 8 : 4;
+    const PartBufs P = carve((char *)v.scratch, v.m, kb);
+    return place_back(h, P, v.m, ans, out, s);
+}
 
 void drop_splitters(idx_index *h, hipStream_t s) {
     if (h->split) h->alloc.put(h->split, s);

@@ -250,6 +250,37 @@ def test_range_parity(layout, k, aos, bits):
                 for mode in (1, 2):
                     ix.set_params(range_scan=mode)
                     check_range(ix, keys, rows, bits, seed=n + 3 * k)
+            if n > 1000 and not aos:
+                # counts on the batch partitioned by the lower bounds' rank buckets
+                ix.set_params(reorder=2)
+                check_range(ix, keys, rows, bits, seed=n + 5 * k)
+
+
+@pytest.mark.parametrize("bits,n,kind", [(64, 1 << 22, "unique"), (32, 1 << 21, "dup")])
+def test_partitioned_range_counts_large(bits, n, kind):
+    """Range counts through the rank-bucket partition (reorder = 2) at sizes
+    with 32 to 128 buckets (coarse and fine scatter passes), every layout:
+    offsets and row IDs equal the oracle's, including inverted, unbounded and
+    empty ranges."""
+    keys, rows = key_set(71 + bits, n, bits, kind)
+    sk, sr = oracle.stable_sort(keys, rows)
+    L, U, _ = gen.ranges(72, keys, 1 << 20, 1, 64)
+    rng = np.random.default_rng(73)
+    dt = keys.dtype
+    top = int(np.iinfo(dt).max)
+    R1 = rng.integers(0, top, size=(2, 4000), dtype=np.uint64, endpoint=True).astype(dt)
+    L = np.concatenate([L, R1.min(axis=0), R1.max(axis=0), np.array([0, top, 0], dtype=dt)])
+    U = np.concatenate([U, R1.max(axis=0), R1.min(axis=0), np.array([top, top, 0], dtype=dt)])
+    perm = rng.permutation(len(L))
+    L, U = L[perm], U[perm]
+    want_off, want = oracle.range_lookup(sk, sr, L, U, nthreads=8)
+    for layout, k in (("bs", 1), ("ebs", 2), ("eks", 9)):
+        with build(keys, rows, layout, k, False) as ix:
+            ix.set_params(reorder=2)
+            say(f"partitioned range counts {layout} bits={bits} n={n} {kind}")
+            off, got = ix.range(to_dev(L), to_dev(U))
+            assert np.array_equal(off.cpu().numpy().view(np.uint64), want_off), layout
+            assert np.array_equal(rows_host(got), want), layout
 
 
 def test_range_scan_modes_on_wide_ranges():
