@@ -57,10 +57,11 @@ def levels_eytzinger(n: int, k: int):
 
 
 def algo_bytes(form: str, n: int, k: int, key_bytes: int, early_exit: bool = True, window: float = 0.0,
-               leaves: int = 0, aos=False) -> dict:
+               leaves: int = 0, aos=False, onchip: int = ONCHIP_BYTES) -> dict:
+    ONCHIP_BYTES = onchip  # noqa: N806 (the capacity this estimate assumes)
     stream = key_bytes + 4
     uncached = 0.0
-    rowid = GRANULE
+    rowid = GRANULE if n * (key_bytes + 4) > onchip else 0
     if form == "learned":
         # leaf record (32 B each; counted only if the table exceeds on-chip
         # capacity) + binary search over the mean window: one granule per
@@ -97,6 +98,41 @@ def algo_bytes(form: str, n: int, k: int, key_bytes: int, early_exit: bool = Tru
             if cum > ONCHIP_BYTES:
                 uncached += reach * node_g
     return {"stream": stream, "tree": uncached, "rowid": rowid, "total": stream + uncached + rowid}
+
+
+# Algorithmic bytes per range lookup of `width` matches: the two bounds in,
+# the offset and the row IDs out, the descent of the lower bound as for a
+# point lookup, one more granule where the upper bound's search ends (its
+# path shares the rest), and the granules holding the matches' row IDs where
+# the layout stores them (sampled at random ranks: consecutive ranks lie in
+# one run on the sorted array, on a few levels of an Eytzinger layout).
+def algo_bytes_range(form: str, n: int, k: int, key_bytes: int, width: int, rank_slot=None, window: float = 0.0,
+                     leaves: int = 0, aos=False, samples: int = 2048) -> dict:
+    import numpy as np
+
+    pt = algo_bytes(form, n, k, key_bytes, early_exit=False, window=window, leaves=leaves, aos=aos)
+    rng = np.random.default_rng(1)
+    starts = rng.integers(0, n - width + 1, size=samples)
+    total = 0
+    for r0 in starts.tolist():
+        addrs = set()
+        for r in range(r0, r0 + width):
+            if form in ("bs", "learned") and not aos:
+                a = 4 * r
+            elif form == "learned":
+                a = (16 if aos == "padded" else key_bytes + 4) * r + key_bytes
+            elif form == "ebs":
+                a = 4 * (1 + rank_slot(n, 2, r))
+            else:
+                a = 4 * rank_slot(n, k, r)
+            addrs.add(a // GRANULE)
+        total += len(addrs)
+    rowid_g = total / samples
+    stream = 2 * key_bytes + 8 + 4 * width
+    tree = pt["tree"] + GRANULE
+    rowid = rowid_g * GRANULE
+    return {"stream": stream, "tree": tree, "rowid": round(rowid, 1), "rowid_granules": round(rowid_g, 3),
+            "total": round(stream + tree + rowid, 1)}
 
 
 def source_sha() -> str:
@@ -178,7 +214,24 @@ def run_batched(args, idx, gen, np, torch, dev, log, table):
         b.synchronize()
         return a.elapsed_time(b) / reps
 
-    res = {"indexes": count, "keys": int(sizes.sum()), "queries": total, "forms_by_count": forms_used}
+    # roofline of the one-launch kernel: per lookup the algorithmic bytes of
+    # its index's form (4 B query + 4 B answer, plus the granules of levels,
+    # leaf records, windows and row IDs that cannot stay in one XCD's 4 MiB
+    # L2: the launch walks many indexes at once, so the shared 256 MiB
+    # Infinity Cache is not counted as on-chip here), weighted by the lookups
+    # each index receives
+    algo_total = 0.0
+    for j, ix in enumerate(idxs):
+        lay, kk, per_leaf, _ = autotune._form(autotune.batch_form(int(sizes[j]), 32, table))
+        nj = int(sizes[j])
+        if per_leaf:
+            st = ix.learn_stats()
+            ab = algo_bytes("learned", nj, 1, 4, window=st["mean_window"], leaves=st["leaves"], onchip=4 << 20)
+        else:
+            ab = algo_bytes(lay, nj, kk, 4, onchip=4 << 20)
+        algo_total += ab["total"] * int(qcounts[j])
+    res = {"indexes": count, "keys": int(sizes.sum()), "queries": total, "forms_by_count": forms_used,
+           "algorithmic_bytes_per_lookup": round(algo_total / max(total, 1), 1)}
     with idx.Batch(idxs) as bt:
         ms_eager = timed(lambda: bt.point(dq, doff, out), 10)
         exact_eager = bool(torch.equal(out, de))
@@ -195,6 +248,10 @@ def run_batched(args, idx, gen, np, torch, dev, log, table):
     out.fill_(-1)
     ms_loop = timed(loop, 2)
     exact_loop = bool(torch.equal(out, de))
+    ach = algo_total / (min(ms_eager, ms_graph) / 1e3) / 1e9
+    res["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": "k_batch_point",
+                       "onchip_bytes_assumed": 4 << 20}
     res.update({"ms_one_launch": round(ms_eager, 4), "ms_graph_replay": round(ms_graph, 4),
                 "ms_per_index_loop": round(ms_loop, 4),
                 "lookups_per_s_one_launch": total / ms_eager * 1e3,
@@ -1026,6 +1083,23 @@ def main():
                 "kernel": kernel_key, "algorithmic_bytes_per_lookup": ab,
                 "launch_ms": round(mean[f"point_{headline}"], 4)}
 
+    # ---------------------------------------- roofline of the range phases
+    # each form's whole range call (count, scan, fill) over 2^log2ranges
+    # ranges of 16 keys, against the algorithmic bytes per range
+    range_roofline = {}
+    for name, rec in forms:
+        if f"range_{name}" not in mean:
+            continue
+        lay = rec["layout"]
+        rb = algo_bytes_range(lay, n, rec["k"], 8, 16, rank_slot=idx.lib().idx_rank_slot,
+                              window=rec.get("mean_window", 0.0), leaves=rec["params"].get("leaves", 0),
+                              aos=rec["aos"] if lay == "learned" else False)
+        t = mean[f"range_{name}"] / 1e3
+        ach = rb["total"] * mr / t / 1e9
+        range_roofline[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_range": rb,
+                                "range_call_ms": round(mean[f"range_{name}"], 4)}
+
     # ------------------------------------------------------ random-access probe
     probe = {}
     try:
@@ -1169,6 +1243,7 @@ def main():
                             if "mean_window" in rec else {})} for name, rec in forms},
         "phases_ms": {k: round(v, 4) for k, v in mean.items()},
         "range_lookups_per_s": {k[6:]: mr / v * 1e3 for k, v in mean.items() if k.startswith("range_")},
+        "range_roofline": range_roofline,
         "bit_exact": (all(r["bit_exact"] for r in checked) and all(step_exact.values())
                       and all(r["bit_exact"] for r in ksweep) and (small is None or small["bit_exact"])
                       and (scan_row is None or scan_row["bit_exact"])),

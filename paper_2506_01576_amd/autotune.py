@@ -70,6 +70,11 @@ def candidates(key_bits: int, n: int):
     if n >= 1 << 20:
         out.append(("bs", 1, False, {"reorder": 2, "per_lane": 4}))
         out.append(("bs", 1, False, {"reorder": 2, "per_lane": 8}))
+        # partitioned and pinned: the top levels from LDS, the rest from L2
+        out.append(("bs", 1, False, {"reorder": 2, "per_lane": 4, "lds_levels": 12, "persistent": 2,
+                                     "block": 1024}))
+        out.append(("ebs", 2, False, {"reorder": 2, "per_lane": 4, "lds_levels": 12, "persistent": 2,
+                                      "block": 1024}))
         out.append(("ebs", 2, False, {"reorder": 2, "per_lane": 8}))
         out.append(("ebs", 2, False, {"reorder": 2, "per_lane": 4}))
         out.append(("eks", 9, False, {"group": 1, "per_lane": 4, "reorder": 2}))
@@ -334,6 +339,106 @@ def tune_batch(gen_module, key_bits: int = 32, per_class: int = 64, queries_per_
     return best, records
 
 
+def batch_class_of(n: int):
+    """The batch size class (lo, hi) of an index of n keys."""
+    lg = max(0, math.ceil(math.log2(max(n, 1))))
+    for lo, hi in BATCH_CLASSES:
+        if lg <= hi:
+            return lo, hi
+    return BATCH_CLASSES[-1]
+
+
+def tune_batch_joint(gen_module, key_bits: int = 32, count: int = 1024, seed: int = 11, forms=None, table=None,
+                     log=None):
+    """Coordinate descent over the size classes on one representative batch:
+    `count` indexes with n log-uniform in [2^6, 2^22] and query batches
+    log-uniform in [1, 2^16] with 80% hits (the many-index configuration
+    scaled down), all served by one launch, so each class is timed under the
+    cache pressure of the others.  Every index starts in its class's current
+    form (the table's, else the per-class measurement's); class by class,
+    largest first, each candidate form is built for that class's indexes and
+    the whole launch is timed (median of 5 samples of 10 launches); the
+    fastest bit-exact form is kept before the next class.  Returns
+    ({class_lo: best record}, all records)."""
+    from ._binding import Batch
+    import numpy as np
+
+    forms = forms if forms is not None else BATCH_FORMS
+    table = table if table is not None else load_table()
+    dev = torch.device("cuda")
+    view = np.int32 if key_bits == 32 else np.int64
+    sizes = gen_module.log_uniform(seed, 1, 1 << 6, 1 << 22, count)
+    qcounts = gen_module.log_uniform(seed, 2, 1, 1 << 16, count)
+    keys, rows, qs, ex = [], [], [], []
+    for j in range(count):
+        kh, rh = gen_module.unique_keys(seed * 100003 + j, int(sizes[j]), key_bits)
+        qh, eh = gen_module.point_queries(seed * 100003 + j, int(sizes[j]), int(qcounts[j]), 0.8, key_bits)
+        keys.append(torch.from_numpy(kh.view(view)).to(dev))
+        rows.append(torch.from_numpy(rh.view(np.int32)).to(dev))
+        qs.append(qh)
+        ex.append(eh)
+    dq = torch.from_numpy(np.concatenate(qs).view(view)).to(dev)
+    de = torch.from_numpy(np.concatenate(ex).view(np.int32)).to(dev)
+    off = np.zeros(count + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(q) for q in qs])
+    doff = torch.from_numpy(off).to(dev)
+    out = torch.empty(len(dq), dtype=torch.int32, device=dev)
+    cls = [batch_class_of(int(n))[0] for n in sizes]
+    current = {lo: batch_form(1 << lo, key_bits, table) for lo, _ in BATCH_CLASSES}
+    idxs = [build_form(keys[j], rows[j], current[cls[j]]) for j in range(count)]
+
+    def timed():
+        with Batch(idxs) as bt:
+            out.fill_(-1)
+            bt.point(dq, doff, out)
+            torch.cuda.synchronize()
+            exact = bool(torch.equal(out, de))
+            ts = []
+            for _ in range(5):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(10):
+                    bt.point(dq, doff, out)
+                b.record()
+                b.synchronize()
+                ts.append(a.elapsed_time(b) / 10)
+        return sorted(ts)[len(ts) // 2], exact
+
+    best, records = {}, []
+    try:
+        for lo, hi in reversed(BATCH_CLASSES):
+            members = [j for j in range(count) if cls[j] == lo]
+            if not members:
+                continue
+            for form in forms:
+                layout, k, per_leaf, params = _form(form)
+                for j in members:
+                    idxs[j].close()
+                    idxs[j] = build_form(keys[j], rows[j], form)
+                used = idxs[members[0]].params()
+                ms, exact = timed()
+                rec = {"log2n_lo": lo, "log2n_hi": hi, "layout": layout, "k": k, "keys_per_leaf": per_leaf,
+                       "params": {f: used[f] for f in ("group", "lds_levels") if f in params},
+                       "ms": round(ms, 4), "lookups_per_s": len(dq) / ms * 1e3, "bit_exact": exact,
+                       "members": len(members), "lookups_in_class": int(sum(int(qcounts[j]) for j in members))}
+                records.append(rec)
+                if log:
+                    log(f"batch joint class 2^{lo}-2^{hi} ({len(members)} indexes) {layout} k={k} leaf={per_leaf} "
+                        f"{params}: whole launch {ms:.4f} ms exact={exact}")
+                if exact and (lo not in best or ms < best[lo]["ms"]):
+                    best[lo] = rec
+            win = best[lo]
+            current[lo] = (win["layout"], win["k"], win["keys_per_leaf"], win["params"])
+            for j in members:
+                idxs[j].close()
+                idxs[j] = build_form(keys[j], rows[j], current[lo])
+    finally:
+        for ix in idxs:
+            ix.close()
+    return best, records
+
+
 def record_batch(table: dict, key_bits: int, best: dict):
     table["batch"] = [e for e in table.get("batch", []) if e["key_bits"] != key_bits]
     for lo, rec in sorted(best.items()):
@@ -377,6 +482,8 @@ def _main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2506_01576_amd.autotune")
     ap.add_argument("--point", action="store_true", help="single-index forms per size class")
     ap.add_argument("--batch", action="store_true", help="batched-launch forms per size class")
+    ap.add_argument("--batch-joint", action="store_true",
+                    help="batched-launch forms per size class, timed inside one representative many-index launch")
     ap.add_argument("--bits", default="32,64")
     ap.add_argument("--log2n", default="12,16,20,23,25,26,29",
                     help="one measured size per class (log2 of the key count)")
@@ -418,8 +525,11 @@ def _main(argv=None):
                 torch.cuda.empty_cache()
                 if args.write:
                     save_table(table, args.out)
-        if args.batch:
-            best, _ = tune_batch(gen, bits, log=log)
+        if args.batch or args.batch_joint:
+            if args.batch_joint:
+                best, _ = tune_batch_joint(gen, bits, table=table, log=log)
+            else:
+                best, _ = tune_batch(gen, bits, log=log)
             table = record_batch(table, bits, best)
             for lo, rec in sorted(best.items()):
                 log(f"batch {bits}-bit class 2^{lo}: {rec['layout']} k={rec['k']} leaf={rec['keys_per_leaf']} "

@@ -112,6 +112,12 @@ struct PointIO {
     uint32_t *out;
     bool local_sort;       // sort each tile of lookups in LDS first (Section 7.4)
     bool xcd;              // walk tiles XCD by XCD
+    // a batch partitioned by rank bucket: the bucket of every lookup, and the
+    // rank interval [start(b), start(b) + span] that holds the lower bound of
+    // a key of bucket b, start(b) = b * step + (b > 0) (sorted array only)
+    const uint16_t *bkt = nullptr;
+    uint64_t bstep = 0;
+    uint64_t bspan = 0;
 };
 int point_lookup(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s);
 // One launch of the handle's point-lookup form over `io`.
@@ -137,7 +143,12 @@ struct PartView {
     uint32_t *ans;
     uint64_t m;
     void *scratch;
+    const uint16_t *bkt;  // bucket of every entry (partitioned order)
+    uint64_t bstep;       // ranks per bucket; lower bounds of bucket b lie in
+    uint64_t bspan;       // [b * bstep + (b > 0), that + bspan]
 };
+// Rank interval that holds the lower bound of a key of bucket b.
+__host__ __device__ inline uint64_t bucket_start(uint64_t b, uint64_t step) { return b ? b * step + 1 : 0; }
 constexpr uint64_t kPartChunk = 1ull << 31;
 size_t partition_scratch_bytes(const idx_index *h, uint64_t m);
 int partition_forward(idx_index *h, const void *q, uint64_t m, void *scratch, PartView *out, hipStream_t s);

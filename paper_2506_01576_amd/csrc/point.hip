@@ -71,7 +71,17 @@ __global__ __launch_bounds__(1024) void k_point_bs(PointArgs<K, AOS> a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) base[r] = 0;
         uint64_t len = n;
-        if (a.pin_levels) {
+        if (!SORT && a.io.bkt) {
+            // partitioned batch: each lookup's bucket bounds its lower bound,
+            // so the search starts inside that bucket's rank interval (the
+            // steps above it are the same for the whole bucket)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t qi = t0 + src_of<R, SORT>(src, r);
+                base[r] = qi < a.io.m ? bucket_start(a.io.bkt[qi], a.io.bstep) : 0;
+            }
+            len = a.io.bspan;
+        } else if (a.pin_levels) {
             uint32_t v[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) v[r] = 1;
@@ -443,6 +453,9 @@ PointArgs<K, AOS> make_args(const idx_index *h, const PointIO &io, uint32_t pin_
     a.io.local_sort = io.local_sort ? 1u : 0u;
     a.io.xcd = io.xcd ? 1u : 0u;
     a.io.rounds = h->params.window_rounds == 1 ? 1u : 2u;
+    a.io.bkt = io.bkt;
+    a.io.bstep = io.bstep;
+    a.io.bspan = io.bspan;
     a.pin = (const K *)h->pin;
     a.pin_entries = pin_levels ? h->pin_keys : 0;
     a.pin_levels = pin_levels;

@@ -40,6 +40,9 @@ struct QueryIO {
     uint32_t xcd;         // 1: XCD-contiguous tile order
     uint32_t sort_off;    // byte offset of the sort buffer in dynamic LDS
     uint32_t rounds;      // short-window scan: 1 = whole window at once, 2 = first line first
+    const uint16_t *__restrict__ bkt;  // partitioned batch: bucket of every lookup, or null
+    uint64_t bstep;       // its lower bound lies in [bucket_start(b, bstep), that + bspan]
+    uint64_t bspan;
 };
 
 // Tile of loop slot `it`; >= ntiles for the padding slots of the remap.

@@ -49,10 +49,12 @@ struct RangeArgs {
 // in lockstep; while their intervals coincide the second reads nothing of
 // its own.  The SoA array stops at a window of at most 15 keys and reads it
 // with independent 16-byte loads (the short-window scan).
+// Both lower bounds are known to lie in [base, base + len] (base + len <= n).
 template <typename K, bool AOS>
-__device__ __forceinline__ void bs_ranks(const RangeArgs<K, AOS> &a, K x0, K x1, uint64_t &r0, uint64_t &r1) {
+__device__ __forceinline__ void bs_ranks_in(const RangeArgs<K, AOS> &a, uint64_t base, uint64_t len, K x0, K x1,
+                                            uint64_t &r0, uint64_t &r1) {
     const uint64_t n = a.G.n;
-    uint64_t b0 = 0, b1 = 0, len = n;
+    uint64_t b0 = base, b1 = base;
     const uint64_t stop = AOS ? 1 : 15;
     while (len > stop) {
         const uint64_t half = len >> 1;
@@ -69,9 +71,14 @@ __device__ __forceinline__ void bs_ranks(const RangeArgs<K, AOS> &a, K x0, K x1,
         r0 = b0 + count_below<K, 16>(a.L.k, b0, (uint32_t)s0, x0, eq);
         r1 = b1 + count_below<K, 16>(a.L.k, b1, (uint32_t)s1, x1, eq);
     } else {
-        r0 = b0 + (a.L.key(b0) < x0 ? 1 : 0);
-        r1 = b1 + (a.L.key(b1) < x1 ? 1 : 0);
+        r0 = b0 + (b0 < n && a.L.key(b0) < x0 ? 1 : 0);
+        r1 = b1 + (b1 < n && a.L.key(b1) < x1 ? 1 : 0);
     }
+}
+
+template <typename K, bool AOS>
+__device__ __forceinline__ void bs_ranks(const RangeArgs<K, AOS> &a, K x0, K x1, uint64_t &r0, uint64_t &r1) {
+    bs_ranks_in(a, 0, a.G.n, x0, x1, r0, r1);
 }
 
 // Eytzinger layouts: lower-bound ranks of x0 and of x1 >= x0 (when `two`),
@@ -181,18 +188,39 @@ __global__ __launch_bounds__(256) void k_range_count(RangeArgs<K, AOS> a) {
 // there.  The tiles are walked XCD by XCD, so the ranges one XCD has in
 // flight fall in a few buckets whose slice of the index stays in its L2.
 // Both ranks go out in partitioned order.
+// On the sorted array the lower bound's bucket bounds its rank (see
+// bucket_start): both searches start inside that interval, and the upper
+// bound's search widens to the rest of the array only when its answer is
+// past the interval (a range that leaves the bucket).
 template <typename K, bool AOS>
 __global__ __launch_bounds__(256) void k_range_count_part(RangeArgs<K, AOS> a, const K *__restrict__ q2,
-                                                          const uint32_t *__restrict__ pos, uint64_t ntiles,
-                                                          uint64_t iters, uint32_t *__restrict__ r0o,
-                                                          uint32_t *__restrict__ r1o) {
+                                                          const uint32_t *__restrict__ pos,
+                                                          const uint16_t *__restrict__ bkt, uint64_t bstep,
+                                                          uint64_t bspan, uint64_t ntiles, uint64_t iters,
+                                                          uint32_t *__restrict__ r0o, uint32_t *__restrict__ r1o) {
     for (uint64_t it = blockIdx.x; it < iters; it += gridDim.x) {
         const uint64_t tl = tile_of(it, ntiles, 1);
         if (tl >= ntiles) continue;
         const uint64_t j = tl * 256 + threadIdx.x;
         if (j >= a.m) continue;
-        uint64_t r0, r1;
-        range_ranks(a, q2[j], a.hi[pos[j]], r0, r1);
+        const K L = q2[j], U = a.hi[pos[j]];
+        uint64_t r0 = 0, r1 = 0;
+        if (a.layout == IDX_BS && L <= U) {
+            const bool top = U == key_max<K>();
+            const K x1 = top ? U : (K)(U + 1);
+            const uint64_t base = bucket_start(bkt[j], bstep);
+            bs_ranks_in(a, base, bspan, L, x1, r0, r1);
+            // the window scan may also count the key at base + bspan, so an
+            // answer past the interval shows as end or end + 1
+            const uint64_t end = base + bspan;
+            if (r1 >= end && end < a.G.n) {
+                uint64_t unused;
+                bs_ranks_in(a, end, a.G.n - end, x1, x1, r1, unused);
+            }
+            if (top) r1 = a.G.n;
+        } else {
+            range_ranks(a, L, U, r0, r1);
+        }
         r0o[j] = (uint32_t)r0;
         r1o[j] = (uint32_t)r1;
     }
@@ -229,7 +257,7 @@ int range_count_partitioned(idx_index *h, const RangeArgs<K, AOS> &a, hipStream_
         const uint64_t tiles = (mc + 255) / 256;
         const uint64_t iters = ((tiles + kXcds - 1) / kXcds) * kXcds;
         hipLaunchKernelGGL((k_range_count_part<K, AOS>), dim3((uint32_t)iters), dim3(256), 0, s, b, (const K *)v.q,
-                           v.pos, tiles, iters, v.ans, r1p);
+                           v.pos, v.bkt, v.bstep, v.bspan, tiles, iters, v.ans, r1p);
         if (hipGetLastError() != hipSuccess) {
             rc = IDX_ERR_HIP;
             break;

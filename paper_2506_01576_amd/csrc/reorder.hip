@@ -278,6 +278,7 @@ __global__ __launch_bounds__(kPartThreads) void k_scatter(ScatterArgs<K, Pass> a
                     } else if constexpr (!BWD) {
                         a.q_out[d[u]] = a.q_in[i];
                         a.p_out[d[u]] = a.p_in[i];
+                        a.b_out[d[u]] = a.b_in[i];
                     } else {
                         a.pk_out[d[u]] = ((uint64_t)a.p_in[i] << 32) | a.r_in[i];
                     }
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(kPartThreads) void k_scatter(ScatterArgs<K, Pass> a
                 } else {
                     qq[u] = a.q_in[i];
                     pp[u] = COARSE ? (uint32_t)i : a.p_in[i];
-                    bb[u] = COARSE ? a.b_in[i] : (uint16_t)0;
+                    bb[u] = a.b_in[i];
                 }
             }
             __syncthreads();
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(kPartThreads) void k_scatter(ScatterArgs<K, Pass> a
                 } else {
                     st_q[j] = qq[u];
                     st_p[j] = pp[u];
-                    if constexpr (COARSE) st_b[j] = bb[u];
+                    st_b[j] = bb[u];
                 }
             }
             __syncthreads();
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(kPartThreads) void k_scatter(ScatterArgs<K, Pass> a
                 } else {
                     a.q_out[d] = st_q[j];
                     a.p_out[d] = st_p[j];
-                    if constexpr (COARSE) a.b_out[d] = st_b[j];
+                    a.b_out[d] = st_b[j];
                 }
             }
             __syncthreads();
@@ -392,6 +393,18 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place(const uint64_t *__restr
         for (uint32_t r = 0; r < kPlacePer; ++r)
             if (v[r] != ~0ull) out[v[r] >> 32] = (uint32_t)v[r];
     }
+}
+
+// Length of the rank interval [bucket_start(b), that + span] holding the
+// lower bound of any key of bucket b: splitter b - 1 (rank b * step) is below
+// the key and splitter b (rank (b + 1) * step) is not, so the lower bound is
+// in [b * step + 1, (b + 1) * step] (from 0 for b = 0, up to n for the last
+// bucket); the largest such interval serves every bucket and never reaches
+// past n.
+uint64_t bucket_span(uint64_t n, uint32_t B) {
+    const uint64_t step = n / B;
+    const uint64_t last = n - (B - 1) * step - 1;
+    return step > last ? step : last;
 }
 
 // Bucket count for the handle: a power of two giving about kBucketBytes of
@@ -440,7 +453,7 @@ struct PartBufs {
     void *q1;         // coarse-partitioned queries; later the (position, answer) pairs
     uint32_t *p1;     // coarse-partitioned positions; later the answers in partitioned order
     uint16_t *b1;     // coarse-partitioned fine bucket ids
-    uint16_t *bkt;    // fine bucket id of every query
+    uint16_t *bkt;    // fine bucket id of every query; after the fine pass, in partitioned order
     void *q2;         // fine-partitioned queries
     uint32_t *p2;     // fine-partitioned positions
     uint32_t *total;  // kMaxBuckets per-bucket totals
@@ -521,6 +534,7 @@ int partition_fwd(idx_index *h, const K *q, uint64_t m, uint32_t B, const PartBu
         a.b_in = P.b1;
         a.q_out = (K *)P.q2;
         a.p_out = P.p2;
+        a.b_out = P.bkt;  // caller-order bucket ids are no longer needed
         a.cur = P.fcur;
         a.m = m;
         a.ntiles = tiles;
@@ -576,8 +590,14 @@ int partition_chunk(idx_index *h, const K *q, uint64_t m, uint32_t *out, uint32_
                     hipStream_t s) {
     int rc = partition_fwd<K>(h, q, m, B, P, s);
     if (rc != IDX_OK) return rc;
-    // answers in partitioned order go to p1 (free after the fine pass)
+    // answers in partitioned order go to p1 (free after the fine pass); the
+    // sorted array's search starts inside each lookup's bucket
     PointIO io{P.q2, m, P.p1, false, true};
+    if (h->layout == IDX_BS && !(h->learned && h->params.model != 2)) {
+        io.bkt = P.bkt;
+        io.bstep = h->n / B;
+        io.bspan = bucket_span(h->n, B);
+    }
     rc = point_run(h, io, s);
     if (rc != IDX_OK) return rc;
     return place_back(h, P, m, P.p1, out, s);
@@ -605,6 +625,9 @@ int partition_forward(idx_index *h, const void *q, uint64_t m, void *scratch, Pa
     out->ans = P.p1;
     out->m = m;
     out->scratch = scratch;
+    out->bkt = P.bkt;
+    out->bstep = h->n / B;
+    out->bspan = bucket_span(h->n, B);
     return IDX_OK;
 }
 

@@ -152,3 +152,27 @@ def test_partitioned_scatter_paths(m):
             torch.cuda.synchronize()
             assert torch.equal(got, to_dev(expect))
             assert np.array_equal(rows_host(got)[sample], want_s)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("aos", [False, True])
+def test_partitioned_duplicates_many_buckets(bits, aos):
+    """The sorted array's partitioned search starts inside each lookup's
+    bucket; with every key repeated about 8 times, equal splitters border
+    many buckets.  n = 2^21 + 3 keys, 2^20 + 7 lookups (half hits, some
+    below and above every key): every answer equals the oracle's (the first
+    row ID of the key in stable order)."""
+    n, m = (1 << 21) + 3, (1 << 20) + 7
+    keys, rows = key_set(90 + bits, n, bits, True)
+    keys = (keys // 2 + 3).astype(keys.dtype)  # about 8 copies of each value
+    q = queries(91 + bits, keys, m, bits)
+    q[:3] = np.array([0, 1, 2], dtype=q.dtype)  # below every key
+    sk, sr = oracle.stable_sort(keys, rows)
+    want = oracle.point(sk, sr, q, nthreads=8)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs", aos=aos) as ix:
+        for params in ({"reorder": 2}, {"reorder": 2, "per_lane": 8}):
+            ix.set_params(**params)
+            say(f"partitioned duplicates bits={bits} aos={aos} {params}")
+            got = rows_host(ix.point(to_dev(q)))
+            bad = np.nonzero(got != want)[0]
+            assert len(bad) == 0, f"{len(bad)} mismatches, first q={q[bad[0]]} got={got[bad[0]]} want={want[bad[0]]}"
