@@ -299,7 +299,9 @@ typedef struct idx_lookup_params {
     uint32_t reorder;    /* 1 = sort each workgroup's point lookups locally before searching;
                             2 = partition the batch by rank bucket of the index first (point
                             lookups, and the count phase of range lookups by their lower bounds),
-                            answers returned to the caller's order */
+                            answers returned to the caller's order by two counting passes;
+                            3 = the same partition, each point answer written straight to its
+                            position */
     uint32_t early_exit; /* 1 = stop at an equal key (only used when keys are unique) */
     uint32_t model;      /* 0/1 = use the learned model when one is trained (idx_learn), 2 = ignore it */
     uint32_t window_rounds; /* short-window scan (BS and learned forms): 0 = default (2); 2 = read the
@@ -429,7 +431,7 @@ typedef struct idx_batch *idx_batch_t;
 /*
  * idx_batch_create -- gather `count` indexes (same key width, SoA layouts;
  * any of BS, EBS, EKS, or BS with a learned model) into one batch.  Each
- * member's descriptor copies four of its lookup parameters (idx_set_params),
+ * member's descriptor copies five of its lookup parameters (idx_set_params),
  * so the autotuner can choose them per size class:
  *   model       whether its learned model is used;
  *   early_exit  the EKS early exit on an equal key;
@@ -439,12 +441,14 @@ typedef struct idx_batch *idx_batch_t;
  *   lds_levels  top levels served from LDS (cache pinning, Section 7.3): a
  *               workgroup whose chunk of lookups belongs to one member copies
  *               that member's pin table into LDS first (not for the learned
- *               form); the launch reserves LDS for the largest table.
+ *               form); the launch reserves LDS for the largest table;
+ *   range_scan  how idx_batch_mixed collects an Eytzinger member's range
+ *               row IDs (gather by rank, or the level scan).
  * The batch's device descriptors point at the members' layout, pin and model
  * buffers, so until idx_batch_destroy every member is held: on a held handle
  * idx_destroy, idx_learn, idx_unlearn and idx_learn_batch return IDX_ERR_ARG
  * and change nothing, and idx_set_params returns IDX_ERR_ARG for a parameter
- * set that changes any of the four copied parameters.  A handle may belong to
+ * set that changes any of the five copied parameters.  A handle may belong to
  * several batches.  Synchronises `stream`.  Errors: IDX_ERR_ARG (null, mixed
  * key widths, AoS layout), IDX_ERR_NOMEM.
  */

@@ -78,6 +78,9 @@ def candidates(key_bits: int, n: int):
         out.append(("ebs", 2, False, {"reorder": 2, "per_lane": 8}))
         out.append(("ebs", 2, False, {"reorder": 2, "per_lane": 4}))
         out.append(("eks", 9, False, {"group": 1, "per_lane": 4, "reorder": 2}))
+        # the partition with each answer written straight to its position
+        out.append(("bs", 1, False, {"reorder": 3, "per_lane": 4}))
+        out.append(("ebs", 2, False, {"reorder": 3, "per_lane": 4}))
         out.append(("eks", 17, "padded", {"group": 1, "per_lane": 4, "reorder": 2}))
     return out
 

@@ -430,10 +430,11 @@ int idx_set_params(idx_handle h, const idx_lookup_params *p) {
     const int rc = resolve_params(h, p, &r);
     if (rc != IDX_OK) return rc;
     // the batch descriptors holding h copied its use of the model, its early
-    // exit, its EKS lanes per lookup and its pinned levels (and point at its
-    // pin table)
+    // exit, its EKS lanes per lookup, its pinned levels (and point at its pin
+    // table) and its range fill
     if (h->batch_refs && (r.model != h->params.model || r.early_exit != h->params.early_exit ||
-                          r.group != h->params.group || r.lds_levels != h->params.lds_levels))
+                          r.group != h->params.group || r.lds_levels != h->params.lds_levels ||
+                          r.range_scan != h->params.range_scan))
         return IDX_ERR_ARG;
     h->params = r;
     return IDX_OK;

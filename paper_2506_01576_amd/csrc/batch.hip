@@ -15,10 +15,12 @@
 // first persistent launch answers every point lookup and sizes every range
 // (first and past-the-end rank of its bounds), an exclusive scan turns the
 // sizes into output offsets, and a second persistent launch writes each
-// range's row IDs in key order -- a wave-cooperative copy of the contiguous
-// run on the sorted-array forms, the level scan with rank scatter of
-// Section 5 on the Eytzinger forms (each index's tree geometry is kept in a
-// device table beside its descriptor).
+// range's row IDs in key order -- a wave-cooperative copy of the run of
+// ranks [first, first + count): contiguous on the sorted-array forms, read at
+// the slots the layout build wrote those ranks to on the Eytzinger forms (or,
+// when a member asks for it, the level scan with rank scatter of Section 5);
+// each index's tree geometry is kept in a device table beside its
+// descriptor.
 #include <new>
 #include <vector>
 
@@ -43,7 +45,9 @@ struct __align__(16) Desc {
     uint32_t pin_levels;    // levels served from LDS (0 = none)
     uint32_t pin_keys;      // entries of `pin`
     RootRec root;           // learned form only
-    uint32_t vec, pad1, pad2, pad3;  // vec: EKS nodes read with 16-byte loads
+    uint32_t vec;           // EKS nodes read with 16-byte loads
+    uint32_t rscan;         // Eytzinger ranges: 3 = gather by rank, 1/2 = level scan (range_scan)
+    uint64_t kinv;          // ceil(2^64 / k) for the rank-to-slot map (k > 2)
 };
 static_assert(sizeof(Desc) == 144, "descriptor layout");
 
@@ -553,6 +557,9 @@ __global__ __launch_bounds__(BT) void k_batch_point(const Desc *__restrict__ des
 // ------------------------------------------------------------ mixed stream
 
 enum : uint8_t { Q_POINT = 0, Q_RANGE = 1 };
+// Where a range's ranks are stored: the sorted array itself, or the slots of
+// the binary / k-ary Eytzinger layout the build wrote them to.
+enum : uint32_t { MAP_SORTED = 0, MAP_BINARY = 1, MAP_KARY = 2 };
 
 // Sorted rank of the first key >= x in the index of descriptor d.
 // Lower-bound rank of x in index d.  EYT selects the forms compiled in:
@@ -756,10 +763,16 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
                                                          const uint64_t *__restrict__ offs,
                                                          uint32_t *__restrict__ rows_out) {
     // per wave: the start of each lane's run in the wave's concatenation of
-    // runs, and source / destination pointers offset by that start
+    // runs, the run's row IDs, its first rank and destination offset by that
+    // start, and where its ranks are stored (sorted array: the rank itself;
+    // Eytzinger layouts: the slot the layout build wrote the rank to)
     __shared__ uint32_t s_start[BT / kWave][kWave + 1];
-    __shared__ const uint32_t *s_src[BT / kWave][kWave];
+    __shared__ const uint32_t *s_rows[BT / kWave][kWave];
+    __shared__ int64_t s_rank0[BT / kWave][kWave];
     __shared__ uint32_t *s_dst[BT / kWave][kWave];
+    __shared__ const Geo *s_geo[BT / kWave][kWave];
+    __shared__ uint64_t s_kinv[BT / kWave][kWave];
+    __shared__ uint32_t s_mode[BT / kWave][kWave];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint64_t wave_global = ((uint64_t)blockIdx.x * BT + threadIdx.x) / kWave;
     const uint64_t waves = (uint64_t)gridDim.x * (BT / kWave);
@@ -776,7 +789,9 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
             // this lane's run: a sorted-array range is copied by the whole
             // wave below; an Eytzinger range is scanned by its own lane
             const uint32_t *run_rows = nullptr;
-            uint64_t run_first = 0, run_out = 0, run_len = 0;
+            uint64_t run_first = 0, run_out = 0, run_len = 0, run_kinv = 0;
+            uint32_t run_mode = MAP_SORTED;
+            const Geo *run_geo = nullptr;
             bool paused = false;
             ScanState st{};
             uint64_t scan_o = 0, scan_cnt = 0;
@@ -790,6 +805,14 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
                         run_out = o;
                         run_len = cnt;
                     }
+                } else if (cnt > 0 && is_eyt(d.form) && d.rscan == 3) {
+                    run_rows = d.rows;
+                    run_first = first[p];
+                    run_out = o;
+                    run_len = cnt;
+                    run_mode = d.form == F_EBS ? MAP_BINARY : MAP_KARY;
+                    run_geo = geos + ii;
+                    run_kinv = d.kinv;
                 } else if (cnt > 0 && is_eyt(d.form)) {
                     const Geo &Gi = geos[ii];
                     const uint64_t eoff = d.form == F_EBS ? 1 : 0;
@@ -831,11 +854,11 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
                 eyt_scan_wave(Lw, geos[wi], dw.form == F_EBS ? 1 : 0, lo[wp], hi[wp], (uint64_t)first[wp], wcnt,
                               rows_out + wo, w);
             }
-            // wave-cooperative copy of the lanes' sorted-array runs: every
-            // element finds its run by a binary search over the runs' starts
-            // (per wave, in LDS), so the wave copies 64 elements per step with
-            // CU independent loads per lane in flight
-            if constexpr (!EYT) {
+            // wave-cooperative copy of the lanes' runs: every element finds
+            // its run by a binary search over the runs' starts (per wave, in
+            // LDS), so the wave copies 64 elements per step with CU
+            // independent loads per lane in flight
+            {
                 const uint32_t w = threadIdx.x / kWave;
                 uint32_t len32 = (uint32_t)run_len, incl = len32;
 #pragma unroll
@@ -848,8 +871,12 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
                     const uint32_t start = incl - len32;
                     s_start[w][lane] = start;
                     if (lane == kWave - 1) s_start[w][kWave] = total;
-                    s_src[w][lane] = (const uint32_t *)run_rows + run_first - start;
+                    s_rows[w][lane] = run_rows;
+                    s_rank0[w][lane] = (int64_t)run_first - (int64_t)start;
                     s_dst[w][lane] = rows_out + run_out - start;
+                    s_geo[w][lane] = run_geo;
+                    s_kinv[w][lane] = run_kinv;
+                    s_mode[w][lane] = run_mode;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -864,7 +891,14 @@ __global__ __launch_bounds__(BT) void k_batch_mixed_fill(const Desc *__restrict_
                             for (uint32_t step = kWave / 2; step > 0; step >>= 1)
                                 if (s_start[w][lo + step] <= t) lo += step;
                             q[u] = lo;
-                            if (t < total) v[u] = s_src[w][lo][t];
+                            if (t < total) {
+                                const uint64_t rank = (uint64_t)(s_rank0[w][lo] + (int64_t)t);
+                                uint64_t slot = rank;
+                                if (EYT && s_mode[w][lo] == MAP_BINARY) slot = 1 + rank_slot_binary(*s_geo[w][lo], rank);
+                                else if (EYT && s_mode[w][lo] == MAP_KARY)
+                                    slot = rank_slot_general(*s_geo[w][lo], rank, s_kinv[w][lo]);
+                                v[u] = s_rows[w][lo][slot];
+                            }
                         }
 #pragma unroll
                         for (int u = 0; u < CU; ++u) {
@@ -962,6 +996,8 @@ int idx_batch_create(const idx_handle *indexes, uint32_t count, idx_stream strea
         // lookup, and the top levels pinned in LDS (its pin table)
         d.lanes = h->layout == IDX_EKS ? h->params.group : 1u;
         d.vec = (h->layout == IDX_EKS && scan_vec_ok(h->geo, 0, h->u64 ? 8 : 4, false)) ? 1u : 0u;
+        d.rscan = h->params.range_scan;
+        d.kinv = h->geo.k > 2 ? ~0ull / h->geo.k + 1 : 0;  // ceil(2^64 / k)
         if (h->params.lds_levels && !(h->learned && h->params.model != 2)) {
             const int rc = build_pin(h, h->params.lds_levels, (hipStream_t)stream);
             if (rc != IDX_OK) return rc;

@@ -118,6 +118,8 @@ struct PointIO {
     const uint16_t *bkt = nullptr;
     uint64_t bstep = 0;
     uint64_t bspan = 0;
+    // answer of lookup i goes to out[pos[i]] (nullptr: out[i])
+    const uint32_t *pos = nullptr;
 };
 int point_lookup(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s);
 // One launch of the handle's point-lookup form over `io`.

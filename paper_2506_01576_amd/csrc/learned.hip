@@ -708,6 +708,7 @@ int point_learned(idx_index *h, const PointIO &pio, hipStream_t s) {
         io.xcd = pio.xcd ? 1u : 0u;                                                                         \
         io.sort_off = 0;                                                                                    \
         io.rounds = h->params.window_rounds == 1 ? 1u : 2u;                                                 \
+        io.pos = pio.pos;                                                                                   \
         set_tiles(io, tile);                                                                                \
         uint64_t grid = io.iters;                                                                           \
         if (h->params.persistent) {                                                                         \

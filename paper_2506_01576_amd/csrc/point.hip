@@ -255,7 +255,7 @@ __global__ __launch_bounds__(1024) void k_point_eks_group(PointArgs<K, AOS> a) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const uint64_t qi = wbase + (uint64_t)r * GPW + grp;
-                if (qi < a.io.m) a.io.out[qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
+                if (qi < a.io.m) a.io.out[a.io.pos ? a.io.pos[qi] : qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
             }
         }
     }
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(1024) void k_point_eks_vgroup(PointArgs<K, AOS> a) 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const uint64_t qi = wbase + (uint64_t)r * GPW + grp;
-                if (qi < a.io.m) a.io.out[qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
+                if (qi < a.io.m) a.io.out[a.io.pos ? a.io.pos[qi] : qi] = ceq[r] ? a.L.row(cand[r]) : kMiss;
             }
         }
     }
@@ -453,6 +453,7 @@ PointArgs<K, AOS> make_args(const idx_index *h, const PointIO &io, uint32_t pin_
     a.io.local_sort = io.local_sort ? 1u : 0u;
     a.io.xcd = io.xcd ? 1u : 0u;
     a.io.rounds = h->params.window_rounds == 1 ? 1u : 2u;
+    a.io.pos = io.pos;
     a.io.bkt = io.bkt;
     a.io.bstep = io.bstep;
     a.io.bspan = io.bspan;
@@ -654,8 +655,9 @@ int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_p
     if (p.persistent > 64) return IDX_ERR_ARG;
     // lookup reordering: 0 = none; 1 = sort each tile of block * per_lane
     // lookups in LDS (one lookup per lane only); 2 = partition the batch by
-    // rank bucket first
-    if (p.reorder > 2) return IDX_ERR_ARG;
+    // rank bucket first, answers returned by two counting passes; 3 = the
+    // same partition, each answer written straight to its position
+    if (p.reorder > 3) return IDX_ERR_ARG;
     if (p.reorder == 1) {
         const uint64_t T = (uint64_t)p.block * p.per_lane;
         if (p.group > 1 || T > kMaxSortTile) return IDX_ERR_ARG;
@@ -690,7 +692,7 @@ int point_run(idx_index *h, const PointIO &io, hipStream_t s) {
 
 int point_lookup(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s) {
     if (m == 0) return IDX_OK;
-    if (h->params.reorder == 2) return point_partitioned(h, q, m, out, s);
+    if (h->params.reorder >= 2) return point_partitioned(h, q, m, out, s);
     PointIO io{q, m, out, h->params.reorder == 1, false};
     return point_run(h, io, s);
 }

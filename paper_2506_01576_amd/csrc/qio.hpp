@@ -40,6 +40,7 @@ struct QueryIO {
     uint32_t xcd;         // 1: XCD-contiguous tile order
     uint32_t sort_off;    // byte offset of the sort buffer in dynamic LDS
     uint32_t rounds;      // short-window scan: 1 = whole window at once, 2 = first line first
+    const uint32_t *__restrict__ pos;  // answer of lookup i goes to out[pos[i]] (null: out[i])
     const uint16_t *__restrict__ bkt;  // partitioned batch: bucket of every lookup, or null
     uint64_t bstep;       // its lower bound lies in [bucket_start(b, bstep), that + bspan]
     uint64_t bspan;
@@ -137,7 +138,7 @@ __device__ __forceinline__ void tile_put(const QueryIO<K> &io, char *smem, uint6
         ((uint32_t *)(smem + io.sort_off))[src] = v;
     } else {
         const uint64_t qi = t0 + src;
-        if (qi < io.m) io.out[qi] = v;
+        if (qi < io.m) io.out[io.pos ? io.pos[qi] : qi] = v;
     }
 }
 

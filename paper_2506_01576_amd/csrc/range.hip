@@ -513,7 +513,7 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
         if (h->learned && h->params.model != 2) {
             rc = range_count_learned(h, lo, hi, m, a.first_rank, offsets, s);
             if (rc != IDX_OK) break;
-        } else if (h->params.reorder == 2 && !given && h->n >= 4) {
+        } else if (h->params.reorder >= 2 && !given && h->n >= 4) {
             // the caller-given scratch (no-allocation entry point) has no room
             // for the partition: those calls count unpartitioned
             rc = range_count_partitioned(h, a, s);

@@ -590,16 +590,19 @@ int partition_chunk(idx_index *h, const K *q, uint64_t m, uint32_t *out, uint32_
                     hipStream_t s) {
     int rc = partition_fwd<K>(h, q, m, B, P, s);
     if (rc != IDX_OK) return rc;
-    // answers in partitioned order go to p1 (free after the fine pass); the
-    // sorted array's search starts inside each lookup's bucket
-    PointIO io{P.q2, m, P.p1, false, true};
+    // answers in partitioned order go to p1 (free after the fine pass), or
+    // (reorder = 3) straight to their positions in out; the sorted array's
+    // search starts inside each lookup's bucket
+    const bool direct = h->params.reorder == 3;
+    PointIO io{P.q2, m, direct ? out : P.p1, false, true};
+    if (direct) io.pos = P.p2;
     if (h->layout == IDX_BS && !(h->learned && h->params.model != 2)) {
         io.bkt = P.bkt;
         io.bstep = h->n / B;
         io.bspan = bucket_span(h->n, B);
     }
     rc = point_run(h, io, s);
-    if (rc != IDX_OK) return rc;
+    if (rc != IDX_OK || direct) return rc;
     return place_back(h, P, m, P.p1, out, s);
 }
 

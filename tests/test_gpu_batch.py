@@ -210,7 +210,8 @@ def test_batch_holds_its_members():
     bt2 = idx.Batch([e, a])  # a handle may belong to two batches
     for call in (lambda: a.learn(32, 2), a.unlearn, a.close, lambda: idx.learn_batch([a], [16]),
                  lambda: a.set_params(model=2), e.close, lambda: e.set_params(early_exit=2),
-                 lambda: e.set_params(group=8), lambda: e.set_params(lds_levels=2)):
+                 lambda: e.set_params(group=8), lambda: e.set_params(lds_levels=2),
+                 lambda: e.set_params(range_scan=1)):
         with pytest.raises(idx.IdxError) as ei:
             call()
         assert ei.value.status == idx.IDX_ERR_ARG

@@ -169,8 +169,9 @@ def mixed_stream(indexes_keys, seed, bits, per_index):
     return los, his, kinds, off
 
 
+@pytest.mark.parametrize("rscan", [3, 1])
 @pytest.mark.parametrize("bits", [32, 64])
-def test_batch_mixed_parity(bits):
+def test_batch_mixed_parity(bits, rscan):
     sizes = [0, 1, 3, 64, 1000, 4097, 20011, 65536, 131071, 5000, 300, 99991]
     rng = np.random.default_rng(bits)
     per_index = [0 if j == 5 else int(x) for j, x in enumerate(rng.integers(1, 6000, len(sizes)))]
@@ -185,6 +186,8 @@ def test_batch_mixed_parity(bits):
                 ix.learn(max(1, len(keys) // 64), 2)
         else:
             ix = idx.Index(to_dev(keys), to_dev(rows), layout=layout, k=k)
+            # Eytzinger members: row IDs gathered by rank (3) or the level scan (1)
+            ix.set_params(range_scan=rscan)
         made.append((keys, rows))
         ixs.append(ix)
     los, his, kinds, off = mixed_stream([k for k, _ in made], 77 + bits, bits, per_index)

@@ -317,7 +317,7 @@ def test_bad_params_rejected():
     with build(keys, rows, "eks", 9) as ix:
         before = ix.params()
         for bad in ({"group": 128}, {"group": 3}, {"block": 96}, {"per_lane": 3}, {"lds_levels": 30},
-                    {"early_exit": 3}, {"reorder": 3}, {"reorder": 1, "group": 8}, {"range_scan": 4}):
+                    {"early_exit": 3}, {"reorder": 4}, {"reorder": 1, "group": 8}, {"range_scan": 4}):
             with pytest.raises(idx.IdxError):
                 ix.set_params(**bad)
             assert ix.params() == before

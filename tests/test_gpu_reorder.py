@@ -74,7 +74,7 @@ def make(keys, rows, layout, k, aos):
 
 
 @pytest.mark.parametrize("bits", [32, 64])
-@pytest.mark.parametrize("reorder", [1, 2])
+@pytest.mark.parametrize("reorder", [1, 2, 3])
 @pytest.mark.parametrize("form", range(len(FORMS)))
 def test_reorder_parity(form, reorder, bits):
     layout, k, aos, params = FORMS[form]
@@ -119,7 +119,8 @@ def test_partitioned_many_buckets(layout, k, aos, bits):
     sample = rng.integers(0, m, 4096)
     want_s = oracle.point(sk, sr, q[sample], nthreads=8)
     with make(keys, rows, layout, k, aos) as ix:
-        for params in ({"reorder": 2}, {"reorder": 2, "persistent": 2, "block": 1024, "per_lane": 4}):
+        for params in ({"reorder": 2}, {"reorder": 2, "persistent": 2, "block": 1024, "per_lane": 4},
+                       {"reorder": 3}):
             ix.set_params(**params)
             say(f"partitioned {layout} k={k} aos={aos} bits={bits} {ix.params()}")
             got = ix.point(to_dev(q))
@@ -146,12 +147,13 @@ def test_partitioned_scatter_paths(m):
     want_s = oracle.point(sk, sr, q[sample], nthreads=8)
     for layout, k in (("bs", 1), ("ebs", 2)):
         with idx.Index(to_dev(keys), to_dev(rows), layout=layout, k=k) as ix:
-            ix.set_params(reorder=2)
-            say(f"partitioned paths {layout} n={n} m={m}")
-            got = ix.point(to_dev(q))
-            torch.cuda.synchronize()
-            assert torch.equal(got, to_dev(expect))
-            assert np.array_equal(rows_host(got)[sample], want_s)
+            for reorder in (2, 3):
+                ix.set_params(reorder=reorder)
+                say(f"partitioned paths {layout} n={n} m={m} reorder={reorder}")
+                got = ix.point(to_dev(q))
+                torch.cuda.synchronize()
+                assert torch.equal(got, to_dev(expect))
+                assert np.array_equal(rows_host(got)[sample], want_s)
 
 
 @pytest.mark.parametrize("bits", [32, 64])
@@ -170,7 +172,7 @@ def test_partitioned_duplicates_many_buckets(bits, aos):
     sk, sr = oracle.stable_sort(keys, rows)
     want = oracle.point(sk, sr, q, nthreads=8)
     with idx.Index(to_dev(keys), to_dev(rows), layout="bs", aos=aos) as ix:
-        for params in ({"reorder": 2}, {"reorder": 2, "per_lane": 8}):
+        for params in ({"reorder": 2}, {"reorder": 2, "per_lane": 8}, {"reorder": 3}):
             ix.set_params(**params)
             say(f"partitioned duplicates bits={bits} aos={aos} {params}")
             got = rows_host(ix.point(to_dev(q)))
