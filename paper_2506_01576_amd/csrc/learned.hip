@@ -610,6 +610,89 @@ __device__ __forceinline__ uint32_t count_below_slots(const Load<K, true> &L, ui
     return cnt;
 }
 
+// Window scan on the packed array of structures (64-bit key and 32-bit row
+// ID per 12-byte slot): the slots [b, b + len) (len <= W) are read as aligned
+// 16-byte chunks, every chunk of a round issued at once, and keys and row IDs
+// are taken from the registers, so a hit needs no further load.  (Loading the
+// row ID after the keys were counted often found its line evicted from L2:
+// with hundreds of thousands of lookups in flight per XCD a line does not
+// stay there long.)  Two rounds as in count_below_slots: first the chunks of
+// the 128-byte line of the window's first chunk, the rest only when every
+// slot read so far is below x.  A slot starts at word S + 3 j of the chunks,
+// S = (12 b mod 16) / 4 differing from lane to lane: the loads do not depend
+// on S (so no lane waits for another's), and each word is selected from the
+// four candidates by S after they arrive.
+template <int W>
+__device__ __forceinline__ uint32_t count_below_packed(const char *__restrict__ base, uint64_t b, uint32_t len,
+                                                       uint64_t x, bool &eq, uint32_t &row, bool two) {
+    constexpr int NC = (3 * 4 + W * 12 + 15) / 16;  // chunks covering W slots from any word S <= 3
+    const char *p0 = base + ((b * 12) & ~(uint64_t)15);
+    const uint32_t S = (uint32_t)((b * 12) & 15) >> 2;
+    const uint64_t line0 = (uint64_t)(uintptr_t)p0 >> 7;
+    const uint32_t end_word = S + 3 * len;  // words [S, end_word) hold the window
+    uint4 w[NC];
+    uint32_t got = 0;  // bit c: chunk c loaded
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const bool need = (uint32_t)(4 * c) < end_word;
+        const bool first = !two || ((uint64_t)(uintptr_t)(p0 + 16 * c) >> 7) == line0;
+        w[c] = make_uint4(0u, 0u, 0u, 0u);
+        if (need && first) {
+            w[c] = *(const uint4 *)(p0 + 16 * c);
+            got |= 1u << c;
+        }
+    }
+    auto word = [&](int i) -> uint32_t {  // static i
+        const uint4 &v = w[i >> 2];
+        return (i & 3) == 0 ? v.x : (i & 3) == 1 ? v.y : (i & 3) == 2 ? v.z : v.w;
+    };
+    auto pick = [&](int i) -> uint32_t {  // word S + i
+        const uint32_t a = word(i), bb = word(i + 1), c = word(i + 2), d = word(i + 3);
+        return S == 0 ? a : S == 1 ? bb : S == 2 ? c : d;
+    };
+    auto slot_in = [&](int j) -> bool {  // all three words of slot j loaded
+        const uint32_t k0 = S + 3 * (uint32_t)j;
+        return ((got >> (k0 >> 2)) & 1u) && ((got >> ((k0 + 2) >> 2)) & 1u);
+    };
+    uint32_t cnt = 0, avail = 0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const bool in = (uint32_t)j < len && slot_in(j);
+        const uint64_t k = ((uint64_t)pick(3 * j + 1) << 32) | pick(3 * j);
+        avail += in ? 1u : 0u;
+        cnt += (in && k < x) ? 1u : 0u;
+    }
+    if (two && cnt == avail && avail < len) {
+        // every slot read is below x: the lower bound lies further on
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (!((got >> c) & 1u) && (uint32_t)(4 * c) < end_word) {
+                w[c] = *(const uint4 *)(p0 + 16 * c);
+                got |= 1u << c;
+            }
+        cnt = 0;
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const uint64_t k = ((uint64_t)pick(3 * j + 1) << 32) | pick(3 * j);
+            cnt += ((uint32_t)j < len && k < x) ? 1u : 0u;
+        }
+    }
+    // the lower bound is slot cnt: a hit when its key equals x
+    bool e = false;
+    uint32_t rw = kMiss;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const uint64_t k = ((uint64_t)pick(3 * j + 1) << 32) | pick(3 * j);
+        if ((uint32_t)j == cnt && (uint32_t)j < len && slot_in(j) && k == x) {
+            e = true;
+            rw = pick(3 * j + 2);
+        }
+    }
+    eq = e;
+    row = rw;
+    return cnt;
+}
+
 // Windows are narrowed with binary-search steps down to STOP keys: 15 on the
 // structure-of-arrays layout (its scan reads 16 keys in 9 vector loads), 7
 // on the array of structures (8 slots, each with its row ID).
@@ -663,7 +746,10 @@ __global__ __launch_bounds__(1024) void k_point_learned(Load<K, AOS> keys, uint6
                 bool eq;
                 if constexpr (AOS) {
                     uint32_t row;
-                    (void)count_below_slots<K, STOP + 1>(keys, b[r], (uint32_t)sl, x[r], eq, row, TWO);
+                    if (sizeof(K) == 8 && keys.stride == 12)
+                        (void)count_below_packed<STOP + 1>(keys.base, b[r], (uint32_t)sl, (uint64_t)x[r], eq, row, TWO);
+                    else
+                        (void)count_below_slots<K, STOP + 1>(keys, b[r], (uint32_t)sl, x[r], eq, row, TWO);
                     if (eq) res = row;
                 } else {
                     const uint32_t c = count_below<K, 16>(keys.k, b[r], (uint32_t)sl, x[r], eq, TWO);
