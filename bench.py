@@ -57,11 +57,23 @@ def levels_eytzinger(n: int, k: int):
 
 
 def algo_bytes(form: str, n: int, k: int, key_bytes: int, early_exit: bool = True, window: float = 0.0,
-               leaves: int = 0, aos=False, onchip: int = ONCHIP_BYTES) -> dict:
+               leaves: int = 0, aos=False, onchip: int = ONCHIP_BYTES, lines: bool = False,
+               over: float = 0.0) -> dict:
     ONCHIP_BYTES = onchip  # noqa: N806 (the capacity this estimate assumes)
     stream = key_bytes + 4
     uncached = 0.0
     rowid = GRANULE if n * (key_bytes + 4) > onchip else 0
+    if form == "learned" and lines:
+        # leaf lines: the 128-byte line of the query's leaf (its keys, then
+        # their row IDs: both granules), counted if the lines exceed on-chip
+        # capacity; the share `over` of lookups in leaves too large for a
+        # line also searches the leaf's window as below
+        big = algo_bytes(form, n, k, key_bytes, early_exit, window, leaves, aos, onchip)
+        inline = 2 * GRANULE if leaves * 128 > ONCHIP_BYTES else 0
+        tree = inline + over * (big["tree"] + big["rowid"])
+        req = (1.0 if inline else 0.0) + over * (big["tree"] + big["rowid"]) / GRANULE
+        return {"stream": stream, "tree": round(tree, 1), "rowid": 0, "total": round(stream + tree, 1),
+                "random_lines": round(req, 3), "over": round(over, 5)}
     if form == "learned":
         # leaf record (32 B each; counted only if the table exceeds on-chip
         # capacity) + binary search over the mean window: one granule per
@@ -106,11 +118,23 @@ def algo_bytes(form: str, n: int, k: int, key_bytes: int, early_exit: bool = Tru
 # path shares the rest), and the granules holding the matches' row IDs where
 # the layout stores them (sampled at random ranks: consecutive ranks lie in
 # one run on the sorted array, on a few levels of an Eytzinger layout).
+def line_overflow(ix, leaves: int, cap: int) -> float:
+    """Share of the build keys (so of uniform hit lookups) whose leaf has more
+    than `cap` keys and is held in its line by record, from the exported leaf
+    table (word 3 of each 32-byte record is the leaf's size)."""
+    import torch
+
+    sizes = ix.learn_export().view(torch.int32).reshape(leaves, 8)[:, 3].to(torch.int64)
+    tot = int(sizes.sum())
+    return float(sizes[sizes > cap].sum()) / tot if tot else 0.0
+
+
 def algo_bytes_range(form: str, n: int, k: int, key_bytes: int, width: int, rank_slot=None, window: float = 0.0,
-                     leaves: int = 0, aos=False, samples: int = 2048) -> dict:
+                     leaves: int = 0, aos=False, samples: int = 2048, lines: bool = False, over: float = 0.0) -> dict:
     import numpy as np
 
-    pt = algo_bytes(form, n, k, key_bytes, early_exit=False, window=window, leaves=leaves, aos=aos)
+    pt = algo_bytes(form, n, k, key_bytes, early_exit=False, window=window, leaves=leaves, aos=aos, lines=lines,
+                    over=over)
     rng = np.random.default_rng(1)
     starts = rng.integers(0, n - width + 1, size=samples)
     total = 0
@@ -129,7 +153,9 @@ def algo_bytes_range(form: str, n: int, k: int, key_bytes: int, width: int, rank
         total += len(addrs)
     rowid_g = total / samples
     stream = 2 * key_bytes + 8 + 4 * width
-    tree = pt["tree"] + GRANULE
+    # the upper bound's search: one more granule where its path leaves the
+    # lower bound's; through leaf lines, its own line
+    tree = 2 * pt["tree"] if lines else pt["tree"] + GRANULE
     rowid = rowid_g * GRANULE
     return {"stream": stream, "tree": tree, "rowid": round(rowid, 1), "rowid_granules": round(rowid_g, 3),
             "total": round(stream + tree + rowid, 1)}
@@ -918,34 +944,40 @@ def main():
     lrec = None
     if not args.no_learned:
         if args.sweep:
-            cands = [(L, r, 0, False) for L in (1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 21, 1 << 22)
-                     for r in (4, 8)]
-            cands += [(1 << 20, 8, 1, False), (1 << 20, 4, 2, False)]
+            cands = [(L, {"per_lane": r}, False) for L in (1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 21,
+                                                           1 << 22) for r in (4, 8)]
+            cands += [(1 << 20, {"per_lane": 8, "reorder": 1}, False), (1 << 20, {"per_lane": 4, "reorder": 2}, False)]
             # the array of structures: the window scan reads each key with its row ID
-            cands += [(L, r, 0, a) for a in ("padded", True) for L in (1 << 21, 1 << 22) for r in (2, 4, 8)]
+            cands += [(L, {"per_lane": r}, a) for a in ("padded", True) for L in (1 << 21, 1 << 22) for r in (2, 4, 8)]
+            # leaf lines: a line per leaf of at most a few keys on average
+            cands += [(L, {"per_lane": r, "leaf_lines": 1}, a) for a in (False, True) for L in (1 << 23, 1 << 24)
+                      for r in (1, 2, 4)]
         else:
             _, _, laos, lp = autotune.choose(n, 64, "learned")
-            cands = [(lp.get("leaves", 1 << 16), lp.get("per_lane", 4), lp.get("reorder", 0), laos)]
+            cands = [(lp.get("leaves", 1 << 16), {kk: v for kk, v in lp.items() if kk != "leaves"}, laos)]
         trained = None
         arrays = {False: base}
-        for L, r, ro, la in cands:
+        for L, lparams, la in cands:
             if la not in arrays:
                 arrays[la] = base.relayout("bs", 1, la)
             arr = arrays[la]
             if trained != (L, la):
                 st = arr.learn(L, 2)
                 trained = (L, la)
-            arr.set_params(per_lane=r, model=0, reorder=ro)
+            arr.set_params(**{**lparams, "model": 0})
+            r, ro = arr.params()["per_lane"], arr.params()["reorder"]
             ms, ok = time_point(arr, reps=3 if args.sweep else 10, check=True)
             rec = {"layout": "learned", "k": 1, "aos": la, "params": dict(arr.params(), leaves=L), "ms": round(ms, 4),
                    "lookups_per_s": m / ms * 1e3, "bit_exact": ok, "mean_window": st["mean_window"],
                    "max_window": st["max_window"]}
+            if arr.params()["leaf_lines"] == 1:
+                rec["line_overflow"] = line_overflow(arr, L, 10)
             if not args.sweep:
                 rec["ms_cold"] = round(time_point(arr, reps=10, cold=True)[0], 4)
             if args.sweep:
                 sweep.append(rec)
-            log(f"learned leaves={L} R={r} reorder={ro} aos={la}: {ms:.3f} ms exact={ok} "
-                f"mean window {st['mean_window']:.1f}")
+            log(f"learned leaves={L} R={r} reorder={ro} aos={la} lines={arr.params()['leaf_lines'] == 1}: "
+                f"{ms:.3f} ms exact={ok} mean window {st['mean_window']:.1f}")
             if ok and (lrec is None or ms < lrec["ms"]):
                 lrec = rec
         for la, arr in arrays.items():
@@ -998,6 +1030,7 @@ def main():
                 # the array of structures first when the form uses it)
                 a = ev()
                 arr = bs if not rec["aos"] else bs.relayout("bs", 1, rec["aos"])
+                arr.set_params(**lookup_params(rec))  # leaf lines, when used, are written by the training call
                 arr.learn(rec["params"]["leaves"], 2)
                 b = ev()
                 hs[name] = arr
@@ -1070,12 +1103,14 @@ def main():
     # ------------------------------------------------------------ roofline
     ab = algo_bytes(hrec["layout"], n, hrec["k"], 8, early_exit=hrec["params"].get("early_exit", 1) == 1,
                     window=hrec.get("mean_window", 0.0), leaves=hrec["params"].get("leaves", 0),
-                    aos=hrec["aos"] if hrec["layout"] == "learned" else False)
+                    aos=hrec["aos"] if hrec["layout"] == "learned" else False,
+                    lines=hrec["params"].get("leaf_lines") == 1, over=hrec.get("line_overflow", 0.0))
     t_kernel = mean[f"point_{headline}"] / 1e3
     achieved = ab["total"] * m / t_kernel / 1e9
     hp = hrec["params"]
     kernel_key = (f"point_{hrec['layout']}_k{hrec['k']}_{'soa' if not hrec['aos'] else hrec['aos'] if hrec['aos'] != True else 'aos'}"
-                  f"_g{hp['group']}_r{hp['per_lane']}_l{hp['lds_levels']}_p{hp['persistent']}_b{hp['block']}")
+                  f"_g{hp['group']}_r{hp['per_lane']}_l{hp['lds_levels']}_p{hp['persistent']}_b{hp['block']}"
+                  f"{'_lines' if hp.get('leaf_lines') == 1 else ''}")
     traffic = read_traffic(kernel_key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -1093,7 +1128,8 @@ def main():
         lay = rec["layout"]
         rb = algo_bytes_range(lay, n, rec["k"], 8, 16, rank_slot=idx.lib().idx_rank_slot,
                               window=rec.get("mean_window", 0.0), leaves=rec["params"].get("leaves", 0),
-                              aos=rec["aos"] if lay == "learned" else False)
+                              aos=rec["aos"] if lay == "learned" else False,
+                              lines=rec["params"].get("leaf_lines") == 1, over=rec.get("line_overflow", 0.0))
         t = mean[f"range_{name}"] / 1e3
         ach = rb["total"] * mr / t / 1e9
         range_roofline[name] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -1123,7 +1159,8 @@ def main():
     # divided by the lookup's algorithmic granules beyond on-chip capacity, D
     if "group1" in probe:
         a_rand = probe["group1"]["granules_per_s"]
-        d_gran = (ab["tree"] + ab["rowid"]) / GRANULE
+        # (through leaf lines: the random 128-byte lines a lookup reads)
+        d_gran = ab["random_lines"] if "random_lines" in ab else (ab["tree"] + ab["rowid"]) / GRANULE
         bound = a_rand / d_gran if d_gran > 0 else None
         roofline["random_access"] = {"a_rand_per_s": a_rand, "granules_per_lookup": d_gran,
                                      "bound_lookups_per_s": bound,

@@ -316,6 +316,18 @@ typedef struct idx_lookup_params {
                             3 = gather by rank: the matches are the ranks [first, first + count)
                             of the count phase, each read at the slot the layout build wrote
                             that rank to (the inverse permutation, no key reads) */
+    uint32_t leaf_lines; /* learned form: 0 = default (2); 1 = give every leaf of the model one
+                            128-byte line holding its base rank, its size and, when it has at
+                            most 10 keys (64-bit keys; 15 for 32-bit keys), those keys and their
+                            row IDs, else its leaf record: a point lookup or a range bound then
+                            reads the root's line and, for small leaves, nothing else; two
+                            lanes share each lookup, one per half line (at most 256 threads per
+                            workgroup are used, and with reorder = 1, where each lane reads its
+                            whole line, at most 4 lookups per lane).  The
+                            lines (leaves x 128 bytes of device memory) are written by idx_learn
+                            when this is set before training, else by the first lookup that uses
+                            them, and freed with the model; 2 = search the leaf record's window
+                            in the sorted array */
 } idx_lookup_params;
 
 /* Set (p != NULL) or reset to defaults (p == NULL).  Errors: IDX_ERR_ARG for an
@@ -367,7 +379,7 @@ typedef struct idx_learn_stats {
  *   h        an IDX_BS index (any storage: SoA, AoS or line-padded AoS, where
  *            the window scan reads each key with its row ID) with n >= 1
  *            (IDX_ERR_ARG otherwise)
- *   leaves   1 <= leaves <= 2^22;  epochs 1..16;  feature IDX_FEATURE_* (LINEAR
+ *   leaves   1 <= leaves <= 2^24;  epochs 1..16;  feature IDX_FEATURE_* (LINEAR
  *            and LOG: that linear root; SPLINE: the spline root whose bin
  *            feature has the lower root loss; AUTO: the better linear root and
  *            the spline root each get trained leaves, and the one with the

@@ -76,6 +76,7 @@ class idx_lookup_params(ctypes.Structure):
         ("model", ctypes.c_uint32),
         ("window_rounds", ctypes.c_uint32),
         ("range_scan", ctypes.c_uint32),
+        ("leaf_lines", ctypes.c_uint32),
     ]
 
     def as_dict(self):

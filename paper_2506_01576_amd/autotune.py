@@ -86,14 +86,22 @@ def candidates(key_bits: int, n: int):
 
 
 def learned_candidates(n: int):
-    """Learned forms worth measuring: (leaves, lookups per lane, storage)."""
-    out = []
+    """Learned forms worth measuring: (leaves, lookup parameters, storage).
+    Leaf lines pay off when most leaves fit a line (a few keys per leaf on
+    average)."""
+    out = {}
     for per_leaf in (64, 16, 8):
         L = max(1, min(1 << 22, n // per_leaf))
         for r in (4, 8):
             for aos in (False, True):
-                out.append((L, r, aos))
-    return sorted(set(out), key=lambda c: (c[0], c[1], str(c[2])))
+                out[(L, r, 0, 0, aos)] = (L, {"per_lane": r}, aos)
+    for per_leaf in (4, 2):
+        L = max(1, min(1 << 24, n // per_leaf))
+        for r in (2, 4):
+            for block in (128, 256):
+                for aos in (False, True):
+                    out[(L, r, 1, block, aos)] = (L, {"per_lane": r, "leaf_lines": 1, "block": block}, aos)
+    return [out[k] for k in sorted(out, key=lambda c: (c[0], c[1], c[2], c[3], str(c[4])))]
 
 
 def tune_learned(base: Index, q: torch.Tensor, expect: torch.Tensor, cands=None, reps: int = 3, log=None):
@@ -104,14 +112,14 @@ def tune_learned(base: Index, q: torch.Tensor, expect: torch.Tensor, cands=None,
     out = torch.empty(len(q), dtype=torch.int32, device=q.device)
     arrays, records, best, trained = {False: base}, [], None, {}
     try:
-        for L, r, aos in cands:
+        for L, params, aos in cands:
             if aos not in arrays:
                 arrays[aos] = base.relayout("bs", 1, aos)
             arr = arrays[aos]
             if trained.get(aos) != L:
                 st = arr.learn(L, 2)
                 trained[aos] = L
-            arr.set_params(per_lane=r, model=0)
+            arr.set_params(**params, model=0)
             ms = _time_point(arr, q, out, reps)
             exact = bool(torch.equal(out, expect))
             rec = {"layout": "learned", "k": 1, "aos": aos, "params": dict(arr.params(), leaves=L),
@@ -119,7 +127,7 @@ def tune_learned(base: Index, q: torch.Tensor, expect: torch.Tensor, cands=None,
                    "mean_window": st["mean_window"]}
             records.append(rec)
             if log:
-                log(f"tune learned leaves={L} R={r} aos={aos}: {ms:.3f} ms {rec['lookups_per_s'] / 1e9:.2f} G/s "
+                log(f"tune learned leaves={L} {params} aos={aos}: {ms:.3f} ms {rec['lookups_per_s'] / 1e9:.2f} G/s "
                     f"exact={exact}")
             if exact and (best is None or ms < best["ms"]):
                 best = rec
@@ -196,7 +204,7 @@ def save_table(table: dict, path: str = TABLE_PATH):
 def record_best(table: dict, key_bits: int, n: int, best: dict):
     lo, hi = size_class(n)
     table["entries"] = [e for e in table["entries"]
-                        if not (e["key_bits"] == key_bits and e["log2n_lo"] == lo)]
+                        if not (e["key_bits"] == key_bits and e["log2n_lo"] == lo and e["layout"] in best)]
     for layout, rec in best.items():
         table["entries"].append({"key_bits": key_bits, "log2n_lo": lo, "log2n_hi": hi, "layout": layout,
                                  "k": rec["k"], "aos": rec["aos"], "params": rec["params"],
@@ -484,6 +492,8 @@ def _main(argv=None):
 
     ap = argparse.ArgumentParser(prog="python -m paper_2506_01576_amd.autotune")
     ap.add_argument("--point", action="store_true", help="single-index forms per size class")
+    ap.add_argument("--learned-only", action="store_true",
+                    help="with --point: measure only the learned forms (other entries are kept)")
     ap.add_argument("--batch", action="store_true", help="batched-launch forms per size class")
     ap.add_argument("--batch-joint", action="store_true",
                     help="batched-launch forms per size class, timed inside one representative many-index launch")
@@ -516,7 +526,7 @@ def _main(argv=None):
                 del kh, rh, qh, eh
                 log(f"point: {bits}-bit keys, n = 2^{lg}, {m} lookups")
                 with Index(keys, rows, layout="bs") as base:
-                    _, best = tune(base, q, expect, log=log)
+                    best = {} if args.learned_only else tune(base, q, expect, log=log)[1]
                     _, lbest = tune_learned(base, q, expect, log=log)
                 if lbest:
                     best["learned"] = lbest

@@ -186,6 +186,8 @@ int learn_export(const idx_index *h, void *leaves_out, hipStream_t s);
 int learn_eval(idx_index *h, uint32_t feature, const float *root_ab, uint32_t leaves, const float *leaf_ab,
                double *root_acc, double *leaf_acc, hipStream_t s);
 int point_learned(idx_index *h, const PointIO &io, hipStream_t s);
+// The attached model's leaf lines, written unless they are there.
+int ensure_lines(idx_index *h, hipStream_t s);
 // first-match ranks and counts of ranges through the model
 int range_count_learned(idx_index *h, const void *lo, const void *hi, uint64_t m, uint32_t *first, uint64_t *count,
                         hipStream_t s);

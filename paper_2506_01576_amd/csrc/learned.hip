@@ -484,7 +484,7 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
 
 int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream_t s) {
     if (h->layout != IDX_BS || h->n == 0) return IDX_ERR_ARG;
-    if (L == 0 || L > (1u << 22) || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_SPLINE) return IDX_ERR_ARG;
+    if (L == 0 || L > (1u << 24) || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_SPLINE) return IDX_ERR_ARG;
     drop_model(h, s);
     LearnedModel *M = new (std::nothrow) LearnedModel();
     if (!M) return IDX_ERR_NOMEM;
@@ -519,6 +519,14 @@ int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream
         h->alloc.put(M->spline, s);
         M->spline = nullptr;
     }
+    if (h->params.leaf_lines == 1) {
+        rc = ensure_lines(h, s);
+        if (rc == IDX_OK && hipStreamSynchronize(s) != hipSuccess) rc = IDX_ERR_HIP;
+        if (rc != IDX_OK) {
+            drop_model(h, s);
+            return rc;
+        }
+    }
     return IDX_OK;
 }
 
@@ -526,6 +534,7 @@ void drop_model(idx_index *h, hipStream_t s) {
     if (!h->learned) return;
     h->alloc.put(h->learned->leaves, s);
     if (h->learned->spline) h->alloc.put(h->learned->spline, s);
+    if (h->learned->lines) h->alloc.put(h->learned->lines, s);
     delete h->learned;
     h->learned = nullptr;
 }
@@ -762,9 +771,353 @@ __global__ __launch_bounds__(1024) void k_point_learned(Load<K, AOS> keys, uint6
     }
 }
 
+// ------------------------------------------------------------- leaf lines
+
+// Word i of a leaf record as laid out in memory (kmin low, kmin high, base,
+// size, b0, b1, elo, ehi).
+__device__ __forceinline__ uint32_t rec_word(const LeafRec &r, uint32_t i) {
+    switch (i) {
+        case 0: return (uint32_t)r.kmin;
+        case 1: return (uint32_t)(r.kmin >> 32);
+        case 2: return r.base;
+        case 3: return r.size;
+        case 4: return __float_as_uint(r.b0);
+        case 5: return __float_as_uint(r.b1);
+        case 6: return (uint32_t)r.elo;
+        default: return (uint32_t)r.ehi;
+    }
+}
+
+// The leaf lines (line layout at line_scan), one thread per 16-byte chunk,
+// so that a wave writes four whole lines.
+template <typename K, bool AOS>
+__global__ __launch_bounds__(256) void k_leaf_lines(Load<K, AOS> keys, const LeafRec *__restrict__ leaves, uint32_t L,
+                                                    uint4 *__restrict__ lines) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (uint64_t)L * kLineChunks) return;
+    const uint32_t l = (uint32_t)(t / kLineChunks), c = (uint32_t)(t % kLineChunks);
+    const LeafRec r = leaves[l];
+    constexpr uint32_t C = line_slots<K>();
+    constexpr uint32_t KW = sizeof(K) / 4;  // words per key
+    uint32_t v[4];
+#pragma unroll
+    for (uint32_t i = 0; i < 4; ++i) {
+        const uint32_t wi = 4 * c + i;
+        uint32_t x = 0;
+        if (wi == 0) {
+            x = r.base;
+        } else if (wi == 1) {
+            x = r.size;
+        } else if (r.size > C) {
+            if (wi >= 4 && wi < 12) x = rec_word(r, wi - 4);
+        } else if (wi < 2 + C * KW) {
+            const uint32_t j = (wi - 2) / KW;
+            if (j < r.size) {
+                const uint64_t k = (uint64_t)keys.key((uint64_t)r.base + j);
+                x = (KW == 2 && ((wi - 2) & 1u)) ? (uint32_t)(k >> 32) : (uint32_t)k;
+            }
+        } else {
+            const uint32_t j = wi - 2 - C * KW;
+            if (j < r.size) x = keys.row((uint64_t)r.base + j);
+        }
+        v[i] = x;
+    }
+    lines[t] = make_uint4(v[0], v[1], v[2], v[3]);
+}
+
+// Answer for x in the window [b, b + len] of the sorted array: halved while
+// it spans more than the scan's width, then the short-window scan.
+template <typename K, bool AOS>
+__device__ __forceinline__ uint32_t window_find(const Load<K, AOS> &keys, uint64_t n, uint64_t b, uint64_t len, K x,
+                                                bool two) {
+    constexpr uint32_t STOP = window_stop<AOS>();
+    while (len > STOP) {
+        const uint64_t half = len >> 1;
+        b = keys.key(b + half - 1) < x ? b + half : b;
+        len -= half;
+    }
+    const uint64_t sl = (len + 1) < (n - b) ? (len + 1) : (n - b);
+    bool eq;
+    if constexpr (AOS) {
+        uint32_t row;
+        if (sizeof(K) == 8 && keys.stride == 12)
+            (void)count_below_packed<STOP + 1>(keys.base, b, (uint32_t)sl, (uint64_t)x, eq, row, two);
+        else
+            (void)count_below_slots<K, STOP + 1>(keys, b, (uint32_t)sl, x, eq, row, two);
+        return eq ? row : kMiss;
+    } else {
+        const uint32_t c = count_below<K, 16>(keys.k, b, (uint32_t)sl, x, eq, two);
+        return eq ? keys.r[b + c] : kMiss;
+    }
+}
+
+// The same, kept out of line: called only for the few lookups in leaves too
+// large for their line, so the callers' loops over their lookups stay small
+// enough to unroll.
+template <typename K, bool AOS>
+__device__ __noinline__ uint32_t window_find_call(Load<K, AOS> keys, uint64_t n, uint64_t b, uint64_t len, K x,
+                                                  bool two) {
+    return window_find<K, AOS>(keys, n, b, len, x, two);
+}
+
+// Point lookups through the leaf lines: the R lookups of a lane load their
+// leaves' lines together (eight independent 16-byte loads of one line each),
+// then each is answered from its registers; a lookup in a leaf held by
+// record searches that record's window instead.
+template <typename K, int R, bool SORT, bool AOS, bool TWO>
+__global__ __launch_bounds__(256) void k_point_lines(Load<K, AOS> keys, uint64_t n, RootRec root,
+                                                     const uint4 *__restrict__ lines, QueryIO<K> io) {
+    extern __shared__ __align__(16) char smem[];
+    const uint64_t tile = (uint64_t)blockDim.x * R;
+    for (uint64_t it = blockIdx.x; it < io.iters; it += gridDim.x) {
+        const uint64_t tl = tile_of(it, io.ntiles, io.xcd);
+        if (tl >= io.ntiles) continue;
+        const uint64_t t0 = tl * tile;
+        K x[R];
+        uint32_t src[R];
+        tile_load<K, R, SORT>(io, smem, t0, x, src);
+        uint4 w[R][kLineChunks];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool v = tile_valid(io.m, t0, src_of<R, SORT>(src, r));
+            const uint4 *p = lines + (uint64_t)leaf_of(root, (uint64_t)x[r]) * kLineChunks;
+#pragma unroll
+            for (int c = 0; c < (int)kLineChunks; ++c) w[r][c] = v ? p[c] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        // answers from the lines first, so that no line is held while a
+        // large leaf's window is searched
+        uint32_t res[R];
+        uint64_t b[R], len[R];
+        bool big[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            res[r] = kMiss;
+            big[r] = false;
+            b[r] = len[r] = 0;
+            if (tile_valid(io.m, t0, src_of<R, SORT>(src, r))) {
+                uint32_t cnt, row;
+                bool eq;
+                if (line_scan<K>(w[r], x[r], cnt, eq, row)) {
+                    if (eq) res[r] = row;
+                } else {
+                    big[r] = true;
+                    leaf_window(line_leaf(w[r]), (uint64_t)x[r], b[r], len[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (big[r]) res[r] = window_find_call<K, AOS>(keys, n, b[r], len[r], x[r], TWO);
+            tile_put<K, SORT>(io, smem, t0, src_of<R, SORT>(src, r), res[r]);
+        }
+        tile_flush<K, R, SORT>(io, smem, t0);
+    }
+}
+
+// Point lookups through the leaf lines, two lanes per lookup: lane h of a
+// pair loads the line's half h (four 16-byte loads).  A lane reading a whole
+// line with eight loads makes the memory system serve far fewer random lines
+// per second than lanes sharing it (measured on MI355X: 13 against 48 G
+// lines/s).  Each lane counts its half's keys below x and at most x; the pair
+// adds both counts with one exchange each, and a hit is a key equal to x
+// (more keys at most x than below it).  The row IDs lie in the upper half, so
+// its lane writes the answer; for a leaf held by record (in the lower half)
+// the lower lane searches the window and writes.
+template <typename K, int R, bool AOS, bool TWO>
+__global__ __launch_bounds__(256) void k_point_lines_pair(Load<K, AOS> keys, uint64_t n, RootRec root,
+                                                          const uint4 *__restrict__ lines, QueryIO<K> io) {
+    constexpr uint32_t C = line_slots<K>();
+    constexpr uint32_t KW = sizeof(K) / 4;  // words per key
+    constexpr uint32_t R0 = 2 + C * KW;     // first row ID word (>= 16: in the upper half)
+    static_assert(R0 >= 16, "row IDs in the upper half of the line");
+    const uint32_t hf = threadIdx.x & 1u;
+    const uint64_t pairs = blockDim.x / 2, pi = threadIdx.x / 2;
+    const uint64_t tile = pairs * R;
+    for (uint64_t it = blockIdx.x; it < io.iters; it += gridDim.x) {
+        const uint64_t tl = tile_of(it, io.ntiles, io.xcd);
+        if (tl >= io.ntiles) continue;
+        const uint64_t t0 = tl * tile;
+        K x[R];
+        bool v[R];
+        uint4 w[R][4];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = t0 + (uint64_t)r * pairs + pi;
+            v[r] = qi < io.m;
+            x[r] = v[r] ? io.q[qi] : K(0);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint4 *p = lines + (uint64_t)leaf_of(root, (uint64_t)x[r]) * kLineChunks + 4 * hf;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) w[r][c] = v[r] ? p[c] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        uint32_t res[R];
+        uint64_t b[R], len[R];
+        bool big[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            auto word = [&](int i) -> uint32_t {  // static i: word 16 hf + i of the line
+                const uint4 &c = w[r][i >> 2];
+                return (i & 3) == 0 ? c.x : (i & 3) == 1 ? c.y : (i & 3) == 2 ? c.z : c.w;
+            };
+            res[r] = kMiss;
+            b[r] = len[r] = 0;
+            const uint32_t other = __shfl_xor(w[r][0].y, 1);
+            const uint32_t size = hf ? other : w[r][0].y;
+            big[r] = size > C;
+            if (!big[r]) {
+                uint32_t lt = 0, le = 0;
+#pragma unroll
+                for (int i = 0; i < 16; i += (int)KW) {
+                    const uint32_t wi = 16 * hf + (uint32_t)i;
+                    K key;
+                    if constexpr (KW == 2) key = ((uint64_t)word(i + 1) << 32) | word(i);
+                    else key = word(i);
+                    const bool in = wi >= 2 && wi < R0 && (wi - 2) / KW < size;
+                    lt += (in && key < x[r]) ? 1u : 0u;
+                    le += (in && key <= x[r]) ? 1u : 0u;
+                }
+                lt += __shfl_xor(lt, 1);
+                le += __shfl_xor(le, 1);
+                if (le > lt) {
+                    const uint32_t ri = R0 - 16 + lt;  // the row ID's word in the upper half
+                    uint32_t row = 0;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) row = (uint32_t)i == ri ? word(i) : row;
+                    res[r] = row;
+                }
+            } else if (hf == 0) {
+                leaf_window(leaf_of_chunks(w[r][1], w[r][2]), (uint64_t)x[r], b[r], len[r]);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t qi = t0 + (uint64_t)r * pairs + pi;
+            if (big[r] && hf == 0) res[r] = window_find_call<K, AOS>(keys, n, b[r], len[r], x[r], TWO);
+            if (v[r] && hf == (big[r] ? 0u : 1u)) io.out[io.pos ? io.pos[qi] : qi] = res[r];
+        }
+    }
+}
+
+}  // namespace
+
+// Write the model's leaf lines unless they are there.
+int ensure_lines(idx_index *h, hipStream_t s) {
+    LearnedModel *M = h->learned;
+    if (M->lines) return IDX_OK;
+    const uint32_t L = M->root.L;
+    uint4 *lines = (uint4 *)h->alloc.get((size_t)L * kLineBytes, s);
+    if (!lines) return IDX_ERR_NOMEM;
+    const uint64_t threads = (uint64_t)L * kLineChunks;
+    const uint32_t g = grid_for(threads, 256);
+    if (h->u64) {
+        if (h->aos) hipLaunchKernelGGL((k_leaf_lines<uint64_t, true>), dim3(g), dim3(256), 0, s, make_load<uint64_t, true>(h), M->leaves, L, lines);
+        else hipLaunchKernelGGL((k_leaf_lines<uint64_t, false>), dim3(g), dim3(256), 0, s, make_load<uint64_t, false>(h), M->leaves, L, lines);
+    } else {
+        if (h->aos) hipLaunchKernelGGL((k_leaf_lines<uint32_t, true>), dim3(g), dim3(256), 0, s, make_load<uint32_t, true>(h), M->leaves, L, lines);
+        else hipLaunchKernelGGL((k_leaf_lines<uint32_t, false>), dim3(g), dim3(256), 0, s, make_load<uint32_t, false>(h), M->leaves, L, lines);
+    }
+    if (hipGetLastError() != hipSuccess) {
+        h->alloc.put(lines, s);
+        return IDX_ERR_HIP;
+    }
+    M->lines = lines;
+    return IDX_OK;
+}
+
+namespace {
+// Query IO of a leaf-line launch over tiles of `tile` lookups, and its grid.
+template <typename KT>
+QueryIO<KT> lines_io(const idx_index *h, const PointIO &pio, uint64_t tile, uint32_t &grid) {
+    QueryIO<KT> io{};
+    io.q = (const KT *)pio.q;
+    io.out = pio.out;
+    io.m = pio.m;
+    io.local_sort = pio.local_sort ? 1u : 0u;
+    io.xcd = pio.xcd ? 1u : 0u;
+    io.sort_off = 0;
+    io.rounds = h->params.window_rounds == 1 ? 1u : 2u;
+    io.pos = pio.pos;
+    set_tiles(io, tile);
+    uint64_t g = io.iters;
+    if (h->params.persistent) {
+        uint64_t cap = (uint64_t)h->cu_count * h->params.persistent;
+        if (io.xcd && cap >= kXcds) cap -= cap % kXcds;
+        if (g > cap) g = cap;
+    }
+    grid = (uint32_t)(g ? (g > 0x7FFFFFFFull ? 0x7FFFFFFFull : g) : 1);
+    return io;
+}
+
+template <typename KT, int RR>
+void launch_lines(idx_index *h, const PointIO &pio, uint32_t block, hipStream_t s) {
+    const LearnedModel *M = h->learned;
+    uint32_t g;
+    if (pio.local_sort) {  // one lane per lookup, at most 4 lookups per lane
+        constexpr int RS = RR > 4 ? 4 : RR;
+        const uint64_t tile = (uint64_t)block * RS;
+        const QueryIO<KT> io = lines_io<KT>(h, pio, tile, g);
+        const size_t smem = sort_lds_bytes((uint32_t)tile, sizeof(KT));
+        if (h->aos && io.rounds == 2)
+            hipLaunchKernelGGL((k_point_lines<KT, RS, true, true, true>), dim3(g), dim3(block), smem, s,
+                               make_load<KT, true>(h), h->n, M->root, M->lines, io);
+        else if (h->aos)
+            hipLaunchKernelGGL((k_point_lines<KT, RS, true, true, false>), dim3(g), dim3(block), smem, s,
+                               make_load<KT, true>(h), h->n, M->root, M->lines, io);
+        else if (io.rounds == 2)
+            hipLaunchKernelGGL((k_point_lines<KT, RS, true, false, true>), dim3(g), dim3(block), smem, s,
+                               make_load<KT, false>(h), h->n, M->root, M->lines, io);
+        else
+            hipLaunchKernelGGL((k_point_lines<KT, RS, true, false, false>), dim3(g), dim3(block), smem, s,
+                               make_load<KT, false>(h), h->n, M->root, M->lines, io);
+        return;
+    }
+    const QueryIO<KT> io = lines_io<KT>(h, pio, (uint64_t)(block / 2) * RR, g);
+    if (h->aos && io.rounds == 2)
+        hipLaunchKernelGGL((k_point_lines_pair<KT, RR, true, true>), dim3(g), dim3(block), 0, s,
+                           make_load<KT, true>(h), h->n, M->root, M->lines, io);
+    else if (h->aos)
+        hipLaunchKernelGGL((k_point_lines_pair<KT, RR, true, false>), dim3(g), dim3(block), 0, s,
+                           make_load<KT, true>(h), h->n, M->root, M->lines, io);
+    else if (io.rounds == 2)
+        hipLaunchKernelGGL((k_point_lines_pair<KT, RR, false, true>), dim3(g), dim3(block), 0, s,
+                           make_load<KT, false>(h), h->n, M->root, M->lines, io);
+    else
+        hipLaunchKernelGGL((k_point_lines_pair<KT, RR, false, false>), dim3(g), dim3(block), 0, s,
+                           make_load<KT, false>(h), h->n, M->root, M->lines, io);
+}
+
+// Point lookups through the leaf lines: at most 256 threads per workgroup.
+int point_lines(idx_index *h, const PointIO &pio, hipStream_t s) {
+    const uint32_t block = h->params.block > 256 ? 256u : h->params.block;
+    const uint32_t R = h->params.per_lane;
+    if (h->u64) {
+        switch (R) {
+            case 1: launch_lines<uint64_t, 1>(h, pio, block, s); break;
+            case 2: launch_lines<uint64_t, 2>(h, pio, block, s); break;
+            case 4: launch_lines<uint64_t, 4>(h, pio, block, s); break;
+            default: launch_lines<uint64_t, 8>(h, pio, block, s); break;
+        }
+    } else {
+        switch (R) {
+            case 1: launch_lines<uint32_t, 1>(h, pio, block, s); break;
+            case 2: launch_lines<uint32_t, 2>(h, pio, block, s); break;
+            case 4: launch_lines<uint32_t, 4>(h, pio, block, s); break;
+            default: launch_lines<uint32_t, 8>(h, pio, block, s); break;
+        }
+    }
+    IDX_LAUNCH_CHECK();
+    return IDX_OK;
+}
+
 }  // namespace
 
 int point_learned(idx_index *h, const PointIO &pio, hipStream_t s) {
+    if (h->params.leaf_lines == 1) {
+        const int rc = ensure_lines(h, s);
+        return rc != IDX_OK ? rc : point_lines(h, pio, s);
+    }
     const LearnedModel *M = h->learned;
     const uint32_t block = h->params.block;
     const uint32_t R = h->params.per_lane;
@@ -867,17 +1220,106 @@ __global__ __launch_bounds__(256) void k_range_count_learned(Load<K, AOS> keys, 
     count[q] = r1 > r0 ? r1 - r0 : 0;
 }
 
+// Lower-bound rank of x in the window [b, b + len] of the sorted array.
+template <typename K, bool AOS>
+__device__ __forceinline__ uint64_t window_lower_rank(const Load<K, AOS> &keys, uint64_t b, uint64_t len, K x) {
+    constexpr uint32_t STOP = window_stop<AOS>();
+    while (len > STOP) {
+        const uint64_t half = len >> 1;
+        b = keys.key(b + half - 1) < x ? b + half : b;
+        len -= half;
+    }
+    bool eq;
+    uint32_t row;
+    if constexpr (AOS) return b + count_below_slots<K, STOP + 1>(keys, b, (uint32_t)len, x, eq, row);
+    else return b + count_below<K, 16>(keys.k, b, (uint32_t)len, x, eq);
+}
+
+// Lower-bound rank of x from half hf of its leaf's line (w), as two lanes of
+// a pair hold it (both call this together; the lower lane gets the rank):
+// the base rank plus the leaf's keys below x, or for a leaf held by record
+// (in the lower half) a search of its window by the lower lane.
+template <typename K, bool AOS>
+__device__ __forceinline__ uint64_t pair_lower_rank(const Load<K, AOS> &keys, const uint4 (&w)[4], uint32_t hf, K x) {
+    constexpr uint32_t C = line_slots<K>();
+    constexpr uint32_t KW = sizeof(K) / 4;
+    constexpr uint32_t R0 = 2 + C * KW;
+    auto word = [&](int i) -> uint32_t {  // static i
+        const uint4 &c = w[i >> 2];
+        return (i & 3) == 0 ? c.x : (i & 3) == 1 ? c.y : (i & 3) == 2 ? c.z : c.w;
+    };
+    const uint32_t other = __shfl_xor(w[0].y, 1);
+    const uint32_t size = hf ? other : w[0].y;
+    if (size <= C) {
+        uint32_t lt = 0;
+#pragma unroll
+        for (int i = 0; i < 16; i += (int)KW) {
+            const uint32_t wi = 16 * hf + (uint32_t)i;
+            K key;
+            if constexpr (KW == 2) key = ((uint64_t)word(i + 1) << 32) | word(i);
+            else key = word(i);
+            lt += (wi >= 2 && wi < R0 && (wi - 2) / KW < size && key < x) ? 1u : 0u;
+        }
+        lt += __shfl_xor(lt, 1);
+        return (uint64_t)w[0].x + lt;
+    }
+    if (hf != 0) return 0;
+    uint64_t b, len;
+    leaf_window(leaf_of_chunks(w[1], w[2]), (uint64_t)x, b, len);
+    return window_lower_rank<K, AOS>(keys, b, len, x);
+}
+
+// Range counts through the leaf lines, two lanes per range (each loads one
+// half of both bounds' lines, all eight loads together); the lower lane
+// writes the range's first rank and count.
+template <typename K, bool AOS>
+__global__ __launch_bounds__(256) void k_range_count_lines(Load<K, AOS> keys, uint64_t n, RootRec root,
+                                                           const uint4 *__restrict__ lines, const K *__restrict__ lo,
+                                                           const K *__restrict__ hi, uint64_t m,
+                                                           uint32_t *__restrict__ first, uint64_t *__restrict__ count) {
+    const uint32_t hf = threadIdx.x & 1u;
+    const uint64_t q = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1;
+    const bool live = q < m;  // the same for both lanes of a pair
+    const K L = live ? lo[q] : K(0), U = live ? hi[q] : K(0);
+    const bool act = live && L <= U, top = U == ~K(0);
+    const K x1 = top ? U : (K)(U + 1);
+    uint4 w0[4], w1[4];
+    const uint4 *p0 = lines + (uint64_t)leaf_of(root, (uint64_t)L) * kLineChunks + 4 * hf;
+    const uint4 *p1 = lines + (uint64_t)leaf_of(root, (uint64_t)x1) * kLineChunks + 4 * hf;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        w0[c] = act ? p0[c] : make_uint4(0u, 0u, 0u, 0u);
+        w1[c] = act && !top ? p1[c] : make_uint4(0u, 0u, 0u, 0u);
+    }
+    const uint64_t r0 = pair_lower_rank<K, AOS>(keys, w0, hf, L);
+    const uint64_t r1u = pair_lower_rank<K, AOS>(keys, w1, hf, x1);
+    if (!live || hf != 0) return;
+    const uint64_t r1 = !act ? 0 : top ? n : r1u;
+    first[q] = act ? (uint32_t)r0 : 0u;
+    count[q] = act && r1 > r0 ? r1 - r0 : 0;
+}
+
 template <typename K, bool AOS>
 void launch_range_count(const idx_index *h, const void *lo, const void *hi, uint64_t m, uint32_t *first,
                         uint64_t *count, hipStream_t s) {
     const LearnedModel *M = h->learned;
-    hipLaunchKernelGGL((k_range_count_learned<K, AOS>), dim3(grid_for(m, 256)), dim3(256), 0, s, make_load<K, AOS>(h),
-                       h->n, M->root, M->leaves, (const K *)lo, (const K *)hi, m, first, count);
+    if (M->lines && h->params.leaf_lines == 1)
+        hipLaunchKernelGGL((k_range_count_lines<K, AOS>), dim3(grid_for(2 * m, 256)), dim3(256), 0, s,
+                           make_load<K, AOS>(h), h->n, M->root, M->lines, (const K *)lo, (const K *)hi, m, first,
+                           count);
+    else
+        hipLaunchKernelGGL((k_range_count_learned<K, AOS>), dim3(grid_for(m, 256)), dim3(256), 0, s,
+                           make_load<K, AOS>(h), h->n, M->root, M->leaves, (const K *)lo, (const K *)hi, m, first,
+                           count);
 }
 }  // namespace
 
 int range_count_learned(idx_index *h, const void *lo, const void *hi, uint64_t m, uint32_t *first, uint64_t *count,
                         hipStream_t s) {
+    if (h->params.leaf_lines == 1) {
+        const int rc = ensure_lines(h, s);
+        if (rc != IDX_OK) return rc;
+    }
     if (h->u64) {
         if (h->aos) launch_range_count<uint64_t, true>(h, lo, hi, m, first, count, s);
         else launch_range_count<uint64_t, false>(h, lo, hi, m, first, count, s);
@@ -947,7 +1389,7 @@ int learn_eval(idx_index *h, uint32_t mode, const float *root_ab, uint32_t L, co
                double *leaf_acc, hipStream_t s) {
     if (h->layout != IDX_BS || h->n == 0) return IDX_ERR_ARG;
     if (mode != IDX_FEATURE_LINEAR && mode != IDX_FEATURE_LOG) return IDX_ERR_ARG;
-    if (L == 0 || L > (1u << 22) || !root_ab || !root_acc) return IDX_ERR_ARG;
+    if (L == 0 || L > (1u << 24) || !root_ab || !root_acc) return IDX_ERR_ARG;
     if (h->u64)
         return h->aos ? eval_t<uint64_t, true>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s)
                       : eval_t<uint64_t, false>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s);

@@ -44,6 +44,7 @@ struct LearnedModel {
     RootRec root{};
     LeafRec *leaves = nullptr;  // device, L records
     SplineBin *spline = nullptr;  // device: the spline root's bins (spline root only)
+    uint4 *lines = nullptr;       // device: one 128-byte line per leaf, written on first use
     idx_learn_stats stats{};
 };
 
@@ -191,11 +192,9 @@ __device__ __forceinline__ uint32_t pred_local(const LeafRec &L, uint64_t key) {
     return (uint32_t)p;
 }
 
-// Search window [first, first + len] of x: the leaf's predicted local rank
-// widened by the leaf's measured errors, clamped to the leaf's rank interval.
-__device__ __forceinline__ void learned_window(const RootRec &root, const LeafRec *__restrict__ leaves, uint64_t x,
-                                               uint64_t &first, uint64_t &len) {
-    const LeafRec L = leaves[leaf_of(root, x)];
+// Search window [first, first + len] of x in leaf L: the leaf's predicted
+// local rank widened by its measured errors, clamped to its rank interval.
+__device__ __forceinline__ void leaf_window(const LeafRec &L, uint64_t x, uint64_t &first, uint64_t &len) {
     const int64_t p = (int64_t)pred_local(L, x);
     int64_t w0 = p + L.elo, w1 = p + (int64_t)L.ehi + 1;
     w0 = w0 < 0 ? 0 : (w0 > (int64_t)L.size ? (int64_t)L.size : w0);
@@ -203,6 +202,82 @@ __device__ __forceinline__ void learned_window(const RootRec &root, const LeafRe
     first = L.base + (uint64_t)w0;
     len = (uint64_t)(w1 - w0);
 }
+
+// The window of x in the leaf the root sends it to.
+__device__ __forceinline__ void learned_window(const RootRec &root, const LeafRec *__restrict__ leaves, uint64_t x,
+                                               uint64_t &first, uint64_t &len) {
+    leaf_window(leaves[leaf_of(root, x)], x, first, len);
+}
+
+// ---- leaf lines: one 128-byte line per leaf, so that a lookup in a small
+// leaf reads one line after the root.  The root is non-decreasing in the
+// key, so every build key below x lies in a leaf before x's leaf or in it,
+// and every key above x in it or after it: the lower bound of x is the
+// leaf's base rank plus the leaf's keys below x.  Line layout (32-bit
+// words): word 0 the base rank, word 1 the size; a leaf of at most
+// line_slots keys holds them from byte 8 in ascending order, then their row
+// IDs; a larger leaf holds its leaf record at bytes 16-47, whose window is
+// searched in the sorted array instead.
+constexpr uint32_t kLineBytes = 128;
+constexpr uint32_t kLineChunks = kLineBytes / 16;
+
+template <typename K>
+__host__ __device__ constexpr uint32_t line_slots() {
+    return (kLineBytes - 8) / (uint32_t)(sizeof(K) + 4);  // 64-bit keys: 10; 32-bit keys: 15
+}
+
+// Word i (static) of a line held in registers.
+__device__ __forceinline__ uint32_t line_word(const uint4 (&w)[kLineChunks], int i) {
+    const uint4 &v = w[i >> 2];
+    return (i & 3) == 0 ? v.x : (i & 3) == 1 ? v.y : (i & 3) == 2 ? v.z : v.w;
+}
+
+template <typename K>
+__device__ __forceinline__ K line_key(const uint4 (&w)[kLineChunks], int j) {
+    if constexpr (sizeof(K) == 8) return ((uint64_t)line_word(w, 3 + 2 * j) << 32) | line_word(w, 2 + 2 * j);
+    else return line_word(w, 2 + j);
+}
+
+// Keys of an inline leaf below x (cnt), and the row ID of the key at rank
+// cnt when it equals x.  False, with nothing set, for a leaf held by record.
+template <typename K>
+__device__ __forceinline__ bool line_scan(const uint4 (&w)[kLineChunks], K x, uint32_t &cnt, bool &eq,
+                                          uint32_t &row) {
+    constexpr uint32_t C = line_slots<K>();
+    constexpr int R0 = 2 + (int)(C * sizeof(K) / 4);  // first row ID word
+    const uint32_t size = w[0].y;
+    if (size > C) return false;
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < (int)C; ++j) c += ((uint32_t)j < size && line_key<K>(w, j) < x) ? 1u : 0u;
+    bool e = false;
+    uint32_t r = kMiss;
+#pragma unroll
+    for (int j = 0; j < (int)C; ++j)
+        if ((uint32_t)j == c && (uint32_t)j < size && line_key<K>(w, j) == x) {
+            e = true;
+            r = line_word(w, R0 + j);
+        }
+    cnt = c;
+    eq = e;
+    row = r;
+    return true;
+}
+
+// The leaf record a line of a large leaf holds, from its chunks 1 and 2.
+__device__ __forceinline__ LeafRec leaf_of_chunks(const uint4 &c1, const uint4 &c2) {
+    LeafRec L;
+    L.kmin = ((uint64_t)c1.y << 32) | c1.x;
+    L.base = c1.z;
+    L.size = c1.w;
+    L.b0 = __uint_as_float(c2.x);
+    L.b1 = __uint_as_float(c2.y);
+    L.elo = (int32_t)c2.z;
+    L.ehi = (int32_t)c2.w;
+    return L;
+}
+
+__device__ __forceinline__ LeafRec line_leaf(const uint4 (&w)[kLineChunks]) { return leaf_of_chunks(w[1], w[2]); }
 
 // Lower-bound rank of x through the model (exact: the window holds it).
 template <typename K>

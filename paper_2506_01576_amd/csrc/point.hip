@@ -675,6 +675,9 @@ int resolve_params(const idx_index *h, const idx_lookup_params *in, idx_lookup_p
     // scan, 2 = single-lane level scan, 3 = gather by rank
     if (p.range_scan == 0) p.range_scan = 3;
     if (p.range_scan > 3) return IDX_ERR_ARG;
+    // learned form: 0 = default (off), 1 = one line per leaf, 2 = off
+    if (p.leaf_lines == 0) p.leaf_lines = 2;
+    if (p.leaf_lines > 2) return IDX_ERR_ARG;
     *out = p;
     return IDX_OK;
 }

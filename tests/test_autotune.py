@@ -61,7 +61,10 @@ def test_candidate_lists():
     assert any(p.get("reorder") == 2 and p.get("lds_levels") for _, _, _, p in c)
     assert not any(p.get("reorder") == 2 for _, _, _, p in autotune.candidates(32, 1 << 12))
     lc = autotune.learned_candidates(1 << 20)
-    assert (1 << 16, 4, False) in lc and all(1 <= L <= 1 << 22 for L, _, _ in lc)
+    assert (1 << 16, {"per_lane": 4}, False) in lc
+    assert all(1 <= L <= 1 << 22 for L, p, _ in lc if not p.get("leaf_lines"))
+    assert (1 << 18, {"per_lane": 2, "leaf_lines": 1, "block": 128}, True) in lc
+    assert all(L <= 1 << 24 for L, _, _ in lc)
     forms = [autotune._form(f) for f in autotune.BATCH_FORMS]
     assert any(p.get("group", 1) > 1 for _, _, _, p in forms)
     assert any(p.get("lds_levels") for _, _, _, p in forms)
@@ -75,3 +78,13 @@ def test_table_is_valid_json_with_exact_records():
         assert e["lookups_per_s"] > 0 and e["measured_n"] >= 1
     for e in table["batch"]:
         assert e["bit_exact"] is True
+
+
+def test_record_best_replaces_only_the_measured_layouts():
+    table = {"device": "gfx950", "entries": []}
+    rec = {"k": 1, "aos": False, "params": {"per_lane": 4}, "lookups_per_s": 1e9}
+    table = autotune.record_best(table, 64, 1 << 26, {"bs": rec, "learned": dict(rec, params={"leaves": 4})})
+    table = autotune.record_best(table, 64, 1 << 26, {"learned": dict(rec, params={"leaves": 8}, lookups_per_s=2e9)})
+    lay = sorted(e["layout"] for e in table["entries"])
+    assert lay == ["bs", "learned"]
+    assert autotune.choose(1 << 26, 64, "learned", table=table)[3] == {"leaves": 8}

@@ -150,7 +150,7 @@ def test_learn_rejects_other_layouts():
         with pytest.raises(idx.IdxError):
             ix.learn(64)
     with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
-        for bad in ((0, 2, AUTO), (1 << 23, 2, AUTO), (64, 0, AUTO), (64, 2, 4)):
+        for bad in ((0, 2, AUTO), ((1 << 24) + 1, 2, AUTO), (64, 0, AUTO), (64, 2, 4)):
             with pytest.raises(idx.IdxError):
                 ix.learn(*bad)
 
@@ -353,3 +353,85 @@ def test_window_rounds_parity(aos, rounds):
                 assert np.array_equal(rows_host(ix.point(to_dev(q))), want)
             with pytest.raises(idx.IdxError):
                 ix.set_params(window_rounds=3)
+
+
+@pytest.mark.parametrize("aos", [False, True, "padded"])
+@pytest.mark.parametrize("kind", ["uniform32", "uniform64", "lognormal", "dup"])
+@pytest.mark.parametrize("per_leaf", [0.25, 3, 8, 40])
+def test_leaf_lines_parity(kind, per_leaf, aos):
+    """Lookups through the leaf lines (one 128-byte line per leaf, small
+    leaves inline, larger ones by their leaf record): point lookups of every
+    build key and of misses, range counts and row IDs equal the oracle's in
+    every storage and at every lookup count per lane; the lines follow a
+    retrained model; leaf_lines = 2 returns to the window search."""
+    n = 50021
+    keys, rows = make(kind, n, seed=int(per_leaf * 4) + 1)
+    sk, sr = oracle.stable_sort(keys, rows)
+    q = queries(keys, 20011, seed=int(per_leaf * 4) + 2)
+    want = oracle.point(sk, sr, q, nthreads=4)
+    all_want = oracle.point(sk, sr, keys, nthreads=4)
+    L, U, _ = gen.ranges(5, keys, 3001, 1, 64)
+    L = np.concatenate([L, q[:500]]).astype(keys.dtype)
+    U = np.concatenate([U, np.maximum(q[:500], q[500:1000])]).astype(keys.dtype)
+    woff, wrows = oracle.range_lookup(sk, sr, L, U, nthreads=4)
+    cap = 10 if keys.dtype.itemsize == 8 else 15
+    say(f"leaf lines {kind} per_leaf={per_leaf} aos={aos}")
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs", aos=aos) as ix:
+        leaves = max(1, int(n / per_leaf))
+        ix.learn(leaves, 2)
+        sizes = ix.learn_export().cpu().numpy().view(np.uint8).reshape(leaves, 32)[:, 12:16].copy().view(np.uint32)
+        say(f"  leaves {leaves}: inline {int((sizes <= cap).sum())}, by record {int((sizes > cap).sum())}")
+        if per_leaf == 8:  # both kinds of line
+            assert (sizes <= cap).any() and (sizes > cap).any()
+        # lookups per lane pair; partitioned batches (answers placed back or
+        # written in place); locally sorted tiles (one lane per line);
+        # workgroup sizes and persistent grids
+        for R, reorder, block, persistent in [(1, 0, 256, 0), (2, 0, 256, 0), (4, 0, 256, 0), (8, 0, 256, 0),
+                                              (4, 0, 64, 0), (4, 0, 1024, 0), (2, 0, 256, 3), (1, 1, 256, 0),
+                                              (4, 1, 128, 0), (4, 2, 256, 0), (4, 3, 256, 0), (2, 3, 128, 2)]:
+            ix.set_params(per_lane=R, leaf_lines=1, reorder=reorder, block=block, persistent=persistent)
+            got = rows_host(ix.point(to_dev(q)))
+            bad = np.nonzero(got != want)[0]
+            assert len(bad) == 0, f"R={R} reorder={reorder} block={block}: {len(bad)} mismatches, first q={q[bad[0]]}"
+        ix.set_params(per_lane=4, leaf_lines=1)
+        assert ix.params()["leaf_lines"] == 1
+        all_got = rows_host(ix.point(to_dev(keys)))
+        bad = np.nonzero(all_got != all_want)[0]
+        assert len(bad) == 0, f"{len(bad)} build keys not found through the lines, first {keys[bad[0]]}"
+        off, rr = ix.range(to_dev(L), to_dev(U))
+        assert np.array_equal(off.cpu().numpy().view(np.uint64), woff)
+        assert np.array_equal(rows_host(rr), wrows)
+        # a retrained model gets new lines
+        ix.learn(max(1, leaves // 3), 2)
+        assert np.array_equal(rows_host(ix.point(to_dev(q))), want)
+        assert np.array_equal(rows_host(ix.point(to_dev(keys))), all_want)
+        ix.set_params(leaf_lines=2)
+        assert np.array_equal(rows_host(ix.point(to_dev(q))), want)
+        off, rr = ix.range(to_dev(L), to_dev(U))
+        assert np.array_equal(off.cpu().numpy().view(np.uint64), woff)
+        with pytest.raises(idx.IdxError):
+            ix.set_params(leaf_lines=3)
+
+
+def test_leaf_lines_tiny_sets_and_max_leaves():
+    """Leaf lines on sets of 1 to 17 keys, and a model with the largest leaf
+    count (2^24 leaves over 2^18 keys: almost every line empty)."""
+    for n in (1, 2, 3, 17):
+        keys, rows = make("uniform64", n, seed=n + 40)
+        sk, sr = oracle.stable_sort(keys, rows)
+        q = queries(keys, 64, seed=n)
+        with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+            ix.learn(16, 2, AUTO)
+            for reorder in (0, 1):
+                ix.set_params(leaf_lines=1, reorder=reorder)
+                assert np.array_equal(rows_host(ix.point(to_dev(q))), oracle.point(sk, sr, q))
+                assert np.array_equal(rows_host(ix.point(to_dev(keys))), oracle.point(sk, sr, keys))
+    n = 1 << 18
+    keys, rows = make("uniform32", n, seed=77)
+    sk, sr = oracle.stable_sort(keys, rows)
+    q = queries(keys, 1 << 16, seed=78)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        ix.set_params(leaf_lines=1)  # the lines are written by the training call
+        ix.learn(1 << 24, 1, AUTO)
+        assert np.array_equal(rows_host(ix.point(to_dev(q))), oracle.point(sk, sr, q, nthreads=4))
+        assert np.array_equal(rows_host(ix.point(to_dev(keys))), oracle.point(sk, sr, keys, nthreads=4))
