@@ -299,9 +299,10 @@ typedef struct idx_lookup_params {
     uint32_t reorder;    /* 1 = sort each workgroup's point lookups locally before searching;
                             2 = partition the batch by rank bucket of the index first (point
                             lookups, and the count phase of range lookups by their lower bounds),
-                            answers returned to the caller's order by two counting passes;
+                            point answers returned to the caller's order by two counting passes,
+                            range counts written straight to their ranges' positions;
                             3 = the same partition, each point answer written straight to its
-                            position */
+                            position too */
     uint32_t early_exit; /* 1 = stop at an equal key (only used when keys are unique) */
     uint32_t model;      /* 0/1 = use the learned model when one is trained (idx_learn), 2 = ignore it */
     uint32_t window_rounds; /* short-window scan (BS and learned forms): 0 = default (2); 2 = read the

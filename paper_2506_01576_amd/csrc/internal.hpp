@@ -136,13 +136,11 @@ uint32_t pin_entries_for(const idx_index *h, uint32_t levels);
 int point_partitioned(idx_index *h, const void *q, uint64_t m, uint32_t *out, hipStream_t s);
 void drop_splitters(idx_index *h, hipStream_t s);
 // The partition for other lookups: one chunk of m <= 2^31 query keys
-// partitioned by rank bucket (keys q, batch positions pos, both in
-// partitioned order; ans is a free u32 array of m entries), and answers in
-// partitioned order placed back at their positions (may run several times).
+// partitioned by rank bucket (keys q and batch positions pos, both in
+// partitioned order); the caller writes each answer at its position.
 struct PartView {
     const void *q;
     const uint32_t *pos;
-    uint32_t *ans;
     uint64_t m;
     void *scratch;
     const uint16_t *bkt;  // bucket of every entry (partitioned order)
@@ -154,7 +152,6 @@ __host__ __device__ inline uint64_t bucket_start(uint64_t b, uint64_t step) { re
 constexpr uint64_t kPartChunk = 1ull << 31;
 size_t partition_scratch_bytes(const idx_index *h, uint64_t m);
 int partition_forward(idx_index *h, const void *q, uint64_t m, void *scratch, PartView *out, hipStream_t s);
-int partition_place(idx_index *h, const PartView &v, const uint32_t *ans, uint32_t *out, hipStream_t s);
 
 // ---- range.hip --------------------------------------------------------------
 // Exclusive scan of v[0..m) in place, v[m] = total; partial holds

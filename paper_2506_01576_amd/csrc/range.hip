@@ -187,7 +187,9 @@ __global__ __launch_bounds__(256) void k_range_count(RangeArgs<K, AOS> a) {
 // q2[j] of the range at batch position pos[j], whose upper bound is read
 // there.  The tiles are walked XCD by XCD, so the ranges one XCD has in
 // flight fall in a few buckets whose slice of the index stays in its L2.
-// Both ranks go out in partitioned order.
+// The range's first rank and count go straight to its position (a random
+// 4-byte and 8-byte write per range, cheaper than returning both ranks to
+// the ranges' order by two placement passes).
 // On the sorted array the lower bound's bucket bounds its rank (see
 // bucket_start): both searches start inside that interval, and the upper
 // bound's search widens to the rest of the array only when its answer is
@@ -196,8 +198,7 @@ template <typename K, bool AOS>
 __global__ __launch_bounds__(256) void k_range_count_part(RangeArgs<K, AOS> a, const K *__restrict__ q2,
                                                           const uint32_t *__restrict__ pos,
                                                           const uint16_t *__restrict__ bkt, uint64_t bstep,
-                                                          uint64_t bspan, uint64_t ntiles, uint64_t iters,
-                                                          uint32_t *__restrict__ r0o, uint32_t *__restrict__ r1o) {
+                                                          uint64_t bspan, uint64_t ntiles, uint64_t iters) {
     for (uint64_t it = blockIdx.x; it < iters; it += gridDim.x) {
         const uint64_t tl = tile_of(it, ntiles, 1);
         if (tl >= ntiles) continue;
@@ -221,30 +222,22 @@ __global__ __launch_bounds__(256) void k_range_count_part(RangeArgs<K, AOS> a, c
         } else {
             range_ranks(a, L, U, r0, r1);
         }
-        r0o[j] = (uint32_t)r0;
-        r1o[j] = (uint32_t)r1;
+        const uint32_t p = pos[j];
+        a.first_rank[p] = (uint32_t)r0;
+        a.offsets[p] = r1 > r0 ? r1 - r0 : 0;
     }
 }
 
-__global__ __launch_bounds__(256) void k_range_combine(const uint32_t *__restrict__ r0, const uint32_t *__restrict__ r1,
-                                                       uint64_t m, uint64_t *__restrict__ counts) {
-    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < m) counts[q] = r1[q] > r0[q] ? (uint64_t)(r1[q] - r0[q]) : 0ull;
-}
-
 // Counts through the partition: per chunk of at most 2^31 ranges, partition
-// the lower bounds, count in partitioned order, then place both ranks back
-// at the ranges' positions and take their difference.
+// the lower bounds, then count in partitioned order, each count written at
+// its range's position.
 template <typename K, bool AOS>
 int range_count_partitioned(idx_index *h, const RangeArgs<K, AOS> &a, hipStream_t s) {
     const uint64_t m = a.m;
     const uint64_t chunk = m < kPartChunk ? m : kPartChunk;
     const size_t pb = (partition_scratch_bytes(h, chunk) + 255) & ~(size_t)255;
-    const size_t ab = ((chunk * 4 + 255) / 256) * 256;
-    char *t = (char *)h->alloc.get(pb + 2 * ab, s);
+    char *t = (char *)h->alloc.get(pb, s);
     if (!t) return IDX_ERR_NOMEM;
-    uint32_t *r1p = (uint32_t *)(t + pb);       // past-the-end ranks, partitioned order
-    uint32_t *r1c = (uint32_t *)(t + pb + ab);  // the same at the ranges' positions
     int rc = IDX_OK;
     for (uint64_t c0 = 0; c0 < m && rc == IDX_OK; c0 += chunk) {
         const uint64_t mc = (m - c0) < chunk ? (m - c0) : chunk;
@@ -254,19 +247,12 @@ int range_count_partitioned(idx_index *h, const RangeArgs<K, AOS> &a, hipStream_
         RangeArgs<K, AOS> b = a;
         b.hi = a.hi + c0;
         b.m = mc;
+        b.first_rank = a.first_rank + c0;
+        b.offsets = a.offsets + c0;
         const uint64_t tiles = (mc + 255) / 256;
         const uint64_t iters = ((tiles + kXcds - 1) / kXcds) * kXcds;
         hipLaunchKernelGGL((k_range_count_part<K, AOS>), dim3((uint32_t)iters), dim3(256), 0, s, b, (const K *)v.q,
-                           v.pos, v.bkt, v.bstep, v.bspan, tiles, iters, v.ans, r1p);
-        if (hipGetLastError() != hipSuccess) {
-            rc = IDX_ERR_HIP;
-            break;
-        }
-        rc = partition_place(h, v, v.ans, a.first_rank + c0, s);
-        if (rc == IDX_OK) rc = partition_place(h, v, r1p, r1c, s);
-        if (rc != IDX_OK) break;
-        hipLaunchKernelGGL(k_range_combine, dim3((uint32_t)((mc + 255) / 256)), dim3(256), 0, s, a.first_rank + c0,
-                           r1c, mc, a.offsets + c0);
+                           v.pos, v.bkt, v.bstep, v.bspan, tiles, iters);
         if (hipGetLastError() != hipSuccess) rc = IDX_ERR_HIP;
     }
     h->alloc.put(t, s);

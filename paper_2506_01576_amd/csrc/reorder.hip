@@ -625,19 +625,12 @@ int partition_forward(idx_index *h, const void *q, uint64_t m, void *scratch, Pa
     if (rc != IDX_OK) return rc;
     out->q = P.q2;
     out->pos = P.p2;
-    out->ans = P.p1;
     out->m = m;
     out->scratch = scratch;
     out->bkt = P.bkt;
     out->bstep = h->n / B;
     out->bspan = bucket_span(h->n, B);
     return IDX_OK;
-}
-
-int partition_place(idx_index *h, const PartView &v, const uint32_t *ans, uint32_t *out, hipStream_t s) {
-    const size_t kb = h->u64 ? 8 : 4;
-    const PartBufs P = carve((char *)v.scratch, v.m, kb);
-    return place_back(h, P, v.m, ans, out, s);
 }
 
 void drop_splitters(idx_index *h, hipStream_t s) {
