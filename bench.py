@@ -295,11 +295,9 @@ def run_skewed(args, idx, gen, np, torch, dev, log):
     """The learned-model configuration: n = 2^log2n_skew unique uint64 keys from
     the 64-cluster lognormal mixture, 2^27 lookups: Zipf(1.1)-popular hits
     plus 10% uniform misses.  The learned form with 4096 leaves (the
-    configuration's model) and with the tuned leaf count, against EKS with
-    16 keys per node (k = 17) and k = 16; all must agree, hits must return
-    the generator's rowids."""
-    from paper_2506_01576_amd import autotune
-
+    configuration's model), with 2^22 leaves and with leaf lines, against EKS
+    with 16 keys per node (k = 17) and k = 16; all must agree, hits must
+    return the generator's rowids."""
     n, m = 1 << args.log2n_skew, 1 << 27
     seed = gen.BASE_SEED + 3
     t0 = time.time()
@@ -331,24 +329,22 @@ def run_skewed(args, idx, gen, np, torch, dev, log):
 
     forms, answers = {}, {}
     base = idx.Index(keys, rows, layout="bs")
-    _, _, laos, lp = autotune.choose(1 << 26, 64, "learned")
+    # the 4096-leaf model; 2^22 leaves (window search), the scan in two
+    # rounds and in one (skewed batches keep many windows cached); leaf
+    # lines with about four keys per leaf (spline root)
     cands = [("learned_4096", 4096, False, {"per_lane": 8}),
-             ("learned_tuned", lp.get("leaves", 1 << 22), laos, {"per_lane": lp.get("per_lane", 8)})]
-    if laos:  # the tuned leaf count on the plain sorted array too, at 8 and 4 lookups per lane
-        cands.append(("learned_tuned_soa", lp.get("leaves", 1 << 22), False, {"per_lane": lp.get("per_lane", 8)}))
-        cands.append(("learned_tuned_soa_r4", lp.get("leaves", 1 << 22), False, {"per_lane": 4}))
-        # skewed batches keep many windows cached: the scan in one round as well
-        cands.append(("learned_tuned_soa_r4_1round", lp.get("leaves", 1 << 22), False,
-                      {"per_lane": 4, "window_rounds": 1}))
+             ("learned_2^22_soa_r4", 1 << 22, False, {"per_lane": 4}),
+             ("learned_2^22_soa_r4_1round", 1 << 22, False, {"per_lane": 4, "window_rounds": 1}),
+             ("learned_lines", min(1 << 26, n // 4), False, {"per_lane": 4, "block": 128, "leaf_lines": 1})]
     for name, L, aos, params in cands:
         arr = base if not aos else base.relayout("bs", 1, aos)
+        arr.set_params(model=0, **params)  # leaf lines, when used, are written by the training call
         a = torch.cuda.Event(enable_timing=True)
         b = torch.cuda.Event(enable_timing=True)
         a.record()
         st = arr.learn(L, 2)
         b.record()
         b.synchronize()
-        arr.set_params(model=0, **params)
         ms, res = timed(arr)
         forms[name] = {"leaves": L, "aos": aos, "ms": round(ms, 4), "lookups_per_s": m / ms * 1e3,
                        "train_ms": round(a.elapsed_time(b), 3), "mean_window": st["mean_window"],

@@ -380,7 +380,9 @@ typedef struct idx_learn_stats {
  *   h        an IDX_BS index (any storage: SoA, AoS or line-padded AoS, where
  *            the window scan reads each key with its row ID) with n >= 1
  *            (IDX_ERR_ARG otherwise)
- *   leaves   1 <= leaves <= 2^24;  epochs 1..16;  feature IDX_FEATURE_* (LINEAR
+ *   leaves   1 <= leaves <= 2^26 (a linear root resolves about 2^24 leaves in
+ *            FP32; beyond that only the spline root spreads keys evenly);
+ *            epochs 1..16;  feature IDX_FEATURE_* (LINEAR
  *            and LOG: that linear root; SPLINE: the spline root whose bin
  *            feature has the lower root loss; AUTO: the better linear root and
  *            the spline root each get trained leaves, and the one with the

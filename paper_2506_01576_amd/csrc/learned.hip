@@ -406,7 +406,8 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
                 hipLaunchKernelGGL(k_leaf_update, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_acc, L);
         }
         hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, stats, (uint64_t)4);
-        hipLaunchKernelGGL(k_sum_leaf_loss, dim3(64), dim3(256), 0, s, leaf_acc, L, stats + 2);
+        hipLaunchKernelGGL(k_sum_leaf_loss, dim3(grid_for(L, 256) < 1024 ? grid_for(L, 256) : 1024), dim3(256), 0, s,
+                           leaf_acc, L, stats + 2);
         hipLaunchKernelGGL((k_leaf_errors_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s, keys, leaves, L);
         hipLaunchKernelGGL((k_leaf_errors_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves, d_big);
         hipLaunchKernelGGL(k_leaf_finish, dim3(grid_for(L, 256) < 1024 ? grid_for(L, 256) : 1024), dim3(256), 0, s,
@@ -484,7 +485,7 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
 
 int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream_t s) {
     if (h->layout != IDX_BS || h->n == 0) return IDX_ERR_ARG;
-    if (L == 0 || L > (1u << 24) || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_SPLINE) return IDX_ERR_ARG;
+    if (L == 0 || L > (1u << 26) || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_SPLINE) return IDX_ERR_ARG;
     drop_model(h, s);
     LearnedModel *M = new (std::nothrow) LearnedModel();
     if (!M) return IDX_ERR_NOMEM;
@@ -1389,7 +1390,7 @@ int learn_eval(idx_index *h, uint32_t mode, const float *root_ab, uint32_t L, co
                double *leaf_acc, hipStream_t s) {
     if (h->layout != IDX_BS || h->n == 0) return IDX_ERR_ARG;
     if (mode != IDX_FEATURE_LINEAR && mode != IDX_FEATURE_LOG) return IDX_ERR_ARG;
-    if (L == 0 || L > (1u << 24) || !root_ab || !root_acc) return IDX_ERR_ARG;
+    if (L == 0 || L > (1u << 26) || !root_ab || !root_acc) return IDX_ERR_ARG;
     if (h->u64)
         return h->aos ? eval_t<uint64_t, true>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s)
                       : eval_t<uint64_t, false>(h, mode, root_ab, L, leaf_ab, root_acc, leaf_acc, s);

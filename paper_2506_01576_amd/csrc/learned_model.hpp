@@ -14,7 +14,7 @@ namespace idx {
 struct __align__(16) SplineBin {
     uint64_t anchor;       // smallest build key of the bin (0 for an empty bin)
     uint32_t mul;          // leaves per key offset, 32-bit fixed point
-    uint32_t first_shift;  // bits 0-23: first leaf of the bin; bits 24-31: shift
+    uint32_t first_shift;  // bits 0-25: first leaf of the bin; bits 26-31: shift (<= 32)
 };
 static_assert(sizeof(SplineBin) == 16, "spline bin is 16 bytes");
 
@@ -104,10 +104,10 @@ __host__ __device__ inline void spline_geometry(RootRec &R, uint64_t kmin, uint6
 __device__ __forceinline__ uint32_t spline_leaf(const RootRec &R, uint64_t key, float *coord = nullptr) {
     const SplineBin r = R.bins[bin_of(R, key)];
     const uint64_t d = key > r.anchor ? key - r.anchor : 0ull;
-    const uint32_t sh = r.first_shift >> 24;
+    const uint32_t sh = r.first_shift >> 26;
     const uint64_t prod = (uint64_t)(uint32_t)(d >> sh) * (uint64_t)r.mul;
-    const uint64_t leaf = (uint64_t)(r.first_shift & 0xFFFFFFu) + (prod >> 32);
-    if (coord) *coord = __fadd_rn((float)(r.first_shift & 0xFFFFFFu), __fmul_rn((float)prod, 0x1p-32f));
+    const uint64_t leaf = (uint64_t)(r.first_shift & 0x3FFFFFFu) + (prod >> 32);
+    if (coord) *coord = __fadd_rn((float)(r.first_shift & 0x3FFFFFFu), __fmul_rn((float)prod, 0x1p-32f));
     return leaf < R.L ? (uint32_t)leaf : R.L - 1;
 }
 
@@ -166,7 +166,7 @@ __host__ __device__ inline SplineBin spline_bin(const KeyAt &key, uint64_t n, co
     const uint64_t ws = (wm1 >> sh) + 1;  // <= 2^32
     const uint64_t m = ((f1 - f0) << 32) / ws;
     out.mul = m > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)m;
-    out.first_shift = (uint32_t)f0 | (sh << 24);
+    out.first_shift = (uint32_t)f0 | (sh << 26);
     return out;
 }
 

@@ -99,7 +99,7 @@ uint32_t merge_grid(uint64_t total) {
 }
 
 // ---- blob format (host, little endian)
-constexpr char kMagic[8] = {'I', 'D', 'X', 'B', 'L', 'O', 'B', '1'};
+constexpr char kMagic[8] = {'I', 'D', 'X', 'B', 'L', 'O', 'B', '2'};  // 2: spline bins with 26-bit first leaves
 
 struct BlobHeader {
     char magic[8];
@@ -249,7 +249,7 @@ int idx_load(const void *blob, uint64_t size, const idx_allocator *alloc, idx_st
     BlobHeader hd;
     std::memcpy(&hd, blob, sizeof(hd));
     if (std::memcmp(hd.magic, kMagic, sizeof(kMagic)) != 0) return IDX_ERR_ARG;
-    if (hd.has_model > 1 || (hd.has_model && (hd.layout != IDX_BS || hd.leaves == 0 || hd.leaves > (1u << 24) ||
+    if (hd.has_model > 1 || (hd.has_model && (hd.layout != IDX_BS || hd.leaves == 0 || hd.leaves > (1u << 26) ||
                                               hd.root.L != hd.leaves || hd.root.mode == 0 ||
                                               hd.root.mode > IDX_FEATURE_SPLINE ||
                                               (hd.root.mode == IDX_FEATURE_SPLINE &&

@@ -150,7 +150,7 @@ def test_learn_rejects_other_layouts():
         with pytest.raises(idx.IdxError):
             ix.learn(64)
     with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
-        for bad in ((0, 2, AUTO), ((1 << 24) + 1, 2, AUTO), (64, 0, AUTO), (64, 2, 4)):
+        for bad in ((0, 2, AUTO), ((1 << 26) + 1, 2, AUTO), (64, 0, AUTO), (64, 2, 4)):
             with pytest.raises(idx.IdxError):
                 ix.learn(*bad)
 
@@ -299,6 +299,36 @@ def test_spline_root_partition_matches_oracle(kind, leaves, aos):
     assert np.array_equal(table[:, 12:16].copy().view(np.uint32).ravel(), size.astype(np.uint32))
     assert np.array_equal(table[:, 8:12].copy().view(np.uint32).ravel(), base.astype(np.uint32))
     assert np.array_equal(got, oracle.point(sk, sr, q, nthreads=4))
+
+
+def test_spline_root_beyond_2p24_leaves():
+    """A spline root with more than 2^24 leaves (the first-leaf field's upper
+    bits): the leaf sizes and bases equal the oracle's evaluation of the same
+    definition, and points (every build key, misses) and ranges through the
+    model, with and without leaf lines, equal the oracle's answers."""
+    n, leaves = 1 << 20, (1 << 25) + 3
+    keys, rows = make("lognormal", n, seed=25)
+    sk, sr = oracle.stable_sort(keys, rows)
+    q = queries(keys, 1 << 16, 26)
+    L, U, _ = gen.ranges(27, keys, 4001, 1, 64)
+    woff, wrows = oracle.range_lookup(sk, sr, L, U, nthreads=4)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        st = ix.learn(leaves, 1, SPLINE)
+        words = ix.learn_export().view(torch.int32).reshape(leaves, 8)
+        base_d, size_d = words[:, 2].cpu().numpy().view(np.uint32), words[:, 3].cpu().numpy().view(np.uint32)
+        del words
+        leaf = oracle_leaves(sk, st, leaves)
+        assert int(leaf.max()) >= 1 << 24  # keys reach leaves beyond 2^24
+        _, _, base, size = oracle.leaf_frame(sk, leaf, leaves)
+        assert np.array_equal(size_d, size.astype(np.uint32))
+        assert np.array_equal(base_d, base.astype(np.uint32))
+        for lines in (2, 1):
+            ix.set_params(leaf_lines=lines)
+            assert np.array_equal(rows_host(ix.point(to_dev(q))), oracle.point(sk, sr, q, nthreads=4))
+            assert np.array_equal(rows_host(ix.point(to_dev(keys))), oracle.point(sk, sr, keys, nthreads=4))
+            off, rr = ix.range(to_dev(L), to_dev(U))
+            assert np.array_equal(off.cpu().numpy().view(np.uint64), woff)
+            assert np.array_equal(rows_host(rr), wrows)
 
 
 def test_spline_root_gain_on_clustered_keys():
