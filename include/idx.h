@@ -214,7 +214,9 @@ int idx_range(idx_handle h, const void *lo, const void *hi, uint64_t m, uint64_t
  * the caller.  IDX_ERR_SCRATCH when m > IDX_NOALLOC_MAX_RANGES (nothing is
  * enqueued).  The rank-bucket partition (lookup parameter reorder = 2) needs
  * scratch proportional to the batch, so these calls count unpartitioned;
- * the answers are the same.  Synchronises `stream` once, like idx_range.
+ * and a learned model's leaf lines (leaf_lines = 1) are used only when they
+ * exist already (else the leaf records' windows are searched); the answers
+ * are the same.  Synchronises `stream` once, like idx_range.
  */
 #define IDX_NOALLOC_MAX_RANGES (1ull << 23)
 int idx_range_noalloc(idx_handle h, const void *lo, const void *hi, uint64_t m, uint64_t *out_offsets,

@@ -186,8 +186,10 @@ int point_learned(idx_index *h, const PointIO &io, hipStream_t s);
 // The attached model's leaf lines, written unless they are there.
 int ensure_lines(idx_index *h, hipStream_t s);
 // first-match ranks and counts of ranges through the model
+// may_alloc: the leaf lines may be written here (else they are used only if
+// they exist).
 int range_count_learned(idx_index *h, const void *lo, const void *hi, uint64_t m, uint32_t *first, uint64_t *count,
-                        hipStream_t s);
+                        bool may_alloc, hipStream_t s);
 
 // ---- abi.hip: handle life cycle ----------------------------------------------
 // A handle with its layout buffers allocated (validates layout, k, flags).

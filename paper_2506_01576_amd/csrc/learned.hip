@@ -1316,8 +1316,8 @@ void launch_range_count(const idx_index *h, const void *lo, const void *hi, uint
 }  // namespace
 
 int range_count_learned(idx_index *h, const void *lo, const void *hi, uint64_t m, uint32_t *first, uint64_t *count,
-                        hipStream_t s) {
-    if (h->params.leaf_lines == 1) {
+                        bool may_alloc, hipStream_t s) {
+    if (h->params.leaf_lines == 1 && may_alloc) {
         const int rc = ensure_lines(h, s);
         if (rc != IDX_OK) return rc;
     }

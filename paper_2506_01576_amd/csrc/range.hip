@@ -497,7 +497,9 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
     const uint32_t blocks = (uint32_t)((m + 255) / 256);
     do {
         if (h->learned && h->params.model != 2) {
-            rc = range_count_learned(h, lo, hi, m, a.first_rank, offsets, s);
+            // the no-allocation entry point uses leaf lines only when they
+            // exist already (writing them would allocate)
+            rc = range_count_learned(h, lo, hi, m, a.first_rank, offsets, given == nullptr, s);
             if (rc != IDX_OK) break;
         } else if (h->params.reorder >= 2 && !given && h->n >= 4) {
             // the caller-given scratch (no-allocation entry point) has no room

@@ -48,14 +48,31 @@ def _both(ix, lo, hi):
 
 
 @pytest.mark.parametrize("layout,k,bits,learn", [("bs", 1, 64, False), ("eks", 9, 32, False),
-                                                 ("ebs", 2, 64, False), ("bs", 1, 64, True)])
+                                                 ("ebs", 2, 64, False), ("bs", 1, 64, True),
+                                                 ("bs", 1, 64, "lines"), ("bs", 1, 32, "lines_later")])
 def test_noalloc_matches_idx_range(layout, k, bits, learn):
     n = 30011
     seed = gen.BASE_SEED + 77
     keys, rows = gen.unique_keys(seed, n, bits)
     sk, sr = oracle.stable_sort(keys, rows)
     with idx.Index(to_dev(keys), to_dev(rows), layout=layout, k=k) as ix:
-        if learn:
+        if learn == "lines":  # leaf lines written by the training call
+            ix.set_params(leaf_lines=1)
+            ix.learn(n // 4, 2)
+        elif learn == "lines_later":  # leaf lines asked for after training: not written yet
+            ix.learn(n // 4, 2)
+            ix.set_params(leaf_lines=1)
+            # the no-allocation call searches the leaf records' windows (it may
+            # not write the lines); idx_range below then writes them
+            lo, hi = _ranges(keys, 2000, 50, seed + 9)
+            off = torch.empty(len(lo) + 1, dtype=torch.int64, device="cuda")
+            out = torch.empty(2000 * 50, dtype=torch.int32, device="cuda")
+            total = ix.range_noalloc(to_dev(lo), to_dev(hi), off, out)
+            want_off, want_rows = oracle.range_lookup(sk, sr, lo, hi)
+            assert total == int(want_off[-1])
+            assert np.array_equal(off.cpu().numpy().view(np.uint64), want_off)
+            assert np.array_equal(rows_host(out[:total]), want_rows)
+        elif learn:
             ix.learn(256, 2)
         # two calls in a row, the second smaller
         for call, (m, width) in enumerate(((9000, 300), (1500, 40))):
