@@ -320,10 +320,11 @@ typedef struct idx_lookup_params {
                             of the count phase, each read at the slot the layout build wrote
                             that rank to (the inverse permutation, no key reads) */
     uint32_t leaf_lines; /* learned form: 0 = default (2); 1 = give every leaf of the model one
-                            128-byte line holding its base rank, its size and, when it has at
-                            most 10 keys (64-bit keys; 15 for 32-bit keys), those keys and their
-                            row IDs, else its leaf record: a point lookup or a range bound then
-                            reads the root's line and, for small leaves, nothing else; two
+                            128-byte line holding its base rank, its size and its first 10 keys
+                            (64-bit keys; 15 for 32-bit keys) with their row IDs: a point lookup
+                            or a range bound then reads the root's line and nothing else unless
+                            it lies past those keys in a larger leaf (then the rest of the leaf
+                            is searched in the sorted array); two
                             lanes share each lookup, one per half line (at most 256 threads per
                             workgroup are used, and with reorder = 1, where each lane reads its
                             whole line, at most 4 lookups per lane).  The

@@ -774,21 +774,6 @@ __global__ __launch_bounds__(1024) void k_point_learned(Load<K, AOS> keys, uint6
 
 // ------------------------------------------------------------- leaf lines
 
-// Word i of a leaf record as laid out in memory (kmin low, kmin high, base,
-// size, b0, b1, elo, ehi).
-__device__ __forceinline__ uint32_t rec_word(const LeafRec &r, uint32_t i) {
-    switch (i) {
-        case 0: return (uint32_t)r.kmin;
-        case 1: return (uint32_t)(r.kmin >> 32);
-        case 2: return r.base;
-        case 3: return r.size;
-        case 4: return __float_as_uint(r.b0);
-        case 5: return __float_as_uint(r.b1);
-        case 6: return (uint32_t)r.elo;
-        default: return (uint32_t)r.ehi;
-    }
-}
-
 // The leaf lines (line layout at line_scan), one thread per 16-byte chunk,
 // so that a wave writes four whole lines.
 template <typename K, bool AOS>
@@ -809,8 +794,6 @@ __global__ __launch_bounds__(256) void k_leaf_lines(Load<K, AOS> keys, const Lea
             x = r.base;
         } else if (wi == 1) {
             x = r.size;
-        } else if (r.size > C) {
-            if (wi >= 4 && wi < 12) x = rec_word(r, wi - 4);
         } else if (wi < 2 + C * KW) {
             const uint32_t j = (wi - 2) / KW;
             if (j < r.size) {
@@ -898,11 +881,10 @@ __global__ __launch_bounds__(256) void k_point_lines(Load<K, AOS> keys, uint64_t
             if (tile_valid(io.m, t0, src_of<R, SORT>(src, r))) {
                 uint32_t cnt, row;
                 bool eq;
-                if (line_scan<K>(w[r], x[r], cnt, eq, row)) {
+                if (line_scan<K>(w[r], x[r], cnt, eq, row, b[r], len[r])) {
                     if (eq) res[r] = row;
                 } else {
                     big[r] = true;
-                    leaf_window(line_leaf(w[r]), (uint64_t)x[r], b[r], len[r]);
                 }
             }
         }
@@ -922,8 +904,9 @@ __global__ __launch_bounds__(256) void k_point_lines(Load<K, AOS> keys, uint64_t
 // lines/s).  Each lane counts its half's keys below x and at most x; the pair
 // adds both counts with one exchange each, and a hit is a key equal to x
 // (more keys at most x than below it).  The row IDs lie in the upper half, so
-// its lane writes the answer; for a leaf held by record (in the lower half)
-// the lower lane searches the window and writes.
+// its lane writes the answer; when x lies past every key of the line in a
+// leaf that has more, the lower lane searches the rest of the leaf in the
+// sorted array and writes.
 template <typename K, int R, bool AOS, bool TWO>
 __global__ __launch_bounds__(256) void k_point_lines_pair(Load<K, AOS> keys, uint64_t n, RootRec root,
                                                           const uint4 *__restrict__ lines, QueryIO<K> io) {
@@ -966,21 +949,23 @@ __global__ __launch_bounds__(256) void k_point_lines_pair(Load<K, AOS> keys, uin
             b[r] = len[r] = 0;
             const uint32_t other = __shfl_xor(w[r][0].y, 1);
             const uint32_t size = hf ? other : w[r][0].y;
-            big[r] = size > C;
-            if (!big[r]) {
-                uint32_t lt = 0, le = 0;
+            uint32_t lt = 0, le = 0;
 #pragma unroll
-                for (int i = 0; i < 16; i += (int)KW) {
-                    const uint32_t wi = 16 * hf + (uint32_t)i;
-                    K key;
-                    if constexpr (KW == 2) key = ((uint64_t)word(i + 1) << 32) | word(i);
-                    else key = word(i);
-                    const bool in = wi >= 2 && wi < R0 && (wi - 2) / KW < size;
-                    lt += (in && key < x[r]) ? 1u : 0u;
-                    le += (in && key <= x[r]) ? 1u : 0u;
-                }
-                lt += __shfl_xor(lt, 1);
-                le += __shfl_xor(le, 1);
+            for (int i = 0; i < 16; i += (int)KW) {
+                const uint32_t wi = 16 * hf + (uint32_t)i;
+                K key;
+                if constexpr (KW == 2) key = ((uint64_t)word(i + 1) << 32) | word(i);
+                else key = word(i);
+                const bool in = wi >= 2 && wi < R0 && (wi - 2) / KW < size;
+                lt += (in && key < x[r]) ? 1u : 0u;
+                le += (in && key <= x[r]) ? 1u : 0u;
+            }
+            lt += __shfl_xor(lt, 1);
+            le += __shfl_xor(le, 1);
+            // past every key of the line in a leaf that has more: the rest
+            // of the leaf is searched in the sorted array (by the lower lane)
+            big[r] = lt == C && size > C;
+            if (!big[r]) {
                 if (le > lt) {
                     const uint32_t ri = R0 - 16 + lt;  // the row ID's word in the upper half
                     uint32_t row = 0;
@@ -989,7 +974,8 @@ __global__ __launch_bounds__(256) void k_point_lines_pair(Load<K, AOS> keys, uin
                     res[r] = row;
                 }
             } else if (hf == 0) {
-                leaf_window(leaf_of_chunks(w[r][1], w[r][2]), (uint64_t)x[r], b[r], len[r]);
+                b[r] = (uint64_t)w[r][0].x + C;
+                len[r] = size - C;
             }
         }
 #pragma unroll
@@ -1238,8 +1224,9 @@ __device__ __forceinline__ uint64_t window_lower_rank(const Load<K, AOS> &keys, 
 
 // Lower-bound rank of x from half hf of its leaf's line (w), as two lanes of
 // a pair hold it (both call this together; the lower lane gets the rank):
-// the base rank plus the leaf's keys below x, or for a leaf held by record
-// (in the lower half) a search of its window by the lower lane.
+// the base rank plus the line's keys below x, or, when x lies past every key
+// of the line in a leaf that has more, a search of the rest of the leaf by
+// the lower lane.
 template <typename K, bool AOS>
 __device__ __forceinline__ uint64_t pair_lower_rank(const Load<K, AOS> &keys, const uint4 (&w)[4], uint32_t hf, K x) {
     constexpr uint32_t C = line_slots<K>();
@@ -1251,23 +1238,19 @@ __device__ __forceinline__ uint64_t pair_lower_rank(const Load<K, AOS> &keys, co
     };
     const uint32_t other = __shfl_xor(w[0].y, 1);
     const uint32_t size = hf ? other : w[0].y;
-    if (size <= C) {
-        uint32_t lt = 0;
+    uint32_t lt = 0;
 #pragma unroll
-        for (int i = 0; i < 16; i += (int)KW) {
-            const uint32_t wi = 16 * hf + (uint32_t)i;
-            K key;
-            if constexpr (KW == 2) key = ((uint64_t)word(i + 1) << 32) | word(i);
-            else key = word(i);
-            lt += (wi >= 2 && wi < R0 && (wi - 2) / KW < size && key < x) ? 1u : 0u;
-        }
-        lt += __shfl_xor(lt, 1);
-        return (uint64_t)w[0].x + lt;
+    for (int i = 0; i < 16; i += (int)KW) {
+        const uint32_t wi = 16 * hf + (uint32_t)i;
+        K key;
+        if constexpr (KW == 2) key = ((uint64_t)word(i + 1) << 32) | word(i);
+        else key = word(i);
+        lt += (wi >= 2 && wi < R0 && (wi - 2) / KW < size && key < x) ? 1u : 0u;
     }
+    lt += __shfl_xor(lt, 1);
+    if (lt < C || size <= C) return (uint64_t)w[0].x + lt;
     if (hf != 0) return 0;
-    uint64_t b, len;
-    leaf_window(leaf_of_chunks(w[1], w[2]), (uint64_t)x, b, len);
-    return window_lower_rank<K, AOS>(keys, b, len, x);
+    return window_lower_rank<K, AOS>(keys, (uint64_t)w[0].x + C, size - C, x);
 }
 
 // Range counts through the leaf lines, two lanes per range (each loads one

@@ -214,10 +214,11 @@ __device__ __forceinline__ void learned_window(const RootRec &root, const LeafRe
 // key, so every build key below x lies in a leaf before x's leaf or in it,
 // and every key above x in it or after it: the lower bound of x is the
 // leaf's base rank plus the leaf's keys below x.  Line layout (32-bit
-// words): word 0 the base rank, word 1 the size; a leaf of at most
-// line_slots keys holds them from byte 8 in ascending order, then their row
-// IDs; a larger leaf holds its leaf record at bytes 16-47, whose window is
-// searched in the sorted array instead.
+// words): word 0 the base rank, word 1 the size; from byte 8 the leaf's
+// first min(size, line_slots) keys in ascending order, then their row IDs.
+// When x is above every key the line holds and the leaf has more, its lower
+// bound lies among the leaf's remaining keys [base + line_slots, base +
+// size), which are searched in the sorted array.
 constexpr uint32_t kLineBytes = 128;
 constexpr uint32_t kLineChunks = kLineBytes / 16;
 
@@ -238,18 +239,23 @@ __device__ __forceinline__ K line_key(const uint4 (&w)[kLineChunks], int j) {
     else return line_word(w, 2 + j);
 }
 
-// Keys of an inline leaf below x (cnt), and the row ID of the key at rank
-// cnt when it equals x.  False, with nothing set, for a leaf held by record.
+// The line's keys below x (cnt), and the row ID of the key at rank cnt when
+// it equals x.  False when the lower bound lies past the line's keys in a
+// leaf that has more: [tail, tail + tail_len] then holds it.
 template <typename K>
 __device__ __forceinline__ bool line_scan(const uint4 (&w)[kLineChunks], K x, uint32_t &cnt, bool &eq,
-                                          uint32_t &row) {
+                                          uint32_t &row, uint64_t &tail, uint64_t &tail_len) {
     constexpr uint32_t C = line_slots<K>();
     constexpr int R0 = 2 + (int)(C * sizeof(K) / 4);  // first row ID word
     const uint32_t size = w[0].y;
-    if (size > C) return false;
     uint32_t c = 0;
 #pragma unroll
     for (int j = 0; j < (int)C; ++j) c += ((uint32_t)j < size && line_key<K>(w, j) < x) ? 1u : 0u;
+    if (c == C && size > C) {
+        tail = (uint64_t)w[0].x + C;
+        tail_len = size - C;
+        return false;
+    }
     bool e = false;
     uint32_t r = kMiss;
 #pragma unroll
@@ -263,21 +269,6 @@ __device__ __forceinline__ bool line_scan(const uint4 (&w)[kLineChunks], K x, ui
     row = r;
     return true;
 }
-
-// The leaf record a line of a large leaf holds, from its chunks 1 and 2.
-__device__ __forceinline__ LeafRec leaf_of_chunks(const uint4 &c1, const uint4 &c2) {
-    LeafRec L;
-    L.kmin = ((uint64_t)c1.y << 32) | c1.x;
-    L.base = c1.z;
-    L.size = c1.w;
-    L.b0 = __uint_as_float(c2.x);
-    L.b1 = __uint_as_float(c2.y);
-    L.elo = (int32_t)c2.z;
-    L.ehi = (int32_t)c2.w;
-    return L;
-}
-
-__device__ __forceinline__ LeafRec line_leaf(const uint4 (&w)[kLineChunks]) { return leaf_of_chunks(w[1], w[2]); }
 
 // Lower-bound rank of x through the model (exact: the window holds it).
 template <typename K>

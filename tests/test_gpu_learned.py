@@ -389,11 +389,12 @@ def test_window_rounds_parity(aos, rounds):
 @pytest.mark.parametrize("kind", ["uniform32", "uniform64", "lognormal", "dup"])
 @pytest.mark.parametrize("per_leaf", [0.25, 3, 8, 40])
 def test_leaf_lines_parity(kind, per_leaf, aos):
-    """Lookups through the leaf lines (one 128-byte line per leaf, small
-    leaves inline, larger ones by their leaf record): point lookups of every
-    build key and of misses, range counts and row IDs equal the oracle's in
-    every storage and at every lookup count per lane; the lines follow a
-    retrained model; leaf_lines = 2 returns to the window search."""
+    """Lookups through the leaf lines (one 128-byte line per leaf holding its
+    first keys; past them a larger leaf's rest is searched in the sorted
+    array): point lookups of every build key and of misses, range counts and
+    row IDs equal the oracle's in every storage and at every lookup count per
+    lane; the lines follow a retrained model; leaf_lines = 2 returns to the
+    window search."""
     n = 50021
     keys, rows = make(kind, n, seed=int(per_leaf * 4) + 1)
     sk, sr = oracle.stable_sort(keys, rows)
@@ -410,8 +411,8 @@ def test_leaf_lines_parity(kind, per_leaf, aos):
         leaves = max(1, int(n / per_leaf))
         ix.learn(leaves, 2)
         sizes = ix.learn_export().cpu().numpy().view(np.uint8).reshape(leaves, 32)[:, 12:16].copy().view(np.uint32)
-        say(f"  leaves {leaves}: inline {int((sizes <= cap).sum())}, by record {int((sizes > cap).sum())}")
-        if per_leaf == 8:  # both kinds of line
+        say(f"  leaves {leaves}: within a line {int((sizes <= cap).sum())}, larger {int((sizes > cap).sum())}")
+        if per_leaf == 8:  # both kinds of leaf
             assert (sizes <= cap).any() and (sizes > cap).any()
         # lookups per lane pair; partitioned batches (answers placed back or
         # written in place); locally sorted tiles (one lane per line);
