@@ -119,14 +119,15 @@ def algo_bytes(form: str, n: int, k: int, key_bytes: int, early_exit: bool = Tru
 # the layout stores them (sampled at random ranks: consecutive ranks lie in
 # one run on the sorted array, on a few levels of an Eytzinger layout).
 def line_overflow(ix, leaves: int, cap: int) -> float:
-    """Share of the build keys (so of uniform hit lookups) whose leaf has more
-    than `cap` keys and is held in its line by record, from the exported leaf
-    table (word 3 of each 32-byte record is the leaf's size)."""
+    """Share of the build keys (so of uniform hit lookups) that lie past the
+    first `cap` keys of their leaf, whose lookups search the rest of the leaf
+    beyond its line, from the exported leaf table (word 3 of each 32-byte
+    record is the leaf's size)."""
     import torch
 
     sizes = ix.learn_export().view(torch.int32).reshape(leaves, 8)[:, 3].to(torch.int64)
     tot = int(sizes.sum())
-    return float(sizes[sizes > cap].sum()) / tot if tot else 0.0
+    return float((sizes - cap).clamp(min=0).sum()) / tot if tot else 0.0
 
 
 def algo_bytes_range(form: str, n: int, k: int, key_bytes: int, width: int, rank_slot=None, window: float = 0.0,
