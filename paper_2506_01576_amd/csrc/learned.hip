@@ -835,8 +835,8 @@ __device__ __forceinline__ uint32_t window_find(const Load<K, AOS> &keys, uint64
     }
 }
 
-// The same, kept out of line: called only for the few lookups in leaves too
-// large for their line, so the callers' loops over their lookups stay small
+// The same, kept out of line: called only for the few lookups that go past
+// their leaf's line, so the callers' loops over their lookups stay small
 // enough to unroll.
 template <typename K, bool AOS>
 __device__ __noinline__ uint32_t window_find_call(Load<K, AOS> keys, uint64_t n, uint64_t b, uint64_t len, K x,
@@ -844,10 +844,11 @@ __device__ __noinline__ uint32_t window_find_call(Load<K, AOS> keys, uint64_t n,
     return window_find<K, AOS>(keys, n, b, len, x, two);
 }
 
-// Point lookups through the leaf lines: the R lookups of a lane load their
-// leaves' lines together (eight independent 16-byte loads of one line each),
-// then each is answered from its registers; a lookup in a leaf held by
-// record searches that record's window instead.
+// Point lookups through the leaf lines, one lane per lookup (the sorted-tile
+// form): the R lookups of a lane load their leaves' lines together (eight
+// independent 16-byte loads of one line each), then each is answered from
+// its registers; a lookup past every key of its line in a larger leaf
+// searches the rest of that leaf in the sorted array.
 template <typename K, int R, bool SORT, bool AOS, bool TWO>
 __global__ __launch_bounds__(256) void k_point_lines(Load<K, AOS> keys, uint64_t n, RootRec root,
                                                      const uint4 *__restrict__ lines, QueryIO<K> io) {
@@ -868,8 +869,8 @@ __global__ __launch_bounds__(256) void k_point_lines(Load<K, AOS> keys, uint64_t
 #pragma unroll
             for (int c = 0; c < (int)kLineChunks; ++c) w[r][c] = v ? p[c] : make_uint4(0u, 0u, 0u, 0u);
         }
-        // answers from the lines first, so that no line is held while a
-        // large leaf's window is searched
+        // answers from the lines first, so that no line is held while the
+        // rest of a larger leaf is searched
         uint32_t res[R];
         uint64_t b[R], len[R];
         bool big[R];
