@@ -198,32 +198,40 @@ __global__ void k_leaf_update(LeafRec *__restrict__ leaves, const double *__rest
     leaves[l].b1 = r.b1;
 }
 
-// Per-leaf error bounds, one thread per leaf of at most kLeafCap keys.
+// Per-leaf error bounds, one thread per leaf of at most kLeafCap keys, and
+// those leaves' squared residuals added to *loss (one atomic per wave).
 template <typename K, bool AOS>
 __global__ __launch_bounds__(kLeafBlock) void k_leaf_errors_small(Load<K, AOS> keys, LeafRec *__restrict__ leaves,
-                                                                  uint32_t L) {
+                                                                  uint32_t L, double *__restrict__ loss) {
     __shared__ K s_key[kStageKeys];
     uint64_t kb;
     const bool staged = stage_leaf_keys(keys, leaves, L, s_key, kb);
     const uint32_t l = blockIdx.x * kLeafBlock + threadIdx.x;
-    if (l >= L) return;
-    const LeafRec r = leaves[l];
-    if (r.size == 0 || r.size > kLeafCap) return;
-    long long lo, hi;
-    if (staged) leaf_errs_thread([&](uint64_t i) { return (uint64_t)s_key[i - kb]; }, r, lo, hi);
-    else leaf_errs_thread([&](uint64_t i) { return (uint64_t)keys.key(i); }, r, lo, hi);
-    leaves[l].elo = (int32_t)lo;
-    leaves[l].ehi = (int32_t)hi;
+    double ls = 0.0;
+    if (l < L) {
+        const LeafRec r = leaves[l];
+        if (r.size != 0 && r.size <= kLeafCap) {
+            long long lo, hi;
+            if (staged) leaf_errs_thread([&](uint64_t i) { return (uint64_t)s_key[i - kb]; }, r, lo, hi, &ls);
+            else leaf_errs_thread([&](uint64_t i) { return (uint64_t)keys.key(i); }, r, lo, hi, &ls);
+            leaves[l].elo = (int32_t)lo;
+            leaves[l].ehi = (int32_t)hi;
+        }
+    }
+    ls = wave_sum(ls);
+    if ((threadIdx.x & (kWave - 1)) == 0 && ls != 0.0) atomicAdd(loss, ls);
 }
 
 // Error bounds of the leaves larger than kLeafCap (the wave walk).
 template <typename K, bool AOS>
 __global__ __launch_bounds__(LT) void k_leaf_errors_big(Load<K, AOS> keys, uint64_t n, const RootRec *Rp,
-                                                        LeafRec *__restrict__ leaves, const uint32_t *big) {
+                                                        LeafRec *__restrict__ leaves, const uint32_t *big,
+                                                        double *__restrict__ loss) {
     if (*big == 0u) return;
     const RootRec R = *Rp;
     const uint64_t b = ((uint64_t)blockIdx.x * LT + (threadIdx.x & ~(uint32_t)(kWave - 1))) * CHUNK;
     const uint64_t e = b + (uint64_t)kWave * CHUNK < n ? b + (uint64_t)kWave * CHUNK : n;
+    double ls = 0.0;  // this lane's squared residuals over the large leaves' keys
     wave_leaf_maxes(
         b, e,
         [&](uint64_t i, uint32_t &l, long long *a) {
@@ -234,12 +242,15 @@ __global__ __launch_bounds__(LT) void k_leaf_errors_big(Load<K, AOS> keys, uint6
             const long long err = leaf_err(L, i, key);
             a[0] = -err;
             a[1] = err;
+            ls += leaf_sq_residual(L, i, key);
             return true;
         },
         [&](uint32_t l, const long long *v) {
             atomicMin(&leaves[l].elo, (int32_t)(-v[0]));
             atomicMax(&leaves[l].ehi, (int32_t)v[1]);
         });
+    ls = wave_sum(ls);
+    if ((threadIdx.x & (kWave - 1)) == 0 && ls != 0.0) atomicAdd(loss, ls);
 }
 
 // Empty leaves get a zero window; statistics of the windows.
@@ -284,14 +295,6 @@ __global__ __launch_bounds__(256) void k_leaf_finish(LeafRec *__restrict__ leave
             old = prev;
         }
     }
-}
-
-__global__ void k_sum_leaf_loss(const double *__restrict__ acc, uint32_t L, double *out) {
-    double s = 0;
-    for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < L; l += gridDim.x * blockDim.x)
-        s += acc[(uint64_t)l * NACC + 5];
-    s = wave_sum(s);
-    if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(out, s);
 }
 
 // Spline root geometry from the smallest and largest build key (one thread).
@@ -397,19 +400,19 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
         int rc = leaf_layout<K, AOS>(keys, n, d_root, L, count, partial, leaves, s);
         if (rc != IDX_OK) return rc;
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, d_big, (uint64_t)1, 0u);
-        for (uint32_t ep = 0; ep <= epochs; ++ep) {
+        for (uint32_t ep = 0; ep < epochs; ++ep) {
             hipLaunchKernelGGL((k_leaf_accum_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s, keys, leaves, L,
                                leaf_acc, d_big);
             hipLaunchKernelGGL((k_leaf_accum_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
                                leaf_acc, d_big);
-            if (ep < epochs)
-                hipLaunchKernelGGL(k_leaf_update, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_acc, L);
+            hipLaunchKernelGGL(k_leaf_update, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_acc, L);
         }
+        // the final leaf loss comes with the error bounds (same walk)
         hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, stats, (uint64_t)4);
-        hipLaunchKernelGGL(k_sum_leaf_loss, dim3(grid_for(L, 256) < 1024 ? grid_for(L, 256) : 1024), dim3(256), 0, s,
-                           leaf_acc, L, stats + 2);
-        hipLaunchKernelGGL((k_leaf_errors_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s, keys, leaves, L);
-        hipLaunchKernelGGL((k_leaf_errors_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves, d_big);
+        hipLaunchKernelGGL((k_leaf_errors_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s, keys, leaves, L,
+                           stats + 2);
+        hipLaunchKernelGGL((k_leaf_errors_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves, d_big,
+                           stats + 2);
         hipLaunchKernelGGL(k_leaf_finish, dim3(grid_for(L, 256) < 1024 ? grid_for(L, 256) : 1024), dim3(256), 0, s,
                            leaves, L, stats);
         if (hipGetLastError() != hipSuccess) return IDX_ERR_HIP;

@@ -457,9 +457,19 @@ __device__ __forceinline__ void leaf_sums_thread(const KeyAt &key, const LeafRec
     }
 }
 
-// The error bounds of one leaf, walked by one thread.
+// A key's squared FP32 forward residual (the loss term of leaf_terms).
+__device__ __forceinline__ double leaf_sq_residual(const LeafRec &L, uint64_t i, uint64_t key) {
+    const float d = local_feature(L, key);
+    const float y = (float)(uint32_t)(i - L.base);
+    const float r = __fsub_rn(__fadd_rn(__fmul_rn(L.b1, d), L.b0), y);
+    return (double)r * r;
+}
+
+// The error bounds of one leaf, walked by one thread; with loss, the leaf's
+// squared residuals are added to *loss in the same walk.
 template <typename KeyAt>
-__device__ __forceinline__ void leaf_errs_thread(const KeyAt &key, const LeafRec &L, long long &lo, long long &hi) {
+__device__ __forceinline__ void leaf_errs_thread(const KeyAt &key, const LeafRec &L, long long &lo, long long &hi,
+                                                 double *loss = nullptr) {
     lo = INT_MAX;
     hi = INT_MIN;
     const uint64_t end = (uint64_t)L.base + L.size;
@@ -473,6 +483,7 @@ __device__ __forceinline__ void leaf_errs_thread(const KeyAt &key, const LeafRec
             const long long e = leaf_err(L, i0 + u, kb[u]);
             lo = e < lo ? e : lo;
             hi = e > hi ? e : hi;
+            if (loss) *loss += leaf_sq_residual(L, i0 + u, kb[u]);
         }
     }
 }
