@@ -145,8 +145,11 @@ __device__ __forceinline__ bool stage_leaf_keys(Load<K, AOS> keys, const LeafRec
 
 // Per-leaf sums, one thread per leaf over its key range; a leaf of more than
 // kLeafCap keys gets zero sums here and raises *big for k_leaf_accum_big.
-template <typename K, bool AOS>
-__global__ __launch_bounds__(kLeafBlock) void k_leaf_accum_small(Load<K, AOS> keys, const LeafRec *__restrict__ leaves,
+// UPDATE (training): a leaf of at most kLeafCap keys takes its Newton step
+// at once from the sums in registers, which are not stored; the large
+// leaves' steps follow k_leaf_accum_big (k_leaf_update_big).
+template <typename K, bool AOS, bool UPDATE = false>
+__global__ __launch_bounds__(kLeafBlock) void k_leaf_accum_small(Load<K, AOS> keys, LeafRec *__restrict__ leaves,
                                                                  uint32_t L, double *__restrict__ acc, uint32_t *big) {
     __shared__ K s_key[kStageKeys];
     uint64_t kb;
@@ -158,6 +161,13 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_accum_small(Load<K, AOS> ke
     if (r.size > kLeafCap) *big = 1u;
     else if (staged) leaf_sums_thread([&](uint64_t i) { return (uint64_t)s_key[i - kb]; }, r, a);
     else leaf_sums_thread([&](uint64_t i) { return (uint64_t)keys.key(i); }, r, a);
+    if (UPDATE && r.size <= kLeafCap) {
+        float b0 = r.b0, b1 = r.b1;
+        newton_linear(a, b0, b1);
+        leaves[l].b0 = b0;
+        leaves[l].b1 = b1;
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < NACC; ++j) acc[(uint64_t)l * NACC + j] = a[j];
 }
@@ -189,37 +199,41 @@ __global__ __launch_bounds__(LT) void k_leaf_accum_big(Load<K, AOS> keys, uint64
         });
 }
 
-__global__ void k_leaf_update(LeafRec *__restrict__ leaves, const double *__restrict__ acc, uint32_t L) {
+// The Newton step of the leaves larger than kLeafCap (nothing to do when
+// *big is 0; the others stepped in k_leaf_accum_small).
+__global__ void k_leaf_update_big(LeafRec *__restrict__ leaves, const double *__restrict__ acc, uint32_t L,
+                                  const uint32_t *big) {
+    if (*big == 0u) return;
     const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= L) return;
     LeafRec r = leaves[l];
+    if (r.size <= kLeafCap) return;
     newton_linear(acc + (uint64_t)l * NACC, r.b0, r.b1);
     leaves[l].b0 = r.b0;
     leaves[l].b1 = r.b1;
 }
 
-// Per-leaf error bounds, one thread per leaf of at most kLeafCap keys, and
-// those leaves' squared residuals added to *loss (one atomic per wave).
+// Per-leaf error bounds, one thread per leaf of at most kLeafCap keys; each
+// leaf's squared residuals go to its loss slot (acc[l * NACC + 5]; 0 for the
+// large leaves, whose loss k_leaf_errors_big adds to the total itself).
 template <typename K, bool AOS>
 __global__ __launch_bounds__(kLeafBlock) void k_leaf_errors_small(Load<K, AOS> keys, LeafRec *__restrict__ leaves,
-                                                                  uint32_t L, double *__restrict__ loss) {
+                                                                  uint32_t L, double *__restrict__ acc) {
     __shared__ K s_key[kStageKeys];
     uint64_t kb;
     const bool staged = stage_leaf_keys(keys, leaves, L, s_key, kb);
     const uint32_t l = blockIdx.x * kLeafBlock + threadIdx.x;
+    if (l >= L) return;
+    const LeafRec r = leaves[l];
     double ls = 0.0;
-    if (l < L) {
-        const LeafRec r = leaves[l];
-        if (r.size != 0 && r.size <= kLeafCap) {
-            long long lo, hi;
-            if (staged) leaf_errs_thread([&](uint64_t i) { return (uint64_t)s_key[i - kb]; }, r, lo, hi, &ls);
-            else leaf_errs_thread([&](uint64_t i) { return (uint64_t)keys.key(i); }, r, lo, hi, &ls);
-            leaves[l].elo = (int32_t)lo;
-            leaves[l].ehi = (int32_t)hi;
-        }
+    if (r.size != 0 && r.size <= kLeafCap) {
+        long long lo, hi;
+        if (staged) leaf_errs_thread([&](uint64_t i) { return (uint64_t)s_key[i - kb]; }, r, lo, hi, &ls);
+        else leaf_errs_thread([&](uint64_t i) { return (uint64_t)keys.key(i); }, r, lo, hi, &ls);
+        leaves[l].elo = (int32_t)lo;
+        leaves[l].ehi = (int32_t)hi;
     }
-    ls = wave_sum(ls);
-    if ((threadIdx.x & (kWave - 1)) == 0 && ls != 0.0) atomicAdd(loss, ls);
+    acc[(uint64_t)l * NACC + 5] = ls;
 }
 
 // Error bounds of the leaves larger than kLeafCap (the wave walk).
@@ -253,12 +267,15 @@ __global__ __launch_bounds__(LT) void k_leaf_errors_big(Load<K, AOS> keys, uint6
     if ((threadIdx.x & (kWave - 1)) == 0 && ls != 0.0) atomicAdd(loss, ls);
 }
 
-// Empty leaves get a zero window; statistics of the windows.
+// Empty leaves get a zero window; statistics of the windows and the leaves'
+// losses (their slots in acc).
 __global__ __launch_bounds__(256) void k_leaf_finish(LeafRec *__restrict__ leaves, uint32_t L,
+                                                     const double *__restrict__ acc,
                                                      double *__restrict__ stats /* sum_w*size, max_w, sum loss */) {
-    __shared__ double s_ws[256 / kWave], s_wm[256 / kWave];
-    double ws = 0, wmax = 0;
+    __shared__ double s_ws[256 / kWave], s_wm[256 / kWave], s_ls[256 / kWave];
+    double ws = 0, wmax = 0, ls = 0;
     for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < L; l += gridDim.x * blockDim.x) {
+        ls += acc[(uint64_t)l * NACC + 5];
         LeafRec r = leaves[l];
         if (r.size == 0 || r.elo > r.ehi) {
             leaves[l].elo = 0;
@@ -270,6 +287,7 @@ __global__ __launch_bounds__(256) void k_leaf_finish(LeafRec *__restrict__ leave
         }
     }
     ws = wave_sum(ws);
+    ls = wave_sum(ls);
     for (int off = kWave / 2; off > 0; off >>= 1) {
         const double o = __shfl_xor(wmax, off, kWave);
         wmax = o > wmax ? o : wmax;
@@ -278,14 +296,17 @@ __global__ __launch_bounds__(256) void k_leaf_finish(LeafRec *__restrict__ leave
     if ((threadIdx.x & (kWave - 1)) == 0) {
         s_ws[wave] = ws;
         s_wm[wave] = wmax;
+        s_ls[wave] = ls;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (uint32_t w = 1; w < blockDim.x / kWave; ++w) {
             ws += s_ws[w];
             wmax = s_wm[w] > wmax ? s_wm[w] : wmax;
+            ls += s_ls[w];
         }
         atomicAdd(&stats[0], ws);
+        atomicAdd(&stats[2], ls);
         // max via compare-and-swap on the bit pattern (values are >= 0)
         unsigned long long *p = (unsigned long long *)&stats[1];
         unsigned long long old = *p;
@@ -401,20 +422,20 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
         if (rc != IDX_OK) return rc;
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, d_big, (uint64_t)1, 0u);
         for (uint32_t ep = 0; ep < epochs; ++ep) {
-            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s, keys, leaves, L,
-                               leaf_acc, d_big);
+            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS, true>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s,
+                               keys, leaves, L, leaf_acc, d_big);
             hipLaunchKernelGGL((k_leaf_accum_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
                                leaf_acc, d_big);
-            hipLaunchKernelGGL(k_leaf_update, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_acc, L);
+            hipLaunchKernelGGL(k_leaf_update_big, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_acc, L, d_big);
         }
         // the final leaf loss comes with the error bounds (same walk)
         hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, stats, (uint64_t)4);
         hipLaunchKernelGGL((k_leaf_errors_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s, keys, leaves, L,
-                           stats + 2);
+                           leaf_acc);
         hipLaunchKernelGGL((k_leaf_errors_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves, d_big,
                            stats + 2);
         hipLaunchKernelGGL(k_leaf_finish, dim3(grid_for(L, 256) < 1024 ? grid_for(L, 256) : 1024), dim3(256), 0, s,
-                           leaves, L, stats);
+                           leaves, L, leaf_acc, stats);
         if (hipGetLastError() != hipSuccess) return IDX_ERR_HIP;
         if (hipMemcpyAsync(st, stats, 4 * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
