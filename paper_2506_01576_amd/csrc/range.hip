@@ -185,11 +185,13 @@ __global__ __launch_bounds__(256) void k_range_count(RangeArgs<K, AOS> a) {
 // The same on a batch of ranges partitioned by the rank bucket of their
 // lower bounds (lookup parameter reorder = 2): entry j holds lower bound
 // q2[j] of the range at batch position pos[j], whose upper bound is read
-// there.  The tiles are walked XCD by XCD, so the ranges one XCD has in
+// there (reading the upper bounds into partitioned order first, in a kernel
+// of their own, cost more).  The tiles are walked XCD by XCD, so the ranges one XCD has in
 // flight fall in a few buckets whose slice of the index stays in its L2.
-// The range's first rank and count go straight to its position (a random
-// 4-byte and 8-byte write per range, cheaper than returning both ranks to
-// the ranges' order by two placement passes).
+// Both ranks go out in partitioned order, one 8-byte pair per range;
+// k_range_put then writes each range's first rank and count at its position
+// (random writes in a kernel of their own cost less than inside this one,
+// where they slow the searches, or than two placement passes).
 // On the sorted array the lower bound's bucket bounds its rank (see
 // bucket_start): both searches start inside that interval, and the upper
 // bound's search widens to the rest of the array only when its answer is
@@ -198,7 +200,8 @@ template <typename K, bool AOS>
 __global__ __launch_bounds__(256) void k_range_count_part(RangeArgs<K, AOS> a, const K *__restrict__ q2,
                                                           const uint32_t *__restrict__ pos,
                                                           const uint16_t *__restrict__ bkt, uint64_t bstep,
-                                                          uint64_t bspan, uint64_t ntiles, uint64_t iters) {
+                                                          uint64_t bspan, uint64_t ntiles, uint64_t iters,
+                                                          uint2 *__restrict__ ranks) {
     for (uint64_t it = blockIdx.x; it < iters; it += gridDim.x) {
         const uint64_t tl = tile_of(it, ntiles, 1);
         if (tl >= ntiles) continue;
@@ -222,22 +225,33 @@ __global__ __launch_bounds__(256) void k_range_count_part(RangeArgs<K, AOS> a, c
         } else {
             range_ranks(a, L, U, r0, r1);
         }
-        const uint32_t p = pos[j];
-        a.first_rank[p] = (uint32_t)r0;
-        a.offsets[p] = r1 > r0 ? r1 - r0 : 0;
+        ranks[j] = make_uint2((uint32_t)r0, (uint32_t)r1);
     }
 }
 
+// Each range's first rank and count at its position.
+__global__ __launch_bounds__(256) void k_range_put(const uint2 *__restrict__ ranks, const uint32_t *__restrict__ pos,
+                                                   uint64_t m, uint32_t *__restrict__ first,
+                                                   uint64_t *__restrict__ counts) {
+    const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const uint2 r = ranks[j];
+    const uint32_t p = pos[j];
+    first[p] = r.x;
+    counts[p] = r.y > r.x ? (uint64_t)(r.y - r.x) : 0ull;
+}
+
 // Counts through the partition: per chunk of at most 2^31 ranges, partition
-// the lower bounds, then count in partitioned order, each count written at
-// its range's position.
+// the lower bounds, count in partitioned order, then write each count at its
+// range's position.
 template <typename K, bool AOS>
 int range_count_partitioned(idx_index *h, const RangeArgs<K, AOS> &a, hipStream_t s) {
     const uint64_t m = a.m;
     const uint64_t chunk = m < kPartChunk ? m : kPartChunk;
     const size_t pb = (partition_scratch_bytes(h, chunk) + 255) & ~(size_t)255;
-    char *t = (char *)h->alloc.get(pb, s);
+    char *t = (char *)h->alloc.get(pb + (size_t)chunk * 8, s);
     if (!t) return IDX_ERR_NOMEM;
+    uint2 *ranks = (uint2 *)(t + pb);  // both ranks of every range, partitioned order
     int rc = IDX_OK;
     for (uint64_t c0 = 0; c0 < m && rc == IDX_OK; c0 += chunk) {
         const uint64_t mc = (m - c0) < chunk ? (m - c0) : chunk;
@@ -247,12 +261,12 @@ int range_count_partitioned(idx_index *h, const RangeArgs<K, AOS> &a, hipStream_
         RangeArgs<K, AOS> b = a;
         b.hi = a.hi + c0;
         b.m = mc;
-        b.first_rank = a.first_rank + c0;
-        b.offsets = a.offsets + c0;
         const uint64_t tiles = (mc + 255) / 256;
         const uint64_t iters = ((tiles + kXcds - 1) / kXcds) * kXcds;
         hipLaunchKernelGGL((k_range_count_part<K, AOS>), dim3((uint32_t)iters), dim3(256), 0, s, b, (const K *)v.q,
-                           v.pos, v.bkt, v.bstep, v.bspan, tiles, iters);
+                           v.pos, v.bkt, v.bstep, v.bspan, tiles, iters, ranks);
+        hipLaunchKernelGGL(k_range_put, dim3((uint32_t)tiles), dim3(256), 0, s, (const uint2 *)ranks, v.pos, mc,
+                           a.first_rank + c0, a.offsets + c0);
         if (hipGetLastError() != hipSuccess) rc = IDX_ERR_HIP;
     }
     h->alloc.put(t, s);
