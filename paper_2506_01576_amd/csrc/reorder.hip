@@ -53,6 +53,7 @@ constexpr uint64_t kBucketBytes = 512 * 1024;   // target index bytes per bucket
 constexpr uint32_t kWindowShift = 19;           // at least 2^19 answers (2 MiB) per output window
 constexpr uint32_t kMaxWindows = 256;
 constexpr uint64_t kChunk = 1ull << 31;         // batch positions fit u32
+constexpr int kLoadAhead = 8;                   // entries a thread loads before using them
 
 // Splitters from the sorted array: split[j] = key at rank (j + 1) * step.
 template <typename K, bool AOS>
@@ -107,10 +108,23 @@ __global__ __launch_bounds__(kPartThreads) void k_fwd_count(const K *__restrict_
     }
     __syncthreads();
     const uint64_t lo = (uint64_t)blockIdx.x * kPartTile, hi = tile_end(lo, m);
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const uint32_t b = bucket_of(s_split, B, q[i]);
-        bkt[i] = (uint16_t)b;
-        atomicAdd(&s_hist[b], 1u);
+    // kLoadAhead queries per thread are loaded before any is placed, so
+    // their loads are in flight together
+    for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)kLoadAhead * blockDim.x) {
+        K v[kLoadAhead];
+#pragma unroll
+        for (int u = 0; u < kLoadAhead; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * blockDim.x;
+            v[u] = i < hi ? q[i] : K(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadAhead; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * blockDim.x;
+            if (i >= hi) continue;
+            const uint32_t b = bucket_of(s_split, B, v[u]);
+            bkt[i] = (uint16_t)b;
+            atomicAdd(&s_hist[b], 1u);
+        }
     }
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < B; b += blockDim.x)
@@ -200,7 +214,7 @@ __device__ __forceinline__ uint32_t run_of(const ScatterArgs<K, Pass> &a, uint64
 // sorted by run in LDS, and every run's piece leaves with consecutive lanes
 // writing consecutive addresses.  A tile whose runs span more than kSpan run
 // ids (a fine pass over a small batch) places entries directly instead.
-constexpr uint32_t kSubPer = 2;
+constexpr uint32_t kSubPer = 4;
 constexpr uint32_t kSub = kPartThreads * kSubPer;
 constexpr uint32_t kSpan = 256;
 
@@ -241,11 +255,20 @@ __global__ __launch_bounds__(kPartThreads) void k_scatter(ScatterArgs<K, Pass> a
         __syncthreads();
         const uint64_t lo = tl * kPartTile, hi = tile_end(lo, a.m);
         uint32_t rmin = 0xFFFFFFFFu, rmax = 0;
-        for (uint64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            const uint32_t r = run_of(a, i);
-            atomicAdd(&s_cnt[r], 1u);
-            rmin = r < rmin ? r : rmin;
-            rmax = r > rmax ? r : rmax;
+        for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += (uint64_t)kLoadAhead * blockDim.x) {
+            uint32_t rv[kLoadAhead];
+#pragma unroll
+            for (int u = 0; u < kLoadAhead; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * blockDim.x;
+                rv[u] = i < hi ? run_of(a, i) : 0xFFFFFFFFu;
+            }
+#pragma unroll
+            for (int u = 0; u < kLoadAhead; ++u) {
+                if (rv[u] == 0xFFFFFFFFu) continue;
+                atomicAdd(&s_cnt[rv[u]], 1u);
+                rmin = rv[u] < rmin ? rv[u] : rmin;
+                rmax = rv[u] > rmax ? rv[u] : rmax;
+            }
         }
         if (rmin != 0xFFFFFFFFu) {
             atomicMin(&s_lo, rmin);
