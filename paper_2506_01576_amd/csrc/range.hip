@@ -229,21 +229,21 @@ __global__ __launch_bounds__(256) void k_range_count_part(RangeArgs<K, AOS> a, c
     }
 }
 
-// Each range's first rank and count at its position.
+// Each range's first rank and count at its position, packed into one 8-byte
+// word (first rank << 32 | count; both are below 2^32): one random write per
+// range instead of two.  The scan that follows unpacks them.
 __global__ __launch_bounds__(256) void k_range_put(const uint2 *__restrict__ ranks, const uint32_t *__restrict__ pos,
-                                                   uint64_t m, uint32_t *__restrict__ first,
-                                                   uint64_t *__restrict__ counts) {
+                                                   uint64_t m, uint64_t *__restrict__ packed) {
     const uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= m) return;
     const uint2 r = ranks[j];
-    const uint32_t p = pos[j];
-    first[p] = r.x;
-    counts[p] = r.y > r.x ? (uint64_t)(r.y - r.x) : 0ull;
+    const uint32_t cnt = r.y > r.x ? r.y - r.x : 0u;
+    packed[pos[j]] = ((uint64_t)r.x << 32) | cnt;
 }
 
 // Counts through the partition: per chunk of at most 2^31 ranges, partition
-// the lower bounds, count in partitioned order, then write each count at its
-// range's position.
+// the lower bounds, count in partitioned order, then write each range's
+// packed first rank and count at its position (the scan unpacks them).
 template <typename K, bool AOS>
 int range_count_partitioned(idx_index *h, const RangeArgs<K, AOS> &a, hipStream_t s) {
     const uint64_t m = a.m;
@@ -266,7 +266,7 @@ int range_count_partitioned(idx_index *h, const RangeArgs<K, AOS> &a, hipStream_
         hipLaunchKernelGGL((k_range_count_part<K, AOS>), dim3((uint32_t)iters), dim3(256), 0, s, b, (const K *)v.q,
                            v.pos, v.bkt, v.bstep, v.bspan, tiles, iters, ranks);
         hipLaunchKernelGGL(k_range_put, dim3((uint32_t)tiles), dim3(256), 0, s, (const uint2 *)ranks, v.pos, mc,
-                           a.first_rank + c0, a.offsets + c0);
+                           a.offsets + c0);
         if (hipGetLastError() != hipSuccess) rc = IDX_ERR_HIP;
     }
     h->alloc.put(t, s);
@@ -416,6 +416,9 @@ __device__ __forceinline__ uint64_t block_scan_u64(uint64_t v, uint64_t *s_wave,
     return before + incl - v;
 }
 
+// PACKED: each value is (first rank << 32 | count) and only the count is
+// summed (k_range_put's words).
+template <bool PACKED>
 __global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint64_t *__restrict__ v, uint64_t m,
                                                             uint64_t *__restrict__ partial) {
     __shared__ uint64_t s_wave[SC_THREADS / kWave];
@@ -424,7 +427,8 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_reduce(const uint64_t *__re
 #pragma unroll
     for (int j = 0; j < SC_ITEMS; ++j) {
         const uint64_t i = base + (uint64_t)j * SC_THREADS + threadIdx.x;
-        sum += i < m ? v[i] : 0;
+        const uint64_t x = i < m ? v[i] : 0;
+        sum += PACKED ? (x & 0xFFFFFFFFull) : x;
     }
     uint64_t total;
     block_scan_u64(sum, s_wave, &total);
@@ -455,33 +459,88 @@ __global__ __launch_bounds__(SC_THREADS) void k_scan_partials(uint64_t *__restri
 }
 
 // Tile-local exclusive scan plus the tile's prefix; writes offsets[m] = total.
+// PACKED: the values are k_range_put's words; the counts are scanned and the
+// first ranks written to `first`.
+template <bool PACKED>
 __global__ __launch_bounds__(SC_THREADS) void k_scan_apply(uint64_t *__restrict__ v, uint64_t m,
-                                                           const uint64_t *__restrict__ partial) {
+                                                           const uint64_t *__restrict__ partial,
+                                                           uint32_t *__restrict__ first) {
     __shared__ uint64_t s_wave[SC_THREADS / kWave];
     const uint64_t base = (uint64_t)blockIdx.x * SC_TILE + (uint64_t)threadIdx.x * SC_ITEMS;
+    // a thread's items are consecutive: whole ones move as 16-byte loads and
+    // stores (a per-element store is one memory request each)
+    const bool vec = base + SC_ITEMS <= m && ((uintptr_t)v & 15) == 0;
     uint64_t x[SC_ITEMS], sum = 0;
+    if (vec) {
+        const uint4 *p = (const uint4 *)(v + base);
 #pragma unroll
-    for (int j = 0; j < SC_ITEMS; ++j) {
-        x[j] = base + j < m ? v[base + j] : 0;
-        sum += x[j];
+        for (int c = 0; c < SC_ITEMS / 2; ++c) {
+            const uint4 w = p[c];
+            x[2 * c] = ((uint64_t)w.y << 32) | w.x;
+            x[2 * c + 1] = ((uint64_t)w.w << 32) | w.z;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < SC_ITEMS; ++j) x[j] = base + j < m ? v[base + j] : 0;
     }
+    if constexpr (PACKED) {
+        uint32_t f[SC_ITEMS];
+#pragma unroll
+        for (int j = 0; j < SC_ITEMS; ++j) {
+            f[j] = (uint32_t)(x[j] >> 32);
+            x[j] &= 0xFFFFFFFFull;
+        }
+        if (vec) {  // `first` is 256-byte aligned and base a multiple of 16
+            uint4 *q = (uint4 *)(first + base);
+#pragma unroll
+            for (int c = 0; c < SC_ITEMS / 4; ++c) q[c] = make_uint4(f[4 * c], f[4 * c + 1], f[4 * c + 2], f[4 * c + 3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < SC_ITEMS; ++j)
+                if (base + j < m) first[base + j] = f[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < SC_ITEMS; ++j) sum += x[j];
     uint64_t total;
     uint64_t acc = partial[blockIdx.x] + block_scan_u64(sum, s_wave, &total);
+    uint64_t o[SC_ITEMS];
 #pragma unroll
     for (int j = 0; j < SC_ITEMS; ++j) {
-        if (base + j < m) v[base + j] = acc;
+        o[j] = acc;
         acc += x[j];
+    }
+    if (vec) {
+        uint4 *p = (uint4 *)(v + base);
+#pragma unroll
+        for (int c = 0; c < SC_ITEMS / 2; ++c)
+            p[c] = make_uint4((uint32_t)o[2 * c], (uint32_t)(o[2 * c] >> 32), (uint32_t)o[2 * c + 1],
+                              (uint32_t)(o[2 * c + 1] >> 32));
+    } else {
+#pragma unroll
+        for (int j = 0; j < SC_ITEMS; ++j)
+            if (base + j < m) v[base + j] = o[j];
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SC_THREADS - 1) v[m] = acc;
 }
 
-int exclusive_scan(uint64_t *v, uint64_t m, uint64_t *partial, hipStream_t s) {
+// Exclusive scan of v[0, m) in place, v[m] = total.  With `first`, v holds
+// k_range_put's packed words: the counts are scanned and the first ranks go
+// to first[0, m).
+int exclusive_scan(uint64_t *v, uint64_t m, uint64_t *partial, hipStream_t s, uint32_t *first = nullptr) {
     const uint64_t tiles = (m + SC_TILE - 1) / SC_TILE;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)tiles), dim3(SC_THREADS), 0, s, v, m, partial);
+    if (first)
+        hipLaunchKernelGGL(k_scan_reduce<true>, dim3((uint32_t)tiles), dim3(SC_THREADS), 0, s, v, m, partial);
+    else
+        hipLaunchKernelGGL(k_scan_reduce<false>, dim3((uint32_t)tiles), dim3(SC_THREADS), 0, s, v, m, partial);
     IDX_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SC_THREADS), 0, s, partial, tiles);
     IDX_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_apply, dim3((uint32_t)tiles), dim3(SC_THREADS), 0, s, v, m, partial);
+    if (first)
+        hipLaunchKernelGGL(k_scan_apply<true>, dim3((uint32_t)tiles), dim3(SC_THREADS), 0, s, v, m, partial, first);
+    else
+        hipLaunchKernelGGL(k_scan_apply<false>, dim3((uint32_t)tiles), dim3(SC_THREADS), 0, s, v, m, partial,
+                           (uint32_t *)nullptr);
     IDX_LAUNCH_CHECK();
     return IDX_OK;
 }
@@ -508,6 +567,7 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
     uint64_t *partial = (uint64_t *)(scratch + rank_bytes);
     int rc = IDX_OK;
     uint64_t tot = 0;
+    bool packed = false;  // offsets hold k_range_put's packed words
     const uint32_t blocks = (uint32_t)((m + 255) / 256);
     do {
         if (h->learned && h->params.model != 2) {
@@ -520,6 +580,7 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
             // for the partition: those calls count unpartitioned
             rc = range_count_partitioned(h, a, s);
             if (rc != IDX_OK) break;
+            packed = true;
         } else {
             hipLaunchKernelGGL((k_range_count<K, AOS>), dim3(blocks), dim3(256), 0, s, a);
             if (hipGetLastError() != hipSuccess) {
@@ -527,7 +588,7 @@ int range_t(idx_index *h, const void *lo, const void *hi, uint64_t m, uint64_t *
                 break;
             }
         }
-        rc = exclusive_scan(offsets, m, partial, s);
+        rc = exclusive_scan(offsets, m, partial, s, packed ? a.first_rank : nullptr);
         if (rc != IDX_OK) break;
         hipError_t e = hipMemcpyAsync(&tot, offsets + m, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -259,9 +259,9 @@ def test_range_parity(layout, k, aos, bits):
 @pytest.mark.parametrize("bits,n,kind", [(64, 1 << 22, "unique"), (32, 1 << 21, "dup")])
 def test_partitioned_range_counts_large(bits, n, kind):
     """Range counts through the rank-bucket partition (reorder = 2) at sizes
-    with 32 to 128 buckets (coarse and fine scatter passes), every layout:
-    offsets and row IDs equal the oracle's, including inverted, unbounded and
-    empty ranges."""
+    with 32 to 128 buckets (coarse and fine scatter passes), every layout (the
+    sorted array also in AoS storage): offsets and row IDs equal the oracle's,
+    including inverted, unbounded and empty ranges."""
     keys, rows = key_set(71 + bits, n, bits, kind)
     sk, sr = oracle.stable_sort(keys, rows)
     L, U, _ = gen.ranges(72, keys, 1 << 20, 1, 64)
@@ -274,13 +274,13 @@ def test_partitioned_range_counts_large(bits, n, kind):
     perm = rng.permutation(len(L))
     L, U = L[perm], U[perm]
     want_off, want = oracle.range_lookup(sk, sr, L, U, nthreads=8)
-    for layout, k in (("bs", 1), ("ebs", 2), ("eks", 9)):
-        with build(keys, rows, layout, k, False) as ix:
+    for layout, k, aos in (("bs", 1, False), ("bs", 1, True), ("ebs", 2, False), ("eks", 9, False)):
+        with build(keys, rows, layout, k, aos) as ix:
             ix.set_params(reorder=2)
-            say(f"partitioned range counts {layout} bits={bits} n={n} {kind}")
+            say(f"partitioned range counts {layout} aos={aos} bits={bits} n={n} {kind}")
             off, got = ix.range(to_dev(L), to_dev(U))
-            assert np.array_equal(off.cpu().numpy().view(np.uint64), want_off), layout
-            assert np.array_equal(rows_host(got), want), layout
+            assert np.array_equal(off.cpu().numpy().view(np.uint64), want_off), (layout, aos)
+            assert np.array_equal(rows_host(got), want), (layout, aos)
 
 
 def test_range_scan_modes_on_wide_ranges():
