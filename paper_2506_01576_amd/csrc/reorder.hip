@@ -20,8 +20,9 @@
 //  forward
 //   1. splitters: B - 1 index keys at ranks step, 2 step, ... (step = n / B),
 //      built once per handle and cached;
-//   2. count: every query's fine bucket (binary search of the splitters in
-//      LDS), kept as u16, and per-bucket totals;
+//   2. count: every query's fine bucket (a table of key cells in LDS, then
+//      a search of the few splitters in the query's cell), kept as u16, and
+//      per-bucket totals;
 //   3. bucket starts (one workgroup);
 //   4. scatter to B1 coarse buckets (query, batch position, fine bucket);
 //   5. scatter within each coarse bucket to its B2 fine buckets;
@@ -76,11 +77,65 @@ __global__ void k_split_eyt(Load<K, AOS> L, Geo G, uint64_t first, uint64_t step
     if (j < B) split[j - 1] = L.key(t + first);
 }
 
-// Number of splitters below x (B a power of two, split[B - 1] = max key).
+// Bucket table: the key range from the first splitter to the second-largest
+// one is cut into kCells cells of 2^sh keys (the last cell also takes every
+// larger key, the first every smaller one).  Cell h's keys lie between the
+// splitters cell_first[h] and cell_first[h + 1], so a lookup searches only
+// those: none or one for uniform keys, never more than all B.
+constexpr uint32_t kCellBits = 12;
+constexpr uint32_t kCells = 1u << kCellBits;
+
 template <typename K>
-__device__ __forceinline__ uint32_t bucket_of(const K *s_split, uint32_t B, K x) {
-    uint32_t b = 0;
-    for (uint32_t h = B >> 1; h > 0; h >>= 1) b += (s_split[b + h - 1] < x) ? h : 0;
+__device__ __forceinline__ uint32_t cell_of(K x, K base, uint32_t sh) {
+    if (x < base) return 0;
+    const uint64_t c = (uint64_t)(x - base) >> sh;
+    return c < kCells - 1 ? (uint32_t)c : kCells - 1;
+}
+
+// Cell width: the smallest 2^sh for which the span from split[0] to
+// split[B - 2] fits kCells cells.
+template <typename K>
+__device__ __forceinline__ uint32_t cell_shift(const K *s_split, uint32_t B) {
+    const uint64_t span = B >= 2 ? (uint64_t)(s_split[B - 2] - s_split[0]) : 0;
+    const uint32_t bits = span ? 64u - (uint32_t)__clzll((long long)span) : 0u;
+    return bits > kCellBits ? bits - kCellBits : 0u;
+}
+
+// Fills cell_first[0, kCells]: the number of splitters whose cell is below h.
+template <typename K>
+__device__ __forceinline__ void build_cells(const K *s_split, uint32_t B, K base, uint32_t sh, uint16_t *cell_first) {
+    for (uint32_t h = threadIdx.x; h <= kCells; h += blockDim.x) {
+        uint32_t lo = 0, n = B;  // first splitter j with cell_of(split[j]) >= h
+        while (n) {
+            const uint32_t half = n >> 1;
+            if (cell_of(s_split[lo + half], base, sh) < h) {
+                lo += half + 1;
+                n -= half + 1;
+            } else {
+                n = half;
+            }
+        }
+        cell_first[h] = (uint16_t)lo;
+    }
+}
+
+// Bucket of x = the number of splitters below x (splitters ascend, the last
+// is the largest key): all those of lower cells plus those of x's own cell
+// that are below x.
+template <typename K>
+__device__ __forceinline__ uint32_t bucket_of_cells(const K *s_split, const uint16_t *cell_first, K base, uint32_t sh,
+                                                    K x) {
+    const uint32_t h = cell_of(x, base, sh);
+    uint32_t b = cell_first[h], n = (uint32_t)cell_first[h + 1] - b;
+    while (n) {
+        const uint32_t half = n >> 1;
+        if (s_split[b + half] < x) {
+            b += half + 1;
+            n -= half + 1;
+        } else {
+            n = half;
+        }
+    }
     return b;
 }
 
@@ -102,10 +157,15 @@ __global__ __launch_bounds__(kPartThreads) void k_fwd_count(const K *__restrict_
     extern __shared__ __align__(16) char smem[];
     K *s_split = (K *)smem;
     uint32_t *s_hist = (uint32_t *)(s_split + B);
+    uint16_t *s_cell = (uint16_t *)(s_hist + B);  // kCells + 1 entries
     for (uint32_t i = threadIdx.x; i < B; i += blockDim.x) {
         s_split[i] = split[i];
         s_hist[i] = 0;
     }
+    __syncthreads();
+    const K base = s_split[0];
+    const uint32_t sh = cell_shift(s_split, B);
+    build_cells(s_split, B, base, sh, s_cell);
     __syncthreads();
     const uint64_t lo = (uint64_t)blockIdx.x * kPartTile, hi = tile_end(lo, m);
     // kLoadAhead queries per thread are loaded before any is placed, so
@@ -121,7 +181,7 @@ __global__ __launch_bounds__(kPartThreads) void k_fwd_count(const K *__restrict_
         for (int u = 0; u < kLoadAhead; ++u) {
             const uint64_t i = i0 + (uint64_t)u * blockDim.x;
             if (i >= hi) continue;
-            const uint32_t b = bucket_of(s_split, B, v[u]);
+            const uint32_t b = bucket_of_cells(s_split, s_cell, base, sh, v[u]);
             bkt[i] = (uint16_t)b;
             atomicAdd(&s_hist[b], 1u);
         }
@@ -529,7 +589,8 @@ int partition_fwd(idx_index *h, const K *q, uint64_t m, uint32_t B, const PartBu
     // sequence can be captured in a graph)
     hipLaunchKernelGGL(k_zero_u32, dim3(kMaxBuckets / 256), dim3(256), 0, s, P.total, kMaxBuckets);
     IDX_LAUNCH_CHECK();
-    hipLaunchKernelGGL((k_fwd_count<K>), dim3((uint32_t)tiles), dim3(kPartThreads), (size_t)B * (sizeof(K) + 4), s, q,
+    hipLaunchKernelGGL((k_fwd_count<K>), dim3((uint32_t)tiles), dim3(kPartThreads),
+                       (size_t)B * (sizeof(K) + 4) + (kCells + 1) * 2, s, q,
                        m, (const K *)h->split, B, P.bkt, P.total);
     IDX_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_starts, dim3(1), dim3(kPartThreads), 0, s, P.total, B, B2, P.fcur, P.ccur, D, shift, P.dcur);
