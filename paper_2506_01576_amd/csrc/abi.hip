@@ -77,7 +77,7 @@ size_t lds_max_of_current_device() {
 uint64_t padded_slots(uint64_t slots) { return ((slots + 63) / 64) * 64 + 64; }
 
 void free_handle_buffers(idx_index *h, hipStream_t s) {
-    drop_model(h, s);
+    drop_model(h, s);  // also frees a spare leaf-line buffer
     drop_splitters(h, s);
     h->alloc.put(h->keys, s);
     h->alloc.put(h->rowids, s);

@@ -72,6 +72,11 @@ struct idx_index {
     idx::LearnedModel *learned = nullptr;  // attached rank model (BS layout only)
     void *split = nullptr;       // rank-bucket splitter keys for partitioned lookups
     uint32_t split_buckets = 0;  // buckets those splitters define (0 = none built)
+    // Leaf-line buffer of the model a re-training replaced, kept for the new
+    // model's lines when the leaf count is the same (a fresh buffer of that
+    // size costs a mapping of device memory on every re-training).
+    void *spare_lines = nullptr;
+    size_t spare_lines_bytes = 0;
     // Batches (idx_batch_create) holding this handle: their descriptors point
     // at its layout and model buffers, so while any holds it the handle may
     // not be destroyed, retrained or have its model dropped.
@@ -177,7 +182,9 @@ int learn(idx_index *h, uint32_t leaves, uint32_t epochs, uint32_t feature, hipS
 // learn_batch.hip: models of many indexes trained by one launch sequence.
 int learn_batch(idx_index *const *hs, uint32_t count, const uint32_t *leaves, uint32_t epochs, uint32_t feature,
                 hipStream_t s);
-void drop_model(idx_index *h, hipStream_t s);
+// Frees the attached model (and any spare leaf-line buffer).  keep_lines: the
+// model's leaf lines become the handle's spare buffer instead.
+void drop_model(idx_index *h, hipStream_t s, bool keep_lines = false);
 int learn_stats(const idx_index *h, idx_learn_stats *out);
 int learn_export(const idx_index *h, void *leaves_out, hipStream_t s);
 int learn_eval(idx_index *h, uint32_t feature, const float *root_ab, uint32_t leaves, const float *leaf_ab,

@@ -510,7 +510,7 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
 int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream_t s) {
     if (h->layout != IDX_BS || h->n == 0) return IDX_ERR_ARG;
     if (L == 0 || L > (1u << 26) || epochs == 0 || epochs > 16 || feature > IDX_FEATURE_SPLINE) return IDX_ERR_ARG;
-    drop_model(h, s);
+    drop_model(h, s, h->params.leaf_lines == 1);
     LearnedModel *M = new (std::nothrow) LearnedModel();
     if (!M) return IDX_ERR_NOMEM;
     M->leaves = (LeafRec *)h->alloc.get((size_t)L * sizeof(LeafRec), s);
@@ -555,11 +555,22 @@ int learn(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStream
     return IDX_OK;
 }
 
-void drop_model(idx_index *h, hipStream_t s) {
+void drop_model(idx_index *h, hipStream_t s, bool keep_lines) {
+    void *lines = h->learned ? h->learned->lines : nullptr;
+    if (h->spare_lines && (!keep_lines || lines)) {
+        h->alloc.put(h->spare_lines, s);
+        h->spare_lines = nullptr;
+        h->spare_lines_bytes = 0;
+    }
     if (!h->learned) return;
     h->alloc.put(h->learned->leaves, s);
     if (h->learned->spline) h->alloc.put(h->learned->spline, s);
-    if (h->learned->lines) h->alloc.put(h->learned->lines, s);
+    if (lines && keep_lines) {
+        h->spare_lines = lines;
+        h->spare_lines_bytes = (size_t)h->learned->root.L * kLineBytes;
+    } else if (lines) {
+        h->alloc.put(lines, s);
+    }
     delete h->learned;
     h->learned = nullptr;
 }
@@ -1039,7 +1050,16 @@ int ensure_lines(idx_index *h, hipStream_t s) {
     LearnedModel *M = h->learned;
     if (M->lines) return IDX_OK;
     const uint32_t L = M->root.L;
-    uint4 *lines = (uint4 *)h->alloc.get((size_t)L * kLineBytes, s);
+    const size_t bytes = (size_t)L * kLineBytes;
+    uint4 *lines = nullptr;
+    if (h->spare_lines && h->spare_lines_bytes == bytes) {
+        lines = (uint4 *)h->spare_lines;  // every line is rewritten below
+    } else {
+        if (h->spare_lines) h->alloc.put(h->spare_lines, s);
+        lines = (uint4 *)h->alloc.get(bytes, s);
+    }
+    h->spare_lines = nullptr;
+    h->spare_lines_bytes = 0;
     if (!lines) return IDX_ERR_NOMEM;
     const uint64_t threads = (uint64_t)L * kLineChunks;
     const uint32_t g = grid_for(threads, kLinesBlock);

@@ -466,3 +466,29 @@ def test_leaf_lines_tiny_sets_and_max_leaves():
         ix.learn(1 << 24, 1, AUTO)
         assert np.array_equal(rows_host(ix.point(to_dev(q))), oracle.point(sk, sr, q, nthreads=4))
         assert np.array_equal(rows_host(ix.point(to_dev(keys))), oracle.point(sk, sr, keys, nthreads=4))
+
+
+def test_leaf_lines_after_retraining():
+    """Re-training a model with leaf lines reuses the previous lines' buffer
+    when the leaf count is the same, and takes a new one otherwise: every
+    lookup equals the oracle's after each training, after dropping the model
+    and training again, and for ranges through the reused lines."""
+    n = 200003
+    keys, rows = make("lognormal", n, seed=91)
+    sk, sr = oracle.stable_sort(keys, rows)
+    q = queries(keys, 50000, seed=92)
+    want, want_keys = oracle.point(sk, sr, q), oracle.point(sk, sr, keys)
+    lo, hi, _ = gen.ranges(93, keys, 4000, 1, 40)
+    want_off, want_rows = oracle.range_lookup(sk, sr, lo, hi)
+    with idx.Index(to_dev(keys), to_dev(rows), layout="bs") as ix:
+        ix.set_params(leaf_lines=1)
+        for step, L in enumerate((n // 4, n // 4, n // 2, n // 2, 4096)):
+            if step == 3:
+                ix.unlearn()
+            ix.learn(L, 2, AUTO)
+            say(f"re-training step {step}: {L} leaves")
+            assert np.array_equal(rows_host(ix.point(to_dev(q))), want), (step, L)
+            assert np.array_equal(rows_host(ix.point(to_dev(keys))), want_keys), (step, L)
+            off, got = ix.range(to_dev(lo), to_dev(hi))
+            assert np.array_equal(off.cpu().numpy().view(np.uint64), want_off), (step, L)
+            assert np.array_equal(rows_host(got), want_rows), (step, L)
