@@ -214,11 +214,14 @@ __global__ void k_leaf_update_big(LeafRec *__restrict__ leaves, const double *__
 }
 
 // Per-leaf error bounds, one thread per leaf of at most kLeafCap keys; each
-// leaf's squared residuals go to its loss slot (acc[l * NACC + 5]; 0 for the
-// large leaves, whose loss k_leaf_errors_big adds to the total itself).
+// leaf's squared residuals go to loss[l] (0 for the large leaves, whose loss
+// k_leaf_errors_big adds to the total itself).  `loss` is the start of the
+// per-leaf accumulators, which training no longer needs: dense, so the
+// writes here and the reads in k_leaf_finish move 8 bytes per leaf, not a
+// strided line each.
 template <typename K, bool AOS>
 __global__ __launch_bounds__(kLeafBlock) void k_leaf_errors_small(Load<K, AOS> keys, LeafRec *__restrict__ leaves,
-                                                                  uint32_t L, double *__restrict__ acc) {
+                                                                  uint32_t L, double *__restrict__ loss) {
     __shared__ K s_key[kStageKeys];
     uint64_t kb;
     const bool staged = stage_leaf_keys(keys, leaves, L, s_key, kb);
@@ -233,7 +236,7 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_errors_small(Load<K, AOS> k
         leaves[l].elo = (int32_t)lo;
         leaves[l].ehi = (int32_t)hi;
     }
-    acc[(uint64_t)l * NACC + 5] = ls;
+    loss[l] = ls;
 }
 
 // Error bounds of the leaves larger than kLeafCap (the wave walk).
@@ -268,14 +271,14 @@ __global__ __launch_bounds__(LT) void k_leaf_errors_big(Load<K, AOS> keys, uint6
 }
 
 // Empty leaves get a zero window; statistics of the windows and the leaves'
-// losses (their slots in acc).
+// losses (loss[l], written by k_leaf_errors_small).
 __global__ __launch_bounds__(256) void k_leaf_finish(LeafRec *__restrict__ leaves, uint32_t L,
-                                                     const double *__restrict__ acc,
+                                                     const double *__restrict__ loss,
                                                      double *__restrict__ stats /* sum_w*size, max_w, sum loss */) {
     __shared__ double s_ws[256 / kWave], s_wm[256 / kWave], s_ls[256 / kWave];
     double ws = 0, wmax = 0, ls = 0;
     for (uint32_t l = blockIdx.x * blockDim.x + threadIdx.x; l < L; l += gridDim.x * blockDim.x) {
-        ls += acc[(uint64_t)l * NACC + 5];
+        ls += loss[l];
         LeafRec r = leaves[l];
         if (r.size == 0 || r.elo > r.ehi) {
             leaves[l].elo = 0;
