@@ -813,58 +813,67 @@ __global__ __launch_bounds__(1024) void k_point_learned(Load<K, AOS> keys, uint6
 // ------------------------------------------------------------- leaf lines
 
 // The leaf lines (line layout at line_scan), one thread per 16-byte chunk,
-// so that a wave writes eight whole lines.  The workgroup's 32 leaves cover
-// one contiguous rank range; when it is short enough its keys and row IDs
-// are first copied to LDS with consecutive loads.
+// so that a wave writes eight whole lines.  A workgroup writes kLinesGroups
+// groups of 32 leaves in turn; a group's leaves cover one contiguous rank
+// range, and when it is short enough its keys and row IDs are first copied
+// to LDS with consecutive loads.
 constexpr uint32_t kLinesBlock = 256;                         // threads: 32 leaves x 8 chunks
-constexpr uint32_t kLinesStage = 1024;                        // keys staged per workgroup at most
+constexpr uint32_t kLinesStage = 1024;                        // keys staged per group at most
+constexpr uint32_t kLinesGroups = 8;  // groups of 32 leaves per workgroup (fewer workgroups to dispatch)
 template <typename K, bool AOS>
 __global__ __launch_bounds__(kLinesBlock) void k_leaf_lines(Load<K, AOS> keys, const LeafRec *__restrict__ leaves,
                                                             uint32_t L, uint4 *__restrict__ lines) {
     __shared__ K s_key[kLinesStage];
     __shared__ uint32_t s_row[kLinesStage];
-    const uint32_t l0 = blockIdx.x * (kLinesBlock / kLineChunks);
-    const uint32_t l1 = l0 + kLinesBlock / kLineChunks < L ? l0 + kLinesBlock / kLineChunks : L;
-    if (l0 >= L) return;  // workgroup-uniform
-    const uint64_t kb = leaves[l0].base, ke = (uint64_t)leaves[l1 - 1].base + leaves[l1 - 1].size;
-    const bool staged = ke - kb <= kLinesStage;  // workgroup-uniform
-    if (staged) {
-        for (uint64_t i = kb + threadIdx.x; i < ke; i += kLinesBlock) {
-            s_key[i - kb] = keys.key(i);
-            s_row[i - kb] = keys.row(i);
-        }
-        __syncthreads();
-    }
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (uint64_t)L * kLineChunks) return;
-    const uint32_t l = (uint32_t)(t / kLineChunks), c = (uint32_t)(t % kLineChunks);
-    const LeafRec r = leaves[l];
-    auto key_at = [&](uint64_t i) -> uint64_t { return staged ? (uint64_t)s_key[i - kb] : (uint64_t)keys.key(i); };
-    auto row_at = [&](uint64_t i) -> uint32_t { return staged ? s_row[i - kb] : keys.row(i); };
-    constexpr uint32_t C = line_slots<K>();
-    constexpr uint32_t KW = sizeof(K) / 4;  // words per key
-    uint32_t v[4];
-#pragma unroll
-    for (uint32_t i = 0; i < 4; ++i) {
-        const uint32_t wi = 4 * c + i;
-        uint32_t x = 0;
-        if (wi == 0) {
-            x = r.base;
-        } else if (wi == 1) {
-            x = r.size;
-        } else if (wi < 2 + C * KW) {
-            const uint32_t j = (wi - 2) / KW;
-            if (j < r.size) {
-                const uint64_t k = key_at((uint64_t)r.base + j);
-                x = (KW == 2 && ((wi - 2) & 1u)) ? (uint32_t)(k >> 32) : (uint32_t)k;
+    constexpr uint32_t GL = kLinesBlock / kLineChunks;  // leaves per group
+    for (uint32_t gi = 0; gi < kLinesGroups; ++gi) {
+        const uint64_t l0 = ((uint64_t)blockIdx.x * kLinesGroups + gi) * GL;
+        if (l0 >= L) return;  // workgroup-uniform
+        const uint64_t l1 = l0 + GL < L ? l0 + GL : L;
+        const uint64_t kb = leaves[l0].base, ke = (uint64_t)leaves[l1 - 1].base + leaves[l1 - 1].size;
+        const bool staged = ke - kb <= kLinesStage;  // workgroup-uniform
+        if (staged) {
+            for (uint64_t i = kb + threadIdx.x; i < ke; i += kLinesBlock) {
+                s_key[i - kb] = keys.key(i);
+                s_row[i - kb] = keys.row(i);
             }
-        } else {
-            const uint32_t j = wi - 2 - C * KW;
-            if (j < r.size) x = row_at((uint64_t)r.base + j);
+            __syncthreads();
         }
-        v[i] = x;
+        const uint64_t t = l0 * kLineChunks + threadIdx.x;
+        if (t < (uint64_t)L * kLineChunks) {
+            const uint32_t l = (uint32_t)(t / kLineChunks), c = (uint32_t)(t % kLineChunks);
+            const LeafRec r = leaves[l];
+            auto key_at = [&](uint64_t i) -> uint64_t {
+                return staged ? (uint64_t)s_key[i - kb] : (uint64_t)keys.key(i);
+            };
+            auto row_at = [&](uint64_t i) -> uint32_t { return staged ? s_row[i - kb] : keys.row(i); };
+            constexpr uint32_t C = line_slots<K>();
+            constexpr uint32_t KW = sizeof(K) / 4;  // words per key
+            uint32_t v[4];
+#pragma unroll
+            for (uint32_t i = 0; i < 4; ++i) {
+                const uint32_t wi = 4 * c + i;
+                uint32_t x = 0;
+                if (wi == 0) {
+                    x = r.base;
+                } else if (wi == 1) {
+                    x = r.size;
+                } else if (wi < 2 + C * KW) {
+                    const uint32_t j = (wi - 2) / KW;
+                    if (j < r.size) {
+                        const uint64_t k = key_at((uint64_t)r.base + j);
+                        x = (KW == 2 && ((wi - 2) & 1u)) ? (uint32_t)(k >> 32) : (uint32_t)k;
+                    }
+                } else {
+                    const uint32_t j = wi - 2 - C * KW;
+                    if (j < r.size) x = row_at((uint64_t)r.base + j);
+                }
+                v[i] = x;
+            }
+            lines[t] = make_uint4(v[0], v[1], v[2], v[3]);
+        }
+        __syncthreads();  // the next group restages
     }
-    lines[t] = make_uint4(v[0], v[1], v[2], v[3]);
 }
 
 // Answer for x in the window [b, b + len] of the sorted array: halved while
@@ -1064,8 +1073,8 @@ int ensure_lines(idx_index *h, hipStream_t s) {
     h->spare_lines = nullptr;
     h->spare_lines_bytes = 0;
     if (!lines) return IDX_ERR_NOMEM;
-    const uint64_t threads = (uint64_t)L * kLineChunks;
-    const uint32_t g = grid_for(threads, kLinesBlock);
+    const uint64_t groups = ((uint64_t)L + kLinesBlock / kLineChunks - 1) / (kLinesBlock / kLineChunks);
+    const uint32_t g = (uint32_t)((groups + kLinesGroups - 1) / kLinesGroups);
     if (h->u64) {
         if (h->aos) hipLaunchKernelGGL((k_leaf_lines<uint64_t, true>), dim3(g), dim3(256), 0, s, make_load<uint64_t, true>(h), M->leaves, L, lines);
         else hipLaunchKernelGGL((k_leaf_lines<uint64_t, false>), dim3(g), dim3(256), 0, s, make_load<uint64_t, false>(h), M->leaves, L, lines);
