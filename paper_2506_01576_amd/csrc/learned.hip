@@ -132,15 +132,26 @@ __global__ void k_leaf_init(Load<K, AOS> keys, const unsigned long long *__restr
 // The workgroup's leaves' keys into LDS (false: the range is too large).
 template <typename K, bool AOS>
 __device__ __forceinline__ bool stage_leaf_keys(Load<K, AOS> keys, const LeafRec *__restrict__ leaves, uint32_t L,
-                                                K *s_key, uint64_t &kb) {
+                                                K *s_key, uint32_t cap, uint64_t &kb) {
     const uint32_t l0 = blockIdx.x * kLeafBlock;
     if (l0 >= L) return false;  // workgroup-uniform (a launch over no leaves)
     const uint32_t l1 = l0 + kLeafBlock < L ? l0 + kLeafBlock : L;
     kb = leaves[l0].base;
     const uint64_t ke = (uint64_t)leaves[l1 - 1].base + leaves[l1 - 1].size;
-    if (ke - kb > kStageKeys) return false;  // workgroup-uniform
+    if (ke - kb > cap) return false;  // workgroup-uniform
     stage_keys<K>([&](uint64_t i) { return keys.key(i); }, kb, ke, s_key);
     return true;
+}
+
+// Keys staged per workgroup of the per-leaf passes: twice a workgroup's mean
+// key count, a power of two in [1024, kStageKeys].  A workgroup whose leaves
+// hold more reads its keys from memory instead; a small area leaves room in
+// LDS for more workgroups per compute unit (the full area allows two).
+inline uint32_t stage_cap(uint64_t n, uint32_t L) {
+    const uint64_t want = 2ull * kLeafBlock * ((n + L - 1) / L);
+    uint32_t cap = 1024;
+    while (cap < want && cap < kStageKeys) cap <<= 1;
+    return cap;
 }
 
 // Per-leaf sums, one thread per leaf over its key range; a leaf of more than
@@ -148,12 +159,15 @@ __device__ __forceinline__ bool stage_leaf_keys(Load<K, AOS> keys, const LeafRec
 // UPDATE (training): a leaf of at most kLeafCap keys takes its Newton step
 // at once from the sums in registers, which are not stored; the large
 // leaves' steps follow k_leaf_accum_big (k_leaf_update_big).
+// The staging area holds `cap` keys (dynamic LDS, sized by stage_cap).
 template <typename K, bool AOS, bool UPDATE = false>
 __global__ __launch_bounds__(kLeafBlock) void k_leaf_accum_small(Load<K, AOS> keys, LeafRec *__restrict__ leaves,
-                                                                 uint32_t L, double *__restrict__ acc, uint32_t *big) {
-    __shared__ K s_key[kStageKeys];
+                                                                 uint32_t L, double *__restrict__ acc, uint32_t *big,
+                                                                 uint32_t cap) {
+    extern __shared__ __align__(16) char smem_stage[];
+    K *s_key = (K *)smem_stage;
     uint64_t kb;
-    const bool staged = stage_leaf_keys(keys, leaves, L, s_key, kb);
+    const bool staged = stage_leaf_keys(keys, leaves, L, s_key, cap, kb);
     const uint32_t l = blockIdx.x * kLeafBlock + threadIdx.x;
     if (l >= L) return;
     const LeafRec r = leaves[l];
@@ -221,10 +235,11 @@ __global__ void k_leaf_update_big(LeafRec *__restrict__ leaves, const double *__
 // strided line each.
 template <typename K, bool AOS>
 __global__ __launch_bounds__(kLeafBlock) void k_leaf_errors_small(Load<K, AOS> keys, LeafRec *__restrict__ leaves,
-                                                                  uint32_t L, double *__restrict__ loss) {
-    __shared__ K s_key[kStageKeys];
+                                                                  uint32_t L, double *__restrict__ loss, uint32_t cap) {
+    extern __shared__ __align__(16) char smem_stage[];
+    K *s_key = (K *)smem_stage;
     uint64_t kb;
-    const bool staged = stage_leaf_keys(keys, leaves, L, s_key, kb);
+    const bool staged = stage_leaf_keys(keys, leaves, L, s_key, cap, kb);
     const uint32_t l = blockIdx.x * kLeafBlock + threadIdx.x;
     if (l >= L) return;
     const LeafRec r = leaves[l];
@@ -417,6 +432,7 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
         loss = acc[5];
         return IDX_OK;
     };
+    const uint32_t cap = stage_cap(n, L);  // keys staged per workgroup of the per-leaf passes
     // Leaves under root R into `leaves`: layout, Newton steps, error bounds;
     // st = {sum of window * size, max window, leaf loss}.
     auto leaves_for = [&](const RootRec &R, LeafRec *leaves, double st[4]) -> int {
@@ -425,16 +441,16 @@ int train_t(idx_index *h, uint32_t L, uint32_t epochs, uint32_t feature, hipStre
         if (rc != IDX_OK) return rc;
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, d_big, (uint64_t)1, 0u);
         for (uint32_t ep = 0; ep < epochs; ++ep) {
-            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS, true>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s,
-                               keys, leaves, L, leaf_acc, d_big);
+            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS, true>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock),
+                               (size_t)cap * sizeof(K), s, keys, leaves, L, leaf_acc, d_big, cap);
             hipLaunchKernelGGL((k_leaf_accum_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
                                leaf_acc, d_big);
             hipLaunchKernelGGL(k_leaf_update_big, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_acc, L, d_big);
         }
         // the final leaf loss comes with the error bounds (same walk)
         hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, s, stats, (uint64_t)4);
-        hipLaunchKernelGGL((k_leaf_errors_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s, keys, leaves, L,
-                           leaf_acc);
+        hipLaunchKernelGGL((k_leaf_errors_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock),
+                           (size_t)cap * sizeof(K), s, keys, leaves, L, leaf_acc, cap);
         hipLaunchKernelGGL((k_leaf_errors_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves, d_big,
                            stats + 2);
         hipLaunchKernelGGL(k_leaf_finish, dim3(grid_for(L, 256) < 1024 ? grid_for(L, 256) : 1024), dim3(256), 0, s,
@@ -1432,8 +1448,9 @@ int eval_t(idx_index *h, uint32_t mode, const float *root_ab, uint32_t L, const 
             uint32_t *d_big = (uint32_t *)(tmp + 256 + 128);
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, s, d_big, (uint64_t)1, 0u);
             hipLaunchKernelGGL(k_set_leaf_params, dim3(grid_for(L, 256)), dim3(256), 0, s, leaves, leaf_ab, L);
-            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock), 0, s, keys, leaves, L,
-                               leaf_acc_d, d_big);
+            const uint32_t cap = stage_cap(n, L);
+            hipLaunchKernelGGL((k_leaf_accum_small<K, AOS>), dim3(grid_for(L, kLeafBlock)), dim3(kLeafBlock),
+                               (size_t)cap * sizeof(K), s, keys, leaves, L, leaf_acc_d, d_big, cap);
             hipLaunchKernelGGL((k_leaf_accum_big<K, AOS>), dim3(cblocks), dim3(LT), 0, s, keys, n, d_root, leaves,
                                leaf_acc_d, d_big);
         }

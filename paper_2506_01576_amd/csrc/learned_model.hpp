@@ -410,10 +410,10 @@ constexpr int kLeafBatch = 8;
 
 // Per-leaf passes run one thread per leaf, kLeafBlock leaves per workgroup;
 // those leaves cover one contiguous rank range (the bases are the exclusive
-// scan of the sizes).  When it holds at most kStageKeys keys the workgroup
-// copies it into LDS with consecutive loads and each thread walks its leaf
-// there: a thread walking its leaf in global memory issues loads that touch
-// 64 different lines per wave.
+// scan of the sizes).  When it holds no more keys than the staging area
+// (kStageKeys at most) the workgroup copies it into LDS with consecutive
+// loads and each thread walks its leaf there: a thread walking its leaf in
+// global memory issues loads that touch 64 different lines per wave.
 constexpr uint32_t kLeafBlock = 256;
 constexpr uint32_t kStageKeys = 8192;
 
