@@ -271,10 +271,10 @@ __device__ __forceinline__ uint32_t leaf_owner(const TDesc *__restrict__ d, uint
 }
 
 // The workgroup's leaves' keys into LDS, when all its leaves belong to one
-// index and their range holds at most kStageKeys keys (else false).
+// index and their range holds at most `cap` keys (else false).
 template <typename K>
 __device__ __forceinline__ bool bt_stage_leaf_keys(const TDesc *__restrict__ d, uint32_t count, uint64_t total,
-                                                   K *s_key, uint64_t &kb) {
+                                                   K *s_key, uint32_t cap, uint64_t &kb) {
     const uint64_t g0 = (uint64_t)blockIdx.x * kLeafBlock;
     if (g0 >= total) return false;  // workgroup-uniform, as every test below
     const uint64_t g1 = g0 + kLeafBlock < total ? g0 + kLeafBlock : total;
@@ -284,7 +284,7 @@ __device__ __forceinline__ bool bt_stage_leaf_keys(const TDesc *__restrict__ d, 
     kb = D.leaves[g0 - D.leaf_off].base;
     const LeafRec last = D.leaves[g1 - 1 - D.leaf_off];
     const uint64_t ke = (uint64_t)last.base + last.size;
-    if (ke - kb > kStageKeys) return false;
+    if (ke - kb > cap) return false;
     const K *keys = (const K *)D.keys;
     stage_keys<K>([&](uint64_t i) { return keys[i]; }, kb, ke, s_key);
     return true;
@@ -293,12 +293,14 @@ __device__ __forceinline__ bool bt_stage_leaf_keys(const TDesc *__restrict__ d, 
 // Per-leaf sums, one thread per leaf (global leaf g) over its key range; a
 // leaf of more than kLeafCap keys gets zero sums and raises *big.
 template <typename K>
+// (The staging area holds `cap` keys: dynamic LDS sized by stage_cap.)
 __global__ __launch_bounds__(kLeafBlock) void k_bt_leaf_accum_small(const TDesc *__restrict__ d, uint32_t count,
                                                                     uint64_t total, double *__restrict__ acc,
-                                                                    uint32_t *big) {
-    __shared__ K s_key[kStageKeys];
+                                                                    uint32_t *big, uint32_t cap) {
+    extern __shared__ __align__(16) char smem_stage[];
+    K *s_key = (K *)smem_stage;
     uint64_t kb;
-    const bool staged = bt_stage_leaf_keys(d, count, total, s_key, kb);
+    const bool staged = bt_stage_leaf_keys(d, count, total, s_key, cap, kb);
     const uint64_t g = (uint64_t)blockIdx.x * kLeafBlock + threadIdx.x;
     if (g >= total) return;
     const TDesc D = d[leaf_owner(d, count, g)];
@@ -357,10 +359,11 @@ __global__ void k_bt_leaf_update(const TDesc *__restrict__ d, uint32_t count, ui
 // Per-leaf error bounds, one thread per leaf of at most kLeafCap keys.
 template <typename K>
 __global__ __launch_bounds__(kLeafBlock) void k_bt_leaf_errors_small(const TDesc *__restrict__ d, uint32_t count,
-                                                                     uint64_t total) {
-    __shared__ K s_key[kStageKeys];
+                                                                     uint64_t total, uint32_t cap) {
+    extern __shared__ __align__(16) char smem_stage[];
+    K *s_key = (K *)smem_stage;
     uint64_t kb;
-    const bool staged = bt_stage_leaf_keys(d, count, total, s_key, kb);
+    const bool staged = bt_stage_leaf_keys(d, count, total, s_key, cap, kb);
     const uint64_t g = (uint64_t)blockIdx.x * kLeafBlock + threadIdx.x;
     if (g >= total) return;
     const TDesc D = d[leaf_owner(d, count, g)];
@@ -492,10 +495,11 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
     std::vector<TDesc> desc(count), desc_alt;
     std::vector<Unit> units;
     std::vector<uint64_t> bin_off(count);
-    uint64_t total_leaves = 0, total_bins = 0;
+    uint64_t total_leaves = 0, total_bins = 0, total_keys = 0;
     uint32_t max_bins = 1;
     for (uint32_t i = 0; i < count; ++i) {
         const idx_index *h = hs[i];
+        total_keys += h->n;
         desc[i] = TDesc{h->keys, h->n, h->learned->leaves, total_leaves, h->learned->spline, leaves[i], 0};
         total_leaves += leaves[i];
         bin_off[i] = total_bins;
@@ -565,6 +569,7 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
     }
     std::vector<RootRec> best(count);
     std::vector<double> stats((size_t)NST * count);
+    const uint32_t cap = stage_cap(total_keys, total_leaves);  // keys staged per workgroup of the leaf passes
     // the leaf stage under the roots `br` into the tables of `dd`, statistics
     // (entries 0-2) into `st`
     auto leaf_stage = [&](const TDesc *dd, const RootRec *br, double *st) {
@@ -573,15 +578,15 @@ int train_batch_t(idx_index *const *hs, uint32_t count, const uint32_t *leaves, 
         hipLaunchKernelGGL((k_bt_leaf_layout<K>), dim3(count), dim3(1024), 0, s, dd, d_cnt);
         hipLaunchKernelGGL(k_bt_zero_u32, dim3(1), dim3(64), 0, s, d_big, (uint64_t)1);
         for (uint32_t ep = 0; ep <= epochs; ++ep) {
-            hipLaunchKernelGGL((k_bt_leaf_accum_small<K>), dim3(blocks_for(total_leaves, kLeafBlock)), dim3(kLeafBlock), 0, s, dd,
-                               count, total_leaves, d_lacc, d_big);
+            hipLaunchKernelGGL((k_bt_leaf_accum_small<K>), dim3(blocks_for(total_leaves, kLeafBlock)), dim3(kLeafBlock),
+                               (size_t)cap * sizeof(K), s, dd, count, total_leaves, d_lacc, d_big, cap);
             hipLaunchKernelGGL((k_bt_leaf_accum_big<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br, d_lacc, d_big);
             if (ep < epochs)
                 hipLaunchKernelGGL(k_bt_leaf_update, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd, count,
                                    total_leaves, d_lacc);
         }
-        hipLaunchKernelGGL((k_bt_leaf_errors_small<K>), dim3(blocks_for(total_leaves, kLeafBlock)), dim3(kLeafBlock), 0, s, dd, count,
-                           total_leaves);
+        hipLaunchKernelGGL((k_bt_leaf_errors_small<K>), dim3(blocks_for(total_leaves, kLeafBlock)), dim3(kLeafBlock),
+                           (size_t)cap * sizeof(K), s, dd, count, total_leaves, cap);
         hipLaunchKernelGGL((k_bt_leaf_errors_big<K>), dim3(nunits), dim3(BT), 0, s, d_units, dd, br, d_big);
         hipLaunchKernelGGL(k_bt_leaf_finish, dim3(blocks_for(total_leaves, 256)), dim3(256), 0, s, dd, count,
                            total_leaves, d_lacc, st);

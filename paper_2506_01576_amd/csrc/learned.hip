@@ -143,17 +143,6 @@ __device__ __forceinline__ bool stage_leaf_keys(Load<K, AOS> keys, const LeafRec
     return true;
 }
 
-// Keys staged per workgroup of the per-leaf passes: twice a workgroup's mean
-// key count, a power of two in [1024, kStageKeys].  A workgroup whose leaves
-// hold more reads its keys from memory instead; a small area leaves room in
-// LDS for more workgroups per compute unit (the full area allows two).
-inline uint32_t stage_cap(uint64_t n, uint32_t L) {
-    const uint64_t want = 2ull * kLeafBlock * ((n + L - 1) / L);
-    uint32_t cap = 1024;
-    while (cap < want && cap < kStageKeys) cap <<= 1;
-    return cap;
-}
-
 // Per-leaf sums, one thread per leaf over its key range; a leaf of more than
 // kLeafCap keys gets zero sums here and raises *big for k_leaf_accum_big.
 // UPDATE (training): a leaf of at most kLeafCap keys takes its Newton step

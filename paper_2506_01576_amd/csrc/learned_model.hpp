@@ -417,6 +417,21 @@ constexpr int kLeafBatch = 8;
 constexpr uint32_t kLeafBlock = 256;
 constexpr uint32_t kStageKeys = 8192;
 
+// Keys staged per workgroup of the per-leaf passes over n keys in L leaves
+// (dynamic LDS of the launch): twice a workgroup's mean key count as a power
+// of two in [1024, kStageKeys], or none when that mean alone exceeds
+// kStageKeys (staging would seldom succeed and the area would only cost
+// occupancy: the full area allows two workgroups per compute unit).  A
+// workgroup whose leaves hold more keys than the area reads them from memory.
+inline uint32_t stage_cap(uint64_t n, uint64_t L) {
+    if (L == 0) return 0;
+    const uint64_t mean = (uint64_t)kLeafBlock * ((n + L - 1) / L);
+    if (mean > kStageKeys) return 0;
+    uint32_t cap = 1024;
+    while (cap < 2 * mean && cap < kStageKeys) cap <<= 1;
+    return cap;
+}
+
 // Copies keys [kb, ke) (ke - kb <= kStageKeys) into s_key, then a barrier.
 template <typename K, typename KeyAt>
 __device__ __forceinline__ void stage_keys(const KeyAt &key, uint64_t kb, uint64_t ke, K *s_key) {
