@@ -419,14 +419,15 @@ constexpr uint32_t kStageKeys = 8192;
 
 // Keys staged per workgroup of the per-leaf passes over n keys in L leaves
 // (dynamic LDS of the launch): twice a workgroup's mean key count as a power
-// of two in [1024, kStageKeys], or none when that mean alone exceeds
-// kStageKeys (staging would seldom succeed and the area would only cost
-// occupancy: the full area allows two workgroups per compute unit).  A
-// workgroup whose leaves hold more keys than the area reads them from memory.
+// of two in [1024, kStageKeys].  A small area lets more workgroups share a
+// compute unit (the full one allows two).  A workgroup whose leaves hold more
+// keys than the area reads them from memory; where that is the rule (long
+// leaves) the full area stays, since those per-thread walks ran slower at
+// the higher occupancy a small area allows (batched training of 64-key
+// leaves: 240 -> 270 ms without an area).
 inline uint32_t stage_cap(uint64_t n, uint64_t L) {
-    if (L == 0) return 0;
+    if (L == 0) return kStageKeys;
     const uint64_t mean = (uint64_t)kLeafBlock * ((n + L - 1) / L);
-    if (mean > kStageKeys) return 0;
     uint32_t cap = 1024;
     while (cap < 2 * mean && cap < kStageKeys) cap <<= 1;
     return cap;
