@@ -391,6 +391,11 @@ typedef struct idx_learn_stats {
  *            the spline root each get trained leaves, and the one with the
  *            lower log2(1 + mean window), plus 1 for the spline's bin record,
  *            is kept -- a tie keeps the linear root)
+ * With leaf lines selected (lookup parameter leaf_lines = 1) the lines are
+ * written here, 128 bytes per leaf; a re-training keeps the replaced model's
+ * line buffer and rewrites it when the leaf count is the same, and frees it
+ * otherwise (idx_unlearn and idx_destroy free it too).  Work on another
+ * stream that still reads the previous model must be ordered before this call.
  * Synchronises `stream`.  Errors: IDX_ERR_ARG, IDX_ERR_NOMEM, IDX_ERR_HIP.
  */
 int idx_learn(idx_handle h, uint32_t leaves, uint32_t epochs, uint32_t feature, idx_stream stream);
