@@ -412,11 +412,20 @@ def run_study(args, idx, gen, np, torch, dev, log):
     v4 = base.relayout("eks", 9)
     v4.set_params(group=4, per_lane=4)
     forms["EKS(k=9,vgroup4)"] = v4
-    _, _, laos, lp = autotune.choose(n, 64, "learned")
-    ln = base.relayout("bs", 1, laos) if laos else base.relayout("bs", 1, False)
-    ln.learn(lp.get("leaves", 1 << 22), 2)
-    ln.set_params(model=0, per_lane=lp.get("per_lane", 8))
+    # the window search form (2^22 leaves, about 16 keys each) ...
+    ln = base.relayout("bs", 1, False)
+    ln.set_params(model=0, per_lane=4, leaf_lines=2)
+    ln.learn(1 << 22, 2)
     forms["LEARNED"] = ln
+    # ... and the tuned form (leaf lines), trained with its parameters set so
+    # that the training writes its lines
+    _, _, laos, lp = autotune.choose(n, 64, "learned")
+    lp = dict(lp)
+    lines_leaves = lp.pop("leaves", 1 << 24)
+    ll = base.relayout("bs", 1, laos)
+    ll.set_params(**lp)
+    ll.learn(lines_leaves, 2)
+    forms["LEARNED(lines)" if lp.get("leaf_lines") == 1 else "LEARNED(tuned)"] = ll
     out = torch.empty(m, dtype=torch.int32, device=dev)
 
     def timed(ix, q, reps=3):
